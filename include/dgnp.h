@@ -1,0 +1,216 @@
+/*
+ * dgnp -- C ABI of the MI355X (gfx950) solver for the discontinuous-Galerkin
+ * discretisation of the charge-conservation Nernst-Planck (CNP) equations of
+ * arXiv 2112.09271 ("A scalable DG solver for the electroneutral
+ * Nernst-Planck equations").
+ *
+ * Problem (paper Sec. 2.2, Eqs. NP2, charge2, substitution; nondimensional
+ * form of Sec. 2.3): m ions with valences z_k and diffusivities D_k; ion m is
+ * eliminated by electroneutrality, c_m = -(1/z_m) sum_{k<m} z_k c_k.  The
+ * unknowns are phi and c_1..c_{m-1} in the broken space V_h^p of tensor-product
+ * polynomials of degree p per axis on a structured box of hexahedra (d = 3) or
+ * quadrilaterals (d = 2).  The discrete residual is Eqs. NPDG / chargeDG
+ * (Sec. 3.3): SIPG diffusion with penalty C_IP p^2/h (Eq. deltap, h = cell
+ * diameter), upwinded advection-migration with q_k = u - z_k D_k grad phi,
+ * SIPG potential with the concentration-dependent conductivity
+ * kappa = sum_k z_k (z_k D_k - z_m D_m) c_k.
+ *
+ * Conventions common to every call:
+ *  - Vectors are caller-owned DEVICE buffers of length N = m * N_f, field-major:
+ *    index = f * N_f + e * n_b + l with f = 0 for phi, f = k for c_k;
+ *    e = ix + nx*(iy + ny*iz); l = a + (p+1)*(b + (p+1)*c) over the
+ *    Gauss-Lobatto nodes of the element (a along x).  N_f = E * n_b,
+ *    n_b = (p+1)^d.  Element/face tables follow the same order.
+ *  - `prec` selects the arithmetic of a vector argument: DGNP_F64 (double)
+ *    or DGNP_F32 (float).  The residual is always double.
+ *  - `stream` is a hipStream_t (NULL = default stream).  Apply calls are
+ *    stream-ordered and return without synchronising.  dgnp_setup,
+ *    dgnp_set_state, dgnp_solve and dgnp_adjoint synchronise.
+ *  - Every call returns a DGNP_* status; no C++ exception crosses the ABI.
+ *    dgnp_last_error() returns the text of the last failure on this thread.
+ *  - The library never keeps a caller pointer after returning.  The context
+ *    owns all device workspace (hipMalloc) and frees it in dgnp_destroy.
+ *  - One context per host thread at a time.
+ */
+#ifndef DGNP_H
+#define DGNP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DGNP_OK = 0,
+  DGNP_E_ARG = 1,        /* invalid argument (sizes, enums, NULL pointers) */
+  DGNP_E_ALLOC = 2,      /* device or host allocation failed */
+  DGNP_E_HIP = 3,        /* a HIP runtime call failed */
+  DGNP_E_STATE = 4,      /* call order violated (e.g. apply before set_state) */
+  DGNP_E_NOCONV = 5,     /* Newton / Krylov did not reach the tolerance */
+  DGNP_E_BREAKDOWN = 6,  /* Krylov breakdown or line-search failure */
+  DGNP_E_NONFINITE = 7   /* NaN/Inf met in a residual or norm */
+};
+enum { DGNP_F64 = 0, DGNP_F32 = 1 };
+/* boundary kinds per box face, faces tagged 0..5 = x-, x+, y-, y+, z-, z+ */
+enum { DGNP_C_WALL = 0, DGNP_C_DIRICHLET = 1, DGNP_C_INFLOW = 2, DGNP_C_OUTFLOW = 3 };
+enum { DGNP_PHI_NEUMANN0 = 0, DGNP_PHI_DIRICHLET = 1 };
+/* velocity u = Pe * u_hat(x):
+ *   VORTEX        u_hat = (sin(pi x) cos(pi y), -cos(pi x) sin(pi y), 0)
+ *   POISEUILLE_X  u_hat = (6 y'(H - y')/H^2, 0, 0), y' = y - lo[1], H = hi[1] - lo[1]
+ *   CONST         u_hat = (param[0], param[1], param[2])                         */
+enum { DGNP_VEL_VORTEX = 0, DGNP_VEL_POISEUILLE_X = 1, DGNP_VEL_CONST = 2 };
+/* built-in manufactured solutions (m = 2 only); they supply the volume sources
+ * and all Dirichlet data:
+ *   TRIG2D   c1 = 1 + sin(pi x) sin(pi y)/2,  phi = cos(pi x) cos(pi y)/10
+ *   PAPER3D  c1 = cos x + sin y + 3,          phi = sin x + cos y + 3 (Sec. 5.1) */
+enum { DGNP_MMS_NONE = 0, DGNP_MMS_TRIG2D = 1, DGNP_MMS_PAPER3D = 2 };
+/* block-triangular preconditioner order (Sec. 4.1 Eq. P1, Sec. 4.2 Eq. P2) */
+enum { DGNP_PC_P2 = 0, DGNP_PC_P1 = 1 };
+
+typedef struct dgnp_ctx dgnp_ctx; /* opaque; owned by the library */
+
+typedef struct {
+  int32_t dim;        /* 2 or 3 */
+  int32_t n[3];       /* elements per axis (n[2] ignored when dim = 2) */
+  double lo[3], hi[3];
+  int32_t c_bc[6];    /* DGNP_C_* per box face (all concentrations alike) */
+  int32_t phi_bc[6];  /* DGNP_PHI_* per box face */
+  double phi_val[6];  /* potential on DIRICHLET faces (ignored with a manufactured solution) */
+} dgnp_mesh;
+
+typedef struct {
+  int32_t m;          /* number of ions, 2..4; ion m is eliminated (z[m-1] != 0) */
+  const double *z;    /* host [m] valences */
+  const double *D;    /* host [m] nondimensional diffusivities (> 0) */
+} dgnp_species;
+
+typedef struct {
+  int32_t kind;       /* DGNP_VEL_* */
+  double Pe;          /* velocity scale */
+  double param[3];    /* CONST direction */
+} dgnp_velocity;
+
+typedef struct {
+  double c_ip;             /* interior-penalty constant C_IP (paper: 10) */
+  int32_t mms;             /* DGNP_MMS_* */
+  const double *bc_conc;   /* host [m-1][n_bnode] nodal data on DIRICHLET / INFLOW
+                              faces (ignored with a manufactured solution); order:
+                              box faces 0..5, element faces by element index,
+                              face nodes with the lower tangential axis fastest */
+} dgnp_options;
+
+typedef struct {
+  double rtol;        /* Newton stop: ||R(x)||_2 <= rtol * ||R(x_0)||_2 */
+  double atol;        /* ... or ||R(x)||_2 <= atol */
+  int32_t max_newton;
+  int32_t prec;       /* DGNP_F64, or DGNP_F32 = FP32 apply + preconditioner under
+                         FP64 Newton residual, FP64 Arnoldi and FP64 iterative refinement */
+  double lin_rtol;    /* outer FGMRES tolerance per Newton step (paper: 1e-3) */
+  int32_t restart;    /* FGMRES restart length */
+  int32_t max_lin_it; /* FGMRES iterations per linear solve */
+  int32_t pc_kind;    /* DGNP_PC_P2 or DGNP_PC_P1 */
+  int32_t verbose;
+} dgnp_solve_opts;
+
+#define DGNP_MAX_HIST 64
+typedef struct {
+  int32_t newton_its;
+  int32_t lin_its_total;       /* FGMRES iterations over all Newton steps */
+  int32_t refine_its_total;    /* iterative-refinement passes (mixed precision) */
+  int32_t status;
+  double res0, res_final;      /* ||R(x_0)||_2, ||R(x)||_2 */
+  double t_total, t_setup, t_krylov; /* seconds: whole call, set_state, FGMRES */
+  double res_hist[DGNP_MAX_HIST];
+  int32_t lin_its[DGNP_MAX_HIST];
+} dgnp_solve_stats;
+
+/* Builds mesh/face/DOF tables, reference tables (Gauss-Lobatto nodes, p+2
+ * Gauss points per axis), boundary data and the symbolic preconditioner
+ * setup; uploads them on `stream`.  order = p in 1..3.  Errors: DGNP_E_ARG
+ * for unsupported sizes/kinds, DGNP_E_ALLOC / DGNP_E_HIP. */
+int dgnp_setup(const dgnp_mesh *mesh, int32_t order, const dgnp_species *sp,
+               const dgnp_velocity *vel, const dgnp_options *opt, void *stream,
+               dgnp_ctx **out);
+
+/* Sizes: E elements, N_f = E * n_b DOFs per field, m fields, n_bnode nodal
+ * boundary-data entries per concentration.  Any pointer may be NULL. */
+int dgnp_sizes(const dgnp_ctx *ctx, int64_t *E, int64_t *n_dof_field,
+               int32_t *n_fields, int64_t *n_bnode);
+
+/* Host copies of the mesh tables (any pointer may be NULL):
+ *   elem_nbr   [E][2d]  neighbour across slot (x-, x+, y-, y+, z-, z+) or -1
+ *   face_elems [F][2]   interior faces: lower ("-") and upper ("+") element;
+ *                       all x-normal faces by lower element, then y, then z
+ *   face_axis  [F]      normal axis of each interior face
+ * dgnp_n_faces gives F.                                                       */
+int dgnp_n_faces(const dgnp_ctx *ctx, int64_t *n_interior, int64_t *n_boundary);
+int dgnp_connectivity(const dgnp_ctx *ctx, int32_t *elem_nbr, int32_t *face_elems,
+                      int32_t *face_axis);
+
+/* r = R(x), Eqs. NPDG / chargeDG.  x, r: device double [N]. */
+int dgnp_residual(dgnp_ctx *ctx, const double *x, double *r, void *stream);
+
+/* r = dR/dPe at x (exact derivative of the residual with respect to the
+ * velocity scale, |s|' = sign(s), sign(0) = 0).  Device double [N]. */
+int dgnp_residual_dpe(dgnp_ctx *ctx, const double *x, double *r, void *stream);
+
+/* Sets the linearisation point x (device double [N]) for the Jacobian and the
+ * preconditioner: stores x (and a float copy), assembles the diagonal field
+ * blocks A_phiphi, A_ckck on the device, factors element-block ILU(0) of
+ * every A_ckck and sets up the AMG hierarchy of A_phiphi.  prec = DGNP_F32
+ * also prepares float copies of all of it.  Synchronises. */
+int dgnp_set_state(dgnp_ctx *ctx, const double *x, int32_t prec, void *stream);
+
+/* y = J(x) v (transpose = 0) or y = J(x)^T v (transpose = 1), matrix-free,
+ * at the point of the last dgnp_set_state (Sec. 4, Eq. blockmatrix).  v, y:
+ * device [N] of the type `prec` names.  DGNP_E_STATE before set_state. */
+int dgnp_jacobian_apply(dgnp_ctx *ctx, const void *v, void *y, int32_t prec,
+                        int32_t transpose, void *stream);
+
+/* z = P r, the block-triangular preconditioner (Eq. P2 when pc_kind =
+ * DGNP_PC_P2, Eq. P1 otherwise): one element-block ILU(0) solve per
+ * concentration block, one AMG V-cycle on the potential block, coupling
+ * blocks applied matrix-free.  transpose = 1 applies P^T.  r, z: device [N] of
+ * type `prec`.  DGNP_E_STATE before set_state. */
+int dgnp_precond_apply(dgnp_ctx *ctx, const void *r, void *z, int32_t prec,
+                       int32_t transpose, int32_t pc_kind, void *stream);
+
+/* Newton with backtracking line search (Sec. 4) around right-preconditioned
+ * FGMRES with FP64 classical Gram-Schmidt (twice).  x: device double [N]; on
+ * entry an initial guess, or all-NaN to request the paper's initial guess
+ * (Sec. 4.3: constant concentrations = mean boundary data, potential from
+ * the charge equation at those concentrations); on exit the solution.
+ * opts may be NULL (defaults: rtol 1e-8, lin_rtol 1e-3, restart 30, P2, FP64).
+ * stats may be NULL.  Synchronises.  DGNP_E_NOCONV if max_newton is reached. */
+int dgnp_solve(dgnp_ctx *ctx, double *x, const dgnp_solve_opts *opts, dgnp_solve_stats *stats);
+
+/* Adjoint of the outflow-flux objective J = int_{x = x_max} (q_1 . n) c_1 ds
+ * (objective = 0, the only one defined) at the converged state x (device
+ * double [N]): solves J(x)^T lambda = dJ/dx with FGMRES using the transposed
+ * Jacobian apply and the transposed preconditioner, then
+ *   dJ/d(bc data) = -lambda^T dR/d(bc data)      host double [m-1][n_bnode]
+ *   dJ/dPe        = dJ/dPe|_x - lambda^T dR/dPe   host double [1]
+ * J_out (host [1]) receives J(x); lambda (device double [N]) may be NULL.
+ * Synchronises. */
+int dgnp_adjoint(dgnp_ctx *ctx, const double *x, int32_t objective, double *dJ_dbc,
+                 double *dJ_dPe, double *J_out, double *lambda, const dgnp_solve_opts *opts,
+                 dgnp_solve_stats *stats);
+
+/* Copies the assembled block (field f, element e, slot s: 0 = diagonal,
+ * 1 + j = coupling to neighbour slot j) of the last set_state into host
+ * double [n_b][n_b] (row = test function).  For tests and diagnostics. */
+int dgnp_get_block(dgnp_ctx *ctx, int32_t field, int64_t elem, int32_t slot, double *out);
+
+/* Per-kernel timing of the last apply/solve calls on this context (seconds,
+ * summed since the last reset); names as in the profiler summaries. */
+int dgnp_timer(dgnp_ctx *ctx, const char *name, double *seconds, int64_t *calls, int32_t reset);
+
+void dgnp_destroy(dgnp_ctx *ctx);
+const char *dgnp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGNP_H */

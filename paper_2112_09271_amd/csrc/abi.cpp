@@ -1,0 +1,336 @@
+// C ABI entry points (include/dgnp.h).  Every function converts exceptions into
+// status codes and records the message for dgnp_last_error().
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "context.hpp"
+#include "solver.hpp"
+
+using namespace dgnp;
+
+static thread_local std::string g_last_error;
+
+template <typename F>
+static int guard(F&& f) {
+  try {
+    f();
+    return DGNP_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return DGNP_E_ALLOC;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return DGNP_E_ARG;
+  } catch (...) {
+    g_last_error = "unknown failure";
+    return DGNP_E_ARG;
+  }
+}
+
+dgnp::KArgs dgnp_ctx::kargs() const {
+  KArgs A{};
+  A.E = E;
+  for (int i = 0; i < 3; ++i) {
+    A.n[i] = n[i];
+    A.lo[i] = lo[i];
+    A.h[i] = h[i];
+  }
+  A.detJ = 1.0;
+  for (int i = 0; i < dim; ++i) A.detJ *= 0.5 * h[i];
+  A.delta = delta;
+  A.Pe = vel.Pe;
+  A.vel_kind = vel.kind;
+  for (int i = 0; i < 3; ++i) A.vel_param[i] = vel.param[i];
+  A.vel_H = hi[1] - lo[1];
+  A.vel_ylo = lo[1];
+  for (int i = 0; i < 4; ++i) {
+    A.z[i] = z[i];
+    A.D[i] = D[i];
+    A.a[i] = a[i];
+    A.b[i] = b[i];
+  }
+  for (int t = 0; t < 6; ++t) {
+    A.c_bc[t] = c_bc[t];
+    A.phi_bc[t] = phi_bc[t];
+    A.btag_off[t] = btag_off[t];
+  }
+  A.n_bface = n_bface;
+  A.nbr = d_nbr.p;
+  A.bcq = d_bcq.p;
+  A.src = d_src.p;
+  A.objective_tag = 1;
+  return A;
+}
+
+// boundary data at the face Gauss points, [m][n_bface][nqf]
+static void build_boundary_data(dgnp_ctx& c) {
+  const int d = c.dim, nq = c.nq, nn = c.nn;
+  std::vector<double> bcq(size_t(c.m) * c.n_bface * c.nqf, 0.0);
+  int64_t stride2 = int64_t(c.n[0]) * c.n[1];
+  for (int t = 0; t < 2 * d; ++t) {
+    const int a = t / 2, side = (t & 1) ? 1 : -1;
+    const int t1 = d == 3 ? (a == 0 ? 1 : 0) : 1 - a;
+    const int t2 = d == 3 ? (a == 2 ? 1 : 2) : 0;
+    const bool phid = c.phi_bc[t] == DGNP_PHI_DIRICHLET;
+    const bool cdat = c.c_bc[t] == DGNP_C_DIRICHLET || c.c_bc[t] == DGNP_C_INFLOW;
+    int64_t lin = 0;
+    for (int64_t e = 0; e < c.E; ++e) {
+      int id[3] = {int(e % c.n[0]), int((e / c.n[0]) % c.n[1]), d == 3 ? int(e / stride2) : 0};
+      if (id[a] != (side < 0 ? 0 : c.n[a] - 1)) continue;
+      const int64_t bf = c.btag_off[t] + lin;
+      for (int qf = 0; qf < c.nqf; ++qf) {
+        const int qi = qf % nq, qj = qf / nq;
+        double x[3] = {0, 0, 0};
+        x[a] = c.lo[a] + (id[a] + (side > 0 ? 1.0 : 0.0)) * c.h[a];
+        x[t1] = c.lo[t1] + (id[t1] + 0.5 * (c.ref.xq[qi] + 1.0)) * c.h[t1];
+        if (d == 3) x[t2] = c.lo[t2] + (id[t2] + 0.5 * (c.ref.xq[qj] + 1.0)) * c.h[t2];
+        double ph = 0.0, c1 = 0.0;
+        if (c.mms) mms_exact(c, x, &ph, &c1);
+        if (phid) bcq[(0 * c.n_bface + bf) * c.nqf + qf] = c.mms ? ph : c.phi_val[t];
+        if (cdat) {
+          for (int k = 1; k < c.m; ++k) {
+            double g = 0.0;
+            if (c.mms) {
+              g = c1;
+            } else {
+              const double* nodal = c.bc_conc.data() + size_t(k - 1) * c.n_bnode + c.bnode_off[t] + lin * c.nfn;
+              for (int jn = 0; jn < c.nfn; ++jn) {
+                const int ji = jn % nn, jj = jn / nn;
+                double psi = c.ref.B[qi * nn + ji];
+                if (d == 3) psi *= c.ref.B[qj * nn + jj];
+                g += psi * nodal[jn];
+              }
+            }
+            bcq[(size_t(k) * c.n_bface + bf) * c.nqf + qf] = g;
+          }
+        }
+      }
+      ++lin;
+    }
+  }
+  c.d_bcq.upload(bcq, c.stream);
+  if (c.mms) {
+    std::vector<double> src(size_t(c.m) * c.E * c.nqv, 0.0);
+    for (int64_t e = 0; e < c.E; ++e) {
+      int id[3] = {int(e % c.n[0]), int((e / c.n[0]) % c.n[1]), d == 3 ? int(e / stride2) : 0};
+      for (int q = 0; q < c.nqv; ++q) {
+        int qc[3] = {q % nq, (q / nq) % nq, q / (nq * nq)};
+        double x[3] = {0, 0, 0};
+        for (int i = 0; i < d; ++i) x[i] = c.lo[i] + (id[i] + 0.5 * (c.ref.xq[qc[i]] + 1.0)) * c.h[i];
+        double sp, sc;
+        mms_source(c, x, &sp, &sc);
+        src[(0 * c.E + e) * c.nqv + q] = sp;
+        src[(1 * c.E + e) * c.nqv + q] = sc;
+      }
+    }
+    c.d_src.upload(src, c.stream);
+  }
+}
+
+extern "C" {
+
+int dgnp_setup(const dgnp_mesh* mesh, int32_t order, const dgnp_species* sp, const dgnp_velocity* vel,
+               const dgnp_options* opt, void* stream, dgnp_ctx** out) {
+  return guard([&] {
+    DGNP_REQUIRE(mesh && sp && vel && out, DGNP_E_ARG, "NULL argument");
+    DGNP_REQUIRE(mesh->dim == 2 || mesh->dim == 3, DGNP_E_ARG, "dim must be 2 or 3");
+    DGNP_REQUIRE(order >= 1 && order <= 3, DGNP_E_ARG, "order must be 1..3");
+    DGNP_REQUIRE(sp->m >= 2 && sp->m <= 3, DGNP_E_ARG, "number of ions must be 2 or 3");
+    DGNP_REQUIRE(sp->z && sp->D, DGNP_E_ARG, "species arrays missing");
+    DGNP_REQUIRE(sp->z[sp->m - 1] != 0.0, DGNP_E_ARG, "eliminated ion must be charged");
+    auto c = std::make_unique<dgnp_ctx>();
+    c->dim = mesh->dim;
+    c->p = order;
+    c->m = sp->m;
+    c->nn = order + 1;
+    c->nq = order + 2;
+    c->nb = c->dim == 3 ? c->nn * c->nn * c->nn : c->nn * c->nn;
+    c->nqv = c->dim == 3 ? c->nq * c->nq * c->nq : c->nq * c->nq;
+    c->nqf = c->dim == 3 ? c->nq * c->nq : c->nq;
+    c->nfn = c->dim == 3 ? c->nn * c->nn : c->nn;
+    c->E = 1;
+    double diam2 = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      c->n[i] = i < c->dim ? mesh->n[i] : 1;
+      c->lo[i] = i < c->dim ? mesh->lo[i] : 0.0;
+      c->hi[i] = i < c->dim ? mesh->hi[i] : 1.0;
+      DGNP_REQUIRE(c->n[i] >= 1, DGNP_E_ARG, "element counts must be positive");
+      DGNP_REQUIRE(c->hi[i] > c->lo[i], DGNP_E_ARG, "empty box");
+      c->h[i] = (c->hi[i] - c->lo[i]) / c->n[i];
+      if (i < c->dim) diam2 += c->h[i] * c->h[i];
+      c->E *= c->n[i];
+    }
+    DGNP_REQUIRE(c->E <= (int64_t(1) << 30), DGNP_E_ARG, "too many elements");
+    c->Nf = c->E * c->nb;
+    c->N = c->m * c->Nf;
+    for (int k = 0; k < c->m; ++k) {
+      c->z[k] = sp->z[k];
+      c->D[k] = sp->D[k];
+      DGNP_REQUIRE(sp->D[k] > 0.0, DGNP_E_ARG, "diffusivities must be positive");
+    }
+    const double zm = c->z[c->m - 1], Dm = c->D[c->m - 1];
+    for (int k = 0; k < c->m - 1; ++k) {
+      c->a[k] = c->z[k] * (c->D[k] - Dm);
+      c->b[k] = c->z[k] * (c->z[k] * c->D[k] - zm * Dm);
+    }
+    c->c_ip = opt ? opt->c_ip : 10.0;
+    c->delta = c->c_ip * order * order / std::sqrt(diam2);
+    c->mms = opt ? opt->mms : 0;
+    DGNP_REQUIRE(c->mms == 0 || c->m == 2, DGNP_E_ARG, "manufactured solutions need two ions");
+    DGNP_REQUIRE(c->mms >= 0 && c->mms <= 2, DGNP_E_ARG, "unknown manufactured solution");
+    c->vel = *vel;
+    DGNP_REQUIRE(vel->kind >= 0 && vel->kind <= 2, DGNP_E_ARG, "unknown velocity kind");
+    for (int t = 0; t < 6; ++t) {
+      c->c_bc[t] = t < 2 * c->dim ? mesh->c_bc[t] : 0;
+      c->phi_bc[t] = t < 2 * c->dim ? mesh->phi_bc[t] : 0;
+      c->phi_val[t] = t < 2 * c->dim ? mesh->phi_val[t] : 0.0;
+      DGNP_REQUIRE(c->c_bc[t] >= 0 && c->c_bc[t] <= 3, DGNP_E_ARG, "unknown concentration boundary kind");
+      DGNP_REQUIRE(c->phi_bc[t] >= 0 && c->phi_bc[t] <= 1, DGNP_E_ARG, "unknown potential boundary kind");
+    }
+    c->stream = static_cast<hipStream_t>(stream);
+    c->ref = make_ref_tables(order);
+    {
+      RefTables all[3] = {make_ref_tables(1), make_ref_tables(2), make_ref_tables(3)};
+      upload_ref_tables(all, 3);
+    }
+    build_tables(*c);
+    if (c->mms == 0 && c->n_bnode > 0) {
+      DGNP_REQUIRE(opt && opt->bc_conc, DGNP_E_ARG, "boundary data (bc_conc) required");
+      c->bc_conc.assign(opt->bc_conc, opt->bc_conc + size_t(c->m - 1) * c->n_bnode);
+      for (double v : c->bc_conc) DGNP_REQUIRE(std::isfinite(v), DGNP_E_NONFINITE, "non-finite boundary data");
+    }
+    c->d_nbr.upload(c->nbr, c->stream);
+    build_boundary_data(*c);
+    c->d_aux.alloc(size_t(std::max<int64_t>(2 * c->E, c->m * c->n_bface * c->nqf)));
+    precond_symbolic(*c);
+    DGNP_HIP(hipStreamSynchronize(c->stream));
+    *out = c.release();
+  });
+}
+
+int dgnp_sizes(const dgnp_ctx* c, int64_t* E, int64_t* nf, int32_t* nfields, int64_t* nbn) {
+  return guard([&] {
+    DGNP_REQUIRE(c, DGNP_E_ARG, "NULL context");
+    if (E) *E = c->E;
+    if (nf) *nf = c->Nf;
+    if (nfields) *nfields = c->m;
+    if (nbn) *nbn = c->n_bnode;
+  });
+}
+
+int dgnp_n_faces(const dgnp_ctx* c, int64_t* ni, int64_t* nbd) {
+  return guard([&] {
+    DGNP_REQUIRE(c, DGNP_E_ARG, "NULL context");
+    if (ni) *ni = c->F;
+    if (nbd) *nbd = c->n_bface;
+  });
+}
+
+int dgnp_connectivity(const dgnp_ctx* c, int32_t* elem_nbr, int32_t* face_elems, int32_t* face_axis) {
+  return guard([&] {
+    DGNP_REQUIRE(c, DGNP_E_ARG, "NULL context");
+    if (elem_nbr) std::memcpy(elem_nbr, c->nbr.data(), c->nbr.size() * sizeof(int));
+    if (face_elems) std::memcpy(face_elems, c->face_elems.data(), c->face_elems.size() * sizeof(int));
+    if (face_axis) std::memcpy(face_axis, c->face_axis.data(), c->face_axis.size() * sizeof(int));
+  });
+}
+
+int dgnp_residual(dgnp_ctx* c, const double* x, double* r, void* stream) {
+  return guard([&] {
+    DGNP_REQUIRE(c && x && r, DGNP_E_ARG, "NULL argument");
+    launch_dg(c->dim, c->p, c->m, false, M_RES, c->kargs(), x, nullptr, r, nullptr,
+              static_cast<hipStream_t>(stream));
+  });
+}
+
+int dgnp_residual_dpe(dgnp_ctx* c, const double* x, double* r, void* stream) {
+  return guard([&] {
+    DGNP_REQUIRE(c && x && r, DGNP_E_ARG, "NULL argument");
+    launch_dg(c->dim, c->p, c->m, false, M_DPE, c->kargs(), x, nullptr, r, nullptr,
+              static_cast<hipStream_t>(stream));
+  });
+}
+
+int dgnp_set_state(dgnp_ctx* c, const double* x, int32_t prec, void* stream) {
+  return guard([&] {
+    DGNP_REQUIRE(c && x, DGNP_E_ARG, "NULL argument");
+    DGNP_REQUIRE(prec == DGNP_F64 || prec == DGNP_F32, DGNP_E_ARG, "prec must be F64 or F32");
+    set_state(*c, x, prec, static_cast<hipStream_t>(stream));
+  });
+}
+
+int dgnp_jacobian_apply(dgnp_ctx* c, const void* v, void* y, int32_t prec, int32_t transpose,
+                        void* stream) {
+  return guard([&] {
+    DGNP_REQUIRE(c && v && y, DGNP_E_ARG, "NULL argument");
+    DGNP_REQUIRE(prec == DGNP_F64 || prec == DGNP_F32, DGNP_E_ARG, "prec must be F64 or F32");
+    jac_apply(*c, v, y, prec == DGNP_F32, transpose != 0, static_cast<hipStream_t>(stream));
+  });
+}
+
+int dgnp_precond_apply(dgnp_ctx* c, const void* r, void* z, int32_t prec, int32_t transpose,
+                       int32_t pc_kind, void* stream) {
+  return guard([&] {
+    DGNP_REQUIRE(c && r && z, DGNP_E_ARG, "NULL argument");
+    DGNP_REQUIRE(prec == DGNP_F64 || prec == DGNP_F32, DGNP_E_ARG, "prec must be F64 or F32");
+    DGNP_REQUIRE(pc_kind == DGNP_PC_P2 || pc_kind == DGNP_PC_P1, DGNP_E_ARG, "unknown preconditioner");
+    precond_apply(*c, r, z, prec == DGNP_F32, transpose != 0, pc_kind, static_cast<hipStream_t>(stream));
+  });
+}
+
+int dgnp_solve(dgnp_ctx* c, double* x, const dgnp_solve_opts* opts, dgnp_solve_stats* stats) {
+  return guard([&] {
+    DGNP_REQUIRE(c && x, DGNP_E_ARG, "NULL argument");
+    dgnp_solve_opts o = default_solve_opts();
+    if (opts) o = *opts;
+    dgnp_solve_stats st{};
+    int code = newton_solve(*c, x, o, st);
+    if (stats) *stats = st;
+    if (code != DGNP_OK) throw Error(code, st.status == DGNP_E_NOCONV ? "Newton did not converge"
+                                                                      : "solve failed");
+  });
+}
+
+int dgnp_adjoint(dgnp_ctx* c, const double* x, int32_t objective, double* dJ_dbc, double* dJ_dPe,
+                 double* J_out, double* lambda, const dgnp_solve_opts* opts, dgnp_solve_stats* stats) {
+  return guard([&] {
+    DGNP_REQUIRE(c && x, DGNP_E_ARG, "NULL argument");
+    DGNP_REQUIRE(objective == 0, DGNP_E_ARG, "objective 0 (outflow flux of species 1) is the only one");
+    dgnp_solve_opts o = default_solve_opts();
+    if (opts) o = *opts;
+    dgnp_solve_stats st{};
+    int code = adjoint_solve(*c, x, dJ_dbc, dJ_dPe, J_out, lambda, o, st);
+    if (stats) *stats = st;
+    if (code != DGNP_OK) throw Error(code, "adjoint solve failed");
+  });
+}
+
+int dgnp_get_block(dgnp_ctx* c, int32_t field, int64_t elem, int32_t slot, double* out) {
+  return guard([&] {
+    DGNP_REQUIRE(c && out, DGNP_E_ARG, "NULL argument");
+    DGNP_REQUIRE(field >= 0 && field < c->m && elem >= 0 && elem < c->E && slot >= 0 &&
+                     slot <= 2 * c->dim,
+                 DGNP_E_ARG, "block index out of range");
+    get_block(*c, field, elem, slot, out);
+  });
+}
+
+int dgnp_timer(dgnp_ctx* c, const char* name, double* seconds, int64_t* calls, int32_t reset) {
+  return guard([&] {
+    DGNP_REQUIRE(c && name, DGNP_E_ARG, "NULL argument");
+    auto it = c->timers.find(name);
+    if (seconds) *seconds = it == c->timers.end() ? 0.0 : it->second.first;
+    if (calls) *calls = it == c->timers.end() ? 0 : it->second.second;
+    if (reset) c->timers.clear();
+  });
+}
+
+void dgnp_destroy(dgnp_ctx* c) { delete c; }
+
+const char* dgnp_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,190 @@
+// Vector kernels for the Krylov and Newton drivers.  Reductions are two-pass
+// (fixed block partials, then one block), so results do not depend on timing.
+#include "blas.hpp"
+
+namespace dgnp {
+
+static constexpr int VB = 256;
+static constexpr int RED_BLOCKS = 1024;
+
+static inline unsigned grid_for(int64_t n) {
+  int64_t g = (n + VB * 4 - 1) / (VB * 4);
+  if (g < 1) g = 1;
+  if (g > 65535) g = 65535;
+  return unsigned(g);
+}
+
+__global__ void k_d2f(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB)
+    y[i] = float(x[i]);
+}
+__global__ void k_f2d(const float* __restrict__ x, double* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB)
+    y[i] = double(x[i]);
+}
+template <typename T>
+__global__ void k_fill(T* __restrict__ x, T v, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) x[i] = v;
+}
+template <typename T>
+__global__ void k_copy(const T* __restrict__ x, T* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) y[i] = x[i];
+}
+template <typename T>
+__global__ void k_axpby(T a, const T* __restrict__ x, T b, T* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB)
+    y[i] = a * x[i] + b * y[i];
+}
+template <typename T>
+__global__ void k_axpy(T a, const T* __restrict__ x, T* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB)
+    y[i] += a * x[i];
+}
+template <typename T>
+__global__ void k_scale(T a, T* __restrict__ x, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) x[i] *= a;
+}
+
+void cvt_d2f(const double* x, float* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_d2f, dim3(grid_for(n)), dim3(VB), 0, s, x, y, n);
+}
+void cvt_f2d(const float* x, double* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_f2d, dim3(grid_for(n)), dim3(VB), 0, s, x, y, n);
+}
+template <typename T>
+void vfill(T* x, T v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(VB), 0, s, x, v, n);
+}
+template <typename T>
+void vcopy(const T* x, T* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_copy<T>, dim3(grid_for(n)), dim3(VB), 0, s, x, y, n);
+}
+template <typename T>
+void vaxpy(T a, const T* x, T* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_axpy<T>, dim3(grid_for(n)), dim3(VB), 0, s, a, x, y, n);
+}
+template <typename T>
+void vaxpby(T a, const T* x, T b, T* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for(n)), dim3(VB), 0, s, a, x, b, y, n);
+}
+template <typename T>
+void vscale(T a, T* x, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_scale<T>, dim3(grid_for(n)), dim3(VB), 0, s, a, x, n);
+}
+template void vfill<double>(double*, double, int64_t, hipStream_t);
+template void vfill<float>(float*, float, int64_t, hipStream_t);
+template void vcopy<double>(const double*, double*, int64_t, hipStream_t);
+template void vcopy<float>(const float*, float*, int64_t, hipStream_t);
+template void vaxpy<double>(double, const double*, double*, int64_t, hipStream_t);
+template void vaxpy<float>(float, const float*, float*, int64_t, hipStream_t);
+template void vaxpby<double>(double, const double*, double, double*, int64_t, hipStream_t);
+template void vaxpby<float>(float, const float*, float, float*, int64_t, hipStream_t);
+template void vscale<double>(double, double*, int64_t, hipStream_t);
+template void vscale<float>(float, float*, int64_t, hipStream_t);
+
+// ---- reductions ---------------------------------------------------------------
+__device__ inline double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = VB / 2; s > 0; s >>= 1) {
+    if (int(threadIdx.x) < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// partial[j][blk] = sum over the block's chunk of V_j * w
+__global__ void k_dots_partial(const double* __restrict__ V, int64_t ldv, const double* __restrict__ w,
+                               int64_t n, double* __restrict__ partial) {
+  __shared__ double sh[VB];
+  const int j = blockIdx.y;
+  const double* v = V + j * ldv;
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB)
+    acc += v[i] * w[i];
+  double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[int64_t(j) * RED_BLOCKS + blockIdx.x] = s;
+}
+
+__global__ void k_dots_final(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
+  __shared__ double sh[VB];
+  const int j = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += VB) acc += partial[int64_t(j) * RED_BLOCKS + i];
+  double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[j] = s;
+}
+
+int64_t reduce_scratch_size() { return int64_t(64) * RED_BLOCKS + 64; }
+
+static unsigned red_grid(int64_t n) {
+  int64_t g = (n + VB * 8 - 1) / (VB * 8);
+  if (g < 1) g = 1;
+  if (g > RED_BLOCKS) g = RED_BLOCKS;
+  return unsigned(g);
+}
+
+void vdots(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* out_dev,
+           hipStream_t s) {
+  // out_dev must have room for k results followed by the k * RED_BLOCKS partials
+  if (k <= 0) return;
+  double* partial = out_dev + 64;
+  unsigned g = red_grid(n);
+  hipLaunchKernelGGL(k_dots_partial, dim3(g, unsigned(k)), dim3(VB), 0, s, V, ldv, w, n, partial);
+  hipLaunchKernelGGL(k_dots_final, dim3(unsigned(k)), dim3(VB), 0, s, partial, int(g), out_dev);
+}
+
+double vdot(const double* x, const double* y, int64_t n, double* scratch_dev, hipStream_t s) {
+  vdots(x, 0, 1, y, n, scratch_dev, s);
+  double h = 0.0;
+  DGNP_HIP(hipMemcpyAsync(&h, scratch_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+  DGNP_HIP(hipStreamSynchronize(s));
+  return h;
+}
+
+double vnorm2(const double* x, int64_t n, double* scratch_dev, hipStream_t s) {
+  double d = vdot(x, x, n, scratch_dev, s);
+  return d > 0.0 ? sqrt(d) : 0.0;
+}
+
+__global__ void k_maxpy(const double* __restrict__ V, int64_t ldv, int k, const double* __restrict__ h,
+                        double* __restrict__ w, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
+    double acc = w[i];
+    for (int j = 0; j < k; ++j) acc -= h[j] * V[j * ldv + i];
+    w[i] = acc;
+  }
+}
+
+void vmaxpy(const double* V, int64_t ldv, int k, const double* h_dev, double* w, int64_t n,
+            hipStream_t s) {
+  if (k <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_maxpy, dim3(grid_for(n)), dim3(VB), 0, s, V, ldv, k, h_dev, w, n);
+}
+
+template <typename T>
+__global__ void k_combine(const T* __restrict__ Z, int64_t ldz, int k, const double* __restrict__ h,
+                          double* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
+    double acc = y[i];
+    for (int j = 0; j < k; ++j) acc += h[j] * double(Z[j * ldz + i]);
+    y[i] = acc;
+  }
+}
+
+template <typename T>
+void vcombine(const T* Z, int64_t ldz, int k, const double* h_dev, double* y, int64_t n, hipStream_t s) {
+  if (k <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_combine<T>, dim3(grid_for(n)), dim3(VB), 0, s, Z, ldz, k, h_dev, y, n);
+}
+template void vcombine<double>(const double*, int64_t, int, const double*, double*, int64_t, hipStream_t);
+template void vcombine<float>(const float*, int64_t, int, const double*, double*, int64_t, hipStream_t);
+
+}  // namespace dgnp

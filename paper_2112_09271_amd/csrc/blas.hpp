@@ -1,0 +1,26 @@
+// Vector kernels (blas.hip): conversions, axpy-type updates, reductions.
+#pragma once
+
+#include "dgnp_impl.hpp"
+
+namespace dgnp {
+void cvt_d2f(const double* x, float* y, int64_t n, hipStream_t s);
+void cvt_f2d(const float* x, double* y, int64_t n, hipStream_t s);
+template <typename T> void vfill(T* x, T v, int64_t n, hipStream_t s);
+template <typename T> void vcopy(const T* x, T* y, int64_t n, hipStream_t s);
+template <typename T> void vaxpy(T a, const T* x, T* y, int64_t n, hipStream_t s);        // y += a x
+template <typename T> void vaxpby(T a, const T* x, T b, T* y, int64_t n, hipStream_t s);  // y = a x + b y
+template <typename T> void vscale(T a, T* x, int64_t n, hipStream_t s);
+// out[j] = <V_j, w> for j < k, V column-major [k][n] (double accumulation)
+void vdots(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* out_dev,
+           hipStream_t s);
+// w -= sum_j h[j] V_j
+void vmaxpy(const double* V, int64_t ldv, int k, const double* h_dev, double* w, int64_t n,
+            hipStream_t s);
+// y = sum_j h[j] Z_j (Z of type T) accumulated in double into y (y += when accumulate)
+template <typename T>
+void vcombine(const T* Z, int64_t ldz, int k, const double* h_dev, double* y, int64_t n, hipStream_t s);
+double vnorm2(const double* x, int64_t n, double* scratch_dev, hipStream_t s);  // synchronises
+double vdot(const double* x, const double* y, int64_t n, double* scratch_dev, hipStream_t s);
+int64_t reduce_scratch_size();
+}  // namespace dgnp

@@ -1,0 +1,53 @@
+// Library context: mesh tables, reference tables, boundary data, state and
+// preconditioner storage of one problem on one GPU.
+#pragma once
+
+#include "dgnp_impl.hpp"
+
+namespace dgnp {
+struct Precond;  // preconditioner storage (precond.hip)
+void precond_destroy(Precond*);
+}  // namespace dgnp
+
+struct dgnp_ctx {
+  int dim = 3, p = 1, m = 2, nn = 2, nq = 3, nb = 8, nqv = 27, nqf = 9, nfn = 4;
+  int64_t E = 0, Nf = 0, N = 0, F = 0, n_bface = 0, n_bnode = 0;
+  int n[3] = {1, 1, 1};
+  double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1}, h[3] = {1, 1, 1};
+  double z[4] = {}, D[4] = {}, a[4] = {}, b[4] = {};
+  double delta = 0, c_ip = 10;
+  int mms = 0;
+  dgnp_velocity vel{};
+  int c_bc[6] = {}, phi_bc[6] = {};
+  double phi_val[6] = {};
+  std::vector<int> nbr;          // [E][2d]
+  std::vector<int> face_elems;   // [F][2]
+  std::vector<int> face_axis;    // [F]
+  int64_t btag_off[6] = {};      // first boundary face of each box face
+  int64_t bnode_off[6] = {};     // first data node of each box face (-1: no data)
+  std::vector<double> bc_conc;   // [m-1][n_bnode]
+  dgnp::RefTables ref;
+  hipStream_t stream = nullptr;
+
+  dgnp::DevBuf<int> d_nbr;
+  dgnp::DevBuf<double> d_bcq;    // [m][n_bface][nqf]
+  dgnp::DevBuf<double> d_src;    // [m][E][nqv] (manufactured solutions only)
+  dgnp::DevBuf<double> d_aux;    // objective partial sums etc.
+
+  // linearisation point
+  dgnp::DevBuf<double> d_x;
+  dgnp::DevBuf<float> d_x32;
+  bool has_state = false, has_state32 = false;
+
+  dgnp::Precond* pc = nullptr;
+  std::map<std::string, std::pair<double, int64_t>> timers;
+
+  ~dgnp_ctx() { dgnp::precond_destroy(pc); }
+  dgnp::KArgs kargs() const;
+};
+
+namespace dgnp {
+void build_tables(dgnp_ctx& c);                 // mesh, faces, boundary data (tables.cpp)
+void mms_exact(const dgnp_ctx& c, const double* x, double* phi, double* c1);
+void mms_source(const dgnp_ctx& c, const double* x, double* s_phi, double* s_c1);
+}  // namespace dgnp

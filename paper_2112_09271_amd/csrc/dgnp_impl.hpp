@@ -1,0 +1,108 @@
+// Internal declarations of the dgnp library (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/dgnp.h"
+
+namespace dgnp {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& msg) : std::runtime_error(msg), code(c) {}
+};
+
+#define DGNP_HIP(call)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      throw ::dgnp::Error(DGNP_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define DGNP_REQUIRE(cond, code, msg)                            \
+  do {                                                           \
+    if (!(cond)) throw ::dgnp::Error((code), std::string(msg));  \
+  } while (0)
+
+// Owning device buffer.
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void alloc(size_t count) {
+    if (count == n && p) return;
+    release();
+    if (count == 0) return;
+    if (hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)) != hipSuccess) {
+      p = nullptr;
+      throw Error(DGNP_E_ALLOC, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    n = count;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void upload(const T* host, size_t count, hipStream_t s) {
+    alloc(count);
+    DGNP_HIP(hipMemcpyAsync(p, host, count * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  void upload(const std::vector<T>& v, hipStream_t s) { upload(v.data(), v.size(), s); }
+};
+
+// 1-D reference tables on [-1, 1]: Gauss-Lobatto nodes (p+1), Gauss points and
+// weights (p+2), Lagrange values / derivatives at the Gauss points and at the
+// two end points.
+struct RefTables {
+  int p = 0, nn = 0, nq = 0;
+  std::vector<double> xn, xq, wq;
+  std::vector<double> B, Dq;      // [nq][nn]
+  std::vector<double> Dend[2];    // derivative of each basis function at -1 / +1
+};
+RefTables make_ref_tables(int p);
+
+// Argument block shared by every DG kernel (passed by value).
+struct KArgs {
+  int64_t E;
+  int n[3];
+  double lo[3], h[3];
+  double detJ;          // prod h/2
+  double delta;         // interior penalty
+  double Pe;
+  int vel_kind;
+  double vel_param[3];
+  double vel_H, vel_ylo;
+  double z[4], D[4], a[4], b[4];
+  int c_bc[6], phi_bc[6];
+  int64_t btag_off[6];  // first boundary-face index of each box face
+  int64_t n_bface;
+  const int* nbr;       // [E][2d]
+  const double* bcq;    // [m][n_bface][nqf] boundary data at face points (f = 0: phi)
+  const double* src;    // [m][E][nqv] volume sources or nullptr
+  int objective_tag;    // box face of the objective
+};
+
+enum Mode { M_RES = 0, M_JAC = 1, M_JACT = 2, M_DPE = 3, M_OBJG = 4, M_DATAT = 5 };
+
+// Launch one DG operator pass over all elements (kernels_dg.hip).
+//   M_RES / M_DPE: xs = state (double), out = R or dR/dPe
+//   M_JAC / M_JACT: xs = state, vin = v (same type T), out = J v / J^T v
+//   M_OBJG: out = dJ/dx, aux[E][2] = per-element (J, dJ/dPe) contributions
+//   M_DATAT: vin = lambda, aux[m][n_bface][nqf] = lambda^T dR/d(data at face points)
+void launch_dg(int dim, int p, int m, bool f32, int mode, const KArgs& A, const void* xs,
+               const void* vin, void* out, double* aux, hipStream_t s);
+void upload_ref_tables(const RefTables* tabs, int count);
+
+}  // namespace dgnp

@@ -1,0 +1,21 @@
+// Host drivers: state, operator applies, preconditioner, Newton-FGMRES, adjoint.
+#pragma once
+
+#include "context.hpp"
+
+namespace dgnp {
+
+void precond_symbolic(dgnp_ctx& c);                                   // precond.hip
+void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s);            // precond.hip
+void precond_apply(dgnp_ctx& c, const void* r, void* z, bool f32, bool transpose, int pc_kind,
+                   hipStream_t s);                                     // precond.hip
+void get_block(dgnp_ctx& c, int field, int64_t elem, int slot, double* out);
+
+void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s);  // solver.hip
+void jac_apply(dgnp_ctx& c, const void* v, void* y, bool f32, bool transpose, hipStream_t s);
+dgnp_solve_opts default_solve_opts();
+int newton_solve(dgnp_ctx& c, double* x, const dgnp_solve_opts& o, dgnp_solve_stats& st);
+int adjoint_solve(dgnp_ctx& c, const double* x, double* dJ_dbc, double* dJ_dPe, double* J_out,
+                  double* lambda, const dgnp_solve_opts& o, dgnp_solve_stats& st);
+
+}  // namespace dgnp

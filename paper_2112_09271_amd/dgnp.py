@@ -1,0 +1,300 @@
+"""ctypes binding of libdgnp.so (include/dgnp.h), plus a thin torch-facing wrapper.
+
+Only argument marshalling happens here: every step of the solver runs in the
+library's HIP kernels and C++ drivers.  Device buffers are torch tensors whose
+data pointers are handed to the C ABI; streams are torch's current HIP stream.
+Importing this module fails loudly when the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgnp.so")
+
+DGNP_OK, DGNP_E_ARG, DGNP_E_ALLOC, DGNP_E_HIP, DGNP_E_STATE, DGNP_E_NOCONV, DGNP_E_BREAKDOWN, \
+    DGNP_E_NONFINITE = range(8)
+DGNP_F64, DGNP_F32 = 0, 1
+DGNP_PC_P2, DGNP_PC_P1 = 0, 1
+MAX_HIST = 64
+
+
+class dgnp_mesh(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("c_bc", C.c_int32 * 6), ("phi_bc", C.c_int32 * 6), ("phi_val", C.c_double * 6)]
+
+
+class dgnp_species(C.Structure):
+    _fields_ = [("m", C.c_int32), ("z", C.POINTER(C.c_double)), ("D", C.POINTER(C.c_double))]
+
+
+class dgnp_velocity(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("Pe", C.c_double), ("param", C.c_double * 3)]
+
+
+class dgnp_options(C.Structure):
+    _fields_ = [("c_ip", C.c_double), ("mms", C.c_int32), ("bc_conc", C.POINTER(C.c_double))]
+
+
+class dgnp_solve_opts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_newton", C.c_int32),
+                ("prec", C.c_int32), ("lin_rtol", C.c_double), ("restart", C.c_int32),
+                ("max_lin_it", C.c_int32), ("pc_kind", C.c_int32), ("verbose", C.c_int32)]
+
+
+class dgnp_solve_stats(C.Structure):
+    _fields_ = [("newton_its", C.c_int32), ("lin_its_total", C.c_int32), ("refine_its_total", C.c_int32),
+                ("status", C.c_int32), ("res0", C.c_double), ("res_final", C.c_double),
+                ("t_total", C.c_double), ("t_setup", C.c_double), ("t_krylov", C.c_double),
+                ("res_hist", C.c_double * MAX_HIST), ("lin_its", C.c_int32 * MAX_HIST)]
+
+
+_vp = C.c_void_p
+_SIGS = {
+    "dgnp_setup": [C.POINTER(dgnp_mesh), C.c_int32, C.POINTER(dgnp_species), C.POINTER(dgnp_velocity),
+                   C.POINTER(dgnp_options), _vp, C.POINTER(_vp)],
+    "dgnp_sizes": [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                   C.POINTER(C.c_int64)],
+    "dgnp_n_faces": [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
+    "dgnp_connectivity": [_vp, _vp, _vp, _vp],
+    "dgnp_residual": [_vp, _vp, _vp, _vp],
+    "dgnp_residual_dpe": [_vp, _vp, _vp, _vp],
+    "dgnp_set_state": [_vp, _vp, C.c_int32, _vp],
+    "dgnp_jacobian_apply": [_vp, _vp, _vp, C.c_int32, C.c_int32, _vp],
+    "dgnp_precond_apply": [_vp, _vp, _vp, C.c_int32, C.c_int32, C.c_int32, _vp],
+    "dgnp_solve": [_vp, _vp, C.POINTER(dgnp_solve_opts), C.POINTER(dgnp_solve_stats)],
+    "dgnp_adjoint": [_vp, _vp, C.c_int32, _vp, _vp, _vp, _vp, C.POINTER(dgnp_solve_opts),
+                     C.POINTER(dgnp_solve_stats)],
+    "dgnp_get_block": [_vp, C.c_int32, C.c_int64, C.c_int32, _vp],
+    "dgnp_timer": [_vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32],
+    "dgnp_destroy": [_vp],
+    "dgnp_last_error": [],
+}
+EXPORTED = tuple(_SIGS)
+
+_lib = None
+
+
+def lib():
+    """Load libdgnp.so (raises when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2112_09271_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = None if name == "dgnp_destroy" else (C.c_char_p if name == "dgnp_last_error"
+                                                                 else C.c_int)
+        _lib = L
+    return _lib
+
+
+class DgnpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dgnp error {code}: {msg}")
+        self.code = code
+
+
+def _check(code):
+    if code != DGNP_OK:
+        raise DgnpError(code, lib().dgnp_last_error().decode())
+
+
+# ---- thin wrappers with the C names ----------------------------------------
+def dgnp_setup(mesh, order, species, velocity, options, stream=None):
+    ctx = _vp()
+    _check(lib().dgnp_setup(C.byref(mesh), order, C.byref(species), C.byref(velocity), C.byref(options),
+                            stream, C.byref(ctx)))
+    return ctx
+
+
+def dgnp_residual(ctx, x_ptr, r_ptr, stream=None):
+    _check(lib().dgnp_residual(ctx, x_ptr, r_ptr, stream))
+
+
+def dgnp_residual_dpe(ctx, x_ptr, r_ptr, stream=None):
+    _check(lib().dgnp_residual_dpe(ctx, x_ptr, r_ptr, stream))
+
+
+def dgnp_set_state(ctx, x_ptr, prec, stream=None):
+    _check(lib().dgnp_set_state(ctx, x_ptr, prec, stream))
+
+
+def dgnp_jacobian_apply(ctx, v_ptr, y_ptr, prec, transpose, stream=None):
+    _check(lib().dgnp_jacobian_apply(ctx, v_ptr, y_ptr, prec, transpose, stream))
+
+
+def dgnp_precond_apply(ctx, r_ptr, z_ptr, prec, transpose, pc_kind=DGNP_PC_P2, stream=None):
+    _check(lib().dgnp_precond_apply(ctx, r_ptr, z_ptr, prec, transpose, pc_kind, stream))
+
+
+def dgnp_solve(ctx, x_ptr, opts=None, stats=None):
+    _check(lib().dgnp_solve(ctx, x_ptr, C.byref(opts) if opts is not None else None,
+                            C.byref(stats) if stats is not None else None))
+
+
+def dgnp_adjoint(ctx, x_ptr, objective, dJ_dbc, dJ_dPe, J_out, lam_ptr, opts=None, stats=None):
+    _check(lib().dgnp_adjoint(ctx, x_ptr, objective, dJ_dbc, dJ_dPe, J_out, lam_ptr,
+                              C.byref(opts) if opts is not None else None,
+                              C.byref(stats) if stats is not None else None))
+
+
+def dgnp_destroy(ctx):
+    lib().dgnp_destroy(ctx)
+
+
+# ---- Problem: a context plus torch device buffers ---------------------------
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Problem:
+    """One CNP problem on the current GPU.  `cfg` carries the fields of
+    workload.configs.Config (mesh, order, species, velocity, boundary kinds);
+    `bc_conc` the nodal boundary data [m-1][n_bnode] (None with a manufactured
+    solution)."""
+
+    def __init__(self, cfg, bc_conc=None, Pe=None):
+        import torch
+        self.cfg = cfg
+        d = cfg.dim
+        mesh = dgnp_mesh()
+        mesh.dim = d
+        for i in range(3):
+            mesh.n[i] = cfg.n[i] if i < d else 1
+            mesh.lo[i] = cfg.lo[i] if i < d else 0.0
+            mesh.hi[i] = cfg.hi[i] if i < d else 1.0
+        for t in range(6):
+            mesh.c_bc[t] = cfg.c_bc[t] if t < 2 * d else 0
+            mesh.phi_bc[t] = cfg.phi_bc[t] if t < 2 * d else 0
+            mesh.phi_val[t] = cfg.phi_val[t] if t < 2 * d else 0.0
+        self._z = (C.c_double * cfg.m)(*cfg.z)
+        self._D = (C.c_double * cfg.m)(*cfg.D)
+        sp = dgnp_species(cfg.m, self._z, self._D)
+        vel = dgnp_velocity()
+        vel.kind = cfg.vel_kind
+        vel.Pe = cfg.Pe if Pe is None else Pe
+        for i in range(3):
+            vel.param[i] = cfg.vel_param[i]
+        opt = dgnp_options()
+        opt.c_ip = cfg.c_ip
+        opt.mms = cfg.mms
+        self._bc = None
+        if bc_conc is not None:
+            self._bc = np.ascontiguousarray(bc_conc, dtype=np.float64)
+            opt.bc_conc = self._bc.ctypes.data_as(C.POINTER(C.c_double))
+        self.ctx = dgnp_setup(mesh, cfg.p, sp, vel, opt, _stream())
+        E, Nf, nb = C.c_int64(), C.c_int64(), C.c_int64()
+        m = C.c_int32()
+        _check(lib().dgnp_sizes(self.ctx, C.byref(E), C.byref(Nf), C.byref(m), C.byref(nb)))
+        self.E, self.Nf, self.m, self.n_bnode = E.value, Nf.value, m.value, nb.value
+        self.N = self.m * self.Nf
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            dgnp_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # tables
+    def connectivity(self):
+        nF, nB = C.c_int64(), C.c_int64()
+        _check(lib().dgnp_n_faces(self.ctx, C.byref(nF), C.byref(nB)))
+        d = self.cfg.dim
+        nbr = np.zeros((self.E, 2 * d), np.int32)
+        fe = np.zeros((nF.value, 2), np.int32)
+        fa = np.zeros(nF.value, np.int32)
+        _check(lib().dgnp_connectivity(self.ctx, nbr.ctypes.data, fe.ctypes.data, fa.ctypes.data))
+        return nbr, fe, fa, nB.value
+
+    # operators (torch tensors in, torch tensors out)
+    def _dev(self, a, dtype):
+        import torch
+        t = torch.as_tensor(a, dtype=dtype, device=self.device)
+        return t.contiguous()
+
+    def residual(self, x):
+        import torch
+        x = self._dev(x, torch.float64)
+        r = torch.empty_like(x)
+        dgnp_residual(self.ctx, x.data_ptr(), r.data_ptr(), _stream())
+        return r
+
+    def residual_dpe(self, x):
+        import torch
+        x = self._dev(x, torch.float64)
+        r = torch.empty_like(x)
+        dgnp_residual_dpe(self.ctx, x.data_ptr(), r.data_ptr(), _stream())
+        return r
+
+    def set_state(self, x, prec=DGNP_F64):
+        import torch
+        self._state = self._dev(x, torch.float64)
+        dgnp_set_state(self.ctx, self._state.data_ptr(), prec, _stream())
+
+    def jacobian_apply(self, v, prec=DGNP_F64, transpose=False):
+        import torch
+        v = self._dev(v, torch.float64 if prec == DGNP_F64 else torch.float32)
+        y = torch.empty_like(v)
+        dgnp_jacobian_apply(self.ctx, v.data_ptr(), y.data_ptr(), prec, int(transpose), _stream())
+        return y
+
+    def precond_apply(self, r, prec=DGNP_F64, transpose=False, pc_kind=DGNP_PC_P2):
+        import torch
+        r = self._dev(r, torch.float64 if prec == DGNP_F64 else torch.float32)
+        z = torch.empty_like(r)
+        dgnp_precond_apply(self.ctx, r.data_ptr(), z.data_ptr(), prec, int(transpose), pc_kind, _stream())
+        return z
+
+    def get_block(self, field, elem, slot):
+        nb = self.Nf // self.E
+        out = np.zeros((nb, nb))
+        _check(lib().dgnp_get_block(self.ctx, field, elem, slot, out.ctypes.data))
+        return out
+
+    @staticmethod
+    def solve_opts(**kw):
+        o = dgnp_solve_opts()
+        defaults = dict(rtol=1e-8, atol=0.0, max_newton=30, prec=DGNP_F64, lin_rtol=1e-3, restart=30,
+                        max_lin_it=600, pc_kind=DGNP_PC_P2, verbose=0)
+        defaults.update(kw)
+        for k, v in defaults.items():
+            setattr(o, k, v)
+        return o
+
+    def solve(self, x0=None, **kw):
+        """Newton-FGMRES solve; x0 None requests the paper's initial guess.
+        Returns (x, stats)."""
+        import torch
+        if x0 is None:
+            x = torch.full((self.N,), float("nan"), dtype=torch.float64, device=self.device)
+        else:
+            x = self._dev(x0, torch.float64).clone()
+        st = dgnp_solve_stats()
+        dgnp_solve(self.ctx, x.data_ptr(), self.solve_opts(**kw), st)
+        return x, st
+
+    def adjoint(self, x, **kw):
+        """Returns (J, dJ/d(bc data) [m-1][n_bnode], dJ/dPe, lambda, stats)."""
+        import torch
+        x = self._dev(x, torch.float64)
+        dbc = np.zeros((self.m - 1, self.n_bnode))
+        dpe = np.zeros(1)
+        J = np.zeros(1)
+        lam = torch.empty_like(x)
+        st = dgnp_solve_stats()
+        dgnp_adjoint(self.ctx, x.data_ptr(), 0, dbc.ctypes.data, dpe.ctypes.data, J.ctypes.data,
+                     lam.data_ptr(), self.solve_opts(**kw), st)
+        return float(J[0]), dbc, float(dpe[0]), lam, st

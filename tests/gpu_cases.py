@@ -1,0 +1,42 @@
+"""Shared helpers of the GPU parity tests: one config -> (oracle DG, GPU Problem)."""
+import numpy as np
+import pytest
+
+from oracle.dg import DG
+from oracle.problem import Problem as OProblem
+from tests.oracle_cases import adj2d
+from workload import boundary_data, get_config
+
+torch = pytest.importorskip("torch")
+
+
+def gpu_available():
+    return torch.cuda.is_available()
+
+
+def config(name, **kw):
+    cfg = adj2d() if name == "adj2d" else get_config(name)
+    return cfg.with_(**kw) if kw else cfg
+
+
+def pair(name, with_oracle=True, **kw):
+    from paper_2112_09271_amd.dgnp import Problem
+    cfg = config(name, **kw)
+    data = None if cfg.mms else boundary_data(cfg)
+    print(f"[case] {name} n={cfg.n} p={cfg.p} m={cfg.m}", flush=True)
+    gp = Problem(cfg, data)
+    od = None
+    if with_oracle:
+        od = DG(OProblem(cfg) if cfg.mms else OProblem(cfg, data))
+    return cfg, od, gp
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().double().cpu().numpy()
+
+
+def rel_err(a, b):
+    a = np.asarray(a, float)
+    b = np.asarray(b, float)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
