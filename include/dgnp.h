@@ -53,6 +53,9 @@ enum {
   DGNP_E_NONFINITE = 7   /* NaN/Inf met in a residual or norm */
 };
 enum { DGNP_F64 = 0, DGNP_F32 = 1 };
+/* flag OR-ed into the `prec` of dgnp_set_state: assemble the blocks but skip
+ * the factorisations and the multigrid setup (block inspection in tests) */
+enum { DGNP_STATE_ASSEMBLE_ONLY = 0x100 };
 /* boundary kinds per box face, faces tagged 0..5 = x-, x+, y-, y+, z-, z+ */
 enum { DGNP_C_WALL = 0, DGNP_C_DIRICHLET = 1, DGNP_C_INFLOW = 2, DGNP_C_OUTFLOW = 3 };
 enum { DGNP_PHI_NEUMANN0 = 0, DGNP_PHI_DIRICHLET = 1 };
@@ -81,7 +84,7 @@ typedef struct {
 } dgnp_mesh;
 
 typedef struct {
-  int32_t m;          /* number of ions, 2..4; ion m is eliminated (z[m-1] != 0) */
+  int32_t m;          /* number of ions, 2 or 3; ion m is eliminated (z[m-1] != 0) */
   const double *z;    /* host [m] valences */
   const double *D;    /* host [m] nondimensional diffusivities (> 0) */
 } dgnp_species;

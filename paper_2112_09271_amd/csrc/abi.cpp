@@ -69,7 +69,7 @@ dgnp::KArgs dgnp_ctx::kargs() const {
 // boundary data at the face Gauss points, [m][n_bface][nqf]
 static void build_boundary_data(dgnp_ctx& c) {
   const int d = c.dim, nq = c.nq, nn = c.nn;
-  std::vector<double> bcq(size_t(c.m) * c.n_bface * c.nqf, 0.0);
+  std::vector<double> bcq(static_cast<size_t>(c.m) * c.n_bface * c.nqf, 0.0);
   int64_t stride2 = int64_t(c.n[0]) * c.n[1];
   for (int t = 0; t < 2 * d; ++t) {
     const int a = t / 2, side = (t & 1) ? 1 : -1;
@@ -114,7 +114,7 @@ static void build_boundary_data(dgnp_ctx& c) {
   }
   c.d_bcq.upload(bcq, c.stream);
   if (c.mms) {
-    std::vector<double> src(size_t(c.m) * c.E * c.nqv, 0.0);
+    std::vector<double> src(static_cast<size_t>(c.m) * c.E * c.nqv, 0.0);
     for (int64_t e = 0; e < c.E; ++e) {
       int id[3] = {int(e % c.n[0]), int((e / c.n[0]) % c.n[1]), d == 3 ? int(e / stride2) : 0};
       for (int q = 0; q < c.nqv; ++q) {
@@ -258,8 +258,10 @@ int dgnp_residual_dpe(dgnp_ctx* c, const double* x, double* r, void* stream) {
 int dgnp_set_state(dgnp_ctx* c, const double* x, int32_t prec, void* stream) {
   return guard([&] {
     DGNP_REQUIRE(c && x, DGNP_E_ARG, "NULL argument");
+    const bool asm_only = (prec & DGNP_STATE_ASSEMBLE_ONLY) != 0;
+    prec &= ~DGNP_STATE_ASSEMBLE_ONLY;
     DGNP_REQUIRE(prec == DGNP_F64 || prec == DGNP_F32, DGNP_E_ARG, "prec must be F64 or F32");
-    set_state(*c, x, prec, static_cast<hipStream_t>(stream));
+    set_state(*c, x, prec, static_cast<hipStream_t>(stream), asm_only);
   });
 }
 

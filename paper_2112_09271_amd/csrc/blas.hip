@@ -30,10 +30,15 @@ template <typename T>
 __global__ void k_copy(const T* __restrict__ x, T* __restrict__ y, int64_t n) {
   for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) y[i] = x[i];
 }
+// y = a x + b y; y is not read when b == 0 (it may be uninitialised memory)
 template <typename T>
 __global__ void k_axpby(T a, const T* __restrict__ x, T b, T* __restrict__ y, int64_t n) {
-  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB)
-    y[i] = a * x[i] + b * y[i];
+  if (b == T(0)) {
+    for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) y[i] = a * x[i];
+  } else {
+    for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB)
+      y[i] = a * x[i] + b * y[i];
+  }
 }
 template <typename T>
 __global__ void k_axpy(T a, const T* __restrict__ x, T* __restrict__ y, int64_t n) {

@@ -7,6 +7,8 @@
 namespace dgnp {
 struct Precond;  // preconditioner storage (precond.hip)
 void precond_destroy(Precond*);
+struct Krylov;   // FGMRES storage (solver.hip)
+void krylov_destroy(Krylov*);
 }  // namespace dgnp
 
 struct dgnp_ctx {
@@ -40,9 +42,13 @@ struct dgnp_ctx {
   bool has_state = false, has_state32 = false;
 
   dgnp::Precond* pc = nullptr;
+  dgnp::Krylov* kry = nullptr;
   std::map<std::string, std::pair<double, int64_t>> timers;
 
-  ~dgnp_ctx() { dgnp::precond_destroy(pc); }
+  ~dgnp_ctx() {
+    dgnp::krylov_destroy(kry);
+    dgnp::precond_destroy(pc);
+  }
   dgnp::KArgs kargs() const;
 };
 

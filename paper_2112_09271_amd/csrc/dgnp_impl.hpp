@@ -39,6 +39,20 @@ struct DevBuf {
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) {
+    o.p = nullptr;
+    o.n = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      o.p = nullptr;
+      o.n = 0;
+    }
+    return *this;
+  }
   ~DevBuf() { release(); }
   void alloc(size_t count) {
     if (count == n && p) return;
@@ -55,9 +69,12 @@ struct DevBuf {
     p = nullptr;
     n = 0;
   }
+  // synchronous: the host source may be a temporary
   void upload(const T* host, size_t count, hipStream_t s) {
     alloc(count);
+    if (count == 0) return;
     DGNP_HIP(hipMemcpyAsync(p, host, count * sizeof(T), hipMemcpyHostToDevice, s));
+    DGNP_HIP(hipStreamSynchronize(s));
   }
   void upload(const std::vector<T>& v, hipStream_t s) { upload(v.data(), v.size(), s); }
 };

@@ -1,0 +1,36 @@
+// Launchers of the block kernels (kernels_block.hip) and CSR kernels (kernels_csr.hip).
+#pragma once
+
+#include "dgnp_impl.hpp"
+
+namespace dgnp {
+void upload_ref_tables_block(const RefTables* tabs, int count);
+void upload_gll_nodes(const RefTables* tabs, int count);
+void launch_assemble(int dim, int p, int m, const KArgs& A, const double* xs, double* blk, hipStream_t s);
+void launch_block_inverse(int nb, int64_t E, const double* blk, int nslot, double* out, hipStream_t s);
+void launch_ilu_factor(int nb, int dim, double* blk, const int* nbr, const int* lev, int64_t first,
+                       int64_t count, hipStream_t s);
+// kind 0: forward, 1: backward (in may alias out), 2: transposed forward,
+// 3: transposed backward (aux holds the forward result and is overwritten)
+template <typename T>
+void launch_ilu_solve(int kind, int nb, int dim, const T* blk, const int* nbr, const int* lev, int64_t first,
+                      int64_t count, const T* in, T* out, T* aux, hipStream_t s);
+template <typename T>
+void launch_bspmv(int nb, int dim, int64_t E, const T* blk, const int* nbr, const T* x, const T* b, T alpha,
+                  T beta, T* y, hipStream_t s);
+template <typename T>
+void launch_bdiag(int nb, int64_t E, const T* dinv, const T* x, T* y, hipStream_t s);
+template <typename T>
+void launch_q1(bool prolong, int dim, int p, const int* n, const T* a, T* b, T beta, int64_t E, int64_t nvert,
+               hipStream_t s);
+void launch_q1_galerkin(int dim, int p, int64_t E, const double* blk, double* gal, hipStream_t s);
+
+// CSR: y = alpha * A x + beta * b (b may be null)
+template <typename T>
+void launch_csr_spmv(int n, const int* rp, const int* ci, const T* v, const T* x, const T* b, T alpha, T beta,
+                     T* y, hipStream_t s);
+template <typename T>
+void launch_vmul(int64_t n, const T* d, const T* x, T* y, hipStream_t s);  // y = d .* x
+template <typename T>
+void launch_dense_gemv(int n, const T* M, const T* x, T* y, hipStream_t s);  // y = M x
+}  // namespace dgnp

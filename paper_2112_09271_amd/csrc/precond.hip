@@ -1,18 +1,501 @@
-// Block preconditioner storage and applies.
+// Block-triangular preconditioner (paper Sec. 4.1 Eq. P1 and Sec. 4.2 Eq. P2):
+//   concentration blocks A_ckck  -> one element-block ILU(0) solve each
+//   potential block A_phiphi     -> one multigrid V-cycle: Chebyshev-accelerated
+//                                   element-block Jacobi on the DG level, the
+//                                   Galerkin projection onto the continuous Q1
+//                                   vertex space, and a smoothed-aggregation
+//                                   AMG hierarchy below it
+//   off-diagonal coupling blocks -> matrix-free Jacobian applies
+// One application of each inner solver makes P a fixed linear operator, so its
+// exact transpose exists (used by the adjoint).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+
+#include "amg.hpp"
+#include "blas.hpp"
+#include "kernels_block.hpp"
 #include "solver.hpp"
 
 namespace dgnp {
 
-struct Precond {};
+template <typename T>
+struct DevCsr {
+  int n = 0;
+  DevBuf<int> rp, ci;
+  DevBuf<T> v;
+};
+
+struct MgLevel {  // scalar levels (index >= 1 in the V-cycle)
+  int n = 0;
+  DevCsr<double> A, P, R;  // P: next level -> this level
+  DevCsr<float> A32, P32, R32;
+  DevBuf<double> dinv;
+  DevBuf<float> dinv32;
+  double lmax = 1.0;
+};
+
+template <typename T>
+struct Work {  // per-level work vectors
+  std::vector<DevBuf<T>*> x, b, r, d, z;
+};
+
+struct Precond {
+  int nslot = 0;
+  int64_t bsz = 0;                  // doubles per block = nb * nb
+  DevBuf<double> blk;               // [m][E][nslot][nb][nb]
+  DevBuf<float> blk32;
+  DevBuf<double> dinv_phi;          // [E][nb][nb]
+  DevBuf<float> dinv_phi32;
+  double lmax0 = 1.0;
+  // hyperplane levels of the lexicographic element order
+  std::vector<int64_t> lev_ptr;
+  DevBuf<int> lev_elems;
+  // Q1 vertex space
+  int nvx[3] = {1, 1, 1};
+  int64_t nvert = 0;
+  DevBuf<double> gal;
+  std::vector<MgLevel> mg;          // mg[0] = vertex level
+  DevBuf<double> cinv;
+  DevBuf<float> cinv32;
+  int nc = 0;
+  // work
+  std::vector<std::unique_ptr<DevBuf<double>>> wd;
+  std::vector<std::unique_ptr<DevBuf<float>>> wf;
+  DevBuf<double> vN, yN, tN;
+  DevBuf<float> vN32, yN32, tN32;
+  DevBuf<double> red;
+  bool ready = false, ready32 = false, assembled = false;
+};
 
 void precond_destroy(Precond* p) { delete p; }
-void precond_symbolic(dgnp_ctx&) {}
-void precond_numeric(dgnp_ctx&, bool, hipStream_t) {}
-void precond_apply(dgnp_ctx&, const void*, void*, bool, bool, int, hipStream_t) {
-  throw Error(DGNP_E_STATE, "preconditioner not available");
+
+void precond_symbolic(dgnp_ctx& c) {
+  if (!c.pc) c.pc = new Precond();
+  Precond& P = *c.pc;
+  P.nslot = 2 * c.dim + 1;
+  P.bsz = int64_t(c.nb) * c.nb;
+  // hyperplane levels ix + iy + iz
+  const int L = c.n[0] + c.n[1] + (c.dim == 3 ? c.n[2] : 1) - (c.dim == 3 ? 2 : 1);
+  std::vector<std::vector<int>> lv(static_cast<size_t>(L));
+  for (int64_t e = 0; e < c.E; ++e) {
+    int id[3] = {int(e % c.n[0]), int((e / c.n[0]) % c.n[1]),
+                 c.dim == 3 ? int(e / (int64_t(c.n[0]) * c.n[1])) : 0};
+    lv[size_t(id[0] + id[1] + id[2])].push_back(int(e));
+  }
+  P.lev_ptr.assign(1, 0);
+  std::vector<int> flat;
+  flat.reserve(size_t(c.E));
+  for (auto& v : lv) {
+    flat.insert(flat.end(), v.begin(), v.end());
+    P.lev_ptr.push_back(int64_t(flat.size()));
+  }
+  P.lev_elems.upload(flat, c.stream);
+  P.nvert = 1;
+  for (int d = 0; d < 3; ++d) {
+    P.nvx[d] = d < c.dim ? c.n[d] + 1 : 1;
+    P.nvert *= P.nvx[d];
+  }
+  RefTables all[3] = {make_ref_tables(1), make_ref_tables(2), make_ref_tables(3)};
+  upload_ref_tables_block(all, 3);
+  upload_gll_nodes(all, 3);
+  P.red.alloc(size_t(reduce_scratch_size()));
 }
-void get_block(dgnp_ctx&, int, int64_t, int, double*) {
-  throw Error(DGNP_E_STATE, "no assembled blocks");
+
+// ---- vertex matrix from the per-element Galerkin blocks ----------------------
+static Csr vertex_matrix(const dgnp_ctx& c, const Precond& P, const std::vector<double>& gal) {
+  const int d = c.dim, NV = 1 << d;
+  int ns = 1;
+  for (int i = 0; i < d; ++i) ns *= 3;
+  std::vector<double> st(static_cast<size_t>(P.nvert) * ns, 0.0);
+  auto vid = [&](int64_t e, int o, int* vc) {
+    int id[3] = {int(e % c.n[0]), int((e / c.n[0]) % c.n[1]), d == 3 ? int(e / (int64_t(c.n[0]) * c.n[1])) : 0};
+    int64_t v = 0, s = 1;
+    for (int a = 0; a < d; ++a) {
+      vc[a] = id[a] + ((o >> a) & 1);
+      v += vc[a] * s;
+      s *= P.nvx[a];
+    }
+    return v;
+  };
+  for (int64_t e = 0; e < c.E; ++e)
+    for (int s = 0; s < P.nslot; ++s) {
+      const int64_t nb = s == 0 ? e : c.nbr[size_t(e) * 2 * d + (s - 1)];
+      if (nb < 0) continue;
+      const double* g = gal.data() + (size_t(e) * P.nslot + s) * NV * NV;
+      for (int u = 0; u < NV; ++u) {
+        int ru[3] = {0, 0, 0}, cv[3] = {0, 0, 0};
+        const int64_t row = vid(e, u, ru);
+        for (int v = 0; v < NV; ++v) {
+          vid(nb, v, cv);
+          int off = 0, mul = 1;
+          for (int a = 0; a < d; ++a) {
+            off += (cv[a] - ru[a] + 1) * mul;
+            mul *= 3;
+          }
+          st[size_t(row) * ns + off] += g[u * NV + v];
+        }
+      }
+    }
+  Csr A;
+  A.n = A.m = int(P.nvert);
+  A.rp.assign(size_t(A.n) + 1, 0);
+  for (int64_t r = 0; r < P.nvert; ++r) {
+    int rc[3] = {int(r % P.nvx[0]), int((r / P.nvx[0]) % P.nvx[1]), int(r / (int64_t(P.nvx[0]) * P.nvx[1]))};
+    for (int off = 0; off < ns; ++off) {
+      int oc[3] = {off % 3 - 1, (off / 3) % 3 - 1, off / 9 - 1};
+      bool ok = true;
+      int64_t col = 0, mul = 1;
+      for (int a = 0; a < d; ++a) {
+        const int cc = rc[a] + oc[a];
+        if (cc < 0 || cc >= P.nvx[a]) ok = false;
+        col += cc * mul;
+        mul *= P.nvx[a];
+      }
+      const double val = st[size_t(r) * ns + off];
+      if (!ok || val == 0.0) continue;
+      A.ci.push_back(int(col));
+      A.v.push_back(val);
+    }
+    A.rp[r + 1] = int(A.ci.size());
+  }
+  return A;
+}
+
+template <typename T>
+static void upload_csr(DevCsr<T>& D, const Csr& A, hipStream_t s) {
+  D.n = A.n;
+  D.rp.upload(A.rp, s);
+  D.ci.upload(A.ci, s);
+  std::vector<T> v(A.v.begin(), A.v.end());
+  D.v.upload(v, s);
+}
+
+static void ensure_work(dgnp_ctx& c, Precond& P) {
+  // per V-cycle level: 5 vectors (x, b, r, d, z) for each precision
+  const size_t nlev = 1 + P.mg.size();
+  if (P.wd.size() == 5 * nlev) return;
+  P.wd.clear();
+  P.wf.clear();
+  for (size_t l = 0; l < nlev; ++l) {
+    const size_t n = l == 0 ? size_t(c.Nf) : size_t(P.mg[l - 1].n);
+    for (int k = 0; k < 5; ++k) {
+      P.wd.emplace_back(new DevBuf<double>());
+      P.wd.back()->alloc(n);
+      P.wf.emplace_back(new DevBuf<float>());
+    }
+  }
+  P.vN.alloc(size_t(c.N));
+  P.yN.alloc(size_t(c.N));
+  P.tN.alloc(size_t(c.N));
+}
+
+static void ensure_work32(dgnp_ctx& c, Precond& P) {
+  const size_t nlev = 1 + P.mg.size();
+  for (size_t l = 0; l < nlev; ++l) {
+    const size_t n = l == 0 ? size_t(c.Nf) : size_t(P.mg[l - 1].n);
+    for (int k = 0; k < 5; ++k) P.wf[l * 5 + k]->alloc(n);
+  }
+  P.vN32.alloc(size_t(c.N));
+  P.yN32.alloc(size_t(c.N));
+  P.tN32.alloc(size_t(c.N));
+}
+
+// largest eigenvalue of D_b^{-1} A_phiphi by power iteration on the device
+static double lmax_level0(dgnp_ctx& c, Precond& P, hipStream_t s) {
+  const int64_t n = c.Nf;
+  DevBuf<double>& x = *P.wd[0];
+  DevBuf<double>& y = *P.wd[1];
+  std::vector<double> h(static_cast<size_t>(n));
+  uint64_t st = 0x2545F4914F6CDD1Dull;
+  for (int64_t i = 0; i < n; ++i) {
+    st ^= st << 13;
+    st ^= st >> 7;
+    st ^= st << 17;
+    h[size_t(i)] = double(st % 1000003) / 1000003.0 - 0.5;
+  }
+  DGNP_HIP(hipMemcpyAsync(x.p, h.data(), size_t(n) * sizeof(double), hipMemcpyHostToDevice, s));
+  double lam = 1.0;
+  double nx = vnorm2(x.p, n, P.red.p, s);
+  vscale<double>(1.0 / nx, x.p, n, s);
+  for (int it = 0; it < 20; ++it) {
+    launch_bspmv<double>(c.nb, c.dim, c.E, P.blk.p, c.d_nbr.p, x.p, nullptr, 1.0, 0.0, y.p, s);
+    launch_bdiag<double>(c.nb, c.E, P.dinv_phi.p, y.p, x.p, s);
+    lam = vnorm2(x.p, n, P.red.p, s);
+    if (!(lam > 0.0) || !std::isfinite(lam)) throw Error(DGNP_E_NONFINITE, "power iteration failed");
+    vscale<double>(1.0 / lam, x.p, n, s);
+  }
+  return lam;
+}
+
+void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only) {
+  Precond& P = *c.pc;
+  const int64_t per_field = c.E * P.nslot * P.bsz;
+  P.blk.alloc(size_t(c.m * per_field));
+  launch_assemble(c.dim, c.p, c.m, c.kargs(), c.d_x.p, P.blk.p, s);
+  if (assemble_only) {
+    DGNP_HIP(hipStreamSynchronize(s));
+    P.ready = false;
+    P.assembled = true;
+    return;
+  }
+  // potential block: element-diagonal inverses (block-Jacobi smoother)
+  P.dinv_phi.alloc(size_t(c.E * P.bsz));
+  launch_block_inverse(c.nb, c.E, P.blk.p, P.nslot, P.dinv_phi.p, s);
+  // concentration blocks: BILU(0) level by level
+  for (int k = 1; k < c.m; ++k)
+    for (size_t l = 0; l + 1 < P.lev_ptr.size(); ++l)
+      launch_ilu_factor(c.nb, c.dim, P.blk.p + k * per_field, c.d_nbr.p, P.lev_elems.p, P.lev_ptr[l],
+                        P.lev_ptr[l + 1] - P.lev_ptr[l], s);
+  // Galerkin projection of A_phiphi onto Q1 vertices, then host SA setup
+  const int NV = 1 << c.dim;
+  P.gal.alloc(size_t(c.E) * P.nslot * NV * NV);
+  launch_q1_galerkin(c.dim, c.p, c.E, P.blk.p, P.gal.p, s);
+  std::vector<double> gal(P.gal.n);
+  DGNP_HIP(hipMemcpyAsync(gal.data(), P.gal.p, gal.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  DGNP_HIP(hipStreamSynchronize(s));
+  Csr A1 = vertex_matrix(c, P, gal);
+  AmgHierarchy H = sa_setup(A1, 12, 256, 0.08);
+  P.mg.clear();
+  P.mg.resize(H.A.size());
+  for (size_t l = 0; l < H.A.size(); ++l) {
+    MgLevel& L = P.mg[l];
+    L.n = H.A[l].n;
+    upload_csr(L.A, H.A[l], s);
+    if (l + 1 < H.A.size()) {
+      upload_csr(L.P, H.P[l], s);
+      upload_csr(L.R, H.R[l], s);
+    }
+    L.dinv.upload(H.dinv[l], s);
+    L.lmax = H.lmax[l];
+  }
+  P.nc = H.A.back().n;
+  P.cinv.upload(H.coarse_inv, s);
+  P.wd.clear();
+  ensure_work(c, P);
+  P.lmax0 = lmax_level0(c, P, s);
+  P.ready = true;
+  P.assembled = true;
+  P.ready32 = false;
+  if (f32) {
+    P.blk32.alloc(P.blk.n);
+    cvt_d2f(P.blk.p, P.blk32.p, int64_t(P.blk.n), s);
+    P.dinv_phi32.alloc(P.dinv_phi.n);
+    cvt_d2f(P.dinv_phi.p, P.dinv_phi32.p, int64_t(P.dinv_phi.n), s);
+    for (size_t l = 0; l < H.A.size(); ++l) {
+      MgLevel& L = P.mg[l];
+      upload_csr(L.A32, H.A[l], s);
+      if (l + 1 < H.A.size()) {
+        upload_csr(L.P32, H.P[l], s);
+        upload_csr(L.R32, H.R[l], s);
+      }
+      std::vector<float> di(H.dinv[l].begin(), H.dinv[l].end());
+      L.dinv32.upload(di, s);
+    }
+    std::vector<float> ci(H.coarse_inv.begin(), H.coarse_inv.end());
+    P.cinv32.upload(ci, s);
+    ensure_work32(c, P);
+    P.ready32 = true;
+  }
+  DGNP_HIP(hipStreamSynchronize(s));
+}
+
+void get_block(dgnp_ctx& c, int field, int64_t elem, int slot, double* out) {
+  DGNP_REQUIRE(c.pc && c.pc->assembled, DGNP_E_STATE, "no assembled blocks before set_state");
+  Precond& P = *c.pc;
+  const int64_t off = ((int64_t(field) * c.E + elem) * P.nslot + slot) * P.bsz;
+  DGNP_HIP(hipMemcpy(out, P.blk.p + off, size_t(P.bsz) * sizeof(double), hipMemcpyDeviceToHost));
+}
+
+// ---- typed accessors -------------------------------------------------------------
+template <typename T> struct Sel;
+template <> struct Sel<double> {
+  static double* blk(Precond& P) { return P.blk.p; }
+  static double* dinv(Precond& P) { return P.dinv_phi.p; }
+  static DevCsr<double>& A(MgLevel& L) { return L.A; }
+  static DevCsr<double>& Pm(MgLevel& L) { return L.P; }
+  static DevCsr<double>& R(MgLevel& L) { return L.R; }
+  static double* ldinv(MgLevel& L) { return L.dinv.p; }
+  static double* cinv(Precond& P) { return P.cinv.p; }
+  static double* w(Precond& P, size_t i) { return P.wd[i]->p; }
+  static double* vN(Precond& P) { return P.vN.p; }
+  static double* yN(Precond& P) { return P.yN.p; }
+  static double* tN(Precond& P) { return P.tN.p; }
+};
+template <> struct Sel<float> {
+  static float* blk(Precond& P) { return P.blk32.p; }
+  static float* dinv(Precond& P) { return P.dinv_phi32.p; }
+  static DevCsr<float>& A(MgLevel& L) { return L.A32; }
+  static DevCsr<float>& Pm(MgLevel& L) { return L.P32; }
+  static DevCsr<float>& R(MgLevel& L) { return L.R32; }
+  static float* ldinv(MgLevel& L) { return L.dinv32.p; }
+  static float* cinv(Precond& P) { return P.cinv32.p; }
+  static float* w(Precond& P, size_t i) { return P.wf[i]->p; }
+  static float* vN(Precond& P) { return P.vN32.p; }
+  static float* yN(Precond& P) { return P.yN32.p; }
+  static float* tN(Precond& P) { return P.tN32.p; }
+};
+
+// ---- V-cycle -----------------------------------------------------------------------
+template <typename T>
+struct Mg {
+  dgnp_ctx& c;
+  Precond& P;
+  hipStream_t s;
+  int64_t size(int l) const { return l == 0 ? c.Nf : P.mg[l - 1].n; }
+  // y = alpha A x + beta b
+  void A(int l, const T* x, const T* b, T alpha, T beta, T* y) {
+    if (l == 0)
+      launch_bspmv<T>(c.nb, c.dim, c.E, Sel<T>::blk(P), c.d_nbr.p, x, b, alpha, beta, y, s);
+    else {
+      DevCsr<T>& M = Sel<T>::A(P.mg[l - 1]);
+      launch_csr_spmv<T>(M.n, M.rp.p, M.ci.p, M.v.p, x, b, alpha, beta, y, s);
+    }
+  }
+  void Dinv(int l, const T* x, T* y) {
+    if (l == 0)
+      launch_bdiag<T>(c.nb, c.E, Sel<T>::dinv(P), x, y, s);
+    else
+      launch_vmul<T>(size(l), Sel<T>::ldinv(P.mg[l - 1]), x, y, s);
+  }
+  double lmax(int l) const { return l == 0 ? P.lmax0 : P.mg[l - 1].lmax; }
+  void restrict_(int l, const T* r, T* rc) {
+    if (l == 0) {
+      launch_q1<T>(false, c.dim, c.p, c.n, r, rc, T(0), c.E, P.nvert, s);
+    } else {
+      DevCsr<T>& R = Sel<T>::R(P.mg[l - 1]);
+      launch_csr_spmv<T>(R.n, R.rp.p, R.ci.p, R.v.p, r, nullptr, T(1), T(0), rc, s);
+    }
+  }
+  void prolong_add(int l, const T* xc, T* x) {
+    if (l == 0) {
+      launch_q1<T>(true, c.dim, c.p, c.n, xc, x, T(1), c.E, P.nvert, s);
+    } else {
+      DevCsr<T>& Pm = Sel<T>::Pm(P.mg[l - 1]);
+      launch_csr_spmv<T>(Pm.n, Pm.rp.p, Pm.ci.p, Pm.v.p, xc, x, T(1), T(1), x, s);
+    }
+  }
+  // Chebyshev smoothing on [0.1, 1.1] * lmax(D^{-1} A), degree 2
+  void cheb(int l, const T* b, T* x, bool zero_init) {
+    const int64_t n = size(l);
+    T* r = Sel<T>::w(P, size_t(l) * 5 + 2);
+    T* d = Sel<T>::w(P, size_t(l) * 5 + 3);
+    T* z = Sel<T>::w(P, size_t(l) * 5 + 4);
+    const double lm = lmax(l), lo = 0.1 * lm, hi = 1.1 * lm;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    const int deg = 2;
+    if (zero_init)
+      vcopy<T>(b, r, n, s);
+    else
+      A(l, x, b, T(-1), T(1), r);
+    Dinv(l, r, z);
+    vaxpby<T>(T(1.0 / theta), z, T(0), d, n, s);
+    for (int k = 1; k <= deg; ++k) {
+      if (zero_init && k == 1)
+        vcopy<T>(d, x, n, s);
+      else
+        vaxpy<T>(T(1), d, x, n, s);
+      if (k == deg) break;
+      A(l, d, r, T(-1), T(1), r);
+      const double rho_new = 1.0 / (2.0 * sigma - rho);
+      Dinv(l, r, z);
+      vaxpby<T>(T(2.0 * rho_new / delta), z, T(rho_new * rho), d, n, s);
+      rho = rho_new;
+    }
+  }
+  void vcycle(int l, const T* b, T* x) {
+    const int last = int(P.mg.size());
+    if (l == last) {
+      launch_dense_gemv<T>(P.nc, Sel<T>::cinv(P), b, x, s);
+      return;
+    }
+    cheb(l, b, x, true);
+    T* r = Sel<T>::w(P, size_t(l) * 5 + 2);
+    A(l, x, b, T(-1), T(1), r);
+    T* bc = Sel<T>::w(P, size_t(l + 1) * 5 + 1);
+    T* xc = Sel<T>::w(P, size_t(l + 1) * 5 + 0);
+    restrict_(l, r, bc);
+    vcycle(l + 1, bc, xc);
+    prolong_add(l, xc, x);
+    cheb(l, b, x, false);
+  }
+};
+
+template <typename T>
+static void ilu_solve(dgnp_ctx& c, Precond& P, int k, bool transpose, const T* in, T* out, hipStream_t s) {
+  const T* blk = Sel<T>::blk(P) + int64_t(k) * c.E * P.nslot * P.bsz;
+  const int L = int(P.lev_ptr.size()) - 1;
+  if (!transpose) {
+    for (int l = 0; l < L; ++l)
+      launch_ilu_solve<T>(0, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, P.lev_ptr[l],
+                          P.lev_ptr[l + 1] - P.lev_ptr[l], in, out, nullptr, s);
+    for (int l = L - 1; l >= 0; --l)
+      launch_ilu_solve<T>(1, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, P.lev_ptr[l],
+                          P.lev_ptr[l + 1] - P.lev_ptr[l], out, out, nullptr, s);
+  } else {
+    T* aux = Sel<T>::w(P, 4);  // level-0 work vector of length N_f
+    for (int l = 0; l < L; ++l)
+      launch_ilu_solve<T>(2, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, P.lev_ptr[l],
+                          P.lev_ptr[l + 1] - P.lev_ptr[l], in, aux, nullptr, s);
+    for (int l = L - 1; l >= 0; --l)
+      launch_ilu_solve<T>(3, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, P.lev_ptr[l],
+                          P.lev_ptr[l + 1] - P.lev_ptr[l], nullptr, out, aux, s);
+  }
+}
+
+template <typename T>
+static void apply_t(dgnp_ctx& c, const T* r, T* z, bool transpose, int kind, hipStream_t s) {
+  Precond& P = *c.pc;
+  Mg<T> mg{c, P, s};
+  const int64_t Nf = c.Nf;
+  const bool f32 = std::is_same<T, float>::value;
+  T* u = Sel<T>::vN(P);
+  T* y = Sel<T>::yN(P);
+  T* t = Sel<T>::tN(P);
+  // kinds: "c first" (P2, or P1 transposed) and "phi first" (P1, or P2 transposed)
+  const bool c_first = (kind == DGNP_PC_P2) != transpose;
+  if (c_first) {
+    for (int k = 1; k < c.m; ++k) ilu_solve<T>(c, P, k, transpose, r + k * Nf, z + k * Nf, s);
+    vfill<T>(u, T(0), Nf, s);
+    vcopy<T>(z + Nf, u + Nf, (c.m - 1) * Nf, s);
+    jac_apply(c, u, y, f32, transpose, s);
+    vcopy<T>(r, t, Nf, s);
+    vaxpy<T>(T(-1), y, t, Nf, s);
+    mg.vcycle(0, t, z);
+  } else {
+    mg.vcycle(0, r, z);
+    vfill<T>(u + Nf, T(0), (c.m - 1) * Nf, s);
+    vcopy<T>(z, u, Nf, s);
+    jac_apply(c, u, y, f32, transpose, s);
+    for (int k = 1; k < c.m; ++k) {
+      vcopy<T>(r + k * Nf, t + k * Nf, Nf, s);
+      vaxpy<T>(T(-1), y + k * Nf, t + k * Nf, Nf, s);
+      ilu_solve<T>(c, P, k, transpose, t + k * Nf, z + k * Nf, s);
+    }
+  }
+}
+
+void precond_apply(dgnp_ctx& c, const void* r, void* z, bool f32, bool transpose, int kind, hipStream_t s) {
+  DGNP_REQUIRE(c.pc && c.pc->ready, DGNP_E_STATE, "precond_apply before set_state");
+  if (f32) {
+    DGNP_REQUIRE(c.pc->ready32, DGNP_E_STATE, "float preconditioner needs set_state with DGNP_F32");
+    apply_t<float>(c, static_cast<const float*>(r), static_cast<float*>(z), transpose, kind, s);
+  } else {
+    apply_t<double>(c, static_cast<const double*>(r), static_cast<double*>(z), transpose, kind, s);
+  }
+}
+
+// y = A_phiphi x with the assembled potential block
+void phi_block_apply(dgnp_ctx& c, const double* x, double* y, hipStream_t s) {
+  launch_bspmv<double>(c.nb, c.dim, c.E, c.pc->blk.p, c.d_nbr.p, x, nullptr, 1.0, 0.0, y, s);
+}
+
+// potential-block V-cycle alone (used for the initial potential solve)
+void vcycle_phi(dgnp_ctx& c, const double* b, double* x, hipStream_t s) {
+  Mg<double> mg{c, *c.pc, s};
+  mg.vcycle(0, b, x);
 }
 
 }  // namespace dgnp

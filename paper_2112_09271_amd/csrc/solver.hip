@@ -1,12 +1,22 @@
-// Host drivers: linearisation state and matrix-free Jacobian applies.
+// Host drivers: linearisation state, matrix-free Jacobian applies, flexible
+// GMRES with FP64 classical Gram-Schmidt (twice), Newton with backtracking
+// line search (paper Sec. 4), mixed precision by iterative refinement, and the
+// adjoint of the outflow-flux objective.
+#include <chrono>
+#include <cmath>
+#include <vector>
+
 #include "blas.hpp"
 #include "solver.hpp"
 
 namespace dgnp {
 
-void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s) {
+using clk = std::chrono::steady_clock;
+static double since(clk::time_point t0) { return std::chrono::duration<double>(clk::now() - t0).count(); }
+
+void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assemble_only) {
   c.d_x.alloc(size_t(c.N));
-  vcopy<double>(x, c.d_x.p, c.N, s);
+  if (x != c.d_x.p) vcopy<double>(x, c.d_x.p, c.N, s);
   c.has_state = true;
   c.has_state32 = false;
   if (prec == DGNP_F32) {
@@ -14,7 +24,7 @@ void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s) {
     cvt_d2f(c.d_x.p, c.d_x32.p, c.N, s);
     c.has_state32 = true;
   }
-  precond_numeric(c, prec == DGNP_F32, s);
+  precond_numeric(c, prec == DGNP_F32, s, assemble_only);
   DGNP_HIP(hipStreamSynchronize(s));
 }
 
@@ -39,15 +49,374 @@ dgnp_solve_opts default_solve_opts() {
   return o;
 }
 
-int newton_solve(dgnp_ctx&, double*, const dgnp_solve_opts&, dgnp_solve_stats& st) {
-  st.status = DGNP_E_STATE;
-  throw Error(DGNP_E_STATE, "solver not available");
+// ---------------------------------------------------------------------------
+// Flexible GMRES (right preconditioning) for Op x = b with Op = J or J^T and
+// preconditioner P or P^T.  Arnoldi basis, orthogonalisation and all inner
+// products in FP64.  With f32 the operator and preconditioner are applied in
+// FP32 (the Krylov relation then holds for the FP32 operator); every restart
+// recomputes the true FP64 residual b - Op x, which makes the restarts the
+// steps of an iterative refinement.
+// ---------------------------------------------------------------------------
+struct Krylov {
+  DevBuf<double> V, Z, w, r, hd;
+  DevBuf<float> Z32, v32, w32;
+  int restart = 0;
+  int64_t n = 0;
+};
+
+void krylov_destroy(Krylov* k) { delete k; }
+
+static Krylov& krylov(dgnp_ctx& c, int restart, bool f32) {
+  if (!c.kry) c.kry = new Krylov();
+  Krylov* K = c.kry;
+  if (K->restart != restart || K->n != c.N) {
+    K->V.alloc(size_t(restart + 1) * c.N);
+    K->w.alloc(size_t(c.N));
+    K->r.alloc(size_t(c.N));
+    K->hd.alloc(size_t(reduce_scratch_size()) + 192);
+    K->Z.release();
+    K->Z32.release();
+    K->restart = restart;
+    K->n = c.N;
+  }
+  if (f32 && !K->Z32.p) {
+    K->Z32.alloc(size_t(restart) * c.N);
+    K->v32.alloc(size_t(c.N));
+    K->w32.alloc(size_t(c.N));
+  }
+  if (!f32 && !K->Z.p) K->Z.alloc(size_t(restart) * c.N);
+  return *K;
 }
 
-int adjoint_solve(dgnp_ctx&, const double*, double*, double*, double*, double*, const dgnp_solve_opts&,
-                  dgnp_solve_stats& st) {
-  st.status = DGNP_E_STATE;
-  throw Error(DGNP_E_STATE, "adjoint not available");
+struct LinResult {
+  int its = 0, refinements = 0;
+  double res = 0.0;
+  bool converged = false;
+};
+
+static void op_apply64(dgnp_ctx& c, const double* v, double* y, bool transpose, hipStream_t s) {
+  jac_apply(c, v, y, false, transpose, s);
+}
+
+static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, int restart, int maxit,
+                        bool f32, bool transpose, int pc_kind, bool x_is_zero, int verbose, hipStream_t s) {
+  Krylov& K = krylov(c, restart, f32);
+  const int64_t N = c.N;
+  LinResult out;
+  const size_t rs = static_cast<size_t>(restart);
+  std::vector<double> H((rs + 1) * rs), g(rs + 1), cs(rs), sn(rs), hbuf(129), y(rs);
+  bool first = true;
+  while (true) {
+    // true FP64 residual
+    if (first && x_is_zero) {
+      vcopy<double>(b, K.r.p, N, s);
+    } else {
+      op_apply64(c, x, K.r.p, transpose, s);
+      vaxpby<double>(1.0, b, -1.0, K.r.p, N, s);
+      ++out.refinements;
+    }
+    first = false;
+    const double beta = vnorm2(K.r.p, N, K.hd.p, s);
+    out.res = beta;
+    if (!std::isfinite(beta)) throw Error(DGNP_E_NONFINITE, "non-finite linear residual");
+    if (verbose > 1) fprintf(stderr, "  fgmres restart: |r| = %.3e (target %.3e)\n", beta, target);
+    if (beta <= target) {
+      out.converged = true;
+      break;
+    }
+    if (out.its >= maxit) break;
+    vaxpby<double>(1.0 / beta, K.r.p, 0.0, K.V.p, N, s);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j = 0;
+    bool done = false;
+    for (; j < restart && out.its < maxit; ++j) {
+      double* vj = K.V.p + int64_t(j) * N;
+      double* w = K.w.p;
+      if (f32) {
+        float* zj = K.Z32.p + int64_t(j) * N;
+        cvt_d2f(vj, K.v32.p, N, s);
+        precond_apply(c, K.v32.p, zj, true, transpose, pc_kind, s);
+        jac_apply(c, zj, K.w32.p, true, transpose, s);
+        cvt_f2d(K.w32.p, w, N, s);
+      } else {
+        double* zj = K.Z.p + int64_t(j) * N;
+        precond_apply(c, vj, zj, false, transpose, pc_kind, s);
+        jac_apply(c, zj, w, false, transpose, s);
+      }
+      // classical Gram-Schmidt, twice; coefficients stay on the device until one copy
+      double* h1 = K.hd.p + reduce_scratch_size();
+      double* h2 = h1 + 64;
+      double* ww = h2 + 64;
+      vdots(K.V.p, N, j + 1, w, N, K.hd.p, s);
+      vcopy<double>(K.hd.p, h1, j + 1, s);
+      vmaxpy(K.V.p, N, j + 1, h1, w, N, s);
+      vdots(K.V.p, N, j + 1, w, N, K.hd.p, s);
+      vcopy<double>(K.hd.p, h2, j + 1, s);
+      vmaxpy(K.V.p, N, j + 1, h2, w, N, s);
+      vdots(w, 0, 1, w, N, K.hd.p, s);
+      vcopy<double>(K.hd.p, ww, 1, s);
+      DGNP_HIP(hipMemcpyAsync(hbuf.data(), h1, sizeof(double) * size_t(64 + 64 + 1), hipMemcpyDeviceToHost, s));
+      DGNP_HIP(hipStreamSynchronize(s));
+      ++out.its;
+      double* col = H.data() + size_t(j) * (restart + 1);
+      for (int i = 0; i <= j; ++i) col[i] = hbuf[size_t(i)] + hbuf[size_t(64 + i)];
+      const double hn = std::sqrt(std::max(hbuf[128], 0.0));
+      col[j + 1] = hn;
+      if (!std::isfinite(hn)) throw Error(DGNP_E_NONFINITE, "non-finite Arnoldi vector");
+      if (hn > 0.0) vaxpby<double>(1.0 / hn, w, 0.0, K.V.p + int64_t(j + 1) * N, N, s);
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[size_t(i)] * col[i] + sn[size_t(i)] * col[i + 1];
+        col[i + 1] = -sn[size_t(i)] * col[i] + cs[size_t(i)] * col[i + 1];
+        col[i] = t;
+      }
+      const double den = std::hypot(col[j], col[j + 1]);
+      if (den == 0.0) throw Error(DGNP_E_BREAKDOWN, "FGMRES breakdown");
+      cs[size_t(j)] = col[j] / den;
+      sn[size_t(j)] = col[j + 1] / den;
+      col[j] = den;
+      col[j + 1] = 0.0;
+      g[size_t(j + 1)] = -sn[size_t(j)] * g[size_t(j)];
+      g[size_t(j)] = cs[size_t(j)] * g[size_t(j)];
+      const double est = std::fabs(g[size_t(j + 1)]);
+      if (verbose > 2) fprintf(stderr, "    it %d: est %.3e\n", out.its, est);
+      if (est <= target || hn == 0.0) {
+        ++j;
+        done = true;
+        break;
+      }
+    }
+    // back substitution and update x += Z y
+    const int k = j;
+    for (int i = k - 1; i >= 0; --i) {
+      double acc = g[size_t(i)];
+      for (int l = i + 1; l < k; ++l) acc -= H[size_t(l) * (restart + 1) + i] * y[size_t(l)];
+      y[size_t(i)] = acc / H[size_t(i) * (restart + 1) + i];
+    }
+    double* yd = K.hd.p + reduce_scratch_size() + 129;
+    DGNP_HIP(hipMemcpyAsync(yd, y.data(), sizeof(double) * size_t(k), hipMemcpyHostToDevice, s));
+    if (f32)
+      vcombine<float>(K.Z32.p, N, k, yd, x, N, s);
+    else
+      vcombine<double>(K.Z.p, N, k, yd, x, N, s);
+    DGNP_HIP(hipStreamSynchronize(s));
+    (void)done;
+  }
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// Initial guess (paper Sec. 4.3): constant concentrations equal to the mean
+// of the inflow / Dirichlet data, and the potential from the charge equation
+// at those concentrations, R_phi(c0, phi) = 0, which is linear in phi; solved
+// with conjugate gradients preconditioned by the potential V-cycle.
+// ---------------------------------------------------------------------------
+static void initial_guess(dgnp_ctx& c, double* x, hipStream_t s, int verbose) {
+  const int64_t Nf = c.Nf;
+  vfill<double>(x, 0.0, Nf, s);
+  for (int k = 1; k < c.m; ++k) {
+    double mean = 1.0;
+    if (!c.mms && c.n_bnode > 0) {
+      mean = 0.0;
+      for (int64_t j = 0; j < c.n_bnode; ++j) mean += c.bc_conc[size_t(k - 1) * c.n_bnode + j];
+      mean /= double(c.n_bnode);
+    }
+    vfill<double>(x + k * Nf, mean, Nf, s);
+  }
+  set_state(c, x, DGNP_F64, s);
+  DevBuf<double> r, z, p, q, phi;
+  r.alloc(size_t(c.N));
+  z.alloc(size_t(Nf));
+  p.alloc(size_t(Nf));
+  q.alloc(size_t(Nf));
+  phi.alloc(size_t(Nf));
+  DevBuf<double> red;
+  red.alloc(size_t(reduce_scratch_size()));
+  launch_dg(c.dim, c.p, c.m, false, M_RES, c.kargs(), x, nullptr, r.p, nullptr, s);
+  vscale<double>(-1.0, r.p, Nf, s);  // right-hand side -R_phi(c0, 0), kept in r[0:Nf]
+  const double bn = vnorm2(r.p, Nf, red.p, s);
+  vfill<double>(phi.p, 0.0, Nf, s);
+  if (bn > 0.0) {
+    vcycle_phi(c, r.p, z.p, s);
+    vcopy<double>(z.p, p.p, Nf, s);
+    double rz = vdot(r.p, z.p, Nf, red.p, s);
+    for (int it = 0; it < 500; ++it) {
+      phi_block_apply(c, p.p, q.p, s);
+      const double pq = vdot(p.p, q.p, Nf, red.p, s);
+      const double alpha = rz / pq;
+      vaxpy<double>(alpha, p.p, phi.p, Nf, s);
+      vaxpy<double>(-alpha, q.p, r.p, Nf, s);
+      const double rn = vnorm2(r.p, Nf, red.p, s);
+      if (verbose > 1) fprintf(stderr, "  initial potential CG %d: %.3e\n", it, rn / bn);
+      if (rn <= 1e-6 * bn) break;
+      vcycle_phi(c, r.p, z.p, s);
+      const double rz_new = vdot(r.p, z.p, Nf, red.p, s);
+      vaxpby<double>(1.0, z.p, rz_new / rz, p.p, Nf, s);
+      rz = rz_new;
+    }
+  }
+  vcopy<double>(phi.p, x, Nf, s);
+  DGNP_HIP(hipStreamSynchronize(s));
+}
+
+struct NewtonWork {
+  DevBuf<double> r, rt, xt, dx, b, red;
+};
+
+int newton_solve(dgnp_ctx& c, double* x, const dgnp_solve_opts& o, dgnp_solve_stats& st) {
+  const auto t0 = clk::now();
+  hipStream_t s = c.stream;
+  const int64_t N = c.N;
+  NewtonWork W;
+  W.r.alloc(size_t(N));
+  W.rt.alloc(size_t(N));
+  W.xt.alloc(size_t(N));
+  W.dx.alloc(size_t(N));
+  W.b.alloc(size_t(N));
+  W.red.alloc(size_t(reduce_scratch_size()));
+  st = dgnp_solve_stats{};
+  DGNP_REQUIRE(o.restart >= 1 && o.restart <= 60, DGNP_E_ARG, "restart must be 1..60");
+  DGNP_REQUIRE(o.prec == DGNP_F64 || o.prec == DGNP_F32, DGNP_E_ARG, "prec must be F64 or F32");
+  double x0;
+  DGNP_HIP(hipMemcpy(&x0, x, sizeof(double), hipMemcpyDeviceToHost));
+  if (std::isnan(x0)) {
+    const auto ts = clk::now();
+    initial_guess(c, x, s, o.verbose);
+    st.t_setup += since(ts);
+  }
+  const bool f32 = o.prec == DGNP_F32;
+  auto resid = [&](const double* xv, double* rv) {
+    launch_dg(c.dim, c.p, c.m, false, M_RES, c.kargs(), xv, nullptr, rv, nullptr, s);
+    return vnorm2(rv, N, W.red.p, s);
+  };
+  double res = resid(x, W.r.p);
+  DGNP_REQUIRE(std::isfinite(res), DGNP_E_NONFINITE, "non-finite initial residual");
+  st.res0 = res;
+  st.res_hist[0] = res;
+  int code = DGNP_E_NOCONV;
+  for (int it = 0; it <= o.max_newton; ++it) {
+    if (res <= o.rtol * st.res0 || res <= o.atol) {
+      code = DGNP_OK;
+      break;
+    }
+    if (it == o.max_newton) break;
+    const auto ts = clk::now();
+    set_state(c, x, o.prec, s);
+    st.t_setup += since(ts);
+    vcopy<double>(W.r.p, W.b.p, N, s);
+    vscale<double>(-1.0, W.b.p, N, s);
+    vfill<double>(W.dx.p, 0.0, N, s);
+    const auto tk = clk::now();
+    LinResult lr = fgmres(c, W.b.p, W.dx.p, o.lin_rtol * res, o.restart, o.max_lin_it, f32, false, o.pc_kind,
+                          true, o.verbose, s);
+    st.t_krylov += since(tk);
+    st.lin_its_total += lr.its;
+    st.refine_its_total += lr.refinements;
+    if (it < DGNP_MAX_HIST) st.lin_its[it] = lr.its;
+    // backtracking line search
+    double lam = 1.0, rt = 0.0;
+    bool ok = false;
+    for (int cut = 0; cut <= 10; ++cut) {
+      vcopy<double>(x, W.xt.p, N, s);
+      vaxpy<double>(lam, W.dx.p, W.xt.p, N, s);
+      rt = resid(W.xt.p, W.rt.p);
+      if (std::isfinite(rt) && rt <= (1.0 - 1e-4 * lam) * res) {
+        ok = true;
+        break;
+      }
+      lam *= 0.5;
+    }
+    if (o.verbose)
+      fprintf(stderr, "newton %d: |R| %.3e -> %.3e (lambda %.3g, %d its, lin res %.2e)\n", it, res, rt, lam,
+              lr.its, lr.res / res);
+    if (!ok) {
+      code = DGNP_E_BREAKDOWN;
+      break;
+    }
+    vcopy<double>(W.xt.p, x, N, s);
+    std::swap(W.r.p, W.rt.p);
+    res = rt;
+    st.newton_its = it + 1;
+    if (it + 1 < DGNP_MAX_HIST) st.res_hist[it + 1] = res;
+  }
+  DGNP_HIP(hipStreamSynchronize(s));
+  st.res_final = res;
+  st.status = code;
+  st.t_total = since(t0);
+  return code;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint: J^T lambda = dJ/dx, gradients dJ/dtheta = dJ/dtheta|_x - lambda^T dR/dtheta
+// ---------------------------------------------------------------------------
+int adjoint_solve(dgnp_ctx& c, const double* x, double* dJ_dbc, double* dJ_dPe, double* J_out, double* lambda,
+                  const dgnp_solve_opts& o, dgnp_solve_stats& st) {
+  const auto t0 = clk::now();
+  hipStream_t s = c.stream;
+  const int64_t N = c.N;
+  st = dgnp_solve_stats{};
+  const auto ts = clk::now();
+  set_state(c, x, o.prec, s);
+  st.t_setup = since(ts);
+  DevBuf<double> g, lam, dr, red;
+  g.alloc(size_t(N));
+  lam.alloc(size_t(N));
+  dr.alloc(size_t(N));
+  red.alloc(size_t(reduce_scratch_size()));
+  launch_dg(c.dim, c.p, c.m, false, M_OBJG, c.kargs(), c.d_x.p, nullptr, g.p, c.d_aux.p, s);
+  std::vector<double> part(static_cast<size_t>(2 * c.E));
+  DGNP_HIP(hipMemcpyAsync(part.data(), c.d_aux.p, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  DGNP_HIP(hipStreamSynchronize(s));
+  double J = 0.0, dJdPe_x = 0.0;
+  for (int64_t e = 0; e < c.E; ++e) {
+    J += part[size_t(2 * e)];
+    dJdPe_x += part[size_t(2 * e + 1)];
+  }
+  const double gn = vnorm2(g.p, N, red.p, s);
+  vfill<double>(lam.p, 0.0, N, s);
+  const auto tk = clk::now();
+  LinResult lr = fgmres(c, g.p, lam.p, o.rtol * gn, o.restart, o.max_lin_it, o.prec == DGNP_F32, true, o.pc_kind,
+                        true, o.verbose, s);
+  st.t_krylov = since(tk);
+  st.lin_its_total = lr.its;
+  st.refine_its_total = lr.refinements;
+  st.res0 = gn;
+  st.res_final = lr.res;
+  launch_dg(c.dim, c.p, c.m, false, M_DPE, c.kargs(), c.d_x.p, nullptr, dr.p, nullptr, s);
+  const double ldr = vdot(lam.p, dr.p, N, red.p, s);
+  if (dJ_dPe) *dJ_dPe = dJdPe_x - ldr;
+  if (J_out) *J_out = J;
+  if (dJ_dbc && c.n_bnode > 0) {
+    launch_dg(c.dim, c.p, c.m, false, M_DATAT, c.kargs(), c.d_x.p, lam.p, nullptr, c.d_aux.p, s);
+    std::vector<double> zeta(static_cast<size_t>(c.m) * c.n_bface * c.nqf);
+    DGNP_HIP(hipMemcpyAsync(zeta.data(), c.d_aux.p, zeta.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    DGNP_HIP(hipStreamSynchronize(s));
+    const int nn = c.nn, nq = c.nq;
+    for (int t = 0; t < 2 * c.dim; ++t) {
+      if (c.bnode_off[t] < 0) continue;
+      const int64_t nf = c.E / c.n[t / 2];
+      for (int64_t lin = 0; lin < nf; ++lin) {
+        const int64_t bf = c.btag_off[t] + lin;
+        for (int k = 1; k < c.m; ++k)
+          for (int jn = 0; jn < c.nfn; ++jn) {
+            const int ji = jn % nn, jj = jn / nn;
+            double acc = 0.0;
+            for (int qf = 0; qf < c.nqf; ++qf) {
+              const int qi = qf % nq, qj = qf / nq;
+              double psi = c.ref.B[size_t(qi * nn + ji)];
+              if (c.dim == 3) psi *= c.ref.B[size_t(qj * nn + jj)];
+              acc += psi * zeta[(size_t(k) * c.n_bface + bf) * c.nqf + qf];
+            }
+            dJ_dbc[size_t(k - 1) * c.n_bnode + c.bnode_off[t] + lin * c.nfn + jn] = -acc;
+          }
+      }
+    }
+  }
+  if (lambda) vcopy<double>(lam.p, lambda, N, s);
+  DGNP_HIP(hipStreamSynchronize(s));
+  st.t_total = since(t0);
+  st.status = lr.converged ? DGNP_OK : DGNP_E_NOCONV;
+  return st.status;
 }
 
 }  // namespace dgnp

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libdgnp.so")
 DGNP_OK, DGNP_E_ARG, DGNP_E_ALLOC, DGNP_E_HIP, DGNP_E_STATE, DGNP_E_NOCONV, DGNP_E_BREAKDOWN, \
     DGNP_E_NONFINITE = range(8)
 DGNP_F64, DGNP_F32 = 0, 1
+DGNP_STATE_ASSEMBLE_ONLY = 0x100
 DGNP_PC_P2, DGNP_PC_P1 = 0, 1
 MAX_HIST = 64
 
