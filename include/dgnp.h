@@ -206,8 +206,15 @@ int dgnp_adjoint(dgnp_ctx *ctx, const double *x, int32_t objective, double *dJ_d
  * double [n_b][n_b] (row = test function).  For tests and diagnostics. */
 int dgnp_get_block(dgnp_ctx *ctx, int32_t field, int64_t elem, int32_t slot, double *out);
 
-/* Per-kernel timing of the last apply/solve calls on this context (seconds,
- * summed since the last reset); names as in the profiler summaries. */
+/* Per-kernel event timing.  dgnp_profile(ctx, 1) makes the library record HIP
+ * events around its kernels on the stream they run on (small overhead per
+ * launch); dgnp_timer returns the summed device time in seconds and the number
+ * of launches of one region since the last reset (reset != 0 clears all).
+ * Region names: residual, jac_apply, jac_apply_f32, jacT_apply, jacT_apply_f32,
+ * assemble, block_inverse, ilu_factor, ilu_fwd, ilu_bwd, ilu_fwdT, ilu_bwdT,
+ * ilu_fwd_f32, ilu_bwd_f32, ilu_fwdT_f32, ilu_bwdT_f32, vcycle, vcycle_f32,
+ * bspmv, bspmv_f32, cgs2. */
+int dgnp_profile(dgnp_ctx *ctx, int32_t enable);
 int dgnp_timer(dgnp_ctx *ctx, const char *name, double *seconds, int64_t *calls, int32_t reset);
 
 void dgnp_destroy(dgnp_ctx *ctx);

@@ -242,6 +242,7 @@ int dgnp_connectivity(const dgnp_ctx* c, int32_t* elem_nbr, int32_t* face_elems,
 int dgnp_residual(dgnp_ctx* c, const double* x, double* r, void* stream) {
   return guard([&] {
     DGNP_REQUIRE(c && x && r, DGNP_E_ARG, "NULL argument");
+    ScopeTimer tm(*c, "residual", static_cast<hipStream_t>(stream));
     launch_dg(c->dim, c->p, c->m, false, M_RES, c->kargs(), x, nullptr, r, nullptr,
               static_cast<hipStream_t>(stream));
   });
@@ -324,10 +325,19 @@ int dgnp_get_block(dgnp_ctx* c, int32_t field, int64_t elem, int32_t slot, doubl
 int dgnp_timer(dgnp_ctx* c, const char* name, double* seconds, int64_t* calls, int32_t reset) {
   return guard([&] {
     DGNP_REQUIRE(c && name, DGNP_E_ARG, "NULL argument");
+    c->ev_resolve();
     auto it = c->timers.find(name);
     if (seconds) *seconds = it == c->timers.end() ? 0.0 : it->second.first;
     if (calls) *calls = it == c->timers.end() ? 0 : it->second.second;
     if (reset) c->timers.clear();
+  });
+}
+
+int dgnp_profile(dgnp_ctx* c, int32_t enable) {
+  return guard([&] {
+    DGNP_REQUIRE(c, DGNP_E_ARG, "NULL context");
+    c->ev_resolve();
+    c->profiling = enable != 0;
   });
 }
 

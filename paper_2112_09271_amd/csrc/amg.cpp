@@ -258,6 +258,9 @@ AmgHierarchy sa_setup(const Csr& A1, int max_levels, int coarse_size, double the
     H.R.push_back(std::move(R));
     H.A.push_back(std::move(Ac));
   }
+  if (H.A.back().n > 4096)
+    throw Error(DGNP_E_BREAKDOWN, "algebraic multigrid coarsening stalled at " + std::to_string(H.A.back().n) +
+                                      " unknowns");
   for (const Csr& A : H.A) {
     std::vector<double> d = diag_of(A), dinv(d.size());
     for (size_t i = 0; i < d.size(); ++i) dinv[i] = d[i] != 0.0 ? 1.0 / d[i] : 0.0;

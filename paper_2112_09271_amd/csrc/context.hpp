@@ -43,9 +43,43 @@ struct dgnp_ctx {
 
   dgnp::Precond* pc = nullptr;
   dgnp::Krylov* kry = nullptr;
+
+  // optional per-kernel event timing
+  bool profiling = false;
+  struct Pending {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> ev_pool;
   std::map<std::string, std::pair<double, int64_t>> timers;
+  hipEvent_t ev_get() {
+    if (!ev_pool.empty()) {
+      hipEvent_t e = ev_pool.back();
+      ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void ev_resolve() {
+    for (auto& p : pending) {
+      float ms = 0.0f;
+      if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        auto& t = timers[p.name];
+        t.first += 1e-3 * ms;
+        t.second += 1;
+      }
+      ev_pool.push_back(p.a);
+      ev_pool.push_back(p.b);
+    }
+    pending.clear();
+  }
 
   ~dgnp_ctx() {
+    ev_resolve();
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     dgnp::krylov_destroy(kry);
     dgnp::precond_destroy(pc);
   }
@@ -53,6 +87,25 @@ struct dgnp_ctx {
 };
 
 namespace dgnp {
+// records a pair of events around a region on stream s when profiling is on
+struct ScopeTimer {
+  dgnp_ctx& c;
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ScopeTimer(dgnp_ctx& ctx, const char* nm, hipStream_t st) : c(ctx), name(nm), s(st) {
+    if (c.profiling) {
+      a = c.ev_get();
+      if (a && hipEventRecord(a, s) != hipSuccess) a = nullptr;
+    }
+  }
+  ~ScopeTimer() {
+    if (!a) return;
+    hipEvent_t b = c.ev_get();
+    if (b && hipEventRecord(b, s) == hipSuccess) c.pending.push_back({name, a, b});
+    if (c.pending.size() > 100000) c.ev_resolve();
+  }
+};
 void build_tables(dgnp_ctx& c);                 // mesh, faces, boundary data (tables.cpp)
 void mms_exact(const dgnp_ctx& c, const double* x, double* phi, double* c1);
 void mms_source(const dgnp_ctx& c, const double* x, double* s_phi, double* s_c1);

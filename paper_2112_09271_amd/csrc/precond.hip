@@ -11,6 +11,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <type_traits>
 
 #include "amg.hpp"
@@ -229,11 +232,34 @@ static double lmax_level0(dgnp_ctx& c, Precond& P, hipStream_t s) {
   return lam;
 }
 
+static bool trace_setup() {
+  static const bool on = getenv("DGNP_TRACE_SETUP") != nullptr;
+  return on;
+}
+
+struct PhaseClock {
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  hipStream_t s;
+  explicit PhaseClock(hipStream_t st) : s(st) {}
+  void mark(const char* what) {
+    if (!trace_setup()) return;
+    (void)hipStreamSynchronize(s);
+    const auto now = std::chrono::steady_clock::now();
+    fprintf(stderr, "[setup] %-22s %8.3f ms\n", what, 1e3 * std::chrono::duration<double>(now - t).count());
+    t = now;
+  }
+};
+
 void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only) {
   Precond& P = *c.pc;
+  PhaseClock clk(s);
   const int64_t per_field = c.E * P.nslot * P.bsz;
   P.blk.alloc(size_t(c.m * per_field));
-  launch_assemble(c.dim, c.p, c.m, c.kargs(), c.d_x.p, P.blk.p, s);
+  {
+    ScopeTimer tm(c, "assemble", s);
+    launch_assemble(c.dim, c.p, c.m, c.kargs(), c.d_x.p, P.blk.p, s);
+  }
+  clk.mark("assemble");
   if (assemble_only) {
     DGNP_HIP(hipStreamSynchronize(s));
     P.ready = false;
@@ -242,12 +268,19 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only) {
   }
   // potential block: element-diagonal inverses (block-Jacobi smoother)
   P.dinv_phi.alloc(size_t(c.E * P.bsz));
-  launch_block_inverse(c.nb, c.E, P.blk.p, P.nslot, P.dinv_phi.p, s);
+  {
+    ScopeTimer tm(c, "block_inverse", s);
+    launch_block_inverse(c.nb, c.E, P.blk.p, P.nslot, P.dinv_phi.p, s);
+  }
+  clk.mark("block inverse");
   // concentration blocks: BILU(0) level by level
   for (int k = 1; k < c.m; ++k)
-    for (size_t l = 0; l + 1 < P.lev_ptr.size(); ++l)
+    for (size_t l = 0; l + 1 < P.lev_ptr.size(); ++l) {
+      ScopeTimer tm(c, "ilu_factor", s);
       launch_ilu_factor(c.nb, c.dim, P.blk.p + k * per_field, c.d_nbr.p, P.lev_elems.p, P.lev_ptr[l],
                         P.lev_ptr[l + 1] - P.lev_ptr[l], s);
+    }
+  clk.mark("ilu factor");
   // Galerkin projection of A_phiphi onto Q1 vertices, then host SA setup
   const int NV = 1 << c.dim;
   P.gal.alloc(size_t(c.E) * P.nslot * NV * NV);
@@ -255,8 +288,16 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only) {
   std::vector<double> gal(P.gal.n);
   DGNP_HIP(hipMemcpyAsync(gal.data(), P.gal.p, gal.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   DGNP_HIP(hipStreamSynchronize(s));
+  clk.mark("galerkin + copy");
   Csr A1 = vertex_matrix(c, P, gal);
-  AmgHierarchy H = sa_setup(A1, 12, 256, 0.08);
+  clk.mark("vertex matrix");
+  AmgHierarchy H = sa_setup(A1, 12, 256, 0.0);
+  clk.mark("sa setup");
+  if (trace_setup()) {
+    fprintf(stderr, "[setup] hierarchy: DG %lld", (long long)c.Nf);
+    for (auto& A : H.A) fprintf(stderr, " -> %d (nnz %zu)", A.n, A.v.size());
+    fprintf(stderr, "\n");
+  }
   P.mg.clear();
   P.mg.resize(H.A.size());
   for (size_t l = 0; l < H.A.size(); ++l) {
@@ -272,9 +313,12 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only) {
   }
   P.nc = H.A.back().n;
   P.cinv.upload(H.coarse_inv, s);
+  clk.mark("upload hierarchy");
   P.wd.clear();
   ensure_work(c, P);
+  clk.mark("work vectors");
   P.lmax0 = lmax_level0(c, P, s);
+  clk.mark("lmax level 0");
   P.ready = true;
   P.assembled = true;
   P.ready32 = false;
@@ -297,6 +341,7 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only) {
     P.cinv32.upload(ci, s);
     ensure_work32(c, P);
     P.ready32 = true;
+    clk.mark("float copies");
   }
   DGNP_HIP(hipStreamSynchronize(s));
 }
@@ -427,21 +472,22 @@ template <typename T>
 static void ilu_solve(dgnp_ctx& c, Precond& P, int k, bool transpose, const T* in, T* out, hipStream_t s) {
   const T* blk = Sel<T>::blk(P) + int64_t(k) * c.E * P.nslot * P.bsz;
   const int L = int(P.lev_ptr.size()) - 1;
-  if (!transpose) {
+  const bool f32 = std::is_same<T, float>::value;
+  static const char* names[4][2] = {{"ilu_fwd", "ilu_fwd_f32"}, {"ilu_bwd", "ilu_bwd_f32"},
+                                    {"ilu_fwdT", "ilu_fwdT_f32"}, {"ilu_bwdT", "ilu_bwdT_f32"}};
+  const int k0 = transpose ? 2 : 0;
+  T* aux = transpose ? Sel<T>::w(P, 4) : nullptr;  // level-0 work vector of length N_f
+  {
+    ScopeTimer tm(c, names[k0][f32], s);
     for (int l = 0; l < L; ++l)
-      launch_ilu_solve<T>(0, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, P.lev_ptr[l],
-                          P.lev_ptr[l + 1] - P.lev_ptr[l], in, out, nullptr, s);
+      launch_ilu_solve<T>(k0, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, P.lev_ptr[l],
+                          P.lev_ptr[l + 1] - P.lev_ptr[l], in, transpose ? aux : out, nullptr, s);
+  }
+  {
+    ScopeTimer tm(c, names[k0 + 1][f32], s);
     for (int l = L - 1; l >= 0; --l)
-      launch_ilu_solve<T>(1, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, P.lev_ptr[l],
-                          P.lev_ptr[l + 1] - P.lev_ptr[l], out, out, nullptr, s);
-  } else {
-    T* aux = Sel<T>::w(P, 4);  // level-0 work vector of length N_f
-    for (int l = 0; l < L; ++l)
-      launch_ilu_solve<T>(2, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, P.lev_ptr[l],
-                          P.lev_ptr[l + 1] - P.lev_ptr[l], in, aux, nullptr, s);
-    for (int l = L - 1; l >= 0; --l)
-      launch_ilu_solve<T>(3, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, P.lev_ptr[l],
-                          P.lev_ptr[l + 1] - P.lev_ptr[l], nullptr, out, aux, s);
+      launch_ilu_solve<T>(k0 + 1, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, P.lev_ptr[l],
+                          P.lev_ptr[l + 1] - P.lev_ptr[l], transpose ? nullptr : out, out, aux, s);
   }
 }
 
@@ -463,9 +509,13 @@ static void apply_t(dgnp_ctx& c, const T* r, T* z, bool transpose, int kind, hip
     jac_apply(c, u, y, f32, transpose, s);
     vcopy<T>(r, t, Nf, s);
     vaxpy<T>(T(-1), y, t, Nf, s);
+    ScopeTimer tm(c, f32 ? "vcycle_f32" : "vcycle", s);
     mg.vcycle(0, t, z);
   } else {
-    mg.vcycle(0, r, z);
+    {
+      ScopeTimer tm(c, f32 ? "vcycle_f32" : "vcycle", s);
+      mg.vcycle(0, r, z);
+    }
     vfill<T>(u + Nf, T(0), (c.m - 1) * Nf, s);
     vcopy<T>(z, u, Nf, s);
     jac_apply(c, u, y, f32, transpose, s);

@@ -32,6 +32,8 @@ void jac_apply(dgnp_ctx& c, const void* v, void* y, bool f32, bool transpose, hi
   DGNP_REQUIRE(c.has_state, DGNP_E_STATE, "jacobian_apply before set_state");
   DGNP_REQUIRE(!f32 || c.has_state32, DGNP_E_STATE, "float apply needs set_state with DGNP_F32");
   const void* xs = f32 ? static_cast<const void*>(c.d_x32.p) : static_cast<const void*>(c.d_x.p);
+  static const char* names[2][2] = {{"jac_apply", "jac_apply_f32"}, {"jacT_apply", "jacT_apply_f32"}};
+  ScopeTimer tm(c, names[transpose ? 1 : 0][f32 ? 1 : 0], s);
   launch_dg(c.dim, c.p, c.m, f32, transpose ? M_JACT : M_JAC, c.kargs(), xs, v, y, nullptr, s);
 }
 
@@ -148,6 +150,7 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
       double* h1 = K.hd.p + reduce_scratch_size();
       double* h2 = h1 + 64;
       double* ww = h2 + 64;
+      ScopeTimer tm(c, "cgs2", s);
       vdots(K.V.p, N, j + 1, w, N, K.hd.p, s);
       vcopy<double>(K.hd.p, h1, j + 1, s);
       vmaxpy(K.V.p, N, j + 1, h1, w, N, s);
@@ -286,7 +289,10 @@ int newton_solve(dgnp_ctx& c, double* x, const dgnp_solve_opts& o, dgnp_solve_st
   }
   const bool f32 = o.prec == DGNP_F32;
   auto resid = [&](const double* xv, double* rv) {
-    launch_dg(c.dim, c.p, c.m, false, M_RES, c.kargs(), xv, nullptr, rv, nullptr, s);
+    {
+      ScopeTimer tm(c, "residual", s);
+      launch_dg(c.dim, c.p, c.m, false, M_RES, c.kargs(), xv, nullptr, rv, nullptr, s);
+    }
     return vnorm2(rv, N, W.red.p, s);
   };
   double res = resid(x, W.r.p);

@@ -70,6 +70,7 @@ _SIGS = {
     "dgnp_adjoint": [_vp, _vp, C.c_int32, _vp, _vp, _vp, _vp, C.POINTER(dgnp_solve_opts),
                      C.POINTER(dgnp_solve_stats)],
     "dgnp_get_block": [_vp, C.c_int32, C.c_int64, C.c_int32, _vp],
+    "dgnp_profile": [_vp, C.c_int32],
     "dgnp_timer": [_vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32],
     "dgnp_destroy": [_vp],
     "dgnp_last_error": [],
@@ -263,6 +264,27 @@ class Problem:
         nb = self.Nf // self.E
         out = np.zeros((nb, nb))
         _check(lib().dgnp_get_block(self.ctx, field, elem, slot, out.ctypes.data))
+        return out
+
+    TIMER_NAMES = ("residual", "jac_apply", "jac_apply_f32", "jacT_apply", "jacT_apply_f32", "assemble",
+                   "block_inverse", "ilu_factor", "ilu_fwd", "ilu_bwd", "ilu_fwdT", "ilu_bwdT", "ilu_fwd_f32",
+                   "ilu_bwd_f32", "ilu_fwdT_f32", "ilu_bwdT_f32", "vcycle", "vcycle_f32", "bspmv",
+                   "bspmv_f32", "cgs2")
+
+    def profile(self, enable=True, reset=True):
+        """Turn per-kernel event timing on or off (reset clears the counters)."""
+        if reset:
+            _check(lib().dgnp_timer(self.ctx, b"residual", None, None, 1))
+        _check(lib().dgnp_profile(self.ctx, int(bool(enable))))
+
+    def timers(self):
+        """{region: (seconds, launches)} accumulated since the last reset."""
+        out = {}
+        for n in self.TIMER_NAMES:
+            sec, calls = C.c_double(), C.c_int64()
+            _check(lib().dgnp_timer(self.ctx, n.encode(), C.byref(sec), C.byref(calls), 0))
+            if calls.value:
+                out[n] = (sec.value, calls.value)
         return out
 
     @staticmethod
