@@ -192,6 +192,7 @@ int dgnp_setup(const dgnp_mesh* mesh, int32_t order, const dgnp_species* sp, con
       DGNP_REQUIRE(c->phi_bc[t] >= 0 && c->phi_bc[t] <= 1, DGNP_E_ARG, "unknown potential boundary kind");
     }
     c->stream = static_cast<hipStream_t>(stream);
+    DGNP_HIP(hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking));
     c->ref = make_ref_tables(order);
     {
       RefTables all[3] = {make_ref_tables(1), make_ref_tables(2), make_ref_tables(3)};
@@ -291,6 +292,8 @@ int dgnp_solve(dgnp_ctx* c, double* x, const dgnp_solve_opts* opts, dgnp_solve_s
     dgnp_solve_opts o = default_solve_opts();
     if (opts) o = *opts;
     dgnp_solve_stats st{};
+    DGNP_HIP(hipStreamSynchronize(c->stream));
+    DGNP_HIP(hipDeviceSynchronize());
     int code = newton_solve(*c, x, o, st);
     if (stats) *stats = st;
     if (code != DGNP_OK) throw Error(code, st.status == DGNP_E_NOCONV ? "Newton did not converge"
@@ -306,6 +309,7 @@ int dgnp_adjoint(dgnp_ctx* c, const double* x, int32_t objective, double* dJ_dbc
     dgnp_solve_opts o = default_solve_opts();
     if (opts) o = *opts;
     dgnp_solve_stats st{};
+    DGNP_HIP(hipDeviceSynchronize());
     int code = adjoint_solve(*c, x, dJ_dbc, dJ_dPe, J_out, lambda, o, st);
     if (stats) *stats = st;
     if (code != DGNP_OK) throw Error(code, "adjoint solve failed");

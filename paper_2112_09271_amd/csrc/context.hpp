@@ -29,7 +29,9 @@ struct dgnp_ctx {
   int64_t bnode_off[6] = {};     // first data node of each box face (-1: no data)
   std::vector<double> bc_conc;   // [m-1][n_bnode]
   dgnp::RefTables ref;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;   // the caller's stream at setup
+  hipStream_t work = nullptr;     // library stream for the synchronous drivers (graph capture)
+  uint64_t state_epoch = 0;       // bumped by every set_state (invalidates captured graphs)
 
   dgnp::DevBuf<int> d_nbr;
   dgnp::DevBuf<double> d_bcq;    // [m][n_bface][nqf]
@@ -82,6 +84,7 @@ struct dgnp_ctx {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     dgnp::krylov_destroy(kry);
     dgnp::precond_destroy(pc);
+    if (work) (void)hipStreamDestroy(work);
   }
   dgnp::KArgs kargs() const;
 };

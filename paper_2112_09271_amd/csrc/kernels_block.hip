@@ -470,11 +470,17 @@ __device__ inline T col_dot4(const T* __restrict__ M, const T* x, int c, int par
 }
 
 // forward: w_i = D_i^{-1} r_i - sum_{s lower} Lhat_{i,s} w_nbr
+// blockIdx.y selects one of several independent field blocks: block storage
+// advances by bstride, vectors by vstride.
 template <typename T, int NB, int DIM>
 __global__ void __launch_bounds__(BT) k_ilu_fwd(const T* __restrict__ blk, const int* __restrict__ nbr,
                                                 const int* __restrict__ lev_elems, int64_t first,
-                                                const T* __restrict__ r, T* __restrict__ w) {
+                                                const T* __restrict__ r, T* __restrict__ w, int64_t bstride,
+                                                int64_t vstride) {
   constexpr int NSLOT = 2 * DIM + 1;
+  blk += blockIdx.y * bstride;
+  r += blockIdx.y * vstride;
+  w += blockIdx.y * vstride;
   __shared__ T xs[DIM + 1][NB];
   const int tid = threadIdx.x, row = tid >> 2, part = tid & 3;
   const int64_t i = lev_elems[first + blockIdx.x];
@@ -498,8 +504,11 @@ __global__ void __launch_bounds__(BT) k_ilu_fwd(const T* __restrict__ blk, const
 template <typename T, int NB, int DIM>
 __global__ void __launch_bounds__(BT) k_ilu_bwd(const T* __restrict__ blk, const int* __restrict__ nbr,
                                                 const int* __restrict__ lev_elems, int64_t first,
-                                                const T* w, T* z) {
+                                                const T* w, T* z, int64_t bstride, int64_t vstride) {
   constexpr int NSLOT = 2 * DIM + 1;
+  blk += blockIdx.y * bstride;
+  w += blockIdx.y * vstride;
+  z += blockIdx.y * vstride;
   __shared__ T xs[DIM][NB];
   __shared__ T wi[NB];
   const int tid = threadIdx.x, row = tid >> 2, part = tid & 3;
@@ -524,8 +533,12 @@ __global__ void __launch_bounds__(BT) k_ilu_bwd(const T* __restrict__ blk, const
 template <typename T, int NB, int DIM>
 __global__ void __launch_bounds__(BT) k_ilu_fwdT(const T* __restrict__ blk, const int* __restrict__ nbr,
                                                  const int* __restrict__ lev_elems, int64_t first,
-                                                 const T* __restrict__ r, T* __restrict__ aw) {
+                                                 const T* __restrict__ r, T* __restrict__ aw, int64_t bstride,
+                                                 int64_t vstride) {
   constexpr int NSLOT = 2 * DIM + 1;
+  blk += blockIdx.y * bstride;
+  r += blockIdx.y * vstride;
+  aw += blockIdx.y * vstride;
   __shared__ T xs[DIM][NB];
   const int tid = threadIdx.x, col = tid >> 2, part = tid & 3;
   const int64_t i = lev_elems[first + blockIdx.x];
@@ -549,8 +562,12 @@ __global__ void __launch_bounds__(BT) k_ilu_fwdT(const T* __restrict__ blk, cons
 template <typename T, int NB, int DIM>
 __global__ void __launch_bounds__(BT) k_ilu_bwdT(const T* __restrict__ blk, const int* __restrict__ nbr,
                                                  const int* __restrict__ lev_elems, int64_t first,
-                                                 T* __restrict__ bw, T* __restrict__ z) {
+                                                 T* __restrict__ bw, T* __restrict__ z, int64_t bstride,
+                                                 int64_t vstride) {
   constexpr int NSLOT = 2 * DIM + 1;
+  blk += blockIdx.y * bstride;
+  bw += blockIdx.y * vstride;
+  z += blockIdx.y * vstride;
   __shared__ T xs[DIM][NB];
   __shared__ T bi_s[NB];
   const int tid = threadIdx.x, col = tid >> 2, part = tid & 3;
@@ -773,41 +790,50 @@ void launch_ilu_factor(int nb, int dim, double* blk, const int* nbr, const int* 
 
 template <typename T, int NB, int DIM>
 static void solve_t(int kind, const T* blk, const int* nbr, const int* lev, int64_t first, int64_t count,
-                    const T* in, T* out, T* aux, hipStream_t s) {
-  const dim3 g = dim3(unsigned(count)), b = dim3(BT);
+                    int nfields, int64_t bstride, int64_t vstride, const T* in, T* out, T* aux, hipStream_t s) {
+  const dim3 g = dim3(unsigned(count), unsigned(nfields)), b = dim3(BT);
   switch (kind) {
-    case 0: hipLaunchKernelGGL((k_ilu_fwd<T, NB, DIM>), g, b, 0, s, blk, nbr, lev, first, in, out); break;
-    case 1: hipLaunchKernelGGL((k_ilu_bwd<T, NB, DIM>), g, b, 0, s, blk, nbr, lev, first, in, out); break;
-    case 2: hipLaunchKernelGGL((k_ilu_fwdT<T, NB, DIM>), g, b, 0, s, blk, nbr, lev, first, in, out); break;
-    case 3: hipLaunchKernelGGL((k_ilu_bwdT<T, NB, DIM>), g, b, 0, s, blk, nbr, lev, first, aux, out); break;
+    case 0:
+      hipLaunchKernelGGL((k_ilu_fwd<T, NB, DIM>), g, b, 0, s, blk, nbr, lev, first, in, out, bstride, vstride);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_ilu_bwd<T, NB, DIM>), g, b, 0, s, blk, nbr, lev, first, in, out, bstride, vstride);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_ilu_fwdT<T, NB, DIM>), g, b, 0, s, blk, nbr, lev, first, in, out, bstride, vstride);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_ilu_bwdT<T, NB, DIM>), g, b, 0, s, blk, nbr, lev, first, aux, out, bstride, vstride);
+      break;
   }
 }
 
 template <typename T>
 void launch_ilu_solve(int kind, int nb, int dim, const T* blk, const int* nbr, const int* lev, int64_t first,
-                      int64_t count, const T* in, T* out, T* aux, hipStream_t s) {
-  if (count == 0) return;
+                      int64_t count, int nfields, int64_t bstride, int64_t vstride, const T* in, T* out, T* aux,
+                      hipStream_t s) {
+  if (count == 0 || nfields == 0) return;
   if (dim == 3) {
     switch (nb) {
-      case 8: solve_t<T, 8, 3>(kind, blk, nbr, lev, first, count, in, out, aux, s); break;
-      case 27: solve_t<T, 27, 3>(kind, blk, nbr, lev, first, count, in, out, aux, s); break;
-      case 64: solve_t<T, 64, 3>(kind, blk, nbr, lev, first, count, in, out, aux, s); break;
+      case 8: solve_t<T, 8, 3>(kind, blk, nbr, lev, first, count, nfields, bstride, vstride, in, out, aux, s); break;
+      case 27: solve_t<T, 27, 3>(kind, blk, nbr, lev, first, count, nfields, bstride, vstride, in, out, aux, s); break;
+      case 64: solve_t<T, 64, 3>(kind, blk, nbr, lev, first, count, nfields, bstride, vstride, in, out, aux, s); break;
       default: throw Error(DGNP_E_ARG, "unsupported block size");
     }
   } else {
     switch (nb) {
-      case 4: solve_t<T, 4, 2>(kind, blk, nbr, lev, first, count, in, out, aux, s); break;
-      case 9: solve_t<T, 9, 2>(kind, blk, nbr, lev, first, count, in, out, aux, s); break;
-      case 16: solve_t<T, 16, 2>(kind, blk, nbr, lev, first, count, in, out, aux, s); break;
+      case 4: solve_t<T, 4, 2>(kind, blk, nbr, lev, first, count, nfields, bstride, vstride, in, out, aux, s); break;
+      case 9: solve_t<T, 9, 2>(kind, blk, nbr, lev, first, count, nfields, bstride, vstride, in, out, aux, s); break;
+      case 16: solve_t<T, 16, 2>(kind, blk, nbr, lev, first, count, nfields, bstride, vstride, in, out, aux, s); break;
       default: throw Error(DGNP_E_ARG, "unsupported block size");
     }
   }
   DGNP_HIP(hipGetLastError());
 }
-template void launch_ilu_solve<double>(int, int, int, const double*, const int*, const int*, int64_t, int64_t,
-                                       const double*, double*, double*, hipStream_t);
-template void launch_ilu_solve<float>(int, int, int, const float*, const int*, const int*, int64_t, int64_t,
-                                      const float*, float*, float*, hipStream_t);
+template void launch_ilu_solve<double>(int, int, int, const double*, const int*, const int*, int64_t, int64_t, int,
+                                       int64_t, int64_t, const double*, double*, double*, hipStream_t);
+template void launch_ilu_solve<float>(int, int, int, const float*, const int*, const int*, int64_t, int64_t, int,
+                                      int64_t, int64_t, const float*, float*, float*, hipStream_t);
 
 template <typename T, int NB, int DIM>
 static void bsp_t(int64_t E, const T* blk, const int* nbr, const T* x, const T* b, T alpha, T beta, T* y,

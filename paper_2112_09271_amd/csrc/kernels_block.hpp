@@ -11,10 +11,12 @@ void launch_block_inverse(int nb, int64_t E, const double* blk, int nslot, doubl
 void launch_ilu_factor(int nb, int dim, double* blk, const int* nbr, const int* lev, int64_t first,
                        int64_t count, hipStream_t s);
 // kind 0: forward, 1: backward (in may alias out), 2: transposed forward,
-// 3: transposed backward (aux holds the forward result and is overwritten)
+// 3: transposed backward (aux holds the forward result and is overwritten).
+// nfields independent field blocks at block stride bstride / vector stride vstride.
 template <typename T>
 void launch_ilu_solve(int kind, int nb, int dim, const T* blk, const int* nbr, const int* lev, int64_t first,
-                      int64_t count, const T* in, T* out, T* aux, hipStream_t s);
+                      int64_t count, int nfields, int64_t bstride, int64_t vstride, const T* in, T* out, T* aux,
+                      hipStream_t s);
 template <typename T>
 void launch_bspmv(int nb, int dim, int64_t E, const T* blk, const int* nbr, const T* x, const T* b, T alpha,
                   T beta, T* y, hipStream_t s);

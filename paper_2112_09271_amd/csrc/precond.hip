@@ -468,26 +468,32 @@ struct Mg {
   }
 };
 
+// ILU solves of all concentration blocks at once (one launch per level covers
+// every field): in/out point at the first concentration field (field 1).
 template <typename T>
-static void ilu_solve(dgnp_ctx& c, Precond& P, int k, bool transpose, const T* in, T* out, hipStream_t s) {
-  const T* blk = Sel<T>::blk(P) + int64_t(k) * c.E * P.nslot * P.bsz;
+static void ilu_solve(dgnp_ctx& c, Precond& P, bool transpose, const T* in, T* out, hipStream_t s) {
+  const int64_t fstride = c.E * P.nslot * P.bsz;
+  const T* blk = Sel<T>::blk(P) + fstride;
   const int L = int(P.lev_ptr.size()) - 1;
+  const int nf = c.m - 1;
   const bool f32 = std::is_same<T, float>::value;
   static const char* names[4][2] = {{"ilu_fwd", "ilu_fwd_f32"}, {"ilu_bwd", "ilu_bwd_f32"},
                                     {"ilu_fwdT", "ilu_fwdT_f32"}, {"ilu_bwdT", "ilu_bwdT_f32"}};
   const int k0 = transpose ? 2 : 0;
-  T* aux = transpose ? Sel<T>::w(P, 4) : nullptr;  // level-0 work vector of length N_f
+  T* aux = transpose ? Sel<T>::vN(P) + c.Nf : nullptr;  // concentration part of a work vector
   {
     ScopeTimer tm(c, names[k0][f32], s);
     for (int l = 0; l < L; ++l)
       launch_ilu_solve<T>(k0, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, P.lev_ptr[l],
-                          P.lev_ptr[l + 1] - P.lev_ptr[l], in, transpose ? aux : out, nullptr, s);
+                          P.lev_ptr[l + 1] - P.lev_ptr[l], nf, fstride, c.Nf, in, transpose ? aux : out,
+                          nullptr, s);
   }
   {
     ScopeTimer tm(c, names[k0 + 1][f32], s);
     for (int l = L - 1; l >= 0; --l)
       launch_ilu_solve<T>(k0 + 1, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, P.lev_ptr[l],
-                          P.lev_ptr[l + 1] - P.lev_ptr[l], transpose ? nullptr : out, out, aux, s);
+                          P.lev_ptr[l + 1] - P.lev_ptr[l], nf, fstride, c.Nf, transpose ? nullptr : out, out,
+                          aux, s);
   }
 }
 
@@ -503,7 +509,7 @@ static void apply_t(dgnp_ctx& c, const T* r, T* z, bool transpose, int kind, hip
   // kinds: "c first" (P2, or P1 transposed) and "phi first" (P1, or P2 transposed)
   const bool c_first = (kind == DGNP_PC_P2) != transpose;
   if (c_first) {
-    for (int k = 1; k < c.m; ++k) ilu_solve<T>(c, P, k, transpose, r + k * Nf, z + k * Nf, s);
+    ilu_solve<T>(c, P, transpose, r + Nf, z + Nf, s);
     vfill<T>(u, T(0), Nf, s);
     vcopy<T>(z + Nf, u + Nf, (c.m - 1) * Nf, s);
     jac_apply(c, u, y, f32, transpose, s);
@@ -519,11 +525,9 @@ static void apply_t(dgnp_ctx& c, const T* r, T* z, bool transpose, int kind, hip
     vfill<T>(u + Nf, T(0), (c.m - 1) * Nf, s);
     vcopy<T>(z, u, Nf, s);
     jac_apply(c, u, y, f32, transpose, s);
-    for (int k = 1; k < c.m; ++k) {
-      vcopy<T>(r + k * Nf, t + k * Nf, Nf, s);
-      vaxpy<T>(T(-1), y + k * Nf, t + k * Nf, Nf, s);
-      ilu_solve<T>(c, P, k, transpose, t + k * Nf, z + k * Nf, s);
-    }
+    vcopy<T>(r + Nf, t + Nf, (c.m - 1) * Nf, s);
+    vaxpy<T>(T(-1), y + Nf, t + Nf, (c.m - 1) * Nf, s);
+    ilu_solve<T>(c, P, transpose, t + Nf, z + Nf, s);
   }
 }
 

@@ -4,6 +4,7 @@
 // adjoint of the outflow-flux objective.
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "blas.hpp"
@@ -15,6 +16,7 @@ using clk = std::chrono::steady_clock;
 static double since(clk::time_point t0) { return std::chrono::duration<double>(clk::now() - t0).count(); }
 
 void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assemble_only) {
+  ++c.state_epoch;
   c.d_x.alloc(size_t(c.N));
   if (x != c.d_x.p) vcopy<double>(x, c.d_x.p, c.N, s);
   c.has_state = true;
@@ -44,7 +46,7 @@ dgnp_solve_opts default_solve_opts() {
   o.max_newton = 30;
   o.prec = DGNP_F64;
   o.lin_rtol = 1e-3;
-  o.restart = 30;
+  o.restart = 60;
   o.max_lin_it = 600;
   o.pc_kind = DGNP_PC_P2;
   o.verbose = 0;
@@ -60,13 +62,65 @@ dgnp_solve_opts default_solve_opts() {
 // steps of an iterative refinement.
 // ---------------------------------------------------------------------------
 struct Krylov {
-  DevBuf<double> V, Z, w, r, hd;
-  DevBuf<float> Z32, v32, w32;
+  DevBuf<double> V, Z, w, r, hd, vt, zt;
+  DevBuf<float> Z32, v32, w32, zt32;
   int restart = 0;
   int64_t n = 0;
+  // captured "preconditioner + Jacobian" graphs, keyed by (f32, transpose)
+  hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  uint64_t gepoch[2][2] = {{0, 0}, {0, 0}};
+  int gpc[2][2] = {{-1, -1}, {-1, -1}};
+  ~Krylov() {
+    for (auto& row : gexec)
+      for (auto& g : row)
+        if (g) (void)hipGraphExecDestroy(g);
+  }
 };
 
 void krylov_destroy(Krylov* k) { delete k; }
+
+static bool graphs_enabled(const dgnp_ctx& c) {
+  const char* e = getenv("DGNP_NO_GRAPHS");
+  return !c.profiling && !(e && e[0] && e[0] != '0');
+}
+
+// z_stage = P in_stage; w = J z_stage, either captured once per linearisation
+// point as a HIP graph (the sequence of ~10^2 small level-scheduled kernels
+// then launches as one unit) or issued directly.
+static void pc_then_jac(dgnp_ctx& c, Krylov& K, bool f32, bool transpose, int pc_kind, hipStream_t s) {
+  const void* in = f32 ? static_cast<const void*>(K.v32.p) : static_cast<const void*>(K.vt.p);
+  void* zs = f32 ? static_cast<void*>(K.zt32.p) : static_cast<void*>(K.zt.p);
+  void* w = f32 ? static_cast<void*>(K.w32.p) : static_cast<void*>(K.w.p);
+  if (!graphs_enabled(c)) {
+    precond_apply(c, in, zs, f32, transpose, pc_kind, s);
+    jac_apply(c, zs, w, f32, transpose, s);
+    return;
+  }
+  const int a = f32 ? 1 : 0, b = transpose ? 1 : 0;
+  if (!K.gexec[a][b] || K.gepoch[a][b] != c.state_epoch || K.gpc[a][b] != pc_kind) {
+    if (K.gexec[a][b]) DGNP_HIP(hipGraphExecDestroy(K.gexec[a][b]));
+    K.gexec[a][b] = nullptr;
+    hipGraph_t g = nullptr;
+    DGNP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+      precond_apply(c, in, zs, f32, transpose, pc_kind, s);
+      jac_apply(c, zs, w, f32, transpose, s);
+    } catch (...) {
+      (void)hipStreamEndCapture(s, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    DGNP_HIP(hipStreamEndCapture(s, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    DGNP_HIP(e);
+    K.gexec[a][b] = ex;
+    K.gepoch[a][b] = c.state_epoch;
+    K.gpc[a][b] = pc_kind;
+  }
+  DGNP_HIP(hipGraphLaunch(K.gexec[a][b], s));
+}
 
 static Krylov& krylov(dgnp_ctx& c, int restart, bool f32) {
   if (!c.kry) c.kry = new Krylov();
@@ -85,8 +139,13 @@ static Krylov& krylov(dgnp_ctx& c, int restart, bool f32) {
     K->Z32.alloc(size_t(restart) * c.N);
     K->v32.alloc(size_t(c.N));
     K->w32.alloc(size_t(c.N));
+    K->zt32.alloc(size_t(c.N));
   }
-  if (!f32 && !K->Z.p) K->Z.alloc(size_t(restart) * c.N);
+  if (!f32 && !K->Z.p) {
+    K->Z.alloc(size_t(restart) * c.N);
+    K->vt.alloc(size_t(c.N));
+    K->zt.alloc(size_t(c.N));
+  }
   return *K;
 }
 
@@ -136,15 +195,14 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
       double* vj = K.V.p + int64_t(j) * N;
       double* w = K.w.p;
       if (f32) {
-        float* zj = K.Z32.p + int64_t(j) * N;
         cvt_d2f(vj, K.v32.p, N, s);
-        precond_apply(c, K.v32.p, zj, true, transpose, pc_kind, s);
-        jac_apply(c, zj, K.w32.p, true, transpose, s);
+        pc_then_jac(c, K, true, transpose, pc_kind, s);
+        vcopy<float>(K.zt32.p, K.Z32.p + int64_t(j) * N, N, s);
         cvt_f2d(K.w32.p, w, N, s);
       } else {
-        double* zj = K.Z.p + int64_t(j) * N;
-        precond_apply(c, vj, zj, false, transpose, pc_kind, s);
-        jac_apply(c, zj, w, false, transpose, s);
+        vcopy<double>(vj, K.vt.p, N, s);
+        pc_then_jac(c, K, false, transpose, pc_kind, s);
+        vcopy<double>(K.zt.p, K.Z.p + int64_t(j) * N, N, s);
       }
       // classical Gram-Schmidt, twice; coefficients stay on the device until one copy
       double* h1 = K.hd.p + reduce_scratch_size();
@@ -268,7 +326,7 @@ struct NewtonWork {
 
 int newton_solve(dgnp_ctx& c, double* x, const dgnp_solve_opts& o, dgnp_solve_stats& st) {
   const auto t0 = clk::now();
-  hipStream_t s = c.stream;
+  hipStream_t s = c.work;
   const int64_t N = c.N;
   NewtonWork W;
   W.r.alloc(size_t(N));
@@ -358,7 +416,7 @@ int newton_solve(dgnp_ctx& c, double* x, const dgnp_solve_opts& o, dgnp_solve_st
 int adjoint_solve(dgnp_ctx& c, const double* x, double* dJ_dbc, double* dJ_dPe, double* J_out, double* lambda,
                   const dgnp_solve_opts& o, dgnp_solve_stats& st) {
   const auto t0 = clk::now();
-  hipStream_t s = c.stream;
+  hipStream_t s = c.work;
   const int64_t N = c.N;
   st = dgnp_solve_stats{};
   const auto ts = clk::now();

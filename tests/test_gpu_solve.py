@@ -68,3 +68,22 @@ def test_adjoint_matches_oracle(name):
         assert _rel(dg, dg_ref) <= 1e-7
         assert abs(dpe - dpe_ref) <= 1e-7 * abs(dpe_ref)
         assert _rel(host(lam), lam_ref) <= 1e-7
+
+
+def test_graph_replay_matches_eager():
+    """The FGMRES preconditioner + Jacobian sequence is captured once per
+    linearisation point and replayed every iteration; the whole solve (many
+    replays, eager work in between) must be bitwise identical to eager launches."""
+    import os
+
+    from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64
+    cfg, od, gp = pair("cfg3s", with_oracle=False)
+    for prec in (DGNP_F64, DGNP_F32):
+        os.environ["DGNP_NO_GRAPHS"] = "1"
+        try:
+            xe, ste = gp.solve(rtol=1e-10, prec=prec)
+        finally:
+            del os.environ["DGNP_NO_GRAPHS"]
+        xg, stg = gp.solve(rtol=1e-10, prec=prec)
+        assert ste.lin_its_total == stg.lin_its_total
+        assert np.array_equal(host(xe), host(xg))
