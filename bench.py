@@ -1,21 +1,23 @@
 """Benchmark: Newton-GMRES time-to-1e-8 (mixed precision and FP64) on one MI355X.
 
-A step is one complete mixed-precision solve of the CNP DG system of the
+A step is one complete mixed-precision solve of the CNP DG system on the
 16^3-hex, p = 2, three-ion cube (vortex flow, Pe = 1e3) from the paper's
 initial guess to ||R|| <= 1e-8 ||R_0||: residual, block assembly, BILU(0)
-factorisation, multigrid setup, FGMRES with the block-triangular
-preconditioner (ILU solves, V-cycle, coupling applies), FP32 Jacobian applies
-under FP64 refinement, line search.  Inputs are seeded synthetic boundary data
-already resident on the GPU when timing starts.
+factorisation, multigrid set-up, FGMRES with the block-triangular
+preconditioner (ILU solves, V-cycle, coupling applies) and FP32 Jacobian
+applies under FP64 residuals and refinement, backtracking line search.  The
+seeded synthetic inputs are resident on the GPU before timing starts.
 
-Prints one JSON line.  Extra fields: the FP64 time-to-solution on the same
-input, the adjoint gradient time, the Jacobian-apply bandwidth on the largest
-channel (128x32x16 hexes, p = 3), the roofline of the dominant kernel and the
+One JSON line is printed.  Besides the contract fields it carries the FP64
+time-to-solution on the same input, the adjoint-gradient time, the
+Jacobian-apply bandwidth on the largest channel (128x32x16 hexes, p = 3,
+12.6M DOFs), the roofline of the dominant kernel of the timed solve and the
 CPU oracle baseline.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,7 +26,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_HBM_GBS = 8000.0
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+PEAK_FP32_TFLOPS = 157.3       # vector FP32
+PEAK_FP64_TFLOPS = 78.6        # vector FP64
+METRIC = "Newton-GMRES time-to-1e-8 (FP64 vs mixed); Jacobian-apply HBM GB/s"
 
 
 def parse():
@@ -33,9 +38,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--apply-workload", default="cfg5")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extra", action="store_true", help="skip FP64 / adjoint / large-apply legs")
-    ap.add_argument("--profile", action="store_true", help="per-kernel event timing in the library")
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP64, adjoint and large-apply legs")
+    ap.add_argument("--only-apply", action="store_true", help="run only the large Jacobian-apply leg")
     return ap.parse_args()
 
 
@@ -43,22 +49,148 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# ---- algorithmic byte and flop counts -------------------------------------------
+def ilu_sweep_bytes(cfg, word):
+    """Algorithmic HBM bytes of one forward BILU(0) sweep over all concentration
+    blocks: every element reads its D^-1 block and the scaled coupling block of
+    each lower neighbour, its right-hand side and the neighbours' solution
+    values, and writes its own solution."""
+    import numpy as np
+    n = np.array(cfg.n[: cfg.dim])
+    E = int(np.prod(n))
+    nb = (cfg.p + 1) ** cfg.dim
+    n_low = sum(E // n[a] * (n[a] - 1) for a in range(cfg.dim))  # lower-neighbour couplings
+    per_field = ((E + n_low) * nb * nb + (2 * E + n_low) * nb) * word
+    return float((cfg.m - 1) * per_field), cfg.n[0] + cfg.n[1] + (cfg.n[2] if cfg.dim == 3 else 1) - (cfg.dim - 1)
+
+
+def japply_bytes(N, word):
+    """Algorithmic bytes of one Jacobian apply: the input vector and the
+    linearisation state are read once and the output written once."""
+    return 3 * N * word
+
+
+def japply_flops(cfg):
+    """Floating-point operations of the sum-factorised contractions of one
+    Jacobian apply as the kernel performs them (2 per multiply-add): two
+    volume interpolations (state, input) and one integration per element; per
+    element face four trace evaluations (own and neighbour, state and input)
+    and one face integration.  The pointwise flux arithmetic is not counted."""
+    import numpy as np
+    d, p, m = cfg.dim, cfg.p, cfg.m
+    nn, nq = p + 1, p + 2
+    E = int(np.prod(cfg.n[: d]))
+    if d == 3:
+        vol = m * (2 * nn ** 3 * nq + 3 * nn ** 2 * nq ** 2 + 4 * nn * nq ** 3)
+        trace = m * (nn ** 3 + 2 * nn * nn * nq + 2 * nq * nq * nn)
+        finteg = m * (2 * nn * nq * nq + 2 * nn * nn * nq + nn ** 3)
+    else:
+        vol = m * (2 * nn * nn * nq + 3 * nn * nq * nq)
+        trace = m * (nn * nn + 2 * nn * nq)
+        finteg = m * (2 * nn * nq + nn * nn)
+    per_elem = 3 * vol + 2 * d * (4 * trace + finteg)
+    return 2.0 * per_elem * E
+
+
+def source_hash(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2112_09271_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_key, src_hash):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(kernel_key)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_hash") != src_hash:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+# ---- legs ---------------------------------------------------------------------------
+def cpu_baseline():
+    """The oracle (NumPy/SciPy, SuperLU) solving the same physics on a bounded
+    sample: the 4^3-element cube (1/64 of the elements), to the same 1e-8."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import solve as osolve
+    from oracle.dg import DG
+    from oracle.problem import Problem as OProblem
+    from workload import boundary_data, get_config
+    cfg = get_config("cfg2t")
+    od = DG(OProblem(cfg, boundary_data(cfg)))
+    t0 = time.perf_counter()
+    x, hist = osolve.newton(od, tol=1e-8)
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": dt, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle Newton + SuperLU to 1e-8 on the same physics with 4^3 elements "
+                      f"({od.N} DOFs, 1/64 of the workload's elements; {len(hist) - 1} Newton steps); "
+                      "SuperLU factorisation is single-threaded, BLAS parts use the listed threads"}
+
+
+def apply_bandwidth(name, reps=20):
+    """Jacobian apply (FP32 and FP64) on the largest channel, timed with HIP
+    events on the stream the kernels run on, rotating 4 input/output pairs."""
+    import torch
+
+    from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64, DGNP_STATE_APPLY_ONLY, Problem
+    from workload import boundary_data, get_config, random_state, random_vector
+    cfg = get_config(name)
+    prob = Problem(cfg, boundary_data(cfg))
+    x = torch.as_tensor(random_state(cfg), device="cuda")
+    out = {"workload": f"{cfg.name}: {cfg.note}", "dofs": prob.N}
+    for prec, tag, word, dt_ in ((DGNP_F32, "f32", 4, torch.float32), (DGNP_F64, "f64", 8, torch.float64)):
+        prob.set_state(x, prec=prec | DGNP_STATE_APPLY_ONLY)
+        vs = [torch.as_tensor(random_vector(cfg, 100 + i), device="cuda").to(dt_) for i in range(4)]
+        ys = [torch.empty_like(v) for v in vs]
+        from paper_2112_09271_amd import dgnp as D
+        st = torch.cuda.current_stream().cuda_stream
+        for i in range(3):
+            D.dgnp_jacobian_apply(prob.ctx, vs[i % 4].data_ptr(), ys[i % 4].data_ptr(), prec, 0, st)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for i in range(reps):
+            D.dgnp_jacobian_apply(prob.ctx, vs[i % 4].data_ptr(), ys[i % 4].data_ptr(), prec, 0, st)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3 / reps
+        gbs = japply_bytes(prob.N, word) / sec / 1e9
+        tfl = japply_flops(cfg) / sec / 1e12
+        out[tag] = {"us_per_apply": 1e6 * sec, "GBps": gbs, "hbm_frac": gbs / PEAK_HBM_GBS,
+                    "contraction_TFLOPs": tfl,
+                    "alu_frac": tfl / (PEAK_FP32_TFLOPS if word == 4 else PEAK_FP64_TFLOPS)}
+        log(f"[bench] J apply {tag} on {cfg.name}: {1e6 * sec:.1f} us, {gbs:.0f} GB/s, {tfl:.2f} TFLOP/s")
+    prob.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "run with --gpus 1", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): this build has no "
+              "multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
 
     from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64, Problem
-    from workload import boundary_data, get_config, random_state, random_vector
+    from workload import boundary_data, get_config
 
     torch.cuda.set_device(0)
+    if args.only_apply:
+        print(json.dumps({"jacobian_apply": apply_bandwidth(args.apply_workload)}), flush=True)
+        return
     cfg = get_config(args.workload)
-    data = boundary_data(cfg)
-    prob = Problem(cfg, data)
+    prob = Problem(cfg, boundary_data(cfg))
     log(f"[bench] workload {cfg.name}: {cfg.note}, N = {prob.N} DOFs")
 
     def solve(prec):
@@ -74,20 +206,38 @@ def main():
     for i in range(args.warmup):
         _, st, dt = solve(DGNP_F32)
         log(f"[bench] warmup {i}: {dt:.3f}s newton {st.newton_its} fgmres {st.lin_its_total}")
-    if args.profile:
-        prob.profile(True)
     times = []
     for i in range(args.steps):
         x32, st32, dt = solve(DGNP_F32)
         times.append(dt)
         log(f"[bench] step {i}: {dt:.3f}s newton {st32.newton_its} fgmres {st32.lin_its_total} "
             f"setup {st32.t_setup:.3f}s krylov {st32.t_krylov:.3f}s")
-    kern = prob.timers() if args.profile else {}
-    if args.profile:
-        prob.profile(False)
     t_mixed = float(np.mean(times))
+
+    # one more solve with per-kernel HIP events (not part of `value`): the library
+    # records an event pair around every kernel of the timed regions on its stream
+    prob.profile(True)
+    solve(DGNP_F32)
+    kern = prob.timers()
+    prob.profile(False)
+    ilu_regions = {k: v for k, v in kern.items() if k.startswith("ilu_fwd") or k.startswith("ilu_bwd")}
+    dominant = max(kern.items(), key=lambda kv: kv[1][0])
+    ilu_bytes, ilu_levels = ilu_sweep_bytes(cfg, 4)
+    fwd = kern.get("ilu_fwd_f32", (0.0, 1))
+    per_launch_bytes = ilu_bytes / ilu_levels
+    avg = fwd[0] / fwd[1]
+    achieved = per_launch_bytes / avg / 1e9
+    roofline = {"kernel": "k_ilu_fwd<float> (level-scheduled BILU(0) forward solve, both concentration "
+                          "blocks per launch)",
+                "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "avg_launch_us": 1e6 * avg, "launches": fwd[1],
+                "bytes_per_launch": per_launch_bytes,
+                "traffic": measured_traffic("k_ilu_fwd_f32_cfg2", source_hash("kernels_block.hip"))}
+    log(f"[bench] dominant region {dominant[0]}: {dominant[1][0]:.3f}s in {dominant[1][1]} launches; "
+        f"ILU forward {1e6 * avg:.2f} us/launch, {achieved:.0f} GB/s")
+
     out = {
-        "metric": "Newton-GMRES time-to-1e-8 (FP64 vs mixed); Jacobian-apply HBM GB/s",
+        "metric": METRIC,
         "value": t_mixed,
         "unit": "s",
         "n_gpus": 1,
@@ -97,26 +247,34 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 apply+preconditioner / f64 residual, Arnoldi, refinement",
-        "data": "synthetic (seeded inflow data U[0.5,1.5])",
+        "dtype": "f32 apply+preconditioner, f64 residual/Arnoldi/refinement",
+        "data": "synthetic (seeded inflow data U[0.5,1.5], random-free solve)",
         "config": {"workload": f"{cfg.name}: {cfg.note}", "elements": list(cfg.n), "order": cfg.p,
                    "ions": cfg.m, "dofs": prob.N, "newton_rtol": cfg.newton_tol,
                    "newton_its": st32.newton_its, "fgmres_its": st32.lin_its_total},
+        "roofline": roofline,
+        "kernel_seconds_per_solve": {k: round(v[0], 6) for k, v in kern.items()},
     }
-    if kern:
-        out["kernels"] = kern
     if not args.no_extra:
         x64, st64, t64 = solve(DGNP_F64)
         out["fp64_time_s"] = t64
-        out["mixed_speedup"] = t64 / t_mixed
-        d = (x64 - x32).norm().item() / x64.norm().item()
-        out["mixed_vs_fp64_rel_l2"] = d
+        out["mixed_speedup_vs_fp64"] = t64 / t_mixed
+        out["mixed_vs_fp64_rel_l2"] = (x64 - x32).norm().item() / x64.norm().item()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         J, dg, dpe, lam, ast = prob.adjoint(x32, prec=DGNP_F32, rtol=1e-8)
         torch.cuda.synchronize()
         out["adjoint_time_s"] = time.perf_counter() - t0
-        log(f"[bench] fp64 {t64:.3f}s, adjoint {out['adjoint_time_s']:.3f}s, mixed vs fp64 {d:.2e}")
+        log(f"[bench] fp64 {t64:.3f}s, adjoint {out['adjoint_time_s']:.3f}s")
+        prob.close()
+        ja = apply_bandwidth(args.apply_workload)
+        ja["traffic_f32"] = measured_traffic("k_dg_jac_f32_cfg5", source_hash("kernels_dg.hip", "dg_device.hpp",
+                                                                              "pointwise.hpp"))
+        out["jacobian_apply"] = ja
+    if not args.no_cpu:
+        cb = cpu_baseline()
+        log(f"[bench] cpu oracle: {cb['value']:.2f}s ({cb['sample']})")
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

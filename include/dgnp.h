@@ -53,9 +53,11 @@ enum {
   DGNP_E_NONFINITE = 7   /* NaN/Inf met in a residual or norm */
 };
 enum { DGNP_F64 = 0, DGNP_F32 = 1 };
-/* flag OR-ed into the `prec` of dgnp_set_state: assemble the blocks but skip
- * the factorisations and the multigrid setup (block inspection in tests) */
-enum { DGNP_STATE_ASSEMBLE_ONLY = 0x100 };
+/* flags OR-ed into the `prec` of dgnp_set_state: ASSEMBLE_ONLY assembles the
+ * blocks but skips the factorisations and the multigrid setup (block
+ * inspection); APPLY_ONLY stores the linearisation point for
+ * dgnp_jacobian_apply and builds no preconditioner at all. */
+enum { DGNP_STATE_ASSEMBLE_ONLY = 0x100, DGNP_STATE_APPLY_ONLY = 0x200 };
 /* boundary kinds per box face, faces tagged 0..5 = x-, x+, y-, y+, z-, z+ */
 enum { DGNP_C_WALL = 0, DGNP_C_DIRICHLET = 1, DGNP_C_INFLOW = 2, DGNP_C_OUTFLOW = 3 };
 enum { DGNP_PHI_NEUMANN0 = 0, DGNP_PHI_DIRICHLET = 1 };

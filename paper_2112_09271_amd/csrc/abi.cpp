@@ -261,9 +261,10 @@ int dgnp_set_state(dgnp_ctx* c, const double* x, int32_t prec, void* stream) {
   return guard([&] {
     DGNP_REQUIRE(c && x, DGNP_E_ARG, "NULL argument");
     const bool asm_only = (prec & DGNP_STATE_ASSEMBLE_ONLY) != 0;
-    prec &= ~DGNP_STATE_ASSEMBLE_ONLY;
+    const bool apply_only = (prec & DGNP_STATE_APPLY_ONLY) != 0;
+    prec &= ~(DGNP_STATE_ASSEMBLE_ONLY | DGNP_STATE_APPLY_ONLY);
     DGNP_REQUIRE(prec == DGNP_F64 || prec == DGNP_F32, DGNP_E_ARG, "prec must be F64 or F32");
-    set_state(*c, x, prec, static_cast<hipStream_t>(stream), asm_only);
+    set_state(*c, x, prec, static_cast<hipStream_t>(stream), asm_only, apply_only);
   });
 }
 

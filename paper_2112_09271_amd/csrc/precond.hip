@@ -346,6 +346,10 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only) {
   DGNP_HIP(hipStreamSynchronize(s));
 }
 
+void precond_invalidate(dgnp_ctx& c) {
+  if (c.pc) c.pc->ready = c.pc->ready32 = c.pc->assembled = false;
+}
+
 void get_block(dgnp_ctx& c, int field, int64_t elem, int slot, double* out) {
   DGNP_REQUIRE(c.pc && c.pc->assembled, DGNP_E_STATE, "no assembled blocks before set_state");
   Precond& P = *c.pc;
@@ -481,19 +485,18 @@ static void ilu_solve(dgnp_ctx& c, Precond& P, bool transpose, const T* in, T* o
                                     {"ilu_fwdT", "ilu_fwdT_f32"}, {"ilu_bwdT", "ilu_bwdT_f32"}};
   const int k0 = transpose ? 2 : 0;
   T* aux = transpose ? Sel<T>::vN(P) + c.Nf : nullptr;  // concentration part of a work vector
-  {
+  // timed per level launch (one event pair per kernel) when profiling is on
+  for (int l = 0; l < L; ++l) {
     ScopeTimer tm(c, names[k0][f32], s);
-    for (int l = 0; l < L; ++l)
-      launch_ilu_solve<T>(k0, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, P.lev_ptr[l],
-                          P.lev_ptr[l + 1] - P.lev_ptr[l], nf, fstride, c.Nf, in, transpose ? aux : out,
-                          nullptr, s);
+    launch_ilu_solve<T>(k0, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, P.lev_ptr[l],
+                        P.lev_ptr[l + 1] - P.lev_ptr[l], nf, fstride, c.Nf, in, transpose ? aux : out, nullptr,
+                        s);
   }
-  {
+  for (int l = L - 1; l >= 0; --l) {
     ScopeTimer tm(c, names[k0 + 1][f32], s);
-    for (int l = L - 1; l >= 0; --l)
-      launch_ilu_solve<T>(k0 + 1, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, P.lev_ptr[l],
-                          P.lev_ptr[l + 1] - P.lev_ptr[l], nf, fstride, c.Nf, transpose ? nullptr : out, out,
-                          aux, s);
+    launch_ilu_solve<T>(k0 + 1, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, P.lev_ptr[l],
+                        P.lev_ptr[l + 1] - P.lev_ptr[l], nf, fstride, c.Nf, transpose ? nullptr : out, out, aux,
+                        s);
   }
 }
 

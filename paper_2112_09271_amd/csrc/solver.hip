@@ -15,7 +15,7 @@ namespace dgnp {
 using clk = std::chrono::steady_clock;
 static double since(clk::time_point t0) { return std::chrono::duration<double>(clk::now() - t0).count(); }
 
-void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assemble_only) {
+void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assemble_only, bool apply_only) {
   ++c.state_epoch;
   c.d_x.alloc(size_t(c.N));
   if (x != c.d_x.p) vcopy<double>(x, c.d_x.p, c.N, s);
@@ -26,7 +26,10 @@ void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assem
     cvt_d2f(c.d_x.p, c.d_x32.p, c.N, s);
     c.has_state32 = true;
   }
-  precond_numeric(c, prec == DGNP_F32, s, assemble_only);
+  if (apply_only)
+    precond_invalidate(c);
+  else
+    precond_numeric(c, prec == DGNP_F32, s, assemble_only);
   DGNP_HIP(hipStreamSynchronize(s));
 }
 

@@ -10,10 +10,12 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only = 
 void precond_apply(dgnp_ctx& c, const void* r, void* z, bool f32, bool transpose, int pc_kind,
                    hipStream_t s);                                     // precond.hip
 void get_block(dgnp_ctx& c, int field, int64_t elem, int slot, double* out);
+void precond_invalidate(dgnp_ctx& c);
 void vcycle_phi(dgnp_ctx& c, const double* b, double* x, hipStream_t s);     // precond.hip
 void phi_block_apply(dgnp_ctx& c, const double* x, double* y, hipStream_t s); // precond.hip
 
-void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assemble_only = false);
+void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assemble_only = false,
+               bool apply_only = false);
 void jac_apply(dgnp_ctx& c, const void* v, void* y, bool f32, bool transpose, hipStream_t s);
 dgnp_solve_opts default_solve_opts();
 int newton_solve(dgnp_ctx& c, double* x, const dgnp_solve_opts& o, dgnp_solve_stats& st);

@@ -19,6 +19,7 @@ DGNP_OK, DGNP_E_ARG, DGNP_E_ALLOC, DGNP_E_HIP, DGNP_E_STATE, DGNP_E_NOCONV, DGNP
     DGNP_E_NONFINITE = range(8)
 DGNP_F64, DGNP_F32 = 0, 1
 DGNP_STATE_ASSEMBLE_ONLY = 0x100
+DGNP_STATE_APPLY_ONLY = 0x200
 DGNP_PC_P2, DGNP_PC_P1 = 0, 1
 MAX_HIST = 64
 
