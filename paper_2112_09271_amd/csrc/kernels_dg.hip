@@ -18,34 +18,54 @@ namespace dgnp {
 
 void upload_ref_tables(const RefTables* tabs, int count) { upload_ref_tables_tu(tabs, count); }
 
+#define OP_NT(D, P) ((D) == 3 ? ((P) == 3 ? 256 : 128) : 64)
+
+// One work-group per element.  Phases (each a parallel loop followed by a
+// barrier):
+//   volume   sum-factorised interpolation of the state (and input vector) to the
+//            Gauss points, pointwise flux, transposed contraction -> s_o;
+//   faces    all 2d faces together: F1 traces (value and d/dx_ax) at the face
+//            nodes of own and neighbour element (neighbours read from global
+//            memory), F2/F3 tangential interpolation to the face Gauss points,
+//            F4 numerical flux -> own-side coefficients, F5 tangential
+//            transposes, F6 accumulation into the own element's nodes.
+// Block b works on element (b mod 8) * ceil(E/8) + b / 8: work-groups are
+// dispatched round-robin over the 8 XCDs, so each XCD sweeps one contiguous
+// slab of elements and the neighbour reads of the face terms stay in its L2.
 template <int DIM, int P, int MF, typename T, int MODE>
-__global__ void __launch_bounds__(DG_NT(DIM, P))
+__global__ void __launch_bounds__(OP_NT(DIM, P))
     k_dg(KArgs A, const T* __restrict__ xs, const T* __restrict__ vin, T* __restrict__ out,
-         double* __restrict__ aux) {
+         double* __restrict__ aux, int64_t eper) {
   using S = Sz<DIM, P>;
-  constexpr int NN = S::NN, NQ = S::NQ, NB = S::NB, NQV = S::NQV, NFN = S::NFN, NQF = S::NQF,
-                NT = S::NT;
+  constexpr int NN = S::NN, NQ = S::NQ, NB = S::NB, NQV = S::NQV, NFN = S::NFN, NQF = S::NQF;
+  constexpr int NT = OP_NT(DIM, P);
+  constexpr bool HAS_V = (MODE == M_JAC || MODE == M_JACT || MODE == M_DATAT);
+  constexpr bool VOLUME = (MODE == M_RES || MODE == M_JAC || MODE == M_JACT || MODE == M_DPE);
+  constexpr bool NEED_NB = VOLUME;  // objective and data modes use the own trace only
+  constexpr int NARR = HAS_V ? 2 : 1;
+  constexpr int NC = DIM + 1;
+  constexpr int NFACE = 2 * DIM;
   constexpr int NBT = MF * NB;
-  constexpr int QV = MF * (DIM + 1) * NQV;
+  constexpr int QV = MF * NC * NQV;
   constexpr int S1 = DIM == 3 ? MF * 2 * NN * NN * NQ : MF * 2 * NN * NQ;
   constexpr int S2 = DIM == 3 ? MF * 3 * NN * NQ * NQ : 0;
   constexpr int VOLR = 2 * QV + S1 + S2;
-  constexpr int TRQ = MF * 2 * NQF;
-  constexpr int TRN = MF * 2 * NFN;
-  constexpr int TRM = DIM == 3 ? MF * 2 * NN * NQ : 0;
-  constexpr int FACER = 2 * NBT + 5 * TRQ + TRN + TRM;
-  constexpr int REG = VOLR > FACER ? VOLR : FACER;
-  constexpr bool HAS_V = (MODE == M_JAC || MODE == M_JACT || MODE == M_DATAT);
-  __shared__ T pool[3 * NBT + REG];
+  constexpr int NROW = NFACE * 2 * NARR * MF * 2;  // trace rows: face, side, array, field, value/dn
+  constexpr int NCF = NFACE * MF * 2 * NQF;
+  constexpr int FACR = DIM == 3 ? NROW * (NN * NQ + NQF) : NROW * (NFN + NQF);
+  constexpr int REG = VOLR > FACR ? VOLR : FACR;
+  __shared__ T s_x[NBT];
+  __shared__ T s_v[HAS_V ? NBT : 1];
+  __shared__ T s_o[NBT];
+  __shared__ T R[REG];
   __shared__ STab<P, T> tb;
+  __shared__ int s_nb[NFACE];
 
-  T* s_x = pool;
-  T* s_v = pool + NBT;
-  T* s_o = pool + 2 * NBT;
-  T* R = pool + 3 * NBT;
+  const int64_t bid = blockIdx.x;
+  const int64_t e = (bid % 8) * eper + bid / 8;
+  if (e >= A.E) return;
   const int tid = threadIdx.x;
   load_tab<P, T>(tb, tid, NT);
-
   Phys<T, MF> ph;
   for (int k = 0; k < MF - 1; ++k) {
     ph.zD[k] = T(A.z[k] * A.D[k]);
@@ -54,8 +74,6 @@ __global__ void __launch_bounds__(DG_NT(DIM, P))
     ph.b[k] = T(A.b[k]);
   }
   ph.delta = T(A.delta);
-
-  const int64_t e = blockIdx.x;
   const int64_t Nf = A.E * NB;
   int eid[3];
   eid[0] = int(e % A.n[0]);
@@ -63,16 +81,16 @@ __global__ void __launch_bounds__(DG_NT(DIM, P))
   eid[2] = DIM == 3 ? int(e / (int64_t(A.n[0]) * A.n[1])) : 0;
   T ih[3];
   for (int i = 0; i < 3; ++i) ih[i] = T(2.0 / A.h[i]);
-
   for (int i = tid; i < NBT; i += NT) {
     const int f = i / NB, l = i % NB;
     s_x[i] = xs[f * Nf + e * NB + l];
     if constexpr (HAS_V) s_v[i] = vin[f * Nf + e * NB + l];
   }
+  if (tid < NFACE) s_nb[tid] = A.nbr[e * NFACE + tid];
   __syncthreads();
 
-  // ------------------------------------------------------------------ volume
-  if constexpr (MODE == M_RES || MODE == M_JAC || MODE == M_JACT || MODE == M_DPE) {
+  // ---------------------------------------------------------------- volume
+  if constexpr (VOLUME) {
     T* q_x = R;
     T* q_v = R + QV;
     T* t1 = R + 2 * QV;
@@ -99,8 +117,8 @@ __global__ void __launch_bounds__(DG_NT(DIM, P))
       }
       T val[MF], grad[MF][DIM];
       for (int f = 0; f < MF; ++f) {
-        val[f] = q_x[(f * (DIM + 1)) * NQV + qi];
-        for (int d = 0; d < DIM; ++d) grad[f][d] = q_x[(f * (DIM + 1) + 1 + d) * NQV + qi];
+        val[f] = q_x[(f * NC) * NQV + qi];
+        for (int d = 0; d < DIM; ++d) grad[f][d] = q_x[(f * NC + 1 + d) * NQV + qi];
       }
       T cv[MF], cg[MF][DIM];
       if constexpr (MODE == M_RES) {
@@ -110,23 +128,23 @@ __global__ void __launch_bounds__(DG_NT(DIM, P))
       } else if constexpr (MODE == M_JAC) {
         T dv[MF], dg[MF][DIM];
         for (int f = 0; f < MF; ++f) {
-          dv[f] = q_v[(f * (DIM + 1)) * NQV + qi];
-          for (int d = 0; d < DIM; ++d) dg[f][d] = q_v[(f * (DIM + 1) + 1 + d) * NQV + qi];
+          dv[f] = q_v[(f * NC) * NQV + qi];
+          for (int d = 0; d < DIM; ++d) dg[f][d] = q_v[(f * NC + 1 + d) * NQV + qi];
           cv[f] = T(0);
         }
         vol_jac<T, MF, DIM>(ph, val, grad, u, dv, dg, cg);
       } else if constexpr (MODE == M_JACT) {
         T gw[MF][DIM];
         for (int f = 0; f < MF; ++f)
-          for (int d = 0; d < DIM; ++d) gw[f][d] = q_v[(f * (DIM + 1) + 1 + d) * NQV + qi];
+          for (int d = 0; d < DIM; ++d) gw[f][d] = q_v[(f * NC + 1 + d) * NQV + qi];
         vol_jacT<T, MF, DIM>(ph, val, grad, u, gw, cv, cg);
       } else {
         for (int f = 0; f < MF; ++f) cv[f] = T(0);
         vol_dpe<T, MF, DIM>(ph, val, uh, cg);
       }
       for (int f = 0; f < MF; ++f) {
-        q_v[(f * (DIM + 1)) * NQV + qi] = cv[f] * w;
-        for (int d = 0; d < DIM; ++d) q_v[(f * (DIM + 1) + 1 + d) * NQV + qi] = cg[f][d] * w * ih[d];
+        q_v[(f * NC) * NQV + qi] = cv[f] * w;
+        for (int d = 0; d < DIM; ++d) q_v[(f * NC + 1 + d) * NQV + qi] = cg[f][d] * w * ih[d];
       }
     }
     __syncthreads();
@@ -136,91 +154,138 @@ __global__ void __launch_bounds__(DG_NT(DIM, P))
     __syncthreads();
   }
 
-  // ------------------------------------------------------------------- faces
-  double obj_j = 0.0, obj_dpe = 0.0;
-  for (int slot = 0; slot < 2 * DIM; ++slot) {
-    const int ax = slot >> 1;
-    const int side = (slot & 1) ? 1 : -1;
-    const int nb = A.nbr[e * 2 * DIM + slot];
-    const bool interior = nb >= 0;
-    const int cbc = interior ? 0 : A.c_bc[slot];
-    const bool phid = interior ? false : (A.phi_bc[slot] == DGNP_PHI_DIRICHLET);
-    if constexpr (MODE == M_OBJG) {
-      if (interior || slot != A.objective_tag) continue;
-    } else if constexpr (MODE == M_DATAT) {
-      if (interior || (cbc != BC_DIRICHLET && cbc != BC_INFLOW)) continue;
-    } else if constexpr (MODE == M_DPE) {
-      if (!interior && cbc == BC_WALL) continue;
-    } else {
-      if (!interior && cbc == BC_WALL && !phid) continue;
-    }
-    T* n_x = R;
-    T* n_v = R + NBT;
-    T* tox = R + 2 * NBT;
-    T* tov = tox + TRQ;
-    T* tnx = tov + TRQ;
-    T* tnv = tnx + TRQ;
-    T* cf = tnv + TRQ;
-    T* tn = cf + TRQ;
-    T* tm = tn + TRN;
-    trace<DIM, P, MF, NT, T>(s_x, ax, side, tox, tn, tm, tb, ih[ax], tid);
-    if constexpr (HAS_V) trace<DIM, P, MF, NT, T>(s_v, ax, side, tov, tn, tm, tb, ih[ax], tid);
-    const bool need_nb = interior && (MODE == M_RES || MODE == M_JAC || MODE == M_JACT || MODE == M_DPE);
-    if (need_nb) {
-      for (int i = tid; i < NBT; i += NT) {
-        const int f = i / NB, l = i % NB;
-        n_x[i] = xs[f * Nf + int64_t(nb) * NB + l];
-        if constexpr (HAS_V) n_v[i] = vin[f * Nf + int64_t(nb) * NB + l];
+  // ----------------------------------------------------------------- faces
+  constexpr int OFF_FN = DIM == 3 ? NROW * NN * NQ : 0;     // F1 output
+  constexpr int OFF_FM = 0;                                 // F2 output (3D)
+  constexpr int OFF_FQ = DIM == 3 ? OFF_FN : NROW * NFN;    // face-point traces
+  T* fn = R + OFF_FN;
+  T* fm = R + OFF_FM;
+  T* fq = R + OFF_FQ;
+  T* cf = R;                                                // coefficients (after F3)
+  T* tmt = R + NCF;                                         // transposes (after F4)
+  T* tnt = R + NCF + (DIM == 3 ? NFACE * MF * 2 * NN * NQ : 0);
+  // F1: face-node traces of own / neighbour element
+  for (int idx = tid; idx < NROW * NFN; idx += NT) {
+    const int ij = idx % NFN;
+    int row = idx / NFN;
+    const int c2 = row % 2;
+    row /= 2;
+    const int f = row % MF;
+    row /= MF;
+    const int ar = row % NARR;
+    row /= NARR;
+    const int sd = row % 2;
+    const int fc = row / 2;
+    const int ax = fc >> 1;
+    const int side = (fc & 1) ? 1 : -1;
+    const int sside = sd == 0 ? side : -side;
+    const int i = ij % NN, j = ij / NN;
+    T val = T(0);
+    if (sd == 0) {
+      const T* u = (ar == 0 ? s_x : s_v) + f * NB;
+      if (c2 == 0) {
+        val = u[face_node<DIM, NN>(ax, sside < 0 ? 0 : P, i, j)];
+      } else {
+        const T* De = tb.De[sside < 0 ? 0 : 1];
+        for (int l = 0; l < NN; ++l) val += De[l] * u[face_node<DIM, NN>(ax, l, i, j)];
+        val *= ih[ax];
       }
-      __syncthreads();
-      trace<DIM, P, MF, NT, T>(n_x, ax, -side, tnx, tn, tm, tb, ih[ax], tid);
-      if constexpr (HAS_V) trace<DIM, P, MF, NT, T>(n_v, ax, -side, tnv, tn, tm, tb, ih[ax], tid);
+    } else if (NEED_NB && s_nb[fc] >= 0) {
+      const T* u = (ar == 0 ? xs : vin) + f * Nf + int64_t(s_nb[fc]) * NB;
+      if (c2 == 0) {
+        val = u[face_node<DIM, NN>(ax, sside < 0 ? 0 : P, i, j)];
+      } else {
+        const T* De = tb.De[sside < 0 ? 0 : 1];
+        for (int l = 0; l < NN; ++l) val += De[l] * u[face_node<DIM, NN>(ax, l, i, j)];
+        val *= ih[ax];
+      }
     }
-    // boundary-face index for the data arrays
-    int64_t bf = 0;
-    if (!interior) {
-      int64_t lin;
-      if constexpr (DIM == 3)
-        lin = ax == 0 ? eid[1] + int64_t(A.n[1]) * eid[2]
-                      : (ax == 1 ? eid[0] + int64_t(A.n[0]) * eid[2] : eid[0] + int64_t(A.n[0]) * eid[1]);
-      else
-        lin = ax == 0 ? eid[1] : eid[0];
-      bf = A.btag_off[slot] + lin;
+    fn[idx] = val;
+  }
+  __syncthreads();
+  if constexpr (DIM == 3) {
+    for (int idx = tid; idx < NROW * NN * NQ; idx += NT) {
+      const int qi = idx % NQ, j = (idx / NQ) % NN, row = idx / (NQ * NN);
+      T s = T(0);
+#pragma unroll
+      for (int i = 0; i < NN; ++i) s += tb.B[qi * NN + i] * fn[row * NFN + j * NN + i];
+      fm[idx] = s;
     }
-    const int t1ax = DIM == 3 ? (ax == 0 ? 1 : 0) : 1 - ax;
-    const int t2ax = DIM == 3 ? (ax == 2 ? 1 : 2) : 0;
-    const int own = side > 0 ? 0 : 1;  // own element is the minus side when the face is at +1
-    for (int qf = tid; qf < NQF; qf += NT) {
+    __syncthreads();
+    for (int idx = tid; idx < NROW * NQF; idx += NT) {
+      const int qi = idx % NQ, qj = (idx / NQ) % NQ, row = idx / NQF;
+      T s = T(0);
+#pragma unroll
+      for (int j = 0; j < NN; ++j) s += tb.B[qj * NN + j] * fm[(row * NN + j) * NQ + qi];
+      fq[idx] = s;
+    }
+    __syncthreads();
+  } else {
+    for (int idx = tid; idx < NROW * NQF; idx += NT) {
+      const int qi = idx % NQ, row = idx / NQ;
+      T s = T(0);
+#pragma unroll
+      for (int i = 0; i < NN; ++i) s += tb.B[qi * NN + i] * fn[row * NFN + i];
+      fq[idx] = s;
+    }
+    __syncthreads();
+  }
+  // F4: numerical fluxes at every face point of every face
+  double obj_j = 0.0, obj_dpe = 0.0;
+  auto trow = [&](int fc, int sd, int ar, int f, int c2) { return ((((fc * 2 + sd) * NARR + ar) * MF + f) * 2 + c2); };
+  for (int idx = tid; idx < NFACE * NQF; idx += NT) {
+    const int qf = idx % NQF, fc = idx / NQF;
+    const int ax = fc >> 1;
+    const int side = (fc & 1) ? 1 : -1;
+    const int nb = s_nb[fc];
+    const bool interior = nb >= 0;
+    const int cbc = interior ? 0 : A.c_bc[fc];
+    const bool phid = interior ? false : (A.phi_bc[fc] == DGNP_PHI_DIRICHLET);
+    T Fo[MF], Go[MF];
+    for (int f = 0; f < MF; ++f) Fo[f] = Go[f] = T(0);
+    bool active;
+    if constexpr (MODE == M_OBJG)
+      active = !interior && fc == A.objective_tag;
+    else if constexpr (MODE == M_DATAT)
+      active = !interior && (cbc == BC_DIRICHLET || cbc == BC_INFLOW);
+    else if constexpr (MODE == M_DPE)
+      active = interior || cbc != BC_WALL;
+    else
+      active = interior || cbc != BC_WALL || phid;
+    T w = T(0);
+    if (active) {
       const int qi = qf % NQ, qj = qf / NQ;
+      const int t1ax = DIM == 3 ? (ax == 0 ? 1 : 0) : 1 - ax;
+      const int t2ax = DIM == 3 ? (ax == 2 ? 1 : 2) : 0;
       double xp[3];
       xp[ax] = A.lo[ax] + (eid[ax] + (side > 0 ? 1.0 : 0.0)) * A.h[ax];
       xp[t1ax] = A.lo[t1ax] + (eid[t1ax] + 0.5 * (double(tb.X[qi]) + 1.0)) * A.h[t1ax];
-      T w = T(0.5 * A.h[t1ax]) * tb.W[qi];
+      w = T(0.5 * A.h[t1ax]) * tb.W[qi];
       if constexpr (DIM == 3) {
         xp[t2ax] = A.lo[t2ax] + (eid[t2ax] + 0.5 * (double(tb.X[qj]) + 1.0)) * A.h[t2ax];
         w *= T(0.5 * A.h[t2ax]) * tb.W[qj];
       }
       double uhd[3];
       velocity_hat(A, xp, DIM, uhd);
-      T Fo[MF], Go[MF];
       if (interior) {
+        const int own = side > 0 ? 0 : 1;  // the own element is the minus side of a +1 face
         const T un = T(A.Pe * uhd[ax]);
         T v[2][MF], g[2][MF];
         for (int f = 0; f < MF; ++f) {
-          v[own][f] = tox[(f * 2 + 0) * NQF + qf];
-          g[own][f] = tox[(f * 2 + 1) * NQF + qf];
-          v[1 - own][f] = tnx[(f * 2 + 0) * NQF + qf];
-          g[1 - own][f] = tnx[(f * 2 + 1) * NQF + qf];
+          v[own][f] = fq[trow(fc, 0, 0, f, 0) * NQF + qf];
+          g[own][f] = fq[trow(fc, 0, 0, f, 1) * NQF + qf];
+          v[1 - own][f] = fq[trow(fc, 1, 0, f, 0) * NQF + qf];
+          g[1 - own][f] = fq[trow(fc, 1, 0, f, 1) * NQF + qf];
         }
         if constexpr (MODE == M_RES) {
           face_res<T, MF>(ph, v, g, un, own, Fo, Go);
         } else if constexpr (MODE == M_JAC || MODE == M_JACT) {
           T tv[2][MF], tg[2][MF];
           for (int f = 0; f < MF; ++f) {
-            tv[own][f] = tov[(f * 2 + 0) * NQF + qf];
-            tg[own][f] = tov[(f * 2 + 1) * NQF + qf];
-            tv[1 - own][f] = tnv[(f * 2 + 0) * NQF + qf];
-            tg[1 - own][f] = tnv[(f * 2 + 1) * NQF + qf];
+            tv[own][f] = fq[trow(fc, 0, NARR - 1, f, 0) * NQF + qf];
+            tg[own][f] = fq[trow(fc, 0, NARR - 1, f, 1) * NQF + qf];
+            tv[1 - own][f] = fq[trow(fc, 1, NARR - 1, f, 0) * NQF + qf];
+            tg[1 - own][f] = fq[trow(fc, 1, NARR - 1, f, 1) * NQF + qf];
           }
           if constexpr (MODE == M_JAC)
             face_jac<T, MF>(ph, v, g, tv, tg, un, own, Fo, Go);
@@ -229,18 +294,21 @@ __global__ void __launch_bounds__(DG_NT(DIM, P))
         } else if constexpr (MODE == M_DPE) {
           face_dpe<T, MF>(ph, v, g, un, T(uhd[ax]), own, Fo, Go);
         }
-        for (int f = 0; f < MF; ++f) {
-          cf[(f * 2 + 0) * NQF + qf] = Fo[f] * w;
-          cf[(f * 2 + 1) * NQF + qf] = Go[f] * w;
-        }
       } else {
+        int64_t lin;
+        if constexpr (DIM == 3)
+          lin = ax == 0 ? eid[1] + int64_t(A.n[1]) * eid[2]
+                        : (ax == 1 ? eid[0] + int64_t(A.n[0]) * eid[2] : eid[0] + int64_t(A.n[0]) * eid[1]);
+        else
+          lin = ax == 0 ? eid[1] : eid[0];
+        const int64_t bf = A.btag_off[fc] + lin;
         const T sd = T(side);
         const T un = T(side * A.Pe * uhd[ax]);
         const T uhn = T(side * uhd[ax]);
         T v[MF], g[MF], gd[MF];
         for (int f = 0; f < MF; ++f) {
-          v[f] = tox[(f * 2 + 0) * NQF + qf];
-          g[f] = sd * tox[(f * 2 + 1) * NQF + qf];
+          v[f] = fq[trow(fc, 0, 0, f, 0) * NQF + qf];
+          g[f] = sd * fq[trow(fc, 0, 0, f, 1) * NQF + qf];
           gd[f] = T(A.bcq[(f * A.n_bface + bf) * NQF + qf]);
         }
         if constexpr (MODE == M_RES) {
@@ -248,8 +316,8 @@ __global__ void __launch_bounds__(DG_NT(DIM, P))
         } else if constexpr (MODE == M_JAC || MODE == M_JACT) {
           T tv[MF], tg[MF];
           for (int f = 0; f < MF; ++f) {
-            tv[f] = tov[(f * 2 + 0) * NQF + qf];
-            tg[f] = sd * tov[(f * 2 + 1) * NQF + qf];
+            tv[f] = fq[trow(fc, 0, NARR - 1, f, 0) * NQF + qf];
+            tg[f] = sd * fq[trow(fc, 0, NARR - 1, f, 1) * NQF + qf];
           }
           if constexpr (MODE == M_JAC)
             bnd_jac<T, MF>(ph, v, g, tv, tg, un, cbc, phid, gd, Fo, Go);
@@ -260,7 +328,6 @@ __global__ void __launch_bounds__(DG_NT(DIM, P))
         } else if constexpr (MODE == M_OBJG) {
           // J = int (q_1 . n) c_1: dJ/dc_1 = Q, dJ/d(dphi/dn) = -z_1 D_1 c_1
           const T Q = un - ph.zD[0] * g[0];
-          for (int f = 0; f < MF; ++f) Fo[f] = Go[f] = T(0);
           Fo[1] = Q;
           Go[0] = -ph.zD[0] * v[1];
           obj_j += double(Q * v[1] * w);
@@ -268,23 +335,22 @@ __global__ void __launch_bounds__(DG_NT(DIM, P))
         } else if constexpr (MODE == M_DATAT) {
           T wv[MF], wg[MF], od[MF];
           for (int f = 0; f < MF; ++f) {
-            wv[f] = tov[(f * 2 + 0) * NQF + qf];
-            wg[f] = sd * tov[(f * 2 + 1) * NQF + qf];
+            wv[f] = fq[trow(fc, 0, NARR - 1, f, 0) * NQF + qf];
+            wg[f] = sd * fq[trow(fc, 0, NARR - 1, f, 1) * NQF + qf];
           }
           bnd_dataT<T, MF>(ph, g, wv, wg, un, cbc, od);
           for (int f = 1; f < MF; ++f) aux[(f * A.n_bface + bf) * NQF + qf] = double(od[f] * w);
-          for (int f = 0; f < MF; ++f) Fo[f] = Go[f] = T(0);
         }
-        for (int f = 0; f < MF; ++f) {
-          cf[(f * 2 + 0) * NQF + qf] = Fo[f] * w;
-          cf[(f * 2 + 1) * NQF + qf] = Go[f] * w * sd;
-        }
+        for (int f = 0; f < MF; ++f) Go[f] *= sd;  // outward normal derivative -> d/dx_ax
       }
     }
-    __syncthreads();
-    if constexpr (MODE != M_DATAT)
-      face_integrate<DIM, P, MF, NT, T>(cf, s_o, ax, side, tn, tm, tb, ih[ax], tid);
+    // cf layout [face][field][value / dn][qf]; it does not overlap fq
+    for (int f = 0; f < MF; ++f) {
+      cf[((fc * MF + f) * 2 + 0) * NQF + qf] = Fo[f] * w;
+      cf[((fc * MF + f) * 2 + 1) * NQF + qf] = Go[f] * w * ih[ax];
+    }
   }
+  __syncthreads();
   if constexpr (MODE == M_OBJG) {
     __shared__ double rj[NT], rp[NT];
     rj[tid] = obj_j;
@@ -300,20 +366,69 @@ __global__ void __launch_bounds__(DG_NT(DIM, P))
       aux[2 * e + 1] = sp;
     }
   }
-  if constexpr (MODE != M_DATAT) {
-    for (int i = tid; i < NBT; i += NT) {
-      const int f = i / NB, l = i % NB;
-      out[f * Nf + e * NB + l] = s_o[i];
+  if constexpr (MODE == M_DATAT) return;
+  // F5: tangential transposes of every face's coefficients
+  if constexpr (DIM == 3) {
+    for (int idx = tid; idx < NFACE * MF * 2 * NN * NQ; idx += NT) {
+      const int qi = idx % NQ, j = (idx / NQ) % NN, rc = idx / (NQ * NN);
+      T s = T(0);
+#pragma unroll
+      for (int qj = 0; qj < NQ; ++qj) s += tb.B[qj * NN + j] * cf[rc * NQF + qj * NQ + qi];
+      tmt[idx] = s;
     }
+    __syncthreads();
+    for (int idx = tid; idx < NFACE * MF * 2 * NFN; idx += NT) {
+      const int i = idx % NN, j = (idx / NN) % NN, rc = idx / NFN;
+      T s = T(0);
+#pragma unroll
+      for (int qi = 0; qi < NQ; ++qi) s += tb.B[qi * NN + i] * tmt[(rc * NN + j) * NQ + qi];
+      tnt[idx] = s;
+    }
+    __syncthreads();
+  } else {
+    for (int idx = tid; idx < NFACE * MF * 2 * NFN; idx += NT) {
+      const int i = idx % NN, rc = idx / NFN;
+      T s = T(0);
+#pragma unroll
+      for (int qi = 0; qi < NQ; ++qi) s += tb.B[qi * NN + i] * cf[rc * NQF + qi];
+      tnt[idx] = s;
+    }
+    __syncthreads();
+  }
+  // F6: every node gathers its value / normal-derivative contributions of all faces
+  for (int idx = tid; idx < NBT; idx += NT) {
+    const int f = idx / NB, node = idx % NB;
+    const int cx = node % NN, cy = (node / NN) % NN, cz = node / (NN * NN);
+    T acc = s_o[idx];
+#pragma unroll
+    for (int fc = 0; fc < NFACE; ++fc) {
+      const int ax = fc >> 1;
+      const int sdi = fc & 1;
+      int l, i, j;
+      if constexpr (DIM == 3) {
+        l = ax == 0 ? cx : (ax == 1 ? cy : cz);
+        i = ax == 0 ? cy : cx;
+        j = ax == 2 ? cy : cz;
+      } else {
+        l = ax == 0 ? cx : cy;
+        i = ax == 0 ? cy : cx;
+        j = 0;
+      }
+      const int rc = fc * MF + f;
+      const int ij = j * NN + i;
+      acc += tb.De[sdi][l] * tnt[(rc * 2 + 1) * NFN + ij];
+      if (l == (sdi ? P : 0)) acc += tnt[(rc * 2 + 0) * NFN + ij];
+    }
+    out[f * Nf + e * NB + node] = acc;
   }
 }
 
 template <int DIM, int P, int MF, typename T, int MODE>
 static void launch_t(const KArgs& A, const void* xs, const void* vin, void* out, double* aux,
                      hipStream_t s) {
-  using S = Sz<DIM, P>;
-  hipLaunchKernelGGL((k_dg<DIM, P, MF, T, MODE>), dim3(unsigned(A.E)), dim3(S::NT), 0, s, A,
-                     static_cast<const T*>(xs), static_cast<const T*>(vin), static_cast<T*>(out), aux);
+  const int64_t eper = (A.E + 7) / 8;
+  hipLaunchKernelGGL((k_dg<DIM, P, MF, T, MODE>), dim3(unsigned(8 * eper)), dim3(OP_NT(DIM, P)), 0, s, A,
+                     static_cast<const T*>(xs), static_cast<const T*>(vin), static_cast<T*>(out), aux, eper);
   DGNP_HIP(hipGetLastError());
 }
 
