@@ -139,6 +139,12 @@ int dgnp_setup(const dgnp_mesh *mesh, int32_t order, const dgnp_species *sp,
                const dgnp_velocity *vel, const dgnp_options *opt, void *stream,
                dgnp_ctx **out);
 
+/* Replaces the problem parameters that the adjoint differentiates: the nodal
+ * boundary data (host [m-1][n_bnode], same order as dgnp_options.bc_conc; may
+ * be NULL to keep them) and the velocity scale Pe.  Invalidates the
+ * linearisation point.  DGNP_E_ARG with a manufactured solution. */
+int dgnp_set_params(dgnp_ctx *ctx, const double *bc_conc, double Pe);
+
 /* Sizes: E elements, N_f = E * n_b DOFs per field, m fields, n_bnode nodal
  * boundary-data entries per concentration.  Any pointer may be NULL. */
 int dgnp_sizes(const dgnp_ctx *ctx, int64_t *E, int64_t *n_dof_field,
@@ -202,6 +208,10 @@ int dgnp_solve(dgnp_ctx *ctx, double *x, const dgnp_solve_opts *opts, dgnp_solve
 int dgnp_adjoint(dgnp_ctx *ctx, const double *x, int32_t objective, double *dJ_dbc,
                  double *dJ_dPe, double *J_out, double *lambda, const dgnp_solve_opts *opts,
                  dgnp_solve_stats *stats);
+
+/* J(x) = int_{x = x_max} (q_1 . n) c_1 ds at x (device double [N]); host J_out.
+ * objective must be 0.  Synchronises. */
+int dgnp_objective(dgnp_ctx *ctx, const double *x, int32_t objective, double *J_out);
 
 /* Copies the assembled block (field f, element e, slot s: 0 = diagonal,
  * 1 + j = coupling to neighbour slot j) of the last set_state into host

@@ -213,6 +213,24 @@ int dgnp_setup(const dgnp_mesh* mesh, int32_t order, const dgnp_species* sp, con
   });
 }
 
+int dgnp_set_params(dgnp_ctx* c, const double* bc_conc, double Pe) {
+  return guard([&] {
+    DGNP_REQUIRE(c, DGNP_E_ARG, "NULL context");
+    DGNP_REQUIRE(c->mms == 0, DGNP_E_ARG, "parameters are fixed by the manufactured solution");
+    DGNP_REQUIRE(std::isfinite(Pe), DGNP_E_NONFINITE, "non-finite Pe");
+    if (bc_conc && c->n_bnode > 0) {
+      for (int64_t i = 0; i < (c->m - 1) * c->n_bnode; ++i)
+        DGNP_REQUIRE(std::isfinite(bc_conc[i]), DGNP_E_NONFINITE, "non-finite boundary data");
+      c->bc_conc.assign(bc_conc, bc_conc + size_t(c->m - 1) * c->n_bnode);
+    }
+    c->vel.Pe = Pe;
+    DGNP_HIP(hipDeviceSynchronize());
+    build_boundary_data(*c);
+    c->has_state = c->has_state32 = false;
+    precond_invalidate(*c);
+  });
+}
+
 int dgnp_sizes(const dgnp_ctx* c, int64_t* E, int64_t* nf, int32_t* nfields, int64_t* nbn) {
   return guard([&] {
     DGNP_REQUIRE(c, DGNP_E_ARG, "NULL context");
@@ -314,6 +332,14 @@ int dgnp_adjoint(dgnp_ctx* c, const double* x, int32_t objective, double* dJ_dbc
     int code = adjoint_solve(*c, x, dJ_dbc, dJ_dPe, J_out, lambda, o, st);
     if (stats) *stats = st;
     if (code != DGNP_OK) throw Error(code, "adjoint solve failed");
+  });
+}
+
+int dgnp_objective(dgnp_ctx* c, const double* x, int32_t objective, double* J_out) {
+  return guard([&] {
+    DGNP_REQUIRE(c && x && J_out, DGNP_E_ARG, "NULL argument");
+    DGNP_REQUIRE(objective == 0, DGNP_E_ARG, "objective 0 (outflow flux of species 1) is the only one");
+    *J_out = objective_value(*c, x);
   });
 }
 

@@ -413,6 +413,20 @@ int newton_solve(dgnp_ctx& c, double* x, const dgnp_solve_opts& o, dgnp_solve_st
   return code;
 }
 
+double objective_value(dgnp_ctx& c, const double* x) {
+  hipStream_t s = c.work;
+  DGNP_HIP(hipDeviceSynchronize());
+  DevBuf<double> g;
+  g.alloc(size_t(c.N));
+  launch_dg(c.dim, c.p, c.m, false, M_OBJG, c.kargs(), x, nullptr, g.p, c.d_aux.p, s);
+  std::vector<double> part(static_cast<size_t>(2 * c.E));
+  DGNP_HIP(hipMemcpyAsync(part.data(), c.d_aux.p, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  DGNP_HIP(hipStreamSynchronize(s));
+  double J = 0.0;
+  for (int64_t e = 0; e < c.E; ++e) J += part[size_t(2 * e)];
+  return J;
+}
+
 // ---------------------------------------------------------------------------
 // Adjoint: J^T lambda = dJ/dx, gradients dJ/dtheta = dJ/dtheta|_x - lambda^T dR/dtheta
 // ---------------------------------------------------------------------------

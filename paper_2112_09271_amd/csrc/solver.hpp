@@ -18,6 +18,7 @@ void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assem
                bool apply_only = false);
 void jac_apply(dgnp_ctx& c, const void* v, void* y, bool f32, bool transpose, hipStream_t s);
 dgnp_solve_opts default_solve_opts();
+double objective_value(dgnp_ctx& c, const double* x);
 int newton_solve(dgnp_ctx& c, double* x, const dgnp_solve_opts& o, dgnp_solve_stats& st);
 int adjoint_solve(dgnp_ctx& c, const double* x, double* dJ_dbc, double* dJ_dPe, double* J_out,
                   double* lambda, const dgnp_solve_opts& o, dgnp_solve_stats& st);

@@ -58,6 +58,7 @@ _vp = C.c_void_p
 _SIGS = {
     "dgnp_setup": [C.POINTER(dgnp_mesh), C.c_int32, C.POINTER(dgnp_species), C.POINTER(dgnp_velocity),
                    C.POINTER(dgnp_options), _vp, C.POINTER(_vp)],
+    "dgnp_set_params": [_vp, _vp, C.c_double],
     "dgnp_sizes": [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                    C.POINTER(C.c_int64)],
     "dgnp_n_faces": [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
@@ -70,6 +71,7 @@ _SIGS = {
     "dgnp_solve": [_vp, _vp, C.POINTER(dgnp_solve_opts), C.POINTER(dgnp_solve_stats)],
     "dgnp_adjoint": [_vp, _vp, C.c_int32, _vp, _vp, _vp, _vp, C.POINTER(dgnp_solve_opts),
                      C.POINTER(dgnp_solve_stats)],
+    "dgnp_objective": [_vp, _vp, C.c_int32, _vp],
     "dgnp_get_block": [_vp, C.c_int32, C.c_int64, C.c_int32, _vp],
     "dgnp_profile": [_vp, C.c_int32],
     "dgnp_timer": [_vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32],
@@ -192,6 +194,7 @@ class Problem:
         if bc_conc is not None:
             self._bc = np.ascontiguousarray(bc_conc, dtype=np.float64)
             opt.bc_conc = self._bc.ctypes.data_as(C.POINTER(C.c_double))
+        self.Pe = float(vel.Pe)
         self.ctx = dgnp_setup(mesh, cfg.p, sp, vel, opt, _stream())
         E, Nf, nb = C.c_int64(), C.c_int64(), C.c_int64()
         m = C.c_int32()
@@ -210,6 +213,16 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+    def set_params(self, bc_conc=None, Pe=None):
+        """New boundary data [m-1][n_bnode] and/or velocity scale (invalidates the state)."""
+        ptr = None
+        if bc_conc is not None:
+            self._bc = np.ascontiguousarray(bc_conc, dtype=np.float64).reshape(self.m - 1, self.n_bnode)
+            ptr = self._bc.ctypes.data
+        if Pe is not None:
+            self.Pe = float(Pe)
+        _check(lib().dgnp_set_params(self.ctx, ptr, self.Pe))
 
     # tables
     def connectivity(self):
@@ -309,6 +322,15 @@ class Problem:
         st = dgnp_solve_stats()
         dgnp_solve(self.ctx, x.data_ptr(), self.solve_opts(**kw), st)
         return x, st
+
+    def objective(self, x):
+        """Outflow flux of species 1 through x = x_max at the state x."""
+        import torch
+        x = self._dev(x, torch.float64)
+        J = np.zeros(1)
+        torch.cuda.synchronize()
+        _check(lib().dgnp_objective(self.ctx, x.data_ptr(), 0, J.ctypes.data))
+        return float(J[0])
 
     def adjoint(self, x, **kw):
         """Returns (J, dJ/d(bc data) [m-1][n_bnode], dJ/dPe, lambda, stats)."""
