@@ -10,6 +10,7 @@
 namespace dgnp {
 
 static __constant__ double c_tab[3][2 * 5 * 4 + 5 + 5 + 2 * 4];  // per p: B, Dq, wq, xq, Dend(-1), Dend(+1)
+static __constant__ float c_tabf[3][2 * 5 * 4 + 5 + 5 + 2 * 4];   // float copy
 
 static inline void upload_ref_tables_tu(const RefTables* tabs, int count) {
   double host[3][2 * 5 * 4 + 5 + 5 + 2 * 4] = {};
@@ -32,6 +33,10 @@ static inline void upload_ref_tables_tu(const RefTables* tabs, int count) {
     }
   }
   DGNP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_tab), host, sizeof(host)));
+  float hostf[3][2 * 5 * 4 + 5 + 5 + 2 * 4];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 2 * 5 * 4 + 5 + 5 + 2 * 4; ++j) hostf[i][j] = float(host[i][j]);
+  DGNP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_tabf), hostf, sizeof(hostf)));
 }
 
 #define DG_NT(D, P) (((D) == 3 && (P) == 3) ? 128 : 64)
@@ -66,6 +71,196 @@ __device__ inline void load_tab(STab<P, T>& t, int tid, int nt) {
     t.X[i] = T(c[2 * NQ * NN + NQ + i]);
   }
   for (int i = tid; i < 2 * NN; i += nt) t.De[i / NN][i % NN] = T(c[2 * NQ * NN + 2 * NQ + i]);
+}
+
+// Compile-time-indexed table access: with unrolled loops the offsets are
+// constants, so the entries are scalar loads from constant memory (uniform
+// across the wave) instead of per-lane LDS loads.
+template <typename T, int P>
+struct CT {
+  static constexpr int NN = P + 1, NQ = P + 2;
+  static __device__ __forceinline__ const T* base();
+  static __device__ __forceinline__ T B(int q, int a) { return base()[q * NN + a]; }
+  static __device__ __forceinline__ T D(int q, int a) { return base()[NQ * NN + q * NN + a]; }
+  static __device__ __forceinline__ T De(int s, int a) { return base()[2 * NQ * NN + 2 * NQ + s * NN + a]; }
+};
+template <>
+__device__ __forceinline__ const double* CT<double, 1>::base() { return c_tab[0]; }
+template <>
+__device__ __forceinline__ const double* CT<double, 2>::base() { return c_tab[1]; }
+template <>
+__device__ __forceinline__ const double* CT<double, 3>::base() { return c_tab[2]; }
+template <>
+__device__ __forceinline__ const float* CT<float, 1>::base() { return c_tabf[0]; }
+template <>
+__device__ __forceinline__ const float* CT<float, 2>::base() { return c_tabf[1]; }
+template <>
+__device__ __forceinline__ const float* CT<float, 3>::base() { return c_tabf[2]; }
+
+// ---------------------------------------------------------------------------
+// Line-per-thread sum factorisation (3-D): each thread contracts one complete
+// 1-D line held in registers.  NA arrays (state, input) of MF fields each:
+//   u[NA][MF][NB] -> q[NA][MF][DIM+1][NQV] (value, d/dx, d/dy, d/dz).
+template <int P, int MF, int NA, int NT, typename T>
+__device__ inline void interp_lines(const T* __restrict__ u, T* __restrict__ q, T* t1, T* t2, const T* ih,
+                                    int tid) {
+  constexpr int NN = P + 1, NQ = P + 2;
+  constexpr int NB = NN * NN * NN, NQV = NQ * NQ * NQ;
+  using C = CT<T, P>;
+  // x lines: (arr, f, c, b)
+  for (int ln = tid; ln < NA * MF * NN * NN; ln += NT) {
+    const T* up = u + ln * NN;
+    T x[NN];
+#pragma unroll
+    for (int a = 0; a < NN; ++a) x[a] = up[a];
+    T* o = t1 + ln * 2 * NQ;  // [arr][f][c][b][2][NQ]
+#pragma unroll
+    for (int qx = 0; qx < NQ; ++qx) {
+      T s0 = T(0), s1 = T(0);
+#pragma unroll
+      for (int a = 0; a < NN; ++a) {
+        s0 += C::B(qx, a) * x[a];
+        s1 += C::D(qx, a) * x[a];
+      }
+      o[qx] = s0;
+      o[NQ + qx] = s1;
+    }
+  }
+  __syncthreads();
+  // y lines: (arr, f, c, qx)
+  for (int ln = tid; ln < NA * MF * NN * NQ; ln += NT) {
+    const int qx = ln % NQ, afc = ln / NQ;  // afc = (arr, f, c)
+    T v0[NN], v1[NN];
+#pragma unroll
+    for (int b = 0; b < NN; ++b) {
+      v0[b] = t1[((afc * NN + b) * 2 + 0) * NQ + qx];
+      v1[b] = t1[((afc * NN + b) * 2 + 1) * NQ + qx];
+    }
+    T* o = t2 + afc * 3 * NQ * NQ;  // [arr][f][c][3][qy][qx]
+#pragma unroll
+    for (int qy = 0; qy < NQ; ++qy) {
+      T s00 = T(0), s01 = T(0), s10 = T(0);
+#pragma unroll
+      for (int b = 0; b < NN; ++b) {
+        s00 += C::B(qy, b) * v0[b];
+        s01 += C::D(qy, b) * v0[b];
+        s10 += C::B(qy, b) * v1[b];
+      }
+      o[(0 * NQ + qy) * NQ + qx] = s00;
+      o[(1 * NQ + qy) * NQ + qx] = s01;
+      o[(2 * NQ + qy) * NQ + qx] = s10;
+    }
+  }
+  __syncthreads();
+  // z lines: (arr, f, qy, qx)
+  for (int ln = tid; ln < NA * MF * NQ * NQ; ln += NT) {
+    const int qxy = ln % (NQ * NQ), af = ln / (NQ * NQ);
+    T w0[NN], w1[NN], w2[NN];
+#pragma unroll
+    for (int c = 0; c < NN; ++c) {
+      const T* tp = t2 + (af * NN + c) * 3 * NQ * NQ + qxy;
+      w0[c] = tp[0];
+      w1[c] = tp[NQ * NQ];
+      w2[c] = tp[2 * NQ * NQ];
+    }
+    T* o = q + af * 4 * NQV + qxy;  // [arr][f][4][NQV]
+#pragma unroll
+    for (int qz = 0; qz < NQ; ++qz) {
+      T v = T(0), gz = T(0), gy = T(0), gx = T(0);
+#pragma unroll
+      for (int c = 0; c < NN; ++c) {
+        v += C::B(qz, c) * w0[c];
+        gz += C::D(qz, c) * w0[c];
+        gy += C::B(qz, c) * w1[c];
+        gx += C::B(qz, c) * w2[c];
+      }
+      o[qz * NQ * NQ] = v;
+      o[NQV + qz * NQ * NQ] = gx * ih[0];
+      o[2 * NQV + qz * NQ * NQ] = gy * ih[1];
+      o[3 * NQV + qz * NQ * NQ] = gz * ih[2];
+    }
+  }
+  __syncthreads();
+}
+
+// Transposed line contractions (3-D): c[MF][4][NQV] -> o[MF][NB] (overwritten)
+template <int P, int MF, int NT, typename T>
+__device__ inline void integrate_lines(const T* __restrict__ c, T* __restrict__ o, T* t1, T* t2, int tid) {
+  constexpr int NN = P + 1, NQ = P + 2;
+  constexpr int NB = NN * NN * NN, NQV = NQ * NQ * NQ;
+  using C = CT<T, P>;
+  // z lines: (f, qy, qx)
+  for (int ln = tid; ln < MF * NQ * NQ; ln += NT) {
+    const int qxy = ln % (NQ * NQ), f = ln / (NQ * NQ);
+    const T* cp = c + f * 4 * NQV + qxy;
+    T cv[NQ], cx[NQ], cy[NQ], cz[NQ];
+#pragma unroll
+    for (int qz = 0; qz < NQ; ++qz) {
+      cv[qz] = cp[qz * NQ * NQ];
+      cx[qz] = cp[NQV + qz * NQ * NQ];
+      cy[qz] = cp[2 * NQV + qz * NQ * NQ];
+      cz[qz] = cp[3 * NQV + qz * NQ * NQ];
+    }
+    T* op = t2 + f * NN * 3 * NQ * NQ + qxy;  // [f][c][3][qy][qx]
+#pragma unroll
+    for (int cc = 0; cc < NN; ++cc) {
+      T s0 = T(0), s1 = T(0), s2 = T(0);
+#pragma unroll
+      for (int qz = 0; qz < NQ; ++qz) {
+        s0 += C::B(qz, cc) * cv[qz] + C::D(qz, cc) * cz[qz];
+        s1 += C::B(qz, cc) * cy[qz];
+        s2 += C::B(qz, cc) * cx[qz];
+      }
+      op[(cc * 3 + 0) * NQ * NQ] = s0;
+      op[(cc * 3 + 1) * NQ * NQ] = s1;
+      op[(cc * 3 + 2) * NQ * NQ] = s2;
+    }
+  }
+  __syncthreads();
+  // y lines: (f, c, qx)
+  for (int ln = tid; ln < MF * NN * NQ; ln += NT) {
+    const int qx = ln % NQ, fc = ln / NQ;  // fc = (f, c)
+    const T* tp = t2 + fc * 3 * NQ * NQ + qx;
+    T a0[NQ], a1[NQ], a2[NQ];
+#pragma unroll
+    for (int qy = 0; qy < NQ; ++qy) {
+      a0[qy] = tp[qy * NQ];
+      a1[qy] = tp[NQ * NQ + qy * NQ];
+      a2[qy] = tp[2 * NQ * NQ + qy * NQ];
+    }
+    T* op = t1 + fc * NN * 2 * NQ + qx;  // [f][c][b][2][qx]
+#pragma unroll
+    for (int b = 0; b < NN; ++b) {
+      T s0 = T(0), s1 = T(0);
+#pragma unroll
+      for (int qy = 0; qy < NQ; ++qy) {
+        s0 += C::B(qy, b) * a0[qy] + C::D(qy, b) * a1[qy];
+        s1 += C::B(qy, b) * a2[qy];
+      }
+      op[(b * 2 + 0) * NQ] = s0;
+      op[(b * 2 + 1) * NQ] = s1;
+    }
+  }
+  __syncthreads();
+  // x lines: (f, c, b)
+  for (int ln = tid; ln < MF * NN * NN; ln += NT) {
+    const T* tp = t1 + ln * 2 * NQ;
+    T b0[NQ], b1[NQ];
+#pragma unroll
+    for (int qx = 0; qx < NQ; ++qx) {
+      b0[qx] = tp[qx];
+      b1[qx] = tp[NQ + qx];
+    }
+#pragma unroll
+    for (int a = 0; a < NN; ++a) {
+      T s = T(0);
+#pragma unroll
+      for (int qx = 0; qx < NQ; ++qx) s += C::B(qx, a) * b0[qx] + C::D(qx, a) * b1[qx];
+      o[ln * NN + a] = s;
+    }
+  }
+  __syncthreads();
+  (void)NB;
 }
 
 // ---------------------------------------------------------------------------

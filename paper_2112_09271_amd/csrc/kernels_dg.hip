@@ -49,17 +49,18 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
   constexpr int QV = MF * NC * NQV;
   constexpr int S1 = DIM == 3 ? MF * 2 * NN * NN * NQ : MF * 2 * NN * NQ;
   constexpr int S2 = DIM == 3 ? MF * 3 * NN * NQ * NQ : 0;
-  constexpr int VOLR = 2 * QV + S1 + S2;
+  constexpr int VOLR = 2 * QV + NARR * (S1 + S2);
   constexpr int NROW = NFACE * 2 * NARR * MF * 2;  // trace rows: face, side, array, field, value/dn
   constexpr int NCF = NFACE * MF * 2 * NQF;
-  constexpr int FACR = DIM == 3 ? NROW * (NN * NQ + NQF) : NROW * (NFN + NQF);
+  constexpr int FACR = NROW * NQF + (NROW * NFN > NCF ? NROW * NFN : NCF);
   constexpr int REG = VOLR > FACR ? VOLR : FACR;
-  __shared__ T s_x[NBT];
-  __shared__ T s_v[HAS_V ? NBT : 1];
+  __shared__ T s_xv[NARR * NBT];  // state, then input vector (contiguous for the line contractions)
   __shared__ T s_o[NBT];
   __shared__ T R[REG];
   __shared__ STab<P, T> tb;
   __shared__ int s_nb[NFACE];
+  T* s_x = s_xv;
+  T* s_v = s_xv + (NARR - 1) * NBT;
 
   const int64_t bid = blockIdx.x;
   const int64_t e = (bid % 8) * eper + bid / 8;
@@ -94,9 +95,13 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
     T* q_x = R;
     T* q_v = R + QV;
     T* t1 = R + 2 * QV;
-    T* t2 = t1 + S1;
-    interp<DIM, P, MF, NT, T>(s_x, q_x, t1, t2, tb, ih, tid);
-    if constexpr (HAS_V) interp<DIM, P, MF, NT, T>(s_v, q_v, t1, t2, tb, ih, tid);
+    T* t2 = t1 + NARR * S1;
+    if constexpr (DIM == 3) {
+      interp_lines<P, MF, NARR, NT, T>(s_xv, q_x, t1, t2, ih, tid);
+    } else {
+      interp<DIM, P, MF, NT, T>(s_x, q_x, t1, t2, tb, ih, tid);
+      if constexpr (HAS_V) interp<DIM, P, MF, NT, T>(s_v, q_v, t1, t2, tb, ih, tid);
+    }
     for (int qi = tid; qi < NQV; qi += NT) {
       int qc[3];
       qc[0] = qi % NQ;
@@ -148,88 +153,103 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
       }
     }
     __syncthreads();
-    integrate<DIM, P, MF, NT, T>(q_v, s_o, t1, t2, tb, tid);
+    if constexpr (DIM == 3)
+      integrate_lines<P, MF, NT, T>(q_v, s_o, t1, t2, tid);
+    else
+      integrate<DIM, P, MF, NT, T>(q_v, s_o, t1, t2, tb, tid);
   } else {
     for (int i = tid; i < NBT; i += NT) s_o[i] = T(0);
     __syncthreads();
   }
 
   // ----------------------------------------------------------------- faces
-  constexpr int OFF_FN = DIM == 3 ? NROW * NN * NQ : 0;     // F1 output
-  constexpr int OFF_FM = 0;                                 // F2 output (3D)
-  constexpr int OFF_FQ = DIM == 3 ? OFF_FN : NROW * NFN;    // face-point traces
-  T* fn = R + OFF_FN;
-  T* fm = R + OFF_FM;
-  T* fq = R + OFF_FQ;
-  T* cf = R;                                                // coefficients (after F3)
-  T* tmt = R + NCF;                                         // transposes (after F4)
-  T* tnt = R + NCF + (DIM == 3 ? NFACE * MF * 2 * NN * NQ : 0);
-  // F1: face-node traces of own / neighbour element
-  for (int idx = tid; idx < NROW * NFN; idx += NT) {
-    const int ij = idx % NFN;
-    int row = idx / NFN;
-    const int c2 = row % 2;
-    row /= 2;
-    const int f = row % MF;
-    row /= MF;
-    const int ar = row % NARR;
-    row /= NARR;
-    const int sd = row % 2;
-    const int fc = row / 2;
-    const int ax = fc >> 1;
-    const int side = (fc & 1) ? 1 : -1;
-    const int sside = sd == 0 ? side : -side;
-    const int i = ij % NN, j = ij / NN;
-    T val = T(0);
-    if (sd == 0) {
-      const T* u = (ar == 0 ? s_x : s_v) + f * NB;
-      if (c2 == 0) {
-        val = u[face_node<DIM, NN>(ax, sside < 0 ? 0 : P, i, j)];
-      } else {
-        const T* De = tb.De[sside < 0 ? 0 : 1];
-        for (int l = 0; l < NN; ++l) val += De[l] * u[face_node<DIM, NN>(ax, l, i, j)];
-        val *= ih[ax];
+  // face region: [fq: NROW * NQF][fn: max(NROW * NFN, NCF)].  F1 writes the
+  // node traces fn, F2/F3 interpolate them to fq, F4 reads fq and writes the
+  // coefficients cf over fn, F5 writes the transposes tnt over fq.
+  T* fq = R;
+  T* fn = R + NROW * NQF;
+  T* cf = fn;
+  T* tnt = R;
+  static_assert(NFACE * MF * 2 * NFN <= NROW * NQF, "transposes must fit in the face-point area");
+  // F1: face-node traces (value and d/dx_ax together) of own and neighbour
+  // element; pair row pr = (face, side, array, field) -> rows 2 pr (value),
+  // 2 pr + 1 (normal derivative).  The state's concentration derivatives are
+  // used by the residual only.
+  {
+    using C = CT<T, P>;
+    for (int idx = tid; idx < (NROW / 2) * NFN; idx += NT) {
+      const int ij = idx % NFN;
+      int pr = idx / NFN;
+      const int f = pr % MF;
+      const int ar = (pr / MF) % NARR;
+      const int sd = (pr / (MF * NARR)) % 2;
+      const int fc = pr / (MF * NARR * 2);
+      const int ax = fc >> 1;
+      const int side = (fc & 1) ? 1 : -1;
+      const int sside = sd == 0 ? side : -side;
+      const int i = ij % NN, j = ij / NN;
+      const T* u = nullptr;
+      if (sd == 0)
+        u = (ar == 0 ? s_x : s_v) + f * NB;
+      else if (NEED_NB && s_nb[fc] >= 0)
+        u = (ar == 0 ? xs : vin) + f * Nf + int64_t(s_nb[fc]) * NB;
+      const bool need_dn = MODE == M_RES || ar == 1 || f == 0;
+      T val = T(0), dn = T(0);
+      if (u) {
+        T x[NN];
+#pragma unroll
+        for (int l = 0; l < NN; ++l) x[l] = u[face_node<DIM, NN>(ax, l, i, j)];
+        val = sside < 0 ? x[0] : x[P];
+        if (need_dn) {
+#pragma unroll
+          for (int l = 0; l < NN; ++l) dn += (sside < 0 ? C::De(0, l) : C::De(1, l)) * x[l];
+          dn *= ih[ax];
+        }
       }
-    } else if (NEED_NB && s_nb[fc] >= 0) {
-      const T* u = (ar == 0 ? xs : vin) + f * Nf + int64_t(s_nb[fc]) * NB;
-      if (c2 == 0) {
-        val = u[face_node<DIM, NN>(ax, sside < 0 ? 0 : P, i, j)];
-      } else {
-        const T* De = tb.De[sside < 0 ? 0 : 1];
-        for (int l = 0; l < NN; ++l) val += De[l] * u[face_node<DIM, NN>(ax, l, i, j)];
-        val *= ih[ax];
-      }
+      fn[(2 * pr + 0) * NFN + ij] = val;
+      fn[(2 * pr + 1) * NFN + ij] = dn;
     }
-    fn[idx] = val;
   }
   __syncthreads();
-  if constexpr (DIM == 3) {
-    for (int idx = tid; idx < NROW * NN * NQ; idx += NT) {
-      const int qi = idx % NQ, j = (idx / NQ) % NN, row = idx / (NQ * NN);
-      T s = T(0);
+  // F2/F3: both tangential interpolations of one trace row in registers
+  {
+    using C = CT<T, P>;
+    for (int row = tid; row < NROW; row += NT) {
+      T x[NFN];
 #pragma unroll
-      for (int i = 0; i < NN; ++i) s += tb.B[qi * NN + i] * fn[row * NFN + j * NN + i];
-      fm[idx] = s;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < NROW * NQF; idx += NT) {
-      const int qi = idx % NQ, qj = (idx / NQ) % NQ, row = idx / NQF;
-      T s = T(0);
+      for (int k = 0; k < NFN; ++k) x[k] = fn[row * NFN + k];
+      if constexpr (DIM == 3) {
+        T y[NN][NQ];  // interpolated along the first tangential direction
 #pragma unroll
-      for (int j = 0; j < NN; ++j) s += tb.B[qj * NN + j] * fm[(row * NN + j) * NQ + qi];
-      fq[idx] = s;
-    }
-    __syncthreads();
-  } else {
-    for (int idx = tid; idx < NROW * NQF; idx += NT) {
-      const int qi = idx % NQ, row = idx / NQ;
-      T s = T(0);
+        for (int j = 0; j < NN; ++j)
 #pragma unroll
-      for (int i = 0; i < NN; ++i) s += tb.B[qi * NN + i] * fn[row * NFN + i];
-      fq[idx] = s;
+          for (int qi = 0; qi < NQ; ++qi) {
+            T s = T(0);
+#pragma unroll
+            for (int i = 0; i < NN; ++i) s += C::B(qi, i) * x[j * NN + i];
+            y[j][qi] = s;
+          }
+#pragma unroll
+        for (int qj = 0; qj < NQ; ++qj)
+#pragma unroll
+          for (int qi = 0; qi < NQ; ++qi) {
+            T s = T(0);
+#pragma unroll
+            for (int j = 0; j < NN; ++j) s += C::B(qj, j) * y[j][qi];
+            fq[row * NQF + qj * NQ + qi] = s;
+          }
+      } else {
+#pragma unroll
+        for (int qi = 0; qi < NQ; ++qi) {
+          T s = T(0);
+#pragma unroll
+          for (int i = 0; i < NN; ++i) s += C::B(qi, i) * x[i];
+          fq[row * NQF + qi] = s;
+        }
+      }
     }
-    __syncthreads();
   }
+  __syncthreads();
   // F4: numerical fluxes at every face point of every face
   double obj_j = 0.0, obj_dpe = 0.0;
   auto trow = [&](int fc, int sd, int ar, int f, int c2) { return ((((fc * 2 + sd) * NARR + ar) * MF + f) * 2 + c2); };
@@ -344,7 +364,7 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
         for (int f = 0; f < MF; ++f) Go[f] *= sd;  // outward normal derivative -> d/dx_ax
       }
     }
-    // cf layout [face][field][value / dn][qf]; it does not overlap fq
+    // cf layout [face][field][value / dn][qf]
     for (int f = 0; f < MF; ++f) {
       cf[((fc * MF + f) * 2 + 0) * NQF + qf] = Fo[f] * w;
       cf[((fc * MF + f) * 2 + 1) * NQF + qf] = Go[f] * w * ih[ax];
@@ -367,34 +387,45 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
     }
   }
   if constexpr (MODE == M_DATAT) return;
-  // F5: tangential transposes of every face's coefficients
-  if constexpr (DIM == 3) {
-    for (int idx = tid; idx < NFACE * MF * 2 * NN * NQ; idx += NT) {
-      const int qi = idx % NQ, j = (idx / NQ) % NN, rc = idx / (NQ * NN);
-      T s = T(0);
+  // F5: both tangential transposes of one coefficient row in registers
+  {
+    using C = CT<T, P>;
+    for (int rc = tid; rc < NFACE * MF * 2; rc += NT) {
+      T x[NQF];
 #pragma unroll
-      for (int qj = 0; qj < NQ; ++qj) s += tb.B[qj * NN + j] * cf[rc * NQF + qj * NQ + qi];
-      tmt[idx] = s;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < NFACE * MF * 2 * NFN; idx += NT) {
-      const int i = idx % NN, j = (idx / NN) % NN, rc = idx / NFN;
-      T s = T(0);
+      for (int k = 0; k < NQF; ++k) x[k] = cf[rc * NQF + k];
+      if constexpr (DIM == 3) {
+        T y[NN][NQ];  // transposed along the second tangential direction
 #pragma unroll
-      for (int qi = 0; qi < NQ; ++qi) s += tb.B[qi * NN + i] * tmt[(rc * NN + j) * NQ + qi];
-      tnt[idx] = s;
-    }
-    __syncthreads();
-  } else {
-    for (int idx = tid; idx < NFACE * MF * 2 * NFN; idx += NT) {
-      const int i = idx % NN, rc = idx / NFN;
-      T s = T(0);
+        for (int j = 0; j < NN; ++j)
 #pragma unroll
-      for (int qi = 0; qi < NQ; ++qi) s += tb.B[qi * NN + i] * cf[rc * NQF + qi];
-      tnt[idx] = s;
+          for (int qi = 0; qi < NQ; ++qi) {
+            T s = T(0);
+#pragma unroll
+            for (int qj = 0; qj < NQ; ++qj) s += C::B(qj, j) * x[qj * NQ + qi];
+            y[j][qi] = s;
+          }
+#pragma unroll
+        for (int j = 0; j < NN; ++j)
+#pragma unroll
+          for (int i = 0; i < NN; ++i) {
+            T s = T(0);
+#pragma unroll
+            for (int qi = 0; qi < NQ; ++qi) s += C::B(qi, i) * y[j][qi];
+            tnt[rc * NFN + j * NN + i] = s;
+          }
+      } else {
+#pragma unroll
+        for (int i = 0; i < NN; ++i) {
+          T s = T(0);
+#pragma unroll
+          for (int qi = 0; qi < NQ; ++qi) s += C::B(qi, i) * x[qi];
+          tnt[rc * NFN + i] = s;
+        }
+      }
     }
-    __syncthreads();
   }
+  __syncthreads();
   // F6: every node gathers its value / normal-derivative contributions of all faces
   for (int idx = tid; idx < NBT; idx += NT) {
     const int f = idx / NB, node = idx % NB;
