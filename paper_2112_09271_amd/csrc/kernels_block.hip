@@ -22,31 +22,76 @@ static constexpr int BT = 256;  // threads per block kernel
 // Assembly.  One work-group per (element, field).  blk[f][e][s][i][j]: s = 0
 // diagonal block, s = 1 + slot coupling to the neighbour across `slot`; row i
 // = test function, column j = trial function.
+//
+// The pointwise Jacobian of the field's own flux is tabulated at every
+// quadrature point for each pair (alpha, beta) of test derivative alpha
+// (d/dx_1..d/dx_d) and trial component beta (value, d/dx_1..d/dx_d), and the
+// element matrix
+//   A_ij = sum_q sum_{alpha,beta} T_alpha(q, i) M_q[alpha][beta] T_beta(q, j)
+// is formed by sum factorisation over the tensor-product structure: a pair
+// (alpha, beta) factorises along direction d into E_a(q_d, i_d) E_b(q_d, j_d)
+// with E = interpolation (B) or derivative (D) rows, so the quadrature sum is
+// contracted one direction at a time, pairs whose remaining factors agree
+// being summed before the next contraction.  Pairs whose coefficient vanishes
+// at every point of the element are skipped.  Face terms (value and normal
+// derivative of test and trial on both sides) factorise the same way over the
+// two tangential directions.  2-D problems run the same code with a third
+// direction of one node and one point.
 // ===========================================================================
+template <int DIM>
+struct AsmPairs {
+  static constexpr int NC = DIM + 1;
+  static constexpr int NCB = DIM * NC;  // alpha = 1..DIM, beta = 0..DIM
+  // factor type of pair c along direction d: 2 * (test derivative) + (trial derivative)
+  static constexpr int ty(int c, int d) { return d >= DIM ? 0 : 2 * (c / NC == d) + (c % NC == 1 + d); }
+  static constexpr int key(int c) { return ty(c, 1) + 4 * ty(c, 2); }
+  static constexpr int nkeys() {
+    int n = 0;
+    for (int k = 0; k < 16; ++k) {
+      bool hit = false;
+      for (int c = 0; c < NCB; ++c) hit = hit || key(c) == k;
+      n += hit ? 1 : 0;
+    }
+    return n;
+  }
+};
+
 template <int DIM, int P, int MF>
 __global__ void __launch_bounds__(BT)
     k_assemble(KArgs A, const double* __restrict__ xs, double* __restrict__ blk, int nfields) {
   using S = Sz<DIM, P>;
+  using PR = AsmPairs<DIM>;
   constexpr int NN = S::NN, NQ = S::NQ, NB = S::NB, NQV = S::NQV, NQF = S::NQF, NFN = S::NFN;
-  constexpr int NC = DIM + 1;                       // value + gradient components
+  constexpr int N3 = DIM == 3 ? NN : 1, Q3 = DIM == 3 ? NQ : 1;  // third direction (padded in 2-D)
+  constexpr int NC = DIM + 1;
+  constexpr int NCB = PR::NCB;
+  constexpr int NKMAX = PR::nkeys();
   constexpr int NBT = MF * NB;
+  constexpr int NN2 = NN * NN;
   constexpr int QV = MF * NC * NQV;
   constexpr int S1 = DIM == 3 ? MF * 2 * NN * NN * NQ : MF * 2 * NN * NQ;
   constexpr int S2 = DIM == 3 ? MF * 3 * NN * NQ * NQ : 0;
-  constexpr int QCH = NQ * NQ > 16 ? 16 : NQ * NQ;  // quadrature points per Y chunk
-  constexpr int YCH = QCH * NC * NB;
+  constexpr int Y1K = NN2 * NQ * Q3;   // per key: [q3][q2][i1 j1]
+  constexpr int Y2G = NN2 * NN2 * Q3;  // per third-direction type: [q3][i2 j2][i1 j1]
+  constexpr int VOL1 = NKMAX * Y1K;
+  constexpr int VOL2A = QV + S1 + S2 + NCB * NQV;
+  constexpr int VOL2B = 4 * Y2G;
+  constexpr int VOLR = VOL1 + (VOL2A > VOL2B ? VOL2A : VOL2B);
   constexpr int TRQ = MF * 2 * NQF;
   constexpr int TRN = MF * 2 * NFN;
   constexpr int TRM = DIM == 3 ? MF * 2 * NN * NQ : 0;
-  constexpr int VOLR = (QV + S1 + S2) > YCH ? (QV + S1 + S2) : YCH;
-  constexpr int FACR = NBT + 2 * TRQ + TRN + TRM + NQF * 8;
+  constexpr int ZSZ = 8 * NN2 * Q3;
+  constexpr int CSZ = 8 * NN2 * N3 * N3;
+  constexpr int FACR = NBT + 2 * TRQ + TRN + TRM + NQF * 8 + ZSZ + CSZ;
   constexpr int REG = VOLR > FACR ? VOLR : FACR;
   constexpr int ENT = (NB * NB + BT - 1) / BT;
   constexpr int NSLOT = 2 * DIM + 1;
   __shared__ double s_x[NBT];
-  __shared__ double Mq[NQV * NC * NC];
   __shared__ double R[REG];
+  __shared__ double G[4 * NQ * NN2];  // G[t][q][i][j] = E_{t>>1}(q, i) E_{t&1}(q, j)
   __shared__ STab<P, double> tb;
+  __shared__ int s_nz[NCB];
+  __shared__ int s_keys[16], s_t3[4], s_nk, s_n3;
 
   const int tid = threadIdx.x;
   const int64_t e = blockIdx.x;
@@ -68,16 +113,26 @@ __global__ void __launch_bounds__(BT)
   double ih[3];
   for (int i = 0; i < 3; ++i) ih[i] = 2.0 / A.h[i];
   for (int i = tid; i < NBT; i += BT) s_x[i] = xs[(i / NB) * Nf + e * NB + (i % NB)];
+  if (tid < NCB) s_nz[tid] = 0;
   __syncthreads();
+  for (int idx = tid; idx < 4 * NQ * NN2; idx += BT) {
+    const int j = idx % NN, i = (idx / NN) % NN, q = (idx / NN2) % NQ, t = idx / (NQ * NN2);
+    G[idx] = ((t >> 1) ? tb.D[q * NN + i] : tb.B[q * NN + i]) * ((t & 1) ? tb.D[q * NN + j] : tb.B[q * NN + j]);
+  }
 
-  // ---- volume: pointwise Jacobian restricted to field f -> Mq[q][alpha][beta]
+  double acc[ENT];
+  for (int k = 0; k < ENT; ++k) acc[k] = 0.0;
+  // ---- volume
   {
-    double* q_x = R;
-    double* t1 = R + QV;
+    double* Y1 = R;
+    double* q_x = R + VOL1;
+    double* t1 = q_x + QV;
     double* t2 = t1 + S1;
+    double* M = t2 + S2;  // M[c][q]
+    double* Y2 = R + VOL1;
     interp<DIM, P, MF, BT, double>(s_x, q_x, t1, t2, tb, ih, tid);
     for (int qi = tid; qi < NQV; qi += BT) {
-      int qc[3] = {qi % NQ, (qi / NQ) % NQ, qi / (NQ * NQ)};
+      const int qc[3] = {qi % NQ, (qi / NQ) % NQ, qi / (NQ * NQ)};
       double xp[3], w = A.detJ;
       for (int d = 0; d < DIM; ++d) {
         xp[d] = A.lo[d] + (eid[d] + 0.5 * (tb.X[qc[d]] + 1.0)) * A.h[d];
@@ -92,53 +147,96 @@ __global__ void __launch_bounds__(BT)
         val[g] = q_x[(g * NC) * NQV + qi];
         for (int d = 0; d < DIM; ++d) grad[g][d] = q_x[(g * NC + 1 + d) * NQV + qi];
       }
+      // unit trial directions, written with compile-time indices only (the
+      // field f is a run-time value) so that the arrays stay in registers
       for (int beta = 0; beta < NC; ++beta) {
         double dv[MF], dg[MF][DIM], cg[MF][DIM];
+#pragma unroll
         for (int g = 0; g < MF; ++g) {
-          dv[g] = 0.0;
-          for (int d = 0; d < DIM; ++d) dg[g][d] = 0.0;
+          dv[g] = (beta == 0 && g == f) ? 1.0 : 0.0;
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) dg[g][d] = (beta == 1 + d && g == f) ? 1.0 : 0.0;
         }
-        if (beta == 0) dv[f] = 1.0; else dg[f][beta - 1] = 1.0;
         vol_jac<double, MF, DIM>(ph, val, grad, u, dv, dg, cg);
         const double sb = beta == 0 ? 1.0 : ih[beta - 1];
-        Mq[(qi * NC + 0) * NC + beta] = 0.0;
-        for (int d = 0; d < DIM; ++d) Mq[(qi * NC + 1 + d) * NC + beta] = cg[f][d] * w * sb * ih[d];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          double cf = 0.0;
+#pragma unroll
+          for (int g = 0; g < MF; ++g) cf = g == f ? cg[g][d] : cf;
+          const double m = cf * w * sb * ih[d];
+          M[(d * NC + beta) * NQV + qi] = m;
+          if (m != 0.0) s_nz[d * NC + beta] = 1;
+        }
       }
     }
     __syncthreads();
-  }
-  // reference tabulation T_alpha(q, i) of basis i at volume point q
-  auto tab = [&](int alpha, int q, int i) -> double {
-    int qc[3] = {q % NQ, (q / NQ) % NQ, q / (NQ * NQ)};
-    int ic[3] = {i % NN, (i / NN) % NN, i / (NN * NN)};
-    double t = 1.0;
-    for (int d = 0; d < DIM; ++d) {
-      const double* M = (alpha == 1 + d) ? tb.D : tb.B;
-      t *= M[qc[d] * NN + ic[d]];
-    }
-    return t;
-  };
-  double acc[ENT];
-  for (int k = 0; k < ENT; ++k) acc[k] = 0.0;
-  // Y[qq][beta][i] = sum_alpha T_alpha(q, i) M[q][alpha][beta], in chunks of QCH points
-  for (int q0 = 0; q0 < NQV; q0 += QCH) {
-    const int nq = (NQV - q0) < QCH ? (NQV - q0) : QCH;
-    double* Y = R;
-    for (int idx = tid; idx < nq * NC * NB; idx += BT) {
-      const int i = idx % NB, beta = (idx / NB) % NC, qq = idx / (NB * NC);
-      const int q = q0 + qq;
-      double s = 0.0;
-      for (int alpha = 1; alpha < NC; ++alpha) s += tab(alpha, q, i) * Mq[(q * NC + alpha) * NC + beta];
-      Y[(qq * NC + beta) * NB + i] = s;
+    if (tid == 0) {
+      int nk = 0, n3 = 0;
+      for (int k = 0; k < 16; ++k) {
+        bool hit = false;
+        for (int c = 0; c < NCB; ++c) hit = hit || (s_nz[c] && PR::key(c) == k);
+        if (hit) s_keys[nk++] = k;
+      }
+      for (int t = 0; t < 4; ++t) {
+        bool hit = false;
+        for (int kk = 0; kk < nk; ++kk) hit = hit || (s_keys[kk] >> 2) == t;
+        if (hit) s_t3[n3++] = t;
+      }
+      s_nk = nk;
+      s_n3 = n3;
     }
     __syncthreads();
+    const int nk = s_nk, n3 = s_n3;
+    // direction 1: Y1[key][q3][q2][i1 j1] = sum_{pairs of key} sum_q1 G_t1(q1, i1, j1) M_c(q1, q2, q3)
+    for (int o = tid; o < nk * Y1K; o += BT) {
+      const int kk = o / Y1K, r = o % Y1K;
+      const int ij = r % NN2, q2 = (r / NN2) % NQ, q3 = r / (NN2 * NQ);
+      const int key = s_keys[kk];
+      double s = 0.0;
+      for (int c = 0; c < NCB; ++c) {
+        if (!s_nz[c] || PR::key(c) != key) continue;
+        const double* g = G + PR::ty(c, 0) * NQ * NN2 + ij;
+        const double* m = M + c * NQV + NQ * (q2 + NQ * q3);
+#pragma unroll
+        for (int q1 = 0; q1 < NQ; ++q1) s += g[q1 * NN2] * m[q1];
+      }
+      Y1[o] = s;
+    }
+    __syncthreads();
+    // direction 2: Y2[t3][q3][i2 j2][i1 j1] = sum_{keys with t3} sum_q2 G_t2(q2, i2, j2) Y1[key][q3][q2][i1 j1]
+    for (int o = tid; o < n3 * Y2G; o += BT) {
+      const int gg = o / Y2G, r = o % Y2G;
+      const int ij1 = r % NN2, ij2 = (r / NN2) % NN2, q3 = r / (NN2 * NN2);
+      const int t3 = s_t3[gg];
+      double s = 0.0;
+      for (int kk = 0; kk < nk; ++kk) {
+        const int key = s_keys[kk];
+        if ((key >> 2) != t3) continue;
+        const double* g = G + (key & 3) * NQ * NN2 + ij2;
+        const double* y = Y1 + kk * Y1K + q3 * NQ * NN2 + ij1;
+#pragma unroll
+        for (int q2 = 0; q2 < NQ; ++q2) s += g[q2 * NN2] * y[q2 * NN2];
+      }
+      Y2[o] = s;
+    }
+    __syncthreads();
+    // direction 3: A_ij = sum_t3 sum_q3 G_t3(q3, i3, j3) Y2[t3][q3][i2 j2][i1 j1]
     for (int k = 0; k < ENT; ++k) {
       const int idx = tid + k * BT;
       if (idx >= NB * NB) break;
       const int i = idx / NB, j = idx % NB;
-      double s = acc[k];
-      for (int qq = 0; qq < nq; ++qq)
-        for (int beta = 0; beta < NC; ++beta) s += Y[(qq * NC + beta) * NB + i] * tab(beta, q0 + qq, j);
+      const int i1 = i % NN, i2 = (i / NN) % NN, i3 = i / NN2;
+      const int j1 = j % NN, j2 = (j / NN) % NN, j3 = j / NN2;
+      const double* y = Y2 + (i2 * NN + j2) * NN2 + i1 * NN + j1;
+      double s = 0.0;
+      for (int gg = 0; gg < n3; ++gg) {
+        const int t3 = s_t3[gg];
+        for (int q3 = 0; q3 < Q3; ++q3) {
+          const double g = DIM == 3 ? G[((t3 * NQ + q3) * NN + i3) * NN + j3] : 1.0;
+          s += g * y[gg * Y2G + q3 * NN2 * NN2];
+        }
+      }
       acc[k] = s;
     }
     __syncthreads();
@@ -151,6 +249,8 @@ __global__ void __launch_bounds__(BT)
   double* tn = tnx + TRQ;
   double* tm = tn + TRN;
   double* Mf = tm + TRM;  // [qf][2 test][4 trial: own v, own g, nb v, nb g]
+  double* Z = Mf + NQF * 8;  // [8][q2][i1 j1]
+  double* Cf = Z + ZSZ;      // [8][i2 j2][i1 j1]
   double* out = blk + ((int64_t(f) * A.E + e) * NSLOT) * NB * NB;
   for (int slot = 0; slot < 2 * DIM; ++slot) {
     const int ax = slot >> 1, side = (slot & 1) ? 1 : -1;
@@ -204,14 +304,26 @@ __global__ void __launch_bounds__(BT)
           g[1 - own][c] = tnx[(c * 2 + 1) * NQF + qf];
         }
         for (int beta = 0; beta < 4; ++beta) {
-          double tv[2][MF] = {}, tg[2][MF] = {};
+          double tv[2][MF], tg[2][MF];
           const int sd = beta < 2 ? own : 1 - own;
-          if (beta % 2 == 0) tv[sd][f] = 1.0; else tg[sd][f] = 1.0;
+#pragma unroll
+          for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+            for (int c = 0; c < MF; ++c) {
+              tv[s2][c] = (s2 == sd && c == f && beta % 2 == 0) ? 1.0 : 0.0;
+              tg[s2][c] = (s2 == sd && c == f && beta % 2 == 1) ? 1.0 : 0.0;
+            }
           double Fo[MF], Go[MF];
           face_jac<double, MF>(ph, v, g, tv, tg, un, own, Fo, Go);
+          double fo = 0.0, go = 0.0;
+#pragma unroll
+          for (int c = 0; c < MF; ++c) {
+            fo = c == f ? Fo[c] : fo;
+            go = c == f ? Go[c] : go;
+          }
           const double sb = (beta % 2 == 0) ? 1.0 : ih[ax];
-          Mf[(qf * 2 + 0) * 4 + beta] = Fo[f] * w * sb;
-          Mf[(qf * 2 + 1) * 4 + beta] = Go[f] * w * sb * ih[ax];
+          Mf[(qf * 2 + 0) * 4 + beta] = fo * w * sb;
+          Mf[(qf * 2 + 1) * 4 + beta] = go * w * sb * ih[ax];
         }
       } else {
         const double un = side * A.Pe * uh[ax];
@@ -222,48 +334,77 @@ __global__ void __launch_bounds__(BT)
           gd[c] = A.bcq[(c * A.n_bface + bf) * NQF + qf];
         }
         for (int beta = 0; beta < 2; ++beta) {
-          double tv[MF] = {}, tg[MF] = {};
-          if (beta == 0) tv[f] = 1.0; else tg[f] = 1.0;
+          double tv[MF], tg[MF];
+#pragma unroll
+          for (int c = 0; c < MF; ++c) {
+            tv[c] = (c == f && beta == 0) ? 1.0 : 0.0;
+            tg[c] = (c == f && beta == 1) ? 1.0 : 0.0;
+          }
           double Fo[MF], Go[MF];
           bnd_jac<double, MF>(ph, v, g, tv, tg, un, cbc, phid, gd, Fo, Go);
+          double fo = 0.0, go = 0.0;
+#pragma unroll
+          for (int c = 0; c < MF; ++c) {
+            fo = c == f ? Fo[c] : fo;
+            go = c == f ? Go[c] : go;
+          }
           const double sb = beta == 0 ? 1.0 : side * ih[ax];
-          Mf[(qf * 2 + 0) * 4 + beta] = Fo[f] * w * sb;
-          Mf[(qf * 2 + 1) * 4 + beta] = Go[f] * w * sb * side * ih[ax];
+          Mf[(qf * 2 + 0) * 4 + beta] = fo * w * sb;
+          Mf[(qf * 2 + 1) * 4 + beta] = go * w * sb * side * ih[ax];
           Mf[(qf * 2 + 0) * 4 + 2 + beta] = 0.0;
           Mf[(qf * 2 + 1) * 4 + 2 + beta] = 0.0;
         }
       }
     }
     __syncthreads();
-    // face tabulation of basis i on side `sd` of this face: value or d/dxi_ax
+    // first tangential direction: Z[ab][qj][i1 j1] = sum_qi B(qi, i1) B(qi, j1) Mf[qi, qj][ab]
+    for (int o = tid; o < 8 * Q3 * NN2; o += BT) {
+      const int ij = o % NN2, qj = (o / NN2) % Q3, ab = o / (Q3 * NN2);
+      if ((ab & 3) >= 2 && !interior) continue;
+      double s = 0.0;
+#pragma unroll
+      for (int qi = 0; qi < NQ; ++qi) s += G[qi * NN2 + ij] * Mf[(qj * NQ + qi) * 8 + ab];
+      Z[o] = s;
+    }
+    __syncthreads();
+    // second tangential direction: Cf[ab][i2 j2][i1 j1] = sum_qj B(qj, i2) B(qj, j2) Z[ab][qj][i1 j1]
+    for (int o = tid; o < 8 * N3 * N3 * NN2; o += BT) {
+      const int ij1 = o % NN2, ij2 = (o / NN2) % (N3 * N3), ab = o / (N3 * N3 * NN2);
+      if ((ab & 3) >= 2 && !interior) continue;
+      double s = 0.0;
+      if constexpr (DIM == 3) {
+#pragma unroll
+        for (int qj = 0; qj < NQ; ++qj) s += G[qj * NN2 + ij2] * Z[(ab * Q3 + qj) * NN2 + ij1];
+      } else {
+        s = Z[ab * NN2 + ij1];
+      }
+      Cf[o] = s;
+    }
+    __syncthreads();
+    // expansion over the normal direction: value (l == endpoint) and normal-derivative rows
     const int lend_own = side < 0 ? 0 : P;
     const int lend_nb = side < 0 ? P : 0;
-    auto ftab = [&](int kind, int sdir, int lend, int qf, int i) -> double {
-      const int qi = qf % NQ, qj = qf / NQ;
-      int ic[3] = {i % NN, (i / NN) % NN, i / (NN * NN)};
-      const int l = ic[ax];
-      const int it1 = ic[t1ax];
-      double t = tb.B[qi * NN + it1];
-      if constexpr (DIM == 3) t *= tb.B[qj * NN + ic[t2ax]];
-      if (kind == 0) return l == lend ? t : 0.0;
-      return t * tb.De[sdir < 0 ? 0 : 1][l];
-    };
+    const double* De_own = tb.De[side < 0 ? 0 : 1];
+    const double* De_nb = tb.De[side < 0 ? 1 : 0];
     for (int k = 0; k < ENT; ++k) {
       const int idx = tid + k * BT;
       if (idx >= NB * NB) break;
       const int i = idx / NB, j = idx % NB;
-      double sd = 0.0, so = 0.0;
-      for (int qf = 0; qf < NQF; ++qf) {
-        const double ti0 = ftab(0, side, lend_own, qf, i), ti1 = ftab(1, side, lend_own, qf, i);
-        const double tj0 = ftab(0, side, lend_own, qf, j), tj1 = ftab(1, side, lend_own, qf, j);
-        const double* M = Mf + qf * 8;
-        sd += ti0 * (M[0] * tj0 + M[1] * tj1) + ti1 * (M[4] * tj0 + M[5] * tj1);
-        if (interior) {
-          const double nj0 = ftab(0, -side, lend_nb, qf, j), nj1 = ftab(1, -side, lend_nb, qf, j);
-          so += ti0 * (M[2] * nj0 + M[3] * nj1) + ti1 * (M[6] * nj0 + M[7] * nj1);
-        }
+      const int ic[3] = {i % NN, (i / NN) % NN, DIM == 3 ? i / NN2 : 0};
+      const int jc[3] = {j % NN, (j / NN) % NN, DIM == 3 ? j / NN2 : 0};
+      const int li = ic[ax], lj = jc[ax];
+      const int tix = ic[t1ax] * NN + jc[t1ax];
+      const int t2x = DIM == 3 ? ic[t2ax] * N3 + jc[t2ax] : 0;
+      const double* c = Cf + t2x * NN2 + tix;
+      constexpr int CS = N3 * N3 * NN2;  // stride between pairs ab
+      const double pi0 = li == lend_own ? 1.0 : 0.0, pi1 = De_own[li];
+      const double pj0 = lj == lend_own ? 1.0 : 0.0, pj1 = De_own[lj];
+      acc[k] += pi0 * (pj0 * c[0 * CS] + pj1 * c[1 * CS]) + pi1 * (pj0 * c[4 * CS] + pj1 * c[5 * CS]);
+      double so = 0.0;
+      if (interior) {
+        const double nj0 = lj == lend_nb ? 1.0 : 0.0, nj1 = De_nb[lj];
+        so = pi0 * (nj0 * c[2 * CS] + nj1 * c[3 * CS]) + pi1 * (nj0 * c[6 * CS] + nj1 * c[7 * CS]);
       }
-      acc[k] += sd;
       ob[idx] = so;
     }
     __syncthreads();
@@ -301,12 +442,17 @@ void launch_assemble(int dim, int p, int m, const KArgs& A, const double* xs, do
 
 // ===========================================================================
 // Gauss-Jordan inversion with partial (row) pivoting of an NB x NB matrix held
-// in LDS with leading dimension LD.  The row interchanges are undone as
-// column interchanges at the end, so a holds A^{-1} on exit.
+// in LDS with leading dimension LD.  Each pivot step takes three barriers: the
+// pivot search (one wave), a snapshot of the pivot row, the row it swaps with
+// and the pivot column, and the update of every entry with the swap folded
+// in.  The row interchanges are not undone in place: on exit column c of the
+// inverse is column csrc[c] of a.  Threads tid < NB follow the image of their
+// column through the interchanges, which yields csrc without a serial pass.
 // ===========================================================================
 template <int NB, int LD>
-__device__ void gj_invert(double* a, int* piv, double* colk, int tid) {
+__device__ void gj_invert(double* a, double* prow, double* krow, double* pcol, int* piv, int* csrc, int tid) {
   const int lane = tid & 63;
+  int cur = tid;
   for (int k = 0; k < NB; ++k) {
     if (tid < 64) {
       double best = -1.0;
@@ -330,39 +476,33 @@ __device__ void gj_invert(double* a, int* piv, double* colk, int tid) {
     }
     __syncthreads();
     const int p = piv[k];
-    if (p != k)
-      for (int c = tid; c < NB; c += BT) {
-        const double t = a[k * LD + c];
-        a[k * LD + c] = a[p * LD + c];
-        a[p * LD + c] = t;
-      }
-    __syncthreads();
-    const double inv = 1.0 / a[k * LD + k];
-    for (int r = tid; r < NB; r += BT) colk[r] = a[r * LD + k];
-    __syncthreads();
-    for (int c = tid; c < NB; c += BT) a[k * LD + c] = (c == k) ? inv : a[k * LD + c] * inv;
+    const double inv = 1.0 / a[p * LD + k];
+    for (int c = tid; c < NB; c += BT) {
+      prow[c] = c == k ? inv : a[p * LD + c] * inv;
+      krow[c] = a[k * LD + c];
+      pcol[c] = c == p ? a[k * LD + k] : a[c * LD + k];
+    }
+    if (cur == k)
+      cur = p;
+    else if (cur == p)
+      cur = k;
     __syncthreads();
     for (int idx = tid; idx < NB * NB; idx += BT) {
       const int r = idx / NB, c = idx % NB;
-      if (r == k) continue;
-      const double fr = colk[r];
-      if (c == k)
-        a[r * LD + c] = -fr * inv;
-      else
-        a[r * LD + c] -= fr * a[k * LD + c];
+      double v;
+      if (r == k) {
+        v = prow[c];
+      } else {
+        const double fr = pcol[r];
+        const double src = r == p ? krow[c] : a[r * LD + c];
+        v = c == k ? -fr * inv : src - fr * prow[c];
+      }
+      a[r * LD + c] = v;
     }
     __syncthreads();
   }
-  for (int k = NB - 1; k >= 0; --k) {
-    const int p = piv[k];
-    if (p != k)
-      for (int r = tid; r < NB; r += BT) {
-        const double t = a[r * LD + k];
-        a[r * LD + k] = a[r * LD + p];
-        a[r * LD + p] = t;
-      }
-    __syncthreads();
-  }
+  if (tid < NB) csrc[tid] = cur;
+  __syncthreads();
 }
 
 // out[e] = inverse of the diagonal block of element e (blk slot 0)
@@ -371,71 +511,196 @@ __global__ void __launch_bounds__(BT) k_block_inverse(const double* __restrict__
                                                       double* __restrict__ out) {
   constexpr int LD = NB + 1;
   __shared__ double a[NB * LD];
-  __shared__ double colk[NB];
-  __shared__ int piv[NB];
+  __shared__ double prow[NB], krow[NB], pcol[NB];
+  __shared__ int piv[NB], csrc[NB];
   const int64_t e = blockIdx.x;
   const double* src = blk + e * nslot * NB * NB;
   for (int idx = threadIdx.x; idx < NB * NB; idx += BT) a[(idx / NB) * LD + idx % NB] = src[idx];
   __syncthreads();
-  gj_invert<NB, LD>(a, piv, colk, threadIdx.x);
-  for (int idx = threadIdx.x; idx < NB * NB; idx += BT) out[e * NB * NB + idx] = a[(idx / NB) * LD + idx % NB];
+  gj_invert<NB, LD>(a, prow, krow, pcol, piv, csrc, threadIdx.x);
+  for (int idx = threadIdx.x; idx < NB * NB; idx += BT)
+    out[e * NB * NB + idx] = a[(idx / NB) * LD + csrc[idx % NB]];
 }
 
 // ===========================================================================
-// BILU(0) factorisation of one field block, one hyperplane level per launch.
-// For the 2d+1-point block stencil in lexicographic order, ILU(0) changes only
-// the diagonal blocks: D_i = A_ii - sum_{j lower} A_ij D_j^{-1} A_ji.  Stored in
+// BILU(0) factorisation of the concentration field blocks (blockIdx.y picks
+// the field, at block stride fstride), one hyperplane level per launch.  For
+// the 2d+1-point block stencil in lexicographic order ILU(0) changes only the
+// diagonal blocks: D_i = A_ii - sum_{j lower} A_ij D_j^{-1} A_ji.  Stored in
 // place: slot 0 <- D_i^{-1}; slot 1+s <- D_i^{-1} A_{i,nbr(s)} for every
 // neighbour (lower ones = Lhat, upper ones = Uhat), so that
 //   M = D (I + Lhat)(I + Uhat).
+// The level kernel forms D_i, inverts it and scales the upper blocks (the
+// next levels read them); k_ilu_scale_lower scales the lower blocks of every
+// element afterwards in one fully parallel launch.
+//
+// Products of two NB x NB blocks run on a 16 x 16 thread grid: thread (ty, tx)
+// owns rows ty + 16 i and columns tx + 16 j, and the operands stream through
+// LDS in panels of KP columns / rows.
 // ===========================================================================
-template <int NB, int DIM>
-__global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, const int* __restrict__ nbr,
-                                                   const int* __restrict__ lev_elems, int64_t first) {
-  constexpr int LD = NB + 1;
-  constexpr int NSLOT = 2 * DIM + 1;
-  constexpr int PW = 16;  // column panel width
-  __shared__ double a[NB * LD];
-  __shared__ double pan[NB * PW];
-  __shared__ double colk[NB];
-  __shared__ int piv[NB];
-  const int tid = threadIdx.x;
-  const int64_t i = lev_elems[first + blockIdx.x];
-  double* bi = blk + i * NSLOT * NB * NB;
-  for (int idx = tid; idx < NB * NB; idx += BT) a[(idx / NB) * LD + idx % NB] = bi[idx];
-  __syncthreads();
-  // Schur updates from the lower neighbours (slots 0, 2, 4 = -x, -y, -z)
-  for (int s = 0; s < 2 * DIM; s += 2) {
-    const int j = nbr[i * 2 * DIM + s];
-    if (j < 0) continue;
-    const double* Aij = bi + int64_t(1 + s) * NB * NB;
-    const double* Uji = blk + (int64_t(j) * NSLOT + 1 + (s + 1)) * NB * NB;  // j's slot toward i
-    for (int idx = tid; idx < NB * NB; idx += BT) {
-      const int r = idx / NB, c = idx % NB;
-      double acc = 0.0;
-      for (int k = 0; k < NB; ++k) acc += Aij[r * NB + k] * Uji[k * NB + c];
-      a[r * LD + c] -= acc;
+template <int NB>
+struct BlkGemm {
+  static constexpr int RT = (NB + 15) / 16;  // rows (and columns) per thread
+  static constexpr int KP = NB < 16 ? NB : 16;
+  static constexpr int PLD = KP + 1;         // padded row length of the left panel
+};
+
+// acc += Lft * Rgt over all k, both operands NB x NB row-major in global memory
+template <int NB>
+__device__ inline void gemm_gg(double (&acc)[BlkGemm<NB>::RT][BlkGemm<NB>::RT], const double* __restrict__ L,
+                               const double* __restrict__ Rm, double* pa, double* pb, int tid) {
+  using G = BlkGemm<NB>;
+  const int ty = tid >> 4, tx = tid & 15;
+#pragma unroll 1
+  for (int k0 = 0; k0 < NB; k0 += G::KP) {
+    const int kn = (NB - k0) < G::KP ? (NB - k0) : G::KP;
+    for (int idx = tid; idx < NB * G::KP; idx += BT) {
+      const int r = idx / G::KP, kk = idx % G::KP;
+      pa[r * G::PLD + kk] = kk < kn ? L[r * NB + k0 + kk] : 0.0;
+      const int kr = idx / NB, c = idx % NB;
+      pb[kr * NB + c] = kr < kn ? Rm[(k0 + kr) * NB + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kn; ++kk) {
+      double av[G::RT], bv[G::RT];
+#pragma unroll
+      for (int i = 0; i < G::RT; ++i) {
+        const int r = ty + 16 * i;
+        av[i] = r < NB ? pa[r * G::PLD + kk] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < G::RT; ++j) {
+        const int c = tx + 16 * j;
+        bv[j] = c < NB ? pb[kk * NB + c] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < G::RT; ++i)
+#pragma unroll
+        for (int j = 0; j < G::RT; ++j) acc[i][j] += av[i] * bv[j];
     }
     __syncthreads();
   }
-  gj_invert<NB, LD>(a, piv, colk, tid);
-  for (int idx = tid; idx < NB * NB; idx += BT) bi[idx] = a[(idx / NB) * LD + idx % NB];
-  // scale every neighbour block by D_i^{-1}
-  for (int s = 0; s < 2 * DIM; ++s) {
-    if (nbr[i * 2 * DIM + s] < 0) continue;
-    double* B = bi + int64_t(1 + s) * NB * NB;
-    for (int c0 = 0; c0 < NB; c0 += PW) {
-      const int w = (NB - c0) < PW ? (NB - c0) : PW;
-      __syncthreads();
-      for (int idx = tid; idx < NB * w; idx += BT) pan[(idx / w) * PW + idx % w] = B[(idx / w) * NB + c0 + idx % w];
-      __syncthreads();
-      for (int idx = tid; idx < NB * w; idx += BT) {
-        const int r = idx / w, c = idx % w;
-        double acc = 0.0;
-        for (int k = 0; k < NB; ++k) acc += a[r * LD + k] * pan[k * PW + c];
-        B[r * NB + c0 + c] = acc;
-      }
+}
+
+// B <- Dinv * B in place (B in global memory); Dinv column k is column csrc[k]
+// of the LDS array a (leading dimension LD)
+template <int NB, int LD>
+__device__ inline void scale_block(double* __restrict__ B, const double* a, const int* csrc, double* pb, int tid) {
+  using G = BlkGemm<NB>;
+  const int ty = tid >> 4, tx = tid & 15;
+  double acc[G::RT][G::RT];
+#pragma unroll
+  for (int i = 0; i < G::RT; ++i)
+#pragma unroll
+    for (int j = 0; j < G::RT; ++j) acc[i][j] = 0.0;
+#pragma unroll 1
+  for (int k0 = 0; k0 < NB; k0 += G::KP) {
+    const int kn = (NB - k0) < G::KP ? (NB - k0) : G::KP;
+    for (int idx = tid; idx < NB * G::KP; idx += BT) {
+      const int kr = idx / NB, c = idx % NB;
+      pb[kr * NB + c] = kr < kn ? B[(k0 + kr) * NB + c] : 0.0;
     }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kn; ++kk) {
+      const int kc = csrc[k0 + kk];
+      double av[G::RT], bv[G::RT];
+#pragma unroll
+      for (int i = 0; i < G::RT; ++i) {
+        const int r = ty + 16 * i;
+        av[i] = r < NB ? a[r * LD + kc] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < G::RT; ++j) {
+        const int c = tx + 16 * j;
+        bv[j] = c < NB ? pb[kk * NB + c] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < G::RT; ++i)
+#pragma unroll
+        for (int j = 0; j < G::RT; ++j) acc[i][j] += av[i] * bv[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < G::RT; ++i)
+#pragma unroll
+    for (int j = 0; j < G::RT; ++j) {
+      const int r = ty + 16 * i, c = tx + 16 * j;
+      if (r < NB && c < NB) B[r * NB + c] = acc[i][j];
+    }
+}
+
+template <int NB, int DIM>
+__global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, int64_t fstride,
+                                                   const int* __restrict__ nbr, const int* __restrict__ lev_elems,
+                                                   int64_t first) {
+  using G = BlkGemm<NB>;
+  constexpr int LD = NB + 1;
+  constexpr int NSLOT = 2 * DIM + 1;
+  __shared__ double a[NB * LD];
+  __shared__ double pa[NB * G::PLD];
+  __shared__ double pb[G::KP * NB];
+  __shared__ double prow[NB], krow[NB], pcol[NB];
+  __shared__ int piv[NB], csrc[NB];
+  const int tid = threadIdx.x;
+  const int ty = tid >> 4, tx = tid & 15;
+  blk += blockIdx.y * fstride;
+  const int64_t i = lev_elems[first + blockIdx.x];
+  double* bi = blk + i * NSLOT * NB * NB;
+  for (int idx = tid; idx < NB * NB; idx += BT) a[(idx / NB) * LD + idx % NB] = bi[idx];
+  // Schur complement of the lower neighbours (slots 0, 2, 4 = -x, -y, -z):
+  // A_ij times the scaled block of j toward i (D_j^{-1} A_ji)
+  double acc[G::RT][G::RT];
+#pragma unroll
+  for (int r = 0; r < G::RT; ++r)
+#pragma unroll
+    for (int c = 0; c < G::RT; ++c) acc[r][c] = 0.0;
+  for (int s = 0; s < 2 * DIM; s += 2) {
+    const int j = nbr[i * 2 * DIM + s];
+    if (j < 0) continue;
+    gemm_gg<NB>(acc, bi + int64_t(1 + s) * NB * NB, blk + (int64_t(j) * NSLOT + 1 + (s + 1)) * NB * NB, pa, pb,
+                tid);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < G::RT; ++r)
+#pragma unroll
+    for (int c = 0; c < G::RT; ++c) {
+      const int rr = ty + 16 * r, cc = tx + 16 * c;
+      if (rr < NB && cc < NB) a[rr * LD + cc] -= acc[r][c];
+    }
+  __syncthreads();
+  gj_invert<NB, LD>(a, prow, krow, pcol, piv, csrc, tid);
+  for (int idx = tid; idx < NB * NB; idx += BT) bi[idx] = a[(idx / NB) * LD + csrc[idx % NB]];
+  // upper neighbours (slots 1, 3, 5 = +x, +y, +z)
+  for (int s = 1; s < 2 * DIM; s += 2) {
+    if (nbr[i * 2 * DIM + s] < 0) continue;
+    scale_block<NB, LD>(bi + int64_t(1 + s) * NB * NB, a, csrc, pb, tid);
+  }
+}
+
+// lower blocks of every element: slot 1+s <- D_i^{-1} A_{i,nbr(s)}, s = 0, 2, 4
+template <int NB, int DIM>
+__global__ void __launch_bounds__(BT) k_ilu_scale_lower(double* __restrict__ blk, int64_t fstride,
+                                                        const int* __restrict__ nbr) {
+  using G = BlkGemm<NB>;
+  constexpr int LD = NB + 1;
+  constexpr int NSLOT = 2 * DIM + 1;
+  __shared__ double a[NB * LD];
+  __shared__ double pb[G::KP * NB];
+  __shared__ int csrc[NB];
+  const int tid = threadIdx.x;
+  blk += blockIdx.y * fstride;
+  const int64_t i = blockIdx.x;
+  double* bi = blk + i * NSLOT * NB * NB;
+  for (int idx = tid; idx < NB * NB; idx += BT) a[(idx / NB) * LD + idx % NB] = bi[idx];
+  if (tid < NB) csrc[tid] = tid;
+  __syncthreads();
+  for (int s = 0; s < 2 * DIM; s += 2) {
+    if (nbr[i * 2 * DIM + s] < 0) continue;
+    scale_block<NB, LD>(bi + int64_t(1 + s) * NB * NB, a, csrc, pb, tid);
   }
 }
 
@@ -763,29 +1028,46 @@ void launch_block_inverse(int nb, int64_t E, const double* blk, int nslot, doubl
 }
 
 template <int NB, int DIM>
-static void fac_t(double* blk, const int* nbr, const int* lev, int64_t first, int64_t count, hipStream_t s) {
-  hipLaunchKernelGGL((k_ilu_factor<NB, DIM>), dim3(unsigned(count)), dim3(BT), 0, s, blk, nbr, lev, first);
+static void fac_t(int nfields, int64_t fstride, double* blk, const int* nbr, const int* lev, int64_t first,
+                  int64_t count, hipStream_t s) {
+  if (count > 0)
+    hipLaunchKernelGGL((k_ilu_factor<NB, DIM>), dim3(unsigned(count), unsigned(nfields)), dim3(BT), 0, s, blk,
+                       fstride, nbr, lev, first);
+  else
+    hipLaunchKernelGGL((k_ilu_scale_lower<NB, DIM>), dim3(unsigned(-count), unsigned(nfields)), dim3(BT), 0, s,
+                       blk, fstride, nbr);
 }
 
-void launch_ilu_factor(int nb, int dim, double* blk, const int* nbr, const int* lev, int64_t first,
-                       int64_t count, hipStream_t s) {
-  if (count == 0) return;
+static void fac_dispatch(int nb, int dim, int nfields, int64_t fstride, double* blk, const int* nbr,
+                         const int* lev, int64_t first, int64_t count, hipStream_t s) {
   if (dim == 3) {
     switch (nb) {
-      case 8: fac_t<8, 3>(blk, nbr, lev, first, count, s); break;
-      case 27: fac_t<27, 3>(blk, nbr, lev, first, count, s); break;
-      case 64: fac_t<64, 3>(blk, nbr, lev, first, count, s); break;
+      case 8: fac_t<8, 3>(nfields, fstride, blk, nbr, lev, first, count, s); break;
+      case 27: fac_t<27, 3>(nfields, fstride, blk, nbr, lev, first, count, s); break;
+      case 64: fac_t<64, 3>(nfields, fstride, blk, nbr, lev, first, count, s); break;
       default: throw Error(DGNP_E_ARG, "unsupported block size");
     }
   } else {
     switch (nb) {
-      case 4: fac_t<4, 2>(blk, nbr, lev, first, count, s); break;
-      case 9: fac_t<9, 2>(blk, nbr, lev, first, count, s); break;
-      case 16: fac_t<16, 2>(blk, nbr, lev, first, count, s); break;
+      case 4: fac_t<4, 2>(nfields, fstride, blk, nbr, lev, first, count, s); break;
+      case 9: fac_t<9, 2>(nfields, fstride, blk, nbr, lev, first, count, s); break;
+      case 16: fac_t<16, 2>(nfields, fstride, blk, nbr, lev, first, count, s); break;
       default: throw Error(DGNP_E_ARG, "unsupported block size");
     }
   }
   DGNP_HIP(hipGetLastError());
+}
+
+void launch_ilu_factor(int nb, int dim, int nfields, int64_t fstride, double* blk, const int* nbr,
+                       const int* lev, int64_t first, int64_t count, hipStream_t s) {
+  if (count == 0 || nfields == 0) return;
+  fac_dispatch(nb, dim, nfields, fstride, blk, nbr, lev, first, count, s);
+}
+
+void launch_ilu_scale_lower(int nb, int dim, int nfields, int64_t fstride, double* blk, const int* nbr,
+                            int64_t E, hipStream_t s) {
+  if (E == 0 || nfields == 0) return;
+  fac_dispatch(nb, dim, nfields, fstride, blk, nbr, nullptr, 0, -E, s);
 }
 
 template <typename T, int NB, int DIM>

@@ -274,12 +274,15 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only) {
   }
   clk.mark("block inverse");
   // concentration blocks: BILU(0) level by level
-  for (int k = 1; k < c.m; ++k)
-    for (size_t l = 0; l + 1 < P.lev_ptr.size(); ++l) {
-      ScopeTimer tm(c, "ilu_factor", s);
-      launch_ilu_factor(c.nb, c.dim, P.blk.p + k * per_field, c.d_nbr.p, P.lev_elems.p, P.lev_ptr[l],
-                        P.lev_ptr[l + 1] - P.lev_ptr[l], s);
-    }
+  for (size_t l = 0; l + 1 < P.lev_ptr.size(); ++l) {
+    ScopeTimer tm(c, "ilu_factor", s);
+    launch_ilu_factor(c.nb, c.dim, c.m - 1, per_field, P.blk.p + per_field, c.d_nbr.p, P.lev_elems.p,
+                      P.lev_ptr[l], P.lev_ptr[l + 1] - P.lev_ptr[l], s);
+  }
+  {
+    ScopeTimer tm(c, "ilu_factor", s);
+    launch_ilu_scale_lower(c.nb, c.dim, c.m - 1, per_field, P.blk.p + per_field, c.d_nbr.p, c.E, s);
+  }
   clk.mark("ilu factor");
   // Galerkin projection of A_phiphi onto Q1 vertices, then host SA setup
   const int NV = 1 << c.dim;
