@@ -94,6 +94,25 @@ template void vaxpby<float>(float, const float*, float, float*, int64_t, hipStre
 template void vscale<double>(double, double*, int64_t, hipStream_t);
 template void vscale<float>(float, float*, int64_t, hipStream_t);
 
+// x[i] = pseudo-random value in [-0.5, 0.5) from a counter-based hash of i (splitmix64)
+template <typename T>
+__global__ void k_hash_fill(T* __restrict__ x, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
+    uint64_t z = uint64_t(i) + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[i] = T(double(z % 1000003ull) / 1000003.0 - 0.5);
+  }
+}
+template <typename T>
+void vfill_hash(T* x, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_hash_fill<T>, dim3(grid_for(n)), dim3(VB), 0, s, x, n);
+}
+template void vfill_hash<double>(double*, int64_t, hipStream_t);
+template void vfill_hash<float>(float*, int64_t, hipStream_t);
+
 // ---- reductions ---------------------------------------------------------------
 __device__ inline double block_sum(double v, double* sh) {
   sh[threadIdx.x] = v;
@@ -157,6 +176,29 @@ double vdot(const double* x, const double* y, int64_t n, double* scratch_dev, hi
 double vnorm2(const double* x, int64_t n, double* scratch_dev, hipStream_t s) {
   double d = vdot(x, x, n, scratch_dev, s);
   return d > 0.0 ? sqrt(d) : 0.0;
+}
+
+// partial[blk] = sum over the block's chunk of x^2 (accumulated in double)
+__global__ void k_sq_partial(const float* __restrict__ x, int64_t n, double* __restrict__ partial) {
+  __shared__ double sh[VB];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
+    const double v = double(x[i]);
+    acc += v * v;
+  }
+  double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+double vnorm2(const float* x, int64_t n, double* scratch_dev, hipStream_t s) {
+  double* partial = scratch_dev + 64;
+  unsigned g = red_grid(n);
+  hipLaunchKernelGGL(k_sq_partial, dim3(g), dim3(VB), 0, s, x, n, partial);
+  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(VB), 0, s, partial, int(g), scratch_dev);
+  double h = 0.0;
+  DGNP_HIP(hipMemcpyAsync(&h, scratch_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+  DGNP_HIP(hipStreamSynchronize(s));
+  return h > 0.0 ? sqrt(h) : 0.0;
 }
 
 __global__ void k_maxpy(const double* __restrict__ V, int64_t ldv, int k, const double* __restrict__ h,

@@ -21,6 +21,9 @@ void vmaxpy(const double* V, int64_t ldv, int k, const double* h_dev, double* w,
 template <typename T>
 void vcombine(const T* Z, int64_t ldz, int k, const double* h_dev, double* y, int64_t n, hipStream_t s);
 double vnorm2(const double* x, int64_t n, double* scratch_dev, hipStream_t s);  // synchronises
+double vnorm2(const float* x, int64_t n, double* scratch_dev, hipStream_t s);   // synchronises
+template <typename T>
+void vfill_hash(T* x, int64_t n, hipStream_t s);  // deterministic values in [-0.5, 0.5)
 double vdot(const double* x, const double* y, int64_t n, double* scratch_dev, hipStream_t s);
 int64_t reduce_scratch_size();
 }  // namespace dgnp

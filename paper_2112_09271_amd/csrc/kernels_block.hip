@@ -441,29 +441,43 @@ void launch_assemble(int dim, int p, int m, const KArgs& A, const double* xs, do
 }
 
 // ===========================================================================
-// Gauss-Jordan inversion with partial (row) pivoting of an NB x NB matrix held
-// in LDS with leading dimension LD.  Each pivot step takes three barriers: the
-// pivot search (one wave), a snapshot of the pivot row, the row it swaps with
-// and the pivot column, and the update of every entry with the swap folded
-// in.  The row interchanges are not undone in place: on exit column c of the
-// inverse is column csrc[c] of a.  Threads tid < NB follow the image of their
-// column through the interchanges, which yields csrc without a serial pass.
+// Gauss-Jordan inversion (sweep form) with partial pivoting of an NB x NB
+// matrix (NB <= 64) held in LDS with leading dimension LD.  The matrix lives in
+// registers during the elimination: lane r of wave w owns row r at columns
+// w, w + 4, w + 8, ...  Rows are never interchanged; step k pivots column k on
+// the unused row p of largest magnitude (ties: smallest row), so that on exit
+//   A^{-1}[i][j] = a[rsrc[i]][csrc[j]],  rsrc[k] = p_k,  csrc[p_k] = k.
+// Per step: the wave that owns column k finds the pivot with a lane reduction
+// and publishes column k; after a barrier the pivot row's lanes publish row p;
+// after a second barrier every lane updates its row with one FMA per entry.
+// The published rows and columns are double-buffered, so two barriers suffice.
 // ===========================================================================
 template <int NB, int LD>
-__device__ void gj_invert(double* a, double* prow, double* krow, double* pcol, int* piv, int* csrc, int tid) {
-  const int lane = tid & 63;
-  int cur = tid;
+__device__ void gj_invert(double* a, double* sh, int* shi, int* rsrc, int* csrc, int tid) {
+  static_assert(NB <= 64 && BT == 256, "one row per lane, four waves");
+  constexpr int NC = (NB + 3) / 4;
+  constexpr int SB = 2 * 64 + 1;  // doubles per buffer: column k, row p, pivot value
+  const int r = tid & 63, w = tid >> 6;
+  const bool rowok = r < NB;
+  double x[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const int c = w + 4 * j;
+    x[j] = (rowok && c < NB) ? a[r * LD + c] : 0.0;
+  }
+  bool used = !rowok;
   for (int k = 0; k < NB; ++k) {
-    if (tid < 64) {
-      double best = -1.0;
-      int bi = k;
-      for (int r = k + lane; r < NB; r += 64) {
-        const double v = fabs(a[r * LD + k]);
-        if (v > best) {
-          best = v;
-          bi = r;
-        }
-      }
+    const int b = k & 1;
+    double* pcol = sh + b * SB;
+    double* prow = pcol + 64;
+    double* pval = prow + 64;
+    const int wk = k & 3, jk = k >> 2;
+    if (w == wk) {
+      double xk = 0.0;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) xk = j == jk ? x[j] : xk;
+      double best = used ? -1.0 : fabs(xk);
+      int bi = r;
       for (int off = 32; off > 0; off >>= 1) {
         const double ob = __shfl_xor(best, off, 64);
         const int oi = __shfl_xor(bi, off, 64);
@@ -472,36 +486,49 @@ __device__ void gj_invert(double* a, double* prow, double* krow, double* pcol, i
           bi = oi;
         }
       }
-      if (lane == 0) piv[k] = bi;
-    }
-    __syncthreads();
-    const int p = piv[k];
-    const double inv = 1.0 / a[p * LD + k];
-    for (int c = tid; c < NB; c += BT) {
-      prow[c] = c == k ? inv : a[p * LD + c] * inv;
-      krow[c] = a[k * LD + c];
-      pcol[c] = c == p ? a[k * LD + k] : a[c * LD + k];
-    }
-    if (cur == k)
-      cur = p;
-    else if (cur == p)
-      cur = k;
-    __syncthreads();
-    for (int idx = tid; idx < NB * NB; idx += BT) {
-      const int r = idx / NB, c = idx % NB;
-      double v;
-      if (r == k) {
-        v = prow[c];
-      } else {
-        const double fr = pcol[r];
-        const double src = r == p ? krow[c] : a[r * LD + c];
-        v = c == k ? -fr * inv : src - fr * prow[c];
+      pcol[r] = xk;
+      if (r == bi) {
+        shi[b] = bi;
+        pval[0] = xk;
+        rsrc[k] = bi;
+        csrc[bi] = k;
       }
-      a[r * LD + c] = v;
     }
     __syncthreads();
+    const int p = __builtin_amdgcn_readfirstlane(shi[b]);
+    const double inv = 1.0 / pval[0];
+    if (r == p) {
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const int c = w + 4 * j;
+        if (c < NB) prow[c] = x[j];
+      }
+      used = true;
+    }
+    __syncthreads();
+    const double g = (r == p || !rowok) ? 0.0 : pcol[r] * inv;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const int c = w + 4 * j;
+      if (c < NB) x[j] = fma(-g, prow[c], x[j]);
+    }
+    if (r == p) {
+#pragma unroll
+      for (int j = 0; j < NC; ++j) x[j] *= inv;
+    }
+    if (w == wk) {
+      const double xkn = r == p ? inv : -g;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) x[j] = j == jk ? xkn : x[j];
+    }
   }
-  if (tid < NB) csrc[tid] = cur;
+  if (rowok) {
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const int c = w + 4 * j;
+      if (c < NB) a[r * LD + c] = x[j];
+    }
+  }
   __syncthreads();
 }
 
@@ -511,15 +538,15 @@ __global__ void __launch_bounds__(BT) k_block_inverse(const double* __restrict__
                                                       double* __restrict__ out) {
   constexpr int LD = NB + 1;
   __shared__ double a[NB * LD];
-  __shared__ double prow[NB], krow[NB], pcol[NB];
-  __shared__ int piv[NB], csrc[NB];
+  __shared__ double sh[2 * (2 * 64 + 1)];
+  __shared__ int shi[2], rsrc[NB], csrc[NB];
   const int64_t e = blockIdx.x;
   const double* src = blk + e * nslot * NB * NB;
   for (int idx = threadIdx.x; idx < NB * NB; idx += BT) a[(idx / NB) * LD + idx % NB] = src[idx];
   __syncthreads();
-  gj_invert<NB, LD>(a, prow, krow, pcol, piv, csrc, threadIdx.x);
+  gj_invert<NB, LD>(a, sh, shi, rsrc, csrc, threadIdx.x);
   for (int idx = threadIdx.x; idx < NB * NB; idx += BT)
-    out[e * NB * NB + idx] = a[(idx / NB) * LD + csrc[idx % NB]];
+    out[e * NB * NB + idx] = a[rsrc[idx / NB] * LD + csrc[idx % NB]];
 }
 
 // ===========================================================================
@@ -545,22 +572,39 @@ struct BlkGemm {
   static constexpr int PLD = KP + 1;         // padded row length of the left panel
 };
 
-// acc += Lft * Rgt over all k, both operands NB x NB row-major in global memory
+// acc += Lft * Rgt over all k, both operands NB x NB row-major in global memory.
+// The next panel is fetched into registers while the current one is used.
 template <int NB>
 __device__ inline void gemm_gg(double (&acc)[BlkGemm<NB>::RT][BlkGemm<NB>::RT], const double* __restrict__ L,
                                const double* __restrict__ Rm, double* pa, double* pb, int tid) {
   using G = BlkGemm<NB>;
+  constexpr int PE = (NB * G::KP + BT - 1) / BT;  // panel elements per thread
   const int ty = tid >> 4, tx = tid & 15;
+  double ra[PE], rb[PE];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < PE; ++q) {
+      const int idx = tid + q * BT;
+      const int r = idx / G::KP, kk = idx % G::KP;
+      ra[q] = (idx < NB * G::KP && k0 + kk < NB) ? L[r * NB + k0 + kk] : 0.0;
+      const int kr = idx / NB, cc = idx % NB;
+      rb[q] = (idx < NB * G::KP && k0 + kr < NB) ? Rm[(k0 + kr) * NB + cc] : 0.0;
+    }
+  };
+  fetch(0);
 #pragma unroll 1
   for (int k0 = 0; k0 < NB; k0 += G::KP) {
     const int kn = (NB - k0) < G::KP ? (NB - k0) : G::KP;
-    for (int idx = tid; idx < NB * G::KP; idx += BT) {
-      const int r = idx / G::KP, kk = idx % G::KP;
-      pa[r * G::PLD + kk] = kk < kn ? L[r * NB + k0 + kk] : 0.0;
-      const int kr = idx / NB, c = idx % NB;
-      pb[kr * NB + c] = kr < kn ? Rm[(k0 + kr) * NB + c] : 0.0;
+#pragma unroll
+    for (int q = 0; q < PE; ++q) {
+      const int idx = tid + q * BT;
+      if (idx < NB * G::KP) {
+        pa[(idx / G::KP) * G::PLD + idx % G::KP] = ra[q];
+        pb[idx] = rb[q];
+      }
     }
     __syncthreads();
+    if (k0 + G::KP < NB) fetch(k0 + G::KP);
 #pragma unroll 4
     for (int kk = 0; kk < kn; ++kk) {
       double av[G::RT], bv[G::RT];
@@ -583,25 +627,45 @@ __device__ inline void gemm_gg(double (&acc)[BlkGemm<NB>::RT][BlkGemm<NB>::RT], 
   }
 }
 
-// B <- Dinv * B in place (B in global memory); Dinv column k is column csrc[k]
-// of the LDS array a (leading dimension LD)
+// B <- Dinv * B in place (B in global memory); Dinv[i][k] = a[rsrc[i]][csrc[k]]
+// with the LDS array a of leading dimension LD
 template <int NB, int LD>
-__device__ inline void scale_block(double* __restrict__ B, const double* a, const int* csrc, double* pb, int tid) {
+__device__ inline void scale_block(double* __restrict__ B, const double* a, const int* rsrc, const int* csrc,
+                                   double* pb, int tid) {
   using G = BlkGemm<NB>;
+  constexpr int PE = (NB * G::KP + BT - 1) / BT;
   const int ty = tid >> 4, tx = tid & 15;
   double acc[G::RT][G::RT];
 #pragma unroll
   for (int i = 0; i < G::RT; ++i)
 #pragma unroll
     for (int j = 0; j < G::RT; ++j) acc[i][j] = 0.0;
+  int arow[G::RT];
+#pragma unroll
+  for (int i = 0; i < G::RT; ++i) {
+    const int r = ty + 16 * i;
+    arow[i] = r < NB ? rsrc[r] * LD : 0;
+  }
+  double rb[PE];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < PE; ++q) {
+      const int idx = tid + q * BT;
+      const int kr = idx / NB, cc = idx % NB;
+      rb[q] = (idx < NB * G::KP && k0 + kr < NB) ? B[(k0 + kr) * NB + cc] : 0.0;
+    }
+  };
+  fetch(0);
 #pragma unroll 1
   for (int k0 = 0; k0 < NB; k0 += G::KP) {
     const int kn = (NB - k0) < G::KP ? (NB - k0) : G::KP;
-    for (int idx = tid; idx < NB * G::KP; idx += BT) {
-      const int kr = idx / NB, c = idx % NB;
-      pb[kr * NB + c] = kr < kn ? B[(k0 + kr) * NB + c] : 0.0;
+#pragma unroll
+    for (int q = 0; q < PE; ++q) {
+      const int idx = tid + q * BT;
+      if (idx < NB * G::KP) pb[idx] = rb[q];
     }
     __syncthreads();
+    if (k0 + G::KP < NB) fetch(k0 + G::KP);
 #pragma unroll 4
     for (int kk = 0; kk < kn; ++kk) {
       const int kc = csrc[k0 + kk];
@@ -609,7 +673,7 @@ __device__ inline void scale_block(double* __restrict__ B, const double* a, cons
 #pragma unroll
       for (int i = 0; i < G::RT; ++i) {
         const int r = ty + 16 * i;
-        av[i] = r < NB ? a[r * LD + kc] : 0.0;
+        av[i] = r < NB ? a[arow[i] + kc] : 0.0;
       }
 #pragma unroll
       for (int j = 0; j < G::RT; ++j) {
@@ -642,8 +706,8 @@ __global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, int
   __shared__ double a[NB * LD];
   __shared__ double pa[NB * G::PLD];
   __shared__ double pb[G::KP * NB];
-  __shared__ double prow[NB], krow[NB], pcol[NB];
-  __shared__ int piv[NB], csrc[NB];
+  __shared__ double sh[2 * (2 * 64 + 1)];
+  __shared__ int shi[2], rsrc[NB], csrc[NB];
   const int tid = threadIdx.x;
   const int ty = tid >> 4, tx = tid & 15;
   blk += blockIdx.y * fstride;
@@ -672,12 +736,12 @@ __global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, int
       if (rr < NB && cc < NB) a[rr * LD + cc] -= acc[r][c];
     }
   __syncthreads();
-  gj_invert<NB, LD>(a, prow, krow, pcol, piv, csrc, tid);
-  for (int idx = tid; idx < NB * NB; idx += BT) bi[idx] = a[(idx / NB) * LD + csrc[idx % NB]];
+  gj_invert<NB, LD>(a, sh, shi, rsrc, csrc, tid);
+  for (int idx = tid; idx < NB * NB; idx += BT) bi[idx] = a[rsrc[idx / NB] * LD + csrc[idx % NB]];
   // upper neighbours (slots 1, 3, 5 = +x, +y, +z)
   for (int s = 1; s < 2 * DIM; s += 2) {
     if (nbr[i * 2 * DIM + s] < 0) continue;
-    scale_block<NB, LD>(bi + int64_t(1 + s) * NB * NB, a, csrc, pb, tid);
+    scale_block<NB, LD>(bi + int64_t(1 + s) * NB * NB, a, rsrc, csrc, pb, tid);
   }
 }
 
@@ -690,17 +754,17 @@ __global__ void __launch_bounds__(BT) k_ilu_scale_lower(double* __restrict__ blk
   constexpr int NSLOT = 2 * DIM + 1;
   __shared__ double a[NB * LD];
   __shared__ double pb[G::KP * NB];
-  __shared__ int csrc[NB];
+  __shared__ int ident[NB];
   const int tid = threadIdx.x;
   blk += blockIdx.y * fstride;
   const int64_t i = blockIdx.x;
   double* bi = blk + i * NSLOT * NB * NB;
   for (int idx = tid; idx < NB * NB; idx += BT) a[(idx / NB) * LD + idx % NB] = bi[idx];
-  if (tid < NB) csrc[tid] = tid;
+  if (tid < NB) ident[tid] = tid;
   __syncthreads();
   for (int s = 0; s < 2 * DIM; s += 2) {
     if (nbr[i * 2 * DIM + s] < 0) continue;
-    scale_block<NB, LD>(bi + int64_t(1 + s) * NB * NB, a, csrc, pb, tid);
+    scale_block<NB, LD>(bi + int64_t(1 + s) * NB * NB, a, ident, ident, pb, tid);
   }
 }
 
@@ -1212,6 +1276,78 @@ void launch_q1_galerkin(int dim, int p, int64_t E, const double* blk, double* ga
     else if (p == 2) hipLaunchKernelGGL((k_q1_galerkin<2, 2>), g, dim3(BT), 0, s, blk, gal);
     else hipLaunchKernelGGL((k_q1_galerkin<2, 3>), g, dim3(BT), 0, s, blk, gal);
   }
+  DGNP_HIP(hipGetLastError());
+}
+
+// Vertex stencil of the Galerkin operator: st[r][o] = sum of gal[e][s][u][v]
+// over every element e that has vertex r (local index u) and every slot s whose
+// target element (e itself or its neighbour across face s - 1) has the vertex
+// r + offset(o) (local index v); o runs over the 3^d offsets in {-1, 0, 1}^d.
+// Elements are visited in increasing index and slots in increasing order,
+// which fixes the summation order.  Vertex pairs two layers apart (far sides
+// of two face neighbours) couple only through exact zeros and are not stored.
+template <int DIM>
+__global__ void k_vertex_stencil(const double* __restrict__ gal, const int* __restrict__ nbr, int3 n,
+                                 int64_t nvert, double* __restrict__ st) {
+  constexpr int NV = 1 << DIM;
+  constexpr int NS = DIM == 3 ? 27 : 9;
+  constexpr int NSLOT = 2 * DIM + 1;
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t >= nvert * NS) return;
+  const int64_t r = t / NS;
+  const int o = int(t % NS);
+  const int nv[3] = {n.x + 1, n.y + 1, DIM == 3 ? n.z + 1 : 1};
+  const int ne[3] = {n.x, n.y, DIM == 3 ? n.z : 1};
+  const int rc[3] = {int(r % nv[0]), int((r / nv[0]) % nv[1]), DIM == 3 ? int(r / (int64_t(nv[0]) * nv[1])) : 0};
+  const int oc[3] = {o % 3 - 1, (o / 3) % 3 - 1, DIM == 3 ? o / 9 - 1 : 0};
+  int cc[3];
+  for (int a = 0; a < 3; ++a) cc[a] = rc[a] + oc[a];
+  double acc = 0.0;
+  // elements around r in increasing index: the offset bits run from (1,1,1) down
+  for (int b = NV - 1; b >= 0; --b) {
+    int ec[3] = {0, 0, 0};
+    bool ok = true;
+    int u = 0;
+    for (int a = 0; a < DIM; ++a) {
+      const int bit = (b >> a) & 1;  // descending b: last axis most significant
+      ec[a] = rc[a] - bit;
+      if (ec[a] < 0 || ec[a] >= ne[a]) ok = false;
+      u |= bit << a;
+    }
+    if (!ok) continue;
+    const int64_t e = ec[0] + int64_t(ne[0]) * (ec[1] + int64_t(ne[1]) * ec[2]);
+    for (int sl = 0; sl < NSLOT; ++sl) {
+      int tc[3] = {ec[0], ec[1], ec[2]};
+      if (sl > 0) {
+        if (nbr[e * 2 * DIM + (sl - 1)] < 0) continue;
+        const int ax = (sl - 1) >> 1;
+        tc[ax] += ((sl - 1) & 1) ? 1 : -1;
+      }
+      int v = 0;
+      bool in = true;
+      for (int a = 0; a < DIM; ++a) {
+        const int l = cc[a] - tc[a];
+        if (l < 0 || l > 1) in = false;
+        v |= (l & 1) << a;
+      }
+      if (!in) continue;
+      acc += gal[((e * NSLOT + sl) * NV + u) * NV + v];
+    }
+  }
+  st[t] = acc;
+}
+
+void launch_vertex_stencil(int dim, const double* gal, const int* nbr, const int* n, int64_t nvert, double* st,
+                           hipStream_t s) {
+  const int ns = dim == 3 ? 27 : 9;
+  const int64_t total = nvert * ns;
+  if (total == 0) return;
+  const int3 nn = make_int3(n[0], n[1], dim == 3 ? n[2] : 1);
+  const unsigned g = unsigned((total + BT - 1) / BT);
+  if (dim == 3)
+    hipLaunchKernelGGL(k_vertex_stencil<3>, dim3(g), dim3(BT), 0, s, gal, nbr, nn, nvert, st);
+  else
+    hipLaunchKernelGGL(k_vertex_stencil<2>, dim3(g), dim3(BT), 0, s, gal, nbr, nn, nvert, st);
   DGNP_HIP(hipGetLastError());
 }
 

@@ -30,6 +30,9 @@ template <typename T>
 void launch_q1(bool prolong, int dim, int p, const int* n, const T* a, T* b, T beta, int64_t E, int64_t nvert,
                hipStream_t s);
 void launch_q1_galerkin(int dim, int p, int64_t E, const double* blk, double* gal, hipStream_t s);
+// st[nvert][3^dim]: the Galerkin vertex operator as a dense 3^dim-point stencil per vertex
+void launch_vertex_stencil(int dim, const double* gal, const int* nbr, const int* n, int64_t nvert, double* st,
+                           hipStream_t s);
 
 // CSR: y = alpha * A x + beta * b (b may be null)
 template <typename T>

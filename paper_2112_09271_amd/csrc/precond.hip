@@ -59,6 +59,7 @@ struct Precond {
   int nvx[3] = {1, 1, 1};
   int64_t nvert = 0;
   DevBuf<double> gal;
+  DevBuf<double> vst;               // [nvert][3^d] vertex stencil of the Galerkin operator
   std::vector<MgLevel> mg;          // mg[0] = vertex level
   DevBuf<double> cinv;
   DevBuf<float> cinv32;
@@ -107,43 +108,16 @@ void precond_symbolic(dgnp_ctx& c) {
 }
 
 // ---- vertex matrix from the per-element Galerkin blocks ----------------------
-static Csr vertex_matrix(const dgnp_ctx& c, const Precond& P, const std::vector<double>& gal) {
-  const int d = c.dim, NV = 1 << d;
-  int ns = 1;
-  for (int i = 0; i < d; ++i) ns *= 3;
-  std::vector<double> st(static_cast<size_t>(P.nvert) * ns, 0.0);
-  auto vid = [&](int64_t e, int o, int* vc) {
-    int id[3] = {int(e % c.n[0]), int((e / c.n[0]) % c.n[1]), d == 3 ? int(e / (int64_t(c.n[0]) * c.n[1])) : 0};
-    int64_t v = 0, s = 1;
-    for (int a = 0; a < d; ++a) {
-      vc[a] = id[a] + ((o >> a) & 1);
-      v += vc[a] * s;
-      s *= P.nvx[a];
-    }
-    return v;
-  };
-  for (int64_t e = 0; e < c.E; ++e)
-    for (int s = 0; s < P.nslot; ++s) {
-      const int64_t nb = s == 0 ? e : c.nbr[size_t(e) * 2 * d + (s - 1)];
-      if (nb < 0) continue;
-      const double* g = gal.data() + (size_t(e) * P.nslot + s) * NV * NV;
-      for (int u = 0; u < NV; ++u) {
-        int ru[3] = {0, 0, 0}, cv[3] = {0, 0, 0};
-        const int64_t row = vid(e, u, ru);
-        for (int v = 0; v < NV; ++v) {
-          vid(nb, v, cv);
-          int off = 0, mul = 1;
-          for (int a = 0; a < d; ++a) {
-            off += (cv[a] - ru[a] + 1) * mul;
-            mul *= 3;
-          }
-          st[size_t(row) * ns + off] += g[u * NV + v];
-        }
-      }
-    }
+// CSR of the Galerkin vertex operator from its dense per-vertex stencil
+// st[r][o] (o over {-1, 0, 1}^d, first axis fastest); exact zeros are dropped
+static Csr vertex_matrix(const dgnp_ctx& c, const Precond& P, const std::vector<double>& st) {
+  const int d = c.dim;
+  const int ns = d == 3 ? 27 : 9;
   Csr A;
   A.n = A.m = int(P.nvert);
   A.rp.assign(size_t(A.n) + 1, 0);
+  A.ci.reserve(st.size());
+  A.v.reserve(st.size());
   for (int64_t r = 0; r < P.nvert; ++r) {
     int rc[3] = {int(r % P.nvx[0]), int((r / P.nvx[0]) % P.nvx[1]), int(r / (int64_t(P.nvx[0]) * P.nvx[1]))};
     for (int off = 0; off < ns; ++off) {
@@ -205,29 +179,27 @@ static void ensure_work32(dgnp_ctx& c, Precond& P) {
   P.tN32.alloc(size_t(c.N));
 }
 
-// largest eigenvalue of D_b^{-1} A_phiphi by power iteration on the device
-static double lmax_level0(dgnp_ctx& c, Precond& P, hipStream_t s) {
+// largest eigenvalue of D_b^{-1} A_phiphi by power iteration on the device, in
+// the arithmetic of the smoother that uses it: 20 steps from a hashed start
+// vector, renormalised every 4 steps; the estimate is the growth of the last step
+template <typename T>
+static double lmax_level0(dgnp_ctx& c, Precond& P, hipStream_t s, const T* blk, const T* dinv, T* x, T* y) {
   const int64_t n = c.Nf;
-  DevBuf<double>& x = *P.wd[0];
-  DevBuf<double>& y = *P.wd[1];
-  std::vector<double> h(static_cast<size_t>(n));
-  uint64_t st = 0x2545F4914F6CDD1Dull;
-  for (int64_t i = 0; i < n; ++i) {
-    st ^= st << 13;
-    st ^= st >> 7;
-    st ^= st << 17;
-    h[size_t(i)] = double(st % 1000003) / 1000003.0 - 0.5;
-  }
-  DGNP_HIP(hipMemcpyAsync(x.p, h.data(), size_t(n) * sizeof(double), hipMemcpyHostToDevice, s));
+  vfill_hash<T>(x, n, s);
+  const double nx = vnorm2(x, n, P.red.p, s);
+  vscale<T>(T(1.0 / nx), x, n, s);
   double lam = 1.0;
-  double nx = vnorm2(x.p, n, P.red.p, s);
-  vscale<double>(1.0 / nx, x.p, n, s);
-  for (int it = 0; it < 20; ++it) {
-    launch_bspmv<double>(c.nb, c.dim, c.E, P.blk.p, c.d_nbr.p, x.p, nullptr, 1.0, 0.0, y.p, s);
-    launch_bdiag<double>(c.nb, c.E, P.dinv_phi.p, y.p, x.p, s);
-    lam = vnorm2(x.p, n, P.red.p, s);
+  for (int g = 0; g < 5; ++g) {
+    double n0 = 1.0;
+    for (int it = 0; it < 4; ++it) {
+      if (it == 3) n0 = vnorm2(x, n, P.red.p, s);
+      launch_bspmv<T>(c.nb, c.dim, c.E, blk, c.d_nbr.p, x, nullptr, T(1), T(0), y, s);
+      launch_bdiag<T>(c.nb, c.E, dinv, y, x, s);
+    }
+    const double n1 = vnorm2(x, n, P.red.p, s);
+    lam = n1 / n0;
     if (!(lam > 0.0) || !std::isfinite(lam)) throw Error(DGNP_E_NONFINITE, "power iteration failed");
-    vscale<double>(1.0 / lam, x.p, n, s);
+    vscale<T>(T(1.0 / n1), x, n, s);
   }
   return lam;
 }
@@ -288,11 +260,13 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only) {
   const int NV = 1 << c.dim;
   P.gal.alloc(size_t(c.E) * P.nslot * NV * NV);
   launch_q1_galerkin(c.dim, c.p, c.E, P.blk.p, P.gal.p, s);
-  std::vector<double> gal(P.gal.n);
-  DGNP_HIP(hipMemcpyAsync(gal.data(), P.gal.p, gal.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  P.vst.alloc(size_t(P.nvert) * (c.dim == 3 ? 27 : 9));
+  launch_vertex_stencil(c.dim, P.gal.p, c.d_nbr.p, c.n, P.nvert, P.vst.p, s);
+  std::vector<double> st(P.vst.n);
+  DGNP_HIP(hipMemcpyAsync(st.data(), P.vst.p, st.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   DGNP_HIP(hipStreamSynchronize(s));
-  clk.mark("galerkin + copy");
-  Csr A1 = vertex_matrix(c, P, gal);
+  clk.mark("galerkin + stencil");
+  Csr A1 = vertex_matrix(c, P, st);
   clk.mark("vertex matrix");
   AmgHierarchy H = sa_setup(A1, 12, 256, 0.0);
   clk.mark("sa setup");
@@ -320,8 +294,6 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only) {
   P.wd.clear();
   ensure_work(c, P);
   clk.mark("work vectors");
-  P.lmax0 = lmax_level0(c, P, s);
-  clk.mark("lmax level 0");
   P.ready = true;
   P.assembled = true;
   P.ready32 = false;
@@ -345,7 +317,11 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only) {
     ensure_work32(c, P);
     P.ready32 = true;
     clk.mark("float copies");
+    P.lmax0 = lmax_level0<float>(c, P, s, P.blk32.p, P.dinv_phi32.p, P.wf[0]->p, P.wf[1]->p);
+  } else {
+    P.lmax0 = lmax_level0<double>(c, P, s, P.blk.p, P.dinv_phi.p, P.wd[0]->p, P.wd[1]->p);
   }
+  clk.mark("lmax level 0");
   DGNP_HIP(hipStreamSynchronize(s));
 }
 
