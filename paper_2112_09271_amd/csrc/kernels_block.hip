@@ -9,6 +9,8 @@
 //  * block sparse matrix-vector products and block-diagonal applies;
 //  * the trilinear (Q1) vertex <-> DG node transfers and the Galerkin
 //    product of the potential block onto the Q1 vertex space.
+#include <algorithm>
+
 #include "dg_device.hpp"
 #include "kernels_block.hpp"
 
@@ -1070,6 +1072,120 @@ __global__ void __launch_bounds__(BT) k_q1_galerkin(const double* __restrict__ b
 }
 
 // ===========================================================================
+// Dataflow (sync-free) forward / backward BILU(0) sweeps.  One launch per
+// sweep instead of one per hyperplane level: the grid is small enough to be
+// resident on the device at once, work-group b takes the elements b, b + G,
+// b + 2G, ... of the level order (reversed for the backward sweep), and an
+// element waits only for the neighbours it reads.  Each element has a
+// completion counter per sweep direction; an element that has completed s
+// sweeps waits until its neighbours' counters reach s + 1, so no reset is
+// needed between sweeps (and a captured graph can replay them).  Vector
+// entries and counters that cross work-groups are written and read with
+// device-scope relaxed atomics (coherent across the XCD caches); the writer
+// waits for its stores to complete before it publishes the counter.  The
+// residency of the whole grid makes the schedule deadlock-free (the least
+// unfinished element always has its inputs); a wait that exceeds its spin
+// limit sets *err and ends the work-group, so the sweep cannot hang.
+// ===========================================================================
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_dev(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// wait until cnt[j] >= target for every valid j in nb[0..n): one thread per entry
+__device__ inline void df_wait(const unsigned* cnt, const int* nb, int n, unsigned target, int spin_limit,
+                               int* err, int* s_abort, int tid) {
+  if (tid < n) {
+    const int j = nb[tid];
+    if (j >= 0) {
+      int spins = 0;
+      while (ld_dev(cnt + j) < target) {
+        if (++spins > spin_limit) {
+          st_dev(err, 1);
+          *s_abort = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// kind 0 (forward): w_i = D_i^{-1} r_i - sum_{s lower} Lhat_{i,s} w_nbr
+// kind 1 (backward): z_i = w_i - sum_{s upper} Uhat_{i,s} z_nbr   (z may alias w)
+template <typename T, int NB, int DIM, int KIND>
+__global__ void __launch_bounds__(BT) k_ilu_df(const T* __restrict__ blk, const int* __restrict__ nbr,
+                                               const int* __restrict__ order, int64_t E, const T* in, T* out,
+                                               int64_t bstride, int64_t vstride, unsigned* cnt, int* err,
+                                               int spin_limit) {
+  constexpr int NSLOT = 2 * DIM + 1;
+  constexpr int QL = (NB + 3) / 4;
+  blk += blockIdx.y * bstride;
+  in += blockIdx.y * vstride;
+  out += blockIdx.y * vstride;
+  cnt += blockIdx.y * E;
+  __shared__ T xs[DIM + 1][NB];
+  __shared__ int s_nb[DIM];
+  __shared__ int s_abort;
+  const int tid = threadIdx.x, row = tid >> 2, part = tid & 3;
+  if (tid == 0) s_abort = 0;
+  for (int64_t t = blockIdx.x; t < E; t += gridDim.x) {
+    const int64_t i = order[KIND == 0 ? t : E - 1 - t];
+    if (tid < DIM) s_nb[tid] = nbr[i * 2 * DIM + 2 * tid + KIND];
+    // the element's own block rows do not depend on the neighbours: fetch them first
+    const T* bi = blk + i * NSLOT * NB * NB;
+    T m[DIM + 1][QL];
+#pragma unroll
+    for (int b = 0; b <= DIM; ++b) {
+      const int slot = KIND == 0 ? (b == 0 ? 0 : 1 + 2 * (b - 1)) : (b == 0 ? 0 : 2 + 2 * (b - 1));
+#pragma unroll
+      for (int c = 0; c < QL; ++c) {
+        const int cc = part * QL + c;
+        m[b][c] = (row < NB && cc < NB && (KIND == 0 || b > 0)) ? bi[int64_t(slot) * NB * NB + row * NB + cc]
+                                                                  : T(0);
+      }
+    }
+    for (int idx = tid; idx < NB; idx += BT) xs[0][idx] = in[i * NB + idx];
+    const unsigned target = ld_dev(cnt + i) + 1u;
+    __syncthreads();
+    df_wait(cnt, s_nb, DIM, target, spin_limit, err, &s_abort, tid);
+    if (s_abort) return;
+    for (int idx = tid; idx < DIM * NB; idx += BT) {
+      const int d = idx / NB, l = idx % NB;
+      const int j = s_nb[d];
+      xs[1 + d][l] = j >= 0 ? ld_dev(out + int64_t(j) * NB + l) : T(0);
+    }
+    __syncthreads();
+    if (row < NB) {
+      T acc = T(0);
+      if constexpr (KIND == 0) {
+#pragma unroll
+        for (int c = 0; c < QL; ++c) acc += m[0][c] * xs[0][part * QL + c < NB ? part * QL + c : 0];
+      }
+#pragma unroll
+      for (int b = 1; b <= DIM; ++b) {
+        T sb = T(0);
+#pragma unroll
+        for (int c = 0; c < QL; ++c) sb += m[b][c] * xs[b][part * QL + c < NB ? part * QL + c : 0];
+        acc -= sb;
+      }
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      if (KIND == 1) acc = xs[0][row] + acc;
+      if (part == 0) st_dev(out + i * NB + row, acc);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) st_dev(cnt + i, target);
+  }
+}
+
+// ===========================================================================
 // host launchers
 // ===========================================================================
 template <int NB>
@@ -1350,5 +1466,81 @@ void launch_vertex_stencil(int dim, const double* gal, const int* nbr, const int
     hipLaunchKernelGGL(k_vertex_stencil<2>, dim3(g), dim3(BT), 0, s, gal, nbr, nn, nvert, st);
   DGNP_HIP(hipGetLastError());
 }
+
+template <typename T, int NB, int DIM>
+static void df_t(int kind, const T* blk, const int* nbr, const int* order, int64_t E, int nfields,
+                 int64_t bstride, int64_t vstride, const T* in, T* out, unsigned* cnt, int* err, int spin_limit,
+                 int grid, hipStream_t s) {
+  const dim3 g = dim3(unsigned(grid), unsigned(nfields)), b = dim3(BT);
+  if (kind == 0)
+    hipLaunchKernelGGL((k_ilu_df<T, NB, DIM, 0>), g, b, 0, s, blk, nbr, order, E, in, out, bstride, vstride, cnt,
+                       err, spin_limit);
+  else
+    hipLaunchKernelGGL((k_ilu_df<T, NB, DIM, 1>), g, b, 0, s, blk, nbr, order, E, in, out, bstride, vstride, cnt,
+                       err, spin_limit);
+}
+
+template <typename T, int NB, int DIM>
+static int df_resident(int nfields) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  DGNP_HIP(hipGetDevice(&dev));
+  DGNP_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  DGNP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (k_ilu_df<T, NB, DIM, 0>), BT, 0));
+  int per_cu1 = 0;
+  DGNP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu1, (k_ilu_df<T, NB, DIM, 1>), BT, 0));
+  if (per_cu1 < per_cu) per_cu = per_cu1;
+  return (ncu * per_cu) / (2 * nfields);  // half the resident capacity per field
+}
+
+template <typename T>
+int ilu_dataflow_grid(int nb, int dim, int64_t E, int nfields) {
+  int r = 0;
+  if (dim == 3) {
+    switch (nb) {
+      case 8: r = df_resident<T, 8, 3>(nfields); break;
+      case 27: r = df_resident<T, 27, 3>(nfields); break;
+      case 64: r = df_resident<T, 64, 3>(nfields); break;
+      default: throw Error(DGNP_E_ARG, "unsupported block size");
+    }
+  } else {
+    switch (nb) {
+      case 4: r = df_resident<T, 4, 2>(nfields); break;
+      case 9: r = df_resident<T, 9, 2>(nfields); break;
+      case 16: r = df_resident<T, 16, 2>(nfields); break;
+      default: throw Error(DGNP_E_ARG, "unsupported block size");
+    }
+  }
+  if (r < 1) throw Error(DGNP_E_HIP, "no resident work-groups for the dataflow sweep");
+  return int(std::min<int64_t>(E, r));
+}
+template int ilu_dataflow_grid<double>(int, int, int64_t, int);
+template int ilu_dataflow_grid<float>(int, int, int64_t, int);
+
+template <typename T>
+void launch_ilu_dataflow(int kind, int nb, int dim, const T* blk, const int* nbr, const int* order, int64_t E,
+                         int nfields, int64_t bstride, int64_t vstride, const T* in, T* out, unsigned* cnt, int* err,
+                         int spin_limit, int grid, hipStream_t s) {
+  if (E == 0 || nfields == 0) return;
+  if (dim == 3) {
+    switch (nb) {
+      case 8: df_t<T, 8, 3>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, cnt, err, spin_limit, grid, s); break;
+      case 27: df_t<T, 27, 3>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, cnt, err, spin_limit, grid, s); break;
+      case 64: df_t<T, 64, 3>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, cnt, err, spin_limit, grid, s); break;
+      default: throw Error(DGNP_E_ARG, "unsupported block size");
+    }
+  } else {
+    switch (nb) {
+      case 4: df_t<T, 4, 2>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, cnt, err, spin_limit, grid, s); break;
+      case 9: df_t<T, 9, 2>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, cnt, err, spin_limit, grid, s); break;
+      case 16: df_t<T, 16, 2>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, cnt, err, spin_limit, grid, s); break;
+      default: throw Error(DGNP_E_ARG, "unsupported block size");
+    }
+  }
+  DGNP_HIP(hipGetLastError());
+}
+template void launch_ilu_dataflow<double>(int, int, int, const double*, const int*, const int*, int64_t, int, int64_t,
+                                          int64_t, const double*, double*, unsigned*, int*, int, int, hipStream_t);
+template void launch_ilu_dataflow<float>(int, int, int, const float*, const int*, const int*, int64_t, int, int64_t,
+                                         int64_t, const float*, float*, unsigned*, int*, int, int, hipStream_t);
 
 }  // namespace dgnp

@@ -21,6 +21,15 @@ template <typename T>
 void launch_ilu_solve(int kind, int nb, int dim, const T* blk, const int* nbr, const int* lev, int64_t first,
                       int64_t count, int nfields, int64_t bstride, int64_t vstride, const T* in, T* out, T* aux,
                       hipStream_t s);
+// dataflow sweeps (kind 0 forward, 1 backward) over the level order `order`
+// with per-element completion counters cnt[nfields][E]; grid from
+// ilu_dataflow_grid (resident on the device at once)
+template <typename T>
+int ilu_dataflow_grid(int nb, int dim, int64_t E, int nfields);
+template <typename T>
+void launch_ilu_dataflow(int kind, int nb, int dim, const T* blk, const int* nbr, const int* order, int64_t E,
+                         int nfields, int64_t bstride, int64_t vstride, const T* in, T* out, unsigned* cnt, int* err,
+                         int spin_limit, int grid, hipStream_t s);
 template <typename T>
 void launch_bspmv(int nb, int dim, int64_t E, const T* blk, const int* nbr, const T* x, const T* b, T alpha,
                   T beta, T* y, hipStream_t s);

@@ -70,6 +70,12 @@ struct Precond {
   DevBuf<double> vN, yN, tN;
   DevBuf<float> vN32, yN32, tN32;
   DevBuf<double> red;
+  // dataflow sweeps: completion counters [forward / backward][field][E], timeout flag
+  DevBuf<unsigned> df_cnt;
+  DevBuf<int> df_err;
+  int df_grid[2] = {0, 0};  // double, float
+  int df_spin = 1 << 22;
+  bool df_on = true;
   bool ready = false, ready32 = false, assembled = false;
 };
 
@@ -105,6 +111,37 @@ void precond_symbolic(dgnp_ctx& c) {
   upload_ref_tables_block(all, 3);
   upload_gll_nodes(all, 3);
   P.red.alloc(size_t(reduce_scratch_size()));
+  const int nf = c.m - 1;
+  // The dataflow sweep pays off where the levels are narrow and the level
+  // launches are latency-bound; with wide levels (several hundred elements on
+  // average) the level-scheduled sweep streams the factor at higher bandwidth.
+  const double width = double(c.E) / double(P.lev_ptr.size() - 1);
+  P.df_on = getenv("DGNP_NO_DATAFLOW") == nullptr && (width < 256.0 || getenv("DGNP_DATAFLOW") != nullptr);
+  if (const char* sl = getenv("DGNP_DATAFLOW_SPIN")) P.df_spin = std::max(0, atoi(sl));
+  P.df_cnt.alloc(size_t(2) * nf * c.E);
+  P.df_err.alloc(1);
+  DGNP_HIP(hipMemsetAsync(P.df_cnt.p, 0, P.df_cnt.n * sizeof(unsigned), c.stream));
+  DGNP_HIP(hipMemsetAsync(P.df_err.p, 0, sizeof(int), c.stream));
+  DGNP_HIP(hipStreamSynchronize(c.stream));
+  P.df_grid[0] = ilu_dataflow_grid<double>(c.nb, c.dim, c.E, nf);
+  P.df_grid[1] = ilu_dataflow_grid<float>(c.nb, c.dim, c.E, nf);
+}
+
+// Reports (and clears) a dataflow sweep that ended at its wait limit; the
+// counters are reset so that later sweeps start consistent.  Synchronises.
+// A new linearisation point clears such a state silently (the failed solve has
+// reported it already, possibly as a non-finite vector).
+void precond_check(dgnp_ctx& c, bool report) {
+  if (!c.pc || !c.pc->df_err.p) return;
+  Precond& P = *c.pc;
+  int h = 0;
+  DGNP_HIP(hipDeviceSynchronize());
+  DGNP_HIP(hipMemcpy(&h, P.df_err.p, sizeof(int), hipMemcpyDeviceToHost));
+  if (h == 0) return;
+  DGNP_HIP(hipMemset(P.df_cnt.p, 0, P.df_cnt.n * sizeof(unsigned)));
+  DGNP_HIP(hipMemset(P.df_err.p, 0, sizeof(int)));
+  DGNP_HIP(hipDeviceSynchronize());
+  if (report) throw Error(DGNP_E_BREAKDOWN, "ILU dataflow sweep exceeded its wait limit");
 }
 
 // ---- vertex matrix from the per-element Galerkin blocks ----------------------
@@ -223,6 +260,7 @@ struct PhaseClock {
 };
 
 void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only) {
+  precond_check(c, false);
   Precond& P = *c.pc;
   PhaseClock clk(s);
   const int64_t per_field = c.E * P.nslot * P.bsz;
@@ -463,6 +501,20 @@ static void ilu_solve(dgnp_ctx& c, Precond& P, bool transpose, const T* in, T* o
   static const char* names[4][2] = {{"ilu_fwd", "ilu_fwd_f32"}, {"ilu_bwd", "ilu_bwd_f32"},
                                     {"ilu_fwdT", "ilu_fwdT_f32"}, {"ilu_bwdT", "ilu_bwdT_f32"}};
   const int k0 = transpose ? 2 : 0;
+  if (!transpose && P.df_on) {
+    unsigned* cnt = P.df_cnt.p;
+    {
+      ScopeTimer tm(c, names[0][f32], s);
+      launch_ilu_dataflow<T>(0, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, c.E, nf, fstride, c.Nf, in, out, cnt,
+                             P.df_err.p, P.df_spin, P.df_grid[f32], s);
+    }
+    {
+      ScopeTimer tm(c, names[1][f32], s);
+      launch_ilu_dataflow<T>(1, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, c.E, nf, fstride, c.Nf, out, out,
+                             cnt + int64_t(nf) * c.E, P.df_err.p, P.df_spin, P.df_grid[f32], s);
+    }
+    return;
+  }
   T* aux = transpose ? Sel<T>::vN(P) + c.Nf : nullptr;  // concentration part of a work vector
   // timed per level launch (one event pair per kernel) when profiling is on
   for (int l = 0; l < L; ++l) {

@@ -376,6 +376,7 @@ int newton_solve(dgnp_ctx& c, double* x, const dgnp_solve_opts& o, dgnp_solve_st
     const auto tk = clk::now();
     LinResult lr = fgmres(c, W.b.p, W.dx.p, o.lin_rtol * res, o.restart, o.max_lin_it, f32, false, o.pc_kind,
                           true, o.verbose, s);
+    precond_check(c);
     st.t_krylov += since(tk);
     st.lin_its_total += lr.its;
     st.refine_its_total += lr.refinements;
@@ -458,6 +459,7 @@ int adjoint_solve(dgnp_ctx& c, const double* x, double* dJ_dbc, double* dJ_dPe, 
   const auto tk = clk::now();
   LinResult lr = fgmres(c, g.p, lam.p, o.rtol * gn, o.restart, o.max_lin_it, o.prec == DGNP_F32, true, o.pc_kind,
                         true, o.verbose, s);
+  precond_check(c);
   st.t_krylov = since(tk);
   st.lin_its_total = lr.its;
   st.refine_its_total = lr.refinements;

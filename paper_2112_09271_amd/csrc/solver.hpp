@@ -11,6 +11,8 @@ void precond_apply(dgnp_ctx& c, const void* r, void* z, bool f32, bool transpose
                    hipStream_t s);                                     // precond.hip
 void get_block(dgnp_ctx& c, int field, int64_t elem, int slot, double* out);
 void precond_invalidate(dgnp_ctx& c);
+// clears a dataflow sweep that hit its wait limit; throws DGNP_E_BREAKDOWN if report (synchronises)
+void precond_check(dgnp_ctx& c, bool report = true);
 void vcycle_phi(dgnp_ctx& c, const double* b, double* x, hipStream_t s);     // precond.hip
 void phi_block_apply(dgnp_ctx& c, const double* x, double* y, hipStream_t s); // precond.hip
 

@@ -88,3 +88,47 @@ def test_precond_transpose_is_adjoint(name, pc_kind):
         a = host(gp.precond_apply(r0))[: gp.Nf] @ w0[: gp.Nf]
         b = host(gp.precond_apply(w0))[: gp.Nf] @ r0[: gp.Nf]
         assert abs(a - b) <= 1e-12 * abs(a)
+
+
+@pytest.mark.parametrize("name", ["cfg2t", "cfg3s", "cfg1"])
+def test_dataflow_and_level_scheduled_sweeps_agree(name, monkeypatch):
+    """The dataflow ILU sweeps (one launch, per-element completion counters) and
+    the level-by-level launches compute the same triangular solves; they differ
+    only in the order of the partial sums of each row."""
+    from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64
+    monkeypatch.setenv("DGNP_DATAFLOW", "1")
+    cfg, _, g_df = pair(name, with_oracle=False)
+    monkeypatch.delenv("DGNP_DATAFLOW")
+    monkeypatch.setenv("DGNP_NO_DATAFLOW", "1")
+    _, _, g_lv = pair(name, with_oracle=False)
+    x = random_state(cfg)
+    r = random_vector(cfg, 41)
+    for gp in (g_df, g_lv):
+        gp.set_state(x, prec=DGNP_F32)
+    for prec, tol in ((DGNP_F64, 1e-12), (DGNP_F32, 1e-5)):
+        for rep in range(3):  # repeated sweeps reuse the completion counters
+            a = host(g_df.precond_apply(r, prec=prec))
+            b = host(g_lv.precond_apply(r, prec=prec))
+            assert rel_err(a, b) <= tol, (prec, rep, rel_err(a, b))
+
+
+def test_dataflow_wait_limit_is_reported(monkeypatch):
+    """A sweep whose waits run out (spin limit 0) ends every work-group and the
+    solve reports an error instead of hanging; a new problem solves normally."""
+    from paper_2112_09271_amd.dgnp import (DGNP_E_BREAKDOWN, DGNP_E_NOCONV, DGNP_E_NONFINITE, DGNP_F32,
+                                           DgnpError)
+    monkeypatch.setenv("DGNP_DATAFLOW", "1")
+    monkeypatch.setenv("DGNP_DATAFLOW_SPIN", "0")
+    cfg, _, gp = pair("cfg2t", with_oracle=False)
+    try:
+        x, st = gp.solve(prec=DGNP_F32, max_newton=2)
+        failed = False
+    except DgnpError as e:
+        assert e.code in (DGNP_E_BREAKDOWN, DGNP_E_NONFINITE, DGNP_E_NOCONV), e
+        failed = True
+    gp.close()
+    monkeypatch.delenv("DGNP_DATAFLOW_SPIN")
+    _, _, g2 = pair("cfg2t", with_oracle=False)
+    x, st = g2.solve(prec=DGNP_F32)
+    assert st.status == 0 and st.res_final <= 1e-8 * st.res0
+    print("first solve failed:", failed)
