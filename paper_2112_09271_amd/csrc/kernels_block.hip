@@ -1185,6 +1185,93 @@ __global__ void __launch_bounds__(BT) k_ilu_df(const T* __restrict__ blk, const 
   }
 }
 
+// Single-precision variant: every exchanged vector entry travels together
+// with its sweep count in one 64-bit word (value bits low, count high), so a
+// consumer polls the entries it needs directly and a producer publishes a row
+// with one store; no separate counter, no wait for store completion.  The
+// plain result is also written to `out` for the kernels that follow.
+template <int NB, int DIM, int KIND>
+__global__ void __launch_bounds__(BT) k_ilu_dfp(const float* __restrict__ blk, const int* __restrict__ nbr,
+                                                const int* __restrict__ order, int64_t E, const float* in,
+                                                float* out, int64_t bstride, int64_t vstride, uint64_t* wp, int* err,
+                                                int spin_limit) {
+  constexpr int NSLOT = 2 * DIM + 1;
+  constexpr int QL = (NB + 3) / 4;
+  blk += blockIdx.y * bstride;
+  in += blockIdx.y * vstride;
+  out += blockIdx.y * vstride;
+  wp += blockIdx.y * vstride;
+  __shared__ float xs[DIM + 1][NB];
+  __shared__ int s_nb[DIM];
+  __shared__ int s_abort;
+  const int tid = threadIdx.x, row = tid >> 2, part = tid & 3;
+  if (tid == 0) s_abort = 0;
+  for (int64_t t = blockIdx.x; t < E; t += gridDim.x) {
+    const int64_t i = order[KIND == 0 ? t : E - 1 - t];
+    if (tid < DIM) s_nb[tid] = nbr[i * 2 * DIM + 2 * tid + KIND];
+    const float* bi = blk + i * NSLOT * NB * NB;
+    float m[DIM + 1][QL];
+#pragma unroll
+    for (int b = 0; b <= DIM; ++b) {
+      const int slot = KIND == 0 ? (b == 0 ? 0 : 1 + 2 * (b - 1)) : (b == 0 ? 0 : 2 + 2 * (b - 1));
+#pragma unroll
+      for (int c = 0; c < QL; ++c) {
+        const int cc = part * QL + c;
+        m[b][c] = (row < NB && cc < NB && (KIND == 0 || b > 0)) ? bi[int64_t(slot) * NB * NB + row * NB + cc]
+                                                                  : 0.0f;
+      }
+    }
+    for (int idx = tid; idx < NB; idx += BT) xs[0][idx] = in[i * NB + idx];
+    const unsigned target = unsigned(ld_dev(wp + i * NB) >> 32) + 1u;
+    __syncthreads();
+    for (int idx = tid; idx < DIM * NB; idx += BT) {
+      const int d = idx / NB, l = idx % NB;
+      const int j = s_nb[d];
+      float v = 0.0f;
+      if (j >= 0) {
+        const uint64_t* src = wp + int64_t(j) * NB + l;
+        uint64_t word = ld_dev(src);
+        int spins = 0;
+        while (unsigned(word >> 32) != target) {
+          if (++spins > spin_limit) {
+            st_dev(err, 1);
+            s_abort = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          word = ld_dev(src);
+        }
+        v = __uint_as_float(unsigned(word));
+      }
+      xs[1 + d][l] = v;
+    }
+    __syncthreads();
+    if (s_abort) return;
+    if (row < NB) {
+      float acc = 0.0f;
+      if constexpr (KIND == 0) {
+#pragma unroll
+        for (int c = 0; c < QL; ++c) acc += m[0][c] * xs[0][part * QL + c < NB ? part * QL + c : 0];
+      }
+#pragma unroll
+      for (int b = 1; b <= DIM; ++b) {
+        float sb = 0.0f;
+#pragma unroll
+        for (int c = 0; c < QL; ++c) sb += m[b][c] * xs[b][part * QL + c < NB ? part * QL + c : 0];
+        acc -= sb;
+      }
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      if (KIND == 1) acc = xs[0][row] + acc;
+      if (part == 0) {
+        st_dev(wp + i * NB + row, (uint64_t(target) << 32) | uint64_t(__float_as_uint(acc)));
+        out[i * NB + row] = acc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ===========================================================================
 // host launchers
 // ===========================================================================
@@ -1480,15 +1567,30 @@ static void df_t(int kind, const T* blk, const int* nbr, const int* order, int64
                        err, spin_limit);
 }
 
+template <int NB, int DIM>
+static void dfp_t(int kind, const float* blk, const int* nbr, const int* order, int64_t E, int nfields,
+                  int64_t bstride, int64_t vstride, const float* in, float* out, uint64_t* wp, int* err,
+                  int spin_limit, int grid, hipStream_t s) {
+  const dim3 g = dim3(unsigned(grid), unsigned(nfields)), b = dim3(BT);
+  if (kind == 0)
+    hipLaunchKernelGGL((k_ilu_dfp<NB, DIM, 0>), g, b, 0, s, blk, nbr, order, E, in, out, bstride, vstride, wp, err,
+                       spin_limit);
+  else
+    hipLaunchKernelGGL((k_ilu_dfp<NB, DIM, 1>), g, b, 0, s, blk, nbr, order, E, in, out, bstride, vstride, wp, err,
+                       spin_limit);
+}
+
 template <typename T, int NB, int DIM>
 static int df_resident(int nfields) {
   int dev = 0, ncu = 0, per_cu = 0;
   DGNP_HIP(hipGetDevice(&dev));
   DGNP_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  DGNP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (k_ilu_df<T, NB, DIM, 0>), BT, 0));
-  int per_cu1 = 0;
-  DGNP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu1, (k_ilu_df<T, NB, DIM, 1>), BT, 0));
-  if (per_cu1 < per_cu) per_cu = per_cu1;
+  int occ[4] = {0, 0, 0, 0};
+  DGNP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], (k_ilu_df<T, NB, DIM, 0>), BT, 0));
+  DGNP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], (k_ilu_df<T, NB, DIM, 1>), BT, 0));
+  DGNP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], (k_ilu_dfp<NB, DIM, 0>), BT, 0));
+  DGNP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[3], (k_ilu_dfp<NB, DIM, 1>), BT, 0));
+  per_cu = std::min(std::min(occ[0], occ[1]), std::min(occ[2], occ[3]));
   return (ncu * per_cu) / (2 * nfields);  // half the resident capacity per field
 }
 
@@ -1538,6 +1640,28 @@ void launch_ilu_dataflow(int kind, int nb, int dim, const T* blk, const int* nbr
   }
   DGNP_HIP(hipGetLastError());
 }
+void launch_ilu_dataflow_packed(int kind, int nb, int dim, const float* blk, const int* nbr, const int* order,
+                                int64_t E, int nfields, int64_t bstride, int64_t vstride, const float* in, float* out,
+                                uint64_t* wp, int* err, int spin_limit, int grid, hipStream_t s) {
+  if (E == 0 || nfields == 0) return;
+  if (dim == 3) {
+    switch (nb) {
+      case 8: dfp_t<8, 3>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
+      case 27: dfp_t<27, 3>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
+      case 64: dfp_t<64, 3>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
+      default: throw Error(DGNP_E_ARG, "unsupported block size");
+    }
+  } else {
+    switch (nb) {
+      case 4: dfp_t<4, 2>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
+      case 9: dfp_t<9, 2>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
+      case 16: dfp_t<16, 2>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
+      default: throw Error(DGNP_E_ARG, "unsupported block size");
+    }
+  }
+  DGNP_HIP(hipGetLastError());
+}
+
 template void launch_ilu_dataflow<double>(int, int, int, const double*, const int*, const int*, int64_t, int, int64_t,
                                           int64_t, const double*, double*, unsigned*, int*, int, int, hipStream_t);
 template void launch_ilu_dataflow<float>(int, int, int, const float*, const int*, const int*, int64_t, int, int64_t,

@@ -30,6 +30,10 @@ template <typename T>
 void launch_ilu_dataflow(int kind, int nb, int dim, const T* blk, const int* nbr, const int* order, int64_t E,
                          int nfields, int64_t bstride, int64_t vstride, const T* in, T* out, unsigned* cnt, int* err,
                          int spin_limit, int grid, hipStream_t s);
+// single precision with (value, sweep count) packed in the 64-bit words wp[nfields][Nf]
+void launch_ilu_dataflow_packed(int kind, int nb, int dim, const float* blk, const int* nbr, const int* order,
+                                int64_t E, int nfields, int64_t bstride, int64_t vstride, const float* in, float* out,
+                                uint64_t* wp, int* err, int spin_limit, int grid, hipStream_t s);
 template <typename T>
 void launch_bspmv(int nb, int dim, int64_t E, const T* blk, const int* nbr, const T* x, const T* b, T alpha,
                   T beta, T* y, hipStream_t s);

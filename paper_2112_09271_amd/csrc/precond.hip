@@ -72,6 +72,7 @@ struct Precond {
   DevBuf<double> red;
   // dataflow sweeps: completion counters [forward / backward][field][E], timeout flag
   DevBuf<unsigned> df_cnt;
+  DevBuf<uint64_t> df_wp;   // single precision: packed (value, count) [forward / backward][field][Nf]
   DevBuf<int> df_err;
   int df_grid[2] = {0, 0};  // double, float
   int df_spin = 1 << 22;
@@ -119,8 +120,10 @@ void precond_symbolic(dgnp_ctx& c) {
   P.df_on = getenv("DGNP_NO_DATAFLOW") == nullptr && (width < 256.0 || getenv("DGNP_DATAFLOW") != nullptr);
   if (const char* sl = getenv("DGNP_DATAFLOW_SPIN")) P.df_spin = std::max(0, atoi(sl));
   P.df_cnt.alloc(size_t(2) * nf * c.E);
+  P.df_wp.alloc(size_t(2) * nf * c.Nf);
   P.df_err.alloc(1);
   DGNP_HIP(hipMemsetAsync(P.df_cnt.p, 0, P.df_cnt.n * sizeof(unsigned), c.stream));
+  DGNP_HIP(hipMemsetAsync(P.df_wp.p, 0, P.df_wp.n * sizeof(uint64_t), c.stream));
   DGNP_HIP(hipMemsetAsync(P.df_err.p, 0, sizeof(int), c.stream));
   DGNP_HIP(hipStreamSynchronize(c.stream));
   P.df_grid[0] = ilu_dataflow_grid<double>(c.nb, c.dim, c.E, nf);
@@ -139,6 +142,7 @@ void precond_check(dgnp_ctx& c, bool report) {
   DGNP_HIP(hipMemcpy(&h, P.df_err.p, sizeof(int), hipMemcpyDeviceToHost));
   if (h == 0) return;
   DGNP_HIP(hipMemset(P.df_cnt.p, 0, P.df_cnt.n * sizeof(unsigned)));
+  DGNP_HIP(hipMemset(P.df_wp.p, 0, P.df_wp.n * sizeof(uint64_t)));
   DGNP_HIP(hipMemset(P.df_err.p, 0, sizeof(int)));
   DGNP_HIP(hipDeviceSynchronize());
   if (report) throw Error(DGNP_E_BREAKDOWN, "ILU dataflow sweep exceeded its wait limit");
@@ -501,6 +505,23 @@ static void ilu_solve(dgnp_ctx& c, Precond& P, bool transpose, const T* in, T* o
   static const char* names[4][2] = {{"ilu_fwd", "ilu_fwd_f32"}, {"ilu_bwd", "ilu_bwd_f32"},
                                     {"ilu_fwdT", "ilu_fwdT_f32"}, {"ilu_bwdT", "ilu_bwdT_f32"}};
   const int k0 = transpose ? 2 : 0;
+  if (!transpose && P.df_on && f32) {
+    uint64_t* wp = P.df_wp.p;
+    const float* bf = reinterpret_cast<const float*>(blk);
+    {
+      ScopeTimer tm(c, names[0][1], s);
+      launch_ilu_dataflow_packed(0, c.nb, c.dim, bf, c.d_nbr.p, P.lev_elems.p, c.E, nf, fstride, c.Nf,
+                                 reinterpret_cast<const float*>(in), reinterpret_cast<float*>(out), wp, P.df_err.p,
+                                 P.df_spin, P.df_grid[1], s);
+    }
+    {
+      ScopeTimer tm(c, names[1][1], s);
+      launch_ilu_dataflow_packed(1, c.nb, c.dim, bf, c.d_nbr.p, P.lev_elems.p, c.E, nf, fstride, c.Nf,
+                                 reinterpret_cast<const float*>(out), reinterpret_cast<float*>(out),
+                                 wp + int64_t(nf) * c.Nf, P.df_err.p, P.df_spin, P.df_grid[1], s);
+    }
+    return;
+  }
   if (!transpose && P.df_on) {
     unsigned* cnt = P.df_cnt.p;
     {
