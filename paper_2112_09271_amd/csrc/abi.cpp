@@ -63,6 +63,7 @@ dgnp::KArgs dgnp_ctx::kargs() const {
   A.bcq = d_bcq.p;
   A.src = d_src.p;
   A.objective_tag = 1;
+  A.vin_mask = ~0u;
   return A;
 }
 

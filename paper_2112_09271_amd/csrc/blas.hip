@@ -45,6 +45,11 @@ __global__ void k_axpy(T a, const T* __restrict__ x, T* __restrict__ y, int64_t 
   for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB)
     y[i] += a * x[i];
 }
+// z = x - y
+template <typename T>
+__global__ void k_sub(const T* __restrict__ x, const T* __restrict__ y, T* __restrict__ z, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) z[i] = x[i] - y[i];
+}
 template <typename T>
 __global__ void k_scale(T a, T* __restrict__ x, int64_t n) {
   for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) x[i] *= a;
@@ -78,6 +83,13 @@ void vaxpby(T a, const T* x, T b, T* y, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for(n)), dim3(VB), 0, s, a, x, b, y, n);
 }
+template <typename T>
+void vsub(const T* x, const T* y, T* z, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_sub<T>, dim3(grid_for(n)), dim3(VB), 0, s, x, y, z, n);
+}
+template void vsub<double>(const double*, const double*, double*, int64_t, hipStream_t);
+template void vsub<float>(const float*, const float*, float*, int64_t, hipStream_t);
 template <typename T>
 void vscale(T a, T* x, int64_t n, hipStream_t s) {
   if (n <= 0) return;

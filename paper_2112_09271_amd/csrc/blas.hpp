@@ -11,6 +11,7 @@ template <typename T> void vcopy(const T* x, T* y, int64_t n, hipStream_t s);
 template <typename T> void vaxpy(T a, const T* x, T* y, int64_t n, hipStream_t s);        // y += a x
 template <typename T> void vaxpby(T a, const T* x, T b, T* y, int64_t n, hipStream_t s);  // y = a x + b y
 template <typename T> void vscale(T a, T* x, int64_t n, hipStream_t s);
+template <typename T> void vsub(const T* x, const T* y, T* z, int64_t n, hipStream_t s);  // z = x - y
 // out[j] = <V_j, w> for j < k, V column-major [k][n] (double accumulation)
 void vdots(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* out_dev,
            hipStream_t s);

@@ -109,6 +109,7 @@ struct KArgs {
   const double* bcq;    // [m][n_bface][nqf] boundary data at face points (f = 0: phi)
   const double* src;    // [m][E][nqv] volume sources or nullptr
   int objective_tag;    // box face of the objective
+  unsigned vin_mask;    // fields of the input vector that are read (the others count as zero)
 };
 
 enum Mode { M_RES = 0, M_JAC = 1, M_JACT = 2, M_DPE = 3, M_OBJG = 4, M_DATAT = 5 };

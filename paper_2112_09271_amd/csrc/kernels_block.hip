@@ -1667,4 +1667,89 @@ template void launch_ilu_dataflow<double>(int, int, int, const double*, const in
 template void launch_ilu_dataflow<float>(int, int, int, const float*, const int*, const int*, int64_t, int, int64_t,
                                          int64_t, const float*, float*, unsigned*, int*, int, int, hipStream_t);
 
+// One Chebyshev smoothing step on the element-block level, fused:
+//   r = base - A u          (u null: r = base)
+//   d = c1 * Dinv r + c2 * dprev   (dprev null: no second term)
+//   x_out = x_in + d        (x_in null: x_out = d)
+// with optional stores of r and d.  One work-group per element; x_out must not
+// alias u (the neighbours read u).
+template <typename T, int NB, int DIM>
+__global__ void __launch_bounds__(BT) k_cheb_blk(const T* __restrict__ blk, const int* __restrict__ nbr,
+                                                 const T* __restrict__ dinv, const T* u, const T* base,
+                                                 const T* dprev, const T* x_in, T c1, T c2, T* r_out, T* d_out,
+                                                 T* x_out) {
+  constexpr int NSLOT = 2 * DIM + 1;
+  __shared__ T xs[NSLOT][NB];
+  __shared__ T rs[NB];
+  const int tid = threadIdx.x, row = tid >> 2, part = tid & 3;
+  const int64_t i = blockIdx.x;
+  int nb[NSLOT];
+  nb[0] = int(i);
+  for (int s = 0; s < 2 * DIM; ++s) nb[1 + s] = nbr[i * 2 * DIM + s];
+  if (u) {
+    for (int idx = tid; idx < NB; idx += BT)
+      for (int s = 0; s < NSLOT; ++s) xs[s][idx] = nb[s] >= 0 ? u[int64_t(nb[s]) * NB + idx] : T(0);
+    __syncthreads();
+  }
+  const T* bi = blk + i * NSLOT * NB * NB;
+  if (row < NB) {
+    T acc = T(0);
+    if (u)
+      for (int s = 0; s < NSLOT; ++s)
+        if (nb[s] >= 0) acc += row_dot4<T, NB>(bi + int64_t(s) * NB * NB, xs[s], row, part);
+    if (part == 0) {
+      const T r = base[i * NB + row] - acc;
+      rs[row] = r;
+      if (r_out) r_out[i * NB + row] = r;
+    }
+  }
+  __syncthreads();
+  if (row < NB) {
+    const T z = row_dot4<T, NB>(dinv + i * NB * NB, rs, row, part);
+    if (part == 0) {
+      const int64_t k = i * NB + row;
+      T d = c1 * z;
+      if (dprev) d += c2 * dprev[k];
+      if (d_out) d_out[k] = d;
+      x_out[k] = (x_in ? x_in[k] : T(0)) + d;
+    }
+  }
+}
+
+template <typename T, int NB, int DIM>
+static void cheb_blk_t(int64_t E, const T* blk, const int* nbr, const T* dinv, const T* u, const T* base,
+                       const T* dprev, const T* x_in, T c1, T c2, T* r_out, T* d_out, T* x_out, hipStream_t s) {
+  hipLaunchKernelGGL((k_cheb_blk<T, NB, DIM>), dim3(unsigned(E)), dim3(BT), 0, s, blk, nbr, dinv, u, base, dprev,
+                     x_in, c1, c2, r_out, d_out, x_out);
+}
+
+template <typename T>
+void launch_cheb_blk(int nb, int dim, int64_t E, const T* blk, const int* nbr, const T* dinv, const T* u,
+                     const T* base, const T* dprev, const T* x_in, T c1, T c2, T* r_out, T* d_out, T* x_out,
+                     hipStream_t s) {
+  if (E == 0) return;
+  if (dim == 3) {
+    switch (nb) {
+      case 8: cheb_blk_t<T, 8, 3>(E, blk, nbr, dinv, u, base, dprev, x_in, c1, c2, r_out, d_out, x_out, s); break;
+      case 27: cheb_blk_t<T, 27, 3>(E, blk, nbr, dinv, u, base, dprev, x_in, c1, c2, r_out, d_out, x_out, s); break;
+      case 64: cheb_blk_t<T, 64, 3>(E, blk, nbr, dinv, u, base, dprev, x_in, c1, c2, r_out, d_out, x_out, s); break;
+      default: throw Error(DGNP_E_ARG, "unsupported block size");
+    }
+  } else {
+    switch (nb) {
+      case 4: cheb_blk_t<T, 4, 2>(E, blk, nbr, dinv, u, base, dprev, x_in, c1, c2, r_out, d_out, x_out, s); break;
+      case 9: cheb_blk_t<T, 9, 2>(E, blk, nbr, dinv, u, base, dprev, x_in, c1, c2, r_out, d_out, x_out, s); break;
+      case 16: cheb_blk_t<T, 16, 2>(E, blk, nbr, dinv, u, base, dprev, x_in, c1, c2, r_out, d_out, x_out, s); break;
+      default: throw Error(DGNP_E_ARG, "unsupported block size");
+    }
+  }
+  DGNP_HIP(hipGetLastError());
+}
+template void launch_cheb_blk<double>(int, int, int64_t, const double*, const int*, const double*, const double*,
+                                      const double*, const double*, const double*, double, double, double*,
+                                      double*, double*, hipStream_t);
+template void launch_cheb_blk<float>(int, int, int64_t, const float*, const int*, const float*, const float*,
+                                     const float*, const float*, const float*, float, float, float*, float*,
+                                     float*, hipStream_t);
+
 }  // namespace dgnp

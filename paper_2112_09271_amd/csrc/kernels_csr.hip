@@ -69,4 +69,48 @@ void launch_dense_gemv(int n, const T* M, const T* x, T* y, hipStream_t s) {
 template void launch_dense_gemv<double>(int, const double*, const double*, double*, hipStream_t);
 template void launch_dense_gemv<float>(int, const float*, const float*, float*, hipStream_t);
 
+// One Chebyshev smoothing step on a scalar (CSR) level, fused:
+//   r = base - A u          (u null: r = base)
+//   d = c1 * dinv .* r + c2 * dprev   (dprev null: no second term)
+//   x_out = x_in + d        (x_in null: x_out = d)
+// with optional stores of r and d.  One 8-lane group per row.  x_out must not
+// alias u (other rows read u).
+template <typename T>
+__global__ void k_cheb_csr(int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ v,
+                           const T* __restrict__ dinv, const T* u, const T* base, const T* dprev, const T* x_in,
+                           T c1, T c2, T* r_out, T* d_out, T* x_out) {
+  const int64_t gid = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  const int row = int(gid >> 3), lane = int(gid & 7);
+  T acc = T(0);
+  if (row < n && u)
+    for (int k = rp[row] + lane; k < rp[row + 1]; k += 8) acc += v[k] * u[ci[k]];
+  acc += __shfl_xor(acc, 1, 64);
+  acc += __shfl_xor(acc, 2, 64);
+  acc += __shfl_xor(acc, 4, 64);
+  if (row < n && lane == 0) {
+    const T r = base[row] - acc;
+    T d = c1 * (dinv[row] * r);
+    if (dprev) d += c2 * dprev[row];
+    if (r_out) r_out[row] = r;
+    if (d_out) d_out[row] = d;
+    x_out[row] = (x_in ? x_in[row] : T(0)) + d;
+  }
+}
+
+template <typename T>
+void launch_cheb_csr(int n, const int* rp, const int* ci, const T* v, const T* dinv, const T* u, const T* base,
+                     const T* dprev, const T* x_in, T c1, T c2, T* r_out, T* d_out, T* x_out, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t thr = int64_t(n) * 8;
+  hipLaunchKernelGGL(k_cheb_csr<T>, dim3(unsigned((thr + 255) / 256)), dim3(256), 0, s, n, rp, ci, v, dinv, u,
+                     base, dprev, x_in, c1, c2, r_out, d_out, x_out);
+  DGNP_HIP(hipGetLastError());
+}
+template void launch_cheb_csr<double>(int, const int*, const int*, const double*, const double*, const double*,
+                                      const double*, const double*, const double*, double, double, double*,
+                                      double*, double*, hipStream_t);
+template void launch_cheb_csr<float>(int, const int*, const int*, const float*, const float*, const float*,
+                                     const float*, const float*, const float*, float, float, float*, float*,
+                                     float*, hipStream_t);
+
 }  // namespace dgnp

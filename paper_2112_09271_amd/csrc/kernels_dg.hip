@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
   for (int i = tid; i < NBT; i += NT) {
     const int f = i / NB, l = i % NB;
     s_x[i] = xs[f * Nf + e * NB + l];
-    if constexpr (HAS_V) s_v[i] = vin[f * Nf + e * NB + l];
+    if constexpr (HAS_V) s_v[i] = ((A.vin_mask >> f) & 1u) ? vin[f * Nf + e * NB + l] : T(0);
   }
   if (tid < NFACE) s_nb[tid] = A.nbr[e * NFACE + tid];
   __syncthreads();
@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
       const T* u = nullptr;
       if (sd == 0)
         u = (ar == 0 ? s_x : s_v) + f * NB;
-      else if (NEED_NB && s_nb[fc] >= 0)
+      else if (NEED_NB && s_nb[fc] >= 0 && (ar == 0 || ((A.vin_mask >> f) & 1u)))
         u = (ar == 0 ? xs : vin) + f * Nf + int64_t(s_nb[fc]) * NB;
       const bool need_dn = MODE == M_RES || ar == 1 || f == 0;
       T val = T(0), dn = T(0);

@@ -446,33 +446,37 @@ struct Mg {
       launch_csr_spmv<T>(Pm.n, Pm.rp.p, Pm.ci.p, Pm.v.p, xc, x, T(1), T(1), x, s);
     }
   }
-  // Chebyshev smoothing on [0.1, 1.1] * lmax(D^{-1} A), degree 2
+  // one fused Chebyshev step on level l (see launch_cheb_blk)
+  void step(int l, const T* u, const T* base, const T* dprev, const T* x_in, double c1, double c2, T* r_out,
+            T* d_out, T* x_out) {
+    if (l == 0) {
+      launch_cheb_blk<T>(c.nb, c.dim, c.E, Sel<T>::blk(P), c.d_nbr.p, Sel<T>::dinv(P), u, base, dprev, x_in, T(c1),
+                         T(c2), r_out, d_out, x_out, s);
+    } else {
+      DevCsr<T>& M = Sel<T>::A(P.mg[l - 1]);
+      launch_cheb_csr<T>(M.n, M.rp.p, M.ci.p, M.v.p, Sel<T>::ldinv(P.mg[l - 1]), u, base, dprev, x_in, T(c1),
+                         T(c2), r_out, d_out, x_out, s);
+    }
+  }
+  // Chebyshev smoothing of degree 2 on [0.1, 1.1] * lmax(D^{-1} A):
+  //   d_1 = D^{-1} r_0 / theta,  x_1 = x_0 + d_1,  r_1 = r_0 - A d_1,
+  //   d_2 = (2 rho_1 / delta) D^{-1} r_1 + rho_1 rho_0 d_1,  x_2 = x_1 + d_2,
+  // rho_0 = delta / theta, rho_1 = 1 / (2 theta / delta - rho_0); two fused
+  // launches per sweep.  Zero initial guess: r_0 = b; otherwise r_0 = b - A x_0.
   void cheb(int l, const T* b, T* x, bool zero_init) {
-    const int64_t n = size(l);
-    T* r = Sel<T>::w(P, size_t(l) * 5 + 2);
-    T* d = Sel<T>::w(P, size_t(l) * 5 + 3);
-    T* z = Sel<T>::w(P, size_t(l) * 5 + 4);
+    T* r1 = Sel<T>::w(P, size_t(l) * 5 + 2);
+    T* d1 = Sel<T>::w(P, size_t(l) * 5 + 3);
+    T* x1 = Sel<T>::w(P, size_t(l) * 5 + 4);
     const double lm = lmax(l), lo = 0.1 * lm, hi = 1.1 * lm;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
-    double rho = 1.0 / sigma;
-    const int deg = 2;
-    if (zero_init)
-      vcopy<T>(b, r, n, s);
-    else
-      A(l, x, b, T(-1), T(1), r);
-    Dinv(l, r, z);
-    vaxpby<T>(T(1.0 / theta), z, T(0), d, n, s);
-    for (int k = 1; k <= deg; ++k) {
-      if (zero_init && k == 1)
-        vcopy<T>(d, x, n, s);
-      else
-        vaxpy<T>(T(1), d, x, n, s);
-      if (k == deg) break;
-      A(l, d, r, T(-1), T(1), r);
-      const double rho_new = 1.0 / (2.0 * sigma - rho);
-      Dinv(l, r, z);
-      vaxpby<T>(T(2.0 * rho_new / delta), z, T(rho_new * rho), d, n, s);
-      rho = rho_new;
+    const double rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
+    const double a2 = 2.0 * rho1 / delta, b2 = rho1 * rho0;
+    if (zero_init) {
+      step(l, nullptr, b, nullptr, nullptr, 1.0 / theta, 0.0, nullptr, nullptr, d1);  // x_1 = d_1
+      step(l, d1, b, d1, d1, a2, b2, nullptr, nullptr, x);
+    } else {
+      step(l, x, b, nullptr, x, 1.0 / theta, 0.0, r1, d1, x1);
+      step(l, d1, r1, d1, x1, a2, b2, nullptr, nullptr, x);
     }
   }
   void vcycle(int l, const T* b, T* x) {
@@ -558,18 +562,16 @@ static void apply_t(dgnp_ctx& c, const T* r, T* z, bool transpose, int kind, hip
   Mg<T> mg{c, P, s};
   const int64_t Nf = c.Nf;
   const bool f32 = std::is_same<T, float>::value;
-  T* u = Sel<T>::vN(P);
   T* y = Sel<T>::yN(P);
   T* t = Sel<T>::tN(P);
   // kinds: "c first" (P2, or P1 transposed) and "phi first" (P1, or P2 transposed)
   const bool c_first = (kind == DGNP_PC_P2) != transpose;
+  // the coupling applies read z with the other part masked out (counted as zero)
+  const unsigned phi_only = 1u, conc_only = ~1u;
   if (c_first) {
     ilu_solve<T>(c, P, transpose, r + Nf, z + Nf, s);
-    vfill<T>(u, T(0), Nf, s);
-    vcopy<T>(z + Nf, u + Nf, (c.m - 1) * Nf, s);
-    jac_apply(c, u, y, f32, transpose, s);
-    vcopy<T>(r, t, Nf, s);
-    vaxpy<T>(T(-1), y, t, Nf, s);
+    jac_apply(c, z, y, f32, transpose, s, conc_only);
+    vsub<T>(r, y, t, Nf, s);
     ScopeTimer tm(c, f32 ? "vcycle_f32" : "vcycle", s);
     mg.vcycle(0, t, z);
   } else {
@@ -577,11 +579,8 @@ static void apply_t(dgnp_ctx& c, const T* r, T* z, bool transpose, int kind, hip
       ScopeTimer tm(c, f32 ? "vcycle_f32" : "vcycle", s);
       mg.vcycle(0, r, z);
     }
-    vfill<T>(u + Nf, T(0), (c.m - 1) * Nf, s);
-    vcopy<T>(z, u, Nf, s);
-    jac_apply(c, u, y, f32, transpose, s);
-    vcopy<T>(r + Nf, t + Nf, (c.m - 1) * Nf, s);
-    vaxpy<T>(T(-1), y + Nf, t + Nf, (c.m - 1) * Nf, s);
+    jac_apply(c, z, y, f32, transpose, s, phi_only);
+    vsub<T>(r + Nf, y + Nf, t + Nf, (c.m - 1) * Nf, s);
     ilu_solve<T>(c, P, transpose, t + Nf, z + Nf, s);
   }
 }

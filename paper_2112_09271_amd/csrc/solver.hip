@@ -33,13 +33,15 @@ void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assem
   DGNP_HIP(hipStreamSynchronize(s));
 }
 
-void jac_apply(dgnp_ctx& c, const void* v, void* y, bool f32, bool transpose, hipStream_t s) {
+void jac_apply(dgnp_ctx& c, const void* v, void* y, bool f32, bool transpose, hipStream_t s, unsigned vmask) {
   DGNP_REQUIRE(c.has_state, DGNP_E_STATE, "jacobian_apply before set_state");
   DGNP_REQUIRE(!f32 || c.has_state32, DGNP_E_STATE, "float apply needs set_state with DGNP_F32");
   const void* xs = f32 ? static_cast<const void*>(c.d_x32.p) : static_cast<const void*>(c.d_x.p);
   static const char* names[2][2] = {{"jac_apply", "jac_apply_f32"}, {"jacT_apply", "jacT_apply_f32"}};
   ScopeTimer tm(c, names[transpose ? 1 : 0][f32 ? 1 : 0], s);
-  launch_dg(c.dim, c.p, c.m, f32, transpose ? M_JACT : M_JAC, c.kargs(), xs, v, y, nullptr, s);
+  KArgs A = c.kargs();
+  A.vin_mask = vmask;
+  launch_dg(c.dim, c.p, c.m, f32, transpose ? M_JACT : M_JAC, A, xs, v, y, nullptr, s);
 }
 
 dgnp_solve_opts default_solve_opts() {
