@@ -83,6 +83,19 @@ void vaxpby(T a, const T* x, T b, T* y, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for(n)), dim3(VB), 0, s, a, x, b, y, n);
 }
+// y = a x and y32 = float(a x)
+__global__ void k_scale_dual(double a, const double* __restrict__ x, double* __restrict__ y, float* __restrict__ y32,
+                             int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
+    const double v = a * x[i];
+    y[i] = v;
+    y32[i] = float(v);
+  }
+}
+void vscale_dual(double a, const double* x, double* y, float* y32, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_scale_dual, dim3(grid_for(n)), dim3(VB), 0, s, a, x, y, y32, n);
+}
 template <typename T>
 void vsub(const T* x, const T* y, T* z, int64_t n, hipStream_t s) {
   if (n <= 0) return;
@@ -165,6 +178,39 @@ static unsigned red_grid(int64_t n) {
   if (g < 1) g = 1;
   if (g > RED_BLOCKS) g = RED_BLOCKS;
   return unsigned(g);
+}
+
+// w read in single precision (the Jacobian apply's result); the blocks of the
+// first vector also store it widened to double in w64
+__global__ void k_dots_partial_f(const double* __restrict__ V, int64_t ldv, const float* __restrict__ w,
+                                 double* __restrict__ w64, int64_t n, double* __restrict__ partial) {
+  __shared__ double sh[VB];
+  const int j = blockIdx.y;
+  const double* v = V + j * ldv;
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
+    const double wi = double(w[i]);
+    if (j == 0) w64[i] = wi;
+    acc += v[i] * wi;
+  }
+  double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[int64_t(j) * RED_BLOCKS + blockIdx.x] = s;
+}
+
+void vdots_into(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* out, double* scratch,
+                hipStream_t s) {
+  if (k <= 0) return;
+  unsigned g = red_grid(n);
+  hipLaunchKernelGGL(k_dots_partial, dim3(g, unsigned(k)), dim3(VB), 0, s, V, ldv, w, n, scratch);
+  hipLaunchKernelGGL(k_dots_final, dim3(unsigned(k)), dim3(VB), 0, s, scratch, int(g), out);
+}
+
+void vdots_into_f(const double* V, int64_t ldv, int k, const float* w, double* w64, int64_t n, double* out,
+                  double* scratch, hipStream_t s) {
+  if (k <= 0) return;
+  unsigned g = red_grid(n);
+  hipLaunchKernelGGL(k_dots_partial_f, dim3(g, unsigned(k)), dim3(VB), 0, s, V, ldv, w, w64, n, scratch);
+  hipLaunchKernelGGL(k_dots_final, dim3(unsigned(k)), dim3(VB), 0, s, scratch, int(g), out);
 }
 
 void vdots(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* out_dev,

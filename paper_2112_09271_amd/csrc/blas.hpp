@@ -15,6 +15,14 @@ template <typename T> void vsub(const T* x, const T* y, T* z, int64_t n, hipStre
 // out[j] = <V_j, w> for j < k, V column-major [k][n] (double accumulation)
 void vdots(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* out_dev,
            hipStream_t s);
+// the same with the results in out[0..k) and the block partials in scratch
+// (k * reduce-blocks entries); the _f variant reads w in single precision and
+// also stores it widened to double in w64
+void vdots_into(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* out, double* scratch,
+                hipStream_t s);
+void vdots_into_f(const double* V, int64_t ldv, int k, const float* w, double* w64, int64_t n, double* out,
+                  double* scratch, hipStream_t s);
+void vscale_dual(double a, const double* x, double* y, float* y32, int64_t n, hipStream_t s);  // y = a x, y32 = (float) y
 // w -= sum_j h[j] V_j
 void vmaxpy(const double* V, int64_t ldv, int k, const double* h_dev, double* w, int64_t n,
             hipStream_t s);

@@ -191,7 +191,10 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
       break;
     }
     if (out.its >= maxit) break;
-    vaxpby<double>(1.0 / beta, K.r.p, 0.0, K.V.p, N, s);
+    if (f32)
+      vscale_dual(1.0 / beta, K.r.p, K.V.p, K.v32.p, N, s);  // the basis vector and its single copy
+    else
+      vaxpby<double>(1.0 / beta, K.r.p, 0.0, K.V.p, N, s);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int j = 0;
@@ -199,29 +202,29 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
     for (; j < restart && out.its < maxit; ++j) {
       double* vj = K.V.p + int64_t(j) * N;
       double* w = K.w.p;
+      // classical Gram-Schmidt, twice; coefficients stay on the device until one copy
+      double* h1 = K.hd.p + reduce_scratch_size();
+      double* h2 = h1 + 64;
+      double* ww = h2 + 64;
+      double* part = K.hd.p;  // block partials of the reductions
       if (f32) {
-        cvt_d2f(vj, K.v32.p, N, s);
+        // K.v32 holds the single copy of v_j (written with the basis vector)
         pc_then_jac(c, K, true, transpose, pc_kind, s);
         vcopy<float>(K.zt32.p, K.Z32.p + int64_t(j) * N, N, s);
-        cvt_f2d(K.w32.p, w, N, s);
       } else {
         vcopy<double>(vj, K.vt.p, N, s);
         pc_then_jac(c, K, false, transpose, pc_kind, s);
         vcopy<double>(K.zt.p, K.Z.p + int64_t(j) * N, N, s);
       }
-      // classical Gram-Schmidt, twice; coefficients stay on the device until one copy
-      double* h1 = K.hd.p + reduce_scratch_size();
-      double* h2 = h1 + 64;
-      double* ww = h2 + 64;
       ScopeTimer tm(c, "cgs2", s);
-      vdots(K.V.p, N, j + 1, w, N, K.hd.p, s);
-      vcopy<double>(K.hd.p, h1, j + 1, s);
+      if (f32)
+        vdots_into_f(K.V.p, N, j + 1, K.w32.p, w, N, h1, part, s);  // also widens w to double
+      else
+        vdots_into(K.V.p, N, j + 1, w, N, h1, part, s);
       vmaxpy(K.V.p, N, j + 1, h1, w, N, s);
-      vdots(K.V.p, N, j + 1, w, N, K.hd.p, s);
-      vcopy<double>(K.hd.p, h2, j + 1, s);
+      vdots_into(K.V.p, N, j + 1, w, N, h2, part, s);
       vmaxpy(K.V.p, N, j + 1, h2, w, N, s);
-      vdots(w, 0, 1, w, N, K.hd.p, s);
-      vcopy<double>(K.hd.p, ww, 1, s);
+      vdots_into(w, 0, 1, w, N, ww, part, s);
       DGNP_HIP(hipMemcpyAsync(hbuf.data(), h1, sizeof(double) * size_t(64 + 64 + 1), hipMemcpyDeviceToHost, s));
       DGNP_HIP(hipStreamSynchronize(s));
       ++out.its;
@@ -230,7 +233,12 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
       const double hn = std::sqrt(std::max(hbuf[128], 0.0));
       col[j + 1] = hn;
       if (!std::isfinite(hn)) throw Error(DGNP_E_NONFINITE, "non-finite Arnoldi vector");
-      if (hn > 0.0) vaxpby<double>(1.0 / hn, w, 0.0, K.V.p + int64_t(j + 1) * N, N, s);
+      if (hn > 0.0) {
+        if (f32)
+          vscale_dual(1.0 / hn, w, K.V.p + int64_t(j + 1) * N, K.v32.p, N, s);
+        else
+          vaxpby<double>(1.0 / hn, w, 0.0, K.V.p + int64_t(j + 1) * N, N, s);
+      }
       for (int i = 0; i < j; ++i) {
         const double t = cs[size_t(i)] * col[i] + sn[size_t(i)] * col[i + 1];
         col[i + 1] = -sn[size_t(i)] * col[i] + cs[size_t(i)] * col[i + 1];
