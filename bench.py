@@ -27,7 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
-PEAK_FP32_TFLOPS = 157.3       # vector FP32
+PEAK_FP32_TFLOPS = 157.3       # vector FP32 (published; counts packed FP32 FMAs)
+PEAK_FP32_UNPACKED_TFLOPS = 78.6  # 256 CUs x 64 lanes x 2 flops x 2.4 GHz, packed FP32 disabled in this build
 PEAK_FP64_TFLOPS = 78.6        # vector FP64
 METRIC = "Newton-GMRES time-to-1e-8 (FP64 vs mixed); Jacobian-apply HBM GB/s"
 
@@ -50,18 +51,40 @@ def log(msg):
 
 
 # ---- algorithmic byte and flop counts -------------------------------------------
-def ilu_sweep_bytes(cfg, word):
-    """Algorithmic HBM bytes of one forward BILU(0) sweep over all concentration
-    blocks: every element reads its D^-1 block and the scaled coupling block of
-    each lower neighbour, its right-hand side and the neighbours' solution
-    values, and writes its own solution."""
+def _couplings(cfg):
+    """(elements, block size, lower-neighbour couplings) of the element graph."""
     import numpy as np
     n = np.array(cfg.n[: cfg.dim])
     E = int(np.prod(n))
     nb = (cfg.p + 1) ** cfg.dim
-    n_low = sum(E // n[a] * (n[a] - 1) for a in range(cfg.dim))  # lower-neighbour couplings
-    per_field = ((E + n_low) * nb * nb + (2 * E + n_low) * nb) * word
-    return float((cfg.m - 1) * per_field), cfg.n[0] + cfg.n[1] + (cfg.n[2] if cfg.dim == 3 else 1) - (cfg.dim - 1)
+    n_low = int(sum(E // n[a] * (n[a] - 1) for a in range(cfg.dim)))
+    return E, nb, n_low
+
+
+def ilu_sweep_bytes(cfg, word, backward=False):
+    """Algorithmic HBM bytes of one BILU(0) sweep over all concentration blocks
+    (one launch of the dataflow sweep): forward, every element reads its D^-1
+    block, the scaled coupling block of each lower neighbour, its right-hand
+    side and the lower neighbours' solution values, and writes its solution;
+    backward, the upper coupling blocks, the forward result and the upper
+    neighbours' values."""
+    E, nb, n_low = _couplings(cfg)
+    blocks = n_low if backward else E + n_low
+    per_field = (blocks * nb * nb + (2 * E + n_low) * nb) * word
+    return float((cfg.m - 1) * per_field)
+
+
+def cheb_blk_bytes(cfg, word):
+    """Algorithmic HBM bytes per launch of the fused Chebyshev step on the
+    element-block level, averaged over the four launches of one V-cycle: the
+    first (zero initial guess) reads D^-1 and the right-hand side and writes
+    x; the other three read every block of the potential block row (diagonal
+    and couplings) plus D^-1 and their vectors once (14 vectors of N_f values
+    over the four launches)."""
+    E, nb, n_low = _couplings(cfg)
+    blocks = E * nb * nb + 3 * (2 * E + 2 * n_low) * nb * nb
+    vectors = 14 * E * nb
+    return float((blocks + vectors) * word) / 4.0
 
 
 def japply_bytes(N, word):
@@ -168,6 +191,8 @@ def apply_bandwidth(name, reps=20):
         out[tag] = {"us_per_apply": 1e6 * sec, "GBps": gbs, "hbm_frac": gbs / PEAK_HBM_GBS,
                     "contraction_TFLOPs": tfl,
                     "alu_frac": tfl / (PEAK_FP32_TFLOPS if word == 4 else PEAK_FP64_TFLOPS)}
+        if word == 4:  # without packed FP32 instructions one lane retires one FP32 FMA per cycle
+            out[tag]["alu_frac_unpacked_issue"] = tfl / PEAK_FP32_UNPACKED_TFLOPS
         log(f"[bench] J apply {tag} on {cfg.name}: {1e6 * sec:.1f} us, {gbs:.0f} GB/s, {tfl:.2f} TFLOP/s")
     prob.close()
     return out
@@ -220,21 +245,37 @@ def main():
     solve(DGNP_F32)
     kern = prob.timers()
     prob.profile(False)
-    ilu_regions = {k: v for k, v in kern.items() if k.startswith("ilu_fwd") or k.startswith("ilu_bwd")}
-    dominant = max(kern.items(), key=lambda kv: kv[1][0])
-    ilu_bytes, ilu_levels = ilu_sweep_bytes(cfg, 4)
-    fwd = kern.get("ilu_fwd_f32", (0.0, 1))
-    per_launch_bytes = ilu_bytes / ilu_levels
-    avg = fwd[0] / fwd[1]
+    # roofline of the dominant kernel: the kernel family with the largest
+    # event-timed total among those with an algorithmic byte model
+    models = {
+        "cheb_blk_f32": (cheb_blk_bytes(cfg, 4),
+                         "k_cheb_blk<float> (fused Chebyshev step of the potential smoother on the element blocks)"),
+        "ilu_fwd_f32": (ilu_sweep_bytes(cfg, 4),
+                        "k_ilu_dfp<fwd> (dataflow BILU(0) forward sweep, both concentration blocks)"),
+        "ilu_bwd_f32": (ilu_sweep_bytes(cfg, 4, backward=True),
+                        "k_ilu_dfp<bwd> (dataflow BILU(0) backward sweep, both concentration blocks)"),
+        "jac_apply_f32": (float(japply_bytes(prob.N, 4)), "k_dg<JAC, float> (Jacobian apply)"),
+    }
+    present = {k: v for k, v in kern.items() if k in models}
+    dom = max(present.items(), key=lambda kv: kv[1][0])[0]
+    tot, launches = kern[dom]
+    avg = tot / launches
+    per_launch_bytes, kname = models[dom]
     achieved = per_launch_bytes / avg / 1e9
-    roofline = {"kernel": "k_ilu_fwd<float> (level-scheduled BILU(0) forward solve, both concentration "
-                          "blocks per launch)",
-                "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "avg_launch_us": 1e6 * avg, "launches": fwd[1],
+    keys = {"cheb_blk_f32": "k_cheb_blk_f32_cfg2", "ilu_fwd_f32": "k_ilu_dfp_fwd_cfg2",
+            "ilu_bwd_f32": "k_ilu_dfp_bwd_cfg2", "jac_apply_f32": "k_dg_jac_f32_cfg2"}
+    srcs = ("kernels_dg.hip", "dg_device.hpp", "pointwise.hpp") if dom == "jac_apply_f32" else ("kernels_block.hip",)
+    roofline = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "avg_launch_us": 1e6 * avg, "launches": launches,
                 "bytes_per_launch": per_launch_bytes,
-                "traffic": measured_traffic("k_ilu_fwd_f32_cfg2", source_hash("kernels_block.hip"))}
-    log(f"[bench] dominant region {dominant[0]}: {dominant[1][0]:.3f}s in {dominant[1][1]} launches; "
-        f"ILU forward {1e6 * avg:.2f} us/launch, {achieved:.0f} GB/s")
+                "traffic": measured_traffic(keys[dom], source_hash(*srcs))}
+    log(f"[bench] dominant kernel {dom}: {tot:.3f}s in {launches} launches, {1e6 * avg:.2f} us/launch, "
+        f"{achieved:.0f} GB/s")
+    others = {}
+    for k in models:
+        if k in kern and k != dom:
+            t, n_ = kern[k]
+            others[k] = {"avg_launch_us": 1e6 * t / n_, "GBps": models[k][0] / (t / n_) / 1e9}
 
     out = {
         "metric": METRIC,
@@ -253,6 +294,7 @@ def main():
                    "ions": cfg.m, "dofs": prob.N, "newton_rtol": cfg.newton_tol,
                    "newton_its": st32.newton_its, "fgmres_its": st32.lin_its_total},
         "roofline": roofline,
+        "other_kernels": others,
         "kernel_seconds_per_solve": {k: round(v[0], 6) for k, v in kern.items()},
     }
     if not args.no_extra:

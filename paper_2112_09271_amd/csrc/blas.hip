@@ -8,7 +8,9 @@ static constexpr int VB = 256;
 static constexpr int RED_BLOCKS = 1024;
 
 static inline unsigned grid_for(int64_t n) {
-  int64_t g = (n + VB * 4 - 1) / (VB * 4);
+  // one element per thread up to the grid limit: enough waves in flight to
+  // cover memory latency on vectors of a few hundred thousand entries
+  int64_t g = (n + VB - 1) / VB;
   if (g < 1) g = 1;
   if (g > 65535) g = 65535;
   return unsigned(g);
@@ -155,10 +157,15 @@ __global__ void k_dots_partial(const double* __restrict__ V, int64_t ldv, const 
   __shared__ double sh[VB];
   const int j = blockIdx.y;
   const double* v = V + j * ldv;
-  double acc = 0.0;
-  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB)
-    acc += v[i] * w[i];
-  double s = block_sum(acc, sh);
+  double a0 = 0.0, a1 = 0.0;
+  const int64_t st = int64_t(gridDim.x) * VB;
+  int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x;
+  for (; i + st < n; i += 2 * st) {
+    a0 += v[i] * w[i];
+    a1 += v[i + st] * w[i + st];
+  }
+  if (i < n) a0 += v[i] * w[i];
+  double s = block_sum(a0 + a1, sh);
   if (threadIdx.x == 0) partial[int64_t(j) * RED_BLOCKS + blockIdx.x] = s;
 }
 
@@ -262,9 +269,17 @@ double vnorm2(const float* x, int64_t n, double* scratch_dev, hipStream_t s) {
 __global__ void k_maxpy(const double* __restrict__ V, int64_t ldv, int k, const double* __restrict__ h,
                         double* __restrict__ w, int64_t n) {
   for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
-    double acc = w[i];
-    for (int j = 0; j < k; ++j) acc -= h[j] * V[j * ldv + i];
-    w[i] = acc;
+    // four independent partial sums keep four loads in flight per thread
+    double a0 = w[i], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int j = 0;
+    for (; j + 4 <= k; j += 4) {
+      a0 -= h[j] * V[j * ldv + i];
+      a1 -= h[j + 1] * V[(j + 1) * ldv + i];
+      a2 -= h[j + 2] * V[(j + 2) * ldv + i];
+      a3 -= h[j + 3] * V[(j + 3) * ldv + i];
+    }
+    for (; j < k; ++j) a0 -= h[j] * V[j * ldv + i];
+    w[i] = (a0 + a1) + (a2 + a3);
   }
 }
 
@@ -278,9 +293,16 @@ template <typename T>
 __global__ void k_combine(const T* __restrict__ Z, int64_t ldz, int k, const double* __restrict__ h,
                           double* __restrict__ y, int64_t n) {
   for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
-    double acc = y[i];
-    for (int j = 0; j < k; ++j) acc += h[j] * double(Z[j * ldz + i]);
-    y[i] = acc;
+    double a0 = y[i], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int j = 0;
+    for (; j + 4 <= k; j += 4) {
+      a0 += h[j] * double(Z[j * ldz + i]);
+      a1 += h[j + 1] * double(Z[(j + 1) * ldz + i]);
+      a2 += h[j + 2] * double(Z[(j + 2) * ldz + i]);
+      a3 += h[j + 3] * double(Z[(j + 3) * ldz + i]);
+    }
+    for (; j < k; ++j) a0 += h[j] * double(Z[j * ldz + i]);
+    y[i] = (a0 + a1) + (a2 + a3);
   }
 }
 

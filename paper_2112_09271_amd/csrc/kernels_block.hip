@@ -1689,18 +1689,50 @@ __global__ void __launch_bounds__(BT) k_cheb_blk(const T* __restrict__ blk, cons
   if (u) {
     for (int idx = tid; idx < NB; idx += BT)
       for (int s = 0; s < NSLOT; ++s) xs[s][idx] = nb[s] >= 0 ? u[int64_t(nb[s]) * NB + idx] : T(0);
-    __syncthreads();
   }
   const T* bi = blk + i * NSLOT * NB * NB;
-  if (row < NB) {
-    T acc = T(0);
-    if (u)
-      for (int s = 0; s < NSLOT; ++s)
-        if (nb[s] >= 0) acc += row_dot4<T, NB>(bi + int64_t(s) * NB * NB, xs[s], row, part);
-    if (part == 0) {
-      const T r = base[i * NB + row] - acc;
-      rs[row] = r;
-      if (r_out) r_out[i * NB + row] = r;
+  constexpr int QL = (NB + 3) / 4;
+  // small blocks: every row part of all blocks is fetched before any product
+  // (loads in flight together); large blocks stream block by block
+  constexpr bool PRE = NSLOT * QL * int(sizeof(T)) <= 256;
+  if constexpr (PRE) {
+    T m[NSLOT][QL];
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s)
+#pragma unroll
+      for (int c = 0; c < QL; ++c) {
+        const int cc = part * QL + c;
+        m[s][c] = (u && row < NB && cc < NB && nb[s] >= 0) ? bi[int64_t(s) * NB * NB + row * NB + cc] : T(0);
+      }
+    if (u) __syncthreads();
+    if (row < NB) {
+      T acc = T(0);
+      if (u) {  // without u the LDS operand is not loaded (and the products vanish)
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s)
+#pragma unroll
+          for (int c = 0; c < QL; ++c) acc += m[s][c] * xs[s][part * QL + c < NB ? part * QL + c : 0];
+        acc += __shfl_xor(acc, 1, 64);
+        acc += __shfl_xor(acc, 2, 64);
+      }
+      if (part == 0) {
+        const T r = base[i * NB + row] - acc;
+        rs[row] = r;
+        if (r_out) r_out[i * NB + row] = r;
+      }
+    }
+  } else {
+    if (u) __syncthreads();
+    if (row < NB) {
+      T acc = T(0);
+      if (u)
+        for (int s = 0; s < NSLOT; ++s)
+          if (nb[s] >= 0) acc += row_dot4<T, NB>(bi + int64_t(s) * NB * NB, xs[s], row, part);
+      if (part == 0) {
+        const T r = base[i * NB + row] - acc;
+        rs[row] = r;
+        if (r_out) r_out[i * NB + row] = r;
+      }
     }
   }
   __syncthreads();

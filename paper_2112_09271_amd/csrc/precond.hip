@@ -450,6 +450,7 @@ struct Mg {
   void step(int l, const T* u, const T* base, const T* dprev, const T* x_in, double c1, double c2, T* r_out,
             T* d_out, T* x_out) {
     if (l == 0) {
+      ScopeTimer tm(c, std::is_same<T, float>::value ? "cheb_blk_f32" : "cheb_blk", s);
       launch_cheb_blk<T>(c.nb, c.dim, c.E, Sel<T>::blk(P), c.d_nbr.p, Sel<T>::dinv(P), u, base, dprev, x_in, T(c1),
                          T(c2), r_out, d_out, x_out, s);
     } else {
