@@ -60,7 +60,7 @@ struct AsmPairs {
 
 template <int DIM, int P, int MF>
 __global__ void __launch_bounds__(BT)
-    k_assemble(KArgs A, const double* __restrict__ xs, double* __restrict__ blk, int nfields) {
+    k_assemble(KArgs A, const double* __restrict__ xs, double* __restrict__ blk, int f0) {
   using S = Sz<DIM, P>;
   using PR = AsmPairs<DIM>;
   constexpr int NN = S::NN, NQ = S::NQ, NB = S::NB, NQV = S::NQV, NQF = S::NQF, NFN = S::NFN;
@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(BT)
 
   const int tid = threadIdx.x;
   const int64_t e = blockIdx.x;
-  const int f = blockIdx.y;
+  const int f = f0 + int(blockIdx.y);
   load_tab<P, double>(tb, tid, BT);
   Phys<double, MF> ph;
   for (int k = 0; k < MF - 1; ++k) {
@@ -415,29 +415,31 @@ __global__ void __launch_bounds__(BT)
     const int idx = tid + k * BT;
     if (idx < NB * NB) out[idx] = acc[k];
   }
-  (void)nfields;
 }
 
 template <int DIM, int P>
-static void assemble_t(int m, const KArgs& A, const double* xs, double* blk, hipStream_t s) {
-  dim3 grid(unsigned(A.E), unsigned(m));
+static void assemble_t(int m, int f0, int nf, const KArgs& A, const double* xs, double* blk, hipStream_t s) {
+  const dim3 grid = dim3(unsigned(A.E), unsigned(nf));
   if (m == 2)
-    hipLaunchKernelGGL((k_assemble<DIM, P, 2>), grid, dim3(BT), 0, s, A, xs, blk, m);
+    hipLaunchKernelGGL((k_assemble<DIM, P, 2>), grid, dim3(BT), 0, s, A, xs, blk, f0);
   else
-    hipLaunchKernelGGL((k_assemble<DIM, P, 3>), grid, dim3(BT), 0, s, A, xs, blk, m);
+    hipLaunchKernelGGL((k_assemble<DIM, P, 3>), grid, dim3(BT), 0, s, A, xs, blk, f0);
   DGNP_HIP(hipGetLastError());
 }
 
-void launch_assemble(int dim, int p, int m, const KArgs& A, const double* xs, double* blk, hipStream_t s) {
+void launch_assemble(int dim, int p, int m, int f0, int nf, const KArgs& A, const double* xs, double* blk,
+                     hipStream_t s) {
   DGNP_REQUIRE(m == 2 || m == 3, DGNP_E_ARG, "number of ions must be 2 or 3");
+  DGNP_REQUIRE(f0 >= 0 && nf >= 0 && f0 + nf <= m, DGNP_E_ARG, "field range out of bounds");
+  if (nf == 0 || A.E == 0) return;
   if (dim == 3) {
-    if (p == 1) return assemble_t<3, 1>(m, A, xs, blk, s);
-    if (p == 2) return assemble_t<3, 2>(m, A, xs, blk, s);
-    if (p == 3) return assemble_t<3, 3>(m, A, xs, blk, s);
+    if (p == 1) return assemble_t<3, 1>(m, f0, nf, A, xs, blk, s);
+    if (p == 2) return assemble_t<3, 2>(m, f0, nf, A, xs, blk, s);
+    if (p == 3) return assemble_t<3, 3>(m, f0, nf, A, xs, blk, s);
   } else {
-    if (p == 1) return assemble_t<2, 1>(m, A, xs, blk, s);
-    if (p == 2) return assemble_t<2, 2>(m, A, xs, blk, s);
-    if (p == 3) return assemble_t<2, 3>(m, A, xs, blk, s);
+    if (p == 1) return assemble_t<2, 1>(m, f0, nf, A, xs, blk, s);
+    if (p == 2) return assemble_t<2, 2>(m, f0, nf, A, xs, blk, s);
+    if (p == 3) return assemble_t<2, 3>(m, f0, nf, A, xs, blk, s);
   }
   throw Error(DGNP_E_ARG, "unsupported dimension / order");
 }

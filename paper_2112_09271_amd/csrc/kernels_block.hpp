@@ -6,7 +6,9 @@
 namespace dgnp {
 void upload_ref_tables_block(const RefTables* tabs, int count);
 void upload_gll_nodes(const RefTables* tabs, int count);
-void launch_assemble(int dim, int p, int m, const KArgs& A, const double* xs, double* blk, hipStream_t s);
+// diagonal field blocks of fields f0 .. f0 + nf - 1 (blk holds all m fields)
+void launch_assemble(int dim, int p, int m, int f0, int nf, const KArgs& A, const double* xs, double* blk,
+                     hipStream_t s);
 void launch_block_inverse(int nb, int64_t E, const double* blk, int nslot, double* out, hipStream_t s);
 // BILU(0) of nfields field blocks (block stride fstride): one hyperplane level
 // (D_i^{-1} and the upper blocks), then, after the last level, the lower blocks

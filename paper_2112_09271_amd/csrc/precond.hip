@@ -77,7 +77,12 @@ struct Precond {
   int df_grid[2] = {0, 0};  // double, float
   int df_spin = 1 << 22;
   bool df_on = true;
-  bool ready = false, ready32 = false, assembled = false;
+  // numeric state: potential part (phi block, its inverse blocks, multigrid
+  // hierarchy, lambda_max) and concentration part (BILU(0) factors), in double
+  // and, for the mixed path, single precision
+  bool phi_ok = false, phi32_ok = false, conc_ok = false, conc32_ok = false, assembled = false;
+  bool ready() const { return phi_ok && conc_ok; }
+  bool ready32() const { return phi32_ok && conc32_ok; }
 };
 
 void precond_destroy(Precond* p) { delete p; }
@@ -263,112 +268,125 @@ struct PhaseClock {
   }
 };
 
-void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only) {
+void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, int parts) {
   precond_check(c, false);
   Precond& P = *c.pc;
   PhaseClock clk(s);
   const int64_t per_field = c.E * P.nslot * P.bsz;
+  const bool phi = (parts & PC_PHI) != 0, conc = (parts & PC_CONC) != 0;
   P.blk.alloc(size_t(c.m * per_field));
   {
     ScopeTimer tm(c, "assemble", s);
-    launch_assemble(c.dim, c.p, c.m, c.kargs(), c.d_x.p, P.blk.p, s);
+    const int f0 = phi ? 0 : 1, f1 = conc ? c.m : 1;
+    launch_assemble(c.dim, c.p, c.m, f0, f1 - f0, c.kargs(), c.d_x.p, P.blk.p, s);
   }
   clk.mark("assemble");
+  if (phi) P.phi_ok = P.phi32_ok = false;
+  if (conc) P.conc_ok = P.conc32_ok = false;
   if (assemble_only) {
     DGNP_HIP(hipStreamSynchronize(s));
-    P.ready = false;
     P.assembled = true;
     return;
   }
-  // potential block: element-diagonal inverses (block-Jacobi smoother)
-  P.dinv_phi.alloc(size_t(c.E * P.bsz));
-  {
-    ScopeTimer tm(c, "block_inverse", s);
-    launch_block_inverse(c.nb, c.E, P.blk.p, P.nslot, P.dinv_phi.p, s);
-  }
-  clk.mark("block inverse");
-  // concentration blocks: BILU(0) level by level
-  for (size_t l = 0; l + 1 < P.lev_ptr.size(); ++l) {
-    ScopeTimer tm(c, "ilu_factor", s);
-    launch_ilu_factor(c.nb, c.dim, c.m - 1, per_field, P.blk.p + per_field, c.d_nbr.p, P.lev_elems.p,
-                      P.lev_ptr[l], P.lev_ptr[l + 1] - P.lev_ptr[l], s);
-  }
-  {
-    ScopeTimer tm(c, "ilu_factor", s);
-    launch_ilu_scale_lower(c.nb, c.dim, c.m - 1, per_field, P.blk.p + per_field, c.d_nbr.p, c.E, s);
-  }
-  clk.mark("ilu factor");
-  // Galerkin projection of A_phiphi onto Q1 vertices, then host SA setup
-  const int NV = 1 << c.dim;
-  P.gal.alloc(size_t(c.E) * P.nslot * NV * NV);
-  launch_q1_galerkin(c.dim, c.p, c.E, P.blk.p, P.gal.p, s);
-  P.vst.alloc(size_t(P.nvert) * (c.dim == 3 ? 27 : 9));
-  launch_vertex_stencil(c.dim, P.gal.p, c.d_nbr.p, c.n, P.nvert, P.vst.p, s);
-  std::vector<double> st(P.vst.n);
-  DGNP_HIP(hipMemcpyAsync(st.data(), P.vst.p, st.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-  DGNP_HIP(hipStreamSynchronize(s));
-  clk.mark("galerkin + stencil");
-  Csr A1 = vertex_matrix(c, P, st);
-  clk.mark("vertex matrix");
-  AmgHierarchy H = sa_setup(A1, 12, 256, 0.0);
-  clk.mark("sa setup");
-  if (trace_setup()) {
-    fprintf(stderr, "[setup] hierarchy: DG %lld", (long long)c.Nf);
-    for (auto& A : H.A) fprintf(stderr, " -> %d (nnz %zu)", A.n, A.v.size());
-    fprintf(stderr, "\n");
-  }
-  P.mg.clear();
-  P.mg.resize(H.A.size());
-  for (size_t l = 0; l < H.A.size(); ++l) {
-    MgLevel& L = P.mg[l];
-    L.n = H.A[l].n;
-    upload_csr(L.A, H.A[l], s);
-    if (l + 1 < H.A.size()) {
-      upload_csr(L.P, H.P[l], s);
-      upload_csr(L.R, H.R[l], s);
+  if (f32) P.blk32.alloc(P.blk.n);
+  if (phi) {
+    // potential block: element-diagonal inverses (block-Jacobi smoother)
+    P.dinv_phi.alloc(size_t(c.E * P.bsz));
+    {
+      ScopeTimer tm(c, "block_inverse", s);
+      launch_block_inverse(c.nb, c.E, P.blk.p, P.nslot, P.dinv_phi.p, s);
     }
-    L.dinv.upload(H.dinv[l], s);
-    L.lmax = H.lmax[l];
-  }
-  P.nc = H.A.back().n;
-  P.cinv.upload(H.coarse_inv, s);
-  clk.mark("upload hierarchy");
-  P.wd.clear();
-  ensure_work(c, P);
-  clk.mark("work vectors");
-  P.ready = true;
-  P.assembled = true;
-  P.ready32 = false;
-  if (f32) {
-    P.blk32.alloc(P.blk.n);
-    cvt_d2f(P.blk.p, P.blk32.p, int64_t(P.blk.n), s);
-    P.dinv_phi32.alloc(P.dinv_phi.n);
-    cvt_d2f(P.dinv_phi.p, P.dinv_phi32.p, int64_t(P.dinv_phi.n), s);
+    clk.mark("block inverse");
+    // Galerkin projection of A_phiphi onto Q1 vertices, then host SA setup
+    const int NV = 1 << c.dim;
+    P.gal.alloc(size_t(c.E) * P.nslot * NV * NV);
+    launch_q1_galerkin(c.dim, c.p, c.E, P.blk.p, P.gal.p, s);
+    P.vst.alloc(size_t(P.nvert) * (c.dim == 3 ? 27 : 9));
+    launch_vertex_stencil(c.dim, P.gal.p, c.d_nbr.p, c.n, P.nvert, P.vst.p, s);
+    std::vector<double> st(P.vst.n);
+    DGNP_HIP(hipMemcpyAsync(st.data(), P.vst.p, st.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    DGNP_HIP(hipStreamSynchronize(s));
+    clk.mark("galerkin + stencil");
+    Csr A1 = vertex_matrix(c, P, st);
+    clk.mark("vertex matrix");
+    AmgHierarchy H = sa_setup(A1, 12, 256, 0.0);
+    clk.mark("sa setup");
+    if (trace_setup()) {
+      fprintf(stderr, "[setup] hierarchy: DG %lld", (long long)c.Nf);
+      for (auto& A : H.A) fprintf(stderr, " -> %d (nnz %zu)", A.n, A.v.size());
+      fprintf(stderr, "\n");
+    }
+    P.mg.clear();
+    P.mg.resize(H.A.size());
     for (size_t l = 0; l < H.A.size(); ++l) {
       MgLevel& L = P.mg[l];
-      upload_csr(L.A32, H.A[l], s);
+      L.n = H.A[l].n;
+      upload_csr(L.A, H.A[l], s);
       if (l + 1 < H.A.size()) {
-        upload_csr(L.P32, H.P[l], s);
-        upload_csr(L.R32, H.R[l], s);
+        upload_csr(L.P, H.P[l], s);
+        upload_csr(L.R, H.R[l], s);
       }
-      std::vector<float> di(H.dinv[l].begin(), H.dinv[l].end());
-      L.dinv32.upload(di, s);
+      L.dinv.upload(H.dinv[l], s);
+      L.lmax = H.lmax[l];
     }
-    std::vector<float> ci(H.coarse_inv.begin(), H.coarse_inv.end());
-    P.cinv32.upload(ci, s);
-    ensure_work32(c, P);
-    P.ready32 = true;
-    clk.mark("float copies");
-    P.lmax0 = lmax_level0<float>(c, P, s, P.blk32.p, P.dinv_phi32.p, P.wf[0]->p, P.wf[1]->p);
-  } else {
-    P.lmax0 = lmax_level0<double>(c, P, s, P.blk.p, P.dinv_phi.p, P.wd[0]->p, P.wd[1]->p);
+    P.nc = H.A.back().n;
+    P.cinv.upload(H.coarse_inv, s);
+    clk.mark("upload hierarchy");
+    P.wd.clear();
+    ensure_work(c, P);
+    clk.mark("work vectors");
+    if (f32) {
+      cvt_d2f(P.blk.p, P.blk32.p, per_field, s);
+      P.dinv_phi32.alloc(P.dinv_phi.n);
+      cvt_d2f(P.dinv_phi.p, P.dinv_phi32.p, int64_t(P.dinv_phi.n), s);
+      for (size_t l = 0; l < H.A.size(); ++l) {
+        MgLevel& L = P.mg[l];
+        upload_csr(L.A32, H.A[l], s);
+        if (l + 1 < H.A.size()) {
+          upload_csr(L.P32, H.P[l], s);
+          upload_csr(L.R32, H.R[l], s);
+        }
+        std::vector<float> di(H.dinv[l].begin(), H.dinv[l].end());
+        L.dinv32.upload(di, s);
+      }
+      std::vector<float> ci(H.coarse_inv.begin(), H.coarse_inv.end());
+      P.cinv32.upload(ci, s);
+      ensure_work32(c, P);
+      clk.mark("float copies (phi)");
+      P.lmax0 = lmax_level0<float>(c, P, s, P.blk32.p, P.dinv_phi32.p, P.wf[0]->p, P.wf[1]->p);
+    } else {
+      P.lmax0 = lmax_level0<double>(c, P, s, P.blk.p, P.dinv_phi.p, P.wd[0]->p, P.wd[1]->p);
+    }
+    clk.mark("lmax level 0");
+    P.phi_ok = true;
+    P.phi32_ok = f32;
   }
-  clk.mark("lmax level 0");
+  if (conc) {
+    // concentration blocks: BILU(0) level by level
+    for (size_t l = 0; l + 1 < P.lev_ptr.size(); ++l) {
+      ScopeTimer tm(c, "ilu_factor", s);
+      launch_ilu_factor(c.nb, c.dim, c.m - 1, per_field, P.blk.p + per_field, c.d_nbr.p, P.lev_elems.p,
+                        P.lev_ptr[l], P.lev_ptr[l + 1] - P.lev_ptr[l], s);
+    }
+    {
+      ScopeTimer tm(c, "ilu_factor", s);
+      launch_ilu_scale_lower(c.nb, c.dim, c.m - 1, per_field, P.blk.p + per_field, c.d_nbr.p, c.E, s);
+    }
+    clk.mark("ilu factor");
+    if (f32) {
+      cvt_d2f(P.blk.p + per_field, P.blk32.p + per_field, (c.m - 1) * per_field, s);
+      if (P.wf.empty() || !P.vN32.p) ensure_work32(c, P);
+      clk.mark("float copies (conc)");
+    }
+    P.conc_ok = true;
+    P.conc32_ok = f32;
+  }
+  P.assembled = true;
   DGNP_HIP(hipStreamSynchronize(s));
 }
 
 void precond_invalidate(dgnp_ctx& c) {
-  if (c.pc) c.pc->ready = c.pc->ready32 = c.pc->assembled = false;
+  if (c.pc) c.pc->phi_ok = c.pc->phi32_ok = c.pc->conc_ok = c.pc->conc32_ok = c.pc->assembled = false;
 }
 
 void get_block(dgnp_ctx& c, int field, int64_t elem, int slot, double* out) {
@@ -587,9 +605,9 @@ static void apply_t(dgnp_ctx& c, const T* r, T* z, bool transpose, int kind, hip
 }
 
 void precond_apply(dgnp_ctx& c, const void* r, void* z, bool f32, bool transpose, int kind, hipStream_t s) {
-  DGNP_REQUIRE(c.pc && c.pc->ready, DGNP_E_STATE, "precond_apply before set_state");
+  DGNP_REQUIRE(c.pc && c.pc->ready(), DGNP_E_STATE, "precond_apply before set_state");
   if (f32) {
-    DGNP_REQUIRE(c.pc->ready32, DGNP_E_STATE, "float preconditioner needs set_state with DGNP_F32");
+    DGNP_REQUIRE(c.pc->ready32(), DGNP_E_STATE, "float preconditioner needs set_state with DGNP_F32");
     apply_t<float>(c, static_cast<const float*>(r), static_cast<float*>(z), transpose, kind, s);
   } else {
     apply_t<double>(c, static_cast<const double*>(r), static_cast<double*>(z), transpose, kind, s);
@@ -598,12 +616,23 @@ void precond_apply(dgnp_ctx& c, const void* r, void* z, bool f32, bool transpose
 
 // y = A_phiphi x with the assembled potential block
 void phi_block_apply(dgnp_ctx& c, const double* x, double* y, hipStream_t s) {
+  DGNP_REQUIRE(c.pc && c.pc->phi_ok, DGNP_E_STATE, "potential block not set up");
   launch_bspmv<double>(c.nb, c.dim, c.E, c.pc->blk.p, c.d_nbr.p, x, nullptr, 1.0, 0.0, y, s);
+}
+void phi_block_apply(dgnp_ctx& c, const float* x, float* y, hipStream_t s) {
+  DGNP_REQUIRE(c.pc && c.pc->phi32_ok, DGNP_E_STATE, "single-precision potential block not set up");
+  launch_bspmv<float>(c.nb, c.dim, c.E, c.pc->blk32.p, c.d_nbr.p, x, nullptr, 1.0f, 0.0f, y, s);
 }
 
 // potential-block V-cycle alone (used for the initial potential solve)
 void vcycle_phi(dgnp_ctx& c, const double* b, double* x, hipStream_t s) {
+  DGNP_REQUIRE(c.pc && c.pc->phi_ok, DGNP_E_STATE, "potential hierarchy not set up");
   Mg<double> mg{c, *c.pc, s};
+  mg.vcycle(0, b, x);
+}
+void vcycle_phi(dgnp_ctx& c, const float* b, float* x, hipStream_t s) {
+  DGNP_REQUIRE(c.pc && c.pc->phi32_ok, DGNP_E_STATE, "single-precision potential hierarchy not set up");
+  Mg<float> mg{c, *c.pc, s};
   mg.vcycle(0, b, x);
 }
 

@@ -15,7 +15,8 @@ namespace dgnp {
 using clk = std::chrono::steady_clock;
 static double since(clk::time_point t0) { return std::chrono::duration<double>(clk::now() - t0).count(); }
 
-void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assemble_only, bool apply_only) {
+void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assemble_only, bool apply_only,
+               int parts) {
   ++c.state_epoch;
   c.d_x.alloc(size_t(c.N));
   if (x != c.d_x.p) vcopy<double>(x, c.d_x.p, c.N, s);
@@ -29,7 +30,7 @@ void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assem
   if (apply_only)
     precond_invalidate(c);
   else
-    precond_numeric(c, prec == DGNP_F32, s, assemble_only);
+    precond_numeric(c, prec == DGNP_F32, s, assemble_only, parts);
   DGNP_HIP(hipStreamSynchronize(s));
 }
 
@@ -285,7 +286,7 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
 // at those concentrations, R_phi(c0, phi) = 0, which is linear in phi; solved
 // with conjugate gradients preconditioned by the potential V-cycle.
 // ---------------------------------------------------------------------------
-static void initial_guess(dgnp_ctx& c, double* x, hipStream_t s, int verbose) {
+static void initial_guess(dgnp_ctx& c, double* x, hipStream_t s, int prec, int verbose) {
   const int64_t Nf = c.Nf;
   vfill<double>(x, 0.0, Nf, s);
   for (int k = 1; k < c.m; ++k) {
@@ -297,13 +298,40 @@ static void initial_guess(dgnp_ctx& c, double* x, hipStream_t s, int verbose) {
     }
     vfill<double>(x + k * Nf, mean, Nf, s);
   }
-  set_state(c, x, DGNP_F64, s);
+  // only the potential part of the preconditioner is needed here; with the
+  // single-precision path the operator and the V-cycle run in single precision
+  // inside the double-precision conjugate gradient iteration
+  const bool f32 = prec == DGNP_F32;
+  set_state(c, x, prec, s, false, false, PC_PHI);
   DevBuf<double> r, z, p, q, phi;
   r.alloc(size_t(c.N));
   z.alloc(size_t(Nf));
   p.alloc(size_t(Nf));
   q.alloc(size_t(Nf));
   phi.alloc(size_t(Nf));
+  DevBuf<float> a32, b32;
+  if (f32) {
+    a32.alloc(size_t(Nf));
+    b32.alloc(size_t(Nf));
+  }
+  auto precond = [&](const double* rin, double* zout) {
+    if (f32) {
+      cvt_d2f(rin, a32.p, Nf, s);
+      vcycle_phi(c, a32.p, b32.p, s);
+      cvt_f2d(b32.p, zout, Nf, s);
+    } else {
+      vcycle_phi(c, rin, zout, s);
+    }
+  };
+  auto matvec = [&](const double* xin, double* yout) {
+    if (f32) {
+      cvt_d2f(xin, a32.p, Nf, s);
+      phi_block_apply(c, a32.p, b32.p, s);
+      cvt_f2d(b32.p, yout, Nf, s);
+    } else {
+      phi_block_apply(c, xin, yout, s);
+    }
+  };
   DevBuf<double> red;
   red.alloc(size_t(reduce_scratch_size()));
   launch_dg(c.dim, c.p, c.m, false, M_RES, c.kargs(), x, nullptr, r.p, nullptr, s);
@@ -311,11 +339,11 @@ static void initial_guess(dgnp_ctx& c, double* x, hipStream_t s, int verbose) {
   const double bn = vnorm2(r.p, Nf, red.p, s);
   vfill<double>(phi.p, 0.0, Nf, s);
   if (bn > 0.0) {
-    vcycle_phi(c, r.p, z.p, s);
+    precond(r.p, z.p);
     vcopy<double>(z.p, p.p, Nf, s);
     double rz = vdot(r.p, z.p, Nf, red.p, s);
     for (int it = 0; it < 500; ++it) {
-      phi_block_apply(c, p.p, q.p, s);
+      matvec(p.p, q.p);
       const double pq = vdot(p.p, q.p, Nf, red.p, s);
       const double alpha = rz / pq;
       vaxpy<double>(alpha, p.p, phi.p, Nf, s);
@@ -323,7 +351,7 @@ static void initial_guess(dgnp_ctx& c, double* x, hipStream_t s, int verbose) {
       const double rn = vnorm2(r.p, Nf, red.p, s);
       if (verbose > 1) fprintf(stderr, "  initial potential CG %d: %.3e\n", it, rn / bn);
       if (rn <= 1e-6 * bn) break;
-      vcycle_phi(c, r.p, z.p, s);
+      precond(r.p, z.p);
       const double rz_new = vdot(r.p, z.p, Nf, red.p, s);
       vaxpby<double>(1.0, z.p, rz_new / rz, p.p, Nf, s);
       rz = rz_new;
@@ -353,10 +381,15 @@ int newton_solve(dgnp_ctx& c, double* x, const dgnp_solve_opts& o, dgnp_solve_st
   DGNP_REQUIRE(o.prec == DGNP_F64 || o.prec == DGNP_F32, DGNP_E_ARG, "prec must be F64 or F32");
   double x0;
   DGNP_HIP(hipMemcpy(&x0, x, sizeof(double), hipMemcpyDeviceToHost));
+  // The potential block depends on the concentrations only; right after the
+  // initial guess (which changes the potential alone) the first linearisation
+  // keeps its potential hierarchy and sets up the concentration part.
+  bool phi_current = false;
   if (std::isnan(x0)) {
     const auto ts = clk::now();
-    initial_guess(c, x, s, o.verbose);
+    initial_guess(c, x, s, o.prec, o.verbose);
     st.t_setup += since(ts);
+    phi_current = true;
   }
   const bool f32 = o.prec == DGNP_F32;
   auto resid = [&](const double* xv, double* rv) {
@@ -378,7 +411,8 @@ int newton_solve(dgnp_ctx& c, double* x, const dgnp_solve_opts& o, dgnp_solve_st
     }
     if (it == o.max_newton) break;
     const auto ts = clk::now();
-    set_state(c, x, o.prec, s);
+    set_state(c, x, o.prec, s, false, false, phi_current ? PC_CONC : PC_ALL);
+    phi_current = false;
     st.t_setup += since(ts);
     vcopy<double>(W.r.p, W.b.p, N, s);
     vscale<double>(-1.0, W.b.p, N, s);

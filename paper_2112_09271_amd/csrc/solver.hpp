@@ -6,7 +6,11 @@
 namespace dgnp {
 
 void precond_symbolic(dgnp_ctx& c);                                   // precond.hip
-void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only = false);  // precond.hip
+// parts of the numeric preconditioner set-up: the potential block with its
+// inverse blocks and multigrid hierarchy, and the concentration BILU(0) factors
+enum { PC_PHI = 1, PC_CONC = 2, PC_ALL = 3 };
+void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only = false,
+                     int parts = PC_ALL);  // precond.hip
 void precond_apply(dgnp_ctx& c, const void* r, void* z, bool f32, bool transpose, int pc_kind,
                    hipStream_t s);                                     // precond.hip
 void get_block(dgnp_ctx& c, int field, int64_t elem, int slot, double* out);
@@ -14,10 +18,12 @@ void precond_invalidate(dgnp_ctx& c);
 // clears a dataflow sweep that hit its wait limit; throws DGNP_E_BREAKDOWN if report (synchronises)
 void precond_check(dgnp_ctx& c, bool report = true);
 void vcycle_phi(dgnp_ctx& c, const double* b, double* x, hipStream_t s);     // precond.hip
+void vcycle_phi(dgnp_ctx& c, const float* b, float* x, hipStream_t s);
 void phi_block_apply(dgnp_ctx& c, const double* x, double* y, hipStream_t s); // precond.hip
+void phi_block_apply(dgnp_ctx& c, const float* x, float* y, hipStream_t s);
 
 void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assemble_only = false,
-               bool apply_only = false);
+               bool apply_only = false, int parts = PC_ALL);
 // vmask: fields of v that are read (the others count as zero)
 void jac_apply(dgnp_ctx& c, const void* v, void* y, bool f32, bool transpose, hipStream_t s,
                unsigned vmask = ~0u);

@@ -132,3 +132,22 @@ def test_dataflow_wait_limit_is_reported(monkeypatch):
     x, st = g2.solve(prec=DGNP_F32)
     assert st.status == 0 and st.res_final <= 1e-8 * st.res0
     print("first solve failed:", failed)
+
+
+@pytest.mark.parametrize("name", ["cfg2t", "cfg3s", "cfg1"])
+def test_potential_block_independent_of_potential(name):
+    """The potential-potential block depends on the concentrations only (the
+    charge equation is linear in the potential), bitwise: the solver keeps the
+    potential hierarchy of the initial guess for the first Newton step."""
+    from paper_2112_09271_amd.dgnp import DGNP_F64, DGNP_STATE_ASSEMBLE_ONLY
+    cfg, _, gp = pair(name, with_oracle=False)
+    x1 = random_state(cfg)
+    x2 = x1.copy()
+    x2[: gp.Nf] = random_vector(cfg, 51)[: gp.Nf]
+    elems = [0, gp.E // 2, gp.E - 1]
+    gp.set_state(x1, prec=DGNP_F64 | DGNP_STATE_ASSEMBLE_ONLY)
+    b1 = [gp.get_block(0, e, s) for e in elems for s in range(2 * cfg.dim + 1)]
+    gp.set_state(x2, prec=DGNP_F64 | DGNP_STATE_ASSEMBLE_ONLY)
+    b2 = [gp.get_block(0, e, s) for e in elems for s in range(2 * cfg.dim + 1)]
+    for a, b in zip(b1, b2):
+        assert np.array_equal(a, b)
