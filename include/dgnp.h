@@ -113,7 +113,7 @@ typedef struct {
   int32_t prec;       /* DGNP_F64, or DGNP_F32 = FP32 apply + preconditioner under
                          FP64 Newton residual, FP64 Arnoldi and FP64 iterative refinement */
   double lin_rtol;    /* outer FGMRES tolerance per Newton step (paper: 1e-3) */
-  int32_t restart;    /* FGMRES restart length, 1..60 */
+  int32_t restart;    /* FGMRES restart length, 1..120 */
   int32_t max_lin_it; /* FGMRES iterations per linear solve */
   int32_t pc_kind;    /* DGNP_PC_P2 or DGNP_PC_P1 */
   int32_t verbose;
@@ -193,7 +193,7 @@ int dgnp_precond_apply(dgnp_ctx *ctx, const void *r, void *z, int32_t prec,
  * entry an initial guess, or all-NaN to request the paper's initial guess
  * (Sec. 4.3: constant concentrations = mean boundary data, potential from
  * the charge equation at those concentrations); on exit the solution.
- * opts may be NULL (defaults: rtol 1e-8, lin_rtol 1e-3, restart 60, P2, FP64).
+ * opts may be NULL (defaults: rtol 1e-8, lin_rtol 1e-3, restart 120, P2, FP64).
  * stats may be NULL.  Synchronises.  DGNP_E_NOCONV if max_newton is reached. */
 int dgnp_solve(dgnp_ctx *ctx, double *x, const dgnp_solve_opts *opts, dgnp_solve_stats *stats);
 

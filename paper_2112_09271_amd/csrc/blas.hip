@@ -178,7 +178,7 @@ __global__ void k_dots_final(const double* __restrict__ partial, int nblk, doubl
   if (threadIdx.x == 0) out[j] = s;
 }
 
-int64_t reduce_scratch_size() { return int64_t(64) * RED_BLOCKS + 64; }
+int64_t reduce_scratch_size() { return int64_t(MAXV) * RED_BLOCKS + MAXV; }
 
 static unsigned red_grid(int64_t n) {
   int64_t g = (n + VB * 8 - 1) / (VB * 8);
@@ -222,9 +222,9 @@ void vdots_into_f(const double* V, int64_t ldv, int k, const float* w, double* w
 
 void vdots(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* out_dev,
            hipStream_t s) {
-  // out_dev must have room for k results followed by the k * RED_BLOCKS partials
+  // out_dev must have room for MAXV results followed by the k * RED_BLOCKS partials
   if (k <= 0) return;
-  double* partial = out_dev + 64;
+  double* partial = out_dev + MAXV;
   unsigned g = red_grid(n);
   hipLaunchKernelGGL(k_dots_partial, dim3(g, unsigned(k)), dim3(VB), 0, s, V, ldv, w, n, partial);
   hipLaunchKernelGGL(k_dots_final, dim3(unsigned(k)), dim3(VB), 0, s, partial, int(g), out_dev);
@@ -256,7 +256,7 @@ __global__ void k_sq_partial(const float* __restrict__ x, int64_t n, double* __r
 }
 
 double vnorm2(const float* x, int64_t n, double* scratch_dev, hipStream_t s) {
-  double* partial = scratch_dev + 64;
+  double* partial = scratch_dev + MAXV;
   unsigned g = red_grid(n);
   hipLaunchKernelGGL(k_sq_partial, dim3(g), dim3(VB), 0, s, x, n, partial);
   hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(VB), 0, s, partial, int(g), scratch_dev);

@@ -4,6 +4,8 @@
 #include "dgnp_impl.hpp"
 
 namespace dgnp {
+// most vectors one reduction call handles (the Krylov basis of the longest restart)
+constexpr int MAXV = 128;
 void cvt_d2f(const double* x, float* y, int64_t n, hipStream_t s);
 void cvt_f2d(const float* x, double* y, int64_t n, hipStream_t s);
 template <typename T> void vfill(T* x, T v, int64_t n, hipStream_t s);

@@ -52,7 +52,7 @@ dgnp_solve_opts default_solve_opts() {
   o.max_newton = 30;
   o.prec = DGNP_F64;
   o.lin_rtol = 1e-3;
-  o.restart = 60;
+  o.restart = 120;
   o.max_lin_it = 600;
   o.pc_kind = DGNP_PC_P2;
   o.verbose = 0;
@@ -135,7 +135,7 @@ static Krylov& krylov(dgnp_ctx& c, int restart, bool f32) {
     K->V.alloc(size_t(restart + 1) * c.N);
     K->w.alloc(size_t(c.N));
     K->r.alloc(size_t(c.N));
-    K->hd.alloc(size_t(reduce_scratch_size()) + 192);
+    K->hd.alloc(size_t(reduce_scratch_size()) + 3 * MAXV + 8);
     K->Z.release();
     K->Z32.release();
     K->restart = restart;
@@ -171,7 +171,7 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
   const int64_t N = c.N;
   LinResult out;
   const size_t rs = static_cast<size_t>(restart);
-  std::vector<double> H((rs + 1) * rs), g(rs + 1), cs(rs), sn(rs), hbuf(129), y(rs);
+  std::vector<double> H((rs + 1) * rs), g(rs + 1), cs(rs), sn(rs), hbuf(2 * MAXV + 1), y(rs);
   bool first = true;
   while (true) {
     // true FP64 residual
@@ -205,8 +205,8 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
       double* w = K.w.p;
       // classical Gram-Schmidt, twice; coefficients stay on the device until one copy
       double* h1 = K.hd.p + reduce_scratch_size();
-      double* h2 = h1 + 64;
-      double* ww = h2 + 64;
+      double* h2 = h1 + MAXV;
+      double* ww = h2 + MAXV;
       double* part = K.hd.p;  // block partials of the reductions
       if (f32) {
         // K.v32 holds the single copy of v_j (written with the basis vector)
@@ -226,12 +226,12 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
       vdots_into(K.V.p, N, j + 1, w, N, h2, part, s);
       vmaxpy(K.V.p, N, j + 1, h2, w, N, s);
       vdots_into(w, 0, 1, w, N, ww, part, s);
-      DGNP_HIP(hipMemcpyAsync(hbuf.data(), h1, sizeof(double) * size_t(64 + 64 + 1), hipMemcpyDeviceToHost, s));
+      DGNP_HIP(hipMemcpyAsync(hbuf.data(), h1, sizeof(double) * size_t(2 * MAXV + 1), hipMemcpyDeviceToHost, s));
       DGNP_HIP(hipStreamSynchronize(s));
       ++out.its;
       double* col = H.data() + size_t(j) * (restart + 1);
-      for (int i = 0; i <= j; ++i) col[i] = hbuf[size_t(i)] + hbuf[size_t(64 + i)];
-      const double hn = std::sqrt(std::max(hbuf[128], 0.0));
+      for (int i = 0; i <= j; ++i) col[i] = hbuf[size_t(i)] + hbuf[size_t(MAXV + i)];
+      const double hn = std::sqrt(std::max(hbuf[2 * MAXV], 0.0));
       col[j + 1] = hn;
       if (!std::isfinite(hn)) throw Error(DGNP_E_NONFINITE, "non-finite Arnoldi vector");
       if (hn > 0.0) {
@@ -268,7 +268,7 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
       for (int l = i + 1; l < k; ++l) acc -= H[size_t(l) * (restart + 1) + i] * y[size_t(l)];
       y[size_t(i)] = acc / H[size_t(i) * (restart + 1) + i];
     }
-    double* yd = K.hd.p + reduce_scratch_size() + 129;
+    double* yd = K.hd.p + reduce_scratch_size() + 2 * MAXV + 1;
     DGNP_HIP(hipMemcpyAsync(yd, y.data(), sizeof(double) * size_t(k), hipMemcpyHostToDevice, s));
     if (f32)
       vcombine<float>(K.Z32.p, N, k, yd, x, N, s);
@@ -377,7 +377,7 @@ int newton_solve(dgnp_ctx& c, double* x, const dgnp_solve_opts& o, dgnp_solve_st
   W.b.alloc(size_t(N));
   W.red.alloc(size_t(reduce_scratch_size()));
   st = dgnp_solve_stats{};
-  DGNP_REQUIRE(o.restart >= 1 && o.restart <= 60, DGNP_E_ARG, "restart must be 1..60");
+  DGNP_REQUIRE(o.restart >= 1 && o.restart <= MAXV - 8, DGNP_E_ARG, "restart must be 1..120");
   DGNP_REQUIRE(o.prec == DGNP_F64 || o.prec == DGNP_F32, DGNP_E_ARG, "prec must be F64 or F32");
   double x0;
   DGNP_HIP(hipMemcpy(&x0, x, sizeof(double), hipMemcpyDeviceToHost));
@@ -487,6 +487,8 @@ int adjoint_solve(dgnp_ctx& c, const double* x, double* dJ_dbc, double* dJ_dPe, 
   hipStream_t s = c.work;
   const int64_t N = c.N;
   st = dgnp_solve_stats{};
+  DGNP_REQUIRE(o.restart >= 1 && o.restart <= MAXV - 8, DGNP_E_ARG, "restart must be 1..120");
+  DGNP_REQUIRE(o.prec == DGNP_F64 || o.prec == DGNP_F32, DGNP_E_ARG, "prec must be F64 or F32");
   const auto ts = clk::now();
   set_state(c, x, o.prec, s);
   st.t_setup = since(ts);

@@ -304,7 +304,7 @@ class Problem:
     @staticmethod
     def solve_opts(**kw):
         o = dgnp_solve_opts()
-        defaults = dict(rtol=1e-8, atol=0.0, max_newton=30, prec=DGNP_F64, lin_rtol=1e-3, restart=60,
+        defaults = dict(rtol=1e-8, atol=0.0, max_newton=30, prec=DGNP_F64, lin_rtol=1e-3, restart=120,
                         max_lin_it=600, pc_kind=DGNP_PC_P2, verbose=0)
         defaults.update(kw)
         for k, v in defaults.items():
