@@ -8,9 +8,110 @@
 #include "amg.hpp"
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
+#include <functional>
+#include <mutex>
+#include <thread>
 
 namespace dgnp {
+
+// Rows are processed in fixed chunks of CH rows on up to 16 host threads;
+// every reduction is formed per chunk and combined in chunk order, so results
+// do not depend on the number of threads.
+static constexpr int CH = 2048;
+
+// A persistent pool of host workers (created on first use, joined at exit):
+// a job is a chunk count and a function; the workers and the caller take
+// chunks from a shared counter.
+class HostPool {
+ public:
+  static HostPool& get() {
+    static HostPool pool;
+    return pool;
+  }
+  int size() const { return int(workers_.size()) + 1; }
+  // calls fn(thread, chunk) for every chunk in [0, nch)
+  void run(int nch, const std::function<void(int, int)>& fn) {
+    if (nch < 4 || workers_.empty()) {  // a few chunks: waking the workers costs more than it saves
+      for (int c = 0; c < nch; ++c) fn(0, c);
+      return;
+    }
+    std::lock_guard<std::mutex> one_job(run_m_);  // contexts on several host threads take turns
+    std::unique_lock<std::mutex> lk(m_);
+    job_ = &fn;
+    nch_ = nch;
+    next_.store(0);
+    helpers_ = std::min(int(workers_.size()), nch - 1);  // workers 1..helpers_ take part
+    active_ = helpers_;
+    ++gen_;
+    cv_.notify_all();
+    lk.unlock();
+    work(0);
+    lk.lock();
+    done_cv_.wait(lk, [&] { return active_ == 0; });
+    job_ = nullptr;
+  }
+  ~HostPool() {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      stop_ = true;
+      ++gen_;
+    }
+    cv_.notify_all();
+    for (auto& t : workers_) t.join();
+  }
+
+ private:
+  HostPool() {
+    const int nt = int(std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
+    for (int t = 1; t < nt; ++t)
+      workers_.emplace_back([this, t]() {
+        uint64_t seen = 0;
+        while (true) {
+          std::unique_lock<std::mutex> lk(m_);
+          cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+          if (stop_) return;
+          seen = gen_;
+          if (t > helpers_) continue;
+          lk.unlock();
+          work(t);
+          lk.lock();
+          if (--active_ == 0) done_cv_.notify_all();
+        }
+      });
+  }
+  void work(int t) {
+    for (int c = next_.fetch_add(1); c < nch_; c = next_.fetch_add(1)) (*job_)(t, c);
+  }
+  std::vector<std::thread> workers_;
+  std::mutex run_m_, m_;
+  std::condition_variable cv_, done_cv_;
+  const std::function<void(int, int)>* job_ = nullptr;
+  int nch_ = 0, active_ = 0, helpers_ = 0;
+  std::atomic<int> next_{0};
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
+
+static int host_threads(int) { return HostPool::get().size(); }
+
+// fn(thread, chunk, first row, end row); thread < host_threads(#chunks)
+template <typename F>
+static void parallel_chunks_t(int n, F&& fn) {
+  const int nch = (n + CH - 1) / CH;
+  const std::function<void(int, int)> job = [&](int t, int c) { fn(t, c, c * CH, std::min(n, (c + 1) * CH)); };
+  HostPool::get().run(nch, job);
+}
+
+template <typename F>
+static void parallel_chunks(int n, F&& fn) {
+  parallel_chunks_t(n, [&](int, int c, int r0, int r1) { fn(c, r0, r1); });
+}
 
 Csr csr_transpose(const Csr& A) {
   Csr T;
@@ -31,35 +132,57 @@ Csr csr_transpose(const Csr& A) {
   return T;
 }
 
-// Gustavson row-by-row product with a dense accumulator; columns sorted.
+// Gustavson row-by-row product with a dense accumulator per chunk; columns sorted.
 Csr csr_matmul(const Csr& A, const Csr& B) {
   Csr C;
   C.n = A.n;
   C.m = B.m;
   C.rp.assign(size_t(C.n) + 1, 0);
-  std::vector<double> acc(static_cast<size_t>(B.m), 0.0);
-  std::vector<int> mark(static_cast<size_t>(B.m), -1), cols;
-  for (int i = 0; i < A.n; ++i) {
-    cols.clear();
-    for (int ka = A.rp[i]; ka < A.rp[i + 1]; ++ka) {
-      const int j = A.ci[ka];
-      const double a = A.v[ka];
-      for (int kb = B.rp[j]; kb < B.rp[j + 1]; ++kb) {
-        const int c = B.ci[kb];
-        if (mark[c] != i) {
-          mark[c] = i;
-          acc[c] = 0.0;
-          cols.push_back(c);
+  const int nch = (A.n + CH - 1) / CH;
+  std::vector<std::vector<int>> cch(static_cast<size_t>(nch));
+  std::vector<std::vector<double>> vch(static_cast<size_t>(nch));
+  const int nt = host_threads(nch);
+  std::vector<std::vector<double>> accs(static_cast<size_t>(nt));
+  std::vector<std::vector<int>> marks(static_cast<size_t>(nt)), colss(static_cast<size_t>(nt));
+  parallel_chunks_t(A.n, [&](int t, int ch, int r0, int r1) {
+    std::vector<double>& acc = accs[size_t(t)];
+    std::vector<int>& mark = marks[size_t(t)];
+    std::vector<int>& cols = colss[size_t(t)];
+    if (acc.size() != size_t(B.m)) {
+      acc.assign(size_t(B.m), 0.0);
+      mark.assign(size_t(B.m), -1);
+    }
+    std::vector<int>& ci = cch[size_t(ch)];
+    std::vector<double>& cv = vch[size_t(ch)];
+    for (int i = r0; i < r1; ++i) {
+      cols.clear();
+      for (int ka = A.rp[i]; ka < A.rp[i + 1]; ++ka) {
+        const int j = A.ci[ka];
+        const double a = A.v[ka];
+        for (int kb = B.rp[j]; kb < B.rp[j + 1]; ++kb) {
+          const int c = B.ci[kb];
+          if (mark[c] != i) {
+            mark[c] = i;
+            acc[c] = 0.0;
+            cols.push_back(c);
+          }
+          acc[c] += a * B.v[kb];
         }
-        acc[c] += a * B.v[kb];
       }
+      std::sort(cols.begin(), cols.end());
+      for (int c : cols) {
+        ci.push_back(c);
+        cv.push_back(acc[c]);
+      }
+      C.rp[i + 1] = int(cols.size());
     }
-    std::sort(cols.begin(), cols.end());
-    for (int c : cols) {
-      C.ci.push_back(c);
-      C.v.push_back(acc[c]);
-    }
-    C.rp[i + 1] = int(C.ci.size());
+  });
+  for (int i = 0; i < C.n; ++i) C.rp[i + 1] += C.rp[i];
+  C.ci.reserve(size_t(C.rp[C.n]));
+  C.v.reserve(size_t(C.rp[C.n]));
+  for (int ch = 0; ch < nch; ++ch) {
+    C.ci.insert(C.ci.end(), cch[size_t(ch)].begin(), cch[size_t(ch)].end());
+    C.v.insert(C.v.end(), vch[size_t(ch)].begin(), vch[size_t(ch)].end());
   }
   return C;
 }
@@ -82,20 +205,33 @@ double lmax_dinvA(const Csr& A, const std::vector<double>& dinv, int iters) {
     s ^= s << 17;
     x[i] = double(s % 1000003) / 1000003.0 + 0.5;
   }
+  const int nch = (n + CH - 1) / CH;
+  std::vector<double> px(static_cast<size_t>(nch)), py(static_cast<size_t>(nch));
   double lam = 0.0;
   for (int it = 0; it < iters; ++it) {
+    parallel_chunks(n, [&](int ch, int r0, int r1) {
+      double sx = 0.0, sy = 0.0;
+      for (int i = r0; i < r1; ++i) {
+        double acc = 0.0;
+        for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) acc += A.v[k] * x[A.ci[k]];
+        y[i] = dinv[i] * acc;
+        sx += x[i] * x[i];
+        sy += y[i] * y[i];
+      }
+      px[size_t(ch)] = sx;
+      py[size_t(ch)] = sy;
+    });
     double nx = 0.0, ny = 0.0;
-    for (int i = 0; i < n; ++i) {
-      double acc = 0.0;
-      for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) acc += A.v[k] * x[A.ci[k]];
-      y[i] = dinv[i] * acc;
-      nx += x[i] * x[i];
-      ny += y[i] * y[i];
+    for (int ch = 0; ch < nch; ++ch) {
+      nx += px[size_t(ch)];
+      ny += py[size_t(ch)];
     }
     if (ny == 0.0) return 1.0;
     lam = std::sqrt(ny / nx);
     const double inv = 1.0 / std::sqrt(ny);
-    for (int i = 0; i < n; ++i) x[i] = y[i] * inv;
+    parallel_chunks(n, [&](int, int r0, int r1) {
+      for (int i = r0; i < r1; ++i) x[i] = y[i] * inv;
+    });
   }
   return lam;
 }
@@ -133,7 +269,7 @@ static std::vector<double> dense_inverse(const Csr& A) {
 }
 
 // one coarsening step: returns the smoothed prolongator
-static Csr sa_prolongator(const Csr& A, double theta) {
+static Csr sa_prolongator(const Csr& A, double theta, double lam_A) {
   const int n = A.n;
   const std::vector<double> d = diag_of(A);
   // strength of connection
@@ -141,7 +277,8 @@ static Csr sa_prolongator(const Csr& A, double theta) {
   for (int i = 0; i < n; ++i)
     for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
       const int j = A.ci[k];
-      if (j != i && std::fabs(A.v[k]) >= theta * std::sqrt(std::fabs(d[i] * d[j]))) strong[k] = 1;
+      if (j != i && (theta == 0.0 || std::fabs(A.v[k]) >= theta * std::sqrt(std::fabs(d[i] * d[j]))))
+        strong[k] = 1;
     }
   // aggregation
   std::vector<int> agg(static_cast<size_t>(n), -1);
@@ -190,29 +327,34 @@ static Csr sa_prolongator(const Csr& A, double theta) {
     Pt.ci[i] = agg[i];
   }
   Pt.rp[n] = n;
-  // filtered matrix: weak connections lumped onto the diagonal
-  Csr Af;
-  Af.n = Af.m = n;
-  Af.rp.assign(size_t(n) + 1, 0);
-  for (int i = 0; i < n; ++i) {
+  // filtered matrix: weak connections lumped onto the diagonal (with theta = 0
+  // every connection is strong and the filtered matrix is A itself)
+  Csr Afb;
+  const Csr& Af = theta == 0.0 ? A : Afb;
+  if (theta != 0.0) {
+    Afb.n = Afb.m = n;
+    Afb.rp.assign(size_t(n) + 1, 0);
+  }
+  for (int i = 0; i < n && theta != 0.0; ++i) {
     double lump = 0.0;
     for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
       const int j = A.ci[k];
       if (j == i) continue;
       if (strong[k]) {
-        Af.ci.push_back(j);
-        Af.v.push_back(A.v[k]);
+        Afb.ci.push_back(j);
+        Afb.v.push_back(A.v[k]);
       } else {
         lump += A.v[k];
       }
     }
-    Af.ci.push_back(i);
-    Af.v.push_back(d[i] + lump);
-    Af.rp[i + 1] = int(Af.ci.size());
+    Afb.ci.push_back(i);
+    Afb.v.push_back(d[i] + lump);
+    Afb.rp[i + 1] = int(Afb.ci.size());
   }
   std::vector<double> dinv(static_cast<size_t>(n));
   for (int i = 0; i < n; ++i) dinv[i] = d[i] != 0.0 ? 1.0 / d[i] : 0.0;
-  const double lam = lmax_dinvA(Af, dinv, 20);
+  // with theta = 0 every connection is strong and the filtered matrix is A itself
+  const double lam = theta == 0.0 && lam_A > 0.0 ? lam_A : lmax_dinvA(Af, dinv, 20);
   const double omega = (4.0 / 3.0) / lam;
   Csr AP = csr_matmul(Af, Pt);
   for (int i = 0; i < n; ++i)
@@ -246,28 +388,43 @@ static Csr sa_prolongator(const Csr& A, double theta) {
 }
 
 AmgHierarchy sa_setup(const Csr& A1, int max_levels, int coarse_size, double theta) {
+  static const bool trace = getenv("DGNP_TRACE_SETUP") != nullptr;
+  auto t0 = std::chrono::steady_clock::now();
+  auto mark = [&](const char* what) {
+    if (!trace) return;
+    const auto t1 = std::chrono::steady_clock::now();
+    fprintf(stderr, "[setup]   sa %-18s %8.3f ms\n", what, 1e3 * std::chrono::duration<double>(t1 - t0).count());
+    t0 = t1;
+  };
   AmgHierarchy H;
   H.A.push_back(A1);
-  while (int(H.A.size()) < max_levels && H.A.back().n > coarse_size) {
-    const Csr& A = H.A.back();
-    Csr P = sa_prolongator(A, theta);
-    if (P.m >= A.n * 0.9 || P.m == 0) break;  // stalled coarsening
-    Csr R = csr_transpose(P);
-    Csr Ac = csr_matmul(R, csr_matmul(A, P));
-    H.P.push_back(std::move(P));
-    H.R.push_back(std::move(R));
-    H.A.push_back(std::move(Ac));
-  }
-  if (H.A.back().n > 4096)
-    throw Error(DGNP_E_BREAKDOWN, "algebraic multigrid coarsening stalled at " + std::to_string(H.A.back().n) +
-                                      " unknowns");
-  for (const Csr& A : H.A) {
+  auto smoother_data = [&](const Csr& A) {
     std::vector<double> d = diag_of(A), dinv(d.size());
     for (size_t i = 0; i < d.size(); ++i) dinv[i] = d[i] != 0.0 ? 1.0 / d[i] : 0.0;
     H.lmax.push_back(lmax_dinvA(A, dinv, 20));
     H.dinv.push_back(std::move(dinv));
+  };
+  smoother_data(H.A.back());
+  mark("lmax");
+  while (int(H.A.size()) < max_levels && H.A.back().n > coarse_size) {
+    const Csr& A = H.A.back();
+    Csr P = sa_prolongator(A, theta, H.lmax.back());
+    mark("prolongator");
+    if (P.m >= A.n * 0.9 || P.m == 0) break;  // stalled coarsening
+    Csr R = csr_transpose(P);
+    Csr Ac = csr_matmul(R, csr_matmul(A, P));
+    mark("RAP");
+    H.P.push_back(std::move(P));
+    H.R.push_back(std::move(R));
+    H.A.push_back(std::move(Ac));
+    smoother_data(H.A.back());
+    mark("lmax");
   }
+  if (H.A.back().n > 4096)
+    throw Error(DGNP_E_BREAKDOWN, "algebraic multigrid coarsening stalled at " + std::to_string(H.A.back().n) +
+                                      " unknowns");
   H.coarse_inv = dense_inverse(H.A.back());
+  mark("coarse inverse");
   return H;
 }
 
