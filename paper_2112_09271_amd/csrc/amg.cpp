@@ -68,7 +68,8 @@ class HostPool {
 
  private:
   HostPool() {
-    const int nt = int(std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
+    int nt = int(std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
+    if (const char* e = getenv("DGNP_HOST_THREADS")) nt = std::max(1, std::min(64, atoi(e)));
     for (int t = 1; t < nt; ++t)
       workers_.emplace_back([this, t]() {
         uint64_t seen = 0;

@@ -1,0 +1,123 @@
+// Host check of the smoothed-aggregation set-up (amg.cpp) on the 7-point
+// Laplacian of an n^3 grid: SpGEMM and transpose against dense products,
+// every node aggregated, symmetric Galerkin operators, the coarsest inverse,
+// and bitwise-identical hierarchies across repeated runs.  Prints "ok" and
+// returns 0, or names the failed check and returns 1.
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "amg.hpp"
+
+using dgnp::Csr;
+
+static Csr laplace3d(int n) {
+  Csr A;
+  A.n = A.m = n * n * n;
+  A.rp.push_back(0);
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        const int r = i + n * (j + n * k);
+        const int off[7][3] = {{0, 0, -1}, {0, -1, 0}, {-1, 0, 0}, {0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+        for (auto& o : off) {
+          const int ii = i + o[0], jj = j + o[1], kk = k + o[2];
+          if (ii < 0 || jj < 0 || kk < 0 || ii >= n || jj >= n || kk >= n) continue;
+          A.ci.push_back(ii + n * (jj + n * kk));
+          A.v.push_back(o[0] == 0 && o[1] == 0 && o[2] == 0 ? 6.0 + 0.01 * (r % 7) : -1.0);
+        }
+        A.rp.push_back(int(A.ci.size()));
+      }
+  return A;
+}
+
+static std::vector<double> dense(const Csr& A) {
+  std::vector<double> d(size_t(A.n) * A.m, 0.0);
+  for (int i = 0; i < A.n; ++i)
+    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) d[size_t(i) * A.m + A.ci[k]] += A.v[k];
+  return d;
+}
+
+static int fail(const char* what) {
+  printf("FAILED: %s\n", what);
+  return 1;
+}
+
+int main() {
+  // SpGEMM and transpose on a small case against dense arithmetic
+  {
+    Csr A = laplace3d(5), B = dgnp::csr_transpose(laplace3d(5));
+    Csr C = dgnp::csr_matmul(A, B);
+    std::vector<double> a = dense(A), b = dense(B), c = dense(C);
+    const int n = A.n;
+    double err = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s += a[size_t(i) * n + k] * b[size_t(k) * n + j];
+        err = std::fmax(err, std::fabs(s - c[size_t(i) * n + j]));
+      }
+    if (err > 1e-12) return fail("csr_matmul differs from the dense product");
+    for (int i = 0; i < C.n; ++i)
+      for (int k = C.rp[i] + 1; k < C.rp[i + 1]; ++k)
+        if (C.ci[k] <= C.ci[k - 1]) return fail("csr_matmul columns not sorted");
+  }
+  // hierarchy on a grid large enough for several chunks of rows
+  Csr A = laplace3d(30);
+  dgnp::AmgHierarchy H = dgnp::sa_setup(A, 12, 256, 0.0);
+  if (H.A.size() < 2) return fail("no coarsening");
+  for (size_t l = 0; l + 1 < H.A.size(); ++l) {
+    const Csr& P = H.P[l];
+    if (P.n != H.A[l].n || P.m != H.A[l + 1].n) return fail("prolongator shape");
+    if (P.m >= P.n / 4) return fail("weak coarsening");
+    for (int i = 0; i < P.n; ++i)
+      if (P.rp[i + 1] == P.rp[i]) return fail("row of P without an aggregate");
+    // Galerkin operator symmetric
+    const Csr& Ac = H.A[l + 1];
+    std::vector<double> d = dense(Ac);
+    for (int i = 0; i < Ac.n; ++i)
+      for (int j = 0; j < i; ++j)
+        if (std::fabs(d[size_t(i) * Ac.n + j] - d[size_t(j) * Ac.n + i]) > 1e-10 * std::fabs(d[size_t(i) * Ac.n + i]))
+          return fail("coarse operator not symmetric");
+    if (!(H.lmax[l] > 1.0 && H.lmax[l] < 2.0)) return fail("lambda_max of D^-1 A outside (1, 2)");
+  }
+  // the coarsest inverse
+  {
+    const Csr& Ac = H.A.back();
+    std::vector<double> d = dense(Ac);
+    const int n = Ac.n;
+    double err = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s += H.coarse_inv[size_t(i) * n + k] * d[size_t(k) * n + j];
+        err = std::fmax(err, std::fabs(s - (i == j ? 1.0 : 0.0)));
+      }
+    if (err > 1e-10) return fail("coarsest inverse");
+  }
+  // a second set-up (worker pool already running) gives the same hierarchy bit for bit
+  dgnp::AmgHierarchy H2 = dgnp::sa_setup(A, 12, 256, 0.0);
+  if (H2.A.size() != H.A.size()) return fail("repeat: level count");
+  for (size_t l = 0; l < H.A.size(); ++l)
+    if (H2.A[l].v != H.A[l].v || H2.A[l].ci != H.A[l].ci || H2.lmax[l] != H.lmax[l])
+      return fail("repeat: hierarchy differs");
+  // checksum of every value of the hierarchy (bit patterns), to compare runs
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](double x) {
+    uint64_t b;
+    std::memcpy(&b, &x, sizeof b);
+    h = (h ^ b) * 1099511628211ull;
+  };
+  for (size_t l = 0; l < H.A.size(); ++l) {
+    for (double x : H.A[l].v) mix(x);
+    mix(H.lmax[l]);
+  }
+  for (const Csr& P : H.P)
+    for (double x : P.v) mix(x);
+  printf("ok levels %zu sizes", H.A.size());
+  for (auto& L : H.A) printf(" %d", L.n);
+  printf(" checksum %016llx\n", static_cast<unsigned long long>(h));
+  return 0;
+}
