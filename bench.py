@@ -11,8 +11,9 @@ seeded synthetic inputs are resident on the GPU before timing starts.
 One JSON line is printed.  Besides the contract fields it carries the FP64
 time-to-solution on the same input, the adjoint-gradient time, the
 Jacobian-apply bandwidth on the largest channel (128x32x16 hexes, p = 3,
-12.6M DOFs), the roofline of the dominant kernel of the timed solve and the
-CPU oracle baseline.
+12.6M DOFs), mixed and FP64 time-to-solution on the two channels (64x16x8 and
+128x32x16 hexes, p = 3) with an adjoint on the larger, the roofline of the
+dominant kernel of the timed solve and the CPU oracle baseline.
 """
 from __future__ import annotations
 
@@ -41,7 +42,8 @@ def parse():
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--apply-workload", default="cfg5")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extra", action="store_true", help="skip the FP64, adjoint and large-apply legs")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the FP64, adjoint, large-apply and channel-solve legs")
     ap.add_argument("--only-apply", action="store_true", help="run only the large Jacobian-apply leg")
     return ap.parse_args()
 
@@ -198,6 +200,51 @@ def apply_bandwidth(name, reps=20):
     return out
 
 
+def channel_solves(names):
+    """Time-to-solution on the channel configurations: mixed and FP64 solves from
+    the initial guess to 1e-8 (after one untimed mixed solve), their agreement,
+    and on the largest one a mixed-precision adjoint gradient."""
+    import torch
+
+    from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64, Problem
+    from workload import boundary_data, get_config
+    out = {}
+    for name in names:
+        cfg = get_config(name)
+        prob = Problem(cfg, boundary_data(cfg))
+        rec = {"workload": f"{cfg.name}: {cfg.note}", "dofs": prob.N}
+
+        def run(prec):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, st = prob.solve(rtol=cfg.newton_tol, prec=prec)
+            torch.cuda.synchronize()
+            if st.status != 0:
+                raise RuntimeError(f"{name} solve failed with status {st.status}")
+            return x, st, time.perf_counter() - t0
+
+        run(DGNP_F32)
+        x32, st32, t32 = run(DGNP_F32)
+        x64, st64, t64 = run(DGNP_F64)
+        rec.update({"mixed_s": t32, "fp64_s": t64, "mixed_speedup_vs_fp64": t64 / t32,
+                    "newton_its": st32.newton_its, "fgmres_its_mixed": st32.lin_its_total,
+                    "fgmres_its_fp64": st64.lin_its_total, "setup_s_mixed": st32.t_setup,
+                    "krylov_s_mixed": st32.t_krylov,
+                    "mixed_vs_fp64_rel_l2": (x64 - x32).norm().item() / x64.norm().item()})
+        if name == names[-1]:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            prob.adjoint(x32, prec=DGNP_F32, rtol=1e-8)
+            torch.cuda.synchronize()
+            rec["adjoint_s"] = time.perf_counter() - t0
+        log(f"[bench] {name}: mixed {t32:.3f}s fp64 {t64:.3f}s ({st32.lin_its_total} / {st64.lin_its_total} its)")
+        prob.close()
+        del x32, x64
+        torch.cuda.empty_cache()
+        out[name] = rec
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -313,6 +360,7 @@ def main():
         ja["traffic_f32"] = measured_traffic("k_dg_jac_f32_cfg5", source_hash("kernels_dg.hip", "dg_device.hpp",
                                                                               "pointwise.hpp"))
         out["jacobian_apply"] = ja
+        out["channel_solves"] = channel_solves(["cfg3", "cfg5"])
     if not args.no_cpu:
         cb = cpu_baseline()
         log(f"[bench] cpu oracle: {cb['value']:.2f}s ({cb['sample']})")

@@ -79,12 +79,11 @@ __global__ void __launch_bounds__(BT)
   constexpr int VOL2A = QV + S1 + S2 + NCB * NQV;
   constexpr int VOL2B = 4 * Y2G;
   constexpr int VOLR = VOL1 + (VOL2A > VOL2B ? VOL2A : VOL2B);
-  constexpr int TRQ = MF * 2 * NQF;
-  constexpr int TRN = MF * 2 * NFN;
-  constexpr int TRM = DIM == 3 ? MF * 2 * NN * NQ : 0;
+  constexpr int NFACE = 2 * DIM;
+  constexpr int NROWF = NFACE * 2 * MF * 2;  // face trace rows: face, side (own / neighbour), field, value / dn
   constexpr int ZSZ = 8 * NN2 * Q3;
   constexpr int CSZ = 8 * NN2 * N3 * N3;
-  constexpr int FACR = NBT + 2 * TRQ + TRN + TRM + NQF * 8 + ZSZ + CSZ;
+  constexpr int FACR = NROWF * (NFN + NQF) + NFACE * NQF * 8 + ZSZ + CSZ;
   constexpr int REG = VOLR > FACR ? VOLR : FACR;
   constexpr int ENT = (NB * NB + BT - 1) / BT;
   constexpr int NSLOT = 2 * DIM + 1;
@@ -245,46 +244,87 @@ __global__ void __launch_bounds__(BT)
   }
 
   // ---- faces
-  double* n_x = R;
-  double* tox = R + NBT;
-  double* tnx = tox + TRQ;
-  double* tn = tnx + TRQ;
-  double* tm = tn + TRN;
-  double* Mf = tm + TRM;  // [qf][2 test][4 trial: own v, own g, nb v, nb g]
-  double* Z = Mf + NQF * 8;  // [8][q2][i1 j1]
-  double* Cf = Z + ZSZ;      // [8][i2 j2][i1 j1]
+  // FA: node traces (value, d/dx_ax) of the state on both sides of every face
+  //     (rows: face, side, field, value / dn; the neighbour read from global memory);
+  // FB: both tangential interpolations of every row to the face points;
+  // FC: the pointwise face Jacobian for every (face, point, trial direction),
+  //     Mf[face][qf][test value / dn][trial: own v, own g, nb v, nb g];
+  // then, face by face, the tangential contractions and the expansion below.
+  double* fnod = R;                              // [NROWF][NFN]
+  double* fq = fnod + NROWF * NFN;               // [NROWF][NQF]
+  double* MfA = fq + NROWF * NQF;                // [NFACE][NQF][8]
+  double* Z = MfA + NFACE * NQF * 8;             // [8][q2][i1 j1]
+  double* Cf = Z + ZSZ;                          // [8][i2 j2][i1 j1]
   double* out = blk + ((int64_t(f) * A.E + e) * NSLOT) * NB * NB;
-  for (int slot = 0; slot < 2 * DIM; ++slot) {
-    const int ax = slot >> 1, side = (slot & 1) ? 1 : -1;
-    const int nb = A.nbr[e * 2 * DIM + slot];
-    const bool interior = nb >= 0;
-    const int cbc = interior ? 0 : A.c_bc[slot];
-    const bool phid = interior ? false : (A.phi_bc[slot] == DGNP_PHI_DIRICHLET);
-    double* ob = out + int64_t(1 + slot) * NB * NB;
-    if (!interior && cbc == BC_WALL && !phid) {
-      for (int idx = tid; idx < NB * NB; idx += BT) ob[idx] = 0.0;
-      continue;
+  {
+    for (int idx = tid; idx < (NROWF / 2) * NFN; idx += BT) {
+      const int ij = idx % NFN, pr = idx / NFN;
+      const int c = pr % MF, sd = (pr / MF) % 2, fc = pr / (2 * MF);
+      const int ax = fc >> 1;
+      const int side = (fc & 1) ? 1 : -1;
+      const int sside = sd == 0 ? side : -side;
+      const int nbe = A.nbr[e * 2 * DIM + fc];
+      const double* u = nullptr;
+      if (sd == 0)
+        u = s_x + c * NB;
+      else if (nbe >= 0)
+        u = xs + c * Nf + int64_t(nbe) * NB;
+      const int i = ij % NN, j = ij / NN;
+      double val = 0.0, dn = 0.0;
+      if (u) {
+        const double* De = tb.De[sside < 0 ? 0 : 1];
+        for (int l = 0; l < NN; ++l) {
+          const double x = u[face_node<DIM, NN>(ax, l, i, j)];
+          dn += De[l] * x;
+          if (l == (sside < 0 ? 0 : P)) val = x;
+        }
+        dn *= ih[ax];
+      }
+      fnod[(2 * pr + 0) * NFN + ij] = val;
+      fnod[(2 * pr + 1) * NFN + ij] = dn;
     }
-    trace<DIM, P, MF, BT, double>(s_x, ax, side, tox, tn, tm, tb, ih[ax], tid);
-    if (interior) {
-      for (int i = tid; i < NBT; i += BT) n_x[i] = xs[(i / NB) * Nf + int64_t(nb) * NB + (i % NB)];
-      __syncthreads();
-      trace<DIM, P, MF, BT, double>(n_x, ax, -side, tnx, tn, tm, tb, ih[ax], tid);
+    __syncthreads();
+    for (int row = tid; row < NROWF; row += BT) {
+      const double* x = fnod + row * NFN;
+      if constexpr (DIM == 3) {
+        double y[NN][NQ];
+        for (int j = 0; j < NN; ++j)
+          for (int qi = 0; qi < NQ; ++qi) {
+            double t = 0.0;
+            for (int i = 0; i < NN; ++i) t += tb.B[qi * NN + i] * x[j * NN + i];
+            y[j][qi] = t;
+          }
+        for (int qj = 0; qj < NQ; ++qj)
+          for (int qi = 0; qi < NQ; ++qi) {
+            double t = 0.0;
+            for (int j = 0; j < NN; ++j) t += tb.B[qj * NN + j] * y[j][qi];
+            fq[row * NQF + qj * NQ + qi] = t;
+          }
+      } else {
+        for (int qi = 0; qi < NQ; ++qi) {
+          double t = 0.0;
+          for (int i = 0; i < NN; ++i) t += tb.B[qi * NN + i] * x[i];
+          fq[row * NQF + qi] = t;
+        }
+      }
     }
-    int64_t bf = 0;
-    if (!interior) {
-      int64_t lin;
-      if constexpr (DIM == 3)
-        lin = ax == 0 ? eid[1] + int64_t(A.n[1]) * eid[2]
-                      : (ax == 1 ? eid[0] + int64_t(A.n[0]) * eid[2] : eid[0] + int64_t(A.n[0]) * eid[1]);
-      else
-        lin = ax == 0 ? eid[1] : eid[0];
-      bf = A.btag_off[slot] + lin;
-    }
-    const int t1ax = DIM == 3 ? (ax == 0 ? 1 : 0) : 1 - ax;
-    const int t2ax = DIM == 3 ? (ax == 2 ? 1 : 2) : 0;
-    const int own = side > 0 ? 0 : 1;
-    for (int qf = tid; qf < NQF; qf += BT) {
+    __syncthreads();
+    auto trow = [&](int fc, int sd, int c, int c2) { return ((fc * 2 + sd) * MF + c) * 2 + c2; };
+    for (int idx = tid; idx < NFACE * NQF * 4; idx += BT) {
+      const int beta = idx % 4, qf = (idx / 4) % NQF, fc = idx / (4 * NQF);
+      const int ax = fc >> 1, side = (fc & 1) ? 1 : -1;
+      const int nbe = A.nbr[e * 2 * DIM + fc];
+      const bool interior = nbe >= 0;
+      const int cbc = interior ? 0 : A.c_bc[fc];
+      const bool phid = interior ? false : (A.phi_bc[fc] == DGNP_PHI_DIRICHLET);
+      double* M = MfA + (fc * NQF + qf) * 8;
+      if (!interior && (beta >= 2 || (cbc == BC_WALL && !phid))) {
+        M[0 * 4 + beta] = 0.0;
+        M[1 * 4 + beta] = 0.0;
+        continue;
+      }
+      const int t1ax = DIM == 3 ? (ax == 0 ? 1 : 0) : 1 - ax;
+      const int t2ax = DIM == 3 ? (ax == 2 ? 1 : 2) : 0;
       const int qi = qf % NQ, qj = qf / NQ;
       double xp[3];
       xp[ax] = A.lo[ax] + (eid[ax] + (side > 0 ? 1.0 : 0.0)) * A.h[ax];
@@ -296,68 +336,80 @@ __global__ void __launch_bounds__(BT)
       }
       double uh[3];
       velocity_hat(A, xp, DIM, uh);
+      double fo = 0.0, go = 0.0;
       if (interior) {
         const double un = A.Pe * uh[ax];
-        double v[2][MF], g[2][MF];
+        const int own = side > 0 ? 0 : 1;
+        double v[2][MF], g[2][MF], tv[2][MF], tg[2][MF];
+        const int sdb = beta < 2 ? own : 1 - own;
+#pragma unroll
         for (int c = 0; c < MF; ++c) {
-          v[own][c] = tox[(c * 2 + 0) * NQF + qf];
-          g[own][c] = tox[(c * 2 + 1) * NQF + qf];
-          v[1 - own][c] = tnx[(c * 2 + 0) * NQF + qf];
-          g[1 - own][c] = tnx[(c * 2 + 1) * NQF + qf];
-        }
-        for (int beta = 0; beta < 4; ++beta) {
-          double tv[2][MF], tg[2][MF];
-          const int sd = beta < 2 ? own : 1 - own;
+          v[own][c] = fq[trow(fc, 0, c, 0) * NQF + qf];
+          g[own][c] = fq[trow(fc, 0, c, 1) * NQF + qf];
+          v[1 - own][c] = fq[trow(fc, 1, c, 0) * NQF + qf];
+          g[1 - own][c] = fq[trow(fc, 1, c, 1) * NQF + qf];
 #pragma unroll
-          for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-            for (int c = 0; c < MF; ++c) {
-              tv[s2][c] = (s2 == sd && c == f && beta % 2 == 0) ? 1.0 : 0.0;
-              tg[s2][c] = (s2 == sd && c == f && beta % 2 == 1) ? 1.0 : 0.0;
-            }
-          double Fo[MF], Go[MF];
-          face_jac<double, MF>(ph, v, g, tv, tg, un, own, Fo, Go);
-          double fo = 0.0, go = 0.0;
-#pragma unroll
-          for (int c = 0; c < MF; ++c) {
-            fo = c == f ? Fo[c] : fo;
-            go = c == f ? Go[c] : go;
+          for (int s2 = 0; s2 < 2; ++s2) {
+            tv[s2][c] = (s2 == sdb && c == f && beta % 2 == 0) ? 1.0 : 0.0;
+            tg[s2][c] = (s2 == sdb && c == f && beta % 2 == 1) ? 1.0 : 0.0;
           }
-          const double sb = (beta % 2 == 0) ? 1.0 : ih[ax];
-          Mf[(qf * 2 + 0) * 4 + beta] = fo * w * sb;
-          Mf[(qf * 2 + 1) * 4 + beta] = go * w * sb * ih[ax];
         }
+        double Fo[MF], Go[MF];
+        face_jac<double, MF>(ph, v, g, tv, tg, un, own, Fo, Go);
+#pragma unroll
+        for (int c = 0; c < MF; ++c) {
+          fo = c == f ? Fo[c] : fo;
+          go = c == f ? Go[c] : go;
+        }
+        const double sb = (beta % 2 == 0) ? 1.0 : ih[ax];
+        M[0 * 4 + beta] = fo * w * sb;
+        M[1 * 4 + beta] = go * w * sb * ih[ax];
       } else {
+        int64_t lin;
+        if constexpr (DIM == 3)
+          lin = ax == 0 ? eid[1] + int64_t(A.n[1]) * eid[2]
+                        : (ax == 1 ? eid[0] + int64_t(A.n[0]) * eid[2] : eid[0] + int64_t(A.n[0]) * eid[1]);
+        else
+          lin = ax == 0 ? eid[1] : eid[0];
+        const int64_t bf = A.btag_off[fc] + lin;
         const double un = side * A.Pe * uh[ax];
-        double v[MF], g[MF], gd[MF];
+        double v[MF], g[MF], gd[MF], tv[MF], tg[MF];
+#pragma unroll
         for (int c = 0; c < MF; ++c) {
-          v[c] = tox[(c * 2 + 0) * NQF + qf];
-          g[c] = side * tox[(c * 2 + 1) * NQF + qf];
+          v[c] = fq[trow(fc, 0, c, 0) * NQF + qf];
+          g[c] = side * fq[trow(fc, 0, c, 1) * NQF + qf];
           gd[c] = A.bcq[(c * A.n_bface + bf) * NQF + qf];
+          tv[c] = (c == f && beta == 0) ? 1.0 : 0.0;
+          tg[c] = (c == f && beta == 1) ? 1.0 : 0.0;
         }
-        for (int beta = 0; beta < 2; ++beta) {
-          double tv[MF], tg[MF];
+        double Fo[MF], Go[MF];
+        bnd_jac<double, MF>(ph, v, g, tv, tg, un, cbc, phid, gd, Fo, Go);
 #pragma unroll
-          for (int c = 0; c < MF; ++c) {
-            tv[c] = (c == f && beta == 0) ? 1.0 : 0.0;
-            tg[c] = (c == f && beta == 1) ? 1.0 : 0.0;
-          }
-          double Fo[MF], Go[MF];
-          bnd_jac<double, MF>(ph, v, g, tv, tg, un, cbc, phid, gd, Fo, Go);
-          double fo = 0.0, go = 0.0;
-#pragma unroll
-          for (int c = 0; c < MF; ++c) {
-            fo = c == f ? Fo[c] : fo;
-            go = c == f ? Go[c] : go;
-          }
-          const double sb = beta == 0 ? 1.0 : side * ih[ax];
-          Mf[(qf * 2 + 0) * 4 + beta] = fo * w * sb;
-          Mf[(qf * 2 + 1) * 4 + beta] = go * w * sb * side * ih[ax];
-          Mf[(qf * 2 + 0) * 4 + 2 + beta] = 0.0;
-          Mf[(qf * 2 + 1) * 4 + 2 + beta] = 0.0;
+        for (int c = 0; c < MF; ++c) {
+          fo = c == f ? Fo[c] : fo;
+          go = c == f ? Go[c] : go;
         }
+        const double sb = beta == 0 ? 1.0 : side * ih[ax];
+        M[0 * 4 + beta] = fo * w * sb;
+        M[1 * 4 + beta] = go * w * sb * side * ih[ax];
       }
     }
+    __syncthreads();
+  }
+  for (int slot = 0; slot < 2 * DIM; ++slot) {
+    const int ax = slot >> 1, side = (slot & 1) ? 1 : -1;
+    const int nb = A.nbr[e * 2 * DIM + slot];
+    const bool interior = nb >= 0;
+    const int cbc = interior ? 0 : A.c_bc[slot];
+    const bool phid = interior ? false : (A.phi_bc[slot] == DGNP_PHI_DIRICHLET);
+    double* ob = out + int64_t(1 + slot) * NB * NB;
+    if (!interior && cbc == BC_WALL && !phid) {
+      for (int idx = tid; idx < NB * NB; idx += BT) ob[idx] = 0.0;
+      continue;
+    }
+    const int t1ax = DIM == 3 ? (ax == 0 ? 1 : 0) : 1 - ax;
+    const int t2ax = DIM == 3 ? (ax == 2 ? 1 : 2) : 0;
+    const double* Mf = MfA + slot * NQF * 8;
     __syncthreads();
     // first tangential direction: Z[ab][qj][i1 j1] = sum_qi B(qi, i1) B(qi, j1) Mf[qi, qj][ab]
     for (int o = tid; o < 8 * Q3 * NN2; o += BT) {
@@ -480,16 +532,16 @@ __device__ void gj_invert(double* a, double* sh, int* shi, int* rsrc, int* csrc,
       double xk = 0.0;
 #pragma unroll
       for (int j = 0; j < NC; ++j) xk = j == jk ? x[j] : xk;
-      double best = used ? -1.0 : fabs(xk);
-      int bi = r;
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
+      // pivot: largest |x| among unused rows, compared on the upper word of its
+      // bit pattern (sign, exponent, 20 mantissa bits: non-negative doubles
+      // order like these integers), ties to the smallest row; the reduction is
+      // one 32-bit lane exchange per step and a ballot picks the row
+      const double ax = fabs(xk);
+      const int key = used ? -1 : int(uint32_t(uint64_t(__double_as_longlong(ax)) >> 32));
+      int mk = key;
+      for (int off = 32; off > 0; off >>= 1) mk = max(mk, __shfl_xor(mk, off, 64));
+      const uint64_t hit = __ballot(key == mk);
+      const int bi = __ffsll(static_cast<unsigned long long>(hit)) - 1;
       pcol[r] = xk;
       if (r == bi) {
         shi[b] = bi;
@@ -577,38 +629,43 @@ struct BlkGemm {
 };
 
 // acc += Lft * Rgt over all k, both operands NB x NB row-major in global memory.
-// The next panel is fetched into registers while the current one is used.
+// Panels are fetched into registers two ahead of their use (the panel loop is
+// unrolled, so the two register buffers are addressed at compile time).
 template <int NB>
 __device__ inline void gemm_gg(double (&acc)[BlkGemm<NB>::RT][BlkGemm<NB>::RT], const double* __restrict__ L,
                                const double* __restrict__ Rm, double* pa, double* pb, int tid) {
   using G = BlkGemm<NB>;
   constexpr int PE = (NB * G::KP + BT - 1) / BT;  // panel elements per thread
+  constexpr int NP = (NB + G::KP - 1) / G::KP;    // panels
   const int ty = tid >> 4, tx = tid & 15;
-  double ra[PE], rb[PE];
-  auto fetch = [&](int k0) {
+  double ra[2][PE], rb[2][PE];
+  auto fetch = [&](int p, double (&xa)[PE], double (&xb)[PE]) {
+    const int k0 = p * G::KP;
 #pragma unroll
     for (int q = 0; q < PE; ++q) {
       const int idx = tid + q * BT;
       const int r = idx / G::KP, kk = idx % G::KP;
-      ra[q] = (idx < NB * G::KP && k0 + kk < NB) ? L[r * NB + k0 + kk] : 0.0;
+      xa[q] = (idx < NB * G::KP && k0 + kk < NB) ? L[r * NB + k0 + kk] : 0.0;
       const int kr = idx / NB, cc = idx % NB;
-      rb[q] = (idx < NB * G::KP && k0 + kr < NB) ? Rm[(k0 + kr) * NB + cc] : 0.0;
+      xb[q] = (idx < NB * G::KP && k0 + kr < NB) ? Rm[(k0 + kr) * NB + cc] : 0.0;
     }
   };
-  fetch(0);
-#pragma unroll 1
-  for (int k0 = 0; k0 < NB; k0 += G::KP) {
+  fetch(0, ra[0], rb[0]);
+  if (NP > 1) fetch(1, ra[1], rb[1]);
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int k0 = p * G::KP;
     const int kn = (NB - k0) < G::KP ? (NB - k0) : G::KP;
 #pragma unroll
     for (int q = 0; q < PE; ++q) {
       const int idx = tid + q * BT;
       if (idx < NB * G::KP) {
-        pa[(idx / G::KP) * G::PLD + idx % G::KP] = ra[q];
-        pb[idx] = rb[q];
+        pa[(idx / G::KP) * G::PLD + idx % G::KP] = ra[p & 1][q];
+        pb[idx] = rb[p & 1][q];
       }
     }
     __syncthreads();
-    if (k0 + G::KP < NB) fetch(k0 + G::KP);
+    if (p + 2 < NP) fetch(p + 2, ra[p & 1], rb[p & 1]);
 #pragma unroll 4
     for (int kk = 0; kk < kn; ++kk) {
       double av[G::RT], bv[G::RT];
@@ -638,6 +695,7 @@ __device__ inline void scale_block(double* __restrict__ B, const double* a, cons
                                    double* pb, int tid) {
   using G = BlkGemm<NB>;
   constexpr int PE = (NB * G::KP + BT - 1) / BT;
+  constexpr int NP = (NB + G::KP - 1) / G::KP;
   const int ty = tid >> 4, tx = tid & 15;
   double acc[G::RT][G::RT];
 #pragma unroll
@@ -650,26 +708,29 @@ __device__ inline void scale_block(double* __restrict__ B, const double* a, cons
     const int r = ty + 16 * i;
     arow[i] = r < NB ? rsrc[r] * LD : 0;
   }
-  double rb[PE];
-  auto fetch = [&](int k0) {
+  double rb[2][PE];
+  auto fetch = [&](int p, double (&xb)[PE]) {
+    const int k0 = p * G::KP;
 #pragma unroll
     for (int q = 0; q < PE; ++q) {
       const int idx = tid + q * BT;
       const int kr = idx / NB, cc = idx % NB;
-      rb[q] = (idx < NB * G::KP && k0 + kr < NB) ? B[(k0 + kr) * NB + cc] : 0.0;
+      xb[q] = (idx < NB * G::KP && k0 + kr < NB) ? B[(k0 + kr) * NB + cc] : 0.0;
     }
   };
-  fetch(0);
-#pragma unroll 1
-  for (int k0 = 0; k0 < NB; k0 += G::KP) {
+  fetch(0, rb[0]);
+  if (NP > 1) fetch(1, rb[1]);
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int k0 = p * G::KP;
     const int kn = (NB - k0) < G::KP ? (NB - k0) : G::KP;
 #pragma unroll
     for (int q = 0; q < PE; ++q) {
       const int idx = tid + q * BT;
-      if (idx < NB * G::KP) pb[idx] = rb[q];
+      if (idx < NB * G::KP) pb[idx] = rb[p & 1][q];
     }
     __syncthreads();
-    if (k0 + G::KP < NB) fetch(k0 + G::KP);
+    if (p + 2 < NP) fetch(p + 2, rb[p & 1]);
 #pragma unroll 4
     for (int kk = 0; kk < kn; ++kk) {
       const int kc = csrc[k0 + kk];
