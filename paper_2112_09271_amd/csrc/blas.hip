@@ -20,6 +20,15 @@ __global__ void k_d2f(const double* __restrict__ x, float* __restrict__ y, int64
   for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB)
     y[i] = float(x[i]);
 }
+// y[r][c] = x[r][c] for c < nb, 0 for nb <= c < ld (rows of nb doubles to rows of ld floats)
+__global__ void k_d2f_rows(const double* __restrict__ x, float* __restrict__ y, int64_t rows, int nb, int ld) {
+  const int64_t n = rows * ld;
+  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
+    const int64_t r = i / ld;
+    const int c = int(i - r * ld);
+    y[i] = c < nb ? float(x[r * nb + c]) : 0.f;
+  }
+}
 __global__ void k_f2d(const float* __restrict__ x, double* __restrict__ y, int64_t n) {
   for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB)
     y[i] = double(x[i]);
@@ -60,6 +69,10 @@ __global__ void k_scale(T a, T* __restrict__ x, int64_t n) {
 void cvt_d2f(const double* x, float* y, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_d2f, dim3(grid_for(n)), dim3(VB), 0, s, x, y, n);
+}
+void cvt_d2f_rows(const double* x, float* y, int64_t rows, int nb, int ld, hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(k_d2f_rows, dim3(grid_for(rows * ld)), dim3(VB), 0, s, x, y, rows, nb, ld);
 }
 void cvt_f2d(const float* x, double* y, int64_t n, hipStream_t s) {
   if (n <= 0) return;

@@ -7,6 +7,8 @@ namespace dgnp {
 // most vectors one reduction call handles (the Krylov basis of the longest restart)
 constexpr int MAXV = 128;
 void cvt_d2f(const double* x, float* y, int64_t n, hipStream_t s);
+// rows of nb doubles -> rows of ld >= nb floats, zero-padded
+void cvt_d2f_rows(const double* x, float* y, int64_t rows, int nb, int ld, hipStream_t s);
 void cvt_f2d(const float* x, double* y, int64_t n, hipStream_t s);
 template <typename T> void vfill(T* x, T v, int64_t n, hipStream_t s);
 template <typename T> void vcopy(const T* x, T* y, int64_t n, hipStream_t s);

@@ -10,6 +10,7 @@
 //  * the trilinear (Q1) vertex <-> DG node transfers and the Galerkin
 //    product of the potential block onto the Q1 vertex space.
 #include <algorithm>
+#include <type_traits>
 
 #include "dg_device.hpp"
 #include "kernels_block.hpp"
@@ -994,26 +995,81 @@ __global__ void __launch_bounds__(BT) k_ilu_bwdT(const T* __restrict__ blk, cons
 // ===========================================================================
 // Block sparse products.  y_i = alpha * sum_s A_{i,s} x_{nbr(s)} + beta * b_i
 // ===========================================================================
+// Potential-block kernels (block sparse product, block-diagonal apply, fused
+// Chebyshev step) read the potential block and its inverse diagonal blocks.
+// In single precision, blocks of up to 32 rows are stored with every row
+// padded to LD = a multiple of four floats (zeros in the padding), so that a
+// lane reads four consecutive entries of a row with one 16-byte load and a
+// work-group's loads cover whole cache lines; eight lanes share a row (lanes
+// with part >= LD / 4 hold zeros).  Double precision and larger blocks keep
+// unpadded rows (LD = NB) and four lanes per row.
+template <typename T, int NB>
+struct PotRows {
+  static constexpr bool VEC = std::is_same<T, float>::value && NB <= 32;
+  static constexpr int LD = VEC ? ((NB + 3) & ~3) : NB;
+  static constexpr int QV = LD / 4;
+};
+
+__device__ inline float dot4(const float4& a, const float4& b) {
+  return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
+}
+__device__ inline float sum8(float v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 4, 64);
+  return v;
+}
+__device__ inline float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+
 template <typename T, int NB, int DIM>
 __global__ void __launch_bounds__(BT) k_bspmv(const T* __restrict__ blk, const int* __restrict__ nbr,
                                               const T* __restrict__ x, const T* __restrict__ b, T alpha,
                                               T beta, T* __restrict__ y) {
   constexpr int NSLOT = 2 * DIM + 1;
-  __shared__ T xs[NSLOT][NB];
-  const int tid = threadIdx.x, row = tid >> 2, part = tid & 3;
+  using PR = PotRows<T, NB>;
+  const int tid = threadIdx.x;
   const int64_t i = blockIdx.x;
-  int nb[NSLOT];
-  nb[0] = int(i);
-  for (int s = 0; s < 2 * DIM; ++s) nb[1 + s] = nbr[i * 2 * DIM + s];
-  for (int idx = tid; idx < NB; idx += BT)
-    for (int s = 0; s < NSLOT; ++s) xs[s][idx] = nb[s] >= 0 ? x[int64_t(nb[s]) * NB + idx] : T(0);
-  __syncthreads();
-  const T* bi = blk + i * NSLOT * NB * NB;
-  if (row < NB) {
-    T acc = T(0);
-    for (int s = 0; s < NSLOT; ++s)
-      if (nb[s] >= 0) acc += row_dot4<T, NB>(bi + int64_t(s) * NB * NB, xs[s], row, part);
-    if (part == 0) y[i * NB + row] = alpha * acc + (b ? beta * b[i * NB + row] : T(0));
+  if constexpr (PR::VEC) {
+    constexpr int LD = PR::LD, QV = PR::QV;
+    __shared__ __align__(16) float xv[NSLOT][LD];
+    const int row = tid >> 3, part = tid & 7;
+    const bool on = row < NB && part < QV;
+    const float* bi = blk + i * NSLOT * NB * LD + row * LD + 4 * part;
+    float4 mr[NSLOT];
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) mr[s] = on ? ld4(bi + s * NB * LD) : make_float4(0.f, 0.f, 0.f, 0.f);
+    int nb[NSLOT];
+    nb[0] = int(i);
+    for (int s = 0; s < 2 * DIM; ++s) nb[1 + s] = nbr[i * 2 * DIM + s];
+    for (int idx = tid; idx < NSLOT * LD; idx += BT) {
+      const int sl = idx / LD, c = idx - sl * LD;
+      xv[sl][c] = (c < NB && nb[sl] >= 0) ? x[int64_t(nb[sl]) * NB + c] : 0.f;
+    }
+    __syncthreads();
+    float acc = 0.f;
+    if (on) {
+#pragma unroll
+      for (int s = 0; s < NSLOT; ++s)
+        if (nb[s] >= 0) acc += dot4(mr[s], ld4(&xv[s][4 * part]));
+    }
+    acc = sum8(acc);
+    if (row < NB && part == 0) y[i * NB + row] = alpha * acc + (b ? beta * b[i * NB + row] : 0.f);
+  } else {
+    __shared__ T xs[NSLOT][NB];
+    const int row = tid >> 2, part = tid & 3;
+    int nb[NSLOT];
+    nb[0] = int(i);
+    for (int s = 0; s < 2 * DIM; ++s) nb[1 + s] = nbr[i * 2 * DIM + s];
+    for (int idx = tid; idx < NB; idx += BT)
+      for (int s = 0; s < NSLOT; ++s) xs[s][idx] = nb[s] >= 0 ? x[int64_t(nb[s]) * NB + idx] : T(0);
+    __syncthreads();
+    const T* bi = blk + i * NSLOT * NB * NB;
+    if (row < NB) {
+      T acc = T(0);
+      for (int s = 0; s < NSLOT; ++s)
+        if (nb[s] >= 0) acc += row_dot4<T, NB>(bi + int64_t(s) * NB * NB, xs[s], row, part);
+      if (part == 0) y[i * NB + row] = alpha * acc + (b ? beta * b[i * NB + row] : T(0));
+    }
   }
 }
 
@@ -1021,14 +1077,28 @@ __global__ void __launch_bounds__(BT) k_bspmv(const T* __restrict__ blk, const i
 template <typename T, int NB>
 __global__ void __launch_bounds__(BT) k_bdiag(const T* __restrict__ dinv, const T* __restrict__ x,
                                               T* __restrict__ y) {
-  __shared__ T xs[NB];
-  const int tid = threadIdx.x, row = tid >> 2, part = tid & 3;
+  using PR = PotRows<T, NB>;
+  const int tid = threadIdx.x;
   const int64_t i = blockIdx.x;
-  for (int idx = tid; idx < NB; idx += BT) xs[idx] = x[i * NB + idx];
-  __syncthreads();
-  if (row < NB) {
-    const T v = row_dot4<T, NB>(dinv + i * NB * NB, xs, row, part);
-    if (part == 0) y[i * NB + row] = v;
+  if constexpr (PR::VEC) {
+    constexpr int LD = PR::LD, QV = PR::QV;
+    __shared__ __align__(16) float xv[LD];
+    const int row = tid >> 3, part = tid & 7;
+    const bool on = row < NB && part < QV;
+    const float4 dr = on ? ld4(dinv + (i * NB + row) * LD + 4 * part) : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int idx = tid; idx < LD; idx += BT) xv[idx] = idx < NB ? x[i * NB + idx] : 0.f;
+    __syncthreads();
+    const float v = sum8(on ? dot4(dr, ld4(&xv[4 * part])) : 0.f);
+    if (row < NB && part == 0) y[i * NB + row] = v;
+  } else {
+    __shared__ T xs[NB];
+    const int row = tid >> 2, part = tid & 3;
+    for (int idx = tid; idx < NB; idx += BT) xs[idx] = x[i * NB + idx];
+    __syncthreads();
+    if (row < NB) {
+      const T v = row_dot4<T, NB>(dinv + i * NB * NB, xs, row, part);
+      if (part == 0) y[i * NB + row] = v;
+    }
   }
 }
 
@@ -1735,78 +1805,129 @@ template void launch_ilu_dataflow<float>(int, int, int, const float*, const int*
 //   d = c1 * Dinv r + c2 * dprev   (dprev null: no second term)
 //   x_out = x_in + d        (x_in null: x_out = d)
 // with optional stores of r and d.  One work-group per element; x_out must not
-// alias u (the neighbours read u).
+// alias u (the neighbours read u).  Row layout and lane mapping as for
+// k_bspmv (padded single-precision rows for blocks of up to 32 rows).
 template <typename T, int NB, int DIM>
 __global__ void __launch_bounds__(BT) k_cheb_blk(const T* __restrict__ blk, const int* __restrict__ nbr,
                                                  const T* __restrict__ dinv, const T* u, const T* base,
                                                  const T* dprev, const T* x_in, T c1, T c2, T* r_out, T* d_out,
                                                  T* x_out) {
   constexpr int NSLOT = 2 * DIM + 1;
-  __shared__ T xs[NSLOT][NB];
-  __shared__ T rs[NB];
-  const int tid = threadIdx.x, row = tid >> 2, part = tid & 3;
+  using PR = PotRows<T, NB>;
+  const int tid = threadIdx.x;
   const int64_t i = blockIdx.x;
-  int nb[NSLOT];
-  nb[0] = int(i);
-  for (int s = 0; s < 2 * DIM; ++s) nb[1 + s] = nbr[i * 2 * DIM + s];
-  if (u) {
-    for (int idx = tid; idx < NB; idx += BT)
-      for (int s = 0; s < NSLOT; ++s) xs[s][idx] = nb[s] >= 0 ? u[int64_t(nb[s]) * NB + idx] : T(0);
-  }
-  const T* bi = blk + i * NSLOT * NB * NB;
-  constexpr int QL = (NB + 3) / 4;
-  // small blocks: every row part of all blocks is fetched before any product
-  // (loads in flight together); large blocks stream block by block
-  constexpr bool PRE = NSLOT * QL * int(sizeof(T)) <= 256;
-  if constexpr (PRE) {
-    T m[NSLOT][QL];
+  if constexpr (PR::VEC) {
+    constexpr int LD = PR::LD, QV = PR::QV;
+    __shared__ __align__(16) float xv[NSLOT][LD];
+    __shared__ __align__(16) float rv[LD];
+    const int row = tid >> 3, part = tid & 7;
+    const bool on = row < NB && part < QV;
+    // the block rows and the inverse diagonal row go out first: they do not
+    // depend on the neighbour table
+    const float* bi = blk + i * NSLOT * NB * LD + row * LD + 4 * part;
+    float4 mr[NSLOT];
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s)
-#pragma unroll
-      for (int c = 0; c < QL; ++c) {
-        const int cc = part * QL + c;
-        m[s][c] = (u && row < NB && cc < NB && nb[s] >= 0) ? bi[int64_t(s) * NB * NB + row * NB + cc] : T(0);
+      mr[s] = (u && on) ? ld4(bi + s * NB * LD) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 dr = on ? ld4(dinv + (i * NB + row) * LD + 4 * part) : make_float4(0.f, 0.f, 0.f, 0.f);
+    int nb[NSLOT];
+    nb[0] = int(i);
+    for (int s = 0; s < 2 * DIM; ++s) nb[1 + s] = nbr[i * 2 * DIM + s];
+    if (u) {
+      for (int idx = tid; idx < NSLOT * LD; idx += BT) {
+        const int sl = idx / LD, c = idx - sl * LD;
+        xv[sl][c] = (c < NB && nb[sl] >= 0) ? u[int64_t(nb[sl]) * NB + c] : 0.f;
       }
-    if (u) __syncthreads();
-    if (row < NB) {
-      T acc = T(0);
-      if (u) {  // without u the LDS operand is not loaded (and the products vanish)
-#pragma unroll
-        for (int s = 0; s < NSLOT; ++s)
-#pragma unroll
-          for (int c = 0; c < QL; ++c) acc += m[s][c] * xs[s][part * QL + c < NB ? part * QL + c : 0];
-        acc += __shfl_xor(acc, 1, 64);
-        acc += __shfl_xor(acc, 2, 64);
-      }
-      if (part == 0) {
-        const T r = base[i * NB + row] - acc;
-        rs[row] = r;
-        if (r_out) r_out[i * NB + row] = r;
-      }
+      __syncthreads();
     }
-  } else {
-    if (u) __syncthreads();
-    if (row < NB) {
-      T acc = T(0);
-      if (u)
-        for (int s = 0; s < NSLOT; ++s)
-          if (nb[s] >= 0) acc += row_dot4<T, NB>(bi + int64_t(s) * NB * NB, xs[s], row, part);
-      if (part == 0) {
-        const T r = base[i * NB + row] - acc;
-        rs[row] = r;
-        if (r_out) r_out[i * NB + row] = r;
-      }
+    float acc = 0.f;
+    if (u && on) {
+#pragma unroll
+      for (int s = 0; s < NSLOT; ++s)
+        if (nb[s] >= 0) acc += dot4(mr[s], ld4(&xv[s][4 * part]));
     }
-  }
-  __syncthreads();
-  if (row < NB) {
-    const T z = row_dot4<T, NB>(dinv + i * NB * NB, rs, row, part);
-    if (part == 0) {
+    acc = sum8(acc);
+    if (row < NB && part == 0) {
+      const float r = base[i * NB + row] - acc;
+      rv[row] = r;
+      if (r_out) r_out[i * NB + row] = r;
+    }
+    if (tid < LD - NB) rv[NB + tid] = 0.f;
+    __syncthreads();
+    const float z = sum8(on ? dot4(dr, ld4(&rv[4 * part])) : 0.f);
+    if (row < NB && part == 0) {
       const int64_t k = i * NB + row;
-      T d = c1 * z;
+      float d = c1 * z;
       if (dprev) d += c2 * dprev[k];
       if (d_out) d_out[k] = d;
-      x_out[k] = (x_in ? x_in[k] : T(0)) + d;
+      x_out[k] = (x_in ? x_in[k] : 0.f) + d;
+    }
+  } else {
+    __shared__ T xs[NSLOT][NB];
+    __shared__ T rs[NB];
+    const int row = tid >> 2, part = tid & 3;
+    int nb[NSLOT];
+    nb[0] = int(i);
+    for (int s = 0; s < 2 * DIM; ++s) nb[1 + s] = nbr[i * 2 * DIM + s];
+    if (u) {
+      for (int idx = tid; idx < NB; idx += BT)
+        for (int s = 0; s < NSLOT; ++s) xs[s][idx] = nb[s] >= 0 ? u[int64_t(nb[s]) * NB + idx] : T(0);
+    }
+    const T* bi = blk + i * NSLOT * NB * NB;
+    constexpr int QL = (NB + 3) / 4;
+    // small blocks: every row part of all blocks is fetched before any product
+    // (loads in flight together); large blocks stream block by block
+    constexpr bool PRE = NSLOT * QL * int(sizeof(T)) <= 256;
+    if constexpr (PRE) {
+      T m[NSLOT][QL];
+#pragma unroll
+      for (int s = 0; s < NSLOT; ++s)
+#pragma unroll
+        for (int c = 0; c < QL; ++c) {
+          const int cc = part * QL + c;
+          m[s][c] = (u && row < NB && cc < NB && nb[s] >= 0) ? bi[int64_t(s) * NB * NB + row * NB + cc] : T(0);
+        }
+      if (u) __syncthreads();
+      if (row < NB) {
+        T acc = T(0);
+        if (u) {  // without u the LDS operand is not loaded (and the products vanish)
+#pragma unroll
+          for (int s = 0; s < NSLOT; ++s)
+#pragma unroll
+            for (int c = 0; c < QL; ++c) acc += m[s][c] * xs[s][part * QL + c < NB ? part * QL + c : 0];
+          acc += __shfl_xor(acc, 1, 64);
+          acc += __shfl_xor(acc, 2, 64);
+        }
+        if (part == 0) {
+          const T r = base[i * NB + row] - acc;
+          rs[row] = r;
+          if (r_out) r_out[i * NB + row] = r;
+        }
+      }
+    } else {
+      if (u) __syncthreads();
+      if (row < NB) {
+        T acc = T(0);
+        if (u)
+          for (int s = 0; s < NSLOT; ++s)
+            if (nb[s] >= 0) acc += row_dot4<T, NB>(bi + int64_t(s) * NB * NB, xs[s], row, part);
+        if (part == 0) {
+          const T r = base[i * NB + row] - acc;
+          rs[row] = r;
+          if (r_out) r_out[i * NB + row] = r;
+        }
+      }
+    }
+    __syncthreads();
+    if (row < NB) {
+      const T z = row_dot4<T, NB>(dinv + i * NB * NB, rs, row, part);
+      if (part == 0) {
+        const int64_t k = i * NB + row;
+        T d = c1 * z;
+        if (dprev) d += c2 * dprev[k];
+        if (d_out) d_out[k] = d;
+        x_out[k] = (x_in ? x_in[k] : T(0)) + d;
+      }
     }
   }
 }

@@ -36,6 +36,12 @@ void launch_ilu_dataflow(int kind, int nb, int dim, const T* blk, const int* nbr
 void launch_ilu_dataflow_packed(int kind, int nb, int dim, const float* blk, const int* nbr, const int* order,
                                 int64_t E, int nfields, int64_t bstride, int64_t vstride, const float* in, float* out,
                                 uint64_t* wp, int* err, int spin_limit, int grid, hipStream_t s);
+// Row stride of the potential block and of its inverse diagonal blocks as
+// launch_bspmv, launch_bdiag and launch_cheb_blk read them: single-precision
+// blocks of up to 32 rows have rows padded to a multiple of four floats (zeros
+// in the padding); all others are stored unpadded.
+inline int pot_ld(int nb, bool f32) { return (f32 && nb <= 32) ? ((nb + 3) & ~3) : nb; }
+// y = alpha A x + beta b over the element-block graph (block rows of pot_ld)
 template <typename T>
 void launch_bspmv(int nb, int dim, int64_t E, const T* blk, const int* nbr, const T* x, const T* b, T alpha,
                   T beta, T* y, hipStream_t s);

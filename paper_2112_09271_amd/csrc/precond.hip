@@ -48,9 +48,10 @@ struct Precond {
   int nslot = 0;
   int64_t bsz = 0;                  // doubles per block = nb * nb
   DevBuf<double> blk;               // [m][E][nslot][nb][nb]
-  DevBuf<float> blk32;
+  DevBuf<float> blk32;              // concentration fields only: [m-1][E][nslot][nb][nb]
+  DevBuf<float> phi32;              // potential field: [E][nslot][nb][ld32], ld32 = pot_ld(nb, true)
   DevBuf<double> dinv_phi;          // [E][nb][nb]
-  DevBuf<float> dinv_phi32;
+  DevBuf<float> dinv_phi32;         // [E][nb][ld32]
   double lmax0 = 1.0;
   // hyperplane levels of the lexicographic element order
   std::vector<int64_t> lev_ptr;
@@ -288,7 +289,6 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     P.assembled = true;
     return;
   }
-  if (f32) P.blk32.alloc(P.blk.n);
   if (phi) {
     // potential block: element-diagonal inverses (block-Jacobi smoother)
     P.dinv_phi.alloc(size_t(c.E * P.bsz));
@@ -336,9 +336,11 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     ensure_work(c, P);
     clk.mark("work vectors");
     if (f32) {
-      cvt_d2f(P.blk.p, P.blk32.p, per_field, s);
-      P.dinv_phi32.alloc(P.dinv_phi.n);
-      cvt_d2f(P.dinv_phi.p, P.dinv_phi32.p, int64_t(P.dinv_phi.n), s);
+      const int ld32 = pot_ld(c.nb, true);
+      P.phi32.alloc(size_t(c.E) * P.nslot * c.nb * ld32);
+      cvt_d2f_rows(P.blk.p, P.phi32.p, c.E * P.nslot * c.nb, c.nb, ld32, s);
+      P.dinv_phi32.alloc(size_t(c.E) * c.nb * ld32);
+      cvt_d2f_rows(P.dinv_phi.p, P.dinv_phi32.p, c.E * c.nb, c.nb, ld32, s);
       for (size_t l = 0; l < H.A.size(); ++l) {
         MgLevel& L = P.mg[l];
         upload_csr(L.A32, H.A[l], s);
@@ -353,7 +355,7 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
       P.cinv32.upload(ci, s);
       ensure_work32(c, P);
       clk.mark("float copies (phi)");
-      P.lmax0 = lmax_level0<float>(c, P, s, P.blk32.p, P.dinv_phi32.p, P.wf[0]->p, P.wf[1]->p);
+      P.lmax0 = lmax_level0<float>(c, P, s, P.phi32.p, P.dinv_phi32.p, P.wf[0]->p, P.wf[1]->p);
     } else {
       P.lmax0 = lmax_level0<double>(c, P, s, P.blk.p, P.dinv_phi.p, P.wd[0]->p, P.wd[1]->p);
     }
@@ -374,7 +376,8 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     }
     clk.mark("ilu factor");
     if (f32) {
-      cvt_d2f(P.blk.p + per_field, P.blk32.p + per_field, (c.m - 1) * per_field, s);
+      P.blk32.alloc(size_t((c.m - 1) * per_field));
+      cvt_d2f(P.blk.p + per_field, P.blk32.p, (c.m - 1) * per_field, s);
       if (P.wf.empty() || !P.vN32.p) ensure_work32(c, P);
       clk.mark("float copies (conc)");
     }
@@ -401,6 +404,7 @@ template <typename T> struct Sel;
 template <> struct Sel<double> {
   static double* blk(Precond& P) { return P.blk.p; }
   static double* dinv(Precond& P) { return P.dinv_phi.p; }
+  static double* cblk(Precond& P, int64_t fstride) { return P.blk.p + fstride; }
   static DevCsr<double>& A(MgLevel& L) { return L.A; }
   static DevCsr<double>& Pm(MgLevel& L) { return L.P; }
   static DevCsr<double>& R(MgLevel& L) { return L.R; }
@@ -412,7 +416,8 @@ template <> struct Sel<double> {
   static double* tN(Precond& P) { return P.tN.p; }
 };
 template <> struct Sel<float> {
-  static float* blk(Precond& P) { return P.blk32.p; }
+  static float* blk(Precond& P) { return P.phi32.p; }
+  static float* cblk(Precond& P, int64_t) { return P.blk32.p; }
   static float* dinv(Precond& P) { return P.dinv_phi32.p; }
   static DevCsr<float>& A(MgLevel& L) { return L.A32; }
   static DevCsr<float>& Pm(MgLevel& L) { return L.P32; }
@@ -521,7 +526,7 @@ struct Mg {
 template <typename T>
 static void ilu_solve(dgnp_ctx& c, Precond& P, bool transpose, const T* in, T* out, hipStream_t s) {
   const int64_t fstride = c.E * P.nslot * P.bsz;
-  const T* blk = Sel<T>::blk(P) + fstride;
+  const T* blk = Sel<T>::cblk(P, fstride);
   const int L = int(P.lev_ptr.size()) - 1;
   const int nf = c.m - 1;
   const bool f32 = std::is_same<T, float>::value;
@@ -621,7 +626,7 @@ void phi_block_apply(dgnp_ctx& c, const double* x, double* y, hipStream_t s) {
 }
 void phi_block_apply(dgnp_ctx& c, const float* x, float* y, hipStream_t s) {
   DGNP_REQUIRE(c.pc && c.pc->phi32_ok, DGNP_E_STATE, "single-precision potential block not set up");
-  launch_bspmv<float>(c.nb, c.dim, c.E, c.pc->blk32.p, c.d_nbr.p, x, nullptr, 1.0f, 0.0f, y, s);
+  launch_bspmv<float>(c.nb, c.dim, c.E, c.pc->phi32.p, c.d_nbr.p, x, nullptr, 1.0f, 0.0f, y, s);
 }
 
 // potential-block V-cycle alone (used for the initial potential solve)
