@@ -111,6 +111,23 @@ void vscale_dual(double a, const double* x, double* y, float* y32, int64_t n, hi
   if (n <= 0) return;
   hipLaunchKernelGGL(k_scale_dual, dim3(grid_for(n)), dim3(VB), 0, s, a, x, y, y32, n);
 }
+// y = x / sqrt(q) with q = *ss read on the device (y = 0 when q <= 0), and
+// y32 = float(y) when y32 is not null; 1 / sqrt(q) is formed exactly as the
+// host forms it from the same q (correctly rounded square root and division)
+__global__ void k_scale_rsqrt(const double* __restrict__ ss, const double* __restrict__ x, double* __restrict__ y,
+                              float* __restrict__ y32, int64_t n) {
+  const double q = *ss;
+  const double a = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
+    const double v = a * x[i];
+    y[i] = v;
+    if (y32) y32[i] = float(v);
+  }
+}
+void vscale_rsqrt(const double* ss_dev, const double* x, double* y, float* y32, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_scale_rsqrt, dim3(grid_for(n)), dim3(VB), 0, s, ss_dev, x, y, y32, n);
+}
 template <typename T>
 void vsub(const T* x, const T* y, T* z, int64_t n, hipStream_t s) {
   if (n <= 0) return;

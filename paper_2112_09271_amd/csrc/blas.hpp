@@ -27,6 +27,8 @@ void vdots_into(const double* V, int64_t ldv, int k, const double* w, int64_t n,
 void vdots_into_f(const double* V, int64_t ldv, int k, const float* w, double* w64, int64_t n, double* out,
                   double* scratch, hipStream_t s);
 void vscale_dual(double a, const double* x, double* y, float* y32, int64_t n, hipStream_t s);  // y = a x, y32 = (float) y
+// y = x / sqrt(*ss_dev) (0 if *ss_dev <= 0), y32 = (float) y unless null
+void vscale_rsqrt(const double* ss_dev, const double* x, double* y, float* y32, int64_t n, hipStream_t s);
 // w -= sum_j h[j] V_j
 void vmaxpy(const double* V, int64_t ldv, int k, const double* h_dev, double* w, int64_t n,
             hipStream_t s);

@@ -838,14 +838,31 @@ __global__ void __launch_bounds__(BT) k_ilu_scale_lower(double* __restrict__ blk
 // Level-scheduled solves.  Four threads per block row, each handling a
 // contiguous quarter of the row; partial sums combined with lane shuffles.
 // ===========================================================================
+// Single-precision blocks whose rows split into four 16-byte aligned parts
+// (NB a multiple of 16): a lane reads its part of a row with 16-byte loads.
+template <typename T, int NB>
+struct VecRows {
+  static constexpr bool on = std::is_same<T, float>::value && NB % 16 == 0;
+};
+
 template <typename T, int NB>
 __device__ inline T row_dot4(const T* __restrict__ M, const T* x, int r, int part) {
   constexpr int QL = (NB + 3) / 4;
   T acc = T(0);
   const int c0 = part * QL;
+  if constexpr (VecRows<T, NB>::on) {
+    // QL a multiple of 4 floats: each lane's part of the row is 16-byte aligned
+    const float4* mp = reinterpret_cast<const float4*>(M + r * NB + c0);
 #pragma unroll
-  for (int c = 0; c < QL; ++c)
-    if (c0 + c < NB) acc += M[r * NB + c0 + c] * x[c0 + c];
+    for (int k = 0; k < QL / 4; ++k) {
+      const float4 v = mp[k];
+      acc += v.x * x[c0 + 4 * k] + v.y * x[c0 + 4 * k + 1] + v.z * x[c0 + 4 * k + 2] + v.w * x[c0 + 4 * k + 3];
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < QL; ++c)
+      if (c0 + c < NB) acc += M[r * NB + c0 + c] * x[c0 + c];
+  }
   acc += __shfl_xor(acc, 1, 64);
   acc += __shfl_xor(acc, 2, 64);
   return acc;
@@ -1405,6 +1422,129 @@ __global__ void __launch_bounds__(BT) k_ilu_dfp(const float* __restrict__ blk, c
   }
 }
 
+// Line variant of the single-precision dataflow sweeps: a work-group walks a
+// line of elements along axis ax in the sweep's direction, so the neighbour
+// along the line is the element it has just computed (kept in LDS) and only
+// the neighbours across lines are polled.  Lines are ordered by the level of
+// their first element, work-group b takes lines b, b + G, ... (reversed for
+// the backward sweep), which keeps the schedule deadlock-free on a resident
+// grid as for the element variant.  The block rows of the next element are
+// fetched while the current element waits for its neighbours and computes.
+// line_first: first element of each line (lowest coordinate along ax); the
+// line's elements are line_first + p * lstride, p = 0 .. len - 1.
+template <int NB, int DIM, int KIND>
+__global__ void __launch_bounds__(BT) k_ilu_dfl(const float* __restrict__ blk, const int* __restrict__ nbr,
+                                                const int* __restrict__ line_first, int nline, int len,
+                                                int64_t lstride, int ax, const float* in, float* out,
+                                                int64_t bstride, int64_t vstride, uint64_t* wp, int* err,
+                                                int spin_limit) {
+  constexpr int NSLOT = 2 * DIM + 1;
+  constexpr int QL = (NB + 3) / 4;
+  blk += blockIdx.y * bstride;
+  in += blockIdx.y * vstride;
+  out += blockIdx.y * vstride;
+  wp += blockIdx.y * vstride;
+  __shared__ float xs[DIM + 1][NB];  // [0]: own input; [1 + d]: neighbour across direction d
+  __shared__ int s_abort;
+  const int tid = threadIdx.x, row = tid >> 2, part = tid & 3;
+  if (tid == 0) s_abort = 0;
+  // rows of the element's own blocks that the sweep reads: D^{-1} and the
+  // lower blocks (forward) or the upper blocks (backward)
+  auto fetch = [&](int64_t e, float (&m)[DIM + 1][QL]) {
+    const float* be = blk + e * NSLOT * NB * NB;
+#pragma unroll
+    for (int b = 0; b <= DIM; ++b) {
+      const int slot = KIND == 0 ? (b == 0 ? 0 : 1 + 2 * (b - 1)) : (b == 0 ? 0 : 2 + 2 * (b - 1));
+      if constexpr (VecRows<float, NB>::on) {
+        const float4* mp = reinterpret_cast<const float4*>(be + int64_t(slot) * NB * NB + row * NB + part * QL);
+#pragma unroll
+        for (int k = 0; k < QL / 4; ++k) {
+          const float4 v = (row < NB && (KIND == 0 || b > 0)) ? mp[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+          m[b][4 * k] = v.x;
+          m[b][4 * k + 1] = v.y;
+          m[b][4 * k + 2] = v.z;
+          m[b][4 * k + 3] = v.w;
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < QL; ++c) {
+          const int cc = part * QL + c;
+          m[b][c] = (row < NB && cc < NB && (KIND == 0 || b > 0)) ? be[int64_t(slot) * NB * NB + row * NB + cc]
+                                                                    : 0.0f;
+        }
+      }
+    }
+  };
+  for (int c = blockIdx.x; c < nline; c += gridDim.x) {
+    const int64_t first = line_first[KIND == 0 ? c : nline - 1 - c];
+    const int64_t step = KIND == 0 ? lstride : -lstride;
+    const int64_t start = KIND == 0 ? first : first + int64_t(len - 1) * lstride;
+    float m[DIM + 1][QL], mn[DIM + 1][QL];
+    fetch(start, m);
+    for (int q = 0; q < len; ++q) {
+      const int64_t i = start + q * step;
+      if (q + 1 < len) fetch(i + step, mn);
+      for (int idx = tid; idx < NB; idx += BT) xs[0][idx] = in[i * NB + idx];
+      const unsigned target = unsigned(ld_dev(wp + i * NB) >> 32) + 1u;
+      for (int idx = tid; idx < DIM * NB; idx += BT) {
+        const int d = idx / NB, l = idx % NB;
+        if (d == ax) {
+          if (q == 0) xs[1 + d][l] = 0.0f;  // the line starts at the domain boundary
+          continue;                          // otherwise: the previous element's result
+        }
+        const int j = nbr[i * 2 * DIM + 2 * d + KIND];
+        float v = 0.0f;
+        if (j >= 0) {
+          const uint64_t* src = wp + int64_t(j) * NB + l;
+          uint64_t word = ld_dev(src);
+          int spins = 0;
+          while (unsigned(word >> 32) != target) {
+            if (++spins > spin_limit) {
+              st_dev(err, 1);
+              s_abort = 1;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            word = ld_dev(src);
+          }
+          v = __uint_as_float(unsigned(word));
+        }
+        xs[1 + d][l] = v;
+      }
+      __syncthreads();
+      if (s_abort) return;
+      float acc = 0.0f;
+      if (row < NB) {
+        if constexpr (KIND == 0) {
+#pragma unroll
+          for (int cq = 0; cq < QL; ++cq) acc += m[0][cq] * xs[0][part * QL + cq < NB ? part * QL + cq : 0];
+        }
+#pragma unroll
+        for (int b = 1; b <= DIM; ++b) {
+          float sb = 0.0f;
+#pragma unroll
+          for (int cq = 0; cq < QL; ++cq) sb += m[b][cq] * xs[b][part * QL + cq < NB ? part * QL + cq : 0];
+          acc -= sb;
+        }
+        acc += __shfl_xor(acc, 1, 64);
+        acc += __shfl_xor(acc, 2, 64);
+        if (KIND == 1) acc = xs[0][row] + acc;
+      }
+      __syncthreads();  // every read of xs is done before the next element's inputs land there
+      if (row < NB && part == 0) {
+        st_dev(wp + i * NB + row, (uint64_t(target) << 32) | uint64_t(__float_as_uint(acc)));
+        out[i * NB + row] = acc;
+        xs[1 + ax][row] = acc;
+      }
+#pragma unroll
+      for (int b = 0; b <= DIM; ++b)
+#pragma unroll
+        for (int cq = 0; cq < QL; ++cq) m[b][cq] = mn[b][cq];
+    }
+    __syncthreads();  // the last result of the line is in xs before the next line clears it
+  }
+}
+
 // ===========================================================================
 // host launchers
 // ===========================================================================
@@ -1789,6 +1929,74 @@ void launch_ilu_dataflow_packed(int kind, int nb, int dim, const float* blk, con
       case 4: dfp_t<4, 2>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
       case 9: dfp_t<9, 2>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
       case 16: dfp_t<16, 2>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
+      default: throw Error(DGNP_E_ARG, "unsupported block size");
+    }
+  }
+  DGNP_HIP(hipGetLastError());
+}
+
+template <int NB, int DIM>
+static void dfl_t(int kind, const float* blk, const int* nbr, const int* line_first, int nline, int len,
+                  int64_t lstride, int ax, int nfields, int64_t bstride, int64_t vstride, const float* in,
+                  float* out, uint64_t* wp, int* err, int spin_limit, int grid, hipStream_t s) {
+  const dim3 g = dim3(unsigned(grid), unsigned(nfields)), b = dim3(BT);
+  if (kind == 0)
+    hipLaunchKernelGGL((k_ilu_dfl<NB, DIM, 0>), g, b, 0, s, blk, nbr, line_first, nline, len, lstride, ax, in, out,
+                       bstride, vstride, wp, err, spin_limit);
+  else
+    hipLaunchKernelGGL((k_ilu_dfl<NB, DIM, 1>), g, b, 0, s, blk, nbr, line_first, nline, len, lstride, ax, in, out,
+                       bstride, vstride, wp, err, spin_limit);
+}
+
+template <int NB, int DIM>
+static int dfl_resident(int nfields) {
+  int dev = 0, ncu = 0;
+  DGNP_HIP(hipGetDevice(&dev));
+  DGNP_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  int occ[2] = {0, 0};
+  DGNP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], (k_ilu_dfl<NB, DIM, 0>), BT, 0));
+  DGNP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], (k_ilu_dfl<NB, DIM, 1>), BT, 0));
+  return (ncu * std::min(occ[0], occ[1])) / (2 * nfields);  // half the resident capacity per field
+}
+
+int ilu_lines_grid(int nb, int dim, int nline, int nfields) {
+  int r = 0;
+  if (dim == 3) {
+    switch (nb) {
+      case 8: r = dfl_resident<8, 3>(nfields); break;
+      case 27: r = dfl_resident<27, 3>(nfields); break;
+      case 64: r = dfl_resident<64, 3>(nfields); break;
+      default: throw Error(DGNP_E_ARG, "unsupported block size");
+    }
+  } else {
+    switch (nb) {
+      case 4: r = dfl_resident<4, 2>(nfields); break;
+      case 9: r = dfl_resident<9, 2>(nfields); break;
+      case 16: r = dfl_resident<16, 2>(nfields); break;
+      default: throw Error(DGNP_E_ARG, "unsupported block size");
+    }
+  }
+  if (r < 1) throw Error(DGNP_E_HIP, "no resident work-groups for the line sweep");
+  return std::min(nline, r);
+}
+
+void launch_ilu_lines(int kind, int nb, int dim, const float* blk, const int* nbr, const int* line_first, int nline,
+                      int len, int64_t lstride, int ax, int nfields, int64_t bstride, int64_t vstride,
+                      const float* in, float* out, uint64_t* wp, int* err, int spin_limit, int grid, hipStream_t s) {
+  if (nline == 0 || nfields == 0) return;
+  if (ax < 0 || ax >= dim || grid < 1) throw Error(DGNP_E_ARG, "bad line sweep arguments");
+  if (dim == 3) {
+    switch (nb) {
+      case 8: dfl_t<8, 3>(kind, blk, nbr, line_first, nline, len, lstride, ax, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
+      case 27: dfl_t<27, 3>(kind, blk, nbr, line_first, nline, len, lstride, ax, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
+      case 64: dfl_t<64, 3>(kind, blk, nbr, line_first, nline, len, lstride, ax, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
+      default: throw Error(DGNP_E_ARG, "unsupported block size");
+    }
+  } else {
+    switch (nb) {
+      case 4: dfl_t<4, 2>(kind, blk, nbr, line_first, nline, len, lstride, ax, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
+      case 9: dfl_t<9, 2>(kind, blk, nbr, line_first, nline, len, lstride, ax, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
+      case 16: dfl_t<16, 2>(kind, blk, nbr, line_first, nline, len, lstride, ax, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
       default: throw Error(DGNP_E_ARG, "unsupported block size");
     }
   }

@@ -36,6 +36,13 @@ void launch_ilu_dataflow(int kind, int nb, int dim, const T* blk, const int* nbr
 void launch_ilu_dataflow_packed(int kind, int nb, int dim, const float* blk, const int* nbr, const int* order,
                                 int64_t E, int nfields, int64_t bstride, int64_t vstride, const float* in, float* out,
                                 uint64_t* wp, int* err, int spin_limit, int grid, hipStream_t s);
+// line sweeps (single precision, packed words as launch_ilu_dataflow_packed):
+// lines of `len` elements along axis ax, first elements line_first[0..nline)
+// ordered by level, element stride lstride; grid from ilu_lines_grid
+int ilu_lines_grid(int nb, int dim, int nline, int nfields);
+void launch_ilu_lines(int kind, int nb, int dim, const float* blk, const int* nbr, const int* line_first, int nline,
+                      int len, int64_t lstride, int ax, int nfields, int64_t bstride, int64_t vstride,
+                      const float* in, float* out, uint64_t* wp, int* err, int spin_limit, int grid, hipStream_t s);
 // Row stride of the potential block and of its inverse diagonal blocks as
 // launch_bspmv, launch_bdiag and launch_cheb_blk read them: single-precision
 // blocks of up to 32 rows have rows padded to a multiple of four floats (zeros

@@ -78,6 +78,12 @@ struct Precond {
   int df_grid[2] = {0, 0};  // double, float
   int df_spin = 1 << 22;
   bool df_on = true;
+  // single-precision line sweeps: lines along axis line_ax (the longest), one
+  // first element per line in level order
+  bool lines_on = false;
+  DevBuf<int> line_first;
+  int nline = 0, line_len = 0, line_ax = 0, line_grid = 0;
+  int64_t line_stride = 1;
   // numeric state: potential part (phi block, its inverse blocks, multigrid
   // hierarchy, lambda_max) and concentration part (BILU(0) factors), in double
   // and, for the mixed path, single precision
@@ -134,6 +140,40 @@ void precond_symbolic(dgnp_ctx& c) {
   DGNP_HIP(hipStreamSynchronize(c.stream));
   P.df_grid[0] = ilu_dataflow_grid<double>(c.nb, c.dim, c.E, nf);
   P.df_grid[1] = ilu_dataflow_grid<float>(c.nb, c.dim, c.E, nf);
+  // lines along the longest axis, ordered by the level of their first element
+  {
+    int ax = 0;
+    for (int d = 1; d < c.dim; ++d)
+      if (c.n[d] > c.n[ax]) ax = d;
+    const int n3[3] = {c.n[0], c.n[1], c.dim == 3 ? c.n[2] : 1};
+    const int64_t stride[3] = {1, n3[0], int64_t(n3[0]) * n3[1]};
+    const int o1 = ax == 0 ? 1 : 0, o2 = ax == 2 ? 1 : 2;
+    std::vector<std::vector<int>> bylev(size_t(n3[o1] + n3[o2] - 1));
+    for (int b = 0; b < n3[o2]; ++b)
+      for (int a = 0; a < n3[o1]; ++a) bylev[size_t(a + b)].push_back(int(a * stride[o1] + b * stride[o2]));
+    std::vector<int> first;
+    for (auto& v : bylev) first.insert(first.end(), v.begin(), v.end());
+    P.line_first.upload(first, c.stream);
+    P.nline = int(first.size());
+    P.line_len = n3[ax];
+    P.line_ax = ax;
+    P.line_stride = stride[ax];
+    P.line_grid = ilu_lines_grid(c.nb, c.dim, P.nline, nf);
+    // With narrow levels, 64-row blocks (p = 3) go by lines: the block rows of
+    // the next element stream in while the current one waits; smaller blocks
+    // keep the element order, whose waits are shorter.
+    P.lines_on = P.df_on && c.nb >= 64 && getenv("DGNP_DATAFLOW") == nullptr;
+    const char* sw = getenv("DGNP_ILU_SWEEP");  // "line", "element" or "level"
+    if (sw && std::string(sw) == "line") {
+      P.lines_on = true;
+    } else if (sw && std::string(sw) == "element") {
+      P.lines_on = false;
+      P.df_on = true;
+    } else if (sw && std::string(sw) == "level") {
+      P.lines_on = false;
+      P.df_on = false;
+    }
+  }
 }
 
 // Reports (and clears) a dataflow sweep that ended at its wait limit; the
@@ -533,6 +573,23 @@ static void ilu_solve(dgnp_ctx& c, Precond& P, bool transpose, const T* in, T* o
   static const char* names[4][2] = {{"ilu_fwd", "ilu_fwd_f32"}, {"ilu_bwd", "ilu_bwd_f32"},
                                     {"ilu_fwdT", "ilu_fwdT_f32"}, {"ilu_bwdT", "ilu_bwdT_f32"}};
   const int k0 = transpose ? 2 : 0;
+  if (!transpose && P.lines_on && f32) {
+    uint64_t* wp = P.df_wp.p;
+    const float* bf = reinterpret_cast<const float*>(blk);
+    {
+      ScopeTimer tm(c, names[0][1], s);
+      launch_ilu_lines(0, c.nb, c.dim, bf, c.d_nbr.p, P.line_first.p, P.nline, P.line_len, P.line_stride, P.line_ax,
+                       nf, fstride, c.Nf, reinterpret_cast<const float*>(in), reinterpret_cast<float*>(out), wp,
+                       P.df_err.p, P.df_spin, P.line_grid, s);
+    }
+    {
+      ScopeTimer tm(c, names[1][1], s);
+      launch_ilu_lines(1, c.nb, c.dim, bf, c.d_nbr.p, P.line_first.p, P.nline, P.line_len, P.line_stride, P.line_ax,
+                       nf, fstride, c.Nf, reinterpret_cast<const float*>(out), reinterpret_cast<float*>(out),
+                       wp + int64_t(nf) * c.Nf, P.df_err.p, P.df_spin, P.line_grid, s);
+    }
+    return;
+  }
   if (!transpose && P.df_on && f32) {
     uint64_t* wp = P.df_wp.p;
     const float* bf = reinterpret_cast<const float*>(blk);

@@ -76,10 +76,18 @@ struct Krylov {
   hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   uint64_t gepoch[2][2] = {{0, 0}, {0, 0}};
   int gpc[2][2] = {{-1, -1}, {-1, -1}};
+  // pinned host slots for the coefficients of two consecutive Arnoldi steps
+  // (h1[MAXV], h2[MAXV], |w|^2) and the events that mark their arrival
+  static constexpr size_t HSLOT = 2 * MAXV + 8;
+  double* hpin = nullptr;
+  hipEvent_t hev[2] = {nullptr, nullptr};
   ~Krylov() {
     for (auto& row : gexec)
       for (auto& g : row)
         if (g) (void)hipGraphExecDestroy(g);
+    if (hpin) (void)hipHostFree(hpin);
+    for (auto& e : hev)
+      if (e) (void)hipEventDestroy(e);
   }
 };
 
@@ -141,6 +149,11 @@ static Krylov& krylov(dgnp_ctx& c, int restart, bool f32) {
     K->restart = restart;
     K->n = c.N;
   }
+  if (!K->hpin) {
+    DGNP_HIP(hipHostMalloc(reinterpret_cast<void**>(&K->hpin), 2 * Krylov::HSLOT * sizeof(double),
+                           hipHostMallocDefault));
+    for (auto& e : K->hev) DGNP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
   if (f32 && !K->Z32.p) {
     K->Z32.alloc(size_t(restart) * c.N);
     K->v32.alloc(size_t(c.N));
@@ -171,7 +184,7 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
   const int64_t N = c.N;
   LinResult out;
   const size_t rs = static_cast<size_t>(restart);
-  std::vector<double> H((rs + 1) * rs), g(rs + 1), cs(rs), sn(rs), hbuf(2 * MAXV + 1), y(rs);
+  std::vector<double> H((rs + 1) * rs), g(rs + 1), cs(rs), sn(rs), y(rs);
   bool first = true;
   while (true) {
     // true FP64 residual
@@ -198,47 +211,59 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
       vaxpby<double>(1.0 / beta, K.r.p, 0.0, K.V.p, N, s);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
-    int j = 0;
-    bool done = false;
-    for (; j < restart && out.its < maxit; ++j) {
-      double* vj = K.V.p + int64_t(j) * N;
+    // device locations of the step's coefficients: classical Gram-Schmidt,
+    // twice, h1 and h2, then |w|^2
+    double* h1 = K.hd.p + reduce_scratch_size();
+    double* h2 = h1 + MAXV;
+    double* ww = h2 + MAXV;
+    double* part = K.hd.p;  // block partials of the reductions
+    // Queue Arnoldi step jj: (jj > 0) v_jj = w / |w| on the device, z_jj = P v_jj,
+    // w = Op z_jj, both Gram-Schmidt passes and |w|^2, and the copy of the
+    // coefficients to host slot jj % 2.  Step jj + 1 is queued before the host
+    // reads step jj, so the device never waits for the host's rotations; a step
+    // queued past convergence is discarded.
+    auto issue = [&](int jj) {
+      double* vj = K.V.p + int64_t(jj) * N;
       double* w = K.w.p;
-      // classical Gram-Schmidt, twice; coefficients stay on the device until one copy
-      double* h1 = K.hd.p + reduce_scratch_size();
-      double* h2 = h1 + MAXV;
-      double* ww = h2 + MAXV;
-      double* part = K.hd.p;  // block partials of the reductions
+      if (jj > 0) vscale_rsqrt(ww, w, vj, f32 ? K.v32.p : nullptr, N, s);
       if (f32) {
-        // K.v32 holds the single copy of v_j (written with the basis vector)
         pc_then_jac(c, K, true, transpose, pc_kind, s);
-        vcopy<float>(K.zt32.p, K.Z32.p + int64_t(j) * N, N, s);
+        vcopy<float>(K.zt32.p, K.Z32.p + int64_t(jj) * N, N, s);
       } else {
         vcopy<double>(vj, K.vt.p, N, s);
         pc_then_jac(c, K, false, transpose, pc_kind, s);
-        vcopy<double>(K.zt.p, K.Z.p + int64_t(j) * N, N, s);
+        vcopy<double>(K.zt.p, K.Z.p + int64_t(jj) * N, N, s);
       }
-      ScopeTimer tm(c, "cgs2", s);
-      if (f32)
-        vdots_into_f(K.V.p, N, j + 1, K.w32.p, w, N, h1, part, s);  // also widens w to double
-      else
-        vdots_into(K.V.p, N, j + 1, w, N, h1, part, s);
-      vmaxpy(K.V.p, N, j + 1, h1, w, N, s);
-      vdots_into(K.V.p, N, j + 1, w, N, h2, part, s);
-      vmaxpy(K.V.p, N, j + 1, h2, w, N, s);
-      vdots_into(w, 0, 1, w, N, ww, part, s);
-      DGNP_HIP(hipMemcpyAsync(hbuf.data(), h1, sizeof(double) * size_t(2 * MAXV + 1), hipMemcpyDeviceToHost, s));
-      DGNP_HIP(hipStreamSynchronize(s));
+      {
+        ScopeTimer tm(c, "cgs2", s);
+        if (f32)
+          vdots_into_f(K.V.p, N, jj + 1, K.w32.p, w, N, h1, part, s);  // also widens w to double
+        else
+          vdots_into(K.V.p, N, jj + 1, w, N, h1, part, s);
+        vmaxpy(K.V.p, N, jj + 1, h1, w, N, s);
+        vdots_into(K.V.p, N, jj + 1, w, N, h2, part, s);
+        vmaxpy(K.V.p, N, jj + 1, h2, w, N, s);
+        vdots_into(w, 0, 1, w, N, ww, part, s);
+      }
+      double* slot = K.hpin + size_t(jj % 2) * Krylov::HSLOT;
+      DGNP_HIP(hipMemcpyAsync(slot, h1, sizeof(double) * size_t(2 * MAXV + 1), hipMemcpyDeviceToHost, s));
+      DGNP_HIP(hipEventRecord(K.hev[jj % 2], s));
+    };
+    int j = 0;
+    bool done = false;
+    issue(0);
+    for (; j < restart && out.its < maxit; ++j) {
+      if (j + 1 < restart && out.its + 1 < maxit) issue(j + 1);
+      DGNP_HIP(hipEventSynchronize(K.hev[j % 2]));
+      const double* hb = K.hpin + size_t(j % 2) * Krylov::HSLOT;
       ++out.its;
       double* col = H.data() + size_t(j) * (restart + 1);
-      for (int i = 0; i <= j; ++i) col[i] = hbuf[size_t(i)] + hbuf[size_t(MAXV + i)];
-      const double hn = std::sqrt(std::max(hbuf[2 * MAXV], 0.0));
+      for (int i = 0; i <= j; ++i) col[i] = hb[size_t(i)] + hb[size_t(MAXV + i)];
+      const double hn = std::sqrt(std::max(hb[2 * MAXV], 0.0));
       col[j + 1] = hn;
-      if (!std::isfinite(hn)) throw Error(DGNP_E_NONFINITE, "non-finite Arnoldi vector");
-      if (hn > 0.0) {
-        if (f32)
-          vscale_dual(1.0 / hn, w, K.V.p + int64_t(j + 1) * N, K.v32.p, N, s);
-        else
-          vaxpby<double>(1.0 / hn, w, 0.0, K.V.p + int64_t(j + 1) * N, N, s);
+      if (!std::isfinite(hn)) {
+        DGNP_HIP(hipStreamSynchronize(s));
+        throw Error(DGNP_E_NONFINITE, "non-finite Arnoldi vector");
       }
       for (int i = 0; i < j; ++i) {
         const double t = cs[size_t(i)] * col[i] + sn[size_t(i)] * col[i + 1];
@@ -246,7 +271,10 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
         col[i] = t;
       }
       const double den = std::hypot(col[j], col[j + 1]);
-      if (den == 0.0) throw Error(DGNP_E_BREAKDOWN, "FGMRES breakdown");
+      if (den == 0.0) {
+        DGNP_HIP(hipStreamSynchronize(s));
+        throw Error(DGNP_E_BREAKDOWN, "FGMRES breakdown");
+      }
       cs[size_t(j)] = col[j] / den;
       sn[size_t(j)] = col[j + 1] / den;
       col[j] = den;

@@ -112,12 +112,56 @@ def test_dataflow_and_level_scheduled_sweeps_agree(name, monkeypatch):
             assert rel_err(a, b) <= tol, (prec, rep, rel_err(a, b))
 
 
+@pytest.mark.parametrize("name", ["cfg2t", "cfg3s", "cfg1"])
+def test_line_sweeps_agree_with_level_sweeps(name, monkeypatch):
+    """The single-precision line sweeps (a work-group walks a line of elements,
+    polling only the neighbours across lines) compute the same triangular solves
+    as the level-by-level launches, up to the order of the partial row sums; the
+    element-order dataflow sweeps may run between them on the same counters."""
+    from paper_2112_09271_amd.dgnp import DGNP_F32
+    monkeypatch.setenv("DGNP_ILU_SWEEP", "line")
+    cfg, _, g_ln = pair(name, with_oracle=False)
+    monkeypatch.setenv("DGNP_ILU_SWEEP", "level")
+    _, _, g_lv = pair(name, with_oracle=False)
+    monkeypatch.delenv("DGNP_ILU_SWEEP")
+    x = random_state(cfg)
+    for gp in (g_ln, g_lv):
+        gp.set_state(x, prec=DGNP_F32)
+    for rep in range(3):  # repeated sweeps reuse the packed sweep counts
+        r = random_vector(cfg, 51 + rep)
+        a = host(g_ln.precond_apply(r, prec=DGNP_F32))
+        b = host(g_lv.precond_apply(r, prec=DGNP_F32))
+        assert rel_err(a, b) <= 1e-5, (rep, rel_err(a, b))
+
+
 def test_dataflow_wait_limit_is_reported(monkeypatch):
     """A sweep whose waits run out (spin limit 0) ends every work-group and the
     solve reports an error instead of hanging; a new problem solves normally."""
     from paper_2112_09271_amd.dgnp import (DGNP_E_BREAKDOWN, DGNP_E_NOCONV, DGNP_E_NONFINITE, DGNP_F32,
                                            DgnpError)
     monkeypatch.setenv("DGNP_DATAFLOW", "1")
+    monkeypatch.setenv("DGNP_DATAFLOW_SPIN", "0")
+    cfg, _, gp = pair("cfg2t", with_oracle=False)
+    try:
+        x, st = gp.solve(prec=DGNP_F32, max_newton=2)
+        failed = False
+    except DgnpError as e:
+        assert e.code in (DGNP_E_BREAKDOWN, DGNP_E_NONFINITE, DGNP_E_NOCONV), e
+        failed = True
+    gp.close()
+    monkeypatch.delenv("DGNP_DATAFLOW_SPIN")
+    _, _, g2 = pair("cfg2t", with_oracle=False)
+    x, st = g2.solve(prec=DGNP_F32)
+    assert st.status == 0 and st.res_final <= 1e-8 * st.res0
+    print("first solve failed:", failed)
+
+
+def test_line_sweep_wait_limit_is_reported(monkeypatch):
+    """Line sweeps whose waits run out (spin limit 0) end every work-group and the
+    solve reports an error instead of hanging; a new problem solves normally."""
+    from paper_2112_09271_amd.dgnp import (DGNP_E_BREAKDOWN, DGNP_E_NOCONV, DGNP_E_NONFINITE, DGNP_F32,
+                                           DgnpError)
+    monkeypatch.setenv("DGNP_ILU_SWEEP", "line")
     monkeypatch.setenv("DGNP_DATAFLOW_SPIN", "0")
     cfg, _, gp = pair("cfg2t", with_oracle=False)
     try:
