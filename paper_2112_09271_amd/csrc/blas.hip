@@ -285,6 +285,29 @@ __global__ void k_sq_partial(const float* __restrict__ x, int64_t n, double* __r
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+void vsq_into(const float* x, int64_t n, double* out, double* scratch, hipStream_t s) {
+  unsigned g = red_grid(n);
+  hipLaunchKernelGGL(k_sq_partial, dim3(g), dim3(VB), 0, s, x, n, scratch);
+  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(VB), 0, s, scratch, int(g), out);
+}
+
+// x /= sqrt(*ss) with *ss read on the device (x unchanged when *ss <= 0)
+template <typename T>
+__global__ void k_scale_rsqrt_inplace(const double* __restrict__ ss, T* __restrict__ x, int64_t n) {
+  const double q = *ss;
+  if (!(q > 0.0)) return;
+  const double a = 1.0 / sqrt(q);
+  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB)
+    x[i] = T(a * double(x[i]));
+}
+template <typename T>
+void vscale_rsqrt_inplace(const double* ss_dev, T* x, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_scale_rsqrt_inplace<T>, dim3(grid_for(n)), dim3(VB), 0, s, ss_dev, x, n);
+}
+template void vscale_rsqrt_inplace<double>(const double*, double*, int64_t, hipStream_t);
+template void vscale_rsqrt_inplace<float>(const double*, float*, int64_t, hipStream_t);
+
 double vnorm2(const float* x, int64_t n, double* scratch_dev, hipStream_t s) {
   double* partial = scratch_dev + MAXV;
   unsigned g = red_grid(n);

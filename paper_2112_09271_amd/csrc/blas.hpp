@@ -37,6 +37,11 @@ template <typename T>
 void vcombine(const T* Z, int64_t ldz, int k, const double* h_dev, double* y, int64_t n, hipStream_t s);
 double vnorm2(const double* x, int64_t n, double* scratch_dev, hipStream_t s);  // synchronises
 double vnorm2(const float* x, int64_t n, double* scratch_dev, hipStream_t s);   // synchronises
+// *out = x . x (accumulated in double) without a host wait; scratch holds the block partials
+void vsq_into(const float* x, int64_t n, double* out, double* scratch, hipStream_t s);
+// x /= sqrt(*ss_dev), read on the device (no change when *ss_dev <= 0)
+template <typename T>
+void vscale_rsqrt_inplace(const double* ss_dev, T* x, int64_t n, hipStream_t s);
 template <typename T>
 void vfill_hash(T* x, int64_t n, hipStream_t s);  // deterministic values in [-0.5, 0.5)
 double vdot(const double* x, const double* y, int64_t n, double* scratch_dev, hipStream_t s);

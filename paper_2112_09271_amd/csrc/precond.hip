@@ -268,26 +268,36 @@ static void ensure_work32(dgnp_ctx& c, Precond& P) {
 
 // largest eigenvalue of D_b^{-1} A_phiphi by power iteration on the device, in
 // the arithmetic of the smoother that uses it: 20 steps from a hashed start
-// vector, renormalised every 4 steps; the estimate is the growth of the last step
+// vector, renormalised every 4 steps; the estimate is the growth of the last
+// step.  The norms stay on the device until the end (one host wait).
 template <typename T>
 static double lmax_level0(dgnp_ctx& c, Precond& P, hipStream_t s, const T* blk, const T* dinv, T* x, T* y) {
   const int64_t n = c.Nf;
+  double* sq = P.red.p;            // [0]: |x|^2 before the last step, [1]: after, [2]: start
+  double* part = P.red.p + MAXV;   // block partials
+  auto norm2 = [&](const T* v, double* out) {
+    if constexpr (std::is_same<T, float>::value)
+      vsq_into(v, n, out, part, s);
+    else
+      vdots_into(v, 0, 1, v, n, out, part, s);
+  };
   vfill_hash<T>(x, n, s);
-  const double nx = vnorm2(x, n, P.red.p, s);
-  vscale<T>(T(1.0 / nx), x, n, s);
-  double lam = 1.0;
+  norm2(x, sq + 2);
+  vscale_rsqrt_inplace<T>(sq + 2, x, n, s);
   for (int g = 0; g < 5; ++g) {
-    double n0 = 1.0;
     for (int it = 0; it < 4; ++it) {
-      if (it == 3) n0 = vnorm2(x, n, P.red.p, s);
+      if (it == 3) norm2(x, sq);
       launch_bspmv<T>(c.nb, c.dim, c.E, blk, c.d_nbr.p, x, nullptr, T(1), T(0), y, s);
       launch_bdiag<T>(c.nb, c.E, dinv, y, x, s);
     }
-    const double n1 = vnorm2(x, n, P.red.p, s);
-    lam = n1 / n0;
-    if (!(lam > 0.0) || !std::isfinite(lam)) throw Error(DGNP_E_NONFINITE, "power iteration failed");
-    vscale<T>(T(1.0 / n1), x, n, s);
+    norm2(x, sq + 1);
+    if (g < 4) vscale_rsqrt_inplace<T>(sq + 1, x, n, s);
   }
+  double h[2] = {0.0, 0.0};
+  DGNP_HIP(hipMemcpyAsync(h, sq, sizeof(h), hipMemcpyDeviceToHost, s));
+  DGNP_HIP(hipStreamSynchronize(s));
+  const double lam = std::sqrt(h[1]) / std::sqrt(h[0]);
+  if (!(lam > 0.0) || !std::isfinite(lam)) throw Error(DGNP_E_NONFINITE, "power iteration failed");
   return lam;
 }
 
@@ -329,6 +339,26 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     P.assembled = true;
     return;
   }
+  // concentration blocks: BILU(0) level by level, then their single copy; all
+  // of it is queued without a host wait, so that with both parts it runs on
+  // the device while the host builds the potential hierarchy
+  auto conc_part = [&]() {
+    for (size_t l = 0; l + 1 < P.lev_ptr.size(); ++l) {
+      ScopeTimer tm(c, "ilu_factor", s);
+      launch_ilu_factor(c.nb, c.dim, c.m - 1, per_field, P.blk.p + per_field, c.d_nbr.p, P.lev_elems.p,
+                        P.lev_ptr[l], P.lev_ptr[l + 1] - P.lev_ptr[l], s);
+    }
+    {
+      ScopeTimer tm(c, "ilu_factor", s);
+      launch_ilu_scale_lower(c.nb, c.dim, c.m - 1, per_field, P.blk.p + per_field, c.d_nbr.p, c.E, s);
+    }
+    clk.mark("ilu factor");
+    if (f32) {
+      P.blk32.alloc(size_t((c.m - 1) * per_field));
+      cvt_d2f(P.blk.p + per_field, P.blk32.p, (c.m - 1) * per_field, s);
+      clk.mark("float copies (conc)");
+    }
+  };
   if (phi) {
     // potential block: element-diagonal inverses (block-Jacobi smoother)
     P.dinv_phi.alloc(size_t(c.E * P.bsz));
@@ -347,6 +377,7 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     DGNP_HIP(hipMemcpyAsync(st.data(), P.vst.p, st.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     DGNP_HIP(hipStreamSynchronize(s));
     clk.mark("galerkin + stencil");
+    if (conc) conc_part();  // device work behind the host set-up below
     Csr A1 = vertex_matrix(c, P, st);
     clk.mark("vertex matrix");
     AmgHierarchy H = sa_setup(A1, 12, 256, 0.0);
@@ -403,24 +434,14 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     P.phi_ok = true;
     P.phi32_ok = f32;
   }
-  if (conc) {
-    // concentration blocks: BILU(0) level by level
-    for (size_t l = 0; l + 1 < P.lev_ptr.size(); ++l) {
-      ScopeTimer tm(c, "ilu_factor", s);
-      launch_ilu_factor(c.nb, c.dim, c.m - 1, per_field, P.blk.p + per_field, c.d_nbr.p, P.lev_elems.p,
-                        P.lev_ptr[l], P.lev_ptr[l + 1] - P.lev_ptr[l], s);
-    }
-    {
-      ScopeTimer tm(c, "ilu_factor", s);
-      launch_ilu_scale_lower(c.nb, c.dim, c.m - 1, per_field, P.blk.p + per_field, c.d_nbr.p, c.E, s);
-    }
-    clk.mark("ilu factor");
+  if (conc && !phi) {
+    conc_part();
     if (f32) {
-      P.blk32.alloc(size_t((c.m - 1) * per_field));
-      cvt_d2f(P.blk.p + per_field, P.blk32.p, (c.m - 1) * per_field, s);
-      if (P.wf.empty() || !P.vN32.p) ensure_work32(c, P);
-      clk.mark("float copies (conc)");
+      ensure_work(c, P);
+      ensure_work32(c, P);
     }
+  }
+  if (conc) {
     P.conc_ok = true;
     P.conc32_ok = f32;
   }
