@@ -44,6 +44,51 @@ struct Work {  // per-level work vectors
   std::vector<DevBuf<T>*> x, b, r, d, z;
 };
 
+// Host-to-device uploads of the set-up without a host wait per array: each
+// array is converted into pinned staging memory and copied asynchronously.
+// The staging memory is reused from the next set-up on (the set-up ends with
+// a stream synchronisation); chunks grow as needed and live with the context.
+struct PinnedStage {
+  struct Chunk {
+    char* p;
+    size_t size;
+  };
+  std::vector<Chunk> chunks;
+  size_t cur = 0, used = 0;
+  PinnedStage() = default;
+  PinnedStage(const PinnedStage&) = delete;
+  PinnedStage& operator=(const PinnedStage&) = delete;
+  ~PinnedStage() {
+    for (auto& ch : chunks) (void)hipHostFree(ch.p);
+  }
+  void reset() { cur = used = 0; }
+  void* take(size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    while (cur < chunks.size() && used + bytes > chunks[cur].size) {
+      ++cur;
+      used = 0;
+    }
+    if (cur == chunks.size()) {
+      Chunk ch{nullptr, std::max(bytes, size_t(8) << 20)};
+      DGNP_HIP(hipHostMalloc(reinterpret_cast<void**>(&ch.p), ch.size, hipHostMallocDefault));
+      chunks.push_back(ch);
+      used = 0;
+    }
+    void* r = chunks[cur].p + used;
+    used += bytes;
+    return r;
+  }
+  // dst = (T) src[0..n), asynchronously on s
+  template <typename T, typename S>
+  void upload(DevBuf<T>& dst, const S* src, size_t n, hipStream_t s) {
+    dst.alloc(n);
+    if (n == 0) return;
+    T* h = static_cast<T*>(take(n * sizeof(T)));
+    for (size_t i = 0; i < n; ++i) h[i] = T(src[i]);
+    DGNP_HIP(hipMemcpyAsync(dst.p, h, n * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+};
+
 struct Precond {
   int nslot = 0;
   int64_t bsz = 0;                  // doubles per block = nb * nb
@@ -71,6 +116,7 @@ struct Precond {
   DevBuf<double> vN, yN, tN;
   DevBuf<float> vN32, yN32, tN32;
   DevBuf<double> red;
+  PinnedStage stage;
   // dataflow sweeps: completion counters [forward / backward][field][E], timeout flag
   DevBuf<unsigned> df_cnt;
   DevBuf<uint64_t> df_wp;   // single precision: packed (value, count) [forward / backward][field][Nf]
@@ -228,27 +274,26 @@ static Csr vertex_matrix(const dgnp_ctx& c, const Precond& P, const std::vector<
 }
 
 template <typename T>
-static void upload_csr(DevCsr<T>& D, const Csr& A, hipStream_t s) {
+static void upload_csr(DevCsr<T>& D, const Csr& A, PinnedStage& st, hipStream_t s) {
   D.n = A.n;
-  D.rp.upload(A.rp, s);
-  D.ci.upload(A.ci, s);
-  std::vector<T> v(A.v.begin(), A.v.end());
-  D.v.upload(v, s);
+  st.upload(D.rp, A.rp.data(), A.rp.size(), s);
+  st.upload(D.ci, A.ci.data(), A.ci.size(), s);
+  st.upload(D.v, A.v.data(), A.v.size(), s);
 }
 
 static void ensure_work(dgnp_ctx& c, Precond& P) {
-  // per V-cycle level: 5 vectors (x, b, r, d, z) for each precision
+  // per V-cycle level: 5 vectors (x, b, r, d, z) for each precision; arrays
+  // of unchanged size are kept
   const size_t nlev = 1 + P.mg.size();
-  if (P.wd.size() == 5 * nlev) return;
-  P.wd.clear();
-  P.wf.clear();
+  while (P.wd.size() < 5 * nlev) {
+    P.wd.emplace_back(new DevBuf<double>());
+    P.wf.emplace_back(new DevBuf<float>());
+  }
+  P.wd.resize(5 * nlev);
+  P.wf.resize(5 * nlev);
   for (size_t l = 0; l < nlev; ++l) {
     const size_t n = l == 0 ? size_t(c.Nf) : size_t(P.mg[l - 1].n);
-    for (int k = 0; k < 5; ++k) {
-      P.wd.emplace_back(new DevBuf<double>());
-      P.wd.back()->alloc(n);
-      P.wf.emplace_back(new DevBuf<float>());
-    }
+    for (int k = 0; k < 5; ++k) P.wd[l * 5 + k]->alloc(n);
   }
   P.vN.alloc(size_t(c.N));
   P.yN.alloc(size_t(c.N));
@@ -322,6 +367,7 @@ struct PhaseClock {
 void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, int parts) {
   precond_check(c, false);
   Precond& P = *c.pc;
+  P.stage.reset();  // precond_check has synchronised the device: earlier copies are complete
   PhaseClock clk(s);
   const int64_t per_field = c.E * P.nslot * P.bsz;
   const bool phi = (parts & PC_PHI) != 0, conc = (parts & PC_CONC) != 0;
@@ -387,23 +433,21 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
       for (auto& A : H.A) fprintf(stderr, " -> %d (nnz %zu)", A.n, A.v.size());
       fprintf(stderr, "\n");
     }
-    P.mg.clear();
-    P.mg.resize(H.A.size());
+    P.mg.resize(H.A.size());  // device arrays of equal size are reused
     for (size_t l = 0; l < H.A.size(); ++l) {
       MgLevel& L = P.mg[l];
       L.n = H.A[l].n;
-      upload_csr(L.A, H.A[l], s);
+      upload_csr(L.A, H.A[l], P.stage, s);
       if (l + 1 < H.A.size()) {
-        upload_csr(L.P, H.P[l], s);
-        upload_csr(L.R, H.R[l], s);
+        upload_csr(L.P, H.P[l], P.stage, s);
+        upload_csr(L.R, H.R[l], P.stage, s);
       }
-      L.dinv.upload(H.dinv[l], s);
+      P.stage.upload(L.dinv, H.dinv[l].data(), H.dinv[l].size(), s);
       L.lmax = H.lmax[l];
     }
     P.nc = H.A.back().n;
-    P.cinv.upload(H.coarse_inv, s);
+    P.stage.upload(P.cinv, H.coarse_inv.data(), H.coarse_inv.size(), s);
     clk.mark("upload hierarchy");
-    P.wd.clear();
     ensure_work(c, P);
     clk.mark("work vectors");
     if (f32) {
@@ -414,16 +458,14 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
       cvt_d2f_rows(P.dinv_phi.p, P.dinv_phi32.p, c.E * c.nb, c.nb, ld32, s);
       for (size_t l = 0; l < H.A.size(); ++l) {
         MgLevel& L = P.mg[l];
-        upload_csr(L.A32, H.A[l], s);
+        upload_csr(L.A32, H.A[l], P.stage, s);
         if (l + 1 < H.A.size()) {
-          upload_csr(L.P32, H.P[l], s);
-          upload_csr(L.R32, H.R[l], s);
+          upload_csr(L.P32, H.P[l], P.stage, s);
+          upload_csr(L.R32, H.R[l], P.stage, s);
         }
-        std::vector<float> di(H.dinv[l].begin(), H.dinv[l].end());
-        L.dinv32.upload(di, s);
+        P.stage.upload(L.dinv32, H.dinv[l].data(), H.dinv[l].size(), s);
       }
-      std::vector<float> ci(H.coarse_inv.begin(), H.coarse_inv.end());
-      P.cinv32.upload(ci, s);
+      P.stage.upload(P.cinv32, H.coarse_inv.data(), H.coarse_inv.size(), s);
       ensure_work32(c, P);
       clk.mark("float copies (phi)");
       P.lmax0 = lmax_level0<float>(c, P, s, P.phi32.p, P.dinv_phi32.p, P.wf[0]->p, P.wf[1]->p);
