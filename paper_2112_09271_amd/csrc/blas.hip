@@ -111,23 +111,6 @@ void vscale_dual(double a, const double* x, double* y, float* y32, int64_t n, hi
   if (n <= 0) return;
   hipLaunchKernelGGL(k_scale_dual, dim3(grid_for(n)), dim3(VB), 0, s, a, x, y, y32, n);
 }
-// y = x / sqrt(q) with q = *ss read on the device (y = 0 when q <= 0), and
-// y32 = float(y) when y32 is not null; 1 / sqrt(q) is formed exactly as the
-// host forms it from the same q (correctly rounded square root and division)
-__global__ void k_scale_rsqrt(const double* __restrict__ ss, const double* __restrict__ x, double* __restrict__ y,
-                              float* __restrict__ y32, int64_t n) {
-  const double q = *ss;
-  const double a = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
-  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
-    const double v = a * x[i];
-    y[i] = v;
-    if (y32) y32[i] = float(v);
-  }
-}
-void vscale_rsqrt(const double* ss_dev, const double* x, double* y, float* y32, int64_t n, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_scale_rsqrt, dim3(grid_for(n)), dim3(VB), 0, s, ss_dev, x, y, y32, n);
-}
 template <typename T>
 void vsub(const T* x, const T* y, T* z, int64_t n, hipStream_t s) {
   if (n <= 0) return;
@@ -217,23 +200,6 @@ static unsigned red_grid(int64_t n) {
   return unsigned(g);
 }
 
-// w read in single precision (the Jacobian apply's result); the blocks of the
-// first vector also store it widened to double in w64
-__global__ void k_dots_partial_f(const double* __restrict__ V, int64_t ldv, const float* __restrict__ w,
-                                 double* __restrict__ w64, int64_t n, double* __restrict__ partial) {
-  __shared__ double sh[VB];
-  const int j = blockIdx.y;
-  const double* v = V + j * ldv;
-  double acc = 0.0;
-  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
-    const double wi = double(w[i]);
-    if (j == 0) w64[i] = wi;
-    acc += v[i] * wi;
-  }
-  double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[int64_t(j) * RED_BLOCKS + blockIdx.x] = s;
-}
-
 void vdots_into(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* out, double* scratch,
                 hipStream_t s) {
   if (k <= 0) return;
@@ -242,13 +208,6 @@ void vdots_into(const double* V, int64_t ldv, int k, const double* w, int64_t n,
   hipLaunchKernelGGL(k_dots_final, dim3(unsigned(k)), dim3(VB), 0, s, scratch, int(g), out);
 }
 
-void vdots_into_f(const double* V, int64_t ldv, int k, const float* w, double* w64, int64_t n, double* out,
-                  double* scratch, hipStream_t s) {
-  if (k <= 0) return;
-  unsigned g = red_grid(n);
-  hipLaunchKernelGGL(k_dots_partial_f, dim3(g, unsigned(k)), dim3(VB), 0, s, V, ldv, w, w64, n, scratch);
-  hipLaunchKernelGGL(k_dots_final, dim3(unsigned(k)), dim3(VB), 0, s, scratch, int(g), out);
-}
 
 void vdots(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* out_dev,
            hipStream_t s) {
@@ -319,28 +278,165 @@ double vnorm2(const float* x, int64_t n, double* scratch_dev, hipStream_t s) {
   return h > 0.0 ? sqrt(h) : 0.0;
 }
 
-__global__ void k_maxpy(const double* __restrict__ V, int64_t ldv, int k, const double* __restrict__ h,
-                        double* __restrict__ w, int64_t n) {
+// ---- delayed classical Gram-Schmidt (reorthogonalisation one step late) -------
+// Step j of the Arnoldi process works on u, the new direction after one
+// projection pass (scaled to about unit length), and w = Op z with z = P u.
+// One reduction gives s = V_{<j}^T u, sigma = u.u, c = V_{<j}^T w, tau = u.w and
+// w.w; then v_j = (u - V s) / alpha with alpha = sqrt(sigma - s.s), and the
+// first projection of w against V_{<j} and v_j leaves the next direction.
+// Coefficient block (device, contiguous): [s | sigma] at 0, [c | tau] at MAXV,
+// then w.w, alpha, h_jj, 1/alpha, rho, 1/rho at 2 MAXV + 0..5.
+static constexpr int DC_WW = 2 * MAXV, DC_ALPHA = 2 * MAXV + 1, DC_HJJ = 2 * MAXV + 2, DC_IALPHA = 2 * MAXV + 3,
+                     DC_RHO = 2 * MAXV + 4, DC_IRHO = 2 * MAXV + 5;
+
+// partial[r][y][blk], r = 0: L_y . u, r = 1: L_y . w, row 2 MAXV: w . w
+// (y = j only); L_y = V_y for y < j, L_j = u.  For single-precision w the
+// block row y = j also stores w widened to double in w64 (if not null).
+template <typename TW>
+__global__ void k_dcgs_dots(const double* __restrict__ V, int64_t ldv, int j, const double* __restrict__ u,
+                            const TW* __restrict__ w, double* __restrict__ w64, int64_t n,
+                            double* __restrict__ partial) {
+  __shared__ double sh[VB];
+  const int y = blockIdx.y;
+  const bool last = y == j;
+  const double* L = last ? u : V + int64_t(y) * ldv;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
-    // four independent partial sums keep four loads in flight per thread
-    double a0 = w[i], a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int j = 0;
-    for (; j + 4 <= k; j += 4) {
-      a0 -= h[j] * V[j * ldv + i];
-      a1 -= h[j + 1] * V[(j + 1) * ldv + i];
-      a2 -= h[j + 2] * V[(j + 2) * ldv + i];
-      a3 -= h[j + 3] * V[(j + 3) * ldv + i];
+    const double l = L[i];
+    a0 += l * u[i];
+    if (w) {
+      const double wi = double(w[i]);
+      a1 += l * wi;
+      if (last) {
+        a2 += wi * wi;
+        if (w64) w64[i] = wi;
+      }
     }
-    for (; j < k; ++j) a0 -= h[j] * V[j * ldv + i];
-    w[i] = (a0 + a1) + (a2 + a3);
+  }
+  const double s0 = block_sum(a0, sh);
+  __syncthreads();
+  if (threadIdx.x == 0) partial[int64_t(y) * RED_BLOCKS + blockIdx.x] = s0;
+  if (w) {
+    const double s1 = block_sum(a1, sh);
+    __syncthreads();
+    if (threadIdx.x == 0) partial[int64_t(MAXV + y) * RED_BLOCKS + blockIdx.x] = s1;
+    if (last) {
+      const double s2 = block_sum(a2, sh);
+      if (threadIdx.x == 0) partial[int64_t(2 * MAXV) * RED_BLOCKS + blockIdx.x] = s2;
+    }
   }
 }
 
-void vmaxpy(const double* V, int64_t ldv, int k, const double* h_dev, double* w, int64_t n,
-            hipStream_t s) {
-  if (k <= 0 || n <= 0) return;
-  hipLaunchKernelGGL(k_maxpy, dim3(grid_for(n)), dim3(VB), 0, s, V, ldv, k, h_dev, w, n);
+// out[row] = sum of the row's block partials for the rows 0..j, MAXV..MAXV+j
+// and 2 MAXV (the last two groups only with w)
+__global__ void k_dcgs_final(const double* __restrict__ partial, int nblk, int j, double* __restrict__ out) {
+  __shared__ double sh[VB];
+  const int o = blockIdx.x;
+  const int row = o <= j ? o : (o <= 2 * j + 1 ? MAXV + (o - j - 1) : 2 * MAXV);
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += VB) acc += partial[int64_t(row) * RED_BLOCKS + i];
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[row] = t;
 }
+
+// alpha, h_jj, rho and their reciprocals from the reduced dot products (one block)
+__global__ void k_dcgs_scalars(double* __restrict__ out, int j, int with_w) {
+  __shared__ double sh[VB];
+  double ss = 0.0, sc = 0.0, cc = 0.0;
+  for (int k = threadIdx.x; k < j; k += VB) {
+    const double sk = out[k];
+    ss += sk * sk;
+    if (with_w) {
+      const double ck = out[MAXV + k];
+      sc += sk * ck;
+      cc += ck * ck;
+    }
+  }
+  ss = block_sum(ss, sh);
+  __syncthreads();
+  sc = block_sum(sc, sh);
+  __syncthreads();
+  cc = block_sum(cc, sh);
+  if (threadIdx.x != 0) return;
+  const double a2 = out[j] - ss;
+  const double alpha = a2 > 0.0 ? sqrt(a2) : 0.0;
+  const double ia = alpha > 0.0 ? 1.0 / alpha : 0.0;
+  out[DC_ALPHA] = alpha;
+  out[DC_IALPHA] = ia;
+  if (with_w) {
+    const double hjj = (out[MAXV + j] - sc) * ia;
+    const double ww = out[DC_WW];
+    const double r2 = ww - cc - hjj * hjj;  // |w - V c - v_j h_jj|^2 by Pythagoras: only a scale
+    double rho = r2 > 0.0 ? sqrt(r2) : sqrt(ww);
+    if (!(rho > 0.0)) rho = 1.0;
+    out[DC_HJJ] = hjj;
+    out[DC_RHO] = rho;
+    out[DC_IRHO] = 1.0 / rho;
+  }
+}
+
+// v_j = (u - V s) / alpha into V column j; u <- (w - V c - v_j h_jj) / rho and
+// its copy m = (TM) u (the next preconditioner input).  V is read once.
+template <typename TM>
+__global__ void k_dcgs_update(double* __restrict__ V, int64_t ldv, int j, const double* __restrict__ coef,
+                              double* __restrict__ u, const double* __restrict__ w, TM* __restrict__ m,
+                              int64_t n) {
+  const double ia = coef[DC_IALPHA], hjj = coef[DC_HJJ], irho = coef[DC_IRHO];
+  const double* sv = coef;
+  const double* cv = coef + MAXV;
+  double* vj = V + int64_t(j) * ldv;
+  for (int64_t i = blockIdx.x * int64_t(VB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * VB) {
+    double as0 = 0.0, as1 = 0.0, ac0 = 0.0, ac1 = 0.0;
+    int k = 0;
+    for (; k + 2 <= j; k += 2) {
+      const double x0 = V[int64_t(k) * ldv + i], x1 = V[int64_t(k + 1) * ldv + i];
+      as0 += sv[k] * x0;
+      ac0 += cv[k] * x0;
+      as1 += sv[k + 1] * x1;
+      ac1 += cv[k + 1] * x1;
+    }
+    if (k < j) {
+      const double x0 = V[int64_t(k) * ldv + i];
+      as0 += sv[k] * x0;
+      ac0 += cv[k] * x0;
+    }
+    const double v = (u[i] - (as0 + as1)) * ia;
+    vj[i] = v;
+    const double un = (w[i] - (ac0 + ac1) - v * hjj) * irho;
+    u[i] = un;
+    m[i] = TM(un);
+  }
+}
+
+void dcgs_reduce(const double* V, int64_t ldv, int j, const double* u, const void* w, bool w_f32, double* w64,
+                 int64_t n, double* partial, double* coef, hipStream_t s) {
+  const unsigned g = red_grid(n);
+  const dim3 grid(g, unsigned(j + 1));
+  if (!w)
+    hipLaunchKernelGGL(k_dcgs_dots<double>, grid, dim3(VB), 0, s, V, ldv, j, u, static_cast<const double*>(nullptr),
+                       static_cast<double*>(nullptr), n, partial);
+  else if (w_f32)
+    hipLaunchKernelGGL(k_dcgs_dots<float>, grid, dim3(VB), 0, s, V, ldv, j, u, static_cast<const float*>(w), w64, n,
+                       partial);
+  else
+    hipLaunchKernelGGL(k_dcgs_dots<double>, grid, dim3(VB), 0, s, V, ldv, j, u, static_cast<const double*>(w),
+                       static_cast<double*>(nullptr), n, partial);
+  const unsigned nout = w ? unsigned(2 * j + 3) : unsigned(j + 1);
+  hipLaunchKernelGGL(k_dcgs_final, dim3(nout), dim3(VB), 0, s, partial, int(g), j, coef);
+  hipLaunchKernelGGL(k_dcgs_scalars, dim3(1), dim3(VB), 0, s, coef, j, w ? 1 : 0);
+}
+
+template <typename TM>
+void dcgs_update(double* V, int64_t ldv, int j, const double* coef, double* u, const double* w, TM* m, int64_t n,
+                 hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_dcgs_update<TM>, dim3(grid_for(n)), dim3(VB), 0, s, V, ldv, j, coef, u, w, m, n);
+}
+template void dcgs_update<double>(double*, int64_t, int, const double*, double*, const double*, double*, int64_t,
+                                  hipStream_t);
+template void dcgs_update<float>(double*, int64_t, int, const double*, double*, const double*, float*, int64_t,
+                                 hipStream_t);
+int64_t dcgs_partial_size() { return int64_t(2 * MAXV + 1) * RED_BLOCKS; }
 
 template <typename T>
 __global__ void k_combine(const T* __restrict__ Z, int64_t ldz, int k, const double* __restrict__ h,

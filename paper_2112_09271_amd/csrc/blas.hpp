@@ -24,19 +24,25 @@ void vdots(const double* V, int64_t ldv, int k, const double* w, int64_t n, doub
 // also stores it widened to double in w64
 void vdots_into(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* out, double* scratch,
                 hipStream_t s);
-void vdots_into_f(const double* V, int64_t ldv, int k, const float* w, double* w64, int64_t n, double* out,
-                  double* scratch, hipStream_t s);
 void vscale_dual(double a, const double* x, double* y, float* y32, int64_t n, hipStream_t s);  // y = a x, y32 = (float) y
-// y = x / sqrt(*ss_dev) (0 if *ss_dev <= 0), y32 = (float) y unless null
-void vscale_rsqrt(const double* ss_dev, const double* x, double* y, float* y32, int64_t n, hipStream_t s);
 // w -= sum_j h[j] V_j
-void vmaxpy(const double* V, int64_t ldv, int k, const double* h_dev, double* w, int64_t n,
-            hipStream_t s);
 // y = sum_j h[j] Z_j (Z of type T) accumulated in double into y (y += when accumulate)
 template <typename T>
 void vcombine(const T* Z, int64_t ldz, int k, const double* h_dev, double* y, int64_t n, hipStream_t s);
 double vnorm2(const double* x, int64_t n, double* scratch_dev, hipStream_t s);  // synchronises
 double vnorm2(const float* x, int64_t n, double* scratch_dev, hipStream_t s);   // synchronises
+// Delayed classical Gram-Schmidt, step j (see blas.hip): dcgs_reduce forms the
+// coefficient block coef[2 MAXV + 8] from V[:, <j], u and w (w null: only
+// s, sigma and alpha, for the last column of a cycle; w_f32: w in single
+// precision, widened into w64); dcgs_update writes V[:, j], the next u and
+// its preconditioner-input copy m.  partial holds dcgs_partial_size() doubles.
+void dcgs_reduce(const double* V, int64_t ldv, int j, const double* u, const void* w, bool w_f32, double* w64,
+                 int64_t n, double* partial, double* coef, hipStream_t s);
+template <typename TM>
+void dcgs_update(double* V, int64_t ldv, int j, const double* coef, double* u, const double* w, TM* m, int64_t n,
+                 hipStream_t s);
+int64_t dcgs_partial_size();
+constexpr int DCGS_ALPHA = 2 * MAXV + 1, DCGS_HJJ = 2 * MAXV + 2, DCGS_RHO = 2 * MAXV + 4, DCGS_COEF = 2 * MAXV + 8;
 // *out = x . x (accumulated in double) without a host wait; scratch holds the block partials
 void vsq_into(const float* x, int64_t n, double* out, double* scratch, hipStream_t s);
 // x /= sqrt(*ss_dev), read on the device (no change when *ss_dev <= 0)

@@ -2,6 +2,7 @@
 // GMRES with FP64 classical Gram-Schmidt (twice), Newton with backtracking
 // line search (paper Sec. 4), mixed precision by iterative refinement, and the
 // adjoint of the outflow-flux objective.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -76,9 +77,9 @@ struct Krylov {
   hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   uint64_t gepoch[2][2] = {{0, 0}, {0, 0}};
   int gpc[2][2] = {{-1, -1}, {-1, -1}};
-  // pinned host slots for the coefficients of two consecutive Arnoldi steps
-  // (h1[MAXV], h2[MAXV], |w|^2) and the events that mark their arrival
-  static constexpr size_t HSLOT = 2 * MAXV + 8;
+  // pinned host slots for the coefficient blocks of two consecutive Arnoldi
+  // steps and the events that mark their arrival
+  static constexpr size_t HSLOT = DCGS_COEF;
   double* hpin = nullptr;
   hipEvent_t hev[2] = {nullptr, nullptr};
   ~Krylov() {
@@ -143,7 +144,7 @@ static Krylov& krylov(dgnp_ctx& c, int restart, bool f32) {
     K->V.alloc(size_t(restart + 1) * c.N);
     K->w.alloc(size_t(c.N));
     K->r.alloc(size_t(c.N));
-    K->hd.alloc(size_t(reduce_scratch_size()) + 3 * MAXV + 8);
+    K->hd.alloc(size_t(std::max(reduce_scratch_size(), dcgs_partial_size())) + DCGS_COEF + MAXV + 8);
     K->Z.release();
     K->Z32.release();
     K->restart = restart;
@@ -205,105 +206,134 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
       break;
     }
     if (out.its >= maxit) break;
-    if (f32)
-      vscale_dual(1.0 / beta, K.r.p, K.V.p, K.v32.p, N, s);  // the basis vector and its single copy
-    else
-      vaxpby<double>(1.0 / beta, K.r.p, 0.0, K.V.p, N, s);
+    // u = r / beta (kept in K.r) and its copy for the preconditioner input
+    if (f32) {
+      vscale_dual(1.0 / beta, K.r.p, K.r.p, K.v32.p, N, s);
+    } else {
+      vscale<double>(1.0 / beta, K.r.p, N, s);
+      vcopy<double>(K.r.p, K.vt.p, N, s);
+    }
     std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    // device locations of the step's coefficients: classical Gram-Schmidt,
-    // twice, h1 and h2, then |w|^2
-    double* h1 = K.hd.p + reduce_scratch_size();
-    double* h2 = h1 + MAXV;
-    double* ww = h2 + MAXV;
-    double* part = K.hd.p;  // block partials of the reductions
-    // Queue Arnoldi step jj: (jj > 0) v_jj = w / |w| on the device, z_jj = P v_jj,
-    // w = Op z_jj, both Gram-Schmidt passes and |w|^2, and the copy of the
-    // coefficients to host slot jj % 2.  Step jj + 1 is queued before the host
-    // reads step jj, so the device never waits for the host's rotations; a step
-    // queued past convergence is discarded.
-    auto issue = [&](int jj) {
-      double* vj = K.V.p + int64_t(jj) * N;
-      double* w = K.w.p;
-      if (jj > 0) vscale_rsqrt(ww, w, vj, f32 ? K.v32.p : nullptr, N, s);
+    // Arnoldi with delayed classical Gram-Schmidt: step q applies P and the
+    // operator to u_q (the direction left by step q - 1 after one projection
+    // pass), and one reduction both reorthogonalises u_q against the basis (its
+    // coefficients complete column q - 1 of H) and projects the new w once (the
+    // first part of column q).  The basis is read twice per step instead of
+    // four times.  Step q + 1 is queued before the host reads step q, so the
+    // device does not wait for the host's rotations; steps queued past
+    // convergence are discarded.
+    double* part = K.hd.p;
+    double* coef = K.hd.p + dcgs_partial_size();
+    auto to_host = [&](int q) {
+      DGNP_HIP(hipMemcpyAsync(K.hpin + size_t(q % 2) * Krylov::HSLOT, coef, sizeof(double) * size_t(DCGS_COEF),
+                              hipMemcpyDeviceToHost, s));
+      DGNP_HIP(hipEventRecord(K.hev[q % 2], s));
+    };
+    auto issue_step = [&](int q) {
       if (f32) {
         pc_then_jac(c, K, true, transpose, pc_kind, s);
-        vcopy<float>(K.zt32.p, K.Z32.p + int64_t(jj) * N, N, s);
+        vcopy<float>(K.zt32.p, K.Z32.p + int64_t(q) * N, N, s);
       } else {
-        vcopy<double>(vj, K.vt.p, N, s);
         pc_then_jac(c, K, false, transpose, pc_kind, s);
-        vcopy<double>(K.zt.p, K.Z.p + int64_t(jj) * N, N, s);
+        vcopy<double>(K.zt.p, K.Z.p + int64_t(q) * N, N, s);
       }
       {
         ScopeTimer tm(c, "cgs2", s);
-        if (f32)
-          vdots_into_f(K.V.p, N, jj + 1, K.w32.p, w, N, h1, part, s);  // also widens w to double
-        else
-          vdots_into(K.V.p, N, jj + 1, w, N, h1, part, s);
-        vmaxpy(K.V.p, N, jj + 1, h1, w, N, s);
-        vdots_into(K.V.p, N, jj + 1, w, N, h2, part, s);
-        vmaxpy(K.V.p, N, jj + 1, h2, w, N, s);
-        vdots_into(w, 0, 1, w, N, ww, part, s);
+        if (f32) {
+          dcgs_reduce(K.V.p, N, q, K.r.p, K.w32.p, true, K.w.p, N, part, coef, s);
+          dcgs_update<float>(K.V.p, N, q, coef, K.r.p, K.w.p, K.v32.p, N, s);
+        } else {
+          dcgs_reduce(K.V.p, N, q, K.r.p, K.w.p, false, nullptr, N, part, coef, s);
+          dcgs_update<double>(K.V.p, N, q, coef, K.r.p, K.w.p, K.vt.p, N, s);
+        }
       }
-      double* slot = K.hpin + size_t(jj % 2) * Krylov::HSLOT;
-      DGNP_HIP(hipMemcpyAsync(slot, h1, sizeof(double) * size_t(2 * MAXV + 1), hipMemcpyDeviceToHost, s));
-      DGNP_HIP(hipEventRecord(K.hev[jj % 2], s));
+      to_host(q);
     };
-    int j = 0;
-    bool done = false;
-    issue(0);
-    for (; j < restart && out.its < maxit; ++j) {
-      if (j + 1 < restart && out.its + 1 < maxit) issue(j + 1);
-      DGNP_HIP(hipEventSynchronize(K.hev[j % 2]));
-      const double* hb = K.hpin + size_t(j % 2) * Krylov::HSLOT;
-      ++out.its;
-      double* col = H.data() + size_t(j) * (restart + 1);
-      for (int i = 0; i <= j; ++i) col[i] = hb[size_t(i)] + hb[size_t(MAXV + i)];
-      const double hn = std::sqrt(std::max(hb[2 * MAXV], 0.0));
-      col[j + 1] = hn;
-      if (!std::isfinite(hn)) {
+    auto issue_final = [&](int q) {  // reorthogonalisation of u_q only: completes column q - 1
+      {
+        ScopeTimer tm(c, "cgs2", s);
+        dcgs_reduce(K.V.p, N, q, K.r.p, nullptr, false, nullptr, N, part, coef, s);
+      }
+      to_host(q);
+    };
+    auto read = [&](int q) -> const double* {
+      DGNP_HIP(hipEventSynchronize(K.hev[q % 2]));
+      const double* hb = K.hpin + size_t(q % 2) * Krylov::HSLOT;
+      if (!std::isfinite(hb[DCGS_ALPHA]) || !std::isfinite(hb[DCGS_HJJ]) || !std::isfinite(hb[DCGS_RHO])) {
         DGNP_HIP(hipStreamSynchronize(s));
         throw Error(DGNP_E_NONFINITE, "non-finite Arnoldi vector");
       }
-      for (int i = 0; i < j; ++i) {
+      return hb;
+    };
+    // column jc of H is complete: add the reorthogonalisation s (scaled by the
+    // direction's scale rho), set h_{jc+1,jc}, rotate; true when converged
+    auto finish_column = [&](int jc, const double* hb, double rho) -> bool {
+      double* col = H.data() + size_t(jc) * (restart + 1);
+      for (int i = 0; i <= jc; ++i) col[i] += rho * hb[i];
+      const double hn = rho * hb[DCGS_ALPHA];
+      col[jc + 1] = hn;
+      ++out.its;
+      for (int i = 0; i < jc; ++i) {
         const double t = cs[size_t(i)] * col[i] + sn[size_t(i)] * col[i + 1];
         col[i + 1] = -sn[size_t(i)] * col[i] + cs[size_t(i)] * col[i + 1];
         col[i] = t;
       }
-      const double den = std::hypot(col[j], col[j + 1]);
+      const double den = std::hypot(col[jc], col[jc + 1]);
       if (den == 0.0) {
         DGNP_HIP(hipStreamSynchronize(s));
         throw Error(DGNP_E_BREAKDOWN, "FGMRES breakdown");
       }
-      cs[size_t(j)] = col[j] / den;
-      sn[size_t(j)] = col[j + 1] / den;
-      col[j] = den;
-      col[j + 1] = 0.0;
-      g[size_t(j + 1)] = -sn[size_t(j)] * g[size_t(j)];
-      g[size_t(j)] = cs[size_t(j)] * g[size_t(j)];
-      const double est = std::fabs(g[size_t(j + 1)]);
+      cs[size_t(jc)] = col[jc] / den;
+      sn[size_t(jc)] = col[jc + 1] / den;
+      col[jc] = den;
+      col[jc + 1] = 0.0;
+      g[size_t(jc + 1)] = -sn[size_t(jc)] * g[size_t(jc)];
+      g[size_t(jc)] = cs[size_t(jc)] * g[size_t(jc)];
+      const double est = std::fabs(g[size_t(jc + 1)]);
       if (verbose > 2) fprintf(stderr, "    it %d: est %.3e\n", out.its, est);
-      if (est <= target || hn == 0.0) {
-        ++j;
+      return est <= target || hn == 0.0;
+    };
+    const int jmax = std::min(restart, maxit - out.its);
+    int k = 0;  // columns used for the update
+    bool done = false;
+    double rho_prev = 1.0;
+    issue_step(0);
+    for (int q = 0; q < jmax; ++q) {
+      if (q + 1 < jmax)
+        issue_step(q + 1);
+      else
+        issue_final(q + 1);
+      const double* hb = read(q);
+      if (q == 0) {
+        g[0] = beta * hb[DCGS_ALPHA];  // r = beta u_0 = beta alpha_0 v_0
+      } else if (finish_column(q - 1, hb, rho_prev)) {
+        k = q;
         done = true;
         break;
       }
+      double* col = H.data() + size_t(q) * (restart + 1);
+      for (int i = 0; i < q; ++i) col[i] = hb[MAXV + i];
+      col[q] = hb[DCGS_HJJ];
+      rho_prev = hb[DCGS_RHO];
+    }
+    if (!done && jmax > 0) {
+      const double* hb = read(jmax);
+      finish_column(jmax - 1, hb, rho_prev);
+      k = jmax;
     }
     // back substitution and update x += Z y
-    const int k = j;
     for (int i = k - 1; i >= 0; --i) {
       double acc = g[size_t(i)];
       for (int l = i + 1; l < k; ++l) acc -= H[size_t(l) * (restart + 1) + i] * y[size_t(l)];
       y[size_t(i)] = acc / H[size_t(i) * (restart + 1) + i];
     }
-    double* yd = K.hd.p + reduce_scratch_size() + 2 * MAXV + 1;
+    double* yd = coef + DCGS_COEF;
     DGNP_HIP(hipMemcpyAsync(yd, y.data(), sizeof(double) * size_t(k), hipMemcpyHostToDevice, s));
     if (f32)
       vcombine<float>(K.Z32.p, N, k, yd, x, N, s);
     else
       vcombine<double>(K.Z.p, N, k, yd, x, N, s);
     DGNP_HIP(hipStreamSynchronize(s));
-    (void)done;
   }
   return out;
 }
