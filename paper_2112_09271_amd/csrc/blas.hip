@@ -154,14 +154,18 @@ template void vfill_hash<double>(double*, int64_t, hipStream_t);
 template void vfill_hash<float>(float*, int64_t, hipStream_t);
 
 // ---- reductions ---------------------------------------------------------------
+// sum over the block (returned to every thread): wave sums by lane shuffles,
+// then the VB / 64 wave sums through LDS; sh holds at least VB / 64 doubles
 __device__ inline double block_sum(double v, double* sh) {
-  sh[threadIdx.x] = v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[wave] = v;
   __syncthreads();
-  for (int s = VB / 2; s > 0; s >>= 1) {
-    if (int(threadIdx.x) < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
-  }
-  return sh[0];
+  double t = 0.0;
+#pragma unroll
+  for (int k = 0; k < VB / 64; ++k) t += sh[k];
+  return t;
 }
 
 // partial[j][blk] = sum over the block's chunk of V_j * w
