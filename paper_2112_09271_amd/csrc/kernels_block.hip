@@ -1171,28 +1171,52 @@ __global__ void k_q1_prolong(int3 n3, const T* __restrict__ xv, T* __restrict__ 
 }
 
 // rv[v] = sum over elements e containing v of sum_node N_{o(e,v)}(node) r[e][node]
+// 2^DIM lanes per vertex: lane o takes the element of which v is corner o and
+// contracts its nodal values with the corner's trilinear shape one direction
+// at a time; the lanes' sums are combined by shuffles (a fixed order).
 template <typename T, int DIM, int P>
 __global__ void k_q1_restrict(int3 n3, const T* __restrict__ r, T* __restrict__ rv, int64_t nvert) {
   constexpr int NN = P + 1;
   constexpr int NB = DIM == 3 ? NN * NN * NN : NN * NN;
-  const int64_t v = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (v >= nvert) return;
-  int n[3] = {n3.x, n3.y, n3.z};
-  int vc[3] = {int(v % (n[0] + 1)), int((v / (n[0] + 1)) % (n[1] + 1)),
-               DIM == 3 ? int(v / (int64_t(n[0] + 1) * (n[1] + 1))) : 0};
-  double acc = 0.0;
-  for (int o = 0; o < (1 << DIM); ++o) {
-    int eid[3] = {0, 0, 0};
-    bool ok = true;
-    for (int d = 0; d < DIM; ++d) {
-      eid[d] = vc[d] - ((o >> d) & 1);
-      if (eid[d] < 0 || eid[d] >= n[d]) ok = false;
-    }
-    if (!ok) continue;
-    const int64_t e = eid[0] + int64_t(n[0]) * (eid[1] + int64_t(n[1]) * eid[2]);
-    for (int node = 0; node < NB; ++node) acc += q1_shape<DIM, P>(node, o) * double(r[e * NB + node]);
+  constexpr int NV = 1 << DIM;
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  const int64_t v = t / NV;
+  const int o = int(t % NV);
+  if (v >= nvert) return;  // whole groups of NV lanes leave together
+  const int n[3] = {n3.x, n3.y, n3.z};
+  const int vc[3] = {int(v % (n[0] + 1)), int((v / (n[0] + 1)) % (n[1] + 1)),
+                     DIM == 3 ? int(v / (int64_t(n[0] + 1) * (n[1] + 1))) : 0};
+  int eid[3] = {0, 0, 0};
+  bool ok = true;
+  for (int d = 0; d < DIM; ++d) {
+    eid[d] = vc[d] - ((o >> d) & 1);
+    if (eid[d] < 0 || eid[d] >= n[d]) ok = false;
   }
-  rv[v] = T(acc);
+  double acc = 0.0;
+  if (ok) {
+    const int64_t e = eid[0] + int64_t(n[0]) * (eid[1] + int64_t(n[1]) * eid[2]);
+    double phi[3][NN];
+    for (int d = 0; d < 3; ++d)
+      for (int i = 0; i < NN; ++i) {
+        const double xi = c_gll[P - 1][i];
+        phi[d][i] = ((o >> d) & 1) ? 0.5 * (1.0 + xi) : 0.5 * (1.0 - xi);
+      }
+    const T* re = r + e * NB;
+    constexpr int NK = DIM == 3 ? NN : 1;
+    for (int k = 0; k < NK; ++k) {
+      double sj = 0.0;
+      for (int j = 0; j < NN; ++j) {
+        double si = 0.0;
+#pragma unroll
+        for (int i = 0; i < NN; ++i) si += phi[0][i] * double(re[(k * NN + j) * NN + i]);
+        sj += phi[1][j] * si;
+      }
+      acc += (DIM == 3 ? phi[2][k] : 1.0) * sj;
+    }
+  }
+#pragma unroll
+  for (int m = 1; m < NV; m <<= 1) acc += __shfl_xor(acc, m, 64);
+  if (o == 0) rv[v] = T(acc);
 }
 
 // gal[e][s][u][v] = sum_ij N_u(i) A_{e,s}[i][j] N_v(j)   (s = 0 diag, 1 + slot)
@@ -1717,8 +1741,9 @@ static void q1_t(bool prolong, const int* n, const T* a, T* b, T beta, int64_t E
     hipLaunchKernelGGL((k_q1_prolong<T, DIM, P>), dim3(unsigned((tot + 255) / 256)), dim3(256), 0, s, n3, a, b,
                        beta, E);
   } else {
-    hipLaunchKernelGGL((k_q1_restrict<T, DIM, P>), dim3(unsigned((nvert + 255) / 256)), dim3(256), 0, s, n3, a,
-                       b, nvert);
+    const int64_t tot = nvert << DIM;  // 2^DIM lanes per vertex
+    hipLaunchKernelGGL((k_q1_restrict<T, DIM, P>), dim3(unsigned((tot + 255) / 256)), dim3(256), 0, s, n3, a, b,
+                       nvert);
   }
 }
 
