@@ -98,6 +98,10 @@ struct Precond {
   DevBuf<double> dinv_phi;          // [E][nb][nb]
   DevBuf<float> dinv_phi32;         // [E][nb][ld32]
   double lmax0 = 1.0;
+  // last power-iteration vector of each precision: later estimates (the next
+  // linearisation points) start from it with fewer steps
+  DevBuf<double> lvec64;
+  DevBuf<float> lvec32;
   // hyperplane levels of the lexicographic element order
   std::vector<int64_t> lev_ptr;
   DevBuf<int> lev_elems;
@@ -312,11 +316,13 @@ static void ensure_work32(dgnp_ctx& c, Precond& P) {
 }
 
 // largest eigenvalue of D_b^{-1} A_phiphi by power iteration on the device, in
-// the arithmetic of the smoother that uses it: 20 steps from a hashed start
-// vector, renormalised every 4 steps; the estimate is the growth of the last
-// step.  The norms stay on the device until the end (one host wait).
+// the arithmetic of the smoother that uses it: from a hashed start vector 20
+// steps, from the previous linearisation point's last vector 8 steps
+// (renormalised every 4 steps; the estimate is the growth of the last step).
+// The norms stay on the device until the end (one host wait).
 template <typename T>
-static double lmax_level0(dgnp_ctx& c, Precond& P, hipStream_t s, const T* blk, const T* dinv, T* x, T* y) {
+static double lmax_level0(dgnp_ctx& c, Precond& P, hipStream_t s, const T* blk, const T* dinv, T* x, T* y,
+                          DevBuf<T>& keep) {
   const int64_t n = c.Nf;
   double* sq = P.red.p;            // [0]: |x|^2 before the last step, [1]: after, [2]: start
   double* part = P.red.p + MAXV;   // block partials
@@ -326,23 +332,33 @@ static double lmax_level0(dgnp_ctx& c, Precond& P, hipStream_t s, const T* blk, 
     else
       vdots_into(v, 0, 1, v, n, out, part, s);
   };
-  vfill_hash<T>(x, n, s);
+  const bool warm = keep.n == size_t(n);
+  if (warm)
+    vcopy<T>(keep.p, x, n, s);
+  else
+    vfill_hash<T>(x, n, s);
   norm2(x, sq + 2);
   vscale_rsqrt_inplace<T>(sq + 2, x, n, s);
-  for (int g = 0; g < 5; ++g) {
+  const int groups = warm ? 2 : 5;
+  for (int g = 0; g < groups; ++g) {
     for (int it = 0; it < 4; ++it) {
       if (it == 3) norm2(x, sq);
       launch_bspmv<T>(c.nb, c.dim, c.E, blk, c.d_nbr.p, x, nullptr, T(1), T(0), y, s);
       launch_bdiag<T>(c.nb, c.E, dinv, y, x, s);
     }
     norm2(x, sq + 1);
-    if (g < 4) vscale_rsqrt_inplace<T>(sq + 1, x, n, s);
+    vscale_rsqrt_inplace<T>(sq + 1, x, n, s);
   }
+  keep.alloc(size_t(n));
+  vcopy<T>(x, keep.p, n, s);
   double h[2] = {0.0, 0.0};
   DGNP_HIP(hipMemcpyAsync(h, sq, sizeof(h), hipMemcpyDeviceToHost, s));
   DGNP_HIP(hipStreamSynchronize(s));
   const double lam = std::sqrt(h[1]) / std::sqrt(h[0]);
-  if (!(lam > 0.0) || !std::isfinite(lam)) throw Error(DGNP_E_NONFINITE, "power iteration failed");
+  if (!(lam > 0.0) || !std::isfinite(lam)) {
+    keep.release();
+    throw Error(DGNP_E_NONFINITE, "power iteration failed");
+  }
   return lam;
 }
 
@@ -371,6 +387,10 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
   PhaseClock clk(s);
   const int64_t per_field = c.E * P.nslot * P.bsz;
   const bool phi = (parts & PC_PHI) != 0, conc = (parts & PC_CONC) != 0;
+  if ((parts & PC_WARM) == 0) {  // cold power iteration: results do not depend on earlier solves
+    P.lvec32.release();
+    P.lvec64.release();
+  }
   P.blk.alloc(size_t(c.m * per_field));
   {
     ScopeTimer tm(c, "assemble", s);
@@ -468,9 +488,9 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
       P.stage.upload(P.cinv32, H.coarse_inv.data(), H.coarse_inv.size(), s);
       ensure_work32(c, P);
       clk.mark("float copies (phi)");
-      P.lmax0 = lmax_level0<float>(c, P, s, P.phi32.p, P.dinv_phi32.p, P.wf[0]->p, P.wf[1]->p);
+      P.lmax0 = lmax_level0<float>(c, P, s, P.phi32.p, P.dinv_phi32.p, P.wf[0]->p, P.wf[1]->p, P.lvec32);
     } else {
-      P.lmax0 = lmax_level0<double>(c, P, s, P.blk.p, P.dinv_phi.p, P.wd[0]->p, P.wd[1]->p);
+      P.lmax0 = lmax_level0<double>(c, P, s, P.blk.p, P.dinv_phi.p, P.wd[0]->p, P.wd[1]->p, P.lvec64);
     }
     clk.mark("lmax level 0");
     P.phi_ok = true;

@@ -469,7 +469,7 @@ int newton_solve(dgnp_ctx& c, double* x, const dgnp_solve_opts& o, dgnp_solve_st
     }
     if (it == o.max_newton) break;
     const auto ts = clk::now();
-    set_state(c, x, o.prec, s, false, false, phi_current ? PC_CONC : PC_ALL);
+    set_state(c, x, o.prec, s, false, false, (phi_current ? PC_CONC : PC_ALL) | PC_WARM);
     phi_current = false;
     st.t_setup += since(ts);
     vcopy<double>(W.r.p, W.b.p, N, s);

@@ -8,7 +8,9 @@ namespace dgnp {
 void precond_symbolic(dgnp_ctx& c);                                   // precond.hip
 // parts of the numeric preconditioner set-up: the potential block with its
 // inverse blocks and multigrid hierarchy, and the concentration BILU(0) factors
-enum { PC_PHI = 1, PC_CONC = 2, PC_ALL = 3 };
+// set-up parts; PC_WARM: the potential's power iteration may start from the
+// previous set-up's last vector (within one Newton solve)
+enum { PC_PHI = 1, PC_CONC = 2, PC_ALL = 3, PC_WARM = 4 };
 void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only = false,
                      int parts = PC_ALL);  // precond.hip
 void precond_apply(dgnp_ctx& c, const void* r, void* z, bool f32, bool transpose, int pc_kind,
