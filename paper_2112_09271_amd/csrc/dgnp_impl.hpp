@@ -112,11 +112,12 @@ struct KArgs {
   unsigned vin_mask;    // fields of the input vector that are read (the others count as zero)
 };
 
-enum Mode { M_RES = 0, M_JAC = 1, M_JACT = 2, M_DPE = 3, M_OBJG = 4, M_DATAT = 5 };
+enum Mode { M_RES = 0, M_JAC = 1, M_JACT = 2, M_DPE = 3, M_OBJG = 4, M_DATAT = 5, M_JACP = 6 };
 
 // Launch one DG operator pass over all elements (kernels_dg.hip).
 //   M_RES / M_DPE: xs = state (double), out = R or dR/dPe
 //   M_JAC / M_JACT: xs = state, vin = v (same type T), out = J v / J^T v
+//   M_JACP: as M_JAC, but only the potential rows of J v are formed and written (out[0, Nf))
 //   M_OBJG: out = dJ/dx, aux[E][2] = per-element (J, dJ/dPe) contributions
 //   M_DATAT: vin = lambda, aux[m][n_bface][nqf] = lambda^T dR/d(data at face points)
 void launch_dg(int dim, int p, int m, bool f32, int mode, const KArgs& A, const void* xs,

@@ -39,8 +39,10 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
   using S = Sz<DIM, P>;
   constexpr int NN = S::NN, NQ = S::NQ, NB = S::NB, NQV = S::NQV, NFN = S::NFN, NQF = S::NQF;
   constexpr int NT = OP_NT(DIM, P);
-  constexpr bool HAS_V = (MODE == M_JAC || MODE == M_JACT || MODE == M_DATAT);
-  constexpr bool VOLUME = (MODE == M_RES || MODE == M_JAC || MODE == M_JACT || MODE == M_DPE);
+  constexpr bool JACF = (MODE == M_JAC || MODE == M_JACP);  // forward Jacobian (all rows / potential rows)
+  constexpr bool HAS_V = (JACF || MODE == M_JACT || MODE == M_DATAT);
+  constexpr bool VOLUME = (MODE == M_RES || JACF || MODE == M_JACT || MODE == M_DPE);
+  constexpr int OUTF = MODE == M_JACP ? 1 : MF;  // output fields formed (M_JACP: the potential's)
   constexpr bool NEED_NB = VOLUME;  // objective and data modes use the own trace only
   constexpr int NARR = HAS_V ? 2 : 1;
   constexpr int NC = DIM + 1;
@@ -130,7 +132,7 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
         T src[MF];
         for (int f = 0; f < MF; ++f) src[f] = A.src ? T(A.src[(f * A.E + e) * NQV + qi]) : T(0);
         vol_res<T, MF, DIM>(ph, val, grad, u, src, cv, cg);
-      } else if constexpr (MODE == M_JAC) {
+      } else if constexpr (JACF) {
         T dv[MF], dg[MF][DIM];
         for (int f = 0; f < MF; ++f) {
           dv[f] = q_v[(f * NC) * NQV + qi];
@@ -147,16 +149,16 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
         for (int f = 0; f < MF; ++f) cv[f] = T(0);
         vol_dpe<T, MF, DIM>(ph, val, uh, cg);
       }
-      for (int f = 0; f < MF; ++f) {
+      for (int f = 0; f < OUTF; ++f) {
         q_v[(f * NC) * NQV + qi] = cv[f] * w;
         for (int d = 0; d < DIM; ++d) q_v[(f * NC + 1 + d) * NQV + qi] = cg[f][d] * w * ih[d];
       }
     }
     __syncthreads();
     if constexpr (DIM == 3)
-      integrate_lines<P, MF, NT, T>(q_v, s_o, t1, t2, tid);
+      integrate_lines<P, OUTF, NT, T>(q_v, s_o, t1, t2, tid);
     else
-      integrate<DIM, P, MF, NT, T>(q_v, s_o, t1, t2, tb, tid);
+      integrate<DIM, P, OUTF, NT, T>(q_v, s_o, t1, t2, tb, tid);
   } else {
     for (int i = tid; i < NBT; i += NT) s_o[i] = T(0);
     __syncthreads();
@@ -299,7 +301,7 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
         }
         if constexpr (MODE == M_RES) {
           face_res<T, MF>(ph, v, g, un, own, Fo, Go);
-        } else if constexpr (MODE == M_JAC || MODE == M_JACT) {
+        } else if constexpr (JACF || MODE == M_JACT) {
           T tv[2][MF], tg[2][MF];
           for (int f = 0; f < MF; ++f) {
             tv[own][f] = fq[trow(fc, 0, NARR - 1, f, 0) * NQF + qf];
@@ -307,7 +309,7 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
             tv[1 - own][f] = fq[trow(fc, 1, NARR - 1, f, 0) * NQF + qf];
             tg[1 - own][f] = fq[trow(fc, 1, NARR - 1, f, 1) * NQF + qf];
           }
-          if constexpr (MODE == M_JAC)
+          if constexpr (JACF)
             face_jac<T, MF>(ph, v, g, tv, tg, un, own, Fo, Go);
           else
             face_jacT<T, MF>(ph, v, g, tv, tg, un, own, Fo, Go);
@@ -333,13 +335,13 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
         }
         if constexpr (MODE == M_RES) {
           bnd_res<T, MF>(ph, v, g, un, cbc, phid, gd, Fo, Go);
-        } else if constexpr (MODE == M_JAC || MODE == M_JACT) {
+        } else if constexpr (JACF || MODE == M_JACT) {
           T tv[MF], tg[MF];
           for (int f = 0; f < MF; ++f) {
             tv[f] = fq[trow(fc, 0, NARR - 1, f, 0) * NQF + qf];
             tg[f] = sd * fq[trow(fc, 0, NARR - 1, f, 1) * NQF + qf];
           }
-          if constexpr (MODE == M_JAC)
+          if constexpr (JACF)
             bnd_jac<T, MF>(ph, v, g, tv, tg, un, cbc, phid, gd, Fo, Go);
           else
             bnd_jacT<T, MF>(ph, v, g, tv, tg, un, cbc, phid, gd, Fo, Go);
@@ -365,7 +367,7 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
       }
     }
     // cf layout [face][field][value / dn][qf]
-    for (int f = 0; f < MF; ++f) {
+    for (int f = 0; f < OUTF; ++f) {
       cf[((fc * MF + f) * 2 + 0) * NQF + qf] = Fo[f] * w;
       cf[((fc * MF + f) * 2 + 1) * NQF + qf] = Go[f] * w * ih[ax];
     }
@@ -390,7 +392,8 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
   // F5: both tangential transposes of one coefficient row in registers
   {
     using C = CT<T, P>;
-    for (int rc = tid; rc < NFACE * MF * 2; rc += NT) {
+    for (int ro = tid; ro < NFACE * OUTF * 2; ro += NT) {
+      const int rc = ((ro / (2 * OUTF)) * MF + (ro / 2) % OUTF) * 2 + (ro & 1);  // row of cf / tnt
       T x[NQF];
 #pragma unroll
       for (int k = 0; k < NQF; ++k) x[k] = cf[rc * NQF + k];
@@ -427,7 +430,7 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
   }
   __syncthreads();
   // F6: every node gathers its value / normal-derivative contributions of all faces
-  for (int idx = tid; idx < NBT; idx += NT) {
+  for (int idx = tid; idx < OUTF * NB; idx += NT) {
     const int f = idx / NB, node = idx % NB;
     const int cx = node % NN, cy = (node / NN) % NN, cz = node / (NN * NN);
     T acc = s_o[idx];
@@ -468,12 +471,14 @@ static void launch_mode(bool f32, int mode, const KArgs& A, const void* xs, cons
                         double* aux, hipStream_t s) {
   if (f32) {
     if (mode == M_JAC) return launch_t<DIM, P, MF, float, M_JAC>(A, xs, vin, out, aux, s);
+    if (mode == M_JACP) return launch_t<DIM, P, MF, float, M_JACP>(A, xs, vin, out, aux, s);
     if (mode == M_JACT) return launch_t<DIM, P, MF, float, M_JACT>(A, xs, vin, out, aux, s);
     throw Error(DGNP_E_ARG, "float arithmetic is offered for the Jacobian applies only");
   }
   switch (mode) {
     case M_RES: return launch_t<DIM, P, MF, double, M_RES>(A, xs, vin, out, aux, s);
     case M_JAC: return launch_t<DIM, P, MF, double, M_JAC>(A, xs, vin, out, aux, s);
+    case M_JACP: return launch_t<DIM, P, MF, double, M_JACP>(A, xs, vin, out, aux, s);
     case M_JACT: return launch_t<DIM, P, MF, double, M_JACT>(A, xs, vin, out, aux, s);
     case M_DPE: return launch_t<DIM, P, MF, double, M_DPE>(A, xs, vin, out, aux, s);
     case M_OBJG: return launch_t<DIM, P, MF, double, M_OBJG>(A, xs, vin, out, aux, s);

@@ -35,7 +35,8 @@ void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assem
   DGNP_HIP(hipStreamSynchronize(s));
 }
 
-void jac_apply(dgnp_ctx& c, const void* v, void* y, bool f32, bool transpose, hipStream_t s, unsigned vmask) {
+void jac_apply(dgnp_ctx& c, const void* v, void* y, bool f32, bool transpose, hipStream_t s, unsigned vmask,
+               bool phi_rows) {
   DGNP_REQUIRE(c.has_state, DGNP_E_STATE, "jacobian_apply before set_state");
   DGNP_REQUIRE(!f32 || c.has_state32, DGNP_E_STATE, "float apply needs set_state with DGNP_F32");
   const void* xs = f32 ? static_cast<const void*>(c.d_x32.p) : static_cast<const void*>(c.d_x.p);
@@ -43,7 +44,7 @@ void jac_apply(dgnp_ctx& c, const void* v, void* y, bool f32, bool transpose, hi
   ScopeTimer tm(c, names[transpose ? 1 : 0][f32 ? 1 : 0], s);
   KArgs A = c.kargs();
   A.vin_mask = vmask;
-  launch_dg(c.dim, c.p, c.m, f32, transpose ? M_JACT : M_JAC, A, xs, v, y, nullptr, s);
+  launch_dg(c.dim, c.p, c.m, f32, transpose ? M_JACT : (phi_rows ? M_JACP : M_JAC), A, xs, v, y, nullptr, s);
 }
 
 dgnp_solve_opts default_solve_opts() {
