@@ -104,7 +104,16 @@ typedef struct {
                               faces (ignored with a manufactured solution); order:
                               box faces 0..5, element faces by element index,
                               face nodes with the lower tangential axis fastest */
+  int32_t phi_mg;          /* potential-block multigrid, DGNP_PHIMG_*: Q1 (0, the
+                              default) smooths the assembled order-p block and
+                              starts the coarse levels at the trilinear (Q1) Galerkin
+                              operator; P (1, orders 2 and 3) is p-multigrid (paper
+                              Sec. 4.2): the order-p level is smoothed matrix-free,
+                              the next level is the same DG discretisation at p = 1
+                              (penalty for p = 1, state injected at the corners),
+                              then the Q1 and smoothed-aggregation levels */
 } dgnp_options;
+enum { DGNP_PHIMG_Q1 = 0, DGNP_PHIMG_P = 1 };
 
 typedef struct {
   double rtol;        /* Newton stop: ||R(x)||_2 <= rtol * ||R(x_0)||_2 */

@@ -1219,6 +1219,83 @@ __global__ void k_q1_restrict(int3 n3, const T* __restrict__ r, T* __restrict__ 
   if (o == 0) rv[v] = T(acc);
 }
 
+// ---------------------------------------------------------------------------
+// p-multigrid transfers between the order-p DG space and the p = 1 DG space on
+// the same mesh: element by element, the p = 1 function (values at the 2^d
+// corners) is interpolated at the order-p GLL nodes (prolongation), and the
+// restriction is its transpose.
+// ---------------------------------------------------------------------------
+// x1[f][e][o] = x[f][e][corner node o]  (m fields; the GLL nodes include the corners)
+template <int DIM, int P>
+__global__ void k_p1_inject(const double* __restrict__ x, double* __restrict__ x1, int m, int64_t E) {
+  constexpr int NN = P + 1;
+  constexpr int NB = DIM == 3 ? NN * NN * NN : NN * NN;
+  constexpr int NV = 1 << DIM;
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t >= int64_t(m) * E * NV) return;
+  const int o = int(t % NV);
+  const int64_t fe = t / NV;  // f * E + e
+  int node = 0, st = 1;
+  for (int d = 0; d < DIM; ++d) {
+    node += ((o >> d) & 1) * P * st;
+    st *= NN;
+  }
+  x1[t] = x[fe * NB + node];
+}
+
+// xp[e][node] = sum_o N_o(node) x1[e][o] + beta xp[e][node]   (one thread per node)
+template <typename T, int DIM, int P>
+__global__ void k_p1_prolong(const T* __restrict__ x1, T* __restrict__ xp, T beta, int64_t E) {
+  constexpr int NN = P + 1;
+  constexpr int NB = DIM == 3 ? NN * NN * NN : NN * NN;
+  constexpr int NV = 1 << DIM;
+  const int64_t gid = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (gid >= E * NB) return;
+  const int64_t e = gid / NB;
+  const int node = int(gid % NB);
+  double acc = 0.0;
+#pragma unroll
+  for (int o = 0; o < NV; ++o) acc += q1_shape<DIM, P>(node, o) * double(x1[e * NV + o]);
+  xp[gid] = T(acc) + (beta != T(0) ? beta * xp[gid] : T(0));
+}
+
+// r1[e][o] = sum_node N_o(node) (rp[e][node] - sub[e][node])   (sub may be null);
+// one thread per (element, corner), contracted one direction at a time
+template <typename T, int DIM, int P>
+__global__ void k_p1_restrict(const T* __restrict__ rp, const T* __restrict__ sub, T* __restrict__ r1, int64_t E) {
+  constexpr int NN = P + 1;
+  constexpr int NB = DIM == 3 ? NN * NN * NN : NN * NN;
+  constexpr int NV = 1 << DIM;
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t >= E * NV) return;
+  const int64_t e = t / NV;
+  const int o = int(t % NV);
+  double phi[3][NN];
+  for (int d = 0; d < 3; ++d)
+    for (int i = 0; i < NN; ++i) {
+      const double xi = c_gll[P - 1][i];
+      phi[d][i] = ((o >> d) & 1) ? 0.5 * (1.0 + xi) : 0.5 * (1.0 - xi);
+    }
+  const T* re = rp + e * NB;
+  const T* se = sub ? sub + e * NB : nullptr;
+  constexpr int NK = DIM == 3 ? NN : 1;
+  double acc = 0.0;
+  for (int k = 0; k < NK; ++k) {
+    double sj = 0.0;
+    for (int j = 0; j < NN; ++j) {
+      double si = 0.0;
+#pragma unroll
+      for (int i = 0; i < NN; ++i) {
+        const int node = (k * NN + j) * NN + i;
+        si += phi[0][i] * (double(re[node]) - (se ? double(se[node]) : 0.0));
+      }
+      sj += phi[1][j] * si;
+    }
+    acc += (DIM == 3 ? phi[2][k] : 1.0) * sj;
+  }
+  r1[t] = T(acc);
+}
+
 // gal[e][s][u][v] = sum_ij N_u(i) A_{e,s}[i][j] N_v(j)   (s = 0 diag, 1 + slot)
 template <int DIM, int P>
 __global__ void __launch_bounds__(BT) k_q1_galerkin(const double* __restrict__ blk, double* __restrict__ gal) {
@@ -1761,6 +1838,55 @@ void launch_q1(bool prolong, int dim, int p, const int* n, const T* a, T* b, T b
   }
   DGNP_HIP(hipGetLastError());
 }
+template <int DIM, int P>
+static void p1_inject_t(const double* x, double* x1, int m, int64_t E, hipStream_t s) {
+  const int64_t tot = int64_t(m) * E * (1 << DIM);
+  hipLaunchKernelGGL((k_p1_inject<DIM, P>), dim3(unsigned((tot + 255) / 256)), dim3(256), 0, s, x, x1, m, E);
+}
+void launch_p1_inject(int dim, int p, const double* x, double* x1, int m, int64_t E, hipStream_t s) {
+  if (E == 0) return;
+  if (dim == 3) {
+    if (p == 2) p1_inject_t<3, 2>(x, x1, m, E, s);
+    else if (p == 3) p1_inject_t<3, 3>(x, x1, m, E, s);
+    else throw Error(DGNP_E_ARG, "p-multigrid needs order 2 or 3");
+  } else {
+    if (p == 2) p1_inject_t<2, 2>(x, x1, m, E, s);
+    else if (p == 3) p1_inject_t<2, 3>(x, x1, m, E, s);
+    else throw Error(DGNP_E_ARG, "p-multigrid needs order 2 or 3");
+  }
+  DGNP_HIP(hipGetLastError());
+}
+
+template <typename T, int DIM, int P>
+static void p1_t(bool prolong, const T* a, const T* sub, T* b, T beta, int64_t E, hipStream_t s) {
+  constexpr int NN = P + 1;
+  constexpr int NB = DIM == 3 ? NN * NN * NN : NN * NN;
+  if (prolong) {
+    const int64_t tot = E * NB;
+    hipLaunchKernelGGL((k_p1_prolong<T, DIM, P>), dim3(unsigned((tot + 255) / 256)), dim3(256), 0, s, a, b, beta, E);
+  } else {
+    const int64_t tot = E << DIM;
+    hipLaunchKernelGGL((k_p1_restrict<T, DIM, P>), dim3(unsigned((tot + 255) / 256)), dim3(256), 0, s, a, sub, b, E);
+  }
+}
+
+template <typename T>
+void launch_p1(bool prolong, int dim, int p, const T* a, const T* sub, T* b, T beta, int64_t E, hipStream_t s) {
+  if (E == 0) return;
+  if (dim == 3) {
+    if (p == 2) p1_t<T, 3, 2>(prolong, a, sub, b, beta, E, s);
+    else if (p == 3) p1_t<T, 3, 3>(prolong, a, sub, b, beta, E, s);
+    else throw Error(DGNP_E_ARG, "p-multigrid needs order 2 or 3");
+  } else {
+    if (p == 2) p1_t<T, 2, 2>(prolong, a, sub, b, beta, E, s);
+    else if (p == 3) p1_t<T, 2, 3>(prolong, a, sub, b, beta, E, s);
+    else throw Error(DGNP_E_ARG, "p-multigrid needs order 2 or 3");
+  }
+  DGNP_HIP(hipGetLastError());
+}
+template void launch_p1<double>(bool, int, int, const double*, const double*, double*, double, int64_t, hipStream_t);
+template void launch_p1<float>(bool, int, int, const float*, const float*, float*, float, int64_t, hipStream_t);
+
 template void launch_q1<double>(bool, int, int, const int*, const double*, double*, double, int64_t, int64_t,
                                 hipStream_t);
 template void launch_q1<float>(bool, int, int, const int*, const float*, float*, float, int64_t, int64_t,
@@ -2034,7 +2160,7 @@ template void launch_ilu_dataflow<float>(int, int, int, const float*, const int*
                                          int64_t, const float*, float*, unsigned*, int*, int, int, hipStream_t);
 
 // One Chebyshev smoothing step on the element-block level, fused:
-//   r = base - A u          (u null: r = base)
+//   r = base - A u - sub    (u null: no product; sub null: no subtrahend)
 //   d = c1 * Dinv r + c2 * dprev   (dprev null: no second term)
 //   x_out = x_in + d        (x_in null: x_out = d)
 // with optional stores of r and d.  One work-group per element; x_out must not
@@ -2043,8 +2169,8 @@ template void launch_ilu_dataflow<float>(int, int, int, const float*, const int*
 template <typename T, int NB, int DIM>
 __global__ void __launch_bounds__(BT) k_cheb_blk(const T* __restrict__ blk, const int* __restrict__ nbr,
                                                  const T* __restrict__ dinv, const T* u, const T* base,
-                                                 const T* dprev, const T* x_in, T c1, T c2, T* r_out, T* d_out,
-                                                 T* x_out) {
+                                                 const T* sub, const T* dprev, const T* x_in, T c1, T c2,
+                                                 T* r_out, T* d_out, T* x_out) {
   constexpr int NSLOT = 2 * DIM + 1;
   using PR = PotRows<T, NB>;
   const int tid = threadIdx.x;
@@ -2081,7 +2207,7 @@ __global__ void __launch_bounds__(BT) k_cheb_blk(const T* __restrict__ blk, cons
     }
     acc = sum8(acc);
     if (row < NB && part == 0) {
-      const float r = base[i * NB + row] - acc;
+      const float r = base[i * NB + row] - acc - (sub ? sub[i * NB + row] : 0.f);
       rv[row] = r;
       if (r_out) r_out[i * NB + row] = r;
     }
@@ -2132,7 +2258,7 @@ __global__ void __launch_bounds__(BT) k_cheb_blk(const T* __restrict__ blk, cons
           acc += __shfl_xor(acc, 2, 64);
         }
         if (part == 0) {
-          const T r = base[i * NB + row] - acc;
+          const T r = base[i * NB + row] - acc - (sub ? sub[i * NB + row] : T(0));
           rs[row] = r;
           if (r_out) r_out[i * NB + row] = r;
         }
@@ -2145,7 +2271,7 @@ __global__ void __launch_bounds__(BT) k_cheb_blk(const T* __restrict__ blk, cons
           for (int s = 0; s < NSLOT; ++s)
             if (nb[s] >= 0) acc += row_dot4<T, NB>(bi + int64_t(s) * NB * NB, xs[s], row, part);
         if (part == 0) {
-          const T r = base[i * NB + row] - acc;
+          const T r = base[i * NB + row] - acc - (sub ? sub[i * NB + row] : T(0));
           rs[row] = r;
           if (r_out) r_out[i * NB + row] = r;
         }
@@ -2167,38 +2293,39 @@ __global__ void __launch_bounds__(BT) k_cheb_blk(const T* __restrict__ blk, cons
 
 template <typename T, int NB, int DIM>
 static void cheb_blk_t(int64_t E, const T* blk, const int* nbr, const T* dinv, const T* u, const T* base,
-                       const T* dprev, const T* x_in, T c1, T c2, T* r_out, T* d_out, T* x_out, hipStream_t s) {
-  hipLaunchKernelGGL((k_cheb_blk<T, NB, DIM>), dim3(unsigned(E)), dim3(BT), 0, s, blk, nbr, dinv, u, base, dprev,
-                     x_in, c1, c2, r_out, d_out, x_out);
+                       const T* sub, const T* dprev, const T* x_in, T c1, T c2, T* r_out, T* d_out, T* x_out,
+                       hipStream_t s) {
+  hipLaunchKernelGGL((k_cheb_blk<T, NB, DIM>), dim3(unsigned(E)), dim3(BT), 0, s, blk, nbr, dinv, u, base, sub,
+                     dprev, x_in, c1, c2, r_out, d_out, x_out);
 }
 
 template <typename T>
 void launch_cheb_blk(int nb, int dim, int64_t E, const T* blk, const int* nbr, const T* dinv, const T* u,
-                     const T* base, const T* dprev, const T* x_in, T c1, T c2, T* r_out, T* d_out, T* x_out,
-                     hipStream_t s) {
+                     const T* base, const T* sub, const T* dprev, const T* x_in, T c1, T c2, T* r_out, T* d_out,
+                     T* x_out, hipStream_t s) {
   if (E == 0) return;
   if (dim == 3) {
     switch (nb) {
-      case 8: cheb_blk_t<T, 8, 3>(E, blk, nbr, dinv, u, base, dprev, x_in, c1, c2, r_out, d_out, x_out, s); break;
-      case 27: cheb_blk_t<T, 27, 3>(E, blk, nbr, dinv, u, base, dprev, x_in, c1, c2, r_out, d_out, x_out, s); break;
-      case 64: cheb_blk_t<T, 64, 3>(E, blk, nbr, dinv, u, base, dprev, x_in, c1, c2, r_out, d_out, x_out, s); break;
+      case 8: cheb_blk_t<T, 8, 3>(E, blk, nbr, dinv, u, base, sub, dprev, x_in, c1, c2, r_out, d_out, x_out, s); break;
+      case 27: cheb_blk_t<T, 27, 3>(E, blk, nbr, dinv, u, base, sub, dprev, x_in, c1, c2, r_out, d_out, x_out, s); break;
+      case 64: cheb_blk_t<T, 64, 3>(E, blk, nbr, dinv, u, base, sub, dprev, x_in, c1, c2, r_out, d_out, x_out, s); break;
       default: throw Error(DGNP_E_ARG, "unsupported block size");
     }
   } else {
     switch (nb) {
-      case 4: cheb_blk_t<T, 4, 2>(E, blk, nbr, dinv, u, base, dprev, x_in, c1, c2, r_out, d_out, x_out, s); break;
-      case 9: cheb_blk_t<T, 9, 2>(E, blk, nbr, dinv, u, base, dprev, x_in, c1, c2, r_out, d_out, x_out, s); break;
-      case 16: cheb_blk_t<T, 16, 2>(E, blk, nbr, dinv, u, base, dprev, x_in, c1, c2, r_out, d_out, x_out, s); break;
+      case 4: cheb_blk_t<T, 4, 2>(E, blk, nbr, dinv, u, base, sub, dprev, x_in, c1, c2, r_out, d_out, x_out, s); break;
+      case 9: cheb_blk_t<T, 9, 2>(E, blk, nbr, dinv, u, base, sub, dprev, x_in, c1, c2, r_out, d_out, x_out, s); break;
+      case 16: cheb_blk_t<T, 16, 2>(E, blk, nbr, dinv, u, base, sub, dprev, x_in, c1, c2, r_out, d_out, x_out, s); break;
       default: throw Error(DGNP_E_ARG, "unsupported block size");
     }
   }
   DGNP_HIP(hipGetLastError());
 }
 template void launch_cheb_blk<double>(int, int, int64_t, const double*, const int*, const double*, const double*,
-                                      const double*, const double*, const double*, double, double, double*,
+                                      const double*, const double*, const double*, const double*, double, double, double*,
                                       double*, double*, hipStream_t);
 template void launch_cheb_blk<float>(int, int, int64_t, const float*, const int*, const float*, const float*,
-                                     const float*, const float*, const float*, float, float, float*, float*,
+                                     const float*, const float*, const float*, const float*, float, float, float*, float*,
                                      float*, hipStream_t);
 
 }  // namespace dgnp

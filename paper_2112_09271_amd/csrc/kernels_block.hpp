@@ -62,12 +62,18 @@ void launch_q1_galerkin(int dim, int p, int64_t E, const double* blk, double* ga
 void launch_vertex_stencil(int dim, const double* gal, const int* nbr, const int* n, int64_t nvert, double* st,
                            hipStream_t s);
 
-// fused Chebyshev step (r = base - A u; d = c1 Dinv r + c2 dprev; x_out = x_in + d),
-// null u / dprev / x_in drop their terms, null r_out / d_out skip those stores
+// fused Chebyshev step (r = base - A u - sub; d = c1 Dinv r + c2 dprev; x_out = x_in + d),
+// null u / sub / dprev / x_in drop their terms, null r_out / d_out skip those stores
 template <typename T>
 void launch_cheb_blk(int nb, int dim, int64_t E, const T* blk, const int* nbr, const T* dinv, const T* u,
-                     const T* base, const T* dprev, const T* x_in, T c1, T c2, T* r_out, T* d_out, T* x_out,
-                     hipStream_t s);
+                     const T* base, const T* sub, const T* dprev, const T* x_in, T c1, T c2, T* r_out, T* d_out,
+                     T* x_out, hipStream_t s);
+// p-multigrid: corner values of the state (m fields, order p -> [m][E][2^d]);
+// transfers between order p and p = 1 DG functions element by element:
+// prolong: b = P a + beta b; restrict: b = P^T (a - sub) (sub may be null)
+void launch_p1_inject(int dim, int p, const double* x, double* x1, int m, int64_t E, hipStream_t s);
+template <typename T>
+void launch_p1(bool prolong, int dim, int p, const T* a, const T* sub, T* b, T beta, int64_t E, hipStream_t s);
 template <typename T>
 void launch_cheb_csr(int n, const int* rp, const int* ci, const T* v, const T* dinv, const T* u, const T* base,
                      const T* dprev, const T* x_in, T c1, T c2, T* r_out, T* d_out, T* x_out, hipStream_t s);

@@ -102,6 +102,20 @@ struct Precond {
   // linearisation points) start from it with fewer steps
   DevBuf<double> lvec64;
   DevBuf<float> lvec32;
+  // p-multigrid on the potential: the order-p level is applied matrix-free
+  // (its inverse diagonal blocks above); the next level is the potential block
+  // re-discretised at p = 1 (nb1 = 2^d nodes per element) at the corner values
+  // x1 of the state, and its Q1 Galerkin operator starts the vertex hierarchy
+  bool pmg = false;
+  int nb1 = 0;
+  DevBuf<double> x1;                // [m][E][nb1]
+  DevBuf<double> blk1, dinv1;       // [E][nslot][nb1][nb1], [E][nb1][nb1]
+  DevBuf<float> blk1_32, dinv1_32;
+  double lmax1 = 1.0;
+  DevBuf<double> lvec1_64;
+  DevBuf<float> lvec1_32;
+  DevBuf<double> mf64;              // order-p operator output [Nf]
+  DevBuf<float> mf32;
   // hyperplane levels of the lexicographic element order
   std::vector<int64_t> lev_ptr;
   DevBuf<int> lev_elems;
@@ -144,11 +158,55 @@ struct Precond {
 
 void precond_destroy(Precond* p) { delete p; }
 
+// ---- typed accessors -------------------------------------------------------------
+template <typename T> struct Sel;
+template <> struct Sel<double> {
+  static double* blk(Precond& P) { return P.blk.p; }
+  static double* dinv(Precond& P) { return P.dinv_phi.p; }
+  static double* cblk(Precond& P, int64_t fstride) { return P.blk.p + fstride; }
+  static double* blk1(Precond& P) { return P.blk1.p; }
+  static double* dinv1(Precond& P) { return P.dinv1.p; }
+  static double* mf(Precond& P) { return P.mf64.p; }
+  static DevBuf<double>& lvec(Precond& P) { return P.lvec64; }
+  static DevBuf<double>& lvec1(Precond& P) { return P.lvec1_64; }
+  static DevCsr<double>& A(MgLevel& L) { return L.A; }
+  static DevCsr<double>& Pm(MgLevel& L) { return L.P; }
+  static DevCsr<double>& R(MgLevel& L) { return L.R; }
+  static double* ldinv(MgLevel& L) { return L.dinv.p; }
+  static double* cinv(Precond& P) { return P.cinv.p; }
+  static double* w(Precond& P, size_t i) { return P.wd[i]->p; }
+  static double* vN(Precond& P) { return P.vN.p; }
+  static double* yN(Precond& P) { return P.yN.p; }
+  static double* tN(Precond& P) { return P.tN.p; }
+};
+template <> struct Sel<float> {
+  static float* blk(Precond& P) { return P.phi32.p; }
+  static float* cblk(Precond& P, int64_t) { return P.blk32.p; }
+  static float* blk1(Precond& P) { return P.blk1_32.p; }
+  static float* dinv1(Precond& P) { return P.dinv1_32.p; }
+  static float* mf(Precond& P) { return P.mf32.p; }
+  static DevBuf<float>& lvec(Precond& P) { return P.lvec32; }
+  static DevBuf<float>& lvec1(Precond& P) { return P.lvec1_32; }
+  static float* dinv(Precond& P) { return P.dinv_phi32.p; }
+  static DevCsr<float>& A(MgLevel& L) { return L.A32; }
+  static DevCsr<float>& Pm(MgLevel& L) { return L.P32; }
+  static DevCsr<float>& R(MgLevel& L) { return L.R32; }
+  static float* ldinv(MgLevel& L) { return L.dinv32.p; }
+  static float* cinv(Precond& P) { return P.cinv32.p; }
+  static float* w(Precond& P, size_t i) { return P.wf[i]->p; }
+  static float* vN(Precond& P) { return P.vN32.p; }
+  static float* yN(Precond& P) { return P.yN32.p; }
+  static float* tN(Precond& P) { return P.tN32.p; }
+};
+
+
 void precond_symbolic(dgnp_ctx& c) {
   if (!c.pc) c.pc = new Precond();
   Precond& P = *c.pc;
   P.nslot = 2 * c.dim + 1;
   P.bsz = int64_t(c.nb) * c.nb;
+  P.pmg = c.phi_mg == DGNP_PHIMG_P;
+  P.nb1 = 1 << c.dim;
   // hyperplane levels ix + iy + iz
   const int L = c.n[0] + c.n[1] + (c.dim == 3 ? c.n[2] : 1) - (c.dim == 3 ? 2 : 1);
   std::vector<std::vector<int>> lv(static_cast<size_t>(L));
@@ -285,45 +343,63 @@ static void upload_csr(DevCsr<T>& D, const Csr& A, PinnedStage& st, hipStream_t 
   st.upload(D.v, A.v.data(), A.v.size(), s);
 }
 
+// per V-cycle level: 5 vectors (x, b, r, d, z) for each precision; arrays of
+// unchanged size are kept.  Levels: the order-p DG level, with p-multigrid the
+// p = 1 DG level, then the vertex / aggregation levels.
+static int64_t level_size(const dgnp_ctx& c, const Precond& P, size_t l) {
+  if (l == 0) return c.Nf;
+  if (P.pmg && l == 1) return c.E * P.nb1;
+  return P.mg[l - (P.pmg ? 2 : 1)].n;
+}
+static size_t level_count(const Precond& P) { return 1 + (P.pmg ? 1 : 0) + P.mg.size(); }
+
 static void ensure_work(dgnp_ctx& c, Precond& P) {
-  // per V-cycle level: 5 vectors (x, b, r, d, z) for each precision; arrays
-  // of unchanged size are kept
-  const size_t nlev = 1 + P.mg.size();
+  const size_t nlev = level_count(P);
   while (P.wd.size() < 5 * nlev) {
     P.wd.emplace_back(new DevBuf<double>());
     P.wf.emplace_back(new DevBuf<float>());
   }
   P.wd.resize(5 * nlev);
   P.wf.resize(5 * nlev);
-  for (size_t l = 0; l < nlev; ++l) {
-    const size_t n = l == 0 ? size_t(c.Nf) : size_t(P.mg[l - 1].n);
-    for (int k = 0; k < 5; ++k) P.wd[l * 5 + k]->alloc(n);
-  }
+  for (size_t l = 0; l < nlev; ++l)
+    for (int k = 0; k < 5; ++k) P.wd[l * 5 + k]->alloc(size_t(level_size(c, P, l)));
   P.vN.alloc(size_t(c.N));
   P.yN.alloc(size_t(c.N));
   P.tN.alloc(size_t(c.N));
+  if (P.pmg) P.mf64.alloc(size_t(c.Nf));
 }
 
 static void ensure_work32(dgnp_ctx& c, Precond& P) {
-  const size_t nlev = 1 + P.mg.size();
-  for (size_t l = 0; l < nlev; ++l) {
-    const size_t n = l == 0 ? size_t(c.Nf) : size_t(P.mg[l - 1].n);
-    for (int k = 0; k < 5; ++k) P.wf[l * 5 + k]->alloc(n);
-  }
+  const size_t nlev = level_count(P);
+  for (size_t l = 0; l < nlev; ++l)
+    for (int k = 0; k < 5; ++k) P.wf[l * 5 + k]->alloc(size_t(level_size(c, P, l)));
   P.vN32.alloc(size_t(c.N));
   P.yN32.alloc(size_t(c.N));
   P.tN32.alloc(size_t(c.N));
+  if (P.pmg) P.mf32.alloc(size_t(c.Nf));
 }
 
-// largest eigenvalue of D_b^{-1} A_phiphi by power iteration on the device, in
+// potential rows of J applied to a potential-only vector: y = A_phiphi x at
+// order p, matrix-free (the Jacobian operator with only the potential input
+// read and only the potential rows formed)
+template <typename T>
+static void phi_mf_apply(dgnp_ctx& c, const T* x, T* y, hipStream_t s) {
+  const bool f32 = std::is_same<T, float>::value;
+  ScopeTimer tm(c, f32 ? "phi_apply_f32" : "phi_apply", s);
+  KArgs A = c.kargs();
+  A.vin_mask = 1u;
+  const void* xs = f32 ? static_cast<const void*>(c.d_x32.p) : static_cast<const void*>(c.d_x.p);
+  launch_dg(c.dim, c.p, c.m, f32, M_JACP, A, xs, x, y, nullptr, s);
+}
+
+// largest eigenvalue of D_b^{-1} A on a potential level by power iteration on the device, in
 // the arithmetic of the smoother that uses it: from a hashed start vector 20
 // steps, from the previous linearisation point's last vector 8 steps
 // (renormalised every 4 steps; the estimate is the growth of the last step).
 // The norms stay on the device until the end (one host wait).
-template <typename T>
-static double lmax_level0(dgnp_ctx& c, Precond& P, hipStream_t s, const T* blk, const T* dinv, T* x, T* y,
-                          DevBuf<T>& keep) {
-  const int64_t n = c.Nf;
+// op(x, y): x <- D^{-1} A x with y as work space (n entries).
+template <typename T, typename Op>
+static double power_lmax(dgnp_ctx& c, Precond& P, hipStream_t s, int64_t n, Op op, T* x, T* y, DevBuf<T>& keep) {
   double* sq = P.red.p;            // [0]: |x|^2 before the last step, [1]: after, [2]: start
   double* part = P.red.p + MAXV;   // block partials
   auto norm2 = [&](const T* v, double* out) {
@@ -343,8 +419,7 @@ static double lmax_level0(dgnp_ctx& c, Precond& P, hipStream_t s, const T* blk, 
   for (int g = 0; g < groups; ++g) {
     for (int it = 0; it < 4; ++it) {
       if (it == 3) norm2(x, sq);
-      launch_bspmv<T>(c.nb, c.dim, c.E, blk, c.d_nbr.p, x, nullptr, T(1), T(0), y, s);
-      launch_bdiag<T>(c.nb, c.E, dinv, y, x, s);
+      op(x, y);
     }
     norm2(x, sq + 1);
     vscale_rsqrt_inplace<T>(sq + 1, x, n, s);
@@ -360,6 +435,15 @@ static double lmax_level0(dgnp_ctx& c, Precond& P, hipStream_t s, const T* blk, 
     throw Error(DGNP_E_NONFINITE, "power iteration failed");
   }
   return lam;
+}
+
+// x <- D_b^{-1} A x on an element-block level (nb rows per block)
+template <typename T>
+static auto block_op(dgnp_ctx& c, int nb, const T* blk, const T* dinv, hipStream_t s) {
+  return [&c, nb, blk, dinv, s](T* x, T* y) {
+    launch_bspmv<T>(nb, c.dim, c.E, blk, c.d_nbr.p, x, nullptr, T(1), T(0), y, s);
+    launch_bdiag<T>(nb, c.E, dinv, y, x, s);
+  };
 }
 
 static bool trace_setup() {
@@ -387,9 +471,11 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
   PhaseClock clk(s);
   const int64_t per_field = c.E * P.nslot * P.bsz;
   const bool phi = (parts & PC_PHI) != 0, conc = (parts & PC_CONC) != 0;
-  if ((parts & PC_WARM) == 0) {  // cold power iteration: results do not depend on earlier solves
+  if ((parts & PC_WARM) == 0) {  // cold power iterations: results do not depend on earlier solves
     P.lvec32.release();
     P.lvec64.release();
+    P.lvec1_32.release();
+    P.lvec1_64.release();
   }
   P.blk.alloc(size_t(c.m * per_field));
   {
@@ -433,10 +519,31 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
       launch_block_inverse(c.nb, c.E, P.blk.p, P.nslot, P.dinv_phi.p, s);
     }
     clk.mark("block inverse");
-    // Galerkin projection of A_phiphi onto Q1 vertices, then host SA setup
+    // p-multigrid: the potential block re-discretised at p = 1 (interior
+    // penalty for p = 1) at the state's corner values, and its inverse blocks
+    const double* gal_blk = P.blk.p;
+    int gal_p = c.p;
+    if (P.pmg) {
+      P.x1.alloc(size_t(c.m) * c.E * P.nb1);
+      launch_p1_inject(c.dim, c.p, c.d_x.p, P.x1.p, c.m, c.E, s);
+      KArgs A1 = c.kargs();
+      A1.delta = c.delta / double(c.p * c.p);
+      P.blk1.alloc(size_t(c.E) * P.nslot * P.nb1 * P.nb1);
+      {
+        ScopeTimer tm(c, "assemble", s);
+        launch_assemble(c.dim, 1, c.m, 0, 1, A1, P.x1.p, P.blk1.p, s);
+      }
+      P.dinv1.alloc(size_t(c.E) * P.nb1 * P.nb1);
+      launch_block_inverse(P.nb1, c.E, P.blk1.p, P.nslot, P.dinv1.p, s);
+      gal_blk = P.blk1.p;
+      gal_p = 1;
+      clk.mark("p = 1 level");
+    }
+    // Galerkin projection onto Q1 vertices (of the order-p block, or of the
+    // p = 1 block with p-multigrid), then host SA setup
     const int NV = 1 << c.dim;
     P.gal.alloc(size_t(c.E) * P.nslot * NV * NV);
-    launch_q1_galerkin(c.dim, c.p, c.E, P.blk.p, P.gal.p, s);
+    launch_q1_galerkin(c.dim, gal_p, c.E, gal_blk, P.gal.p, s);
     P.vst.alloc(size_t(P.nvert) * (c.dim == 3 ? 27 : 9));
     launch_vertex_stencil(c.dim, P.gal.p, c.d_nbr.p, c.n, P.nvert, P.vst.p, s);
     std::vector<double> st(P.vst.n);
@@ -486,12 +593,41 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
         P.stage.upload(L.dinv32, H.dinv[l].data(), H.dinv[l].size(), s);
       }
       P.stage.upload(P.cinv32, H.coarse_inv.data(), H.coarse_inv.size(), s);
+      if (P.pmg) {
+        P.blk1_32.alloc(P.blk1.n);
+        cvt_d2f(P.blk1.p, P.blk1_32.p, int64_t(P.blk1.n), s);
+        P.dinv1_32.alloc(P.dinv1.n);
+        cvt_d2f(P.dinv1.p, P.dinv1_32.p, int64_t(P.dinv1.n), s);
+      }
       ensure_work32(c, P);
       clk.mark("float copies (phi)");
-      P.lmax0 = lmax_level0<float>(c, P, s, P.phi32.p, P.dinv_phi32.p, P.wf[0]->p, P.wf[1]->p, P.lvec32);
-    } else {
-      P.lmax0 = lmax_level0<double>(c, P, s, P.blk.p, P.dinv_phi.p, P.wd[0]->p, P.wd[1]->p, P.lvec64);
     }
+    // lambda_max of the smoothers' D^{-1} A on the potential levels, in the
+    // arithmetic of the smoother
+    auto lmax_levels = [&](auto tag) {
+      using T = decltype(tag);
+      T* x0 = Sel<T>::w(P, 0);
+      T* y0 = Sel<T>::w(P, 1);
+      DevBuf<T>& keep0 = Sel<T>::lvec(P);
+      if (P.pmg) {
+        const T* dv = Sel<T>::dinv(P);
+        auto op0 = [&](T* x, T* y) {
+          phi_mf_apply<T>(c, x, y, s);
+          launch_bdiag<T>(c.nb, c.E, dv, y, x, s);
+        };
+        P.lmax0 = power_lmax<T>(c, P, s, c.Nf, op0, x0, y0, keep0);
+        DevBuf<T>& keep1 = Sel<T>::lvec1(P);
+        P.lmax1 = power_lmax<T>(c, P, s, c.E * P.nb1, block_op<T>(c, P.nb1, Sel<T>::blk1(P), Sel<T>::dinv1(P), s),
+                                Sel<T>::w(P, 5), Sel<T>::w(P, 6), keep1);
+      } else {
+        P.lmax0 = power_lmax<T>(c, P, s, c.Nf, block_op<T>(c, c.nb, Sel<T>::blk(P), Sel<T>::dinv(P), s), x0, y0,
+                                keep0);
+      }
+    };
+    if (f32)
+      lmax_levels(float(0));
+    else
+      lmax_levels(double(0));
     clk.mark("lmax level 0");
     P.phi_ok = true;
     P.phi32_ok = f32;
@@ -522,87 +658,79 @@ void get_block(dgnp_ctx& c, int field, int64_t elem, int slot, double* out) {
   DGNP_HIP(hipMemcpy(out, P.blk.p + off, size_t(P.bsz) * sizeof(double), hipMemcpyDeviceToHost));
 }
 
-// ---- typed accessors -------------------------------------------------------------
-template <typename T> struct Sel;
-template <> struct Sel<double> {
-  static double* blk(Precond& P) { return P.blk.p; }
-  static double* dinv(Precond& P) { return P.dinv_phi.p; }
-  static double* cblk(Precond& P, int64_t fstride) { return P.blk.p + fstride; }
-  static DevCsr<double>& A(MgLevel& L) { return L.A; }
-  static DevCsr<double>& Pm(MgLevel& L) { return L.P; }
-  static DevCsr<double>& R(MgLevel& L) { return L.R; }
-  static double* ldinv(MgLevel& L) { return L.dinv.p; }
-  static double* cinv(Precond& P) { return P.cinv.p; }
-  static double* w(Precond& P, size_t i) { return P.wd[i]->p; }
-  static double* vN(Precond& P) { return P.vN.p; }
-  static double* yN(Precond& P) { return P.yN.p; }
-  static double* tN(Precond& P) { return P.tN.p; }
-};
-template <> struct Sel<float> {
-  static float* blk(Precond& P) { return P.phi32.p; }
-  static float* cblk(Precond& P, int64_t) { return P.blk32.p; }
-  static float* dinv(Precond& P) { return P.dinv_phi32.p; }
-  static DevCsr<float>& A(MgLevel& L) { return L.A32; }
-  static DevCsr<float>& Pm(MgLevel& L) { return L.P32; }
-  static DevCsr<float>& R(MgLevel& L) { return L.R32; }
-  static float* ldinv(MgLevel& L) { return L.dinv32.p; }
-  static float* cinv(Precond& P) { return P.cinv32.p; }
-  static float* w(Precond& P, size_t i) { return P.wf[i]->p; }
-  static float* vN(Precond& P) { return P.vN32.p; }
-  static float* yN(Precond& P) { return P.yN32.p; }
-  static float* tN(Precond& P) { return P.tN32.p; }
-};
-
 // ---- V-cycle -----------------------------------------------------------------------
+// Levels: 0 = the order-p DG space; with p-multigrid 0 is applied matrix-free
+// and 1 is the p = 1 DG space (element blocks); the element-block level is
+// followed by the vertex (Q1) and aggregation levels (CSR), the last of which
+// is solved with its dense inverse.
 template <typename T>
 struct Mg {
   dgnp_ctx& c;
   Precond& P;
   hipStream_t s;
-  int64_t size(int l) const { return l == 0 ? c.Nf : P.mg[l - 1].n; }
-  // y = alpha A x + beta b
-  void A(int l, const T* x, const T* b, T alpha, T beta, T* y) {
-    if (l == 0)
-      launch_bspmv<T>(c.nb, c.dim, c.E, Sel<T>::blk(P), c.d_nbr.p, x, b, alpha, beta, y, s);
-    else {
-      DevCsr<T>& M = Sel<T>::A(P.mg[l - 1]);
-      launch_csr_spmv<T>(M.n, M.rp.p, M.ci.p, M.v.p, x, b, alpha, beta, y, s);
+  static constexpr bool F32 = std::is_same<T, float>::value;
+  int top() const { return P.pmg ? 1 : 0; }  // index of the element-block level
+  bool mf(int l) const { return P.pmg && l == 0; }
+  MgLevel& csr(int l) const { return P.mg[size_t(l - top() - 1)]; }
+  int64_t size(int l) const { return level_size(c, P, size_t(l)); }
+  // element-block level data
+  int bnb() const { return P.pmg ? P.nb1 : c.nb; }
+  int bp() const { return P.pmg ? 1 : c.p; }
+  const T* bblk() const { return P.pmg ? Sel<T>::blk1(P) : Sel<T>::blk(P); }
+  const T* bdinv() const { return P.pmg ? Sel<T>::dinv1(P) : Sel<T>::dinv(P); }
+  double lmax(int l) const {
+    if (l == 0) return P.lmax0;
+    if (P.pmg && l == 1) return P.lmax1;
+    return csr(l).lmax;
+  }
+  // rc = R (b - A x): the residual of level l restricted to level l + 1
+  void residual_restrict(int l, const T* x, const T* b, T* r, T* rc) {
+    if (mf(l)) {
+      phi_mf_apply<T>(c, x, r, s);
+      launch_p1<T>(false, c.dim, c.p, b, r, rc, T(0), c.E, s);
+      return;
     }
-  }
-  void Dinv(int l, const T* x, T* y) {
-    if (l == 0)
-      launch_bdiag<T>(c.nb, c.E, Sel<T>::dinv(P), x, y, s);
-    else
-      launch_vmul<T>(size(l), Sel<T>::ldinv(P.mg[l - 1]), x, y, s);
-  }
-  double lmax(int l) const { return l == 0 ? P.lmax0 : P.mg[l - 1].lmax; }
-  void restrict_(int l, const T* r, T* rc) {
-    if (l == 0) {
-      launch_q1<T>(false, c.dim, c.p, c.n, r, rc, T(0), c.E, P.nvert, s);
+    if (l == top()) {
+      launch_bspmv<T>(bnb(), c.dim, c.E, bblk(), c.d_nbr.p, x, b, T(-1), T(1), r, s);
+      launch_q1<T>(false, c.dim, bp(), c.n, r, rc, T(0), c.E, P.nvert, s);
     } else {
-      DevCsr<T>& R = Sel<T>::R(P.mg[l - 1]);
+      DevCsr<T>& M = Sel<T>::A(csr(l));
+      launch_csr_spmv<T>(M.n, M.rp.p, M.ci.p, M.v.p, x, b, T(-1), T(1), r, s);
+      DevCsr<T>& R = Sel<T>::R(csr(l));
       launch_csr_spmv<T>(R.n, R.rp.p, R.ci.p, R.v.p, r, nullptr, T(1), T(0), rc, s);
     }
   }
   void prolong_add(int l, const T* xc, T* x) {
-    if (l == 0) {
-      launch_q1<T>(true, c.dim, c.p, c.n, xc, x, T(1), c.E, P.nvert, s);
+    if (mf(l)) {
+      launch_p1<T>(true, c.dim, c.p, xc, nullptr, x, T(1), c.E, s);
+    } else if (l == top()) {
+      launch_q1<T>(true, c.dim, bp(), c.n, xc, x, T(1), c.E, P.nvert, s);
     } else {
-      DevCsr<T>& Pm = Sel<T>::Pm(P.mg[l - 1]);
+      DevCsr<T>& Pm = Sel<T>::Pm(csr(l));
       launch_csr_spmv<T>(Pm.n, Pm.rp.p, Pm.ci.p, Pm.v.p, xc, x, T(1), T(1), x, s);
     }
   }
   // one fused Chebyshev step on level l (see launch_cheb_blk)
   void step(int l, const T* u, const T* base, const T* dprev, const T* x_in, double c1, double c2, T* r_out,
             T* d_out, T* x_out) {
-    if (l == 0) {
-      ScopeTimer tm(c, std::is_same<T, float>::value ? "cheb_blk_f32" : "cheb_blk", s);
-      launch_cheb_blk<T>(c.nb, c.dim, c.E, Sel<T>::blk(P), c.d_nbr.p, Sel<T>::dinv(P), u, base, dprev, x_in, T(c1),
+    if (mf(l)) {
+      // r = base - A u with the matrix-free product, then the block-diagonal step
+      T* y = nullptr;
+      if (u) {
+        y = Sel<T>::mf(P);
+        phi_mf_apply<T>(c, u, y, s);
+      }
+      ScopeTimer tm(c, F32 ? "cheb_mf_f32" : "cheb_mf", s);
+      launch_cheb_blk<T>(c.nb, c.dim, c.E, Sel<T>::blk(P), c.d_nbr.p, Sel<T>::dinv(P), nullptr, base, y, dprev, x_in,
+                         T(c1), T(c2), r_out, d_out, x_out, s);
+    } else if (l == top()) {
+      ScopeTimer tm(c, P.pmg ? (F32 ? "cheb_blk1_f32" : "cheb_blk1") : (F32 ? "cheb_blk_f32" : "cheb_blk"), s);
+      launch_cheb_blk<T>(bnb(), c.dim, c.E, bblk(), c.d_nbr.p, bdinv(), u, base, nullptr, dprev, x_in, T(c1),
                          T(c2), r_out, d_out, x_out, s);
     } else {
-      DevCsr<T>& M = Sel<T>::A(P.mg[l - 1]);
-      launch_cheb_csr<T>(M.n, M.rp.p, M.ci.p, M.v.p, Sel<T>::ldinv(P.mg[l - 1]), u, base, dprev, x_in, T(c1),
-                         T(c2), r_out, d_out, x_out, s);
+      DevCsr<T>& M = Sel<T>::A(csr(l));
+      launch_cheb_csr<T>(M.n, M.rp.p, M.ci.p, M.v.p, Sel<T>::ldinv(csr(l)), u, base, dprev, x_in, T(c1), T(c2),
+                         r_out, d_out, x_out, s);
     }
   }
   // Chebyshev smoothing of degree 2 on [0.1, 1.1] * lmax(D^{-1} A):
@@ -627,17 +755,16 @@ struct Mg {
     }
   }
   void vcycle(int l, const T* b, T* x) {
-    const int last = int(P.mg.size());
+    const int last = top() + int(P.mg.size());
     if (l == last) {
       launch_dense_gemv<T>(P.nc, Sel<T>::cinv(P), b, x, s);
       return;
     }
     cheb(l, b, x, true);
     T* r = Sel<T>::w(P, size_t(l) * 5 + 2);
-    A(l, x, b, T(-1), T(1), r);
     T* bc = Sel<T>::w(P, size_t(l + 1) * 5 + 1);
     T* xc = Sel<T>::w(P, size_t(l + 1) * 5 + 0);
-    restrict_(l, r, bc);
+    residual_restrict(l, x, b, r, bc);
     vcycle(l + 1, bc, xc);
     prolong_add(l, xc, x);
     cheb(l, b, x, false);

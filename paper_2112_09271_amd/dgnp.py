@@ -21,6 +21,7 @@ DGNP_F64, DGNP_F32 = 0, 1
 DGNP_STATE_ASSEMBLE_ONLY = 0x100
 DGNP_STATE_APPLY_ONLY = 0x200
 DGNP_PC_P2, DGNP_PC_P1 = 0, 1
+DGNP_PHIMG_Q1, DGNP_PHIMG_P = 0, 1  # potential multigrid: Q1 Galerkin start / p-multigrid
 MAX_HIST = 64
 
 
@@ -38,7 +39,8 @@ class dgnp_velocity(C.Structure):
 
 
 class dgnp_options(C.Structure):
-    _fields_ = [("c_ip", C.c_double), ("mms", C.c_int32), ("bc_conc", C.POINTER(C.c_double))]
+    _fields_ = [("c_ip", C.c_double), ("mms", C.c_int32), ("bc_conc", C.POINTER(C.c_double)),
+                ("phi_mg", C.c_int32)]
 
 
 class dgnp_solve_opts(C.Structure):
@@ -163,9 +165,10 @@ class Problem:
     """One CNP problem on the current GPU.  `cfg` carries the fields of
     workload.configs.Config (mesh, order, species, velocity, boundary kinds);
     `bc_conc` the nodal boundary data [m-1][n_bnode] (None with a manufactured
-    solution)."""
+    solution); `phi_mg` the potential-block multigrid (DGNP_PHIMG_Q1 or, for
+    orders 2 and 3, DGNP_PHIMG_P: p-multigrid)."""
 
-    def __init__(self, cfg, bc_conc=None, Pe=None):
+    def __init__(self, cfg, bc_conc=None, Pe=None, phi_mg=0):
         import torch
         self.cfg = cfg
         d = cfg.dim
@@ -190,6 +193,7 @@ class Problem:
         opt = dgnp_options()
         opt.c_ip = cfg.c_ip
         opt.mms = cfg.mms
+        opt.phi_mg = int(phi_mg)
         self._bc = None
         if bc_conc is not None:
             self._bc = np.ascontiguousarray(bc_conc, dtype=np.float64)

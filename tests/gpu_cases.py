@@ -19,12 +19,12 @@ def config(name, **kw):
     return cfg.with_(**kw) if kw else cfg
 
 
-def pair(name, with_oracle=True, **kw):
+def pair(name, with_oracle=True, phi_mg=0, **kw):
     from paper_2112_09271_amd.dgnp import Problem
     cfg = config(name, **kw)
     data = None if cfg.mms else boundary_data(cfg)
-    print(f"[case] {name} n={cfg.n} p={cfg.p} m={cfg.m}", flush=True)
-    gp = Problem(cfg, data)
+    print(f"[case] {name} n={cfg.n} p={cfg.p} m={cfg.m} phi_mg={phi_mg}", flush=True)
+    gp = Problem(cfg, data, phi_mg=phi_mg)
     od = None
     if with_oracle:
         od = DG(OProblem(cfg) if cfg.mms else OProblem(cfg, data))
