@@ -203,10 +203,11 @@ def apply_bandwidth(name, reps=20):
 def channel_solves(names):
     """Time-to-solution on the channel configurations: mixed and FP64 solves from
     the initial guess to 1e-8 (after one untimed mixed solve), their agreement,
-    and on the largest one a mixed-precision adjoint gradient."""
+    on the largest one a mixed-precision adjoint gradient, and the mixed solve
+    with p-multigrid on the potential block."""
     import torch
 
-    from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64, Problem
+    from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64, DGNP_PHIMG_P, Problem
     from workload import boundary_data, get_config
     out = {}
     for name in names:
@@ -239,7 +240,17 @@ def channel_solves(names):
             rec["adjoint_s"] = time.perf_counter() - t0
         log(f"[bench] {name}: mixed {t32:.3f}s fp64 {t64:.3f}s ({st32.lin_its_total} / {st64.lin_its_total} its)")
         prob.close()
-        del x32, x64
+        del x64
+        torch.cuda.empty_cache()
+        # the same mixed solve with p-multigrid on the potential block
+        prob = Problem(cfg, boundary_data(cfg), phi_mg=DGNP_PHIMG_P)
+        run(DGNP_F32)
+        xp, stp, tp = run(DGNP_F32)
+        rec["pmg"] = {"mixed_s": tp, "fgmres_its": stp.lin_its_total, "setup_s": stp.t_setup,
+                      "krylov_s": stp.t_krylov, "vs_default_rel_l2": (xp - x32).norm().item() / x32.norm().item()}
+        log(f"[bench] {name}: p-multigrid mixed {tp:.3f}s ({stp.lin_its_total} its)")
+        prob.close()
+        del x32, xp
         torch.cuda.empty_cache()
         out[name] = rec
     return out

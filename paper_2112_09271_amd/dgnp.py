@@ -287,7 +287,8 @@ class Problem:
     TIMER_NAMES = ("residual", "jac_apply", "jac_apply_f32", "jacT_apply", "jacT_apply_f32", "assemble",
                    "block_inverse", "ilu_factor", "ilu_fwd", "ilu_bwd", "ilu_fwdT", "ilu_bwdT", "ilu_fwd_f32",
                    "ilu_bwd_f32", "ilu_fwdT_f32", "ilu_bwdT_f32", "vcycle", "vcycle_f32", "bspmv",
-                   "bspmv_f32", "cgs2", "cheb_blk", "cheb_blk_f32")
+                   "bspmv_f32", "cgs2", "cheb_blk", "cheb_blk_f32", "cheb_mf", "cheb_mf_f32", "cheb_blk1",
+                   "cheb_blk1_f32", "phi_apply", "phi_apply_f32")
 
     def profile(self, enable=True, reset=True):
         """Turn per-kernel event timing on or off (reset clears the counters)."""
