@@ -204,10 +204,10 @@ def channel_solves(names):
     """Time-to-solution on the channel configurations: mixed and FP64 solves from
     the initial guess to 1e-8 (after one untimed mixed solve), their agreement,
     on the largest one a mixed-precision adjoint gradient, and the mixed solve
-    with p-multigrid on the potential block."""
+    with the other potential-block multigrids."""
     import torch
 
-    from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64, DGNP_PHIMG_P, Problem
+    from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64, DGNP_PHIMG_P, DGNP_PHIMG_Q1, Problem
     from workload import boundary_data, get_config
     out = {}
     for name in names:
@@ -242,16 +242,24 @@ def channel_solves(names):
         prob.close()
         del x64
         torch.cuda.empty_cache()
-        # the same mixed solve with p-multigrid on the potential block
-        prob = Problem(cfg, boundary_data(cfg), phi_mg=DGNP_PHIMG_P)
-        run(DGNP_F32)
-        xp, stp, tp = run(DGNP_F32)
-        rec["pmg"] = {"mixed_s": tp, "fgmres_its": stp.lin_its_total, "setup_s": stp.t_setup,
-                      "krylov_s": stp.t_krylov, "vs_default_rel_l2": (xp - x32).norm().item() / x32.norm().item()}
-        log(f"[bench] {name}: p-multigrid mixed {tp:.3f}s ({stp.lin_its_total} its)")
-        prob.close()
-        del x32, xp
-        torch.cuda.empty_cache()
+        # the same mixed solve with the other potential multigrids (the default at
+        # p = 3 is p-multigrid with the Galerkin p = 1 level)
+        rec["phi_mg"] = "PG (p-multigrid, Galerkin p = 1 level)" if cfg.p >= 3 else "Q1"
+        rec["alternatives"] = {}
+        for label, mode in (("Q1", DGNP_PHIMG_Q1), ("P", DGNP_PHIMG_P)):
+            if label == "Q1" and cfg.p < 3:
+                continue
+            prob = Problem(cfg, boundary_data(cfg), phi_mg=mode)
+            run(DGNP_F32)
+            xp, stp, tp = run(DGNP_F32)
+            rec["alternatives"][label] = {
+                "mixed_s": tp, "fgmres_its": stp.lin_its_total, "setup_s": stp.t_setup, "krylov_s": stp.t_krylov,
+                "vs_default_rel_l2": (xp - x32).norm().item() / x32.norm().item()}
+            log(f"[bench] {name}: phi_mg {label} mixed {tp:.3f}s ({stp.lin_its_total} its)")
+            prob.close()
+            del xp
+            torch.cuda.empty_cache()
+        del x32
         out[name] = rec
     return out
 

@@ -104,16 +104,19 @@ typedef struct {
                               faces (ignored with a manufactured solution); order:
                               box faces 0..5, element faces by element index,
                               face nodes with the lower tangential axis fastest */
-  int32_t phi_mg;          /* potential-block multigrid, DGNP_PHIMG_*: Q1 (0, the
-                              default) smooths the assembled order-p block and
-                              starts the coarse levels at the trilinear (Q1) Galerkin
-                              operator; P (1, orders 2 and 3) is p-multigrid (paper
-                              Sec. 4.2): the order-p level is smoothed matrix-free,
-                              the next level is the same DG discretisation at p = 1
-                              (penalty for p = 1, state injected at the corners),
-                              then the Q1 and smoothed-aggregation levels */
+  int32_t phi_mg;          /* potential-block multigrid, DGNP_PHIMG_*:
+                              Q1: smooth the assembled order-p block and start the
+                              coarse levels at the trilinear (Q1) Galerkin operator;
+                              P (orders 2, 3): p-multigrid (paper Sec. 4.2), the
+                              order-p level smoothed matrix-free and the next level
+                              the same DG discretisation at p = 1 (penalty for
+                              p = 1, state injected at the element corners), then
+                              the Q1 and smoothed-aggregation levels;
+                              PG (orders 2, 3): as P, with the p = 1 level the
+                              Galerkin product P^T A_p P of the order-p block;
+                              AUTO (0, the default): Q1 for p <= 2, PG for p = 3 */
 } dgnp_options;
-enum { DGNP_PHIMG_Q1 = 0, DGNP_PHIMG_P = 1 };
+enum { DGNP_PHIMG_AUTO = 0, DGNP_PHIMG_Q1 = 1, DGNP_PHIMG_P = 2, DGNP_PHIMG_PG = 3 };
 
 typedef struct {
   double rtol;        /* Newton stop: ||R(x)||_2 <= rtol * ||R(x_0)||_2 */

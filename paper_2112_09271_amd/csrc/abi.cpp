@@ -181,8 +181,9 @@ int dgnp_setup(const dgnp_mesh* mesh, int32_t order, const dgnp_species* sp, con
     c->c_ip = opt ? opt->c_ip : 10.0;
     c->delta = c->c_ip * order * order / std::sqrt(diam2);
     c->mms = opt ? opt->mms : 0;
-    c->phi_mg = opt ? opt->phi_mg : DGNP_PHIMG_Q1;
-    DGNP_REQUIRE(c->phi_mg == DGNP_PHIMG_Q1 || c->phi_mg == DGNP_PHIMG_P, DGNP_E_ARG, "unknown phi_mg");
+    c->phi_mg = opt ? opt->phi_mg : DGNP_PHIMG_AUTO;
+    DGNP_REQUIRE(c->phi_mg >= DGNP_PHIMG_AUTO && c->phi_mg <= DGNP_PHIMG_PG, DGNP_E_ARG, "unknown phi_mg");
+    if (c->phi_mg == DGNP_PHIMG_AUTO) c->phi_mg = order >= 3 ? DGNP_PHIMG_PG : DGNP_PHIMG_Q1;
     DGNP_REQUIRE(c->phi_mg == DGNP_PHIMG_Q1 || order >= 2, DGNP_E_ARG, "p-multigrid needs order 2 or 3");
     DGNP_REQUIRE(c->mms == 0 || c->m == 2, DGNP_E_ARG, "manufactured solutions need two ions");
     DGNP_REQUIRE(c->mms >= 0 && c->mms <= 2, DGNP_E_ARG, "unknown manufactured solution");

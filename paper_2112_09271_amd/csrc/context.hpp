@@ -18,7 +18,7 @@ struct dgnp_ctx {
   double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1}, h[3] = {1, 1, 1};
   double z[4] = {}, D[4] = {}, a[4] = {}, b[4] = {};
   double delta = 0, c_ip = 10;
-  int phi_mg = 0;                 // DGNP_PHIMG_*
+  int phi_mg = 1;                 // DGNP_PHIMG_Q1 / _P / _PG (AUTO resolved at setup)
   int mms = 0;
   dgnp_velocity vel{};
   int c_bc[6] = {}, phi_bc[6] = {};

@@ -107,6 +107,7 @@ struct Precond {
   // re-discretised at p = 1 (nb1 = 2^d nodes per element) at the corner values
   // x1 of the state, and its Q1 Galerkin operator starts the vertex hierarchy
   bool pmg = false;
+  bool pmg_galerkin = false;         // p = 1 level: Galerkin product instead of re-discretisation
   int nb1 = 0;
   DevBuf<double> x1;                // [m][E][nb1]
   DevBuf<double> blk1, dinv1;       // [E][nslot][nb1][nb1], [E][nb1][nb1]
@@ -205,7 +206,8 @@ void precond_symbolic(dgnp_ctx& c) {
   Precond& P = *c.pc;
   P.nslot = 2 * c.dim + 1;
   P.bsz = int64_t(c.nb) * c.nb;
-  P.pmg = c.phi_mg == DGNP_PHIMG_P;
+  P.pmg = c.phi_mg == DGNP_PHIMG_P || c.phi_mg == DGNP_PHIMG_PG;
+  P.pmg_galerkin = c.phi_mg == DGNP_PHIMG_PG;
   P.nb1 = 1 << c.dim;
   // hyperplane levels ix + iy + iz
   const int L = c.n[0] + c.n[1] + (c.dim == 3 ? c.n[2] : 1) - (c.dim == 3 ? 2 : 1);
@@ -519,8 +521,9 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
       launch_block_inverse(c.nb, c.E, P.blk.p, P.nslot, P.dinv_phi.p, s);
     }
     clk.mark("block inverse");
-    // p-multigrid: the potential block re-discretised at p = 1 (interior
-    // penalty for p = 1) at the state's corner values, and its inverse blocks
+    // p-multigrid: the potential block at p = 1, re-discretised (interior
+    // penalty for p = 1, at the state's corner values) or as the Galerkin
+    // product of the order-p block, and its inverse blocks
     const double* gal_blk = P.blk.p;
     int gal_p = c.p;
     if (P.pmg) {
@@ -529,7 +532,10 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
       KArgs A1 = c.kargs();
       A1.delta = c.delta / double(c.p * c.p);
       P.blk1.alloc(size_t(c.E) * P.nslot * P.nb1 * P.nb1);
-      {
+      if (P.pmg_galerkin) {
+        // P^T A_p P block by block (P: the element-local p = 1 -> p interpolation)
+        launch_q1_galerkin(c.dim, c.p, c.E, P.blk.p, P.blk1.p, s);
+      } else {
         ScopeTimer tm(c, "assemble", s);
         launch_assemble(c.dim, 1, c.m, 0, 1, A1, P.x1.p, P.blk1.p, s);
       }

@@ -21,7 +21,8 @@ DGNP_F64, DGNP_F32 = 0, 1
 DGNP_STATE_ASSEMBLE_ONLY = 0x100
 DGNP_STATE_APPLY_ONLY = 0x200
 DGNP_PC_P2, DGNP_PC_P1 = 0, 1
-DGNP_PHIMG_Q1, DGNP_PHIMG_P = 0, 1  # potential multigrid: Q1 Galerkin start / p-multigrid
+# potential multigrid: automatic / Q1 Galerkin start / p-multigrid (re-discretised, Galerkin p = 1 level)
+DGNP_PHIMG_AUTO, DGNP_PHIMG_Q1, DGNP_PHIMG_P, DGNP_PHIMG_PG = 0, 1, 2, 3
 MAX_HIST = 64
 
 
@@ -165,8 +166,9 @@ class Problem:
     """One CNP problem on the current GPU.  `cfg` carries the fields of
     workload.configs.Config (mesh, order, species, velocity, boundary kinds);
     `bc_conc` the nodal boundary data [m-1][n_bnode] (None with a manufactured
-    solution); `phi_mg` the potential-block multigrid (DGNP_PHIMG_Q1 or, for
-    orders 2 and 3, DGNP_PHIMG_P: p-multigrid)."""
+    solution); `phi_mg` the potential-block multigrid (DGNP_PHIMG_AUTO: Q1 for
+    p <= 2, PG for p = 3; DGNP_PHIMG_Q1; for orders 2 and 3 DGNP_PHIMG_P or
+    DGNP_PHIMG_PG: p-multigrid with a re-discretised or Galerkin p = 1 level)."""
 
     def __init__(self, cfg, bc_conc=None, Pe=None, phi_mg=0):
         import torch

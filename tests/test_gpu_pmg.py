@@ -11,12 +11,14 @@ pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="n
 
 
 @pytest.mark.parametrize("name", ["cfg2t", "cfg3s", "cfg1"])
-def test_pmg_preconditioner_symmetric_and_transposed(name):
+@pytest.mark.parametrize("mode", ["P", "PG"])
+def test_pmg_preconditioner_symmetric_and_transposed(name, mode):
     """With symmetric smoothing and restriction = prolongation^T the potential
     V-cycle is symmetric, and <P r, w> = <r, P^T w> for the whole block
     preconditioner, double and float."""
-    from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64, DGNP_PHIMG_P
-    cfg, _, gp = pair(name, with_oracle=False, phi_mg=DGNP_PHIMG_P)
+    from paper_2112_09271_amd import dgnp
+    from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64
+    cfg, _, gp = pair(name, with_oracle=False, phi_mg=getattr(dgnp, "DGNP_PHIMG_" + mode))
     x = random_state(cfg)
     gp.set_state(x, prec=DGNP_F32)
     r = random_vector(cfg, 61)
@@ -36,16 +38,40 @@ def test_pmg_preconditioner_symmetric_and_transposed(name):
 
 
 @pytest.mark.parametrize("name", ["cfg2t", "cfg3s"])
-def test_pmg_solve_matches_default_hierarchy(name):
+@pytest.mark.parametrize("mode", ["P", "PG"])
+def test_pmg_solve_matches_q1_hierarchy(name, mode):
     """Newton-FGMRES with p-multigrid reaches the same discrete solution as with
-    the default potential hierarchy (the preconditioner changes the path, not
-    the root), in double and mixed precision."""
-    from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64, DGNP_PHIMG_P
-    cfg, _, g0 = pair(name, with_oracle=False)
-    _, _, g1 = pair(name, with_oracle=False, phi_mg=DGNP_PHIMG_P)
+    the trilinear-start potential hierarchy (the preconditioner changes the
+    path, not the root), in double and mixed precision."""
+    from paper_2112_09271_amd import dgnp
+    from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64, DGNP_PHIMG_Q1
+    cfg, _, g0 = pair(name, with_oracle=False, phi_mg=DGNP_PHIMG_Q1)
+    _, _, g1 = pair(name, with_oracle=False, phi_mg=getattr(dgnp, "DGNP_PHIMG_" + mode))
     x0, st0 = g0.solve(rtol=1e-10, prec=DGNP_F64)
     for prec in (DGNP_F64, DGNP_F32):
         x1, st1 = g1.solve(rtol=1e-10, prec=prec)
-        print(f"{name} prec={prec}: fgmres {st1.lin_its_total} (default hierarchy {st0.lin_its_total})")
+        print(f"{name} {mode} prec={prec}: fgmres {st1.lin_its_total} (Q1 start {st0.lin_its_total})")
         assert st1.status == 0 and st1.res_final <= 1e-10 * st1.res0
         assert rel_err(host(x1), host(x0)) <= 1e-7
+
+
+def test_phi_mg_automatic_choice_and_errors():
+    """The automatic choice is the trilinear start at p <= 2 and Galerkin
+    p-multigrid at p = 3 (identical results to asking for them); p-multigrid at
+    p = 1 and unknown choices are argument errors."""
+    from paper_2112_09271_amd.dgnp import (DGNP_E_ARG, DGNP_F32, DGNP_PHIMG_AUTO, DGNP_PHIMG_P, DGNP_PHIMG_PG,
+                                           DGNP_PHIMG_Q1, DgnpError)
+    for name, explicit in (("cfg2t", DGNP_PHIMG_Q1), ("cfg3s", DGNP_PHIMG_PG)):
+        cfg, _, ga = pair(name, with_oracle=False, phi_mg=DGNP_PHIMG_AUTO)
+        _, _, ge = pair(name, with_oracle=False, phi_mg=explicit)
+        xa, sa = ga.solve(prec=DGNP_F32)
+        xe, se = ge.solve(prec=DGNP_F32)
+        assert sa.lin_its_total == se.lin_its_total
+        assert np.array_equal(host(xa), host(xe))
+    for name, mode in (("cfg1", 7), ("cfg2t", -1)):
+        with pytest.raises(DgnpError) as ei:
+            pair(name, with_oracle=False, phi_mg=mode)
+        assert ei.value.code == DGNP_E_ARG
+    with pytest.raises(DgnpError) as ei:
+        pair("cfg1", with_oracle=False, phi_mg=DGNP_PHIMG_P, p=1)
+    assert ei.value.code == DGNP_E_ARG
