@@ -192,6 +192,18 @@ int dgnp_set_state(dgnp_ctx *ctx, const double *x, int32_t prec, void *stream);
 int dgnp_jacobian_apply(dgnp_ctx *ctx, const void *v, void *y, int32_t prec,
                         int32_t transpose, void *stream);
 
+/* y = A_phiphi v, the potential-potential block of J at the point of the last
+ * dgnp_set_state (the derivative of the charge equation, Eq. chargeDG, with
+ * respect to the potential; Sec. 4.2 smooths with it): kind =
+ * DGNP_PHIOP_ASSEMBLED multiplies the assembled element blocks, kind =
+ * DGNP_PHIOP_MATFREE applies it matrix-free (3-D, with phi_mg = P or PG, where
+ * p-multigrid uses it).  v, y: device [E * nb] (the potential part) of the
+ * type `prec` names.  DGNP_E_STATE before a set_state that built the potential
+ * part of the preconditioner in that precision, DGNP_E_ARG for a matrix-free
+ * request the context does not provide. */
+enum { DGNP_PHIOP_ASSEMBLED = 0, DGNP_PHIOP_MATFREE = 1 };
+int dgnp_phi_apply(dgnp_ctx *ctx, const void *v, void *y, int32_t prec, int32_t kind, void *stream);
+
 /* z = P r, the block-triangular preconditioner (Eq. P2 when pc_kind =
  * DGNP_PC_P2, Eq. P1 otherwise): one element-block ILU(0) solve per
  * concentration block, one AMG V-cycle on the potential block, coupling

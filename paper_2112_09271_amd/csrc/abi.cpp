@@ -300,6 +300,15 @@ int dgnp_jacobian_apply(dgnp_ctx* c, const void* v, void* y, int32_t prec, int32
   });
 }
 
+int dgnp_phi_apply(dgnp_ctx* c, const void* v, void* y, int32_t prec, int32_t kind, void* stream) {
+  return guard([&] {
+    DGNP_REQUIRE(c && v && y, DGNP_E_ARG, "NULL argument");
+    DGNP_REQUIRE(prec == DGNP_F64 || prec == DGNP_F32, DGNP_E_ARG, "prec must be F64 or F32");
+    DGNP_REQUIRE(kind == DGNP_PHIOP_ASSEMBLED || kind == DGNP_PHIOP_MATFREE, DGNP_E_ARG, "unknown kind");
+    phi_apply(*c, v, y, prec == DGNP_F32, kind == DGNP_PHIOP_MATFREE, static_cast<hipStream_t>(stream));
+  });
+}
+
 int dgnp_precond_apply(dgnp_ctx* c, const void* r, void* z, int32_t prec, int32_t transpose,
                        int32_t pc_kind, void* stream) {
   return guard([&] {

@@ -19,6 +19,7 @@
 #include "amg.hpp"
 #include "blas.hpp"
 #include "kernels_block.hpp"
+#include "kernels_phi.hpp"
 #include "solver.hpp"
 
 namespace dgnp {
@@ -117,6 +118,10 @@ struct Precond {
   DevBuf<float> lvec1_32;
   DevBuf<double> mf64;              // order-p operator output [Nf]
   DevBuf<float> mf32;
+  // kappa tables of the matrix-free potential operator (3-D): volume [E][nqv]
+  // and own-trace face [E][6][nqf] Gauss points, with the quadrature weights
+  DevBuf<double> kv64, kf64;
+  DevBuf<float> kv32, kf32;
   // hyperplane levels of the lexicographic element order
   std::vector<int64_t> lev_ptr;
   DevBuf<int> lev_elems;
@@ -232,6 +237,7 @@ void precond_symbolic(dgnp_ctx& c) {
   }
   RefTables all[3] = {make_ref_tables(1), make_ref_tables(2), make_ref_tables(3)};
   upload_ref_tables_block(all, 3);
+  upload_ref_tables_phi(all, 3);
   upload_gll_nodes(all, 3);
   P.red.alloc(size_t(reduce_scratch_size()));
   const int nf = c.m - 1;
@@ -389,6 +395,20 @@ static void phi_mf_apply(dgnp_ctx& c, const T* x, T* y, hipStream_t s) {
   const bool f32 = std::is_same<T, float>::value;
   ScopeTimer tm(c, f32 ? "phi_apply_f32" : "phi_apply", s);
   KArgs A = c.kargs();
+  Precond& P = *c.pc;
+  if (c.dim == 3) {  // SIPG with tabulated kappa (kernels_phi.hip)
+    const size_t nqv = size_t(c.nq) * c.nq * c.nq, nqf = size_t(c.nq) * c.nq;
+    if constexpr (std::is_same<T, float>::value) {
+      DGNP_REQUIRE(P.kv32.p && P.kf32.p && P.kv32.n == size_t(c.E) * nqv && P.kf32.n == size_t(c.E) * 6 * nqf,
+                   DGNP_E_STATE, "single-precision potential operator tables not set up");
+      launch_phi_op<float>(c.p, A, x, P.kv32.p, P.kf32.p, y, s);
+    } else {
+      DGNP_REQUIRE(P.kv64.p && P.kf64.p && P.kv64.n == size_t(c.E) * nqv && P.kf64.n == size_t(c.E) * 6 * nqf,
+                   DGNP_E_STATE, "potential operator tables not set up");
+      launch_phi_op<double>(c.p, A, x, P.kv64.p, P.kf64.p, y, s);
+    }
+    return;
+  }
   A.vin_mask = 1u;
   const void* xs = f32 ? static_cast<const void*>(c.d_x32.p) : static_cast<const void*>(c.d_x.p);
   launch_dg(c.dim, c.p, c.m, f32, M_JACP, A, xs, x, y, nullptr, s);
@@ -526,6 +546,19 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     // product of the order-p block, and its inverse blocks
     const double* gal_blk = P.blk.p;
     int gal_p = c.p;
+    if (P.pmg && c.dim == 3) {
+      // kappa tables of the matrix-free potential operator: double always (the
+      // double V-cycle is usable after either set-up), single with f32
+      const int nqv = c.nq * c.nq * c.nq, nqf = c.nq * c.nq;
+      P.kv64.alloc(size_t(c.E) * nqv);
+      P.kf64.alloc(size_t(c.E) * 6 * nqf);
+      launch_phi_kappa<double>(c.p, c.m, c.kargs(), c.d_x.p, P.kv64.p, P.kf64.p, s);
+      if (f32) {
+        P.kv32.alloc(size_t(c.E) * nqv);
+        P.kf32.alloc(size_t(c.E) * 6 * nqf);
+        launch_phi_kappa<float>(c.p, c.m, c.kargs(), c.d_x.p, P.kv32.p, P.kf32.p, s);
+      }
+    }
     if (P.pmg) {
       P.x1.alloc(size_t(c.m) * c.E * P.nb1);
       launch_p1_inject(c.dim, c.p, c.d_x.p, P.x1.p, c.m, c.E, s);
@@ -900,6 +933,23 @@ void phi_block_apply(dgnp_ctx& c, const double* x, double* y, hipStream_t s) {
 void phi_block_apply(dgnp_ctx& c, const float* x, float* y, hipStream_t s) {
   DGNP_REQUIRE(c.pc && c.pc->phi32_ok, DGNP_E_STATE, "single-precision potential block not set up");
   launch_bspmv<float>(c.nb, c.dim, c.E, c.pc->phi32.p, c.d_nbr.p, x, nullptr, 1.0f, 0.0f, y, s);
+}
+
+void phi_apply(dgnp_ctx& c, const void* x, void* y, bool f32, bool matfree, hipStream_t s) {
+  DGNP_REQUIRE(c.pc && (f32 ? c.pc->phi32_ok : c.pc->phi_ok), DGNP_E_STATE,
+               "potential block not set up in this precision");
+  if (!matfree) {
+    if (f32)
+      phi_block_apply(c, static_cast<const float*>(x), static_cast<float*>(y), s);
+    else
+      phi_block_apply(c, static_cast<const double*>(x), static_cast<double*>(y), s);
+    return;
+  }
+  DGNP_REQUIRE(c.pc->pmg && c.dim == 3, DGNP_E_ARG, "matrix-free potential block: 3-D with p-multigrid");
+  if (f32)
+    phi_mf_apply<float>(c, static_cast<const float*>(x), static_cast<float*>(y), s);
+  else
+    phi_mf_apply<double>(c, static_cast<const double*>(x), static_cast<double*>(y), s);
 }
 
 // potential-block V-cycle alone (used for the initial potential solve)

@@ -23,6 +23,8 @@ void vcycle_phi(dgnp_ctx& c, const double* b, double* x, hipStream_t s);     // 
 void vcycle_phi(dgnp_ctx& c, const float* b, float* x, hipStream_t s);
 void phi_block_apply(dgnp_ctx& c, const double* x, double* y, hipStream_t s); // precond.hip
 void phi_block_apply(dgnp_ctx& c, const float* x, float* y, hipStream_t s);
+// y = A_phiphi x: assembled blocks or (matfree) the matrix-free operator       // precond.hip
+void phi_apply(dgnp_ctx& c, const void* x, void* y, bool f32, bool matfree, hipStream_t s);
 
 void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assemble_only = false,
                bool apply_only = false, int parts = PC_ALL);

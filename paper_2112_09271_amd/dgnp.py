@@ -23,6 +23,7 @@ DGNP_STATE_APPLY_ONLY = 0x200
 DGNP_PC_P2, DGNP_PC_P1 = 0, 1
 # potential multigrid: automatic / Q1 Galerkin start / p-multigrid (re-discretised, Galerkin p = 1 level)
 DGNP_PHIMG_AUTO, DGNP_PHIMG_Q1, DGNP_PHIMG_P, DGNP_PHIMG_PG = 0, 1, 2, 3
+DGNP_PHIOP_ASSEMBLED, DGNP_PHIOP_MATFREE = 0, 1  # potential-block apply: assembled / matrix-free
 MAX_HIST = 64
 
 
@@ -71,6 +72,7 @@ _SIGS = {
     "dgnp_set_state": [_vp, _vp, C.c_int32, _vp],
     "dgnp_jacobian_apply": [_vp, _vp, _vp, C.c_int32, C.c_int32, _vp],
     "dgnp_precond_apply": [_vp, _vp, _vp, C.c_int32, C.c_int32, C.c_int32, _vp],
+    "dgnp_phi_apply": [_vp, _vp, _vp, C.c_int32, C.c_int32, _vp],
     "dgnp_solve": [_vp, _vp, C.POINTER(dgnp_solve_opts), C.POINTER(dgnp_solve_stats)],
     "dgnp_adjoint": [_vp, _vp, C.c_int32, _vp, _vp, _vp, _vp, C.POINTER(dgnp_solve_opts),
                      C.POINTER(dgnp_solve_stats)],
@@ -135,6 +137,10 @@ def dgnp_set_state(ctx, x_ptr, prec, stream=None):
 
 def dgnp_jacobian_apply(ctx, v_ptr, y_ptr, prec, transpose, stream=None):
     _check(lib().dgnp_jacobian_apply(ctx, v_ptr, y_ptr, prec, transpose, stream))
+
+
+def dgnp_phi_apply(ctx, v_ptr, y_ptr, prec, kind, stream=None):
+    _check(lib().dgnp_phi_apply(ctx, v_ptr, y_ptr, prec, kind, stream))
 
 
 def dgnp_precond_apply(ctx, r_ptr, z_ptr, prec, transpose, pc_kind=DGNP_PC_P2, stream=None):
@@ -271,6 +277,14 @@ class Problem:
         v = self._dev(v, torch.float64 if prec == DGNP_F64 else torch.float32)
         y = torch.empty_like(v)
         dgnp_jacobian_apply(self.ctx, v.data_ptr(), y.data_ptr(), prec, int(transpose), _stream())
+        return y
+
+    def phi_apply(self, v, prec=DGNP_F64, kind=0):
+        """A_phiphi v on the potential part (kind 0: assembled blocks, 1: matrix-free)."""
+        import torch
+        v = self._dev(v, torch.float64 if prec == DGNP_F64 else torch.float32)
+        y = torch.empty_like(v)
+        dgnp_phi_apply(self.ctx, v.data_ptr(), y.data_ptr(), prec, int(kind), _stream())
         return y
 
     def precond_apply(self, r, prec=DGNP_F64, transpose=False, pc_kind=DGNP_PC_P2):
