@@ -1580,11 +1580,19 @@ __global__ void __launch_bounds__(BT) k_ilu_dfl(const float* __restrict__ blk, c
     const int64_t first = line_first[KIND == 0 ? c : nline - 1 - c];
     const int64_t step = KIND == 0 ? lstride : -lstride;
     const int64_t start = KIND == 0 ? first : first + int64_t(len - 1) * lstride;
-    float m[DIM + 1][QL], mn[DIM + 1][QL];
-    fetch(start, m);
+    // blocks of up to 32 rows: the next element's rows are fetched while the
+    // current one waits; 64-row blocks are fetched in place, which keeps the
+    // registers for more resident lines
+    constexpr bool PF = NB <= 32;
+    float m[DIM + 1][QL], mn[PF ? DIM + 1 : 1][PF ? QL : 1];
+    if constexpr (PF) fetch(start, m);
     for (int q = 0; q < len; ++q) {
       const int64_t i = start + q * step;
-      if (q + 1 < len) fetch(i + step, mn);
+      if constexpr (PF) {
+        if (q + 1 < len) fetch(i + step, mn);
+      } else {
+        fetch(i, m);
+      }
       for (int idx = tid; idx < NB; idx += BT) xs[0][idx] = in[i * NB + idx];
       const unsigned target = unsigned(ld_dev(wp + i * NB) >> 32) + 1u;
       for (int idx = tid; idx < DIM * NB; idx += BT) {
@@ -1637,10 +1645,12 @@ __global__ void __launch_bounds__(BT) k_ilu_dfl(const float* __restrict__ blk, c
         out[i * NB + row] = acc;
         xs[1 + ax][row] = acc;
       }
+      if constexpr (PF) {
 #pragma unroll
-      for (int b = 0; b <= DIM; ++b)
+        for (int b = 0; b <= DIM; ++b)
 #pragma unroll
-        for (int cq = 0; cq < QL; ++cq) m[b][cq] = mn[b][cq];
+          for (int cq = 0; cq < QL; ++cq) m[b][cq] = mn[b][cq];
+      }
     }
     __syncthreads();  // the last result of the line is in xs before the next line clears it
   }
@@ -2107,7 +2117,10 @@ static int dfl_resident(int nfields) {
   int occ[2] = {0, 0};
   DGNP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], (k_ilu_dfl<NB, DIM, 0>), BT, 0));
   DGNP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], (k_ilu_dfl<NB, DIM, 1>), BT, 0));
-  return (ncu * std::min(occ[0], occ[1])) / (2 * nfields);  // half the resident capacity per field
+  // the whole resident capacity: a line sweep runs alone on its stream, and a
+  // line is one work-group's sequential work, so every resident work-group
+  // shortens the sweep
+  return (ncu * std::min(occ[0], occ[1])) / nfields;
 }
 
 int ilu_lines_grid(int nb, int dim, int nline, int nfields) {

@@ -275,10 +275,12 @@ void precond_symbolic(dgnp_ctx& c) {
     P.line_ax = ax;
     P.line_stride = stride[ax];
     P.line_grid = ilu_lines_grid(c.nb, c.dim, P.nline, nf);
-    // With narrow levels, 64-row blocks (p = 3) go by lines: the block rows of
-    // the next element stream in while the current one waits; smaller blocks
-    // keep the element order, whose waits are shorter.
-    P.lines_on = P.df_on && c.nb >= 64 && getenv("DGNP_DATAFLOW") == nullptr;
+    // 64-row blocks (p = 3) go by lines at any level width: with every line
+    // resident the sweep streams the factors (64x16x8 channel 531 -> 296 us,
+    // 128x32x16 channel 2.0 -> 1.84 ms per forward sweep, against the element
+    // order and the level launches); smaller blocks keep the element order
+    // (narrow levels) or the level launches.
+    P.lines_on = c.nb >= 64 && getenv("DGNP_DATAFLOW") == nullptr && getenv("DGNP_NO_DATAFLOW") == nullptr;
     const char* sw = getenv("DGNP_ILU_SWEEP");  // "line", "element" or "level"
     if (sw && std::string(sw) == "line") {
       P.lines_on = true;
