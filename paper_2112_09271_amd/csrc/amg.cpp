@@ -237,11 +237,63 @@ double lmax_dinvA(const Csr& A, const std::vector<double>& dinv, int iters) {
   return lam;
 }
 
+// dot product with four independent partial sums (a fixed order)
+static inline double dot4(const double* x, const double* y, int n) {
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+  int k = 0;
+  for (; k + 4 <= n; k += 4) {
+    t0 += x[k] * y[k];
+    t1 += x[k + 1] * y[k + 1];
+    t2 += x[k + 2] * y[k + 2];
+    t3 += x[k + 3] * y[k + 3];
+  }
+  for (; k < n; ++k) t0 += x[k] * y[k];
+  return (t0 + t1) + (t2 + t3);
+}
+
+// Inverse of the symmetric positive definite coarsest matrix by Cholesky:
+// A = L L^T (lower triangle of the row-major array), M = L^{-1}, then
+// A^{-1} = M^T M; about n^3 flops, every inner loop a contiguous dot product.
+// Returns false at a pivot that is not positive.
+static bool cholesky_inverse(std::vector<double>& a, int n) {
+  auto at = [&](int i, int j) -> double& { return a[size_t(i) * n + j]; };
+  for (int j = 0; j < n; ++j) {
+    const double* rj = &a[size_t(j) * n];
+    double d = at(j, j) - dot4(rj, rj, j);
+    if (!(d > 0.0)) return false;
+    d = std::sqrt(d);
+    at(j, j) = d;
+    const double id = 1.0 / d;
+    for (int i = j + 1; i < n; ++i) at(i, j) = (at(i, j) - dot4(&a[size_t(i) * n], rj, j)) * id;
+  }
+  // m[j * n + i] = M_ij: column j of M contiguous; M_ij = -(sum_{k=j}^{i-1} L_ik M_kj) / L_ii
+  std::vector<double> m(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    const double il = 1.0 / at(i, i);
+    m[size_t(i) * n + i] = il;
+    const double* li = &a[size_t(i) * n];
+    for (int j = 0; j < i; ++j) m[size_t(j) * n + i] = -dot4(li + j, &m[size_t(j) * n + j], i - j) * il;
+  }
+  // (A^{-1})_ij = sum_{k >= max(i, j)} M_ki M_kj
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      const double t = dot4(&m[size_t(i) * n + i], &m[size_t(j) * n + i], n - i);
+      at(i, j) = t;
+      at(j, i) = t;
+    }
+  return true;
+}
+
 static std::vector<double> dense_inverse(const Csr& A) {
   const int n = A.n;
   std::vector<double> a(static_cast<size_t>(n) * n, 0.0);
   for (int i = 0; i < n; ++i)
     for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) a[size_t(i) * n + A.ci[k]] += A.v[k];
+  {
+    std::vector<double> c = a;
+    if (cholesky_inverse(c, n)) return c;
+  }
+  // not positive definite: Gauss-Jordan with partial pivoting
   std::vector<int> piv(static_cast<size_t>(n));
   for (int k = 0; k < n; ++k) {
     int p = k;
