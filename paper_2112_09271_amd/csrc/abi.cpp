@@ -64,6 +64,7 @@ dgnp::KArgs dgnp_ctx::kargs() const {
   A.src = d_src.p;
   A.objective_tag = 1;
   A.vin_mask = ~0u;
+  A.jbase = nullptr;
   return A;
 }
 

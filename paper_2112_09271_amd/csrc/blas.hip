@@ -384,7 +384,7 @@ __global__ void k_dcgs_scalars(double* __restrict__ out, int j, int with_w) {
 template <typename TM>
 __global__ void k_dcgs_update(double* __restrict__ V, int64_t ldv, int j, const double* __restrict__ coef,
                               double* __restrict__ u, const double* __restrict__ w, TM* __restrict__ m,
-                              int64_t n) {
+                              const TM* __restrict__ zs, TM* __restrict__ zd, int64_t n) {
   const double ia = coef[DC_IALPHA], hjj = coef[DC_HJJ], irho = coef[DC_IRHO];
   const double* sv = coef;
   const double* cv = coef + MAXV;
@@ -409,6 +409,7 @@ __global__ void k_dcgs_update(double* __restrict__ V, int64_t ldv, int j, const 
     const double un = (w[i] - (ac0 + ac1) - v * hjj) * irho;
     u[i] = un;
     m[i] = TM(un);
+    if (zd) zd[i] = zs[i];
   }
 }
 
@@ -431,15 +432,15 @@ void dcgs_reduce(const double* V, int64_t ldv, int j, const double* u, const voi
 }
 
 template <typename TM>
-void dcgs_update(double* V, int64_t ldv, int j, const double* coef, double* u, const double* w, TM* m, int64_t n,
-                 hipStream_t s) {
+void dcgs_update(double* V, int64_t ldv, int j, const double* coef, double* u, const double* w, TM* m,
+                 const TM* zs, TM* zd, int64_t n, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_dcgs_update<TM>, dim3(grid_for(n)), dim3(VB), 0, s, V, ldv, j, coef, u, w, m, n);
+  hipLaunchKernelGGL(k_dcgs_update<TM>, dim3(grid_for(n)), dim3(VB), 0, s, V, ldv, j, coef, u, w, m, zs, zd, n);
 }
-template void dcgs_update<double>(double*, int64_t, int, const double*, double*, const double*, double*, int64_t,
-                                  hipStream_t);
-template void dcgs_update<float>(double*, int64_t, int, const double*, double*, const double*, float*, int64_t,
-                                 hipStream_t);
+template void dcgs_update<double>(double*, int64_t, int, const double*, double*, const double*, double*,
+                                  const double*, double*, int64_t, hipStream_t);
+template void dcgs_update<float>(double*, int64_t, int, const double*, double*, const double*, float*,
+                                 const float*, float*, int64_t, hipStream_t);
 int64_t dcgs_partial_size() { return int64_t(2 * MAXV + 1) * RED_BLOCKS; }
 
 template <typename T>

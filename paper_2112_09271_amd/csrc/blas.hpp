@@ -35,12 +35,13 @@ double vnorm2(const float* x, int64_t n, double* scratch_dev, hipStream_t s);   
 // coefficient block coef[2 MAXV + 8] from V[:, <j], u and w (w null: only
 // s, sigma and alpha, for the last column of a cycle; w_f32: w in single
 // precision, widened into w64); dcgs_update writes V[:, j], the next u and
-// its preconditioner-input copy m.  partial holds dcgs_partial_size() doubles.
+// its preconditioner-input copy m, and (zd not null) copies zs to zd in the same
+// pass.  partial holds dcgs_partial_size() doubles.
 void dcgs_reduce(const double* V, int64_t ldv, int j, const double* u, const void* w, bool w_f32, double* w64,
                  int64_t n, double* partial, double* coef, hipStream_t s);
 template <typename TM>
-void dcgs_update(double* V, int64_t ldv, int j, const double* coef, double* u, const double* w, TM* m, int64_t n,
-                 hipStream_t s);
+void dcgs_update(double* V, int64_t ldv, int j, const double* coef, double* u, const double* w, TM* m,
+                 const TM* zs, TM* zd, int64_t n, hipStream_t s);
 int64_t dcgs_partial_size();
 constexpr int DCGS_ALPHA = 2 * MAXV + 1, DCGS_HJJ = 2 * MAXV + 2, DCGS_RHO = 2 * MAXV + 4, DCGS_COEF = 2 * MAXV + 8;
 // *out = x . x (accumulated in double) without a host wait; scratch holds the block partials

@@ -110,6 +110,7 @@ struct KArgs {
   const double* src;    // [m][E][nqv] volume sources or nullptr
   int objective_tag;    // box face of the objective
   unsigned vin_mask;    // fields of the input vector that are read (the others count as zero)
+  const void* jbase;    // M_JACP: out = jbase - (J v) rows when not null (same type as out)
 };
 
 enum Mode { M_RES = 0, M_JAC = 1, M_JACT = 2, M_DPE = 3, M_OBJG = 4, M_DATAT = 5, M_JACP = 6 };

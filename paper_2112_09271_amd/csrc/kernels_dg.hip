@@ -453,7 +453,12 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
       acc += tb.De[sdi][l] * tnt[(rc * 2 + 1) * NFN + ij];
       if (l == (sdi ? P : 0)) acc += tnt[(rc * 2 + 0) * NFN + ij];
     }
-    out[f * Nf + e * NB + node] = acc;
+    if constexpr (MODE == M_JACP) {
+      const T* jb = static_cast<const T*>(A.jbase);
+      out[f * Nf + e * NB + node] = jb ? jb[f * Nf + e * NB + node] - acc : acc;
+    } else {
+      out[f * Nf + e * NB + node] = acc;
+    }
   }
 }
 

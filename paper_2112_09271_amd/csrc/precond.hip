@@ -902,8 +902,12 @@ static void apply_t(dgnp_ctx& c, const T* r, T* z, bool transpose, int kind, hip
   const unsigned phi_only = 1u, conc_only = ~1u;
   if (c_first) {
     ilu_solve<T>(c, P, transpose, r + Nf, z + Nf, s);
-    jac_apply(c, z, y, f32, transpose, s, conc_only, !transpose);  // only the potential rows are used
-    vsub<T>(r, y, t, Nf, s);
+    if (!transpose) {
+      jac_apply(c, z, t, f32, false, s, conc_only, true, r);  // t = r - A_phic z_c, potential rows only
+    } else {
+      jac_apply(c, z, y, f32, true, s, conc_only);
+      vsub<T>(r, y, t, Nf, s);
+    }
     ScopeTimer tm(c, f32 ? "vcycle_f32" : "vcycle", s);
     mg.vcycle(0, t, z);
   } else {

@@ -36,7 +36,7 @@ void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assem
 }
 
 void jac_apply(dgnp_ctx& c, const void* v, void* y, bool f32, bool transpose, hipStream_t s, unsigned vmask,
-               bool phi_rows) {
+               bool phi_rows, const void* base) {
   DGNP_REQUIRE(c.has_state, DGNP_E_STATE, "jacobian_apply before set_state");
   DGNP_REQUIRE(!f32 || c.has_state32, DGNP_E_STATE, "float apply needs set_state with DGNP_F32");
   const void* xs = f32 ? static_cast<const void*>(c.d_x32.p) : static_cast<const void*>(c.d_x.p);
@@ -44,6 +44,8 @@ void jac_apply(dgnp_ctx& c, const void* v, void* y, bool f32, bool transpose, hi
   ScopeTimer tm(c, names[transpose ? 1 : 0][f32 ? 1 : 0], s);
   KArgs A = c.kargs();
   A.vin_mask = vmask;
+  DGNP_REQUIRE(!base || (phi_rows && !transpose), DGNP_E_ARG, "base needs the potential-rows apply");
+  A.jbase = base;
   launch_dg(c.dim, c.p, c.m, f32, transpose ? M_JACT : (phi_rows ? M_JACP : M_JAC), A, xs, v, y, nullptr, s);
 }
 
@@ -231,21 +233,16 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
       DGNP_HIP(hipEventRecord(K.hev[q % 2], s));
     };
     auto issue_step = [&](int q) {
-      if (f32) {
-        pc_then_jac(c, K, true, transpose, pc_kind, s);
-        vcopy<float>(K.zt32.p, K.Z32.p + int64_t(q) * N, N, s);
-      } else {
-        pc_then_jac(c, K, false, transpose, pc_kind, s);
-        vcopy<double>(K.zt.p, K.Z.p + int64_t(q) * N, N, s);
-      }
+      pc_then_jac(c, K, f32, transpose, pc_kind, s);
       {
+        // the update pass also stores z_q into Z (preconditioner output column)
         ScopeTimer tm(c, "cgs2", s);
         if (f32) {
           dcgs_reduce(K.V.p, N, q, K.r.p, K.w32.p, true, K.w.p, N, part, coef, s);
-          dcgs_update<float>(K.V.p, N, q, coef, K.r.p, K.w.p, K.v32.p, N, s);
+          dcgs_update<float>(K.V.p, N, q, coef, K.r.p, K.w.p, K.v32.p, K.zt32.p, K.Z32.p + int64_t(q) * N, N, s);
         } else {
           dcgs_reduce(K.V.p, N, q, K.r.p, K.w.p, false, nullptr, N, part, coef, s);
-          dcgs_update<double>(K.V.p, N, q, coef, K.r.p, K.w.p, K.vt.p, N, s);
+          dcgs_update<double>(K.V.p, N, q, coef, K.r.p, K.w.p, K.vt.p, K.zt.p, K.Z.p + int64_t(q) * N, N, s);
         }
       }
       to_host(q);

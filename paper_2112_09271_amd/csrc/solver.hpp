@@ -29,9 +29,10 @@ void phi_apply(dgnp_ctx& c, const void* x, void* y, bool f32, bool matfree, hipS
 void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assemble_only = false,
                bool apply_only = false, int parts = PC_ALL);
 // vmask: fields of v that are read (the others count as zero); phi_rows (forward
-// apply only): only the potential rows of y = J v are formed and written
+// apply only): only the potential rows of y = J v are formed and written, as
+// y = base - (J v) when base is not null
 void jac_apply(dgnp_ctx& c, const void* v, void* y, bool f32, bool transpose, hipStream_t s,
-               unsigned vmask = ~0u, bool phi_rows = false);
+               unsigned vmask = ~0u, bool phi_rows = false, const void* base = nullptr);
 dgnp_solve_opts default_solve_opts();
 double objective_value(dgnp_ctx& c, const double* x);
 int newton_solve(dgnp_ctx& c, double* x, const dgnp_solve_opts& o, dgnp_solve_stats& st);
