@@ -505,15 +505,25 @@ void launch_assemble(int dim, int p, int m, int f0, int nf, const KArgs& A, cons
 // the unused row p of largest magnitude (ties: smallest row), so that on exit
 //   A^{-1}[i][j] = a[rsrc[i]][csrc[j]],  rsrc[k] = p_k,  csrc[p_k] = k.
 // Per step: the wave that owns column k finds the pivot with a lane reduction
-// and publishes column k; after a barrier the pivot row's lanes publish row p;
-// after a second barrier every lane updates its row with one FMA per entry.
-// The published rows and columns are double-buffered, so two barriers suffice.
+// and publishes column k and the pivot; after one barrier every lane updates
+// its row with one FMA per entry, taking the pivot row's entry of each of its
+// columns from lane p of its own wave (the same wave holds the same columns of
+// every row).  The published columns are double-buffered, so one barrier per
+// step suffices.
 // ===========================================================================
+// v (a double) of lane `lane` (wave-uniform) of the calling wave
+__device__ inline double readlane_d(double v, int lane) {
+  const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v));
+  const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(u & 0xffffffffu), lane));
+  const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(u >> 32), lane));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
 template <int NB, int LD>
 __device__ void gj_invert(double* a, double* sh, int* shi, int* rsrc, int* csrc, int tid) {
   static_assert(NB <= 64 && BT == 256, "one row per lane, four waves");
   constexpr int NC = (NB + 3) / 4;
-  constexpr int SB = 2 * 64 + 1;  // doubles per buffer: column k, row p, pivot value
+  constexpr int SB = 64 + 1;  // doubles per buffer: column k, pivot value
   const int r = tid & 63, w = tid >> 6;
   const bool rowok = r < NB;
   double x[NC];
@@ -526,8 +536,7 @@ __device__ void gj_invert(double* a, double* sh, int* shi, int* rsrc, int* csrc,
   for (int k = 0; k < NB; ++k) {
     const int b = k & 1;
     double* pcol = sh + b * SB;
-    double* prow = pcol + 64;
-    double* pval = prow + 64;
+    double* pval = pcol + 64;
     const int wk = k & 3, jk = k >> 2;
     if (w == wk) {
       double xk = 0.0;
@@ -552,22 +561,16 @@ __device__ void gj_invert(double* a, double* sh, int* shi, int* rsrc, int* csrc,
       }
     }
     __syncthreads();
+    // one barrier per pivot: the buffers alternate, and each wave takes the
+    // pivot row's entries of its own columns from lane p of its own registers
     const int p = __builtin_amdgcn_readfirstlane(shi[b]);
     const double inv = 1.0 / pval[0];
-    if (r == p) {
-#pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        const int c = w + 4 * j;
-        if (c < NB) prow[c] = x[j];
-      }
-      used = true;
-    }
-    __syncthreads();
+    if (r == p) used = true;
     const double g = (r == p || !rowok) ? 0.0 : pcol[r] * inv;
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
       const int c = w + 4 * j;
-      if (c < NB) x[j] = fma(-g, prow[c], x[j]);
+      if (c < NB) x[j] = fma(-g, readlane_d(x[j], p), x[j]);
     }
     if (r == p) {
 #pragma unroll
@@ -595,7 +598,7 @@ __global__ void __launch_bounds__(BT) k_block_inverse(const double* __restrict__
                                                       double* __restrict__ out) {
   constexpr int LD = NB + 1;
   __shared__ double a[NB * LD];
-  __shared__ double sh[2 * (2 * 64 + 1)];
+  __shared__ double sh[2 * (64 + 1)];
   __shared__ int shi[2], rsrc[NB], csrc[NB];
   const int64_t e = blockIdx.x;
   const double* src = blk + e * nslot * NB * NB;
@@ -762,6 +765,100 @@ __device__ inline void scale_block(double* __restrict__ B, const double* a, cons
     }
 }
 
+// ---- 64-row blocks on the FP64 matrix cores ----------------------------------
+// v_mfma_f64_16x16x4f64 (D = A B + C, A 16 x 4, B 4 x 16): A[i][k] sits in lane
+// i + 16 k, B[k][j] in lane j + 16 k, and D[i][j] in lane j + 16 (i % 4) as
+// element i / 4 of the four-double accumulator.  Wave w of the work-group owns
+// the 16-row strip 16 w .. 16 w + 15 of a 64 x 64 product, as four 16 x 16
+// tiles; the operands are read from global memory (L2) straight into
+// registers, one 16-wide k panel ahead, so no LDS staging or barrier is needed.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// acc += L R over the wave's strip; L, R 64 x 64 row-major
+__device__ inline void gemm_mfma64(v4d (&acc)[4], const double* __restrict__ L, const double* __restrict__ R,
+                                   int tid) {
+  const int l = tid & 63, w = tid >> 6, li = l & 15, lk = l >> 4;
+  const double* lp = L + (16 * w + li) * 64 + lk;  // A[i][k0 + 4 s + lk]
+  const double* rp = R + lk * 64 + li;             // B[k0 + 4 s + lk][16 t + li]
+  double ca[4], cb[4][4], na[4], nb[4][4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    ca[s] = lp[4 * s];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) cb[s][t] = rp[(4 * s) * 64 + 16 * t];
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    if (p + 1 < 4) {
+      const int k0 = 16 * (p + 1);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        na[s] = lp[k0 + 4 * s];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) nb[s][t] = rp[(k0 + 4 * s) * 64 + 16 * t];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[s], cb[s][t], acc[t], 0, 0, 0);
+    if (p + 1 < 4) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        ca[s] = na[s];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) cb[s][t] = nb[s][t];
+      }
+    }
+  }
+}
+
+// B <- Dinv B in place (B 64 x 64 row-major in global memory), Dinv[i][k] =
+// a[rsrc[i] LD + csrc[k]] in LDS.  Every wave reads all of B, so the strips are
+// written only after the work-group's barrier.
+template <int LD>
+__device__ inline void scale_mfma64(double* __restrict__ B, const double* a, const int* rsrc, const int* csrc,
+                                    int tid) {
+  const int l = tid & 63, w = tid >> 6, li = l & 15, lk = l >> 4;
+  const int arow = rsrc[16 * w + li] * LD;
+  const double* rp = B + lk * 64 + li;
+  v4d acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  double cb[4][4], nb[4][4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) cb[s][t] = rp[(4 * s) * 64 + 16 * t];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    if (p + 1 < 4) {
+      const int k0 = 16 * (p + 1);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) nb[s][t] = rp[(k0 + 4 * s) * 64 + 16 * t];
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const double av = a[arow + csrc[16 * p + 4 * s + lk]];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, cb[s][t], acc[t], 0, 0, 0);
+    }
+    if (p + 1 < 4) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) cb[s][t] = nb[s][t];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) B[(16 * w + 4 * q + lk) * 64 + 16 * t + li] = acc[t][q];
+}
+
 template <int NB, int DIM>
 __global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, int64_t fstride,
                                                    const int* __restrict__ nbr, const int* __restrict__ lev_elems,
@@ -770,44 +867,73 @@ __global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, int
   constexpr int LD = NB + 1;
   constexpr int NSLOT = 2 * DIM + 1;
   __shared__ double a[NB * LD];
-  __shared__ double pa[NB * G::PLD];
-  __shared__ double pb[G::KP * NB];
-  __shared__ double sh[2 * (2 * 64 + 1)];
+  __shared__ double sh[2 * (64 + 1)];
   __shared__ int shi[2], rsrc[NB], csrc[NB];
   const int tid = threadIdx.x;
-  const int ty = tid >> 4, tx = tid & 15;
   blk += blockIdx.y * fstride;
   const int64_t i = lev_elems[first + blockIdx.x];
   double* bi = blk + i * NSLOT * NB * NB;
-  for (int idx = tid; idx < NB * NB; idx += BT) a[(idx / NB) * LD + idx % NB] = bi[idx];
-  // Schur complement of the lower neighbours (slots 0, 2, 4 = -x, -y, -z):
-  // A_ij times the scaled block of j toward i (D_j^{-1} A_ji)
-  double acc[G::RT][G::RT];
+  if constexpr (NB == 64) {
+    // Schur complement on the matrix cores, then a = A_ii - sum
+    v4d acc[4];
 #pragma unroll
-  for (int r = 0; r < G::RT; ++r)
-#pragma unroll
-    for (int c = 0; c < G::RT; ++c) acc[r][c] = 0.0;
-  for (int s = 0; s < 2 * DIM; s += 2) {
-    const int j = nbr[i * 2 * DIM + s];
-    if (j < 0) continue;
-    gemm_gg<NB>(acc, bi + int64_t(1 + s) * NB * NB, blk + (int64_t(j) * NSLOT + 1 + (s + 1)) * NB * NB, pa, pb,
-                tid);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < G::RT; ++r)
-#pragma unroll
-    for (int c = 0; c < G::RT; ++c) {
-      const int rr = ty + 16 * r, cc = tx + 16 * c;
-      if (rr < NB && cc < NB) a[rr * LD + cc] -= acc[r][c];
+    for (int t = 0; t < 4; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int s = 0; s < 2 * DIM; s += 2) {
+      const int j = nbr[i * 2 * DIM + s];
+      if (j < 0) continue;
+      gemm_mfma64(acc, bi + int64_t(1 + s) * NB * NB, blk + (int64_t(j) * NSLOT + 1 + (s + 1)) * NB * NB, tid);
     }
-  __syncthreads();
-  gj_invert<NB, LD>(a, sh, shi, rsrc, csrc, tid);
-  for (int idx = tid; idx < NB * NB; idx += BT) bi[idx] = a[rsrc[idx / NB] * LD + csrc[idx % NB]];
-  // upper neighbours (slots 1, 3, 5 = +x, +y, +z)
-  for (int s = 1; s < 2 * DIM; s += 2) {
-    if (nbr[i * 2 * DIM + s] < 0) continue;
-    scale_block<NB, LD>(bi + int64_t(1 + s) * NB * NB, a, rsrc, csrc, pb, tid);
+    {
+      const int l = tid & 63, w = tid >> 6, li = l & 15, lk = l >> 4;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int rr = 16 * w + 4 * q + lk, cc = 16 * t + li;
+          a[rr * LD + cc] = bi[rr * NB + cc] - acc[t][q];
+        }
+    }
+    __syncthreads();
+    gj_invert<NB, LD>(a, sh, shi, rsrc, csrc, tid);
+    for (int idx = tid; idx < NB * NB; idx += BT) bi[idx] = a[rsrc[idx / NB] * LD + csrc[idx % NB]];
+    for (int s = 1; s < 2 * DIM; s += 2) {
+      if (nbr[i * 2 * DIM + s] < 0) continue;
+      scale_mfma64<LD>(bi + int64_t(1 + s) * NB * NB, a, rsrc, csrc, tid);
+    }
+  } else {
+    __shared__ double pa[NB * G::PLD];
+    __shared__ double pb[G::KP * NB];
+    const int ty = tid >> 4, tx = tid & 15;
+    for (int idx = tid; idx < NB * NB; idx += BT) a[(idx / NB) * LD + idx % NB] = bi[idx];
+    // Schur complement of the lower neighbours (slots 0, 2, 4 = -x, -y, -z):
+    // A_ij times the scaled block of j toward i (D_j^{-1} A_ji)
+    double acc[G::RT][G::RT];
+#pragma unroll
+    for (int r = 0; r < G::RT; ++r)
+#pragma unroll
+      for (int c = 0; c < G::RT; ++c) acc[r][c] = 0.0;
+    for (int s = 0; s < 2 * DIM; s += 2) {
+      const int j = nbr[i * 2 * DIM + s];
+      if (j < 0) continue;
+      gemm_gg<NB>(acc, bi + int64_t(1 + s) * NB * NB, blk + (int64_t(j) * NSLOT + 1 + (s + 1)) * NB * NB, pa, pb,
+                  tid);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < G::RT; ++r)
+#pragma unroll
+      for (int c = 0; c < G::RT; ++c) {
+        const int rr = ty + 16 * r, cc = tx + 16 * c;
+        if (rr < NB && cc < NB) a[rr * LD + cc] -= acc[r][c];
+      }
+    __syncthreads();
+    gj_invert<NB, LD>(a, sh, shi, rsrc, csrc, tid);
+    for (int idx = tid; idx < NB * NB; idx += BT) bi[idx] = a[rsrc[idx / NB] * LD + csrc[idx % NB]];
+    // upper neighbours (slots 1, 3, 5 = +x, +y, +z)
+    for (int s = 1; s < 2 * DIM; s += 2) {
+      if (nbr[i * 2 * DIM + s] < 0) continue;
+      scale_block<NB, LD>(bi + int64_t(1 + s) * NB * NB, a, rsrc, csrc, pb, tid);
+    }
   }
 }
 
@@ -819,7 +945,7 @@ __global__ void __launch_bounds__(BT) k_ilu_scale_lower(double* __restrict__ blk
   constexpr int LD = NB + 1;
   constexpr int NSLOT = 2 * DIM + 1;
   __shared__ double a[NB * LD];
-  __shared__ double pb[G::KP * NB];
+  __shared__ double pb[NB == 64 ? 1 : G::KP * NB];  // panel of the vector-unit products only
   __shared__ int ident[NB];
   const int tid = threadIdx.x;
   blk += blockIdx.y * fstride;
@@ -830,7 +956,10 @@ __global__ void __launch_bounds__(BT) k_ilu_scale_lower(double* __restrict__ blk
   __syncthreads();
   for (int s = 0; s < 2 * DIM; s += 2) {
     if (nbr[i * 2 * DIM + s] < 0) continue;
-    scale_block<NB, LD>(bi + int64_t(1 + s) * NB * NB, a, ident, ident, pb, tid);
+    if constexpr (NB == 64)
+      scale_mfma64<LD>(bi + int64_t(1 + s) * NB * NB, a, ident, ident, tid);
+    else
+      scale_block<NB, LD>(bi + int64_t(1 + s) * NB * NB, a, ident, ident, pb, tid);
   }
 }
 

@@ -35,6 +35,41 @@ def test_assembled_blocks_match_oracle(name):
     assert worst <= 1e-12, worst
 
 
+@pytest.mark.parametrize("name", ["cfg2t", "cfg3s"])
+def test_ilu_factors_match_block_ilu0_definition(name):
+    """The stored concentration factors equal block ILU(0) of the oracle's
+    Jacobian blocks (Sec. on the block preconditioner): in lexicographic element
+    order D_i = A_ii - sum_{j lower} A_ij D_j^{-1} A_ji, stored as D_i^{-1} and
+    D_i^{-1} A_{i,nbr} for every neighbour.  cfg3s has 64-row blocks (p = 3)."""
+    from paper_2112_09271_amd.dgnp import DGNP_F64
+    cfg, od, gp = pair(name)
+    x = random_state(cfg)
+    gp.set_state(x, prec=DGNP_F64)
+    J = od.jacobian(x).tocsr()
+    msh = od.msh
+    nb, Nf, E, nd = msh.nb, msh.Nf, msh.E, cfg.dim
+    worst = 0.0
+    for f in range(1, cfg.m):
+        def A(e, g):
+            return J[f * Nf + e * nb: f * Nf + (e + 1) * nb, f * Nf + g * nb: f * Nf + (g + 1) * nb].toarray()
+        Dinv = {}
+        for e in range(E):
+            D = A(e, e)
+            for s in range(0, 2 * nd, 2):
+                j = msh.nbr[e, s]
+                if j >= 0:
+                    D = D - A(e, j) @ Dinv[j] @ A(j, e)
+            Dinv[e] = np.linalg.inv(D)
+            ref = [Dinv[e]] + [Dinv[e] @ A(e, msh.nbr[e, s]) if msh.nbr[e, s] >= 0 else None
+                               for s in range(2 * nd)]
+            for slot, R in enumerate(ref):
+                if R is None:
+                    continue
+                B = gp.get_block(f, e, slot)
+                worst = max(worst, np.abs(B - R).max() / np.abs(R).max())
+    assert worst <= 1e-10, worst
+
+
 def _triangular_case():
     # constant velocity with positive components, tiny diffusion, constant potential:
     # the concentration blocks are block lower triangular in lexicographic order
