@@ -859,6 +859,59 @@ __device__ inline void scale_mfma64(double* __restrict__ B, const double* a, con
     for (int q = 0; q < 4; ++q) B[(16 * w + 4 * q + lk) * 64 + 16 * t + li] = acc[t][q];
 }
 
+// ---- 17..32-row blocks on the FP64 matrix cores (padded to 32 x 32) ----------
+// Wave w owns the 16 x 16 tile (w >> 1, w & 1) of the padded product; its k
+// loop runs over KS = ceil(NB / 4) steps of four, entries past NB read as 0.
+template <int NB>
+struct Mf32 {
+  static constexpr bool on = NB > 16 && NB <= 32;
+  static constexpr int KS = (NB + 3) / 4;
+};
+
+// per-lane operand lists of one padded product: A[i][4 s + lk] and B[4 s + lk][j]
+template <int NB>
+__device__ inline void mf32_load_a(double (&xa)[Mf32<NB>::KS], const double* __restrict__ L, int tid) {
+  const int l = tid & 63, w = tid >> 6, i = 16 * (w >> 1) + (l & 15), lk = l >> 4;
+#pragma unroll
+  for (int s = 0; s < Mf32<NB>::KS; ++s) {
+    const int k = 4 * s + lk;
+    xa[s] = (L && i < NB && k < NB) ? L[i * NB + k] : 0.0;
+  }
+}
+template <int NB>
+__device__ inline void mf32_load_b(double (&xb)[Mf32<NB>::KS], const double* __restrict__ R, int tid) {
+  const int l = tid & 63, w = tid >> 6, j = 16 * (w & 1) + (l & 15), lk = l >> 4;
+#pragma unroll
+  for (int s = 0; s < Mf32<NB>::KS; ++s) {
+    const int k = 4 * s + lk;
+    xb[s] = (R && j < NB && k < NB) ? R[k * NB + j] : 0.0;
+  }
+}
+template <int NB>
+__device__ inline void mf32_mma(v4d& acc, const double (&xa)[Mf32<NB>::KS], const double (&xb)[Mf32<NB>::KS]) {
+#pragma unroll
+  for (int s = 0; s < Mf32<NB>::KS; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[s], xb[s], acc, 0, 0, 0);
+}
+// Dinv[i][k] = a[rsrc[i] LD + csrc[k]] (LDS) as the A operand
+template <int NB, int LD>
+__device__ inline void mf32_load_dinv(double (&xa)[Mf32<NB>::KS], const double* a, const int* rsrc,
+                                      const int* csrc, int tid) {
+  const int l = tid & 63, w = tid >> 6, i = 16 * (w >> 1) + (l & 15), lk = l >> 4;
+  const int arow = i < NB ? rsrc[i] * LD : 0;
+#pragma unroll
+  for (int s = 0; s < Mf32<NB>::KS; ++s) {
+    const int k = 4 * s + lk;
+    xa[s] = (i < NB && k < NB) ? a[arow + csrc[k]] : 0.0;
+  }
+}
+// rows and columns of the lane's four accumulator entries
+template <int NB>
+__device__ inline void mf32_out(int tid, int q, int& rr, int& cc) {
+  const int l = tid & 63, w = tid >> 6;
+  rr = 16 * (w >> 1) + 4 * q + (l >> 4);
+  cc = 16 * (w & 1) + (l & 15);
+}
+
 template <int NB, int DIM>
 __global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, int64_t fstride,
                                                    const int* __restrict__ nbr, const int* __restrict__ lev_elems,
@@ -899,6 +952,52 @@ __global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, int
     for (int s = 1; s < 2 * DIM; s += 2) {
       if (nbr[i * 2 * DIM + s] < 0) continue;
       scale_mfma64<LD>(bi + int64_t(1 + s) * NB * NB, a, rsrc, csrc, tid);
+    }
+  } else if constexpr (Mf32<NB>::on) {
+    constexpr int KS = Mf32<NB>::KS;
+    // every operand of the three Schur products and of the three upper-block
+    // scalings is requested up front; the scalings' blocks wait in registers
+    // through the inversion
+    double la[DIM][KS], rb[DIM][KS], ub[DIM][KS];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int j = nbr[i * 2 * DIM + 2 * d];
+      mf32_load_a<NB>(la[d], j >= 0 ? bi + int64_t(1 + 2 * d) * NB * NB : nullptr, tid);
+      mf32_load_b<NB>(rb[d], j >= 0 ? blk + (int64_t(j) * NSLOT + 2 + 2 * d) * NB * NB : nullptr, tid);
+      const bool up = nbr[i * 2 * DIM + 2 * d + 1] >= 0;
+      mf32_load_b<NB>(ub[d], up ? bi + int64_t(2 + 2 * d) * NB * NB : nullptr, tid);
+    }
+    v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) mf32_mma<NB>(acc, la[d], rb[d]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int rr, cc;
+      mf32_out<NB>(tid, q, rr, cc);
+      if (rr < NB && cc < NB) a[rr * LD + cc] = bi[rr * NB + cc] - acc[q];
+    }
+    __syncthreads();
+    gj_invert<NB, LD>(a, sh, shi, rsrc, csrc, tid);
+    for (int idx = tid; idx < NB * NB; idx += BT) bi[idx] = a[rsrc[idx / NB] * LD + csrc[idx % NB]];
+    double da[KS];
+    mf32_load_dinv<NB, LD>(da, a, rsrc, csrc, tid);
+    v4d ua[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      ua[d] = v4d{0.0, 0.0, 0.0, 0.0};
+      mf32_mma<NB>(ua[d], da, ub[d]);
+    }
+    __syncthreads();  // all reads of the upper blocks are done before any is overwritten
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      if (nbr[i * 2 * DIM + 2 * d + 1] < 0) continue;
+      double* B = bi + int64_t(2 + 2 * d) * NB * NB;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int rr, cc;
+        mf32_out<NB>(tid, q, rr, cc);
+        if (rr < NB && cc < NB) B[rr * NB + cc] = ua[d][q];
+      }
     }
   } else {
     __shared__ double pa[NB * G::PLD];
@@ -945,7 +1044,7 @@ __global__ void __launch_bounds__(BT) k_ilu_scale_lower(double* __restrict__ blk
   constexpr int LD = NB + 1;
   constexpr int NSLOT = 2 * DIM + 1;
   __shared__ double a[NB * LD];
-  __shared__ double pb[NB == 64 ? 1 : G::KP * NB];  // panel of the vector-unit products only
+  __shared__ double pb[(NB == 64 || Mf32<NB>::on) ? 1 : G::KP * NB];  // panel of the vector-unit products only
   __shared__ int ident[NB];
   const int tid = threadIdx.x;
   blk += blockIdx.y * fstride;
@@ -954,12 +1053,39 @@ __global__ void __launch_bounds__(BT) k_ilu_scale_lower(double* __restrict__ blk
   for (int idx = tid; idx < NB * NB; idx += BT) a[(idx / NB) * LD + idx % NB] = bi[idx];
   if (tid < NB) ident[tid] = tid;
   __syncthreads();
-  for (int s = 0; s < 2 * DIM; s += 2) {
-    if (nbr[i * 2 * DIM + s] < 0) continue;
-    if constexpr (NB == 64)
-      scale_mfma64<LD>(bi + int64_t(1 + s) * NB * NB, a, ident, ident, tid);
-    else
-      scale_block<NB, LD>(bi + int64_t(1 + s) * NB * NB, a, ident, ident, pb, tid);
+  if constexpr (Mf32<NB>::on) {
+    constexpr int KS = Mf32<NB>::KS;
+    double lb[DIM][KS], da[KS];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+      mf32_load_b<NB>(lb[d], nbr[i * 2 * DIM + 2 * d] >= 0 ? bi + int64_t(1 + 2 * d) * NB * NB : nullptr, tid);
+    mf32_load_dinv<NB, LD>(da, a, ident, ident, tid);
+    v4d acc[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      acc[d] = v4d{0.0, 0.0, 0.0, 0.0};
+      mf32_mma<NB>(acc[d], da, lb[d]);
+    }
+    __syncthreads();  // all reads of the lower blocks are done before any is overwritten
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      if (nbr[i * 2 * DIM + 2 * d] < 0) continue;
+      double* B = bi + int64_t(1 + 2 * d) * NB * NB;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int rr, cc;
+        mf32_out<NB>(tid, q, rr, cc);
+        if (rr < NB && cc < NB) B[rr * NB + cc] = acc[d][q];
+      }
+    }
+  } else {
+    for (int s = 0; s < 2 * DIM; s += 2) {
+      if (nbr[i * 2 * DIM + s] < 0) continue;
+      if constexpr (NB == 64)
+        scale_mfma64<LD>(bi + int64_t(1 + s) * NB * NB, a, ident, ident, tid);
+      else
+        scale_block<NB, LD>(bi + int64_t(1 + s) * NB * NB, a, ident, ident, pb, tid);
+    }
   }
 }
 
