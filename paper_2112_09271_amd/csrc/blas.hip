@@ -343,8 +343,11 @@ __global__ void k_dcgs_final(const double* __restrict__ partial, int nblk, int j
   if (threadIdx.x == 0) out[row] = t;
 }
 
-// alpha, h_jj, rho and their reciprocals from the reduced dot products (one block)
-__global__ void k_dcgs_scalars(double* __restrict__ out, int j, int with_w) {
+// alpha, h_jj, rho and their reciprocals from the reduced dot products (one
+// block); with hout (host memory mapped for the device), the entries the host
+// reads are stored there as well: s_0..s_j, c_0..c_j, w.w and the scalars
+// (h_jj = 0, rho = 1 without w)
+__global__ void k_dcgs_scalars(double* __restrict__ out, int j, int with_w, double* __restrict__ hout) {
   __shared__ double sh[VB];
   double ss = 0.0, sc = 0.0, cc = 0.0;
   for (int k = threadIdx.x; k < j; k += VB) {
@@ -361,21 +364,36 @@ __global__ void k_dcgs_scalars(double* __restrict__ out, int j, int with_w) {
   sc = block_sum(sc, sh);
   __syncthreads();
   cc = block_sum(cc, sh);
+  if (hout) {
+    for (int k = threadIdx.x; k <= j; k += VB) {
+      hout[k] = out[k];
+      if (with_w) hout[MAXV + k] = out[MAXV + k];
+    }
+  }
   if (threadIdx.x != 0) return;
   const double a2 = out[j] - ss;
   const double alpha = a2 > 0.0 ? sqrt(a2) : 0.0;
   const double ia = alpha > 0.0 ? 1.0 / alpha : 0.0;
   out[DC_ALPHA] = alpha;
   out[DC_IALPHA] = ia;
+  double hjj = 0.0, rho = 1.0;
   if (with_w) {
-    const double hjj = (out[MAXV + j] - sc) * ia;
+    hjj = (out[MAXV + j] - sc) * ia;
     const double ww = out[DC_WW];
     const double r2 = ww - cc - hjj * hjj;  // |w - V c - v_j h_jj|^2 by Pythagoras: only a scale
-    double rho = r2 > 0.0 ? sqrt(r2) : sqrt(ww);
+    rho = r2 > 0.0 ? sqrt(r2) : sqrt(ww);
     if (!(rho > 0.0)) rho = 1.0;
     out[DC_HJJ] = hjj;
     out[DC_RHO] = rho;
     out[DC_IRHO] = 1.0 / rho;
+  }
+  if (hout) {
+    hout[DC_WW] = with_w ? out[DC_WW] : 0.0;
+    hout[DC_ALPHA] = alpha;
+    hout[DC_IALPHA] = ia;
+    hout[DC_HJJ] = hjj;
+    hout[DC_RHO] = rho;
+    hout[DC_IRHO] = 1.0 / rho;
   }
 }
 
@@ -414,7 +432,7 @@ __global__ void k_dcgs_update(double* __restrict__ V, int64_t ldv, int j, const 
 }
 
 void dcgs_reduce(const double* V, int64_t ldv, int j, const double* u, const void* w, bool w_f32, double* w64,
-                 int64_t n, double* partial, double* coef, hipStream_t s) {
+                 int64_t n, double* partial, double* coef, hipStream_t s, double* hout) {
   const unsigned g = red_grid(n);
   const dim3 grid(g, unsigned(j + 1));
   if (!w)
@@ -428,7 +446,7 @@ void dcgs_reduce(const double* V, int64_t ldv, int j, const double* u, const voi
                        static_cast<double*>(nullptr), n, partial);
   const unsigned nout = w ? unsigned(2 * j + 3) : unsigned(j + 1);
   hipLaunchKernelGGL(k_dcgs_final, dim3(nout), dim3(VB), 0, s, partial, int(g), j, coef);
-  hipLaunchKernelGGL(k_dcgs_scalars, dim3(1), dim3(VB), 0, s, coef, j, w ? 1 : 0);
+  hipLaunchKernelGGL(k_dcgs_scalars, dim3(1), dim3(VB), 0, s, coef, j, w ? 1 : 0, hout);
 }
 
 template <typename TM>

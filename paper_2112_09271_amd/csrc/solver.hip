@@ -83,7 +83,8 @@ struct Krylov {
   // pinned host slots for the coefficient blocks of two consecutive Arnoldi
   // steps and the events that mark their arrival
   static constexpr size_t HSLOT = DCGS_COEF;
-  double* hpin = nullptr;
+  double* hpin = nullptr;      // host view
+  double* hpin_dev = nullptr;  // the same memory as the device addresses it
   hipEvent_t hev[2] = {nullptr, nullptr};
   ~Krylov() {
     for (auto& row : gexec)
@@ -154,8 +155,11 @@ static Krylov& krylov(dgnp_ctx& c, int restart, bool f32) {
     K->n = c.N;
   }
   if (!K->hpin) {
+    // coherent host memory: the coefficient kernel stores into it directly
     DGNP_HIP(hipHostMalloc(reinterpret_cast<void**>(&K->hpin), 2 * Krylov::HSLOT * sizeof(double),
-                           hipHostMallocDefault));
+                           hipHostMallocMapped | hipHostMallocCoherent));
+    for (size_t i = 0; i < 2 * Krylov::HSLOT; ++i) K->hpin[i] = 0.0;
+    DGNP_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&K->hpin_dev), K->hpin, 0));
     for (auto& e : K->hev) DGNP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
   if (f32 && !K->Z32.p) {
@@ -227,21 +231,21 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
     // convergence are discarded.
     double* part = K.hd.p;
     double* coef = K.hd.p + dcgs_partial_size();
-    auto to_host = [&](int q) {
-      DGNP_HIP(hipMemcpyAsync(K.hpin + size_t(q % 2) * Krylov::HSLOT, coef, sizeof(double) * size_t(DCGS_COEF),
-                              hipMemcpyDeviceToHost, s));
-      DGNP_HIP(hipEventRecord(K.hev[q % 2], s));
-    };
+    // the coefficient kernel of step q stores the entries the host reads into
+    // pinned slot q % 2 (free again: the host has read step q - 2 before step
+    // q is queued); the event marks the end of the step
+    auto slot = [&](int q) { return K.hpin_dev + size_t(q % 2) * Krylov::HSLOT; };
+    auto to_host = [&](int q) { DGNP_HIP(hipEventRecord(K.hev[q % 2], s)); };
     auto issue_step = [&](int q) {
       pc_then_jac(c, K, f32, transpose, pc_kind, s);
       {
         // the update pass also stores z_q into Z (preconditioner output column)
         ScopeTimer tm(c, "cgs2", s);
         if (f32) {
-          dcgs_reduce(K.V.p, N, q, K.r.p, K.w32.p, true, K.w.p, N, part, coef, s);
+          dcgs_reduce(K.V.p, N, q, K.r.p, K.w32.p, true, K.w.p, N, part, coef, s, slot(q));
           dcgs_update<float>(K.V.p, N, q, coef, K.r.p, K.w.p, K.v32.p, K.zt32.p, K.Z32.p + int64_t(q) * N, N, s);
         } else {
-          dcgs_reduce(K.V.p, N, q, K.r.p, K.w.p, false, nullptr, N, part, coef, s);
+          dcgs_reduce(K.V.p, N, q, K.r.p, K.w.p, false, nullptr, N, part, coef, s, slot(q));
           dcgs_update<double>(K.V.p, N, q, coef, K.r.p, K.w.p, K.vt.p, K.zt.p, K.Z.p + int64_t(q) * N, N, s);
         }
       }
@@ -250,7 +254,7 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
     auto issue_final = [&](int q) {  // reorthogonalisation of u_q only: completes column q - 1
       {
         ScopeTimer tm(c, "cgs2", s);
-        dcgs_reduce(K.V.p, N, q, K.r.p, nullptr, false, nullptr, N, part, coef, s);
+        dcgs_reduce(K.V.p, N, q, K.r.p, nullptr, false, nullptr, N, part, coef, s, slot(q));
       }
       to_host(q);
     };
