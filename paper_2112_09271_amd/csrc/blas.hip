@@ -292,6 +292,9 @@ double vnorm2(const float* x, int64_t n, double* scratch_dev, hipStream_t s) {
 // then w.w, alpha, h_jj, 1/alpha, rho, 1/rho at 2 MAXV + 0..5.
 static constexpr int DC_WW = 2 * MAXV, DC_ALPHA = 2 * MAXV + 1, DC_HJJ = 2 * MAXV + 2, DC_IALPHA = 2 * MAXV + 3,
                      DC_RHO = 2 * MAXV + 4, DC_IRHO = 2 * MAXV + 5;
+// block partials: rows 0 .. 2 MAXV of RED_BLOCKS each, then the completion
+// counter of the final reduction (zero between reductions)
+static constexpr int64_t DC_COUNT = int64_t(2 * MAXV + 1) * RED_BLOCKS;
 
 // partial[r][y][blk], r = 0: L_y . u, r = 1: L_y . w, row 2 MAXV: w . w
 // (y = j only); L_y = V_y for y < j, L_j = u.  For single-precision w the
@@ -331,24 +334,12 @@ __global__ void k_dcgs_dots(const double* __restrict__ V, int64_t ldv, int j, co
   }
 }
 
-// out[row] = sum of the row's block partials for the rows 0..j, MAXV..MAXV+j
-// and 2 MAXV (the last two groups only with w)
-__global__ void k_dcgs_final(const double* __restrict__ partial, int nblk, int j, double* __restrict__ out) {
-  __shared__ double sh[VB];
-  const int o = blockIdx.x;
-  const int row = o <= j ? o : (o <= 2 * j + 1 ? MAXV + (o - j - 1) : 2 * MAXV);
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += VB) acc += partial[int64_t(row) * RED_BLOCKS + i];
-  const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) out[row] = t;
-}
-
-// alpha, h_jj, rho and their reciprocals from the reduced dot products (one
-// block); with hout (host memory mapped for the device), the entries the host
-// reads are stored there as well: s_0..s_j, c_0..c_j, w.w and the scalars
-// (h_jj = 0, rho = 1 without w)
-__global__ void k_dcgs_scalars(double* __restrict__ out, int j, int with_w, double* __restrict__ hout) {
-  __shared__ double sh[VB];
+// alpha, h_jj, rho and their reciprocals from the reduced dot products (run
+// by one whole block); with hout (host memory mapped for the device), the
+// entries the host reads are stored there as well: s_0..s_j, c_0..c_j, w.w and
+// the scalars (h_jj = 0, rho = 1 without w)
+__device__ void dcgs_scalars_block(double* __restrict__ out, int j, int with_w, double* __restrict__ hout,
+                                   double* sh) {
   double ss = 0.0, sc = 0.0, cc = 0.0;
   for (int k = threadIdx.x; k < j; k += VB) {
     const double sk = out[k];
@@ -395,6 +386,31 @@ __global__ void k_dcgs_scalars(double* __restrict__ out, int j, int with_w, doub
     hout[DC_RHO] = rho;
     hout[DC_IRHO] = 1.0 / rho;
   }
+}
+
+// out[row] = sum of the row's block partials for the rows 0..j, MAXV..MAXV+j
+// and 2 MAXV (the last two groups only with w), one block per row; the block
+// that finishes last (device-wide counter, reset by that block for the next
+// reduction) then forms the scalars
+__global__ void k_dcgs_final(const double* __restrict__ partial, int nblk, int j, int with_w,
+                             double* __restrict__ out, double* __restrict__ hout, unsigned* __restrict__ count) {
+  __shared__ double sh[VB];
+  __shared__ int s_last;
+  const int o = blockIdx.x;
+  const int row = o <= j ? o : (o <= 2 * j + 1 ? MAXV + (o - j - 1) : 2 * MAXV);
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += VB) acc += partial[int64_t(row) * RED_BLOCKS + i];
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    out[row] = t;
+    __threadfence();  // the sum is visible device-wide before the count says so
+    s_last = atomicAdd(count, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();  // every other block's sum is visible to this block
+  if (threadIdx.x == 0) *count = 0u;
+  dcgs_scalars_block(out, j, with_w, hout, sh);
 }
 
 // v_j = (u - V s) / alpha into V column j; u <- (w - V c - v_j h_jj) / rho and
@@ -445,8 +461,8 @@ void dcgs_reduce(const double* V, int64_t ldv, int j, const double* u, const voi
     hipLaunchKernelGGL(k_dcgs_dots<double>, grid, dim3(VB), 0, s, V, ldv, j, u, static_cast<const double*>(w),
                        static_cast<double*>(nullptr), n, partial);
   const unsigned nout = w ? unsigned(2 * j + 3) : unsigned(j + 1);
-  hipLaunchKernelGGL(k_dcgs_final, dim3(nout), dim3(VB), 0, s, partial, int(g), j, coef);
-  hipLaunchKernelGGL(k_dcgs_scalars, dim3(1), dim3(VB), 0, s, coef, j, w ? 1 : 0, hout);
+  hipLaunchKernelGGL(k_dcgs_final, dim3(nout), dim3(VB), 0, s, partial, int(g), j, w ? 1 : 0, coef, hout,
+                     reinterpret_cast<unsigned*>(partial + DC_COUNT));
 }
 
 template <typename TM>
@@ -459,7 +475,7 @@ template void dcgs_update<double>(double*, int64_t, int, const double*, double*,
                                   const double*, double*, int64_t, hipStream_t);
 template void dcgs_update<float>(double*, int64_t, int, const double*, double*, const double*, float*,
                                  const float*, float*, int64_t, hipStream_t);
-int64_t dcgs_partial_size() { return int64_t(2 * MAXV + 1) * RED_BLOCKS; }
+int64_t dcgs_partial_size() { return DC_COUNT + 8; }
 
 template <typename T>
 __global__ void k_combine(const T* __restrict__ Z, int64_t ldz, int k, const double* __restrict__ h,

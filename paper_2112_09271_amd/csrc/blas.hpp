@@ -36,7 +36,8 @@ double vnorm2(const float* x, int64_t n, double* scratch_dev, hipStream_t s);   
 // s, sigma and alpha, for the last column of a cycle; w_f32: w in single
 // precision, widened into w64); dcgs_update writes V[:, j], the next u and
 // its preconditioner-input copy m, and (zd not null) copies zs to zd in the same
-// pass.  partial holds dcgs_partial_size() doubles.  hout (not null: host memory
+// pass.  partial holds dcgs_partial_size() doubles, zero-filled once before the
+// first use (the tail holds a counter that each reduction leaves at zero).  hout (not null: host memory
 // mapped for the device, DCGS_COEF doubles) receives the entries of the block
 // that the host reads, written by the reduction's last kernel.
 void dcgs_reduce(const double* V, int64_t ldv, int j, const double* u, const void* w, bool w_f32, double* w64,

@@ -149,6 +149,7 @@ static Krylov& krylov(dgnp_ctx& c, int restart, bool f32) {
     K->w.alloc(size_t(c.N));
     K->r.alloc(size_t(c.N));
     K->hd.alloc(size_t(std::max(reduce_scratch_size(), dcgs_partial_size())) + DCGS_COEF + MAXV + 8);
+    DGNP_HIP(hipMemset(K->hd.p, 0, K->hd.n * sizeof(double)));  // includes the reduction's counter
     K->Z.release();
     K->Z32.release();
     K->restart = restart;
