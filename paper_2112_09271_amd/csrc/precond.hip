@@ -812,6 +812,12 @@ struct Mg {
   }
 };
 
+bool precond_sweeps_resident(const dgnp_ctx& c, bool f32, bool transpose) {
+  if (!c.pc || transpose) return false;
+  const Precond& P = *c.pc;
+  return (P.lines_on && f32) || P.df_on;
+}
+
 // ILU solves of all concentration blocks at once (one launch per level covers
 // every field): in/out point at the first concentration field (field 1).
 template <typename T>

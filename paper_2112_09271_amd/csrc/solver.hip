@@ -103,6 +103,18 @@ static bool graphs_enabled(const dgnp_ctx& c) {
   return !c.profiling && !(e && e[0] && e[0] != '0');
 }
 
+// Graph capture pays for sequences of many short launches (level-scheduled
+// sweeps: one launch per hyperplane level).  With the resident-grid sweeps the
+// sequence is about twenty launches, which the host queues well ahead of the
+// device, and direct launches avoid the graph's entry and exit gaps (16^3 cube
+// 0.139 -> 0.137 s).  DGNP_GRAPHS=1 captures in every case.
+static bool use_graph(const dgnp_ctx& c, bool f32, bool transpose) {
+  if (!graphs_enabled(c)) return false;
+  const char* f = getenv("DGNP_GRAPHS");
+  if (f && f[0] == '1') return true;
+  return !precond_sweeps_resident(c, f32, transpose);
+}
+
 // z_stage = P in_stage; w = J z_stage, either captured once per linearisation
 // point as a HIP graph (the sequence of ~10^2 small level-scheduled kernels
 // then launches as one unit) or issued directly.
@@ -110,7 +122,7 @@ static void pc_then_jac(dgnp_ctx& c, Krylov& K, bool f32, bool transpose, int pc
   const void* in = f32 ? static_cast<const void*>(K.v32.p) : static_cast<const void*>(K.vt.p);
   void* zs = f32 ? static_cast<void*>(K.zt32.p) : static_cast<void*>(K.zt.p);
   void* w = f32 ? static_cast<void*>(K.w32.p) : static_cast<void*>(K.w.p);
-  if (!graphs_enabled(c)) {
+  if (!use_graph(c, f32, transpose)) {
     precond_apply(c, in, zs, f32, transpose, pc_kind, s);
     jac_apply(c, zs, w, f32, transpose, s);
     return;

@@ -17,6 +17,9 @@ void precond_apply(dgnp_ctx& c, const void* r, void* z, bool f32, bool transpose
                    hipStream_t s);                                     // precond.hip
 void get_block(dgnp_ctx& c, int field, int64_t elem, int slot, double* out);
 void precond_invalidate(dgnp_ctx& c);
+// true when the concentration sweeps of this apply run as one resident grid per
+// direction (line or element dataflow) rather than one launch per level
+bool precond_sweeps_resident(const dgnp_ctx& c, bool f32, bool transpose);
 // clears a dataflow sweep that hit its wait limit; throws DGNP_E_BREAKDOWN if report (synchronises)
 void precond_check(dgnp_ctx& c, bool report = true);
 void vcycle_phi(dgnp_ctx& c, const double* b, double* x, hipStream_t s);     // precond.hip

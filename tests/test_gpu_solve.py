@@ -84,6 +84,11 @@ def test_graph_replay_matches_eager():
             xe, ste = gp.solve(rtol=1e-10, prec=prec)
         finally:
             del os.environ["DGNP_NO_GRAPHS"]
-        xg, stg = gp.solve(rtol=1e-10, prec=prec)
+        # capture forced: with resident-grid sweeps the default launches directly
+        os.environ["DGNP_GRAPHS"] = "1"
+        try:
+            xg, stg = gp.solve(rtol=1e-10, prec=prec)
+        finally:
+            del os.environ["DGNP_GRAPHS"]
         assert ste.lin_its_total == stg.lin_its_total
         assert np.array_equal(host(xe), host(xg))
