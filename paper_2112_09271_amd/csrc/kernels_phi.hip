@@ -86,6 +86,7 @@ __global__ void __launch_bounds__(PHI_NT(P)) k_phi_op(KArgs A, const T* __restri
   __shared__ T R[REG];
   __shared__ int s_nb[6];
   __shared__ T s_de[2][NN];
+  __shared__ T s_B[NQ * NN];  // B(q, a) for the lane-indexed contractions of the face traces
   const int64_t bid = blockIdx.x;
   const int64_t e = (bid % 8) * eper + bid / 8;  // one slab of elements per XCD, as the operator kernel
   if (e >= A.E) return;
@@ -97,6 +98,7 @@ __global__ void __launch_bounds__(PHI_NT(P)) k_phi_op(KArgs A, const T* __restri
   for (int i = tid; i < NB; i += NT) s_u[i] = u[e * NB + i];
   if (tid < 6) s_nb[tid] = A.nbr[e * 6 + tid];
   if (tid < 2 * NN) s_de[tid / NN][tid % NN] = C::De(tid / NN, tid % NN);
+  if (tid < NQ * NN) s_B[tid] = C::B(tid / NN, tid % NN);
   __syncthreads();
 
   // volume: kappa grad u . grad v
@@ -147,29 +149,28 @@ __global__ void __launch_bounds__(PHI_NT(P)) k_phi_op(KArgs A, const T* __restri
     fn[(2 * pr + 1) * NFN + ij] = dn;
   }
   __syncthreads();
-  for (int row = tid; row < NROW; row += NT) {
-    T x[NFN];
+  // node traces to face points, one lane per (row, qi): first along i with
+  // the lane's B(qi, .), then along j with compile-time B(qj, .)
+  for (int idx = tid; idx < NROW * NQ; idx += NT) {
+    const int row = idx / NQ, qi = idx % NQ;
+    T b[NN];
 #pragma unroll
-    for (int k = 0; k < NFN; ++k) x[k] = fn[row * NFN + k];
-    T yv[NN][NQ];
+    for (int i = 0; i < NN; ++i) b[i] = s_B[qi * NN + i];
+    T yv[NN];
 #pragma unroll
-    for (int j = 0; j < NN; ++j)
+    for (int j = 0; j < NN; ++j) {
+      T t = T(0);
 #pragma unroll
-      for (int qi = 0; qi < NQ; ++qi) {
-        T s = T(0);
+      for (int i = 0; i < NN; ++i) t += b[i] * fn[row * NFN + j * NN + i];
+      yv[j] = t;
+    }
 #pragma unroll
-        for (int i = 0; i < NN; ++i) s += C::B(qi, i) * x[j * NN + i];
-        yv[j][qi] = s;
-      }
+    for (int qj = 0; qj < NQ; ++qj) {
+      T t = T(0);
 #pragma unroll
-    for (int qj = 0; qj < NQ; ++qj)
-#pragma unroll
-      for (int qi = 0; qi < NQ; ++qi) {
-        T s = T(0);
-#pragma unroll
-        for (int j = 0; j < NN; ++j) s += C::B(qj, j) * yv[j][qi];
-        fq[row * NQF + qj * NQ + qi] = s;
-      }
+      for (int j = 0; j < NN; ++j) t += C::B(qj, j) * yv[j];
+      fq[row * NQF + qj * NQ + qi] = t;
+    }
   }
   __syncthreads();
   // fluxes: coefficients of v and dv/dx_ax of the own element (kappa tables
@@ -199,29 +200,28 @@ __global__ void __launch_bounds__(PHI_NT(P)) k_phi_op(KArgs A, const T* __restri
     cf[(fc * 2 + 1) * NQF + qf] = G * ih[ax];
   }
   __syncthreads();
-  for (int rc = tid; rc < 12; rc += NT) {
-    T x[NQF];
+  // face-point coefficients back to node traces, one lane per (row, j): first
+  // along qj with the lane's B(., j), then along qi with compile-time B(., i)
+  for (int idx = tid; idx < 12 * NN; idx += NT) {
+    const int rc = idx / NN, j = idx % NN;
+    T b[NQ];
 #pragma unroll
-    for (int k = 0; k < NQF; ++k) x[k] = cf[rc * NQF + k];
-    T yv[NN][NQ];
+    for (int qj = 0; qj < NQ; ++qj) b[qj] = s_B[qj * NN + j];
+    T yv[NQ];
 #pragma unroll
-    for (int j = 0; j < NN; ++j)
+    for (int qi = 0; qi < NQ; ++qi) {
+      T t = T(0);
 #pragma unroll
-      for (int qi = 0; qi < NQ; ++qi) {
-        T s = T(0);
+      for (int qj = 0; qj < NQ; ++qj) t += b[qj] * cf[rc * NQF + qj * NQ + qi];
+      yv[qi] = t;
+    }
 #pragma unroll
-        for (int qj = 0; qj < NQ; ++qj) s += C::B(qj, j) * x[qj * NQ + qi];
-        yv[j][qi] = s;
-      }
+    for (int i = 0; i < NN; ++i) {
+      T t = T(0);
 #pragma unroll
-    for (int j = 0; j < NN; ++j)
-#pragma unroll
-      for (int i = 0; i < NN; ++i) {
-        T s = T(0);
-#pragma unroll
-        for (int qi = 0; qi < NQ; ++qi) s += C::B(qi, i) * yv[j][qi];
-        tnt[rc * NFN + j * NN + i] = s;
-      }
+      for (int qi = 0; qi < NQ; ++qi) t += C::B(qi, i) * yv[qi];
+      tnt[rc * NFN + j * NN + i] = t;
+    }
   }
   __syncthreads();
   for (int node = tid; node < NB; node += NT) {
