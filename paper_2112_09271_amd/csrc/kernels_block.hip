@@ -1430,7 +1430,8 @@ __global__ void k_q1_prolong(int3 n3, const T* __restrict__ xv, T* __restrict__ 
 // contracts its nodal values with the corner's trilinear shape one direction
 // at a time; the lanes' sums are combined by shuffles (a fixed order).
 template <typename T, int DIM, int P>
-__global__ void k_q1_restrict(int3 n3, const T* __restrict__ r, T* __restrict__ rv, int64_t nvert) {
+__global__ void k_q1_restrict(int3 n3, const T* __restrict__ r, T* __restrict__ rv, int64_t nvert,
+                              const T* __restrict__ dinv, T c1, T* __restrict__ d1) {
   constexpr int NN = P + 1;
   constexpr int NB = DIM == 3 ? NN * NN * NN : NN * NN;
   constexpr int NV = 1 << DIM;
@@ -1471,7 +1472,13 @@ __global__ void k_q1_restrict(int3 n3, const T* __restrict__ r, T* __restrict__ 
   }
 #pragma unroll
   for (int m = 1; m < NV; m <<= 1) acc += __shfl_xor(acc, m, 64);
-  if (o == 0) rv[v] = T(acc);
+  if (o == 0) {
+    const T rvv = T(acc);
+    rv[v] = rvv;
+    // first Chebyshev step of the vertex level from a zero guess, as the CSR
+    // smoother computes it: d_1 = c1 (D^{-1} r)
+    if (d1) d1[v] = c1 * (dinv[v] * rvv);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2074,7 +2081,8 @@ template void launch_bdiag<double>(int, int64_t, const double*, const double*, d
 template void launch_bdiag<float>(int, int64_t, const float*, const float*, float*, hipStream_t);
 
 template <typename T, int DIM, int P>
-static void q1_t(bool prolong, const int* n, const T* a, T* b, T beta, int64_t E, int64_t nvert, hipStream_t s) {
+static void q1_t(bool prolong, const int* n, const T* a, T* b, T beta, int64_t E, int64_t nvert, const T* dinv,
+                 T c1, T* d1, hipStream_t s) {
   int3 n3 = make_int3(n[0], n[1], n[2]);
   constexpr int NN = P + 1;
   constexpr int NB = DIM == 3 ? NN * NN * NN : NN * NN;
@@ -2085,21 +2093,22 @@ static void q1_t(bool prolong, const int* n, const T* a, T* b, T beta, int64_t E
   } else {
     const int64_t tot = nvert << DIM;  // 2^DIM lanes per vertex
     hipLaunchKernelGGL((k_q1_restrict<T, DIM, P>), dim3(unsigned((tot + 255) / 256)), dim3(256), 0, s, n3, a, b,
-                       nvert);
+                       nvert, dinv, c1, d1);
   }
 }
 
 template <typename T>
 void launch_q1(bool prolong, int dim, int p, const int* n, const T* a, T* b, T beta, int64_t E, int64_t nvert,
-               hipStream_t s) {
+               hipStream_t s, const T* dinv, T c1, T* d1) {
+  if (!prolong && d1 && !dinv) throw Error(DGNP_E_ARG, "vertex restriction: first smoothing step without D^-1");
   if (dim == 3) {
-    if (p == 1) q1_t<T, 3, 1>(prolong, n, a, b, beta, E, nvert, s);
-    else if (p == 2) q1_t<T, 3, 2>(prolong, n, a, b, beta, E, nvert, s);
-    else q1_t<T, 3, 3>(prolong, n, a, b, beta, E, nvert, s);
+    if (p == 1) q1_t<T, 3, 1>(prolong, n, a, b, beta, E, nvert, dinv, c1, d1, s);
+    else if (p == 2) q1_t<T, 3, 2>(prolong, n, a, b, beta, E, nvert, dinv, c1, d1, s);
+    else q1_t<T, 3, 3>(prolong, n, a, b, beta, E, nvert, dinv, c1, d1, s);
   } else {
-    if (p == 1) q1_t<T, 2, 1>(prolong, n, a, b, beta, E, nvert, s);
-    else if (p == 2) q1_t<T, 2, 2>(prolong, n, a, b, beta, E, nvert, s);
-    else q1_t<T, 2, 3>(prolong, n, a, b, beta, E, nvert, s);
+    if (p == 1) q1_t<T, 2, 1>(prolong, n, a, b, beta, E, nvert, dinv, c1, d1, s);
+    else if (p == 2) q1_t<T, 2, 2>(prolong, n, a, b, beta, E, nvert, dinv, c1, d1, s);
+    else q1_t<T, 2, 3>(prolong, n, a, b, beta, E, nvert, dinv, c1, d1, s);
   }
   DGNP_HIP(hipGetLastError());
 }
@@ -2153,9 +2162,9 @@ template void launch_p1<double>(bool, int, int, const double*, const double*, do
 template void launch_p1<float>(bool, int, int, const float*, const float*, float*, float, int64_t, hipStream_t);
 
 template void launch_q1<double>(bool, int, int, const int*, const double*, double*, double, int64_t, int64_t,
-                                hipStream_t);
+                                hipStream_t, const double*, double, double*);
 template void launch_q1<float>(bool, int, int, const int*, const float*, float*, float, int64_t, int64_t,
-                               hipStream_t);
+                               hipStream_t, const float*, float, float*);
 
 void launch_q1_galerkin(int dim, int p, int64_t E, const double* blk, double* gal, hipStream_t s) {
   dim3 g(unsigned(E), unsigned(2 * dim + 1));

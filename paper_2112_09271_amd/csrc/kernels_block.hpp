@@ -54,9 +54,11 @@ void launch_bspmv(int nb, int dim, int64_t E, const T* blk, const int* nbr, cons
                   T beta, T* y, hipStream_t s);
 template <typename T>
 void launch_bdiag(int nb, int64_t E, const T* dinv, const T* x, T* y, hipStream_t s);
+// restriction (d1 not null): also d1 = c1 (dinv .* b), the first Chebyshev
+// step of the vertex level from a zero guess
 template <typename T>
 void launch_q1(bool prolong, int dim, int p, const int* n, const T* a, T* b, T beta, int64_t E, int64_t nvert,
-               hipStream_t s);
+               hipStream_t s, const T* dinv = nullptr, T c1 = T(0), T* d1 = nullptr);
 void launch_q1_galerkin(int dim, int p, int64_t E, const double* blk, double* gal, hipStream_t s);
 // st[nvert][3^dim]: the Galerkin vertex operator as a dense 3^dim-point stencil per vertex
 void launch_vertex_stencil(int dim, const double* gal, const int* nbr, const int* n, int64_t nvert, double* st,

@@ -733,7 +733,14 @@ struct Mg {
     }
     if (l == top()) {
       launch_bspmv<T>(bnb(), c.dim, c.E, bblk(), c.d_nbr.p, x, b, T(-1), T(1), r, s);
-      launch_q1<T>(false, c.dim, bp(), c.n, r, rc, T(0), c.E, P.nvert, s);
+      if (l + 1 < last()) {
+        // the vertex level smooths: its first Chebyshev step rides on the restriction
+        launch_q1<T>(false, c.dim, bp(), c.n, r, rc, T(0), c.E, P.nvert, s, Sel<T>::ldinv(csr(l + 1)),
+                     T(cheb_c1(l + 1)), Sel<T>::w(P, size_t(l + 1) * 5 + 3));
+        first_done = l + 1;
+      } else {
+        launch_q1<T>(false, c.dim, bp(), c.n, r, rc, T(0), c.E, P.nvert, s);
+      }
     } else {
       DevCsr<T>& M = Sel<T>::A(csr(l));
       launch_csr_spmv<T>(M.n, M.rp.p, M.ci.p, M.v.p, x, b, T(-1), T(1), r, s);
@@ -779,6 +786,13 @@ struct Mg {
   //   d_2 = (2 rho_1 / delta) D^{-1} r_1 + rho_1 rho_0 d_1,  x_2 = x_1 + d_2,
   // rho_0 = delta / theta, rho_1 = 1 / (2 theta / delta - rho_0); two fused
   // launches per sweep.  Zero initial guess: r_0 = b; otherwise r_0 = b - A x_0.
+  int last() const { return top() + int(P.mg.size()); }
+  // level whose first zero-guess Chebyshev step the restriction already wrote
+  int first_done = -1;
+  double cheb_c1(int l) const {
+    const double lm = lmax(l), lo = 0.1 * lm, hi = 1.1 * lm;
+    return 1.0 / (0.5 * (hi + lo));
+  }
   void cheb(int l, const T* b, T* x, bool zero_init) {
     T* r1 = Sel<T>::w(P, size_t(l) * 5 + 2);
     T* d1 = Sel<T>::w(P, size_t(l) * 5 + 3);
@@ -788,7 +802,10 @@ struct Mg {
     const double rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
     const double a2 = 2.0 * rho1 / delta, b2 = rho1 * rho0;
     if (zero_init) {
-      step(l, nullptr, b, nullptr, nullptr, 1.0 / theta, 0.0, nullptr, nullptr, d1);  // x_1 = d_1
+      if (first_done == l)
+        first_done = -1;  // d_1 written by the restriction into this level
+      else
+        step(l, nullptr, b, nullptr, nullptr, cheb_c1(l), 0.0, nullptr, nullptr, d1);  // x_1 = d_1
       step(l, d1, b, d1, d1, a2, b2, nullptr, nullptr, x);
     } else {
       step(l, x, b, nullptr, x, 1.0 / theta, 0.0, r1, d1, x1);
@@ -796,8 +813,7 @@ struct Mg {
     }
   }
   void vcycle(int l, const T* b, T* x) {
-    const int last = top() + int(P.mg.size());
-    if (l == last) {
+    if (l == last()) {
       launch_dense_gemv<T>(P.nc, Sel<T>::cinv(P), b, x, s);
       return;
     }
