@@ -196,15 +196,19 @@ static std::vector<double> diag_of(const Csr& A) {
   return d;
 }
 
-double lmax_dinvA(const Csr& A, const std::vector<double>& dinv, int iters) {
+double lmax_dinvA(const Csr& A, const std::vector<double>& dinv, int iters, std::vector<double>* x_io) {
   const int n = A.n;
   std::vector<double> x(static_cast<size_t>(n)), y(static_cast<size_t>(n));
-  uint64_t s = 0x9E3779B97F4A7C15ull;
-  for (int i = 0; i < n; ++i) {
-    s ^= s << 13;
-    s ^= s >> 7;
-    s ^= s << 17;
-    x[i] = double(s % 1000003) / 1000003.0 + 0.5;
+  if (x_io && x_io->size() == size_t(n)) {
+    x = *x_io;  // warm start from an earlier estimate's last vector
+  } else {
+    uint64_t s = 0x9E3779B97F4A7C15ull;
+    for (int i = 0; i < n; ++i) {
+      s ^= s << 13;
+      s ^= s >> 7;
+      s ^= s << 17;
+      x[i] = double(s % 1000003) / 1000003.0 + 0.5;
+    }
   }
   const int nch = (n + CH - 1) / CH;
   std::vector<double> px(static_cast<size_t>(nch)), py(static_cast<size_t>(nch));
@@ -234,6 +238,7 @@ double lmax_dinvA(const Csr& A, const std::vector<double>& dinv, int iters) {
       for (int i = r0; i < r1; ++i) x[i] = y[i] * inv;
     });
   }
+  if (x_io) *x_io = std::move(x);
   return lam;
 }
 
@@ -407,7 +412,7 @@ static Csr sa_prolongator(const Csr& A, double theta, double lam_A) {
   std::vector<double> dinv(static_cast<size_t>(n));
   for (int i = 0; i < n; ++i) dinv[i] = d[i] != 0.0 ? 1.0 / d[i] : 0.0;
   // with theta = 0 every connection is strong and the filtered matrix is A itself
-  const double lam = theta == 0.0 && lam_A > 0.0 ? lam_A : lmax_dinvA(Af, dinv, 20);
+  const double lam = theta == 0.0 && lam_A > 0.0 ? lam_A : lmax_dinvA(Af, dinv, 20, nullptr);
   const double omega = (4.0 / 3.0) / lam;
   Csr AP = csr_matmul(Af, Pt);
   for (int i = 0; i < n; ++i)
@@ -440,24 +445,31 @@ static Csr sa_prolongator(const Csr& A, double theta, double lam_A) {
   return P;
 }
 
-AmgHierarchy sa_setup(const Csr& A1, int max_levels, int coarse_size, double theta) {
+static void sa_mark(std::chrono::steady_clock::time_point& t0, const char* what) {
   static const bool trace = getenv("DGNP_TRACE_SETUP") != nullptr;
+  if (!trace) return;
+  const auto t1 = std::chrono::steady_clock::now();
+  fprintf(stderr, "[setup]   sa %-18s %8.3f ms\n", what, 1e3 * std::chrono::duration<double>(t1 - t0).count());
+  t0 = t1;
+}
+
+// Jacobi diagonal and the largest eigenvalue estimate of D^{-1} A of a level;
+// x0 (finest level only, may be null): start vector in, last vector out, with
+// `iters` power steps
+static void smoother_data(AmgHierarchy& H, const Csr& A, int iters, std::vector<double>* x0) {
+  std::vector<double> d = diag_of(A), dinv(d.size());
+  for (size_t i = 0; i < d.size(); ++i) dinv[i] = d[i] != 0.0 ? 1.0 / d[i] : 0.0;
+  H.lmax.push_back(lmax_dinvA(A, dinv, iters, x0));
+  H.dinv.push_back(std::move(dinv));
+}
+
+AmgHierarchy sa_setup(const Csr& A1, int max_levels, int coarse_size, double theta, std::vector<double>* x0) {
   auto t0 = std::chrono::steady_clock::now();
-  auto mark = [&](const char* what) {
-    if (!trace) return;
-    const auto t1 = std::chrono::steady_clock::now();
-    fprintf(stderr, "[setup]   sa %-18s %8.3f ms\n", what, 1e3 * std::chrono::duration<double>(t1 - t0).count());
-    t0 = t1;
-  };
+  auto mark = [&](const char* what) { sa_mark(t0, what); };
   AmgHierarchy H;
   H.A.push_back(A1);
-  auto smoother_data = [&](const Csr& A) {
-    std::vector<double> d = diag_of(A), dinv(d.size());
-    for (size_t i = 0; i < d.size(); ++i) dinv[i] = d[i] != 0.0 ? 1.0 / d[i] : 0.0;
-    H.lmax.push_back(lmax_dinvA(A, dinv, 20));
-    H.dinv.push_back(std::move(dinv));
-  };
-  smoother_data(H.A.back());
+  if (x0) x0->clear();  // cold: the estimate does not depend on earlier set-ups
+  smoother_data(H, H.A.back(), 20, x0);
   mark("lmax");
   while (int(H.A.size()) < max_levels && H.A.back().n > coarse_size) {
     const Csr& A = H.A.back();
@@ -470,12 +482,33 @@ AmgHierarchy sa_setup(const Csr& A1, int max_levels, int coarse_size, double the
     H.P.push_back(std::move(P));
     H.R.push_back(std::move(R));
     H.A.push_back(std::move(Ac));
-    smoother_data(H.A.back());
+    smoother_data(H, H.A.back(), 20, nullptr);
     mark("lmax");
   }
   if (H.A.back().n > 4096)
     throw Error(DGNP_E_BREAKDOWN, "algebraic multigrid coarsening stalled at " + std::to_string(H.A.back().n) +
                                       " unknowns");
+  H.coarse_inv = dense_inverse(H.A.back());
+  mark("coarse inverse");
+  return H;
+}
+
+AmgHierarchy sa_setup_reuse(const Csr& A1, const AmgHierarchy& prev, std::vector<double>* x0) {
+  auto t0 = std::chrono::steady_clock::now();
+  auto mark = [&](const char* what) { sa_mark(t0, what); };
+  if (prev.A.empty() || prev.A[0].n != A1.n)
+    throw Error(DGNP_E_STATE, "aggregation reuse: the vertex level changed size");
+  AmgHierarchy H;
+  H.A.push_back(A1);
+  smoother_data(H, H.A.back(), x0 && x0->size() == size_t(A1.n) ? 8 : 20, x0);
+  mark("lmax (warm)");
+  for (size_t l = 0; l < prev.P.size(); ++l) {
+    H.P.push_back(prev.P[l]);
+    H.R.push_back(prev.R[l]);
+    H.A.push_back(csr_matmul(H.R.back(), csr_matmul(H.A[l], H.P.back())));
+    smoother_data(H, H.A.back(), 20, nullptr);
+  }
+  mark("RAP (kept P)");
   H.coarse_inv = dense_inverse(H.A.back());
   mark("coarse inverse");
   return H;

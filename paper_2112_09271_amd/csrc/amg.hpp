@@ -23,7 +23,15 @@ struct AmgHierarchy {
 
 Csr csr_transpose(const Csr& A);
 Csr csr_matmul(const Csr& A, const Csr& B);
-double lmax_dinvA(const Csr& A, const std::vector<double>& dinv, int iters);
-AmgHierarchy sa_setup(const Csr& A1, int max_levels, int coarse_size, double theta);
+// power iterations for the largest eigenvalue of D^{-1} A; x_io (may be null):
+// start vector in (used when its size matches), last vector out
+double lmax_dinvA(const Csr& A, const std::vector<double>& dinv, int iters, std::vector<double>* x_io = nullptr);
+// x0 (may be null) receives the finest level's last power-iteration vector
+AmgHierarchy sa_setup(const Csr& A1, int max_levels, int coarse_size, double theta,
+                      std::vector<double>* x0 = nullptr);
+// the same hierarchy shape for a new finest matrix with the aggregates and
+// prolongators of prev kept: only the Galerkin products, smoother data and
+// coarse inverse are recomputed; the finest estimate warm-starts from x0
+AmgHierarchy sa_setup_reuse(const Csr& A1, const AmgHierarchy& prev, std::vector<double>* x0);
 
 }  // namespace dgnp

@@ -696,7 +696,7 @@ __device__ inline void gemm_gg(double (&acc)[BlkGemm<NB>::RT][BlkGemm<NB>::RT], 
 // with the LDS array a of leading dimension LD
 template <int NB, int LD>
 __device__ inline void scale_block(double* __restrict__ B, const double* a, const int* rsrc, const int* csrc,
-                                   double* pb, int tid) {
+                                   double* pb, int tid, float* __restrict__ B32) {
   using G = BlkGemm<NB>;
   constexpr int PE = (NB * G::KP + BT - 1) / BT;
   constexpr int NP = (NB + G::KP - 1) / G::KP;
@@ -761,7 +761,10 @@ __device__ inline void scale_block(double* __restrict__ B, const double* a, cons
 #pragma unroll
     for (int j = 0; j < G::RT; ++j) {
       const int r = ty + 16 * i, c = tx + 16 * j;
-      if (r < NB && c < NB) B[r * NB + c] = acc[i][j];
+      if (r < NB && c < NB) {
+        B[r * NB + c] = acc[i][j];
+        if (B32) B32[r * NB + c] = float(acc[i][j]);
+      }
     }
 }
 
@@ -818,7 +821,7 @@ __device__ inline void gemm_mfma64(v4d (&acc)[4], const double* __restrict__ L, 
 // written only after the work-group's barrier.
 template <int LD>
 __device__ inline void scale_mfma64(double* __restrict__ B, const double* a, const int* rsrc, const int* csrc,
-                                    int tid) {
+                                    int tid, float* __restrict__ B32) {
   const int l = tid & 63, w = tid >> 6, li = l & 15, lk = l >> 4;
   const int arow = rsrc[16 * w + li] * LD;
   const double* rp = B + lk * 64 + li;
@@ -856,7 +859,11 @@ __device__ inline void scale_mfma64(double* __restrict__ B, const double* a, con
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) B[(16 * w + 4 * q + lk) * 64 + 16 * t + li] = acc[t][q];
+    for (int q = 0; q < 4; ++q) {
+      const int o = (16 * w + 4 * q + lk) * 64 + 16 * t + li;
+      B[o] = acc[t][q];
+      if (B32) B32[o] = float(acc[t][q]);
+    }
 }
 
 // ---- 17..32-row blocks on the FP64 matrix cores (padded to 32 x 32) ----------
@@ -912,10 +919,19 @@ __device__ inline void mf32_out(int tid, int q, int& rr, int& cc) {
   cc = 16 * (w & 1) + (l & 15);
 }
 
+// single-precision copy of a block that is all zeros (no neighbour there)
+template <int NB>
+__device__ inline void zero_block32(float* f, int tid) {
+  if (f)
+    for (int idx = tid; idx < NB * NB; idx += BT) f[idx] = 0.0f;
+}
+
+// b32 (not null): every block the kernel finalises is also stored in single
+// precision there (same layout and field stride as blk)
 template <int NB, int DIM>
 __global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, int64_t fstride,
                                                    const int* __restrict__ nbr, const int* __restrict__ lev_elems,
-                                                   int64_t first) {
+                                                   int64_t first, float* __restrict__ b32) {
   using G = BlkGemm<NB>;
   constexpr int LD = NB + 1;
   constexpr int NSLOT = 2 * DIM + 1;
@@ -926,6 +942,7 @@ __global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, int
   blk += blockIdx.y * fstride;
   const int64_t i = lev_elems[first + blockIdx.x];
   double* bi = blk + i * NSLOT * NB * NB;
+  float* fi = b32 ? b32 + blockIdx.y * fstride + i * NSLOT * NB * NB : nullptr;
   if constexpr (NB == 64) {
     // Schur complement on the matrix cores, then a = A_ii - sum
     v4d acc[4];
@@ -948,10 +965,18 @@ __global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, int
     }
     __syncthreads();
     gj_invert<NB, LD>(a, sh, shi, rsrc, csrc, tid);
-    for (int idx = tid; idx < NB * NB; idx += BT) bi[idx] = a[rsrc[idx / NB] * LD + csrc[idx % NB]];
+    for (int idx = tid; idx < NB * NB; idx += BT) {
+      const double dv = a[rsrc[idx / NB] * LD + csrc[idx % NB]];
+      bi[idx] = dv;
+      if (fi) fi[idx] = float(dv);
+    }
     for (int s = 1; s < 2 * DIM; s += 2) {
-      if (nbr[i * 2 * DIM + s] < 0) continue;
-      scale_mfma64<LD>(bi + int64_t(1 + s) * NB * NB, a, rsrc, csrc, tid);
+      float* f32s = fi ? fi + int64_t(1 + s) * NB * NB : nullptr;
+      if (nbr[i * 2 * DIM + s] < 0) {
+        zero_block32<NB>(f32s, tid);
+        continue;
+      }
+      scale_mfma64<LD>(bi + int64_t(1 + s) * NB * NB, a, rsrc, csrc, tid, f32s);
     }
   } else if constexpr (Mf32<NB>::on) {
     constexpr int KS = Mf32<NB>::KS;
@@ -978,7 +1003,11 @@ __global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, int
     }
     __syncthreads();
     gj_invert<NB, LD>(a, sh, shi, rsrc, csrc, tid);
-    for (int idx = tid; idx < NB * NB; idx += BT) bi[idx] = a[rsrc[idx / NB] * LD + csrc[idx % NB]];
+    for (int idx = tid; idx < NB * NB; idx += BT) {
+      const double dv = a[rsrc[idx / NB] * LD + csrc[idx % NB]];
+      bi[idx] = dv;
+      if (fi) fi[idx] = float(dv);
+    }
     double da[KS];
     mf32_load_dinv<NB, LD>(da, a, rsrc, csrc, tid);
     v4d ua[DIM];
@@ -990,13 +1019,20 @@ __global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, int
     __syncthreads();  // all reads of the upper blocks are done before any is overwritten
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-      if (nbr[i * 2 * DIM + 2 * d + 1] < 0) continue;
+      float* B32 = fi ? fi + int64_t(2 + 2 * d) * NB * NB : nullptr;
+      if (nbr[i * 2 * DIM + 2 * d + 1] < 0) {
+        zero_block32<NB>(B32, tid);
+        continue;
+      }
       double* B = bi + int64_t(2 + 2 * d) * NB * NB;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         int rr, cc;
         mf32_out<NB>(tid, q, rr, cc);
-        if (rr < NB && cc < NB) B[rr * NB + cc] = ua[d][q];
+        if (rr < NB && cc < NB) {
+          B[rr * NB + cc] = ua[d][q];
+          if (B32) B32[rr * NB + cc] = float(ua[d][q]);
+        }
       }
     }
   } else {
@@ -1027,11 +1063,19 @@ __global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, int
       }
     __syncthreads();
     gj_invert<NB, LD>(a, sh, shi, rsrc, csrc, tid);
-    for (int idx = tid; idx < NB * NB; idx += BT) bi[idx] = a[rsrc[idx / NB] * LD + csrc[idx % NB]];
+    for (int idx = tid; idx < NB * NB; idx += BT) {
+      const double dv = a[rsrc[idx / NB] * LD + csrc[idx % NB]];
+      bi[idx] = dv;
+      if (fi) fi[idx] = float(dv);
+    }
     // upper neighbours (slots 1, 3, 5 = +x, +y, +z)
     for (int s = 1; s < 2 * DIM; s += 2) {
-      if (nbr[i * 2 * DIM + s] < 0) continue;
-      scale_block<NB, LD>(bi + int64_t(1 + s) * NB * NB, a, rsrc, csrc, pb, tid);
+      float* f32s = fi ? fi + int64_t(1 + s) * NB * NB : nullptr;
+      if (nbr[i * 2 * DIM + s] < 0) {
+        zero_block32<NB>(f32s, tid);
+        continue;
+      }
+      scale_block<NB, LD>(bi + int64_t(1 + s) * NB * NB, a, rsrc, csrc, pb, tid, f32s);
     }
   }
 }
@@ -1039,7 +1083,7 @@ __global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, int
 // lower blocks of every element: slot 1+s <- D_i^{-1} A_{i,nbr(s)}, s = 0, 2, 4
 template <int NB, int DIM>
 __global__ void __launch_bounds__(BT) k_ilu_scale_lower(double* __restrict__ blk, int64_t fstride,
-                                                        const int* __restrict__ nbr) {
+                                                        const int* __restrict__ nbr, float* __restrict__ b32) {
   using G = BlkGemm<NB>;
   constexpr int LD = NB + 1;
   constexpr int NSLOT = 2 * DIM + 1;
@@ -1050,6 +1094,7 @@ __global__ void __launch_bounds__(BT) k_ilu_scale_lower(double* __restrict__ blk
   blk += blockIdx.y * fstride;
   const int64_t i = blockIdx.x;
   double* bi = blk + i * NSLOT * NB * NB;
+  float* fi = b32 ? b32 + blockIdx.y * fstride + i * NSLOT * NB * NB : nullptr;
   for (int idx = tid; idx < NB * NB; idx += BT) a[(idx / NB) * LD + idx % NB] = bi[idx];
   if (tid < NB) ident[tid] = tid;
   __syncthreads();
@@ -1069,22 +1114,33 @@ __global__ void __launch_bounds__(BT) k_ilu_scale_lower(double* __restrict__ blk
     __syncthreads();  // all reads of the lower blocks are done before any is overwritten
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-      if (nbr[i * 2 * DIM + 2 * d] < 0) continue;
+      float* B32 = fi ? fi + int64_t(1 + 2 * d) * NB * NB : nullptr;
+      if (nbr[i * 2 * DIM + 2 * d] < 0) {
+        zero_block32<NB>(B32, tid);
+        continue;
+      }
       double* B = bi + int64_t(1 + 2 * d) * NB * NB;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         int rr, cc;
         mf32_out<NB>(tid, q, rr, cc);
-        if (rr < NB && cc < NB) B[rr * NB + cc] = acc[d][q];
+        if (rr < NB && cc < NB) {
+          B[rr * NB + cc] = acc[d][q];
+          if (B32) B32[rr * NB + cc] = float(acc[d][q]);
+        }
       }
     }
   } else {
     for (int s = 0; s < 2 * DIM; s += 2) {
-      if (nbr[i * 2 * DIM + s] < 0) continue;
+      float* f32s = fi ? fi + int64_t(1 + s) * NB * NB : nullptr;
+      if (nbr[i * 2 * DIM + s] < 0) {
+        zero_block32<NB>(f32s, tid);
+        continue;
+      }
       if constexpr (NB == 64)
-        scale_mfma64<LD>(bi + int64_t(1 + s) * NB * NB, a, ident, ident, tid);
+        scale_mfma64<LD>(bi + int64_t(1 + s) * NB * NB, a, ident, ident, tid, f32s);
       else
-        scale_block<NB, LD>(bi + int64_t(1 + s) * NB * NB, a, ident, ident, pb, tid);
+        scale_block<NB, LD>(bi + int64_t(1 + s) * NB * NB, a, ident, ident, pb, tid, f32s);
     }
   }
 }
@@ -1942,29 +1998,29 @@ void launch_block_inverse(int nb, int64_t E, const double* blk, int nslot, doubl
 
 template <int NB, int DIM>
 static void fac_t(int nfields, int64_t fstride, double* blk, const int* nbr, const int* lev, int64_t first,
-                  int64_t count, hipStream_t s) {
+                  int64_t count, float* b32, hipStream_t s) {
   if (count > 0)
     hipLaunchKernelGGL((k_ilu_factor<NB, DIM>), dim3(unsigned(count), unsigned(nfields)), dim3(BT), 0, s, blk,
-                       fstride, nbr, lev, first);
+                       fstride, nbr, lev, first, b32);
   else
     hipLaunchKernelGGL((k_ilu_scale_lower<NB, DIM>), dim3(unsigned(-count), unsigned(nfields)), dim3(BT), 0, s,
-                       blk, fstride, nbr);
+                       blk, fstride, nbr, b32);
 }
 
 static void fac_dispatch(int nb, int dim, int nfields, int64_t fstride, double* blk, const int* nbr,
-                         const int* lev, int64_t first, int64_t count, hipStream_t s) {
+                         const int* lev, int64_t first, int64_t count, float* b32, hipStream_t s) {
   if (dim == 3) {
     switch (nb) {
-      case 8: fac_t<8, 3>(nfields, fstride, blk, nbr, lev, first, count, s); break;
-      case 27: fac_t<27, 3>(nfields, fstride, blk, nbr, lev, first, count, s); break;
-      case 64: fac_t<64, 3>(nfields, fstride, blk, nbr, lev, first, count, s); break;
+      case 8: fac_t<8, 3>(nfields, fstride, blk, nbr, lev, first, count, b32, s); break;
+      case 27: fac_t<27, 3>(nfields, fstride, blk, nbr, lev, first, count, b32, s); break;
+      case 64: fac_t<64, 3>(nfields, fstride, blk, nbr, lev, first, count, b32, s); break;
       default: throw Error(DGNP_E_ARG, "unsupported block size");
     }
   } else {
     switch (nb) {
-      case 4: fac_t<4, 2>(nfields, fstride, blk, nbr, lev, first, count, s); break;
-      case 9: fac_t<9, 2>(nfields, fstride, blk, nbr, lev, first, count, s); break;
-      case 16: fac_t<16, 2>(nfields, fstride, blk, nbr, lev, first, count, s); break;
+      case 4: fac_t<4, 2>(nfields, fstride, blk, nbr, lev, first, count, b32, s); break;
+      case 9: fac_t<9, 2>(nfields, fstride, blk, nbr, lev, first, count, b32, s); break;
+      case 16: fac_t<16, 2>(nfields, fstride, blk, nbr, lev, first, count, b32, s); break;
       default: throw Error(DGNP_E_ARG, "unsupported block size");
     }
   }
@@ -1972,15 +2028,15 @@ static void fac_dispatch(int nb, int dim, int nfields, int64_t fstride, double* 
 }
 
 void launch_ilu_factor(int nb, int dim, int nfields, int64_t fstride, double* blk, const int* nbr,
-                       const int* lev, int64_t first, int64_t count, hipStream_t s) {
+                       const int* lev, int64_t first, int64_t count, hipStream_t s, float* b32) {
   if (count == 0 || nfields == 0) return;
-  fac_dispatch(nb, dim, nfields, fstride, blk, nbr, lev, first, count, s);
+  fac_dispatch(nb, dim, nfields, fstride, blk, nbr, lev, first, count, b32, s);
 }
 
 void launch_ilu_scale_lower(int nb, int dim, int nfields, int64_t fstride, double* blk, const int* nbr,
-                            int64_t E, hipStream_t s) {
+                            int64_t E, hipStream_t s, float* b32) {
   if (E == 0 || nfields == 0) return;
-  fac_dispatch(nb, dim, nfields, fstride, blk, nbr, nullptr, 0, -E, s);
+  fac_dispatch(nb, dim, nfields, fstride, blk, nbr, nullptr, 0, -E, b32, s);
 }
 
 template <typename T, int NB, int DIM>

@@ -95,6 +95,11 @@ struct Precond {
   int64_t bsz = 0;                  // doubles per block = nb * nb
   DevBuf<double> blk;               // [m][E][nslot][nb][nb]
   DevBuf<float> blk32;              // concentration fields only: [m-1][E][nslot][nb][nb]
+  // host aggregation hierarchy of the last set-up and the vertex level's last
+  // power-iteration vector: later set-ups of the same Newton solve keep its
+  // aggregates and prolongators
+  AmgHierarchy sa_prev;
+  std::vector<double> sa_x0;
   DevBuf<float> phi32;              // potential field: [E][nslot][nb][ld32], ld32 = pot_ld(nb, true)
   DevBuf<double> dinv_phi;          // [E][nb][nb]
   DevBuf<float> dinv_phi32;         // [E][nb][ld32]
@@ -519,21 +524,23 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
   // of it is queued without a host wait, so that with both parts it runs on
   // the device while the host builds the potential hierarchy
   auto conc_part = [&]() {
+    // the single-precision copies are written by the factorisation kernels
+    // themselves, block by block as each is finished
+    float* b32 = nullptr;
+    if (f32) {
+      P.blk32.alloc(size_t((c.m - 1) * per_field));
+      b32 = P.blk32.p;
+    }
     for (size_t l = 0; l + 1 < P.lev_ptr.size(); ++l) {
       ScopeTimer tm(c, "ilu_factor", s);
       launch_ilu_factor(c.nb, c.dim, c.m - 1, per_field, P.blk.p + per_field, c.d_nbr.p, P.lev_elems.p,
-                        P.lev_ptr[l], P.lev_ptr[l + 1] - P.lev_ptr[l], s);
+                        P.lev_ptr[l], P.lev_ptr[l + 1] - P.lev_ptr[l], s, b32);
     }
     {
       ScopeTimer tm(c, "ilu_factor", s);
-      launch_ilu_scale_lower(c.nb, c.dim, c.m - 1, per_field, P.blk.p + per_field, c.d_nbr.p, c.E, s);
+      launch_ilu_scale_lower(c.nb, c.dim, c.m - 1, per_field, P.blk.p + per_field, c.d_nbr.p, c.E, s, b32);
     }
-    clk.mark("ilu factor");
-    if (f32) {
-      P.blk32.alloc(size_t((c.m - 1) * per_field));
-      cvt_d2f(P.blk.p + per_field, P.blk32.p, (c.m - 1) * per_field, s);
-      clk.mark("float copies (conc)");
-    }
+    clk.mark("ilu factor (with single-precision copies)");
   };
   if (phi) {
     // potential block: element-diagonal inverses (block-Jacobi smoother)
@@ -594,8 +601,13 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     if (conc) conc_part();  // device work behind the host set-up below
     Csr A1 = vertex_matrix(c, P, st);
     clk.mark("vertex matrix");
-    AmgHierarchy H = sa_setup(A1, 12, 256, 0.0);
-    clk.mark("sa setup");
+    // within one Newton solve the aggregates and smoothed prolongators of the
+    // first set-up are kept (only R A P is recomputed): the potential block
+    // changes with the concentrations, its vertex graph does not
+    const bool no_reuse = getenv("DGNP_NO_AMG_REUSE") != nullptr;
+    const bool reuse = !no_reuse && (parts & PC_WARM) != 0 && !P.sa_prev.A.empty() && P.sa_prev.A[0].n == A1.n;
+    AmgHierarchy H = reuse ? sa_setup_reuse(A1, P.sa_prev, &P.sa_x0) : sa_setup(A1, 12, 256, 0.0, &P.sa_x0);
+    clk.mark(reuse ? "sa setup (prolongators kept)" : "sa setup");
     if (trace_setup()) {
       fprintf(stderr, "[setup] hierarchy: DG %lld", (long long)c.Nf);
       for (auto& A : H.A) fprintf(stderr, " -> %d (nnz %zu)", A.n, A.v.size());
@@ -643,6 +655,7 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
       ensure_work32(c, P);
       clk.mark("float copies (phi)");
     }
+    P.sa_prev = std::move(H);  // the staged uploads above copied what they need
     // lambda_max of the smoothers' D^{-1} A on the potential levels, in the
     // arithmetic of the smoother
     auto lmax_levels = [&](auto tag) {
