@@ -1,7 +1,8 @@
 // Host check of the smoothed-aggregation set-up (amg.cpp) on the 7-point
 // Laplacian of an n^3 grid: SpGEMM and transpose against dense products,
 // every node aggregated, symmetric Galerkin operators, the coarsest inverse,
-// and bitwise-identical hierarchies across repeated runs.  Prints "ok" and
+// bitwise-identical hierarchies across repeated runs, and the set-up that
+// keeps an earlier hierarchy's prolongators.  Prints "ok" and
 // returns 0, or names the failed check and returns 1.
 #include <cmath>
 #include <cstdint>
@@ -103,6 +104,43 @@ int main() {
   for (size_t l = 0; l < H.A.size(); ++l)
     if (H2.A[l].v != H.A[l].v || H2.A[l].ci != H.A[l].ci || H2.lmax[l] != H.lmax[l])
       return fail("repeat: hierarchy differs");
+  // reuse of the prolongators: for the same matrix the Galerkin levels are
+  // those of the fresh set-up bit for bit; the finest lambda_max estimate
+  // continues the power iteration from its last vector, so it can only grow
+  // towards the true value, which the Gershgorin bound 2 caps (row sums of
+  // |D^{-1} A| are at most 1 + 6/6 here); coarser levels repeat the cold
+  // estimate exactly.  For 2 A every Galerkin level doubles and D^{-1} A, hence
+  // lambda_max, is unchanged.
+  {
+    std::vector<double> x0;
+    dgnp::AmgHierarchy Hc = dgnp::sa_setup(A, 12, 256, 0.0, &x0);
+    if (x0.size() != size_t(A.n)) return fail("reuse: no start vector kept");
+    dgnp::AmgHierarchy Hr = dgnp::sa_setup_reuse(A, Hc, &x0);
+    if (Hr.A.size() != Hc.A.size()) return fail("reuse: level count");
+    for (size_t l = 0; l < Hc.A.size(); ++l) {
+      if (Hr.A[l].v != Hc.A[l].v || Hr.A[l].ci != Hc.A[l].ci) return fail("reuse: Galerkin level differs");
+      if (l > 0 && Hr.lmax[l] != Hc.lmax[l]) return fail("reuse: coarse lambda_max differs");
+    }
+    if (!(Hr.lmax[0] >= Hc.lmax[0] * (1.0 - 1e-12) && Hr.lmax[0] <= 2.0))
+      return fail("reuse: warm lambda_max not between the cold estimate and the Gershgorin bound");
+    if (Hr.coarse_inv != Hc.coarse_inv) return fail("reuse: coarsest inverse differs");
+    Csr A2 = A;
+    for (double& v : A2.v) v *= 2.0;
+    dgnp::AmgHierarchy H2r = dgnp::sa_setup_reuse(A2, Hc, &x0);
+    for (size_t l = 1; l < Hc.A.size(); ++l)
+      for (size_t k = 0; k < Hc.A[l].v.size(); ++k)
+        if (std::fabs(H2r.A[l].v[k] - 2.0 * Hc.A[l].v[k]) > 1e-12 * std::fabs(Hc.A[l].v[k]) + 1e-14)
+          return fail("reuse: rescaled Galerkin level");
+    if (!(H2r.lmax[0] >= Hc.lmax[0] * (1.0 - 1e-12) && H2r.lmax[0] <= 2.0)) return fail("reuse: rescaled lambda_max");
+    Csr B = laplace3d(29);
+    bool threw = false;
+    try {
+      (void)dgnp::sa_setup_reuse(B, Hc, &x0);
+    } catch (const dgnp::Error&) {
+      threw = true;
+    }
+    if (!threw) return fail("reuse: a vertex level of another size must be refused");
+  }
   // checksum of every value of the hierarchy (bit patterns), to compare runs
   uint64_t h = 1469598103934665603ull;
   auto mix = [&](double x) {

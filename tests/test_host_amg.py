@@ -1,8 +1,10 @@
 """Host logic of the potential-block multigrid set-up (smoothed aggregation,
 csrc/amg.cpp), compiled for the CPU with a small driver (tests/host/amg_check.cpp):
 SpGEMM/transpose against dense products, aggregation coverage, symmetric
-Galerkin operators, the coarsest inverse, and repeatability across runs of the
-threaded set-up."""
+Galerkin operators, the coarsest inverse, repeatability across runs of the
+threaded set-up, and the set-up that keeps an earlier hierarchy's prolongators
+(same Galerkin levels bit for bit, a warm eigenvalue estimate between the cold
+one and the Gershgorin bound, exact scaling for 2 A, refusal of another size)."""
 import os
 import subprocess
 
