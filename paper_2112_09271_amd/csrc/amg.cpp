@@ -24,6 +24,10 @@ namespace dgnp {
 // every reduction is formed per chunk and combined in chunk order, so results
 // do not depend on the number of threads.
 static constexpr int CH = 2048;
+// Sparse products compute every row on its own (no cross-row reduction), so
+// they take finer chunks (the result does not depend on the chunking); so do
+// the independent columns / rows of the coarsest inverse.
+static constexpr int CHM = 64, CHD = 8;
 
 // A persistent pool of host workers (created on first use, joined at exit):
 // a job is a chunk count and a function; the workers and the caller take
@@ -114,6 +118,14 @@ static void parallel_chunks(int n, F&& fn) {
   parallel_chunks_t(n, [&](int, int c, int r0, int r1) { fn(c, r0, r1); });
 }
 
+// fn(thread, chunk, first, end) over chunks of `ch` indices (row-independent work only)
+template <typename F>
+static void parallel_rows(int n, int ch, F&& fn) {
+  const int nch = (n + ch - 1) / ch;
+  const std::function<void(int, int)> job = [&](int t, int c) { fn(t, c, c * ch, std::min(n, (c + 1) * ch)); };
+  HostPool::get().run(nch, job);
+}
+
 Csr csr_transpose(const Csr& A) {
   Csr T;
   T.n = A.m;
@@ -139,13 +151,13 @@ Csr csr_matmul(const Csr& A, const Csr& B) {
   C.n = A.n;
   C.m = B.m;
   C.rp.assign(size_t(C.n) + 1, 0);
-  const int nch = (A.n + CH - 1) / CH;
+  const int nch = (A.n + CHM - 1) / CHM;
   std::vector<std::vector<int>> cch(static_cast<size_t>(nch));
   std::vector<std::vector<double>> vch(static_cast<size_t>(nch));
   const int nt = host_threads(nch);
   std::vector<std::vector<double>> accs(static_cast<size_t>(nt));
   std::vector<std::vector<int>> marks(static_cast<size_t>(nt)), colss(static_cast<size_t>(nt));
-  parallel_chunks_t(A.n, [&](int t, int ch, int r0, int r1) {
+  parallel_rows(A.n, CHM, [&](int t, int ch, int r0, int r1) {
     std::vector<double>& acc = accs[size_t(t)];
     std::vector<int>& mark = marks[size_t(t)];
     std::vector<int>& cols = colss[size_t(t)];
@@ -271,21 +283,28 @@ static bool cholesky_inverse(std::vector<double>& a, int n) {
     const double id = 1.0 / d;
     for (int i = j + 1; i < n; ++i) at(i, j) = (at(i, j) - dot4(&a[size_t(i) * n], rj, j)) * id;
   }
-  // m[j * n + i] = M_ij: column j of M contiguous; M_ij = -(sum_{k=j}^{i-1} L_ik M_kj) / L_ii
+  // m[j * n + i] = M_ij: column j of M contiguous; M_ij = -(sum_{k=j}^{i-1} L_ik M_kj) / L_ii.
+  // Each column is its own triangular solve: columns run on the worker pool.
   std::vector<double> m(size_t(n) * n, 0.0);
-  for (int i = 0; i < n; ++i) {
-    const double il = 1.0 / at(i, i);
-    m[size_t(i) * n + i] = il;
-    const double* li = &a[size_t(i) * n];
-    for (int j = 0; j < i; ++j) m[size_t(j) * n + i] = -dot4(li + j, &m[size_t(j) * n + j], i - j) * il;
-  }
-  // (A^{-1})_ij = sum_{k >= max(i, j)} M_ki M_kj
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j <= i; ++j) {
-      const double t = dot4(&m[size_t(i) * n + i], &m[size_t(j) * n + i], n - i);
-      at(i, j) = t;
-      at(j, i) = t;
+  parallel_rows(n, CHD, [&](int, int, int j0, int j1) {
+    for (int j = j0; j < j1; ++j) {
+      double* mj = &m[size_t(j) * n];
+      mj[j] = 1.0 / at(j, j);
+      for (int i = j + 1; i < n; ++i) mj[i] = -dot4(&a[size_t(i) * n] + j, mj + j, i - j) * (1.0 / at(i, i));
     }
+  });
+  // (A^{-1})_ij = sum_{k >= max(i, j)} M_ki M_kj; rows i on the pool, each
+  // entry written by the row that owns its lower-triangle position
+  std::vector<double> inv(size_t(n) * n);
+  parallel_rows(n, CHD, [&](int, int, int i0, int i1) {
+    for (int i = i0; i < i1; ++i)
+      for (int j = 0; j <= i; ++j) {
+        const double t = dot4(&m[size_t(i) * n + i], &m[size_t(j) * n + i], n - i);
+        inv[size_t(i) * n + j] = t;
+        inv[size_t(j) * n + i] = t;
+      }
+  });
+  a.swap(inv);
   return true;
 }
 

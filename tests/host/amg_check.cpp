@@ -154,6 +154,7 @@ int main() {
   }
   for (const Csr& P : H.P)
     for (double x : P.v) mix(x);
+  for (double x : H.coarse_inv) mix(x);
   printf("ok levels %zu sizes", H.A.size());
   for (auto& L : H.A) printf(" %d", L.n);
   printf(" checksum %016llx\n", static_cast<unsigned long long>(h));
