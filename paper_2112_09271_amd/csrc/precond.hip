@@ -599,6 +599,21 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     DGNP_HIP(hipStreamSynchronize(s));
     clk.mark("galerkin + stencil");
     if (conc) conc_part();  // device work behind the host set-up below
+    if (f32) {
+      // single-precision potential blocks: they do not depend on the host
+      // hierarchy, so they too run while the host builds it
+      const int ld32 = pot_ld(c.nb, true);
+      P.phi32.alloc(size_t(c.E) * P.nslot * c.nb * ld32);
+      cvt_d2f_rows(P.blk.p, P.phi32.p, c.E * P.nslot * c.nb, c.nb, ld32, s);
+      P.dinv_phi32.alloc(size_t(c.E) * c.nb * ld32);
+      cvt_d2f_rows(P.dinv_phi.p, P.dinv_phi32.p, c.E * c.nb, c.nb, ld32, s);
+      if (P.pmg) {
+        P.blk1_32.alloc(P.blk1.n);
+        cvt_d2f(P.blk1.p, P.blk1_32.p, int64_t(P.blk1.n), s);
+        P.dinv1_32.alloc(P.dinv1.n);
+        cvt_d2f(P.dinv1.p, P.dinv1_32.p, int64_t(P.dinv1.n), s);
+      }
+    }
     Csr A1 = vertex_matrix(c, P, st);
     clk.mark("vertex matrix");
     // within one Newton solve the aggregates and smoothed prolongators of the
@@ -631,11 +646,6 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     ensure_work(c, P);
     clk.mark("work vectors");
     if (f32) {
-      const int ld32 = pot_ld(c.nb, true);
-      P.phi32.alloc(size_t(c.E) * P.nslot * c.nb * ld32);
-      cvt_d2f_rows(P.blk.p, P.phi32.p, c.E * P.nslot * c.nb, c.nb, ld32, s);
-      P.dinv_phi32.alloc(size_t(c.E) * c.nb * ld32);
-      cvt_d2f_rows(P.dinv_phi.p, P.dinv_phi32.p, c.E * c.nb, c.nb, ld32, s);
       for (size_t l = 0; l < H.A.size(); ++l) {
         MgLevel& L = P.mg[l];
         upload_csr(L.A32, H.A[l], P.stage, s);
@@ -646,12 +656,6 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
         P.stage.upload(L.dinv32, H.dinv[l].data(), H.dinv[l].size(), s);
       }
       P.stage.upload(P.cinv32, H.coarse_inv.data(), H.coarse_inv.size(), s);
-      if (P.pmg) {
-        P.blk1_32.alloc(P.blk1.n);
-        cvt_d2f(P.blk1.p, P.blk1_32.p, int64_t(P.blk1.n), s);
-        P.dinv1_32.alloc(P.dinv1.n);
-        cvt_d2f(P.dinv1.p, P.dinv1_32.p, int64_t(P.dinv1.n), s);
-      }
       ensure_work32(c, P);
       clk.mark("float copies (phi)");
     }
