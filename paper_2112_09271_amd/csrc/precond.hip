@@ -14,6 +14,8 @@
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
+#include <exception>
+#include <thread>
 #include <type_traits>
 
 #include "amg.hpp"
@@ -384,6 +386,25 @@ static void ensure_work(dgnp_ctx& c, Precond& P) {
   if (P.pmg) P.mf64.alloc(size_t(c.Nf));
 }
 
+// work vectors of the element levels only (order p and, with p-multigrid,
+// p = 1): their sizes do not depend on the host hierarchy
+static void ensure_work_elem(dgnp_ctx& c, Precond& P, bool f32) {
+  const size_t ne = P.pmg ? 2 : 1;
+  while (P.wd.size() < 5 * ne) {
+    P.wd.emplace_back(new DevBuf<double>());
+    P.wf.emplace_back(new DevBuf<float>());
+  }
+  for (size_t l = 0; l < ne; ++l)
+    for (int k = 0; k < 5; ++k) {
+      P.wd[l * 5 + k]->alloc(size_t(level_size(c, P, l)));
+      if (f32) P.wf[l * 5 + k]->alloc(size_t(level_size(c, P, l)));
+    }
+  if (P.pmg) {
+    P.mf64.alloc(size_t(c.Nf));
+    if (f32) P.mf32.alloc(size_t(c.Nf));
+  }
+}
+
 static void ensure_work32(dgnp_ctx& c, Precond& P) {
   const size_t nlev = level_count(P);
   for (size_t l = 0; l < nlev; ++l)
@@ -598,7 +619,33 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     DGNP_HIP(hipMemcpyAsync(st.data(), P.vst.p, st.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     DGNP_HIP(hipStreamSynchronize(s));
     clk.mark("galerkin + stencil");
-    if (conc) conc_part();  // device work behind the host set-up below
+    // The vertex matrix and its aggregation hierarchy are built on a helper
+    // host thread; this thread meanwhile queues the concentration
+    // factorisation and the single-precision potential blocks and runs the
+    // element levels' lambda_max estimates on the device.  Within one Newton
+    // solve the aggregates and smoothed prolongators of the first set-up are
+    // kept (only R A P is recomputed): the potential block changes with the
+    // concentrations, its vertex graph does not.
+    const bool no_reuse = getenv("DGNP_NO_AMG_REUSE") != nullptr;
+    const bool reuse =
+        !no_reuse && (parts & PC_WARM) != 0 && !P.sa_prev.A.empty() && P.sa_prev.A[0].n == int(P.nvert);
+    AmgHierarchy H;
+    std::exception_ptr sa_err;
+    std::thread sa_thread([&]() {
+      try {
+        const Csr A1 = vertex_matrix(c, P, st);
+        H = reuse ? sa_setup_reuse(A1, P.sa_prev, &P.sa_x0) : sa_setup(A1, 12, 256, 0.0, &P.sa_x0);
+      } catch (...) {
+        sa_err = std::current_exception();
+      }
+    });
+    struct Joiner {
+      std::thread& t;
+      ~Joiner() {
+        if (t.joinable()) t.join();
+      }
+    } joiner{sa_thread};
+    if (conc) conc_part();  // device work behind the host set-up
     if (f32) {
       // single-precision potential blocks: they do not depend on the host
       // hierarchy, so they too run while the host builds it
@@ -614,15 +661,37 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
         cvt_d2f(P.dinv1.p, P.dinv1_32.p, int64_t(P.dinv1.n), s);
       }
     }
-    Csr A1 = vertex_matrix(c, P, st);
-    clk.mark("vertex matrix");
-    // within one Newton solve the aggregates and smoothed prolongators of the
-    // first set-up are kept (only R A P is recomputed): the potential block
-    // changes with the concentrations, its vertex graph does not
-    const bool no_reuse = getenv("DGNP_NO_AMG_REUSE") != nullptr;
-    const bool reuse = !no_reuse && (parts & PC_WARM) != 0 && !P.sa_prev.A.empty() && P.sa_prev.A[0].n == A1.n;
-    AmgHierarchy H = reuse ? sa_setup_reuse(A1, P.sa_prev, &P.sa_x0) : sa_setup(A1, 12, 256, 0.0, &P.sa_x0);
-    clk.mark(reuse ? "sa setup (prolongators kept)" : "sa setup");
+    // lambda_max of the smoothers' D^{-1} A on the element levels, in the
+    // arithmetic of the smoother
+    ensure_work_elem(c, P, f32);
+    auto lmax_levels = [&](auto tag) {
+      using T = decltype(tag);
+      T* x0 = Sel<T>::w(P, 0);
+      T* y0 = Sel<T>::w(P, 1);
+      DevBuf<T>& keep0 = Sel<T>::lvec(P);
+      if (P.pmg) {
+        const T* dv = Sel<T>::dinv(P);
+        auto op0 = [&](T* x, T* y) {
+          phi_mf_apply<T>(c, x, y, s);
+          launch_bdiag<T>(c.nb, c.E, dv, y, x, s);
+        };
+        P.lmax0 = power_lmax<T>(c, P, s, c.Nf, op0, x0, y0, keep0);
+        DevBuf<T>& keep1 = Sel<T>::lvec1(P);
+        P.lmax1 = power_lmax<T>(c, P, s, c.E * P.nb1, block_op<T>(c, P.nb1, Sel<T>::blk1(P), Sel<T>::dinv1(P), s),
+                                Sel<T>::w(P, 5), Sel<T>::w(P, 6), keep1);
+      } else {
+        P.lmax0 = power_lmax<T>(c, P, s, c.Nf, block_op<T>(c, c.nb, Sel<T>::blk(P), Sel<T>::dinv(P), s), x0, y0,
+                                keep0);
+      }
+    };
+    if (f32)
+      lmax_levels(float(0));
+    else
+      lmax_levels(double(0));
+    clk.mark("lmax level 0");
+    sa_thread.join();
+    if (sa_err) std::rethrow_exception(sa_err);
+    clk.mark(reuse ? "vertex matrix + sa setup (prolongators kept)" : "vertex matrix + sa setup");
     if (trace_setup()) {
       fprintf(stderr, "[setup] hierarchy: DG %lld", (long long)c.Nf);
       for (auto& A : H.A) fprintf(stderr, " -> %d (nnz %zu)", A.n, A.v.size());
@@ -660,33 +729,6 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
       clk.mark("float copies (phi)");
     }
     P.sa_prev = std::move(H);  // the staged uploads above copied what they need
-    // lambda_max of the smoothers' D^{-1} A on the potential levels, in the
-    // arithmetic of the smoother
-    auto lmax_levels = [&](auto tag) {
-      using T = decltype(tag);
-      T* x0 = Sel<T>::w(P, 0);
-      T* y0 = Sel<T>::w(P, 1);
-      DevBuf<T>& keep0 = Sel<T>::lvec(P);
-      if (P.pmg) {
-        const T* dv = Sel<T>::dinv(P);
-        auto op0 = [&](T* x, T* y) {
-          phi_mf_apply<T>(c, x, y, s);
-          launch_bdiag<T>(c.nb, c.E, dv, y, x, s);
-        };
-        P.lmax0 = power_lmax<T>(c, P, s, c.Nf, op0, x0, y0, keep0);
-        DevBuf<T>& keep1 = Sel<T>::lvec1(P);
-        P.lmax1 = power_lmax<T>(c, P, s, c.E * P.nb1, block_op<T>(c, P.nb1, Sel<T>::blk1(P), Sel<T>::dinv1(P), s),
-                                Sel<T>::w(P, 5), Sel<T>::w(P, 6), keep1);
-      } else {
-        P.lmax0 = power_lmax<T>(c, P, s, c.Nf, block_op<T>(c, c.nb, Sel<T>::blk(P), Sel<T>::dinv(P), s), x0, y0,
-                                keep0);
-      }
-    };
-    if (f32)
-      lmax_levels(float(0));
-    else
-      lmax_levels(double(0));
-    clk.mark("lmax level 0");
     P.phi_ok = true;
     P.phi32_ok = f32;
   }
