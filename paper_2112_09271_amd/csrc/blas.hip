@@ -291,7 +291,7 @@ double vnorm2(const float* x, int64_t n, double* scratch_dev, hipStream_t s) {
 // Coefficient block (device, contiguous): [s | sigma] at 0, [c | tau] at MAXV,
 // then w.w, alpha, h_jj, 1/alpha, rho, 1/rho at 2 MAXV + 0..5.
 static constexpr int DC_WW = 2 * MAXV, DC_ALPHA = 2 * MAXV + 1, DC_HJJ = 2 * MAXV + 2, DC_IALPHA = 2 * MAXV + 3,
-                     DC_RHO = 2 * MAXV + 4, DC_IRHO = 2 * MAXV + 5;
+                     DC_RHO = 2 * MAXV + 4, DC_IRHO = 2 * MAXV + 5, DC_FLAG = DCGS_FLAG;
 // block partials: rows 0 .. 2 MAXV of RED_BLOCKS each, then the completion
 // counter of the final reduction (zero between reductions)
 static constexpr int64_t DC_COUNT = int64_t(2 * MAXV + 1) * RED_BLOCKS;
@@ -339,7 +339,7 @@ __global__ void k_dcgs_dots(const double* __restrict__ V, int64_t ldv, int j, co
 // entries the host reads are stored there as well: s_0..s_j, c_0..c_j, w.w and
 // the scalars (h_jj = 0, rho = 1 without w)
 __device__ void dcgs_scalars_block(double* __restrict__ out, int j, int with_w, double* __restrict__ hout,
-                                   double* sh) {
+                                   double* sh, unsigned long long seq) {
   double ss = 0.0, sc = 0.0, cc = 0.0;
   for (int k = threadIdx.x; k < j; k += VB) {
     const double sk = out[k];
@@ -361,31 +361,40 @@ __device__ void dcgs_scalars_block(double* __restrict__ out, int j, int with_w, 
       if (with_w) hout[MAXV + k] = out[MAXV + k];
     }
   }
-  if (threadIdx.x != 0) return;
-  const double a2 = out[j] - ss;
-  const double alpha = a2 > 0.0 ? sqrt(a2) : 0.0;
-  const double ia = alpha > 0.0 ? 1.0 / alpha : 0.0;
-  out[DC_ALPHA] = alpha;
-  out[DC_IALPHA] = ia;
-  double hjj = 0.0, rho = 1.0;
-  if (with_w) {
-    hjj = (out[MAXV + j] - sc) * ia;
-    const double ww = out[DC_WW];
-    const double r2 = ww - cc - hjj * hjj;  // |w - V c - v_j h_jj|^2 by Pythagoras: only a scale
-    rho = r2 > 0.0 ? sqrt(r2) : sqrt(ww);
-    if (!(rho > 0.0)) rho = 1.0;
-    out[DC_HJJ] = hjj;
-    out[DC_RHO] = rho;
-    out[DC_IRHO] = 1.0 / rho;
+  if (threadIdx.x == 0) {
+    const double a2 = out[j] - ss;
+    const double alpha = a2 > 0.0 ? sqrt(a2) : 0.0;
+    const double ia = alpha > 0.0 ? 1.0 / alpha : 0.0;
+    out[DC_ALPHA] = alpha;
+    out[DC_IALPHA] = ia;
+    double hjj = 0.0, rho = 1.0;
+    if (with_w) {
+      hjj = (out[MAXV + j] - sc) * ia;
+      const double ww = out[DC_WW];
+      const double r2 = ww - cc - hjj * hjj;  // |w - V c - v_j h_jj|^2 by Pythagoras: only a scale
+      rho = r2 > 0.0 ? sqrt(r2) : sqrt(ww);
+      if (!(rho > 0.0)) rho = 1.0;
+      out[DC_HJJ] = hjj;
+      out[DC_RHO] = rho;
+      out[DC_IRHO] = 1.0 / rho;
+    }
+    if (hout) {
+      hout[DC_WW] = with_w ? out[DC_WW] : 0.0;
+      hout[DC_ALPHA] = alpha;
+      hout[DC_IALPHA] = ia;
+      hout[DC_HJJ] = hjj;
+      hout[DC_RHO] = rho;
+      hout[DC_IRHO] = 1.0 / rho;
+    }
   }
-  if (hout) {
-    hout[DC_WW] = with_w ? out[DC_WW] : 0.0;
-    hout[DC_ALPHA] = alpha;
-    hout[DC_IALPHA] = ia;
-    hout[DC_HJJ] = hjj;
-    hout[DC_RHO] = rho;
-    hout[DC_IRHO] = 1.0 / rho;
-  }
+  if (!hout) return;
+  // the sequence number goes last: every entry above is visible to the host
+  // before it (system-scope release after the block's stores)
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(hout + DC_FLAG), seq, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // out[row] = sum of the row's block partials for the rows 0..j, MAXV..MAXV+j
@@ -393,7 +402,8 @@ __device__ void dcgs_scalars_block(double* __restrict__ out, int j, int with_w, 
 // that finishes last (device-wide counter, reset by that block for the next
 // reduction) then forms the scalars
 __global__ void k_dcgs_final(const double* __restrict__ partial, int nblk, int j, int with_w,
-                             double* __restrict__ out, double* __restrict__ hout, unsigned* __restrict__ count) {
+                             double* __restrict__ out, double* __restrict__ hout, unsigned* __restrict__ count,
+                             unsigned long long seq) {
   __shared__ double sh[VB];
   __shared__ int s_last;
   const int o = blockIdx.x;
@@ -410,7 +420,7 @@ __global__ void k_dcgs_final(const double* __restrict__ partial, int nblk, int j
   if (!s_last) return;
   __threadfence();  // every other block's sum is visible to this block
   if (threadIdx.x == 0) *count = 0u;
-  dcgs_scalars_block(out, j, with_w, hout, sh);
+  dcgs_scalars_block(out, j, with_w, hout, sh, seq);
 }
 
 // v_j = (u - V s) / alpha into V column j; u <- (w - V c - v_j h_jj) / rho and
@@ -448,7 +458,7 @@ __global__ void k_dcgs_update(double* __restrict__ V, int64_t ldv, int j, const 
 }
 
 void dcgs_reduce(const double* V, int64_t ldv, int j, const double* u, const void* w, bool w_f32, double* w64,
-                 int64_t n, double* partial, double* coef, hipStream_t s, double* hout) {
+                 int64_t n, double* partial, double* coef, hipStream_t s, double* hout, unsigned long long seq) {
   const unsigned g = red_grid(n);
   const dim3 grid(g, unsigned(j + 1));
   if (!w)
@@ -462,7 +472,7 @@ void dcgs_reduce(const double* V, int64_t ldv, int j, const double* u, const voi
                        static_cast<double*>(nullptr), n, partial);
   const unsigned nout = w ? unsigned(2 * j + 3) : unsigned(j + 1);
   hipLaunchKernelGGL(k_dcgs_final, dim3(nout), dim3(VB), 0, s, partial, int(g), j, w ? 1 : 0, coef, hout,
-                     reinterpret_cast<unsigned*>(partial + DC_COUNT));
+                     reinterpret_cast<unsigned*>(partial + DC_COUNT), seq);
 }
 
 template <typename TM>

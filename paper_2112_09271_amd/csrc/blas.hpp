@@ -39,14 +39,17 @@ double vnorm2(const float* x, int64_t n, double* scratch_dev, hipStream_t s);   
 // pass.  partial holds dcgs_partial_size() doubles, zero-filled once before the
 // first use (the tail holds a counter that each reduction leaves at zero).  hout (not null: host memory
 // mapped for the device, DCGS_COEF doubles) receives the entries of the block
-// that the host reads, written by the reduction's last kernel.
+// that the host reads, written by the reduction's last kernel, and then, as a
+// 64-bit integer at DCGS_FLAG after a system-scope release, the number seq.
 void dcgs_reduce(const double* V, int64_t ldv, int j, const double* u, const void* w, bool w_f32, double* w64,
-                 int64_t n, double* partial, double* coef, hipStream_t s, double* hout = nullptr);
+                 int64_t n, double* partial, double* coef, hipStream_t s, double* hout = nullptr,
+                 unsigned long long seq = 0);
 template <typename TM>
 void dcgs_update(double* V, int64_t ldv, int j, const double* coef, double* u, const double* w, TM* m,
                  const TM* zs, TM* zd, int64_t n, hipStream_t s);
 int64_t dcgs_partial_size();
-constexpr int DCGS_ALPHA = 2 * MAXV + 1, DCGS_HJJ = 2 * MAXV + 2, DCGS_RHO = 2 * MAXV + 4, DCGS_COEF = 2 * MAXV + 8;
+constexpr int DCGS_ALPHA = 2 * MAXV + 1, DCGS_HJJ = 2 * MAXV + 2, DCGS_RHO = 2 * MAXV + 4, DCGS_FLAG = 2 * MAXV + 7,
+              DCGS_COEF = 2 * MAXV + 8;
 // *out = x . x (accumulated in double) without a host wait; scratch holds the block partials
 void vsq_into(const float* x, int64_t n, double* out, double* scratch, hipStream_t s);
 // x /= sqrt(*ss_dev), read on the device (no change when *ss_dev <= 0)

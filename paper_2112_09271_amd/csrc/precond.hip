@@ -620,31 +620,15 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     DGNP_HIP(hipStreamSynchronize(s));
     clk.mark("galerkin + stencil");
     // The vertex matrix and its aggregation hierarchy are built on a helper
-    // host thread; this thread meanwhile queues the concentration
-    // factorisation and the single-precision potential blocks and runs the
-    // element levels' lambda_max estimates on the device.  Within one Newton
-    // solve the aggregates and smoothed prolongators of the first set-up are
-    // kept (only R A P is recomputed): the potential block changes with the
-    // concentrations, its vertex graph does not.
+    // host thread, after this thread has queued the concentration
+    // factorisation and the single-precision potential blocks; this thread
+    // then runs the element levels' lambda_max estimates on the device.
+    // Within one Newton solve the aggregates and smoothed prolongators of the
+    // first set-up are kept (only R A P is recomputed): the potential block
+    // changes with the concentrations, its vertex graph does not.
     const bool no_reuse = getenv("DGNP_NO_AMG_REUSE") != nullptr;
     const bool reuse =
         !no_reuse && (parts & PC_WARM) != 0 && !P.sa_prev.A.empty() && P.sa_prev.A[0].n == int(P.nvert);
-    AmgHierarchy H;
-    std::exception_ptr sa_err;
-    std::thread sa_thread([&]() {
-      try {
-        const Csr A1 = vertex_matrix(c, P, st);
-        H = reuse ? sa_setup_reuse(A1, P.sa_prev, &P.sa_x0) : sa_setup(A1, 12, 256, 0.0, &P.sa_x0);
-      } catch (...) {
-        sa_err = std::current_exception();
-      }
-    });
-    struct Joiner {
-      std::thread& t;
-      ~Joiner() {
-        if (t.joinable()) t.join();
-      }
-    } joiner{sa_thread};
     if (conc) conc_part();  // device work behind the host set-up
     if (f32) {
       // single-precision potential blocks: they do not depend on the host
@@ -661,6 +645,24 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
         cvt_d2f(P.dinv1.p, P.dinv1_32.p, int64_t(P.dinv1.n), s);
       }
     }
+    // the host hierarchy starts once the device work above is queued (its
+    // worker pool would otherwise compete with the launches)
+    AmgHierarchy H;
+    std::exception_ptr sa_err;
+    std::thread sa_thread([&]() {
+      try {
+        const Csr A1 = vertex_matrix(c, P, st);
+        H = reuse ? sa_setup_reuse(A1, P.sa_prev, &P.sa_x0) : sa_setup(A1, 12, 256, 0.0, &P.sa_x0);
+      } catch (...) {
+        sa_err = std::current_exception();
+      }
+    });
+    struct Joiner {
+      std::thread& t;
+      ~Joiner() {
+        if (t.joinable()) t.join();
+      }
+    } joiner{sa_thread};
     // lambda_max of the smoothers' D^{-1} A on the element levels, in the
     // arithmetic of the smoother
     ensure_work_elem(c, P, f32);

@@ -81,18 +81,18 @@ struct Krylov {
   uint64_t gepoch[2][2] = {{0, 0}, {0, 0}};
   int gpc[2][2] = {{-1, -1}, {-1, -1}};
   // pinned host slots for the coefficient blocks of two consecutive Arnoldi
-  // steps and the events that mark their arrival
+  // steps
   static constexpr size_t HSLOT = DCGS_COEF;
   double* hpin = nullptr;      // host view
   double* hpin_dev = nullptr;  // the same memory as the device addresses it
-  hipEvent_t hev[2] = {nullptr, nullptr};
+  // sequence numbers: the coefficient kernel of a step stores its number into
+  // the slot last, which tells the host that the slot is complete
+  unsigned long long seq = 0, slot_seq[2] = {0, 0};
   ~Krylov() {
     for (auto& row : gexec)
       for (auto& g : row)
         if (g) (void)hipGraphExecDestroy(g);
     if (hpin) (void)hipHostFree(hpin);
-    for (auto& e : hev)
-      if (e) (void)hipEventDestroy(e);
   }
 };
 
@@ -173,7 +173,6 @@ static Krylov& krylov(dgnp_ctx& c, int restart, bool f32) {
                            hipHostMallocMapped | hipHostMallocCoherent));
     for (size_t i = 0; i < 2 * Krylov::HSLOT; ++i) K->hpin[i] = 0.0;
     DGNP_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&K->hpin_dev), K->hpin, 0));
-    for (auto& e : K->hev) DGNP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
   if (f32 && !K->Z32.p) {
     K->Z32.alloc(size_t(restart) * c.N);
@@ -246,34 +245,45 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
     double* coef = K.hd.p + dcgs_partial_size();
     // the coefficient kernel of step q stores the entries the host reads into
     // pinned slot q % 2 (free again: the host has read step q - 2 before step
-    // q is queued); the event marks the end of the step
+    // q is queued) and then the step's sequence number; no event is recorded
+    // between steps, so the device runs them back to back
     auto slot = [&](int q) { return K.hpin_dev + size_t(q % 2) * Krylov::HSLOT; };
-    auto to_host = [&](int q) { DGNP_HIP(hipEventRecord(K.hev[q % 2], s)); };
+    auto next_seq = [&](int q) { return K.slot_seq[q % 2] = ++K.seq; };
     auto issue_step = [&](int q) {
       pc_then_jac(c, K, f32, transpose, pc_kind, s);
       {
         // the update pass also stores z_q into Z (preconditioner output column)
         ScopeTimer tm(c, "cgs2", s);
         if (f32) {
-          dcgs_reduce(K.V.p, N, q, K.r.p, K.w32.p, true, K.w.p, N, part, coef, s, slot(q));
+          dcgs_reduce(K.V.p, N, q, K.r.p, K.w32.p, true, K.w.p, N, part, coef, s, slot(q), next_seq(q));
           dcgs_update<float>(K.V.p, N, q, coef, K.r.p, K.w.p, K.v32.p, K.zt32.p, K.Z32.p + int64_t(q) * N, N, s);
         } else {
-          dcgs_reduce(K.V.p, N, q, K.r.p, K.w.p, false, nullptr, N, part, coef, s, slot(q));
+          dcgs_reduce(K.V.p, N, q, K.r.p, K.w.p, false, nullptr, N, part, coef, s, slot(q), next_seq(q));
           dcgs_update<double>(K.V.p, N, q, coef, K.r.p, K.w.p, K.vt.p, K.zt.p, K.Z.p + int64_t(q) * N, N, s);
         }
       }
-      to_host(q);
     };
     auto issue_final = [&](int q) {  // reorthogonalisation of u_q only: completes column q - 1
       {
         ScopeTimer tm(c, "cgs2", s);
-        dcgs_reduce(K.V.p, N, q, K.r.p, nullptr, false, nullptr, N, part, coef, s, slot(q));
+        dcgs_reduce(K.V.p, N, q, K.r.p, nullptr, false, nullptr, N, part, coef, s, slot(q), next_seq(q));
       }
-      to_host(q);
     };
     auto read = [&](int q) -> const double* {
-      DGNP_HIP(hipEventSynchronize(K.hev[q % 2]));
       const double* hb = K.hpin + size_t(q % 2) * Krylov::HSLOT;
+      const unsigned long long want = K.slot_seq[q % 2];
+      const unsigned long long* flag = reinterpret_cast<const unsigned long long*>(hb + DCGS_FLAG);
+      // wait for the slot's sequence number; the stream is queried now and
+      // then, so that a failed stream raises its error and a finished stream
+      // without the number (not expected) does not leave the host waiting
+      for (unsigned n = 1; __atomic_load_n(flag, __ATOMIC_ACQUIRE) != want; ++n) {
+        if ((n & 1023u) != 0) continue;
+        const hipError_t e = hipStreamQuery(s);
+        if (e == hipErrorNotReady) continue;
+        DGNP_HIP(e);
+        if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) != want)
+          throw Error(DGNP_E_BREAKDOWN, "Arnoldi coefficients did not arrive");
+      }
       if (!std::isfinite(hb[DCGS_ALPHA]) || !std::isfinite(hb[DCGS_HJJ]) || !std::isfinite(hb[DCGS_RHO])) {
         DGNP_HIP(hipStreamSynchronize(s));
         throw Error(DGNP_E_NONFINITE, "non-finite Arnoldi vector");
