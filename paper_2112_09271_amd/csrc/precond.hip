@@ -528,9 +528,13 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     P.lvec1_64.release();
   }
   P.blk.alloc(size_t(c.m * per_field));
+  // with both parts the potential field is assembled first: its Galerkin
+  // stencil then reaches the host sooner, and the concentration fields are
+  // assembled (ahead of their factorisation) while the host builds the hierarchy
+  const bool split = phi && conc && !assemble_only;
   {
     ScopeTimer tm(c, "assemble", s);
-    const int f0 = phi ? 0 : 1, f1 = conc ? c.m : 1;
+    const int f0 = phi ? 0 : 1, f1 = (conc && !split) ? c.m : 1;
     launch_assemble(c.dim, c.p, c.m, f0, f1 - f0, c.kargs(), c.d_x.p, P.blk.p, s);
   }
   clk.mark("assemble");
@@ -545,6 +549,10 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
   // of it is queued without a host wait, so that with both parts it runs on
   // the device while the host builds the potential hierarchy
   auto conc_part = [&]() {
+    if (split) {
+      ScopeTimer tm(c, "assemble", s);
+      launch_assemble(c.dim, c.p, c.m, 1, c.m - 1, c.kargs(), c.d_x.p, P.blk.p, s);
+    }
     // the single-precision copies are written by the factorisation kernels
     // themselves, block by block as each is finished
     float* b32 = nullptr;
