@@ -35,25 +35,28 @@ struct Error : std::runtime_error {
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
-  size_t n = 0;
+  size_t n = 0;    // elements in use
+  size_t cap = 0;  // elements allocated
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) {
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), cap(o.cap) {
     o.p = nullptr;
-    o.n = 0;
+    o.n = o.cap = 0;
   }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
       release();
       p = o.p;
       n = o.n;
+      cap = o.cap;
       o.p = nullptr;
-      o.n = 0;
+      o.n = o.cap = 0;
     }
     return *this;
   }
   ~DevBuf() { release(); }
+  // exactly count elements (a new allocation unless the size is unchanged)
   void alloc(size_t count) {
     if (count == n && p) return;
     release();
@@ -62,12 +65,21 @@ struct DevBuf {
       p = nullptr;
       throw Error(DGNP_E_ALLOC, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
     }
-    n = count;
+    n = cap = count;
+  }
+  // count elements, keeping the allocation when it is large enough (arrays
+  // whose length moves a little between set-ups are not reallocated)
+  void fit(size_t count) {
+    if (p && count <= cap) {
+      n = count;
+      return;
+    }
+    alloc(count);
   }
   void release() {
     if (p) (void)hipFree(p);
     p = nullptr;
-    n = 0;
+    n = cap = 0;
   }
   // synchronous: the host source may be a temporary
   void upload(const T* host, size_t count, hipStream_t s) {

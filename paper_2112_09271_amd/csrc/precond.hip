@@ -84,7 +84,7 @@ struct PinnedStage {
   // dst = (T) src[0..n), asynchronously on s
   template <typename T, typename S>
   void upload(DevBuf<T>& dst, const S* src, size_t n, hipStream_t s) {
-    dst.alloc(n);
+    dst.fit(n);
     if (n == 0) return;
     T* h = static_cast<T*>(take(n * sizeof(T)));
     for (size_t i = 0; i < n; ++i) h[i] = T(src[i]);
