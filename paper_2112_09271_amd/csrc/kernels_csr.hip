@@ -19,19 +19,40 @@ __global__ void k_csr_spmv(int n, const int* __restrict__ rp, const int* __restr
   if (row < n && lane == 0) y[row] = alpha * acc + (b ? beta * b[row] : T(0));
 }
 
+// one 64-lane wave per row, for matrices with long rows (the aggregation
+// restriction R = P^T: tens of entries per row)
+template <typename T>
+__global__ void k_csr_spmv_wide(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                const T* __restrict__ v, const T* __restrict__ x, const T* __restrict__ b, T alpha,
+                                T beta, T* __restrict__ y) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  T acc = T(0);
+  if (row < n)
+    for (int k = rp[row] + lane; k < rp[row + 1]; k += 64) acc += v[k] * x[ci[k]];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (row < n && lane == 0) y[row] = alpha * acc + (b ? beta * b[row] : T(0));
+}
+
 template <typename T>
 void launch_csr_spmv(int n, const int* rp, const int* ci, const T* v, const T* x, const T* b, T alpha, T beta,
-                     T* y, hipStream_t s) {
+                     T* y, hipStream_t s, int64_t nnz) {
   if (n <= 0) return;
-  const int64_t thr = int64_t(n) * 8;
-  hipLaunchKernelGGL(k_csr_spmv<T>, dim3(unsigned((thr + 255) / 256)), dim3(256), 0, s, n, rp, ci, v, x, b,
-                     alpha, beta, y);
+  if (nnz >= int64_t(n) * 32) {
+    hipLaunchKernelGGL(k_csr_spmv_wide<T>, dim3(unsigned((n + 3) / 4)), dim3(256), 0, s, n, rp, ci, v, x, b, alpha,
+                       beta, y);
+  } else {
+    const int64_t thr = int64_t(n) * 8;
+    hipLaunchKernelGGL(k_csr_spmv<T>, dim3(unsigned((thr + 255) / 256)), dim3(256), 0, s, n, rp, ci, v, x, b,
+                       alpha, beta, y);
+  }
   DGNP_HIP(hipGetLastError());
 }
 template void launch_csr_spmv<double>(int, const int*, const int*, const double*, const double*, const double*,
-                                      double, double, double*, hipStream_t);
+                                      double, double, double*, hipStream_t, int64_t);
 template void launch_csr_spmv<float>(int, const int*, const int*, const float*, const float*, const float*,
-                                     float, float, float*, hipStream_t);
+                                     float, float, float*, hipStream_t, int64_t);
 
 template <typename T>
 __global__ void k_vmul(int64_t n, const T* __restrict__ d, const T* __restrict__ x, T* __restrict__ y) {

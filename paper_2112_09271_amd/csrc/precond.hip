@@ -814,7 +814,7 @@ struct Mg {
       DevCsr<T>& M = Sel<T>::A(csr(l));
       launch_csr_spmv<T>(M.n, M.rp.p, M.ci.p, M.v.p, x, b, T(-1), T(1), r, s);
       DevCsr<T>& R = Sel<T>::R(csr(l));
-      launch_csr_spmv<T>(R.n, R.rp.p, R.ci.p, R.v.p, r, nullptr, T(1), T(0), rc, s);
+      launch_csr_spmv<T>(R.n, R.rp.p, R.ci.p, R.v.p, r, nullptr, T(1), T(0), rc, s, int64_t(R.v.n));
     }
   }
   void prolong_add(int l, const T* xc, T* x) {
