@@ -264,6 +264,26 @@ def channel_solves(names):
     return out
 
 
+def copy_bandwidth(mib=512, reps=20):
+    """GB/s (read + write bytes) of a device-to-device copy of `mib` MiB, timed
+    with events over `reps` copies after one untimed copy."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    return 2.0 * n * 4 / sec / 1e9
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -331,10 +351,13 @@ def main():
     keys = {"cheb_blk_f32": "k_cheb_blk_f32_cfg2", "ilu_fwd_f32": "k_ilu_dfp_fwd_cfg2",
             "ilu_bwd_f32": "k_ilu_dfp_bwd_cfg2", "jac_apply_f32": "k_dg_jac_f32_cfg2"}
     srcs = ("kernels_dg.hip", "dg_device.hpp", "pointwise.hpp") if dom == "jac_apply_f32" else ("kernels_block.hip",)
+    copy_gbs = copy_bandwidth()
     roofline = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "avg_launch_us": 1e6 * avg, "launches": launches,
                 "bytes_per_launch": per_launch_bytes,
-                "traffic": measured_traffic(keys[dom], source_hash(*srcs))}
+                "traffic": measured_traffic(keys[dom], source_hash(*srcs)),
+                # context, not the peak: what a plain device-to-device copy sustains here
+                "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs if copy_gbs else None}
     log(f"[bench] dominant kernel {dom}: {tot:.3f}s in {launches} launches, {1e6 * avg:.2f} us/launch, "
         f"{achieved:.0f} GB/s")
     others = {}
