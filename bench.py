@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP32_TFLOPS = 157.3       # vector FP32 (published; counts packed FP32 FMAs)
-PEAK_FP32_UNPACKED_TFLOPS = 78.6  # 256 CUs x 64 lanes x 2 flops x 2.4 GHz, packed FP32 disabled in this build
+PEAK_FP32_UNPACKED_TFLOPS = 78.6  # 256 CUs x 64 lanes x 2 flops x 2.4 GHz (packed FP32 disabled at compile time)
 PEAK_FP64_TFLOPS = 78.6        # vector FP64
 METRIC = "Newton-GMRES time-to-1e-8 (FP64 vs mixed); Jacobian-apply HBM GB/s"
 
@@ -287,7 +287,7 @@ def copy_bandwidth(mib=512, reps=20):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): this build has no "
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library has no "
               "multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
