@@ -21,16 +21,27 @@ pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="n
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def _errors(p, n):
-    from paper_2112_09271_amd.dgnp import DGNP_F64
+def _errors(p, n, mixed_too=False):
+    from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64
     cfg, _, gp = pair("e1", with_oracle=False, n=(n, n, n), p=p)
     x, st = gp.solve(rtol=1e-12, prec=DGNP_F64)
     assert st.status == 0
     xs = host(x)
+    xm = None
+    if mixed_too:
+        x32, st32 = gp.solve(rtol=1e-12, prec=DGNP_F32)
+        assert st32.status == 0
+        xm = host(x32)
     gp.close()
-    e = osolve.l2_errors(DG(OProblem(cfg)), xs)
+    od = DG(OProblem(cfg))
+    e = osolve.l2_errors(od, xs)
     print(f"e1 p={p} n={n}: newton {st.newton_its}, fgmres {st.lin_its_total}, "
           f"errors phi {e[0]:.4e} c1 {e[1]:.4e} total {e[0] + e[1]:.4e}", flush=True)
+    if xm is not None:
+        # mixed precision (single-precision preconditioner and Jacobian apply under
+        # double-precision residuals) reaches the same discretisation error
+        em = osolve.l2_errors(od, xm)
+        assert abs((em[0] + em[1]) - (e[0] + e[1])) <= 1e-3 * (e[0] + e[1]), (em, e)
     return e[0] + e[1]
 
 
@@ -40,7 +51,7 @@ def test_published_errors_and_rates(p, sizes):
         paper = {(r[1], r[2]): r[3] for r in json.load(f)["rows"]}
     with open(os.path.join(GOLD, "e1_errors.json")) as f:
         oracle = {(r["p"], r["n"]): r["total"] for r in json.load(f)["results"]}
-    errs = [_errors(p, n) for n in sizes]
+    errs = [_errors(p, n, mixed_too=(n == sizes[-1])) for n in sizes]
     for n, e in zip(sizes, errs):
         # the same band as the oracle's own check of the published errors: the
         # discretisations differ in unstated details (penalty h, quadrature,
