@@ -617,9 +617,9 @@ __global__ void __launch_bounds__(BT) k_block_inverse(const double* __restrict__
 // place: slot 0 <- D_i^{-1}; slot 1+s <- D_i^{-1} A_{i,nbr(s)} for every
 // neighbour (lower ones = Lhat, upper ones = Uhat), so that
 //   M = D (I + Lhat)(I + Uhat).
-// The level kernel forms D_i, inverts it and scales the upper blocks (the
-// next levels read them); k_ilu_scale_lower scales the lower blocks of every
-// element afterwards in one fully parallel launch.
+// The level kernel forms D_i, inverts it and scales all six off-diagonal
+// blocks of element i: the upper ones are read by the next levels, the lower
+// ones only by element i's own Schur product, which has already run.
 //
 // Products of two NB x NB blocks run on a 16 x 16 thread grid: thread (ty, tx)
 // owns rows ty + 16 i and columns tx + 16 j, and the operands stream through
@@ -970,7 +970,9 @@ __global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, int
       bi[idx] = dv;
       if (fi) fi[idx] = float(dv);
     }
-    for (int s = 1; s < 2 * DIM; s += 2) {
+    // every off-diagonal block: the upper ones (read by later levels) and the
+    // lower ones (read only by this element's Schur product above)
+    for (int s = 0; s < 2 * DIM; ++s) {
       float* f32s = fi ? fi + int64_t(1 + s) * NB * NB : nullptr;
       if (nbr[i * 2 * DIM + s] < 0) {
         zero_block32<NB>(f32s, tid);
@@ -980,15 +982,16 @@ __global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, int
     }
   } else if constexpr (Mf32<NB>::on) {
     constexpr int KS = Mf32<NB>::KS;
-    // every operand of the three Schur products and of the three upper-block
-    // scalings is requested up front; the scalings' blocks wait in registers
-    // through the inversion
-    double la[DIM][KS], rb[DIM][KS], ub[DIM][KS];
+    // every operand of the three Schur products and of the six block scalings
+    // (upper and lower) is requested up front; the scalings' blocks wait in
+    // registers through the inversion
+    double la[DIM][KS], rb[DIM][KS], ub[DIM][KS], lb[DIM][KS];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       const int j = nbr[i * 2 * DIM + 2 * d];
       mf32_load_a<NB>(la[d], j >= 0 ? bi + int64_t(1 + 2 * d) * NB * NB : nullptr, tid);
       mf32_load_b<NB>(rb[d], j >= 0 ? blk + (int64_t(j) * NSLOT + 2 + 2 * d) * NB * NB : nullptr, tid);
+      mf32_load_b<NB>(lb[d], j >= 0 ? bi + int64_t(1 + 2 * d) * NB * NB : nullptr, tid);
       const bool up = nbr[i * 2 * DIM + 2 * d + 1] >= 0;
       mf32_load_b<NB>(ub[d], up ? bi + int64_t(2 + 2 * d) * NB * NB : nullptr, tid);
     }
@@ -1010,28 +1013,30 @@ __global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, int
     }
     double da[KS];
     mf32_load_dinv<NB, LD>(da, a, rsrc, csrc, tid);
-    v4d ua[DIM];
+    v4d ua[2 * DIM];  // slot 1 + s: s even lower, s odd upper
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-      ua[d] = v4d{0.0, 0.0, 0.0, 0.0};
-      mf32_mma<NB>(ua[d], da, ub[d]);
+      ua[2 * d] = v4d{0.0, 0.0, 0.0, 0.0};
+      ua[2 * d + 1] = v4d{0.0, 0.0, 0.0, 0.0};
+      mf32_mma<NB>(ua[2 * d], da, lb[d]);
+      mf32_mma<NB>(ua[2 * d + 1], da, ub[d]);
     }
-    __syncthreads();  // all reads of the upper blocks are done before any is overwritten
+    __syncthreads();  // all reads of the blocks are done before any is overwritten
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      float* B32 = fi ? fi + int64_t(2 + 2 * d) * NB * NB : nullptr;
-      if (nbr[i * 2 * DIM + 2 * d + 1] < 0) {
+    for (int s = 0; s < 2 * DIM; ++s) {
+      float* B32 = fi ? fi + int64_t(1 + s) * NB * NB : nullptr;
+      if (nbr[i * 2 * DIM + s] < 0) {
         zero_block32<NB>(B32, tid);
         continue;
       }
-      double* B = bi + int64_t(2 + 2 * d) * NB * NB;
+      double* B = bi + int64_t(1 + s) * NB * NB;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         int rr, cc;
         mf32_out<NB>(tid, q, rr, cc);
         if (rr < NB && cc < NB) {
-          B[rr * NB + cc] = ua[d][q];
-          if (B32) B32[rr * NB + cc] = float(ua[d][q]);
+          B[rr * NB + cc] = ua[s][q];
+          if (B32) B32[rr * NB + cc] = float(ua[s][q]);
         }
       }
     }
@@ -1068,79 +1073,14 @@ __global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, int
       bi[idx] = dv;
       if (fi) fi[idx] = float(dv);
     }
-    // upper neighbours (slots 1, 3, 5 = +x, +y, +z)
-    for (int s = 1; s < 2 * DIM; s += 2) {
+    // every off-diagonal block (slots 1 + s: s even lower, s odd upper)
+    for (int s = 0; s < 2 * DIM; ++s) {
       float* f32s = fi ? fi + int64_t(1 + s) * NB * NB : nullptr;
       if (nbr[i * 2 * DIM + s] < 0) {
         zero_block32<NB>(f32s, tid);
         continue;
       }
       scale_block<NB, LD>(bi + int64_t(1 + s) * NB * NB, a, rsrc, csrc, pb, tid, f32s);
-    }
-  }
-}
-
-// lower blocks of every element: slot 1+s <- D_i^{-1} A_{i,nbr(s)}, s = 0, 2, 4
-template <int NB, int DIM>
-__global__ void __launch_bounds__(BT) k_ilu_scale_lower(double* __restrict__ blk, int64_t fstride,
-                                                        const int* __restrict__ nbr, float* __restrict__ b32) {
-  using G = BlkGemm<NB>;
-  constexpr int LD = NB + 1;
-  constexpr int NSLOT = 2 * DIM + 1;
-  __shared__ double a[NB * LD];
-  __shared__ double pb[(NB == 64 || Mf32<NB>::on) ? 1 : G::KP * NB];  // panel of the vector-unit products only
-  __shared__ int ident[NB];
-  const int tid = threadIdx.x;
-  blk += blockIdx.y * fstride;
-  const int64_t i = blockIdx.x;
-  double* bi = blk + i * NSLOT * NB * NB;
-  float* fi = b32 ? b32 + blockIdx.y * fstride + i * NSLOT * NB * NB : nullptr;
-  for (int idx = tid; idx < NB * NB; idx += BT) a[(idx / NB) * LD + idx % NB] = bi[idx];
-  if (tid < NB) ident[tid] = tid;
-  __syncthreads();
-  if constexpr (Mf32<NB>::on) {
-    constexpr int KS = Mf32<NB>::KS;
-    double lb[DIM][KS], da[KS];
-#pragma unroll
-    for (int d = 0; d < DIM; ++d)
-      mf32_load_b<NB>(lb[d], nbr[i * 2 * DIM + 2 * d] >= 0 ? bi + int64_t(1 + 2 * d) * NB * NB : nullptr, tid);
-    mf32_load_dinv<NB, LD>(da, a, ident, ident, tid);
-    v4d acc[DIM];
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      acc[d] = v4d{0.0, 0.0, 0.0, 0.0};
-      mf32_mma<NB>(acc[d], da, lb[d]);
-    }
-    __syncthreads();  // all reads of the lower blocks are done before any is overwritten
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      float* B32 = fi ? fi + int64_t(1 + 2 * d) * NB * NB : nullptr;
-      if (nbr[i * 2 * DIM + 2 * d] < 0) {
-        zero_block32<NB>(B32, tid);
-        continue;
-      }
-      double* B = bi + int64_t(1 + 2 * d) * NB * NB;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        int rr, cc;
-        mf32_out<NB>(tid, q, rr, cc);
-        if (rr < NB && cc < NB) {
-          B[rr * NB + cc] = acc[d][q];
-          if (B32) B32[rr * NB + cc] = float(acc[d][q]);
-        }
-      }
-    }
-  } else {
-    for (int s = 0; s < 2 * DIM; s += 2) {
-      float* f32s = fi ? fi + int64_t(1 + s) * NB * NB : nullptr;
-      if (nbr[i * 2 * DIM + s] < 0) {
-        zero_block32<NB>(f32s, tid);
-        continue;
-      }
-      if constexpr (NB == 64)
-        scale_mfma64<LD>(bi + int64_t(1 + s) * NB * NB, a, ident, ident, tid, f32s);
-      else
-        scale_block<NB, LD>(bi + int64_t(1 + s) * NB * NB, a, ident, ident, pb, tid, f32s);
     }
   }
 }
@@ -1999,12 +1939,8 @@ void launch_block_inverse(int nb, int64_t E, const double* blk, int nslot, doubl
 template <int NB, int DIM>
 static void fac_t(int nfields, int64_t fstride, double* blk, const int* nbr, const int* lev, int64_t first,
                   int64_t count, float* b32, hipStream_t s) {
-  if (count > 0)
-    hipLaunchKernelGGL((k_ilu_factor<NB, DIM>), dim3(unsigned(count), unsigned(nfields)), dim3(BT), 0, s, blk,
-                       fstride, nbr, lev, first, b32);
-  else
-    hipLaunchKernelGGL((k_ilu_scale_lower<NB, DIM>), dim3(unsigned(-count), unsigned(nfields)), dim3(BT), 0, s,
-                       blk, fstride, nbr, b32);
+  hipLaunchKernelGGL((k_ilu_factor<NB, DIM>), dim3(unsigned(count), unsigned(nfields)), dim3(BT), 0, s, blk,
+                     fstride, nbr, lev, first, b32);
 }
 
 static void fac_dispatch(int nb, int dim, int nfields, int64_t fstride, double* blk, const int* nbr,
@@ -2033,11 +1969,6 @@ void launch_ilu_factor(int nb, int dim, int nfields, int64_t fstride, double* bl
   fac_dispatch(nb, dim, nfields, fstride, blk, nbr, lev, first, count, b32, s);
 }
 
-void launch_ilu_scale_lower(int nb, int dim, int nfields, int64_t fstride, double* blk, const int* nbr,
-                            int64_t E, hipStream_t s, float* b32) {
-  if (E == 0 || nfields == 0) return;
-  fac_dispatch(nb, dim, nfields, fstride, blk, nbr, nullptr, 0, -E, b32, s);
-}
 
 template <typename T, int NB, int DIM>
 static void solve_t(int kind, const T* blk, const int* nbr, const int* lev, int64_t first, int64_t count,

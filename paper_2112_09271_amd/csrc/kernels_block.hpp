@@ -10,14 +10,12 @@ void upload_gll_nodes(const RefTables* tabs, int count);
 void launch_assemble(int dim, int p, int m, int f0, int nf, const KArgs& A, const double* xs, double* blk,
                      hipStream_t s);
 void launch_block_inverse(int nb, int64_t E, const double* blk, int nslot, double* out, hipStream_t s);
-// BILU(0) of nfields field blocks (block stride fstride): one hyperplane level
-// (D_i^{-1} and the upper blocks), then, after the last level, the lower blocks.
-// b32 (not null): each finished block also stored in single precision there,
-// same layout; between them the two kernels write every slot of every element.
+// BILU(0) of nfields field blocks (block stride fstride), one hyperplane level
+// per launch: D_i^{-1} and every scaled off-diagonal block of the level's
+// elements.  b32 (not null): each finished block also stored in single
+// precision there, same layout; over all levels every slot of every element.
 void launch_ilu_factor(int nb, int dim, int nfields, int64_t fstride, double* blk, const int* nbr,
                        const int* lev, int64_t first, int64_t count, hipStream_t s, float* b32 = nullptr);
-void launch_ilu_scale_lower(int nb, int dim, int nfields, int64_t fstride, double* blk, const int* nbr,
-                            int64_t E, hipStream_t s, float* b32 = nullptr);
 // kind 0: forward, 1: backward (in may alias out), 2: transposed forward,
 // 3: transposed backward (aux holds the forward result and is overwritten).
 // nfields independent field blocks at block stride bstride / vector stride vstride.

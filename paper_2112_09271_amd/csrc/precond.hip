@@ -565,10 +565,6 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
       launch_ilu_factor(c.nb, c.dim, c.m - 1, per_field, P.blk.p + per_field, c.d_nbr.p, P.lev_elems.p,
                         P.lev_ptr[l], P.lev_ptr[l + 1] - P.lev_ptr[l], s, b32);
     }
-    {
-      ScopeTimer tm(c, "ilu_factor", s);
-      launch_ilu_scale_lower(c.nb, c.dim, c.m - 1, per_field, P.blk.p + per_field, c.d_nbr.p, c.E, s, b32);
-    }
     clk.mark("ilu factor (with single-precision copies)");
   };
   if (phi) {
