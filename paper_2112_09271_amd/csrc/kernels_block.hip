@@ -1594,7 +1594,12 @@ __global__ void __launch_bounds__(BT) k_q1_galerkin(const double* __restrict__ b
 // waits for its stores to complete before it publishes the counter.  The
 // residency of the whole grid makes the schedule deadlock-free (the least
 // unfinished element always has its inputs); a wait that exceeds its spin
-// limit sets *err and ends the work-group, so the sweep cannot hang.
+// limit sets *err and ends the work-group, so the sweep cannot hang.  Once
+// *err is set, every other wait of the sweep ends at its next look at the flag
+// and every later sweep returns at entry; a work-group that ends early writes
+// NaN into the rows of the element it was about to compute (it is their only
+// writer), so the failure reaches the Krylov coefficients as a non-finite
+// value and the host reports it at once.
 // ===========================================================================
 template <typename T>
 __device__ __forceinline__ T ld_dev(const T* p) {
@@ -1605,15 +1610,35 @@ __device__ __forceinline__ void st_dev(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// wait until cnt[j] >= target for every valid j in nb[0..n): one thread per entry
+// a wait gives up after spin_limit polls, or earlier when another work-group
+// has already given up (the flag is looked at every 64 polls)
+__device__ __forceinline__ bool df_give_up(int spins, int spin_limit, const int* err) {
+  return spins > spin_limit || ((spins & 63) == 0 && ld_dev(err) != 0);
+}
+
+// the rows of element i of an ended sweep: NaN (one writer per element)
+template <typename T, int NB>
+__device__ __forceinline__ void df_poison(T* out, int64_t i, int tid) {
+  for (int idx = tid; idx < NB; idx += BT) st_dev(out + i * NB + idx, T(__builtin_nan("")));
+}
+
+// true (in every thread) when an earlier wait of this or another sweep gave up
+__device__ __forceinline__ bool df_failed(const int* err, int* s_abort, int tid) {
+  if (tid == 0) *s_abort = ld_dev(err) != 0;
+  __syncthreads();
+  return *s_abort != 0;
+}
+
+// wait until cnt[j] >= target for every valid j in nb[0..n): one thread per
+// entry; the counter load acquires what its producer released
 __device__ inline void df_wait(const unsigned* cnt, const int* nb, int n, unsigned target, int spin_limit,
                                int* err, int* s_abort, int tid) {
   if (tid < n) {
     const int j = nb[tid];
     if (j >= 0) {
       int spins = 0;
-      while (ld_dev(cnt + j) < target) {
-        if (++spins > spin_limit) {
+      while (__hip_atomic_load(cnt + j, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (df_give_up(++spins, spin_limit, err)) {
           st_dev(err, 1);
           *s_abort = 1;
           break;
@@ -1623,6 +1648,8 @@ __device__ inline void df_wait(const unsigned* cnt, const int* nb, int n, unsign
     }
   }
   __syncthreads();
+  // the other threads of the work-group read the neighbours' results next
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 // kind 0 (forward): w_i = D_i^{-1} r_i - sum_{s lower} Lhat_{i,s} w_nbr
@@ -1642,7 +1669,10 @@ __global__ void __launch_bounds__(BT) k_ilu_df(const T* __restrict__ blk, const 
   __shared__ int s_nb[DIM];
   __shared__ int s_abort;
   const int tid = threadIdx.x, row = tid >> 2, part = tid & 3;
-  if (tid == 0) s_abort = 0;
+  if (df_failed(err, &s_abort, tid)) {
+    if (int64_t(blockIdx.x) < E) df_poison<T, NB>(out, order[KIND == 0 ? blockIdx.x : E - 1 - blockIdx.x], tid);
+    return;
+  }
   for (int64_t t = blockIdx.x; t < E; t += gridDim.x) {
     const int64_t i = order[KIND == 0 ? t : E - 1 - t];
     if (tid < DIM) s_nb[tid] = nbr[i * 2 * DIM + 2 * tid + KIND];
@@ -1663,7 +1693,10 @@ __global__ void __launch_bounds__(BT) k_ilu_df(const T* __restrict__ blk, const 
     const unsigned target = ld_dev(cnt + i) + 1u;
     __syncthreads();
     df_wait(cnt, s_nb, DIM, target, spin_limit, err, &s_abort, tid);
-    if (s_abort) return;
+    if (s_abort) {
+      df_poison<T, NB>(out, i, tid);
+      return;
+    }
     for (int idx = tid; idx < DIM * NB; idx += BT) {
       const int d = idx / NB, l = idx % NB;
       const int j = s_nb[d];
@@ -1688,9 +1721,11 @@ __global__ void __launch_bounds__(BT) k_ilu_df(const T* __restrict__ blk, const 
       if (KIND == 1) acc = xs[0][row] + acc;
       if (part == 0) st_dev(out + i * NB + row, acc);
     }
-    __builtin_amdgcn_s_waitcnt(0);
+    // every thread releases its stores at agent scope, then one thread
+    // publishes the element's count with a release store
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (tid == 0) st_dev(cnt + i, target);
+    if (tid == 0) __hip_atomic_store(cnt + i, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -1714,7 +1749,10 @@ __global__ void __launch_bounds__(BT) k_ilu_dfp(const float* __restrict__ blk, c
   __shared__ int s_nb[DIM];
   __shared__ int s_abort;
   const int tid = threadIdx.x, row = tid >> 2, part = tid & 3;
-  if (tid == 0) s_abort = 0;
+  if (df_failed(err, &s_abort, tid)) {
+    if (int64_t(blockIdx.x) < E) df_poison<float, NB>(out, order[KIND == 0 ? blockIdx.x : E - 1 - blockIdx.x], tid);
+    return;
+  }
   for (int64_t t = blockIdx.x; t < E; t += gridDim.x) {
     const int64_t i = order[KIND == 0 ? t : E - 1 - t];
     if (tid < DIM) s_nb[tid] = nbr[i * 2 * DIM + 2 * tid + KIND];
@@ -1742,7 +1780,7 @@ __global__ void __launch_bounds__(BT) k_ilu_dfp(const float* __restrict__ blk, c
         uint64_t word = ld_dev(src);
         int spins = 0;
         while (unsigned(word >> 32) != target) {
-          if (++spins > spin_limit) {
+          if (df_give_up(++spins, spin_limit, err)) {
             st_dev(err, 1);
             s_abort = 1;
             break;
@@ -1755,7 +1793,10 @@ __global__ void __launch_bounds__(BT) k_ilu_dfp(const float* __restrict__ blk, c
       xs[1 + d][l] = v;
     }
     __syncthreads();
-    if (s_abort) return;
+    if (s_abort) {
+      df_poison<float, NB>(out, i, tid);
+      return;
+    }
     if (row < NB) {
       float acc = 0.0f;
       if constexpr (KIND == 0) {
@@ -1806,7 +1847,13 @@ __global__ void __launch_bounds__(BT) k_ilu_dfl(const float* __restrict__ blk, c
   __shared__ float xs[DIM + 1][NB];  // [0]: own input; [1 + d]: neighbour across direction d
   __shared__ int s_abort;
   const int tid = threadIdx.x, row = tid >> 2, part = tid & 3;
-  if (tid == 0) s_abort = 0;
+  if (df_failed(err, &s_abort, tid)) {
+    if (int(blockIdx.x) < nline) {
+      const int64_t first = line_first[KIND == 0 ? blockIdx.x : nline - 1 - blockIdx.x];
+      df_poison<float, NB>(out, KIND == 0 ? first : first + int64_t(len - 1) * lstride, tid);
+    }
+    return;
+  }
   // rows of the element's own blocks that the sweep reads: D^{-1} and the
   // lower blocks (forward) or the upper blocks (backward)
   auto fetch = [&](int64_t e, float (&m)[DIM + 1][QL]) {
@@ -1866,7 +1913,7 @@ __global__ void __launch_bounds__(BT) k_ilu_dfl(const float* __restrict__ blk, c
           uint64_t word = ld_dev(src);
           int spins = 0;
           while (unsigned(word >> 32) != target) {
-            if (++spins > spin_limit) {
+            if (df_give_up(++spins, spin_limit, err)) {
               st_dev(err, 1);
               s_abort = 1;
               break;
@@ -1879,7 +1926,10 @@ __global__ void __launch_bounds__(BT) k_ilu_dfl(const float* __restrict__ blk, c
         xs[1 + d][l] = v;
       }
       __syncthreads();
-      if (s_abort) return;
+      if (s_abort) {
+        df_poison<float, NB>(out, i, tid);
+        return;
+      }
       float acc = 0.0f;
       if (row < NB) {
         if constexpr (KIND == 0) {

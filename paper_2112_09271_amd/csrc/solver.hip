@@ -218,7 +218,10 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
     first = false;
     const double beta = vnorm2(K.r.p, N, K.hd.p, s);
     out.res = beta;
-    if (!std::isfinite(beta)) throw Error(DGNP_E_NONFINITE, "non-finite linear residual");
+    if (!std::isfinite(beta)) {
+      precond_check(c);  // an ended dataflow sweep is reported as such
+      throw Error(DGNP_E_NONFINITE, "non-finite linear residual");
+    }
     if (verbose > 1) fprintf(stderr, "  fgmres restart: |r| = %.3e (target %.3e)\n", beta, target);
     if (beta <= target) {
       out.converged = true;
@@ -286,6 +289,7 @@ static LinResult fgmres(dgnp_ctx& c, const double* b, double* x, double target, 
       }
       if (!std::isfinite(hb[DCGS_ALPHA]) || !std::isfinite(hb[DCGS_HJJ]) || !std::isfinite(hb[DCGS_RHO])) {
         DGNP_HIP(hipStreamSynchronize(s));
+        precond_check(c);  // a dataflow sweep that ended at its wait limit left NaN rows
         throw Error(DGNP_E_NONFINITE, "non-finite Arnoldi vector");
       }
       return hb;

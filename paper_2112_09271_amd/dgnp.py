@@ -236,6 +236,12 @@ class Problem:
             self.Pe = float(Pe)
         _check(lib().dgnp_set_params(self.ctx, ptr, self.Pe))
 
+    def current_bc(self):
+        """The nodal boundary data [m-1][n_bnode] the context holds (None with a manufactured solution)."""
+        if self._bc is None:
+            return None
+        return self._bc.reshape(self.m - 1, self.n_bnode)
+
     # tables
     def connectivity(self):
         nF, nB = C.c_int64(), C.c_int64()

@@ -66,10 +66,9 @@ def test_published_errors_and_rates(p, sizes):
         assert abs(rate - rate_paper) < 0.35, (p, sizes[k], rate, rate_paper)
 
 
-@pytest.mark.skipif(os.environ.get("DGNP_E1_LARGE") != "1",
-                    reason="33.5M DOFs with an error integral of about 20 s on the host: set DGNP_E1_LARGE=1")
 def test_published_error_largest_p1():
-    """Table tab:cpu's largest p = 1 case, 128^3 elements (33.5M DOFs), on one GPU."""
+    """Table tab:cpu's largest p = 1 case, 128^3 elements (33.5M DOFs), on one GPU
+    (the error integral takes about 20 s on the host)."""
     with open(os.path.join(GOLD, "paper_table_cpu.json")) as f:
         paper = {(r[1], r[2]): r[3] for r in json.load(f)["rows"]}
     e = _errors(1, 128)

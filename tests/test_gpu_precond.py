@@ -1,4 +1,6 @@
 """GPU tests of the block assembly and the block preconditioner."""
+import time
+
 import numpy as np
 import pytest
 
@@ -172,17 +174,19 @@ def test_line_sweeps_agree_with_level_sweeps(name, monkeypatch):
 def test_dataflow_wait_limit_is_reported(monkeypatch):
     """A sweep whose waits run out (spin limit 0) ends every work-group and the
     solve reports an error instead of hanging; a new problem solves normally."""
-    from paper_2112_09271_amd.dgnp import (DGNP_E_BREAKDOWN, DGNP_E_NOCONV, DGNP_E_NONFINITE, DGNP_F32,
-                                           DgnpError)
+    from paper_2112_09271_amd.dgnp import DGNP_E_BREAKDOWN, DGNP_F32, DgnpError
     monkeypatch.setenv("DGNP_DATAFLOW", "1")
     monkeypatch.setenv("DGNP_DATAFLOW_SPIN", "0")
     cfg, _, gp = pair("cfg2t", with_oracle=False)
+    t0 = time.perf_counter()
     try:
         x, st = gp.solve(prec=DGNP_F32, max_newton=2)
         failed = False
     except DgnpError as e:
-        assert e.code in (DGNP_E_BREAKDOWN, DGNP_E_NONFINITE, DGNP_E_NOCONV), e
+        # the first sweep that gives up ends the linear solve with its own code
+        assert e.code == DGNP_E_BREAKDOWN, e
         failed = True
+    assert time.perf_counter() - t0 < 20.0
     gp.close()
     monkeypatch.delenv("DGNP_DATAFLOW_SPIN")
     _, _, g2 = pair("cfg2t", with_oracle=False)
@@ -194,17 +198,19 @@ def test_dataflow_wait_limit_is_reported(monkeypatch):
 def test_line_sweep_wait_limit_is_reported(monkeypatch):
     """Line sweeps whose waits run out (spin limit 0) end every work-group and the
     solve reports an error instead of hanging; a new problem solves normally."""
-    from paper_2112_09271_amd.dgnp import (DGNP_E_BREAKDOWN, DGNP_E_NOCONV, DGNP_E_NONFINITE, DGNP_F32,
-                                           DgnpError)
+    from paper_2112_09271_amd.dgnp import DGNP_E_BREAKDOWN, DGNP_F32, DgnpError
     monkeypatch.setenv("DGNP_ILU_SWEEP", "line")
     monkeypatch.setenv("DGNP_DATAFLOW_SPIN", "0")
     cfg, _, gp = pair("cfg2t", with_oracle=False)
+    t0 = time.perf_counter()
     try:
         x, st = gp.solve(prec=DGNP_F32, max_newton=2)
         failed = False
     except DgnpError as e:
-        assert e.code in (DGNP_E_BREAKDOWN, DGNP_E_NONFINITE, DGNP_E_NOCONV), e
+        # the first sweep that gives up ends the linear solve with its own code
+        assert e.code == DGNP_E_BREAKDOWN, e
         failed = True
+    assert time.perf_counter() - t0 < 20.0
     gp.close()
     monkeypatch.delenv("DGNP_DATAFLOW_SPIN")
     _, _, g2 = pair("cfg2t", with_oracle=False)

@@ -29,6 +29,22 @@ def test_newton_solution_matches_oracle(name):
         assert err <= 1e-8
 
 
+@pytest.mark.parametrize("name", ["cfg2t", "cfg3s"])
+def test_p1_preconditioner_solution_matches_oracle(name):
+    """Eq. P1 (potential first, then the concentrations with the coupling to the
+    potential correction), the paper's choice at order 1: a converged solve at
+    p = 1 in both precisions matches the oracle."""
+    from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64, DGNP_PC_P1
+    cfg, od, gp = pair(name, p=1)
+    x_ref, _ = osolve.newton(od, tol=1e-13)
+    for prec in (DGNP_F64, DGNP_F32):
+        x, st = gp.solve(rtol=1e-11, prec=prec, pc_kind=DGNP_PC_P1)
+        err = _rel(host(x), x_ref)
+        print(f"{name} p=1 P1 prec={prec}: newton {st.newton_its}, fgmres {st.lin_its_total}, rel err {err:.2e}")
+        assert st.status == 0 and st.res_final <= 1e-11 * st.res0
+        assert err <= 1e-8
+
+
 def test_full_cube_solves_fp64_and_mixed():
     """16^3 hexes, p = 2, Pe = 1e3 (too large for the oracle's direct solver):
     the oracle's own residual vanishes at the GPU solutions, and the FP64 and
