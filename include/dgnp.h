@@ -28,8 +28,9 @@
  *    dgnp_set_state, dgnp_solve and dgnp_adjoint synchronise.
  *  - Every call returns a DGNP_* status; no C++ exception crosses the ABI.
  *    dgnp_last_error() returns the text of the last failure on this thread.
- *  - The library never keeps a caller pointer after returning.  The context
- *    owns all device workspace (hipMalloc) and frees it in dgnp_destroy.
+ *  - The library never keeps a caller pointer after returning (apart from the
+ *    allocator hook of dgnp_options).  The context owns all device workspace
+ *    (hipMalloc, or the caller's allocator hook) and frees it in dgnp_destroy.
  *  - One context per host thread at a time.
  */
 #ifndef DGNP_H
@@ -115,6 +116,32 @@ typedef struct {
                               PG (orders 2, 3): as P, with the p = 1 level the
                               Galerkin product P^T A_p P of the order-p block;
                               AUTO (0, the default): Q1 for p <= 2, PG for p = 3 */
+  /* Optional data of a forced or manufactured problem, copied at setup (NULL:
+   * none).  Gauss points per axis: nq = p + 2; volume point q = qx + nq (qy +
+   * nq qz); face point qf = qi + nq qj, qi along the face's first tangential
+   * axis (x-faces: y, y- and z-faces: x), qj along the second (x- and
+   * y-faces: z, z-faces: y); boundary faces in the order of the box faces
+   * 0..5, then by element index. */
+  const double *src_vol;   /* host [m][E][nq^d]: volume sources at the Gauss points,
+                              field 0 the charge equation (S_phi), field k species k;
+                              they enter the residual as -int S_f v */
+  const double *dir_face;  /* host [m][n_bface][nq^(d-1)]: boundary data at the face
+                              Gauss points of every boundary face: field 0 the
+                              potential on potential-Dirichlet faces, field k the
+                              concentration c_k on DIRICHLET / INFLOW faces (other
+                              entries are not read); replaces bc_conc and phi_val.
+                              dgnp_set_params and the boundary-data gradient of
+                              dgnp_adjoint are then unavailable (DGNP_E_ARG) */
+  /* Optional device allocator for the context's workspace (for instance
+   * PyTorch's caching allocator): both or neither of alloc and free_.  alloc
+   * returns a device pointer of at least `bytes` bytes on the context's device,
+   * aligned to 256 bytes, or NULL (the call then fails with DGNP_E_ALLOC);
+   * free_ releases it (the library synchronises its streams before freeing
+   * memory that kernels may still use).  Used for allocations made on the
+   * calling thread during calls on this context; NULL: hipMalloc / hipFree. */
+  void *(*alloc)(size_t bytes, void *alloc_ctx);
+  void (*free_)(void *ptr, void *alloc_ctx);
+  void *alloc_ctx;
 } dgnp_options;
 enum { DGNP_PHIMG_AUTO = 0, DGNP_PHIMG_Q1 = 1, DGNP_PHIMG_P = 2, DGNP_PHIMG_PG = 3 };
 
@@ -203,6 +230,13 @@ int dgnp_jacobian_apply(dgnp_ctx *ctx, const void *v, void *y, int32_t prec,
  * request the context does not provide. */
 enum { DGNP_PHIOP_ASSEMBLED = 0, DGNP_PHIOP_MATFREE = 1 };
 int dgnp_phi_apply(dgnp_ctx *ctx, const void *v, void *y, int32_t prec, int32_t kind, void *stream);
+
+/* y = A_phi,c v_c: the potential rows of J(x) applied to the concentration
+ * part of v (the coupling block that Eq. P2 of Sec. 4.2 subtracts from the
+ * potential right-hand side; the potential part of v is not read), at the
+ * point of the last dgnp_set_state.  v: device [N] of type `prec`; y: device
+ * [E * nb] (the potential rows).  DGNP_E_STATE before set_state. */
+int dgnp_coupling_apply(dgnp_ctx *ctx, const void *v, void *y, int32_t prec, void *stream);
 
 /* z = P r, the block-triangular preconditioner (Eq. P2 when pc_kind =
  * DGNP_PC_P2, Eq. P1 otherwise): one element-block ILU(0) solve per

@@ -2,14 +2,17 @@
 // status codes and records the message for dgnp_last_error().
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "context.hpp"
+#include "kernels_jac.hpp"
 #include "solver.hpp"
 
 using namespace dgnp;
 
 static thread_local std::string g_last_error;
+thread_local const dgnp::DevAllocator* dgnp::t_dev_alloc = nullptr;
 
 template <typename F>
 static int guard(F&& f) {
@@ -70,6 +73,11 @@ dgnp::KArgs dgnp_ctx::kargs() const {
 
 // boundary data at the face Gauss points, [m][n_bface][nqf]
 static void build_boundary_data(dgnp_ctx& c) {
+  if (!c.dir_face.empty()) {  // the caller's data at the face points
+    c.d_bcq.upload(c.dir_face, c.stream);
+    if (!c.src_vol.empty()) c.d_src.upload(c.src_vol, c.stream);
+    return;
+  }
   const int d = c.dim, nq = c.nq, nn = c.nn;
   std::vector<double> bcq(static_cast<size_t>(c.m) * c.n_bface * c.nqf, 0.0);
   int64_t stride2 = int64_t(c.n[0]) * c.n[1];
@@ -115,7 +123,9 @@ static void build_boundary_data(dgnp_ctx& c) {
     }
   }
   c.d_bcq.upload(bcq, c.stream);
-  if (c.mms) {
+  if (!c.src_vol.empty()) {
+    c.d_src.upload(c.src_vol, c.stream);
+  } else if (c.mms) {
     std::vector<double> src(static_cast<size_t>(c.m) * c.E * c.nqv, 0.0);
     for (int64_t e = 0; e < c.E; ++e) {
       int id[3] = {int(e % c.n[0]), int((e / c.n[0]) % c.n[1]), d == 3 ? int(e / stride2) : 0};
@@ -144,7 +154,15 @@ int dgnp_setup(const dgnp_mesh* mesh, int32_t order, const dgnp_species* sp, con
     DGNP_REQUIRE(sp->m >= 2 && sp->m <= 3, DGNP_E_ARG, "number of ions must be 2 or 3");
     DGNP_REQUIRE(sp->z && sp->D, DGNP_E_ARG, "species arrays missing");
     DGNP_REQUIRE(sp->z[sp->m - 1] != 0.0, DGNP_E_ARG, "eliminated ion must be charged");
+    DGNP_REQUIRE(!opt || (opt->alloc == nullptr) == (opt->free_ == nullptr), DGNP_E_ARG,
+                 "allocator hook: both alloc and free_, or neither");
     auto c = std::make_unique<dgnp_ctx>();
+    if (opt && opt->alloc) {
+      c->allocator.alloc = opt->alloc;
+      c->allocator.free_ = opt->free_;
+      c->allocator.ctx = opt->alloc_ctx;
+    }
+    AllocScope as(c->allocator);
     c->dim = mesh->dim;
     c->p = order;
     c->m = sp->m;
@@ -203,10 +221,19 @@ int dgnp_setup(const dgnp_mesh* mesh, int32_t order, const dgnp_species* sp, con
     {
       RefTables all[3] = {make_ref_tables(1), make_ref_tables(2), make_ref_tables(3)};
       upload_ref_tables(all, 3);
+      upload_ref_tables_jac(all, 3);
     }
+    c->jac_tab = getenv("DGNP_JAC_GENERAL") == nullptr;
     build_tables(*c);
-    if (c->mms == 0 && c->n_bnode > 0) {
-      DGNP_REQUIRE(opt && opt->bc_conc, DGNP_E_ARG, "boundary data (bc_conc) required");
+    if (opt && opt->src_vol) {
+      c->src_vol.assign(opt->src_vol, opt->src_vol + size_t(c->m) * c->E * c->nqv);
+      for (double v : c->src_vol) DGNP_REQUIRE(std::isfinite(v), DGNP_E_NONFINITE, "non-finite volume sources");
+    }
+    if (opt && opt->dir_face) {
+      c->dir_face.assign(opt->dir_face, opt->dir_face + size_t(c->m) * c->n_bface * c->nqf);
+      for (double v : c->dir_face) DGNP_REQUIRE(std::isfinite(v), DGNP_E_NONFINITE, "non-finite boundary data");
+    } else if (c->mms == 0 && c->n_bnode > 0) {
+      DGNP_REQUIRE(opt && opt->bc_conc, DGNP_E_ARG, "boundary data (bc_conc or dir_face) required");
       c->bc_conc.assign(opt->bc_conc, opt->bc_conc + size_t(c->m - 1) * c->n_bnode);
       for (double v : c->bc_conc) DGNP_REQUIRE(std::isfinite(v), DGNP_E_NONFINITE, "non-finite boundary data");
     }
@@ -223,6 +250,8 @@ int dgnp_set_params(dgnp_ctx* c, const double* bc_conc, double Pe) {
   return guard([&] {
     DGNP_REQUIRE(c, DGNP_E_ARG, "NULL context");
     DGNP_REQUIRE(c->mms == 0, DGNP_E_ARG, "parameters are fixed by the manufactured solution");
+    DGNP_REQUIRE(c->dir_face.empty(), DGNP_E_ARG, "parameters are fixed by the caller's face data");
+    AllocScope as(c->allocator);
     DGNP_REQUIRE(std::isfinite(Pe), DGNP_E_NONFINITE, "non-finite Pe");
     if (bc_conc && c->n_bnode > 0) {
       for (int64_t i = 0; i < (c->m - 1) * c->n_bnode; ++i)
@@ -267,6 +296,7 @@ int dgnp_connectivity(const dgnp_ctx* c, int32_t* elem_nbr, int32_t* face_elems,
 int dgnp_residual(dgnp_ctx* c, const double* x, double* r, void* stream) {
   return guard([&] {
     DGNP_REQUIRE(c && x && r, DGNP_E_ARG, "NULL argument");
+    AllocScope as(c->allocator);
     ScopeTimer tm(*c, "residual", static_cast<hipStream_t>(stream));
     launch_dg(c->dim, c->p, c->m, false, M_RES, c->kargs(), x, nullptr, r, nullptr,
               static_cast<hipStream_t>(stream));
@@ -276,6 +306,7 @@ int dgnp_residual(dgnp_ctx* c, const double* x, double* r, void* stream) {
 int dgnp_residual_dpe(dgnp_ctx* c, const double* x, double* r, void* stream) {
   return guard([&] {
     DGNP_REQUIRE(c && x && r, DGNP_E_ARG, "NULL argument");
+    AllocScope as(c->allocator);
     launch_dg(c->dim, c->p, c->m, false, M_DPE, c->kargs(), x, nullptr, r, nullptr,
               static_cast<hipStream_t>(stream));
   });
@@ -284,6 +315,7 @@ int dgnp_residual_dpe(dgnp_ctx* c, const double* x, double* r, void* stream) {
 int dgnp_set_state(dgnp_ctx* c, const double* x, int32_t prec, void* stream) {
   return guard([&] {
     DGNP_REQUIRE(c && x, DGNP_E_ARG, "NULL argument");
+    AllocScope as(c->allocator);
     const bool asm_only = (prec & DGNP_STATE_ASSEMBLE_ONLY) != 0;
     const bool apply_only = (prec & DGNP_STATE_APPLY_ONLY) != 0;
     prec &= ~(DGNP_STATE_ASSEMBLE_ONLY | DGNP_STATE_APPLY_ONLY);
@@ -296,14 +328,25 @@ int dgnp_jacobian_apply(dgnp_ctx* c, const void* v, void* y, int32_t prec, int32
                         void* stream) {
   return guard([&] {
     DGNP_REQUIRE(c && v && y, DGNP_E_ARG, "NULL argument");
+    AllocScope as(c->allocator);
     DGNP_REQUIRE(prec == DGNP_F64 || prec == DGNP_F32, DGNP_E_ARG, "prec must be F64 or F32");
     jac_apply(*c, v, y, prec == DGNP_F32, transpose != 0, static_cast<hipStream_t>(stream));
+  });
+}
+
+int dgnp_coupling_apply(dgnp_ctx* c, const void* v, void* y, int32_t prec, void* stream) {
+  return guard([&] {
+    DGNP_REQUIRE(c && v && y, DGNP_E_ARG, "NULL argument");
+    AllocScope as(c->allocator);
+    DGNP_REQUIRE(prec == DGNP_F64 || prec == DGNP_F32, DGNP_E_ARG, "prec must be F64 or F32");
+    jac_apply(*c, v, y, prec == DGNP_F32, false, static_cast<hipStream_t>(stream), ~1u, true, nullptr);
   });
 }
 
 int dgnp_phi_apply(dgnp_ctx* c, const void* v, void* y, int32_t prec, int32_t kind, void* stream) {
   return guard([&] {
     DGNP_REQUIRE(c && v && y, DGNP_E_ARG, "NULL argument");
+    AllocScope as(c->allocator);
     DGNP_REQUIRE(prec == DGNP_F64 || prec == DGNP_F32, DGNP_E_ARG, "prec must be F64 or F32");
     DGNP_REQUIRE(kind == DGNP_PHIOP_ASSEMBLED || kind == DGNP_PHIOP_MATFREE, DGNP_E_ARG, "unknown kind");
     phi_apply(*c, v, y, prec == DGNP_F32, kind == DGNP_PHIOP_MATFREE, static_cast<hipStream_t>(stream));
@@ -314,6 +357,7 @@ int dgnp_precond_apply(dgnp_ctx* c, const void* r, void* z, int32_t prec, int32_
                        int32_t pc_kind, void* stream) {
   return guard([&] {
     DGNP_REQUIRE(c && r && z, DGNP_E_ARG, "NULL argument");
+    AllocScope as(c->allocator);
     DGNP_REQUIRE(prec == DGNP_F64 || prec == DGNP_F32, DGNP_E_ARG, "prec must be F64 or F32");
     DGNP_REQUIRE(pc_kind == DGNP_PC_P2 || pc_kind == DGNP_PC_P1, DGNP_E_ARG, "unknown preconditioner");
     precond_apply(*c, r, z, prec == DGNP_F32, transpose != 0, pc_kind, static_cast<hipStream_t>(stream));
@@ -323,6 +367,7 @@ int dgnp_precond_apply(dgnp_ctx* c, const void* r, void* z, int32_t prec, int32_
 int dgnp_solve(dgnp_ctx* c, double* x, const dgnp_solve_opts* opts, dgnp_solve_stats* stats) {
   return guard([&] {
     DGNP_REQUIRE(c && x, DGNP_E_ARG, "NULL argument");
+    AllocScope as(c->allocator);
     dgnp_solve_opts o = default_solve_opts();
     if (opts) o = *opts;
     dgnp_solve_stats st{};
@@ -339,7 +384,10 @@ int dgnp_adjoint(dgnp_ctx* c, const double* x, int32_t objective, double* dJ_dbc
                  double* J_out, double* lambda, const dgnp_solve_opts* opts, dgnp_solve_stats* stats) {
   return guard([&] {
     DGNP_REQUIRE(c && x, DGNP_E_ARG, "NULL argument");
+    AllocScope as(c->allocator);
     DGNP_REQUIRE(objective == 0, DGNP_E_ARG, "objective 0 (outflow flux of species 1) is the only one");
+    DGNP_REQUIRE(!dJ_dbc || c->dir_face.empty(), DGNP_E_ARG,
+                 "no boundary-data gradient with caller face data (dir_face): pass dJ_dbc = NULL");
     dgnp_solve_opts o = default_solve_opts();
     if (opts) o = *opts;
     dgnp_solve_stats st{};
@@ -353,6 +401,7 @@ int dgnp_adjoint(dgnp_ctx* c, const double* x, int32_t objective, double* dJ_dbc
 int dgnp_objective(dgnp_ctx* c, const double* x, int32_t objective, double* J_out) {
   return guard([&] {
     DGNP_REQUIRE(c && x && J_out, DGNP_E_ARG, "NULL argument");
+    AllocScope as(c->allocator);
     DGNP_REQUIRE(objective == 0, DGNP_E_ARG, "objective 0 (outflow flux of species 1) is the only one");
     *J_out = objective_value(*c, x);
   });
@@ -361,6 +410,7 @@ int dgnp_objective(dgnp_ctx* c, const double* x, int32_t objective, double* J_ou
 int dgnp_get_block(dgnp_ctx* c, int32_t field, int64_t elem, int32_t slot, double* out) {
   return guard([&] {
     DGNP_REQUIRE(c && out, DGNP_E_ARG, "NULL argument");
+    AllocScope as(c->allocator);
     DGNP_REQUIRE(field >= 0 && field < c->m && elem >= 0 && elem < c->E && slot >= 0 &&
                      slot <= 2 * c->dim,
                  DGNP_E_ARG, "block index out of range");
@@ -387,7 +437,11 @@ int dgnp_profile(dgnp_ctx* c, int32_t enable) {
   });
 }
 
-void dgnp_destroy(dgnp_ctx* c) { delete c; }
+void dgnp_destroy(dgnp_ctx* c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();  // no kernel of the context is still running when its memory goes
+  delete c;
+}
 
 const char* dgnp_last_error(void) { return g_last_error.c_str(); }
 

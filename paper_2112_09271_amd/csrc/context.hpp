@@ -29,6 +29,9 @@ struct dgnp_ctx {
   int64_t btag_off[6] = {};      // first boundary face of each box face
   int64_t bnode_off[6] = {};     // first data node of each box face (-1: no data)
   std::vector<double> bc_conc;   // [m-1][n_bnode]
+  std::vector<double> src_vol;   // caller sources [m][E][nqv] (empty: none, or the manufactured solution's)
+  std::vector<double> dir_face;  // caller boundary data [m][n_bface][nqf] (empty: from bc_conc / phi_val)
+  dgnp::DevAllocator allocator;  // device workspace allocator (the caller's hook or hipMalloc)
   dgnp::RefTables ref;
   hipStream_t stream = nullptr;   // the caller's stream at setup
   hipStream_t work = nullptr;     // library stream for the synchronous drivers (graph capture)
@@ -43,6 +46,11 @@ struct dgnp_ctx {
   dgnp::DevBuf<double> d_x;
   dgnp::DevBuf<float> d_x32;
   bool has_state = false, has_state32 = false;
+  // tabulated linearisation data of the 3-D Jacobian apply (kernels_jac.hip):
+  // volume [E][m+2][nq^3] and face [E][6][m+1][nq^2] tables per precision
+  bool jac_tab = true;             // use them (DGNP_JAC_GENERAL=1: the general operator kernel)
+  dgnp::DevBuf<double> d_jtv, d_jtf;
+  dgnp::DevBuf<float> d_jtv32, d_jtf32;
 
   dgnp::Precond* pc = nullptr;
   dgnp::Krylov* kry = nullptr;

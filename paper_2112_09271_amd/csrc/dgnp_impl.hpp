@@ -31,16 +31,36 @@ struct Error : std::runtime_error {
     if (!(cond)) throw ::dgnp::Error((code), std::string(msg));  \
   } while (0)
 
-// Owning device buffer.
+// Device allocator of a context: the caller's hook (dgnp_options.alloc /
+// free_ / alloc_ctx), or hipMalloc / hipFree when both are null.
+struct DevAllocator {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*free_)(void*, void*) = nullptr;
+  void* ctx = nullptr;
+};
+// The allocator that DevBuf::alloc uses on this thread: set for the duration
+// of an ABI call on a context that has a hook (null: hipMalloc).  Buffers
+// allocated on other threads (host helper threads) use hipMalloc.
+extern thread_local const DevAllocator* t_dev_alloc;
+struct AllocScope {
+  const DevAllocator* prev;
+  explicit AllocScope(const DevAllocator& a) : prev(t_dev_alloc) { t_dev_alloc = a.alloc ? &a : nullptr; }
+  ~AllocScope() { t_dev_alloc = prev; }
+  AllocScope(const AllocScope&) = delete;
+  AllocScope& operator=(const AllocScope&) = delete;
+};
+
+// Owning device buffer; it frees through the allocator that allocated it.
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;    // elements in use
   size_t cap = 0;  // elements allocated
+  DevAllocator al;  // hook of the allocation (null: hipMalloc)
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), cap(o.cap) {
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), cap(o.cap), al(o.al) {
     o.p = nullptr;
     o.n = o.cap = 0;
   }
@@ -50,6 +70,7 @@ struct DevBuf {
       p = o.p;
       n = o.n;
       cap = o.cap;
+      al = o.al;
       o.p = nullptr;
       o.n = o.cap = 0;
     }
@@ -61,9 +82,17 @@ struct DevBuf {
     if (count == n && p) return;
     release();
     if (count == 0) return;
-    if (hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)) != hipSuccess) {
-      p = nullptr;
-      throw Error(DGNP_E_ALLOC, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    const DevAllocator* a = t_dev_alloc;
+    if (a && a->alloc) {
+      p = static_cast<T*>(a->alloc(count * sizeof(T), a->ctx));
+      if (!p) throw Error(DGNP_E_ALLOC, "allocator hook returned NULL for " + std::to_string(count * sizeof(T)) + " bytes");
+      al = *a;
+    } else {
+      if (hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)) != hipSuccess) {
+        p = nullptr;
+        throw Error(DGNP_E_ALLOC, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+      }
+      al = DevAllocator{};
     }
     n = cap = count;
   }
@@ -77,9 +106,18 @@ struct DevBuf {
     alloc(count);
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (al.free_) {
+        // as hipFree: no kernel may still use the memory when the hook gets it back
+        (void)hipDeviceSynchronize();
+        al.free_(p, al.ctx);
+      } else {
+        (void)hipFree(p);
+      }
+    }
     p = nullptr;
     n = cap = 0;
+    al = DevAllocator{};
   }
   // synchronous: the host source may be a temporary
   void upload(const T* host, size_t count, hipStream_t s) {

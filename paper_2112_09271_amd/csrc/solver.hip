@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "blas.hpp"
+#include "kernels_jac.hpp"
 #include "solver.hpp"
 
 namespace dgnp {
@@ -28,6 +29,19 @@ void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assem
     cvt_d2f(c.d_x.p, c.d_x32.p, c.N, s);
     c.has_state32 = true;
   }
+  if (c.dim == 3 && c.jac_tab) {
+    size_t nf = 0;
+    const size_t nv = jlin_table_sizes(c.p, c.m, c.E, &nf);
+    const KArgs A = c.kargs();
+    c.d_jtv.alloc(nv);
+    c.d_jtf.alloc(nf);
+    launch_jlin_tables<double>(c.p, c.m, A, c.d_x.p, c.d_jtv.p, c.d_jtf.p, s);
+    if (prec == DGNP_F32) {
+      c.d_jtv32.alloc(nv);
+      c.d_jtf32.alloc(nf);
+      launch_jlin_tables<float>(c.p, c.m, A, c.d_x.p, c.d_jtv32.p, c.d_jtf32.p, s);
+    }
+  }
   if (apply_only)
     precond_invalidate(c);
   else
@@ -46,6 +60,17 @@ void jac_apply(dgnp_ctx& c, const void* v, void* y, bool f32, bool transpose, hi
   A.vin_mask = vmask;
   DGNP_REQUIRE(!base || (phi_rows && !transpose), DGNP_E_ARG, "base needs the potential-rows apply");
   A.jbase = base;
+  // forward applies in 3-D read the tabulated linearisation data; the coupling
+  // form (potential rows) assumes that the potential part of v is masked out
+  if (c.dim == 3 && c.jac_tab && !transpose && (!phi_rows || (vmask & 1u) == 0)) {
+    if (f32)
+      launch_jlin<float>(c.p, c.m, phi_rows, A, static_cast<const float*>(v), c.d_jtv32.p, c.d_jtf32.p,
+                         static_cast<float*>(y), s);
+    else
+      launch_jlin<double>(c.p, c.m, phi_rows, A, static_cast<const double*>(v), c.d_jtv.p, c.d_jtf.p,
+                          static_cast<double*>(y), s);
+    return;
+  }
   launch_dg(c.dim, c.p, c.m, f32, transpose ? M_JACT : (phi_rows ? M_JACP : M_JAC), A, xs, v, y, nullptr, s);
 }
 
@@ -378,7 +403,18 @@ static void initial_guess(dgnp_ctx& c, double* x, hipStream_t s, int prec, int v
   vfill<double>(x, 0.0, Nf, s);
   for (int k = 1; k < c.m; ++k) {
     double mean = 1.0;
-    if (!c.mms && c.n_bnode > 0) {
+    if (!c.dir_face.empty()) {
+      // caller face data: the mean over the Gauss points of the data-carrying faces
+      double sum = 0.0;
+      int64_t cnt = 0;
+      for (int t = 0; t < 2 * c.dim; ++t) {
+        if (c.c_bc[t] != DGNP_C_DIRICHLET && c.c_bc[t] != DGNP_C_INFLOW) continue;
+        const int64_t f0 = c.btag_off[t], f1 = t + 1 < 2 * c.dim ? c.btag_off[t + 1] : c.n_bface;
+        for (int64_t bf = f0; bf < f1; ++bf)
+          for (int q = 0; q < c.nqf; ++q, ++cnt) sum += c.dir_face[(size_t(k) * c.n_bface + bf) * c.nqf + q];
+      }
+      if (cnt > 0) mean = sum / double(cnt);
+    } else if (!c.mms && c.n_bnode > 0) {
       mean = 0.0;
       for (int64_t j = 0; j < c.n_bnode; ++j) mean += c.bc_conc[size_t(k - 1) * c.n_bnode + j];
       mean /= double(c.n_bnode);

@@ -40,9 +40,46 @@ class dgnp_velocity(C.Structure):
     _fields_ = [("kind", C.c_int32), ("Pe", C.c_double), ("param", C.c_double * 3)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class dgnp_options(C.Structure):
     _fields_ = [("c_ip", C.c_double), ("mms", C.c_int32), ("bc_conc", C.POINTER(C.c_double)),
-                ("phi_mg", C.c_int32)]
+                ("phi_mg", C.c_int32), ("src_vol", C.POINTER(C.c_double)), ("dir_face", C.POINTER(C.c_double)),
+                ("alloc", ALLOC_FN), ("free_", FREE_FN), ("alloc_ctx", C.c_void_p)]
+
+
+class TorchAllocator:
+    """Device allocator hook backed by PyTorch's caching allocator: every
+    library buffer is a uint8 tensor kept alive until the library frees it."""
+
+    def __init__(self, device=None):
+        import torch
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        self.live = {}
+        self.n_alloc = 0
+        self.n_free = 0
+        self.c_alloc = ALLOC_FN(self._alloc)
+        self.c_free = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, _ctx):
+        import torch
+        try:
+            t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=self.device)
+        except RuntimeError:
+            return None
+        self.live[t.data_ptr()] = t
+        self.n_alloc += 1
+        return t.data_ptr()
+
+    def _free(self, ptr, _ctx):
+        if self.live.pop(ptr, None) is not None:
+            self.n_free += 1
+
+    @property
+    def bytes_live(self):
+        return sum(t.numel() for t in self.live.values())
 
 
 class dgnp_solve_opts(C.Structure):
@@ -71,6 +108,7 @@ _SIGS = {
     "dgnp_residual_dpe": [_vp, _vp, _vp, _vp],
     "dgnp_set_state": [_vp, _vp, C.c_int32, _vp],
     "dgnp_jacobian_apply": [_vp, _vp, _vp, C.c_int32, C.c_int32, _vp],
+    "dgnp_coupling_apply": [_vp, _vp, _vp, C.c_int32, _vp],
     "dgnp_precond_apply": [_vp, _vp, _vp, C.c_int32, C.c_int32, C.c_int32, _vp],
     "dgnp_phi_apply": [_vp, _vp, _vp, C.c_int32, C.c_int32, _vp],
     "dgnp_solve": [_vp, _vp, C.POINTER(dgnp_solve_opts), C.POINTER(dgnp_solve_stats)],
@@ -143,6 +181,10 @@ def dgnp_phi_apply(ctx, v_ptr, y_ptr, prec, kind, stream=None):
     _check(lib().dgnp_phi_apply(ctx, v_ptr, y_ptr, prec, kind, stream))
 
 
+def dgnp_coupling_apply(ctx, v_ptr, y_ptr, prec, stream=None):
+    _check(lib().dgnp_coupling_apply(ctx, v_ptr, y_ptr, prec, stream))
+
+
 def dgnp_precond_apply(ctx, r_ptr, z_ptr, prec, transpose, pc_kind=DGNP_PC_P2, stream=None):
     _check(lib().dgnp_precond_apply(ctx, r_ptr, z_ptr, prec, transpose, pc_kind, stream))
 
@@ -176,7 +218,11 @@ class Problem:
     p <= 2, PG for p = 3; DGNP_PHIMG_Q1; for orders 2 and 3 DGNP_PHIMG_P or
     DGNP_PHIMG_PG: p-multigrid with a re-discretised or Galerkin p = 1 level)."""
 
-    def __init__(self, cfg, bc_conc=None, Pe=None, phi_mg=0):
+    def __init__(self, cfg, bc_conc=None, Pe=None, phi_mg=0, src_vol=None, dir_face=None, allocator=None):
+        """src_vol [m][E][nq^d], dir_face [m][n_bface][nq^(d-1)]: optional caller
+        sources and boundary data at the Gauss points (dgnp_options); allocator:
+        an optional TorchAllocator (or any object with c_alloc / c_free ctypes
+        callbacks) for the library's device workspace."""
         import torch
         self.cfg = cfg
         d = cfg.dim
@@ -206,6 +252,17 @@ class Problem:
         if bc_conc is not None:
             self._bc = np.ascontiguousarray(bc_conc, dtype=np.float64)
             opt.bc_conc = self._bc.ctypes.data_as(C.POINTER(C.c_double))
+        self._src = self._face = None
+        if src_vol is not None:
+            self._src = np.ascontiguousarray(src_vol, dtype=np.float64)
+            opt.src_vol = self._src.ctypes.data_as(C.POINTER(C.c_double))
+        if dir_face is not None:
+            self._face = np.ascontiguousarray(dir_face, dtype=np.float64)
+            opt.dir_face = self._face.ctypes.data_as(C.POINTER(C.c_double))
+        self.allocator = allocator
+        if allocator is not None:
+            opt.alloc = allocator.c_alloc
+            opt.free_ = allocator.c_free
         self.Pe = float(vel.Pe)
         self.ctx = dgnp_setup(mesh, cfg.p, sp, vel, opt, _stream())
         E, Nf, nb = C.c_int64(), C.c_int64(), C.c_int64()
@@ -283,6 +340,14 @@ class Problem:
         v = self._dev(v, torch.float64 if prec == DGNP_F64 else torch.float32)
         y = torch.empty_like(v)
         dgnp_jacobian_apply(self.ctx, v.data_ptr(), y.data_ptr(), prec, int(transpose), _stream())
+        return y
+
+    def coupling_apply(self, v, prec=DGNP_F64):
+        """A_phi,c v_c: potential rows of J applied to the concentration part of v (Eq. P2)."""
+        import torch
+        v = self._dev(v, torch.float64 if prec == DGNP_F64 else torch.float32)
+        y = torch.empty(self.Nf, dtype=v.dtype, device=v.device)
+        dgnp_coupling_apply(self.ctx, v.data_ptr(), y.data_ptr(), prec, _stream())
         return y
 
     def phi_apply(self, v, prec=DGNP_F64, kind=0):
