@@ -13,7 +13,14 @@ these readings of passages the paper leaves open:
     symmetry/penalty on phi-Dirichlet faces; a_k-symmetry on c-Dirichlet faces;
   * INFLOW faces carry (u.n) c_in v; OUTFLOW faces (q.n) c v (the scheme's form,
     Eq. NPDG); walls carry nothing; the charge equation gets no inflow/outflow
-    term (the inlet terms cancel by electroneutrality).
+    term (the inlet terms cancel by electroneutrality);
+  * ELECTRODE faces carry the reaction rate of Eq. electrode: -g v in the
+    equation of the reacting ion r and -z_r g v in the charge equation (the
+    current sum_k z_k g_k of Eq. chargeDG), with the Butler-Volmer rate of
+    Eq. bv in the nondimensional form of Sec. 2.3, gamma = 1 and a reductant of
+    constant concentration (Sec. 5.2):
+      g = J0 [exp(alpha_a n (phi_app - phi)) - c_r exp(-alpha_c n (phi_app - phi))];
+    c_r follows Eq. substitution when r is the eliminated ion.
 d|s|/ds is taken as sign(s) with sign(0) = 0.
 
 Per element test function v, with w_q the quadrature weights:
@@ -26,7 +33,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sps
 
-from workload.configs import C_DIRICHLET, C_INFLOW, C_OUTFLOW
+from workload.configs import C_DIRICHLET, C_ELECTRODE, C_INFLOW, C_OUTFLOW
 
 from .problem import Problem
 
@@ -67,6 +74,9 @@ class DG:
                 d["g"] = [None] + [prob.c_data(k, t) for k in range(1, self.m)]
             if d["phid"]:
                 d["gphi"] = prob.phi_data(t)
+            if prob.c_bc[t] == C_ELECTRODE:
+                d["j0"], d["phiapp"] = prob.bv_data(t)
+                d["prof"] = prob.j0_profile(pts)
             self.bface.append(d)
 
     # ------------------------------------------------------------------
@@ -185,6 +195,36 @@ class DG:
             Gp[k] = -0.5 * D * djc
         return Fv, Gm, Gp
 
+    # ------------------------------------------------------------------
+    # Butler-Volmer electrode rate (Eqs. electrode, bv; Sec. 2.3)
+    def _bv_conc(self, val):
+        """Concentration of the reacting ion from the field traces."""
+        P = self.P
+        r = P.bv_ion
+        if r < self.m:
+            return val[r]
+        return -sum(P.z[k - 1] * val[k] for k in range(1, self.m)) / P.z[self.m - 1]
+
+    def _bv(self, bf, val):
+        """g and its derivatives with respect to phi, c_r, J0 and phi_app."""
+        P = self.P
+        aa, ac = P.bv_alpha
+        j0, pa = bf["j0"], bf["phiapp"]
+        eta = pa - val[0]
+        ea, ec = np.exp(aa * eta), np.exp(-ac * eta)
+        c = self._bv_conc(val)
+        g = j0 * (ea - c * ec)
+        dphi = j0 * (-aa * ea - c * ac * ec)
+        return g, dphi, -j0 * ec, ea - c * ec, -dphi
+
+    def _bv_apply(self, Fv, rate):
+        """Adds the electrode terms of the rate g to the value coefficients."""
+        P = self.P
+        r = P.bv_ion
+        if r < self.m:
+            Fv[r] = Fv[r] - rate
+        Fv[0] = Fv[0] - P.z[r - 1] * rate
+
     def _bface_res(self, bf, val, dn):
         """Boundary face with outward normal derivative dn: returns Fv[f], G[f]."""
         P, dl = self.P, self.P.delta
@@ -210,6 +250,8 @@ class DG:
             cur = sum(P.a[k - 1] * dn[k] for k in range(1, self.m)) + kap * dn[0]
             Fv[0] = -cur + kap * dl * (val[0] - gp)
             G[0] = G[0] - kap * (val[0] - gp)
+        if bf["cbc"] == C_ELECTRODE:
+            self._bv_apply(Fv, self._bv(bf, val)[0])
         return Fv, G
 
     def _bface_lin(self, bf, st, tr):
@@ -243,6 +285,11 @@ class DG:
                     + kap * tdn[0])
             Fv[0] = -dcur + dkap * dl * (val[0] - gp) + kap * dl * tv[0]
             G[0] = G[0] - dkap * (val[0] - gp) - kap * tv[0]
+        if bf["cbc"] == C_ELECTRODE:
+            _, g_phi, g_c, g_j0, g_pa = self._bv(bf, val)
+            rate = g_phi * tv[0] + g_c * self._bv_conc(tv)
+            rate = rate + g_j0 * tr.get("dj0", 0.0) + g_pa * tr.get("dphiapp", 0.0)
+            self._bv_apply(Fv, rate)
         return Fv, G
 
     # ------------------------------------------------------------------
@@ -420,6 +467,9 @@ class DG:
                 bfx["g"] = [None] + [gk[..., None] for gk in bf["g"][1:]]
             if "gphi" in bf:
                 bfx["gphi"] = bf["gphi"][..., None]
+            for key in ("j0", "phiapp"):
+                if key in bf:
+                    bfx[key] = bf[key][..., None]
             for g in range(m):
                 tb_v = [0.0] * m
                 tb_d = [0.0] * m
@@ -490,30 +540,103 @@ class DG:
                 res[k - 1, off: off + len(el) * nfn] = np.asarray(acc).reshape(-1)
         return res
 
-    # ------------------------------------------------------------------
-    # objective: outflow flux of species 1 through the x+ box face
-    def objective(self, x):
-        msh = self.msh
-        bf = self.bface[1]
+    def dR_dbv_T(self, x, lam):
+        """(lam^T dR/dJ0_t, lam^T dR/dphi_app_t) for every box face t (zero on
+        faces without an electrode); J0_t scales the face's exchange-current
+        profile."""
+        msh, d = self.msh, self.msh.dim
+        X, L = self.fields(x), self.fields(lam)
+        out_j0, out_pa = np.zeros(2 * d), np.zeros(2 * d)
+        for bf in self.bface:
+            if bf["cbc"] != C_ELECTRODE:
+                continue
+            a, s, el = bf["a"], bf["s"], bf["el"]
+            w = msh.fw[a]
+            st_b = self._trace(X, el, a, s, outward=True)
+            lv, ldn = self._trace(L, el, a, s, outward=True)
+            for which, key, pert in ((0, "dj0", bf["prof"]), (1, "dphiapp", np.ones_like(bf["prof"]))):
+                tr = dict(val=[0.0] * self.m, dn=[0.0] * self.m, dun=0.0, dg=[0.0] * self.m)
+                tr[key] = pert
+                Fv, G = self._bface_lin(bf, st_b, tr)
+                acc = sum(float(np.sum(np.broadcast_to(Fv[f], lv[f].shape) * w * lv[f])) for f in range(self.m))
+                (out_j0 if which == 0 else out_pa)[bf["t"]] = acc
+        return out_j0, out_pa
+
+    def electrode_currents(self, x):
+        """Integral of the reacting ion's rate g over each box face (zero where
+        there is no electrode)."""
+        msh, d = self.msh, self.msh.dim
         X = self.fields(x)
-        val, dn = self._trace(X, bf["el"], bf["a"], bf["s"], outward=True)
+        out = np.zeros(2 * d)
+        for bf in self.bface:
+            if bf["cbc"] != C_ELECTRODE:
+                continue
+            val, _ = self._trace(X, bf["el"], bf["a"], bf["s"], outward=True)
+            out[bf["t"]] = float(np.sum(self._bv(bf, val)[0] * msh.fw[bf["a"]]))
+        return out
+
+    # ------------------------------------------------------------------
+    # objectives: 0 = outflow flux of species 1 through the x+ box face,
+    # 1 = reaction rate of the reacting ion integrated over the first
+    # electrode face (the cell current divided by its valence)
+    def _electrode_face(self):
+        for bf in self.bface:
+            if bf["cbc"] == C_ELECTRODE:
+                return bf
+        raise ValueError("objective 1 needs an electrode face")
+
+    def objective(self, x, kind=0):
+        msh = self.msh
+        X = self.fields(x)
         P = self.P
+        if kind == 1:
+            bf = self._electrode_face()
+            val, _ = self._trace(X, bf["el"], bf["a"], bf["s"], outward=True)
+            return float(np.sum(self._bv(bf, val)[0] * msh.fw[bf["a"]]))
+        bf = self.bface[1]
+        val, dn = self._trace(X, bf["el"], bf["a"], bf["s"], outward=True)
         Q = bf["un"] - P.z[0] * P.D[0] * dn[0]
         return float(np.sum((Q * val[1]) * msh.fw[bf["a"]]))
 
-    def objective_grad(self, x):
+    def objective_grad(self, x, kind=0):
         """(dJ/dx, dJ/dPe) of the objective."""
         msh = self.msh
+        P = self.P
+        X = self.fields(x)
+        g = np.zeros((self.m, msh.E, msh.nb))
+        if kind == 1:
+            bf = self._electrode_face()
+            a, s, el = bf["a"], bf["s"], bf["el"]
+            val, _ = self._trace(X, el, a, s, outward=True)
+            _, g_phi, g_c, _, _ = self._bv(bf, val)
+            w = msh.fw[a]
+            g[0][el] += (g_phi * w) @ msh.fphi[(a, s)]
+            r = P.bv_ion
+            for k in range(1, self.m):
+                dck = (1.0 if k == r else 0.0) if r < self.m else -P.z[k - 1] / P.z[self.m - 1]
+                if dck != 0.0:
+                    g[k][el] += (dck * g_c * w) @ msh.fphi[(a, s)]
+            return g.reshape(-1), 0.0
         bf = self.bface[1]
         a, s, el = bf["a"], bf["s"], bf["el"]
-        X = self.fields(x)
         val, dn = self._trace(X, el, a, s, outward=True)
-        P = self.P
         zD = P.z[0] * P.D[0]
         Q = bf["un"] - zD * dn[0]
         w = msh.fw[a]
-        g = np.zeros((self.m, msh.E, msh.nb))
         g[1][el] += (Q * w) @ msh.fphi[(a, s)]
         g[0][el] += (-zD * val[1] * w) @ (s * msh.fdn[(a, s)])
         dPe = float(np.sum(bf["uhn"] * val[1] * w))
         return g.reshape(-1), dPe
+
+    def objective_dbv(self, x, kind=0):
+        """Explicit derivatives (dJ/dJ0_t, dJ/dphi_app_t) of the objective at fixed x."""
+        d = self.msh.dim
+        out_j0, out_pa = np.zeros(2 * d), np.zeros(2 * d)
+        if kind == 1:
+            bf = self._electrode_face()
+            val, _ = self._trace(self.fields(x), bf["el"], bf["a"], bf["s"], outward=True)
+            _, _, _, g_j0, g_pa = self._bv(bf, val)
+            w = self.msh.fw[bf["a"]]
+            out_j0[bf["t"]] = float(np.sum(g_j0 * bf["prof"] * w))
+            out_pa[bf["t"]] = float(np.sum(g_pa * w))
+        return out_j0, out_pa

@@ -15,8 +15,8 @@ from __future__ import annotations
 import numpy as np
 import sympy as sp
 
-from workload.configs import (C_DIRICHLET, C_INFLOW, MMS_NONE, MMS_PAPER3D, MMS_TRIG2D,
-                              PHI_DIRICHLET, VEL_CONST, VEL_POISEUILLE_X, VEL_VORTEX, Config)
+from workload.configs import (C_DIRICHLET, C_ELECTRODE, C_INFLOW, J0_PARABOLIC_Z, MMS_NONE, MMS_PAPER3D,
+                              MMS_TRIG2D, PHI_DIRICHLET, VEL_CONST, VEL_POISEUILLE_X, VEL_VORTEX, Config)
 
 from .mesh import BoxMesh
 
@@ -44,6 +44,17 @@ class Problem:
         self.phi_bc = list(cfg.phi_bc[: 2 * self.dim])
         self.phi_val = list(cfg.phi_val[: 2 * self.dim])
         self.mms = cfg.mms if exact_exprs is None else -1
+        # Butler-Volmer electrodes (Sec. 2.1 Eq. bv, nondimensional form of Sec. 2.3)
+        self.bv_ion = int(cfg.bv_ion)
+        self.bv_alpha = tuple(float(a) for a in cfg.bv_alpha)
+        self.bv_j0 = [float(v) for v in cfg.bv_j0[: 2 * self.dim]]
+        self.bv_phi_app = [float(v) for v in cfg.bv_phi_app[: 2 * self.dim]]
+        self.bv_profile = int(cfg.bv_j0_profile)
+        if any(t == C_ELECTRODE for t in self.c_bc):
+            if not 1 <= self.bv_ion <= m:
+                raise ValueError("reacting ion must be one of the m ions")
+            if any(self.c_bc[t] == C_ELECTRODE and self.phi_bc[t] == PHI_DIRICHLET for t in range(2 * self.dim)):
+                raise ValueError("the potential is free on an electrode face")
         self._build_velocity()
         if self.mms != MMS_NONE:
             self._build_mms(exact_exprs)
@@ -162,3 +173,20 @@ class Problem:
 
     def is_phi_dirichlet(self, t):
         return self.phi_bc[t] == PHI_DIRICHLET
+
+    def j0_profile(self, pts):
+        """Shape of the exchange current across the box in z at points (..., d):
+        1, or the parabola of Sec. 5.2 with mean 1 over the z extent."""
+        if self.bv_profile != J0_PARABOLIC_Z or self.dim < 3:
+            return np.ones(pts.shape[:-1])
+        zc = 0.5 * (self.cfg.lo[2] + self.cfg.hi[2])
+        half = 0.5 * (self.cfg.hi[2] - self.cfg.lo[2])
+        return 0.6 * (2.0 - ((pts[..., 2] - zc) / half) ** 2)
+
+    def bv_data(self, t):
+        """(exchange current, applied potential) at the Gauss points of the
+        boundary faces with tag t (an electrode face)."""
+        msh = self.mesh
+        a, s = divmod(t, 2)
+        pts = msh.face_points(msh.bfaces[t], a, -1 if s == 0 else 1)
+        return self.bv_j0[t] * self.j0_profile(pts), np.full(pts.shape[:-1], self.bv_phi_app[t])

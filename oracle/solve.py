@@ -8,7 +8,8 @@
   Armijo test ||R(x + lam delta)|| <= (1 - 1e-4 lam) ||R(x)||, lam halved at most
   10 times; stop when ||R|| <= tol ||R_0|| or the step stalls.
 * Adjoint: J^T lam = dJ/dx by the transposed LU; gradients
-  dJ/dtheta = dJ/dtheta|_x - lam^T dR/dtheta for theta = boundary data and Pe.
+  dJ/dtheta = dJ/dtheta|_x - lam^T dR/dtheta for theta = boundary data and Pe,
+  and the exchange currents and applied potentials of electrode faces.
 * c_m recovery by electroneutrality (Eq. substitution).
 """
 from __future__ import annotations
@@ -64,14 +65,24 @@ def newton(dg: DG, x0=None, tol=1e-12, max_it=30, verbose=False):
     return x, np.array(hist)
 
 
-def adjoint(dg: DG, x):
-    """Returns (J, dJ/d(boundary data) [m-1, n_bnode], dJ/dPe, lambda)."""
+def adjoint(dg: DG, x, kind=0):
+    """Returns (J, dJ/d(boundary data) [m-1, n_bnode], dJ/dPe, lambda) of
+    objective `kind` (0: outflow flux of species 1, 1: electrode current)."""
     J = dg.jacobian(x)
-    gx, gPe = dg.objective_grad(x)
+    gx, gPe = dg.objective_grad(x, kind)
     lam = spla.splu(J.tocsc()).solve(gx, trans="T")
     dg_data = -dg.dR_dg_T(x, lam)
     dPe = gPe - float(lam @ dg.dR_dPe(x))
-    return dg.objective(x), dg_data, dPe, lam
+    return dg.objective(x, kind), dg_data, dPe, lam
+
+
+def adjoint_with_electrodes(dg: DG, x, kind=0):
+    """adjoint() plus the gradients with respect to the electrode parameters
+    (exchange current and applied potential of every box face)."""
+    J, dg_data, dPe, lam = adjoint(dg, x, kind)
+    j0, pa = dg.dR_dbv_T(x, lam)
+    ej0, epa = dg.objective_dbv(x, kind)
+    return J, dg_data, dPe, lam, ej0 - j0, epa - pa
 
 
 def recover_cm(dg: DG, x):

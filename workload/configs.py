@@ -1,7 +1,8 @@
 """Problem configurations (plain data).
 
 Box faces are tagged 0..5 = x-, x+, y-, y+, z-, z+ (tag = 2*axis + side).
-Boundary kinds for the concentrations: WALL, DIRICHLET, INFLOW, OUTFLOW;
+Boundary kinds for the concentrations: WALL, DIRICHLET, INFLOW, OUTFLOW,
+ELECTRODE (Butler-Volmer reaction of one ion, Sec. 2.1);
 for the potential: NEUMANN0, DIRICHLET.  Velocity kinds: VORTEX
 (u = Pe (sin pi x cos pi y, -cos pi x sin pi y, 0)), POISEUILLE_X
 (u_x = 6 Pe y'(H - y')/H^2 with y' = y - y_lo and H the box height in y) and
@@ -15,7 +16,8 @@ from __future__ import annotations
 from dataclasses import dataclass, field, replace
 from typing import Tuple
 
-C_WALL, C_DIRICHLET, C_INFLOW, C_OUTFLOW = 0, 1, 2, 3
+C_WALL, C_DIRICHLET, C_INFLOW, C_OUTFLOW, C_ELECTRODE = 0, 1, 2, 3, 4
+J0_CONST, J0_PARABOLIC_Z = 0, 1
 PHI_NEUMANN0, PHI_DIRICHLET = 0, 1
 VEL_VORTEX, VEL_POISEUILLE_X, VEL_CONST = 0, 1, 2
 MMS_NONE, MMS_TRIG2D, MMS_PAPER3D = 0, 1, 2
@@ -42,6 +44,15 @@ class Config:
     vel_param: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     newton_tol: float = 1e-8
     note: str = ""
+    # Butler-Volmer electrodes (faces tagged C_ELECTRODE): reacting ion (1..m,
+    # the oxidant; m is the eliminated ion), anodic / cathodic exponents
+    # (alpha_a n, alpha_c n), exchange current and applied potential per box
+    # face (nondimensional), and the exchange-current profile across z
+    bv_ion: int = 1
+    bv_alpha: Tuple[float, float] = (1.0, 1.0)
+    bv_j0: Tuple[float, ...] = (0.0,) * 6
+    bv_phi_app: Tuple[float, ...] = (0.0,) * 6
+    bv_j0_profile: int = J0_CONST
 
     @property
     def m(self) -> int:
@@ -88,6 +99,19 @@ CONFIGS["cfg2s"] = CONFIGS["cfg2"].with_(name="cfg2s", n=(8, 8, 8), note="cfg2 p
 CONFIGS["cfg2t"] = CONFIGS["cfg2"].with_(name="cfg2t", n=(4, 4, 4), note="cfg2 physics on 4^3")
 CONFIGS["cfg3s"] = CONFIGS["cfg3"].with_(name="cfg3s", n=(8, 4, 2), hi=(1.0, 0.5, 0.25),
                                          note="channel physics on 8x4x2")
+
+# Channel with Butler-Volmer electrodes (the paper's flow-plate reactor, Sec. 5.2):
+# y = 0 anode (applied potential 0) and y = y_max cathode (applied potential
+# 0.03 V, i.e. 0.03 F/RT = 1.1676 nondimensional), alpha_1 = alpha_2 = 0.5 and
+# n = 2 (exponents alpha n = 1), the exchange current with the paper's parabolic
+# profile across z; the reacting ion is the doubly charged cation (ion 3,
+# eliminated by electroneutrality); the potential is free (natural) on the
+# electrodes, where the Butler-Volmer current fixes it.
+_BV = dict(c_bc=(C_INFLOW, C_OUTFLOW, C_ELECTRODE, C_ELECTRODE, 0, 0), phi_bc=(0,) * 6,
+           phi_val=(0.0,) * 6, bv_ion=3, bv_alpha=(1.0, 1.0), bv_j0=(0.0, 0.0, 1.0, 1.0, 0.0, 0.0),
+           bv_phi_app=(0.0, 0.0, 0.0, 1.1676, 0.0, 0.0), bv_j0_profile=J0_PARABOLIC_Z)
+CONFIGS["bv3s"] = CONFIGS["cfg3s"].with_(name="bv3s", note="BV channel 8x4x2 p=3", **_BV)
+CONFIGS["bv3"] = CONFIGS["cfg3"].with_(name="bv3", note="BV channel 64x16x8 p=3", **_BV)
 
 ADJOINT_SEED = 4
 N_ADJOINT_PARAMS = 64
