@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the FP64, adjoint, large-apply and channel-solve legs")
     ap.add_argument("--only-apply", action="store_true", help="run only the large Jacobian-apply leg")
+    ap.add_argument("--apply-variants", default="",
+                    help="comma-separated launch variants of the Jacobian apply to time (A/B), then exit")
     return ap.parse_args()
 
 
@@ -299,6 +301,14 @@ def main():
     torch.cuda.set_device(0)
     if args.only_apply:
         print(json.dumps({"jacobian_apply": apply_bandwidth(args.apply_workload)}), flush=True)
+        return
+    if args.apply_variants:
+        res = {}
+        for wl in args.apply_workload.split(","):
+            for var in args.apply_variants.split(","):
+                os.environ["DGNP_JAC_VARIANT"] = var
+                res[f"{wl}:{var}"] = apply_bandwidth(wl)
+        print(json.dumps({"jacobian_apply_variants": res}), flush=True)
         return
     cfg = get_config(args.workload)
     prob = Problem(cfg, boundary_data(cfg))

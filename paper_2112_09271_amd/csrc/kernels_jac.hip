@@ -15,16 +15,17 @@
 // every velocity kind (u_d = Pe alpha_d(x) beta_d(y)), so each element
 // evaluates them at its 1-D point sets once instead of at every point.
 //
-// Several elements share a work-group (EPB of them, consecutive in the
-// lexicographic order, so most x-neighbours of the face terms are in LDS);
-// every phase loops over all (element, item) pairs of the group, which keeps
-// the lanes busy in the small per-element contractions.  Phases: sum-factorised
+// A work-group holds EPB elements (consecutive in the lexicographic order, so
+// x-neighbours of the face terms inside the group are read from LDS); every
+// phase loops over all (element, item) pairs of the group.  Phases: sum-factorised
 // interpolation of v (x, y, z lines), pointwise linearised volume flux,
 // transposed contractions (z, y, x), then the 6 faces element-centric: node
 // traces of own and neighbour element, tangential interpolation to the face
 // Gauss points, linearised numerical flux, tangential transposes, accumulation
 // into the own element.  Every output entry has one writer: no atomics, and
 // results are bitwise reproducible.
+#include <cstdlib>
+
 #include "dg_device.hpp"
 #include "kernels_jac.hpp"
 
@@ -32,12 +33,20 @@ namespace dgnp {
 
 void upload_ref_tables_jac(const RefTables* tabs, int count) { upload_ref_tables_tu(tabs, count); }
 
-// elements per work-group: about 50 KB of LDS per group (three groups per CU)
+// Launch shape: elements per work-group and threads.  The kernel is bound by
+// the latency of its phases (barrier, LDS round trip, table loads), so the
+// number of resident work-groups matters more than busy lanes: measured on the
+// 12.6M-DOF channel (p = 3) one element per group is fastest (FP32: 431 us with
+// 128 threads against 733 us with four elements and 256; FP64: 813 us with one
+// element and 256 threads against 1590 us with two and 128); on the 16^3 cube
+// (p = 2) one element and 64 threads (FP32, 20.8 us) and two elements and 256
+// threads (FP64, 33.4 us).
 template <int P, typename T>
-struct Epb {
-  static constexpr int v = (P == 1 ? 12 : (P == 2 ? 6 : 4)) / (sizeof(T) == 8 ? 2 : 1);
+struct Shape {
+  static constexpr bool F64 = sizeof(T) == 8;
+  static constexpr int epb = P == 3 ? 1 : (P == 2 ? (F64 ? 2 : 1) : (F64 ? 2 : 4));
+  static constexpr int nt = P == 3 ? (F64 ? 256 : 128) : (P == 2 ? (F64 ? 256 : 64) : 256);
 };
-static constexpr int JT_NT = 256;
 
 // ---------------------------------------------------------------------------
 // state tables, computed in double from the double state
@@ -101,12 +110,11 @@ __global__ void __launch_bounds__(128) k_jlin_tab(KArgs A, const double* __restr
 // CPL = true: potential rows of J v for an input whose potential part is zero,
 // written as jbase - (J v) when jbase is set (the concentrations of v are read,
 // its potential is not).
-template <int P, int MF, typename T, bool CPL, int EPB>
-__global__ void __launch_bounds__(JT_NT) k_jlin(KArgs A, const T* __restrict__ vin, const T* __restrict__ tv,
+template <int P, int MF, typename T, bool CPL, int EPB, int NT>
+__global__ void __launch_bounds__(NT) k_jlin(KArgs A, const T* __restrict__ vin, const T* __restrict__ tv,
                                                 const T* __restrict__ tf, T* __restrict__ out, int64_t gper) {
   using S = Sz<3, P>;
   constexpr int NN = S::NN, NQ = S::NQ, NB = S::NB, NQV = S::NQV, NFN = S::NFN, NQF = S::NQF;
-  constexpr int NT = JT_NT;
   constexpr int MI = CPL ? MF - 1 : MF;  // input fields held
   constexpr int FI0 = CPL ? 1 : 0;       // field of the first one
   constexpr int MO = CPL ? 1 : MF;       // output fields formed (from field 0 on)
@@ -584,14 +592,35 @@ void launch_jlin_tables(int p, int m, const KArgs& A, const double* xs, T* tv, T
   throw Error(DGNP_E_ARG, "tabulated Jacobian: orders 1..3, 2 or 3 ions");
 }
 
-template <int P, int MF, typename T, bool CPL>
-static void jl_t(const KArgs& A, const T* v, const T* tv, const T* tf, T* y, hipStream_t s) {
-  constexpr int EPB = Epb<P, T>::v;
+template <int P, int MF, typename T, bool CPL, int EPB, int NT>
+static void jl_v(const KArgs& A, const T* v, const T* tv, const T* tf, T* y, hipStream_t s) {
   const int64_t groups = (A.E + EPB - 1) / EPB;
   const int64_t gper = (groups + 7) / 8;
-  hipLaunchKernelGGL((k_jlin<P, MF, T, CPL, EPB>), dim3(unsigned(8 * gper)), dim3(JT_NT), 0, s, A, v, tv, tf, y,
+  hipLaunchKernelGGL((k_jlin<P, MF, T, CPL, EPB, NT>), dim3(unsigned(8 * gper)), dim3(NT), 0, s, A, v, tv, tf, y,
                      gper);
   DGNP_HIP(hipGetLastError());
+}
+
+// launch shape (elements per work-group x threads): the default, or for order 3
+// a variant chosen by the value of DGNP_JAC_VARIANT (A/B measurement)
+static int jl_variant() {
+  const char* e = getenv("DGNP_JAC_VARIANT");
+  return e ? atoi(e) : 0;
+}
+
+template <int P, int MF, typename T, bool CPL>
+static void jl_t(const KArgs& A, const T* v, const T* tv, const T* tf, T* y, hipStream_t s) {
+  if constexpr (P >= 2) {
+    switch (jl_variant()) {  // elements per work-group * 1000 + threads
+      case 1064: return jl_v<P, MF, T, CPL, 1, 64>(A, v, tv, tf, y, s);
+      case 1128: return jl_v<P, MF, T, CPL, 1, 128>(A, v, tv, tf, y, s);
+      case 1256: return jl_v<P, MF, T, CPL, 1, 256>(A, v, tv, tf, y, s);
+      case 2128: return jl_v<P, MF, T, CPL, 2, 128>(A, v, tv, tf, y, s);
+      case 2256: return jl_v<P, MF, T, CPL, 2, 256>(A, v, tv, tf, y, s);
+      default: break;
+    }
+  }
+  jl_v<P, MF, T, CPL, Shape<P, T>::epb, Shape<P, T>::nt>(A, v, tv, tf, y, s);
 }
 
 template <typename T>
