@@ -271,6 +271,18 @@ int dgnp_adjoint(dgnp_ctx *ctx, const double *x, int32_t objective, double *dJ_d
  * objective must be 0.  Synchronises. */
 int dgnp_objective(dgnp_ctx *ctx, const double *x, int32_t objective, double *J_out);
 
+/* Allocation-free form of dgnp_objective, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): J(x) at x (device double [N]) into J_dev (a
+ * caller-owned device double [1]), stream-ordered on `stream`, with no
+ * synchronisation and no allocation.  Its per-element partial sums live in a
+ * static device array of the library (2^19 doubles, 4 MiB, held on each GPU
+ * the library runs on until the process ends), so problems of at most 2^18 =
+ * 262,144 elements are accepted (DGNP_E_ARG beyond).  Every call on one GPU
+ * shares that array: calls that overlap in time on one GPU race.  objective
+ * must be 0. */
+int dgnp_objective_noalloc(dgnp_ctx *ctx, const double *x, int32_t objective, double *J_dev, void *stream);
+
 /* Copies the assembled block (field f, element e, slot s: 0 = diagonal,
  * 1 + j = coupling to neighbour slot j) of the last set_state into host
  * double [n_b][n_b] (row = test function).  For tests and diagnostics. */

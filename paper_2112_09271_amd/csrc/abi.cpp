@@ -224,6 +224,7 @@ int dgnp_setup(const dgnp_mesh* mesh, int32_t order, const dgnp_species* sp, con
       upload_ref_tables_jac(all, 3);
     }
     c->jac_tab = getenv("DGNP_JAC_GENERAL") == nullptr;
+    c->obj_scratch = objective_scratch_init();
     build_tables(*c);
     if (opt && opt->src_vol) {
       c->src_vol.assign(opt->src_vol, opt->src_vol + size_t(c->m) * c->E * c->nqv);
@@ -404,6 +405,14 @@ int dgnp_objective(dgnp_ctx* c, const double* x, int32_t objective, double* J_ou
     AllocScope as(c->allocator);
     DGNP_REQUIRE(objective == 0, DGNP_E_ARG, "objective 0 (outflow flux of species 1) is the only one");
     *J_out = objective_value(*c, x);
+  });
+}
+
+int dgnp_objective_noalloc(dgnp_ctx* c, const double* x, int32_t objective, double* J_dev, void* stream) {
+  return guard([&] {
+    DGNP_REQUIRE(c && x && J_dev, DGNP_E_ARG, "NULL argument");
+    DGNP_REQUIRE(objective == 0, DGNP_E_ARG, "objective 0 (outflow flux of species 1) is the only one");
+    objective_noalloc(c->dim, c->p, c->m, c->kargs(), x, c->obj_scratch, J_dev, static_cast<hipStream_t>(stream));
   });
 }
 

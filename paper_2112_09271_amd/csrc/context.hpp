@@ -41,6 +41,7 @@ struct dgnp_ctx {
   dgnp::DevBuf<double> d_bcq;    // [m][n_bface][nqf]
   dgnp::DevBuf<double> d_src;    // [m][E][nqv] (manufactured solutions only)
   dgnp::DevBuf<double> d_aux;    // objective partial sums etc.
+  double* obj_scratch = nullptr;  // static partial-sum array of the allocation-free objective (this device)
 
   // linearisation point
   dgnp::DevBuf<double> d_x;

@@ -174,5 +174,12 @@ enum Mode { M_RES = 0, M_JAC = 1, M_JACT = 2, M_DPE = 3, M_OBJG = 4, M_DATAT = 5
 void launch_dg(int dim, int p, int m, bool f32, int mode, const KArgs& A, const void* xs,
                const void* vin, void* out, double* aux, hipStream_t s);
 void upload_ref_tables(const RefTables* tabs, int count);
+// allocation-free objective value (kernels_dg.hip): the address of the static
+// partial-sum array on the current device (looked up once per device), the
+// largest element count it holds, and J(x) into J_dev (device double [1])
+double* objective_scratch_init();
+int64_t objective_scratch_max_elements();
+void objective_noalloc(int dim, int p, int m, const KArgs& A, const double* x, double* scratch_dev, double* J_dev,
+                       hipStream_t s);
 
 }  // namespace dgnp

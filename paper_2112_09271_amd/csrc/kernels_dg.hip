@@ -12,6 +12,8 @@
 // element only.  Each face flux is therefore evaluated by both of its
 // elements, but every output entry has exactly one writer: no atomics, and
 // results are bitwise reproducible.
+#include <mutex>
+
 #include "dg_device.hpp"
 
 namespace dgnp {
@@ -387,6 +389,7 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
       aux[2 * e + 0] = sj;
       aux[2 * e + 1] = sp;
     }
+    if (out == nullptr) return;  // the value alone (no gradient)
   }
   if constexpr (MODE == M_DATAT) return;
   // F5: both tangential transposes of one coefficient row in registers
@@ -460,6 +463,57 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
       out[f * Nf + e * NB + node] = acc;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free objective value: the per-element partial sums of the
+// objective kernel go to a static device array instead of library or caller
+// workspace; one work-group then adds them in a fixed order.  The array is
+// shared by every call on one GPU (calls that overlap on a GPU race) and
+// needs no clearing: the objective kernel writes the two partials of every
+// element before the sum reads them.
+static constexpr int64_t OBJ_SCRATCH_ELEMS = int64_t(1) << 18;
+static __device__ __align__(256) double scratch[2 * OBJ_SCRATCH_ELEMS];
+
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[64] = {};  // the array's address on each device
+
+double* objective_scratch_init() {
+  int dev = 0;
+  DGNP_HIP(hipGetDevice(&dev));
+  DGNP_REQUIRE(dev >= 0 && dev < 64, DGNP_E_ARG, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    DGNP_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_dev[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch_dev[dev];
+}
+
+int64_t objective_scratch_max_elements() { return OBJ_SCRATCH_ELEMS; }
+
+__global__ void __launch_bounds__(256) k_obj_sum(const double* __restrict__ part, int64_t E, double* __restrict__ J) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < E; e += 256) acc += part[2 * e];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) J[0] = sh[0];
+}
+
+void objective_noalloc(int dim, int p, int m, const KArgs& A, const double* x, double* scratch_dev, double* J_dev,
+                       hipStream_t s) {
+  DGNP_REQUIRE(A.E <= OBJ_SCRATCH_ELEMS, DGNP_E_ARG,
+               "allocation-free objective: at most 262144 elements (2^18) per problem");
+  DGNP_REQUIRE(scratch_dev, DGNP_E_STATE, "allocation-free objective: scratch not set up on this device");
+  launch_dg(dim, p, m, false, M_OBJG, A, x, nullptr, nullptr, scratch_dev, s);
+  hipLaunchKernelGGL(k_obj_sum, dim3(1), dim3(256), 0, s, scratch_dev, A.E, J_dev);
+  DGNP_HIP(hipGetLastError());
 }
 
 template <int DIM, int P, int MF, typename T, int MODE>

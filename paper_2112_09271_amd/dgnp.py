@@ -115,6 +115,7 @@ _SIGS = {
     "dgnp_adjoint": [_vp, _vp, C.c_int32, _vp, _vp, _vp, _vp, C.POINTER(dgnp_solve_opts),
                      C.POINTER(dgnp_solve_stats)],
     "dgnp_objective": [_vp, _vp, C.c_int32, _vp],
+    "dgnp_objective_noalloc": [_vp, _vp, C.c_int32, _vp, _vp],
     "dgnp_get_block": [_vp, C.c_int32, C.c_int64, C.c_int32, _vp],
     "dgnp_profile": [_vp, C.c_int32],
     "dgnp_timer": [_vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32],
@@ -198,6 +199,10 @@ def dgnp_adjoint(ctx, x_ptr, objective, dJ_dbc, dJ_dPe, J_out, lam_ptr, opts=Non
     _check(lib().dgnp_adjoint(ctx, x_ptr, objective, dJ_dbc, dJ_dPe, J_out, lam_ptr,
                               C.byref(opts) if opts is not None else None,
                               C.byref(stats) if stats is not None else None))
+
+
+def dgnp_objective_noalloc(ctx, x_ptr, objective, J_dev_ptr, stream=None):
+    _check(lib().dgnp_objective_noalloc(ctx, x_ptr, objective, J_dev_ptr, stream))
 
 
 def dgnp_destroy(ctx):
