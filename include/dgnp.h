@@ -60,7 +60,16 @@ enum { DGNP_F64 = 0, DGNP_F32 = 1 };
  * dgnp_jacobian_apply and builds no preconditioner at all. */
 enum { DGNP_STATE_ASSEMBLE_ONLY = 0x100, DGNP_STATE_APPLY_ONLY = 0x200 };
 /* boundary kinds per box face, faces tagged 0..5 = x-, x+, y-, y+, z-, z+ */
-enum { DGNP_C_WALL = 0, DGNP_C_DIRICHLET = 1, DGNP_C_INFLOW = 2, DGNP_C_OUTFLOW = 3 };
+enum { DGNP_C_WALL = 0, DGNP_C_DIRICHLET = 1, DGNP_C_INFLOW = 2, DGNP_C_OUTFLOW = 3, DGNP_C_ELECTRODE = 4 };
+/* exchange-current profile of electrode faces across the box in z: constant,
+ * or the parabola of Sec. 5.2, 0.6 (2 - ((z - z_mid) / (w / 2))^2) with mean 1
+ * over the box's z extent w (3-D only) */
+enum { DGNP_J0_CONST = 0, DGNP_J0_PARABOLIC_Z = 1 };
+/* objectives of dgnp_objective / dgnp_adjoint: 0 the outflow flux of species 1
+ * through the x = x_max face; 1 the reaction rate g of the reacting ion
+ * integrated over the first electrode face (the electrode's current over its
+ * valence) */
+enum { DGNP_OBJ_OUTFLOW = 0, DGNP_OBJ_ELECTRODE = 1 };
 enum { DGNP_PHI_NEUMANN0 = 0, DGNP_PHI_DIRICHLET = 1 };
 /* velocity u = Pe * u_hat(x):
  *   VORTEX        u_hat = (sin(pi x) cos(pi y), -cos(pi x) sin(pi y), 0)
@@ -97,6 +106,23 @@ typedef struct {
   double Pe;          /* velocity scale */
   double param[3];    /* CONST direction */
 } dgnp_velocity;
+
+/* Butler-Volmer electrodes (Sec. 2.1 Eqs. electrode and bv, nondimensional
+ * form of Sec. 2.3): on a face tagged DGNP_C_ELECTRODE the reacting ion r, the
+ * oxidant of a one-step redox reaction whose reductant has constant
+ * concentration (the electrode metal, Sec. 5.2), reacts at the rate
+ *   g = J0 [exp(alpha_a (phi_app - phi)) - c_r exp(-alpha_c (phi_app - phi))]
+ * (gamma = 1; alpha_a, alpha_c are the products alpha n); g enters the
+ * equation of ion r as -int g v (when r < m) and the charge equation as
+ * -int z_r g v.  The potential is free on electrode faces (phi_bc must be
+ * DGNP_PHI_NEUMANN0 there); the velocity is expected tangential. */
+typedef struct {
+  int32_t ion;            /* reacting ion, 1..m (m: the eliminated one) */
+  double alpha_a, alpha_c;
+  double j0[6];           /* exchange current per box face (amplitude of the profile) */
+  double phi_app[6];      /* applied potential per box face */
+  int32_t j0_profile;     /* DGNP_J0_* */
+} dgnp_electrode;
 
 typedef struct {
   double c_ip;             /* interior-penalty constant C_IP (paper: 10) */
@@ -142,6 +168,7 @@ typedef struct {
   void *(*alloc)(size_t bytes, void *alloc_ctx);
   void (*free_)(void *ptr, void *alloc_ctx);
   void *alloc_ctx;
+  const dgnp_electrode *electrode;  /* required when a face is DGNP_C_ELECTRODE, else NULL */
 } dgnp_options;
 enum { DGNP_PHIMG_AUTO = 0, DGNP_PHIMG_Q1 = 1, DGNP_PHIMG_P = 2, DGNP_PHIMG_PG = 3 };
 
@@ -183,6 +210,11 @@ int dgnp_setup(const dgnp_mesh *mesh, int32_t order, const dgnp_species *sp,
  * be NULL to keep them) and the velocity scale Pe.  Invalidates the
  * linearisation point.  DGNP_E_ARG with a manufactured solution. */
 int dgnp_set_params(dgnp_ctx *ctx, const double *bc_conc, double Pe);
+
+/* Replaces the exchange currents and applied potentials of the electrode
+ * faces (the other fields of e must equal those given at setup).  Invalidates
+ * the linearisation point.  DGNP_E_ARG without electrode faces. */
+int dgnp_set_electrode(dgnp_ctx *ctx, const dgnp_electrode *e);
 
 /* Sizes: E elements, N_f = E * n_b DOFs per field, m fields, n_bnode nodal
  * boundary-data entries per concentration.  Any pointer may be NULL. */
@@ -255,9 +287,10 @@ int dgnp_precond_apply(dgnp_ctx *ctx, const void *r, void *z, int32_t prec,
  * stats may be NULL.  Synchronises.  DGNP_E_NOCONV if max_newton is reached. */
 int dgnp_solve(dgnp_ctx *ctx, double *x, const dgnp_solve_opts *opts, dgnp_solve_stats *stats);
 
-/* Adjoint of the outflow-flux objective J = int_{x = x_max} (q_1 . n) c_1 ds
- * (objective = 0, the only one defined) at the converged state x (device
- * double [N]): solves J(x)^T lambda = dJ/dx with FGMRES using the transposed
+/* Adjoint of objective J (DGNP_OBJ_*: 0 the outflow flux
+ * int_{x = x_max} (q_1 . n) c_1 ds, 1 the first electrode's reaction rate)
+ * at the converged state x (device double [N]): solves
+ * J(x)^T lambda = dJ/dx with FGMRES using the transposed
  * Jacobian apply and the transposed preconditioner, then
  *   dJ/d(bc data) = -lambda^T dR/d(bc data)      host double [m-1][n_bnode]
  *   dJ/dPe        = dJ/dPe|_x - lambda^T dR/dPe   host double [1]
@@ -267,8 +300,17 @@ int dgnp_adjoint(dgnp_ctx *ctx, const double *x, int32_t objective, double *dJ_d
                  double *dJ_dPe, double *J_out, double *lambda, const dgnp_solve_opts *opts,
                  dgnp_solve_stats *stats);
 
-/* J(x) = int_{x = x_max} (q_1 . n) c_1 ds at x (device double [N]); host J_out.
- * objective must be 0.  Synchronises. */
+/* Gradient of objective `objective` with respect to the exchange currents
+ * and applied potentials of the electrode faces, from the adjoint solution
+ * lambda of that objective at x (both device double [N], lambda from
+ * dgnp_adjoint): dJ/dtheta = dJ/dtheta|_x - lambda^T dR/dtheta, host double
+ * [6] each (zero on faces without an electrode).  Synchronises. */
+int dgnp_electrode_gradient(dgnp_ctx *ctx, const double *x, int32_t objective, const double *lambda,
+                            double *dJ_dj0, double *dJ_dphi_app);
+
+/* J(x) at x (device double [N]) into host J_out: objective 0 =
+ * int_{x = x_max} (q_1 . n) c_1 ds, objective 1 = the reaction rate integrated
+ * over the first electrode face (DGNP_OBJ_*).  Synchronises. */
 int dgnp_objective(dgnp_ctx *ctx, const double *x, int32_t objective, double *J_out);
 
 /* Allocation-free form of dgnp_objective, for callers that cannot allocate
@@ -276,11 +318,11 @@ int dgnp_objective(dgnp_ctx *ctx, const double *x, int32_t objective, double *J_
  * that forbid hipMalloc): J(x) at x (device double [N]) into J_dev (a
  * caller-owned device double [1]), stream-ordered on `stream`, with no
  * synchronisation and no allocation.  Its per-element partial sums live in a
- * static device array of the library (2^19 doubles, 4 MiB, held on each GPU
+ * static device array of the library (2^20 doubles, 8 MiB, held on each GPU
  * the library runs on until the process ends), so problems of at most 2^18 =
  * 262,144 elements are accepted (DGNP_E_ARG beyond).  Every call on one GPU
- * shares that array: calls that overlap in time on one GPU race.  objective
- * must be 0. */
+ * shares that array: calls that overlap in time on one GPU race.  objective:
+ * DGNP_OBJ_*. */
 int dgnp_objective_noalloc(dgnp_ctx *ctx, const double *x, int32_t objective, double *J_dev, void *stream);
 
 /* Copies the assembled block (field f, element e, slot s: 0 = diagonal,

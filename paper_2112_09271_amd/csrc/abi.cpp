@@ -66,9 +66,28 @@ dgnp::KArgs dgnp_ctx::kargs() const {
   A.bcq = d_bcq.p;
   A.src = d_src.p;
   A.objective_tag = 1;
+  A.objective_kind = 0;
+  A.bv_r = bv_ion;
+  A.bv_z = has_electrode ? z[bv_ion - 1] : 0.0;
+  A.bv_aa = bv_aa;
+  A.bv_ac = bv_ac;
+  for (int k = 0; k < 4; ++k) A.bv_dc[k] = 0.0;
+  for (int k = 1; k < m; ++k)
+    A.bv_dc[k - 1] = bv_ion < m ? (k == bv_ion ? 1.0 : 0.0) : -z[k - 1] / z[m - 1];
+  A.bv_prof = dim == 3 ? bv_prof : 0;
+  A.bv_zc = 0.5 * (lo[2] + hi[2]);
+  A.bv_zhalf = 0.5 * (hi[2] - lo[2]);
   A.vin_mask = ~0u;
   A.jbase = nullptr;
   return A;
+}
+
+// shape of the exchange current of electrode faces across the box in z
+// (DGNP_J0_PARABOLIC_Z: the parabola of Sec. 5.2 with mean 1)
+static double j0_profile(const dgnp_ctx& c, double z) {
+  if (c.bv_prof != DGNP_J0_PARABOLIC_Z || c.dim < 3) return 1.0;
+  const double t = (z - 0.5 * (c.lo[2] + c.hi[2])) / (0.5 * (c.hi[2] - c.lo[2]));
+  return 0.6 * (2.0 - t * t);
 }
 
 // boundary data at the face Gauss points, [m][n_bface][nqf]
@@ -87,6 +106,7 @@ static void build_boundary_data(dgnp_ctx& c) {
     const int t2 = d == 3 ? (a == 2 ? 1 : 2) : 0;
     const bool phid = c.phi_bc[t] == DGNP_PHI_DIRICHLET;
     const bool cdat = c.c_bc[t] == DGNP_C_DIRICHLET || c.c_bc[t] == DGNP_C_INFLOW;
+    const bool elec = c.c_bc[t] == DGNP_C_ELECTRODE;
     int64_t lin = 0;
     for (int64_t e = 0; e < c.E; ++e) {
       int id[3] = {int(e % c.n[0]), int((e / c.n[0]) % c.n[1]), d == 3 ? int(e / stride2) : 0};
@@ -101,6 +121,10 @@ static void build_boundary_data(dgnp_ctx& c) {
         double ph = 0.0, c1 = 0.0;
         if (c.mms) mms_exact(c, x, &ph, &c1);
         if (phid) bcq[(0 * c.n_bface + bf) * c.nqf + qf] = c.mms ? ph : c.phi_val[t];
+        if (elec) {  // applied potential, and the exchange current at the point
+          bcq[(0 * c.n_bface + bf) * c.nqf + qf] = c.bv_phi_app[t];
+          bcq[(1 * c.n_bface + bf) * c.nqf + qf] = c.bv_j0[t] * j0_profile(c, x[2]);
+        }
         if (cdat) {
           for (int k = 1; k < c.m; ++k) {
             double g = 0.0;
@@ -212,8 +236,40 @@ int dgnp_setup(const dgnp_mesh* mesh, int32_t order, const dgnp_species* sp, con
       c->c_bc[t] = t < 2 * c->dim ? mesh->c_bc[t] : 0;
       c->phi_bc[t] = t < 2 * c->dim ? mesh->phi_bc[t] : 0;
       c->phi_val[t] = t < 2 * c->dim ? mesh->phi_val[t] : 0.0;
-      DGNP_REQUIRE(c->c_bc[t] >= 0 && c->c_bc[t] <= 3, DGNP_E_ARG, "unknown concentration boundary kind");
+      DGNP_REQUIRE(c->c_bc[t] >= 0 && c->c_bc[t] <= 4, DGNP_E_ARG, "unknown concentration boundary kind");
       DGNP_REQUIRE(c->phi_bc[t] >= 0 && c->phi_bc[t] <= 1, DGNP_E_ARG, "unknown potential boundary kind");
+      if (c->c_bc[t] == DGNP_C_ELECTRODE) {
+        c->has_electrode = true;
+        DGNP_REQUIRE(c->phi_bc[t] == DGNP_PHI_NEUMANN0, DGNP_E_ARG, "the potential is free on an electrode face");
+      }
+    }
+    if (c->has_electrode) {
+      DGNP_REQUIRE(opt && opt->electrode, DGNP_E_ARG, "electrode faces need dgnp_options.electrode");
+      const dgnp_electrode& el = *opt->electrode;
+      DGNP_REQUIRE(el.ion >= 1 && el.ion <= c->m, DGNP_E_ARG, "reacting ion must be 1..m");
+      DGNP_REQUIRE(el.j0_profile == DGNP_J0_CONST || el.j0_profile == DGNP_J0_PARABOLIC_Z, DGNP_E_ARG,
+                   "unknown exchange-current profile");
+      DGNP_REQUIRE(std::isfinite(el.alpha_a) && std::isfinite(el.alpha_c), DGNP_E_NONFINITE, "non-finite exponents");
+      c->bv_ion = el.ion;
+      c->bv_aa = el.alpha_a;
+      c->bv_ac = el.alpha_c;
+      c->bv_prof = el.j0_profile;
+      for (int t = 0; t < 6; ++t) {
+        DGNP_REQUIRE(std::isfinite(el.j0[t]) && std::isfinite(el.phi_app[t]), DGNP_E_NONFINITE,
+                     "non-finite electrode data");
+        c->bv_j0[t] = el.j0[t];
+        c->bv_phi_app[t] = el.phi_app[t];
+      }
+    }
+    // the potential enters the residual through its gradient only, except on
+    // potential-Dirichlet faces and in the Butler-Volmer rate of electrode
+    // faces: without either it is fixed only up to a constant
+    {
+      bool fixed = false;
+      for (int t = 0; t < 2 * c->dim; ++t)
+        fixed = fixed || c->phi_bc[t] == DGNP_PHI_DIRICHLET || c->c_bc[t] == DGNP_C_ELECTRODE;
+      DGNP_REQUIRE(fixed, DGNP_E_ARG,
+                   "the potential is not fixed: no potential-Dirichlet or electrode face (singular problem)");
     }
     c->stream = static_cast<hipStream_t>(stream);
     DGNP_HIP(hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking));
@@ -231,6 +287,7 @@ int dgnp_setup(const dgnp_mesh* mesh, int32_t order, const dgnp_species* sp, con
       for (double v : c->src_vol) DGNP_REQUIRE(std::isfinite(v), DGNP_E_NONFINITE, "non-finite volume sources");
     }
     if (opt && opt->dir_face) {
+      DGNP_REQUIRE(!c->has_electrode, DGNP_E_ARG, "caller face data and electrode faces cannot be combined");
       c->dir_face.assign(opt->dir_face, opt->dir_face + size_t(c->m) * c->n_bface * c->nqf);
       for (double v : c->dir_face) DGNP_REQUIRE(std::isfinite(v), DGNP_E_NONFINITE, "non-finite boundary data");
     } else if (c->mms == 0 && c->n_bnode > 0) {
@@ -240,7 +297,7 @@ int dgnp_setup(const dgnp_mesh* mesh, int32_t order, const dgnp_species* sp, con
     }
     c->d_nbr.upload(c->nbr, c->stream);
     build_boundary_data(*c);
-    c->d_aux.alloc(size_t(std::max<int64_t>(2 * c->E, c->m * c->n_bface * c->nqf)));
+    c->d_aux.alloc(size_t(std::max<int64_t>(4 * c->E, c->m * c->n_bface * c->nqf)));
     precond_symbolic(*c);
     DGNP_HIP(hipStreamSynchronize(c->stream));
     *out = c.release();
@@ -260,6 +317,28 @@ int dgnp_set_params(dgnp_ctx* c, const double* bc_conc, double Pe) {
       c->bc_conc.assign(bc_conc, bc_conc + size_t(c->m - 1) * c->n_bnode);
     }
     c->vel.Pe = Pe;
+    DGNP_HIP(hipDeviceSynchronize());
+    build_boundary_data(*c);
+    c->has_state = c->has_state32 = false;
+    precond_invalidate(*c);
+  });
+}
+
+int dgnp_set_electrode(dgnp_ctx* c, const dgnp_electrode* e) {
+  return guard([&] {
+    DGNP_REQUIRE(c && e, DGNP_E_ARG, "NULL argument");
+    DGNP_REQUIRE(c->has_electrode, DGNP_E_ARG, "the problem has no electrode faces");
+    DGNP_REQUIRE(e->ion == c->bv_ion && e->alpha_a == c->bv_aa && e->alpha_c == c->bv_ac &&
+                     e->j0_profile == c->bv_prof,
+                 DGNP_E_ARG, "only the exchange currents and applied potentials can change");
+    for (int t = 0; t < 6; ++t)
+      DGNP_REQUIRE(std::isfinite(e->j0[t]) && std::isfinite(e->phi_app[t]), DGNP_E_NONFINITE,
+                   "non-finite electrode data");
+    AllocScope as(c->allocator);
+    for (int t = 0; t < 6; ++t) {
+      c->bv_j0[t] = e->j0[t];
+      c->bv_phi_app[t] = e->phi_app[t];
+    }
     DGNP_HIP(hipDeviceSynchronize());
     build_boundary_data(*c);
     c->has_state = c->has_state32 = false;
@@ -386,14 +465,14 @@ int dgnp_adjoint(dgnp_ctx* c, const double* x, int32_t objective, double* dJ_dbc
   return guard([&] {
     DGNP_REQUIRE(c && x, DGNP_E_ARG, "NULL argument");
     AllocScope as(c->allocator);
-    DGNP_REQUIRE(objective == 0, DGNP_E_ARG, "objective 0 (outflow flux of species 1) is the only one");
+    DGNP_REQUIRE(objective == 0 || objective == 1, DGNP_E_ARG, "objective must be 0 or 1");
     DGNP_REQUIRE(!dJ_dbc || c->dir_face.empty(), DGNP_E_ARG,
                  "no boundary-data gradient with caller face data (dir_face): pass dJ_dbc = NULL");
     dgnp_solve_opts o = default_solve_opts();
     if (opts) o = *opts;
     dgnp_solve_stats st{};
     DGNP_HIP(hipDeviceSynchronize());
-    int code = adjoint_solve(*c, x, dJ_dbc, dJ_dPe, J_out, lambda, o, st);
+    int code = adjoint_solve(*c, x, objective, dJ_dbc, dJ_dPe, J_out, lambda, o, st);
     if (stats) *stats = st;
     if (code != DGNP_OK) throw Error(code, "adjoint solve failed");
   });
@@ -403,16 +482,27 @@ int dgnp_objective(dgnp_ctx* c, const double* x, int32_t objective, double* J_ou
   return guard([&] {
     DGNP_REQUIRE(c && x && J_out, DGNP_E_ARG, "NULL argument");
     AllocScope as(c->allocator);
-    DGNP_REQUIRE(objective == 0, DGNP_E_ARG, "objective 0 (outflow flux of species 1) is the only one");
-    *J_out = objective_value(*c, x);
+    DGNP_REQUIRE(objective == 0 || objective == 1, DGNP_E_ARG, "objective must be 0 or 1");
+    *J_out = objective_value(*c, x, objective);
   });
 }
 
 int dgnp_objective_noalloc(dgnp_ctx* c, const double* x, int32_t objective, double* J_dev, void* stream) {
   return guard([&] {
     DGNP_REQUIRE(c && x && J_dev, DGNP_E_ARG, "NULL argument");
-    DGNP_REQUIRE(objective == 0, DGNP_E_ARG, "objective 0 (outflow flux of species 1) is the only one");
-    objective_noalloc(c->dim, c->p, c->m, c->kargs(), x, c->obj_scratch, J_dev, static_cast<hipStream_t>(stream));
+    DGNP_REQUIRE(objective == 0 || objective == 1, DGNP_E_ARG, "objective must be 0 or 1");
+    objective_noalloc(c->dim, c->p, c->m, objective_args(*c, objective), x, c->obj_scratch, J_dev,
+                      static_cast<hipStream_t>(stream));
+  });
+}
+
+int dgnp_electrode_gradient(dgnp_ctx* c, const double* x, int32_t objective, const double* lambda, double* dJ_dj0,
+                            double* dJ_dphi_app) {
+  return guard([&] {
+    DGNP_REQUIRE(c && x && lambda, DGNP_E_ARG, "NULL argument");
+    DGNP_REQUIRE(objective == 0 || objective == 1, DGNP_E_ARG, "objective must be 0 or 1");
+    AllocScope as(c->allocator);
+    electrode_gradient(*c, x, objective, lambda, dJ_dj0, dJ_dphi_app);
   });
 }
 

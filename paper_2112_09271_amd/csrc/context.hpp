@@ -32,6 +32,10 @@ struct dgnp_ctx {
   std::vector<double> src_vol;   // caller sources [m][E][nqv] (empty: none, or the manufactured solution's)
   std::vector<double> dir_face;  // caller boundary data [m][n_bface][nqf] (empty: from bc_conc / phi_val)
   dgnp::DevAllocator allocator;  // device workspace allocator (the caller's hook or hipMalloc)
+  // Butler-Volmer electrodes (faces tagged DGNP_C_ELECTRODE)
+  bool has_electrode = false;
+  int bv_ion = 1, bv_prof = 0;
+  double bv_aa = 0, bv_ac = 0, bv_j0[6] = {}, bv_phi_app[6] = {};
   dgnp::RefTables ref;
   hipStream_t stream = nullptr;   // the caller's stream at setup
   hipStream_t work = nullptr;     // library stream for the synchronous drivers (graph capture)

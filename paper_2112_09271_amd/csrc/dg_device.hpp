@@ -550,6 +550,33 @@ __device__ inline void face_integrate(const T* __restrict__ cf, T* __restrict__ 
   __syncthreads();
 }
 
+// physical constants of the pointwise fluxes in the arithmetic T
+template <typename T, int MF>
+__device__ inline Phys<T, MF> make_phys(const KArgs& A) {
+  Phys<T, MF> ph;
+  for (int k = 0; k < MF - 1; ++k) {
+    ph.zD[k] = T(A.z[k] * A.D[k]);
+    ph.D[k] = T(A.D[k]);
+    ph.a[k] = T(A.a[k]);
+    ph.b[k] = T(A.b[k]);
+    ph.bv_dc[k] = T(A.bv_dc[k]);
+  }
+  ph.delta = T(A.delta);
+  ph.bv_r = A.bv_r;
+  ph.bv_z = T(A.bv_z);
+  ph.bv_aa = T(A.bv_aa);
+  ph.bv_ac = T(A.bv_ac);
+  return ph;
+}
+
+// shape of the exchange current across the box in z (the parabola of Sec. 5.2
+// with mean 1, or 1)
+__device__ inline double j0_profile(const KArgs& A, double z) {
+  if (A.bv_prof == 0) return 1.0;
+  const double t = (z - A.bv_zc) / A.bv_zhalf;
+  return 0.6 * (2.0 - t * t);
+}
+
 __device__ inline void velocity_hat(const KArgs& A, const double* x, int dim, double* uh) {
   uh[0] = uh[1] = uh[2] = 0.0;
   if (A.vel_kind == DGNP_VEL_VORTEX) {

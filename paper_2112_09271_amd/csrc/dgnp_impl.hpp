@@ -159,6 +159,16 @@ struct KArgs {
   const double* bcq;    // [m][n_bface][nqf] boundary data at face points (f = 0: phi)
   const double* src;    // [m][E][nqv] volume sources or nullptr
   int objective_tag;    // box face of the objective
+  int objective_kind;   // 0: outflow flux of species 1; 1: reaction rate on an electrode face
+  // Butler-Volmer electrodes: reacting ion (1..m), its valence, exponents
+  // alpha_a n / alpha_c n, dc_r / dc_k (k = 1..m-1, index k-1), and the
+  // exchange-current profile in z (0: constant; 1: parabola about bv_zc with
+  // half width bv_zhalf).  The per-point data sit in bcq: f = 0 the applied
+  // potential, f = 1 the exchange current at the point.
+  int bv_r;
+  double bv_z, bv_aa, bv_ac, bv_dc[4];
+  int bv_prof;
+  double bv_zc, bv_zhalf;
   unsigned vin_mask;    // fields of the input vector that are read (the others count as zero)
   const void* jbase;    // M_JACP: out = jbase - (J v) rows when not null (same type as out)
 };
@@ -169,8 +179,12 @@ enum Mode { M_RES = 0, M_JAC = 1, M_JACT = 2, M_DPE = 3, M_OBJG = 4, M_DATAT = 5
 //   M_RES / M_DPE: xs = state (double), out = R or dR/dPe
 //   M_JAC / M_JACT: xs = state, vin = v (same type T), out = J v / J^T v
 //   M_JACP: as M_JAC, but only the potential rows of J v are formed and written (out[0, Nf))
-//   M_OBJG: out = dJ/dx, aux[E][2] = per-element (J, dJ/dPe) contributions
-//   M_DATAT: vin = lambda, aux[m][n_bface][nqf] = lambda^T dR/d(data at face points)
+//   M_OBJG: out = dJ/dx (out null: not formed), aux[E][4] = per-element (J,
+//           dJ/dPe, dJ/dJ0, dJ/dphi_app) contributions (the last two: explicit
+//           derivatives with respect to the objective face's electrode parameters)
+//   M_DATAT: vin = lambda, aux[m][n_bface][nqf] = lambda^T dR/d(data at face points);
+//           on electrode faces f = 0 the applied potential, f = 1 the exchange
+//           current (amplitude of its profile)
 void launch_dg(int dim, int p, int m, bool f32, int mode, const KArgs& A, const void* xs,
                const void* vin, void* out, double* aux, hipStream_t s);
 void upload_ref_tables(const RefTables* tabs, int count);

@@ -99,14 +99,7 @@ __global__ void __launch_bounds__(BT)
   const int64_t e = blockIdx.x;
   const int f = f0 + int(blockIdx.y);
   load_tab<P, double>(tb, tid, BT);
-  Phys<double, MF> ph;
-  for (int k = 0; k < MF - 1; ++k) {
-    ph.zD[k] = A.z[k] * A.D[k];
-    ph.D[k] = A.D[k];
-    ph.a[k] = A.a[k];
-    ph.b[k] = A.b[k];
-  }
-  ph.delta = A.delta;
+  const Phys<double, MF> ph = make_phys<double, MF>(A);
   const int64_t Nf = A.E * NB;
   int eid[3];
   eid[0] = int(e % A.n[0]);

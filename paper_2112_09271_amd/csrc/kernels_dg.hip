@@ -71,14 +71,7 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
   if (e >= A.E) return;
   const int tid = threadIdx.x;
   load_tab<P, T>(tb, tid, NT);
-  Phys<T, MF> ph;
-  for (int k = 0; k < MF - 1; ++k) {
-    ph.zD[k] = T(A.z[k] * A.D[k]);
-    ph.D[k] = T(A.D[k]);
-    ph.a[k] = T(A.a[k]);
-    ph.b[k] = T(A.b[k]);
-  }
-  ph.delta = T(A.delta);
+  const Phys<T, MF> ph = make_phys<T, MF>(A);
   const int64_t Nf = A.E * NB;
   int eid[3];
   eid[0] = int(e % A.n[0]);
@@ -255,7 +248,7 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
   }
   __syncthreads();
   // F4: numerical fluxes at every face point of every face
-  double obj_j = 0.0, obj_dpe = 0.0;
+  double obj_j = 0.0, obj_dpe = 0.0, obj_j0 = 0.0, obj_pa = 0.0;
   auto trow = [&](int fc, int sd, int ar, int f, int c2) { return ((((fc * 2 + sd) * NARR + ar) * MF + f) * 2 + c2); };
   for (int idx = tid; idx < NFACE * NQF; idx += NT) {
     const int qf = idx % NQF, fc = idx / NQF;
@@ -271,7 +264,7 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
     if constexpr (MODE == M_OBJG)
       active = !interior && fc == A.objective_tag;
     else if constexpr (MODE == M_DATAT)
-      active = !interior && (cbc == BC_DIRICHLET || cbc == BC_INFLOW);
+      active = !interior && (cbc == BC_DIRICHLET || cbc == BC_INFLOW || cbc == BC_ELECTRODE);
     else if constexpr (MODE == M_DPE)
       active = interior || cbc != BC_WALL;
     else
@@ -350,20 +343,35 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
         } else if constexpr (MODE == M_DPE) {
           bnd_dpe<T, MF>(ph, v, g, un, uhn, cbc, gd, Fo, Go);
         } else if constexpr (MODE == M_OBJG) {
-          // J = int (q_1 . n) c_1: dJ/dc_1 = Q, dJ/d(dphi/dn) = -z_1 D_1 c_1
-          const T Q = un - ph.zD[0] * g[0];
-          Fo[1] = Q;
-          Go[0] = -ph.zD[0] * v[1];
-          obj_j += double(Q * v[1] * w);
-          obj_dpe += double(uhn * v[1] * w);
+          if (A.objective_kind == 1) {
+            // J = int g (the reacting ion's rate on an electrode face)
+            const BvRate<T> r = bv_rate(ph, v, gd);
+            Fo[0] = r.dphi;
+            for (int k = 1; k < MF; ++k) Fo[k] = r.dc * ph.bv_dc[k - 1];
+            obj_j += double(r.g * w);
+            obj_j0 += double(r.dj0 * w) * (DIM == 3 ? j0_profile(A, xp[2]) : 1.0);
+            obj_pa += double(r.dpa * w);
+          } else {
+            // J = int (q_1 . n) c_1: dJ/dc_1 = Q, dJ/d(dphi/dn) = -z_1 D_1 c_1
+            const T Q = un - ph.zD[0] * g[0];
+            Fo[1] = Q;
+            Go[0] = -ph.zD[0] * v[1];
+            obj_j += double(Q * v[1] * w);
+            obj_dpe += double(uhn * v[1] * w);
+          }
         } else if constexpr (MODE == M_DATAT) {
           T wv[MF], wg[MF], od[MF];
           for (int f = 0; f < MF; ++f) {
             wv[f] = fq[trow(fc, 0, NARR - 1, f, 0) * NQF + qf];
             wg[f] = sd * fq[trow(fc, 0, NARR - 1, f, 1) * NQF + qf];
           }
-          bnd_dataT<T, MF>(ph, g, wv, wg, un, cbc, od);
-          for (int f = 1; f < MF; ++f) aux[(f * A.n_bface + bf) * NQF + qf] = double(od[f] * w);
+          bnd_dataT<T, MF>(ph, v, g, wv, wg, un, cbc, gd, od);
+          if (cbc == BC_ELECTRODE) {  // applied potential, exchange-current amplitude
+            aux[(0 * A.n_bface + bf) * NQF + qf] = double(od[0] * w);
+            aux[(1 * A.n_bface + bf) * NQF + qf] = double(od[1] * w) * (DIM == 3 ? j0_profile(A, xp[2]) : 1.0);
+          } else {
+            for (int f = 1; f < MF; ++f) aux[(f * A.n_bface + bf) * NQF + qf] = double(od[f] * w);
+          }
         }
         for (int f = 0; f < MF; ++f) Go[f] *= sd;  // outward normal derivative -> d/dx_ax
       }
@@ -376,18 +384,16 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
   }
   __syncthreads();
   if constexpr (MODE == M_OBJG) {
-    __shared__ double rj[NT], rp[NT];
-    rj[tid] = obj_j;
-    rp[tid] = obj_dpe;
+    __shared__ double rj[4][NT];
+    rj[0][tid] = obj_j;
+    rj[1][tid] = obj_dpe;
+    rj[2][tid] = obj_j0;
+    rj[3][tid] = obj_pa;
     __syncthreads();
-    if (tid == 0) {
-      double sj = 0.0, sp = 0.0;
-      for (int i = 0; i < NT; ++i) {
-        sj += rj[i];
-        sp += rp[i];
-      }
-      aux[2 * e + 0] = sj;
-      aux[2 * e + 1] = sp;
+    if (tid < 4) {
+      double sj = 0.0;
+      for (int i = 0; i < NT; ++i) sj += rj[tid][i];
+      aux[4 * e + tid] = sj;
     }
     if (out == nullptr) return;  // the value alone (no gradient)
   }
@@ -473,7 +479,7 @@ __global__ void __launch_bounds__(OP_NT(DIM, P))
 // needs no clearing: the objective kernel writes the two partials of every
 // element before the sum reads them.
 static constexpr int64_t OBJ_SCRATCH_ELEMS = int64_t(1) << 18;
-static __device__ __align__(256) double scratch[2 * OBJ_SCRATCH_ELEMS];
+static __device__ __align__(256) double scratch[4 * OBJ_SCRATCH_ELEMS];
 
 static std::mutex g_scratch_mu;
 static double* g_scratch_dev[64] = {};  // the array's address on each device
@@ -496,7 +502,7 @@ int64_t objective_scratch_max_elements() { return OBJ_SCRATCH_ELEMS; }
 __global__ void __launch_bounds__(256) k_obj_sum(const double* __restrict__ part, int64_t E, double* __restrict__ J) {
   __shared__ double sh[256];
   double acc = 0.0;
-  for (int64_t e = threadIdx.x; e < E; e += 256) acc += part[2 * e];
+  for (int64_t e = threadIdx.x; e < E; e += 256) acc += part[4 * e];
   sh[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -508,6 +514,7 @@ __global__ void __launch_bounds__(256) k_obj_sum(const double* __restrict__ part
 
 void objective_noalloc(int dim, int p, int m, const KArgs& A, const double* x, double* scratch_dev, double* J_dev,
                        hipStream_t s) {
+  // A selects the objective (objective_kind, objective_tag)
   DGNP_REQUIRE(A.E <= OBJ_SCRATCH_ELEMS, DGNP_E_ARG,
                "allocation-free objective: at most 262144 elements (2^18) per problem");
   DGNP_REQUIRE(scratch_dev, DGNP_E_STATE, "allocation-free objective: scratch not set up on this device");

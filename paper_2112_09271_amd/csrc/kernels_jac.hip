@@ -141,14 +141,7 @@ __global__ void __launch_bounds__(NT) k_jlin(KArgs A, const T* __restrict__ vin,
   const int64_t E = A.E, Nf = E * NB;
   using C = CT<T, P>;
   const double* cd = CT<double, P>::base();  // double tables: Gauss points at cd[2 NQ NN + NQ + q]
-  Phys<T, MF> ph;
-  for (int k = 0; k < MF - 1; ++k) {
-    ph.zD[k] = T(A.z[k] * A.D[k]);
-    ph.D[k] = T(A.D[k]);
-    ph.a[k] = T(A.a[k]);
-    ph.b[k] = T(A.b[k]);
-  }
-  ph.delta = T(A.delta);
+  const Phys<T, MF> ph = make_phys<T, MF>(A);
   T ih[3];
   for (int i = 0; i < 3; ++i) ih[i] = T(2.0 / A.h[i]);
   auto ecoord = [&](int64_t e, int d) -> int {

@@ -1,8 +1,10 @@
 // Matrix-free potential-potential block for p-multigrid smoothing (3-D).
 //
-// The charge equation (Eq. chargeDG) is linear in the potential, and its
-// derivative with respect to the potential is the SIPG diffusion operator
-// with the coefficient kappa(c) = sum_k b_k c_k of the linearisation point:
+// The derivative of the charge equation (Eq. chargeDG) with respect to the
+// potential is the SIPG diffusion operator with the coefficient
+// kappa(c) = sum_k b_k c_k of the linearisation point (plus a Robin term on
+// Butler-Volmer electrode faces, the only place where the equation is
+// nonlinear in the potential):
 //   (A u, v) = sum_K int_K kappa grad u . grad v
 //            + sum_F int_F ( -{kappa du/dn}[v] - [u]{kappa dv/dn} + {kappa} delta [u][v] )
 //            + sum_{F potential-Dirichlet} int_F ( -kappa du/dn v - u kappa dv/dn + kappa delta u v ).
@@ -24,7 +26,9 @@ void upload_ref_tables_phi(const RefTables* tabs, int count) { upload_ref_tables
 #define PHI_NT(P) ((P) == 3 ? 256 : 128)
 
 // kv[e][q] = kappa w_q detJ at the volume Gauss points; kf[e][fc][qf] = kappa
-// w_f at the Gauss points of face fc from the element's own traces
+// w_f at the Gauss points of face fc from the element's own traces (on an
+// electrode face: the Robin coefficient -z_r dg/dphi w_f of the Butler-Volmer
+// term instead)
 template <int P, int MF, typename T>
 __global__ void __launch_bounds__(PHI_NT(P)) k_phi_kappa(KArgs A, const double* __restrict__ xs, T* __restrict__ kv,
                                                          T* __restrict__ kf) {
@@ -55,16 +59,30 @@ __global__ void __launch_bounds__(PHI_NT(P)) k_phi_kappa(KArgs A, const double* 
     const int ax = fc >> 1, l = (fc & 1) ? P : 0;
     const int qi = qf % NQ, qj = qf / NQ;
     const int t1ax = ax == 0 ? 1 : 0, t2ax = ax == 2 ? 1 : 2;
-    double kap = 0.0;
-    for (int k = 1; k < MF; ++k) {
-      const double* x = xs + k * Nf + e * NB;
+    double val[MF];
+    for (int f = 0; f < MF; ++f) {
+      const double* x = xs + f * Nf + e * NB;
       double s = 0.0;
       for (int j = 0; j < NN; ++j)
         for (int i = 0; i < NN; ++i) s += C::B(qi, i) * C::B(qj, j) * x[face_node<3, NN>(ax, l, i, j)];
-      kap += A.b[k - 1] * s;
+      val[f] = s;
     }
+    double kap = 0.0;
+    for (int k = 1; k < MF; ++k) kap += A.b[k - 1] * val[k];
     const double w = 0.25 * A.h[t1ax] * A.h[t2ax] * wq[qi] * wq[qj];
-    kf[(e * 6 + fc) * NQF + qf] = T(kap * w);
+    double coef = kap * w;
+    if (A.nbr[e * 6 + fc] < 0 && A.c_bc[fc] == BC_ELECTRODE) {
+      // electrode face: the Butler-Volmer term -z_r g v of the charge equation,
+      // linearised in the potential, is a Robin term with coefficient -z_r dg/dphi
+      const int ex = int(e % A.n[0]), ey = int((e / A.n[0]) % A.n[1]), ez = int(e / (int64_t(A.n[0]) * A.n[1]));
+      const int64_t lin = ax == 0 ? ey + int64_t(A.n[1]) * ez : (ax == 1 ? ex + int64_t(A.n[0]) * ez : ex + int64_t(A.n[0]) * ey);
+      const int64_t bf = A.btag_off[fc] + lin;
+      double gd[MF];
+      for (int f = 0; f < MF; ++f) gd[f] = A.bcq[(f * A.n_bface + bf) * NQF + qf];
+      const Phys<double, MF> ph = make_phys<double, MF>(A);
+      coef = -ph.bv_z * bv_rate(ph, val, gd).dphi * w;
+    }
+    kf[(e * 6 + fc) * NQF + qf] = T(coef);
   }
 }
 
@@ -195,6 +213,8 @@ __global__ void __launch_bounds__(PHI_NT(P)) k_phi_op(KArgs A, const T* __restri
     } else if (A.phi_bc[fc] == DGNP_PHI_DIRICHLET) {
       F = -side * ko * dno + ko * delta * uo;
       G = -side * ko * uo;
+    } else if (A.c_bc[fc] == BC_ELECTRODE) {
+      F = ko * uo;  // Robin coefficient of the electrode term (weight included)
     }
     cf[(fc * 2 + 0) * NQF + qf] = F;
     cf[(fc * 2 + 1) * NQF + qf] = G * ih[ax];

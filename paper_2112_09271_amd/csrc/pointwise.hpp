@@ -24,7 +24,7 @@
 
 namespace dgnp {
 
-enum { BC_WALL = 0, BC_DIRICHLET = 1, BC_INFLOW = 2, BC_OUTFLOW = 3 };
+enum { BC_WALL = 0, BC_DIRICHLET = 1, BC_INFLOW = 2, BC_OUTFLOW = 3, BC_ELECTRODE = 4 };
 
 template <typename T, int MF>
 struct Phys {
@@ -33,6 +33,13 @@ struct Phys {
   T a[MF];
   T b[MF];
   T delta;      // interior penalty C_IP p^2 / h
+  // Butler-Volmer electrode faces: the reacting ion r (1..m; m is the
+  // eliminated one), its valence, the exponents alpha_a n and alpha_c n, and
+  // the derivatives of c_r with respect to c_1..c_{m-1} (a unit vector, or
+  // -z_k / z_m by electroneutrality when r = m), index k-1
+  int bv_r;
+  T bv_z, bv_aa, bv_ac;
+  T bv_dc[MF];
 };
 
 template <typename T>
@@ -245,6 +252,53 @@ __host__ __device__ inline void face_dpe(const Phys<T, MF>& ph, const T (*v)[MF]
 }
 
 // ----------------------------------------------------------------------------
+// Butler-Volmer rate of the reacting ion at an electrode point (Sec. 2.1 Eq. bv
+// in the nondimensional form of Sec. 2.3, gamma = 1, reductant of constant
+// concentration as in Sec. 5.2):
+//   g = J0 [exp(alpha_a n eta) - c_r exp(-alpha_c n eta)],  eta = phi_app - phi,
+// with the point data gd[0] = phi_app and gd[1] = J0 (exchange current times
+// its profile).  It enters the reacting ion's equation as -g v (Eq. NPDG,
+// Eq. electrode) and the charge equation as -z_r g v (Eq. chargeDG).
+template <typename T>
+struct BvRate {
+  T g, dphi, dc, dj0, dpa;  // g and its derivatives: phi, c_r, J0, phi_app
+};
+
+template <typename T, int MF>
+__host__ __device__ inline T bv_conc(const Phys<T, MF>& ph, const T* v) {
+  T c = T(0);
+  for (int k = 1; k < MF; ++k) c += ph.bv_dc[k - 1] * v[k];
+  return c;
+}
+
+template <typename T, int MF>
+__host__ __device__ inline BvRate<T> bv_rate(const Phys<T, MF>& ph, const T* v, const T* gd) {
+  const T eta = gd[0] - v[0];
+  const T ea = exp(ph.bv_aa * eta), ec = exp(-ph.bv_ac * eta);
+  const T c = bv_conc(ph, v);
+  BvRate<T> r;
+  r.g = gd[1] * (ea - c * ec);
+  r.dphi = gd[1] * (-ph.bv_aa * ea - c * ph.bv_ac * ec);
+  r.dc = -gd[1] * ec;
+  r.dj0 = ea - c * ec;
+  r.dpa = -r.dphi;
+  return r;
+}
+
+// value coefficients of the electrode terms for a rate (or its linearisation) s
+template <typename T, int MF>
+__host__ __device__ inline void bv_add(const Phys<T, MF>& ph, T s, T* F) {
+  if (ph.bv_r < MF) F[ph.bv_r] -= s;
+  F[0] -= ph.bv_z * s;
+}
+
+// the test-trace combination that the electrode terms are tested with
+template <typename T, int MF>
+__host__ __device__ inline T bv_weight(const Phys<T, MF>& ph, const T* wv) {
+  return (ph.bv_r < MF ? wv[ph.bv_r] : T(0)) + ph.bv_z * wv[0];
+}
+
+// ----------------------------------------------------------------------------
 // Boundary faces (outward normal).  cbc: concentration kind of the face,
 // phid: potential Dirichlet flag, gd[f]: data (gd[0] potential, gd[k] c_k).
 template <typename T, int MF>
@@ -277,6 +331,7 @@ __host__ __device__ inline void bnd_res(const Phys<T, MF>& ph, const T* v, const
     F[0] = -cur + kap * ph.delta * jp;
     G[0] -= kap * jp;
   }
+  if (cbc == BC_ELECTRODE) bv_add(ph, bv_rate(ph, v, gd).g, F);
 }
 
 template <typename T, int MF>
@@ -313,6 +368,10 @@ __host__ __device__ inline void bnd_jac(const Phys<T, MF>& ph, const T* v, const
     F[0] = -dcur + dkap * ph.delta * jp + kap * ph.delta * tv[0];
     G[0] += -dkap * jp - kap * tv[0];
   }
+  if (cbc == BC_ELECTRODE) {
+    const BvRate<T> r = bv_rate(ph, v, gd);
+    bv_add(ph, r.dphi * tv[0] + r.dc * bv_conc(ph, tv), F);
+  }
 }
 
 template <typename T, int MF>
@@ -347,6 +406,12 @@ __host__ __device__ inline void bnd_jacT(const Phys<T, MF>& ph, const T* v, cons
     Tg[0] += -kap * wv[0];
     Tv[0] += kap * ph.delta * wv[0] - kap * wg[0];
   }
+  if (cbc == BC_ELECTRODE) {
+    const BvRate<T> r = bv_rate(ph, v, gd);
+    const T W = bv_weight(ph, wv);
+    Tv[0] -= r.dphi * W;
+    for (int k = 1; k < MF; ++k) Tv[k] -= r.dc * ph.bv_dc[k - 1] * W;
+  }
 }
 
 template <typename T, int MF>
@@ -370,11 +435,21 @@ __host__ __device__ inline void bnd_dpe(const Phys<T, MF>& ph, const T* v, const
 }
 
 // lambda^T dR/d(data): coefficient of the concentration data gd[k] at one point,
-// given the adjoint traces (wv, wg)
+// given the adjoint traces (wv, wg); on an electrode face the coefficients of
+// the applied potential (out[0]) and of the exchange current (out[1], per unit
+// of the point value gd[1])
 template <typename T, int MF>
-__host__ __device__ inline void bnd_dataT(const Phys<T, MF>& ph, const T* g, const T* wv, const T* wg,
-                                          T un, int cbc, T* out) {
+__host__ __device__ inline void bnd_dataT(const Phys<T, MF>& ph, const T* v, const T* g, const T* wv,
+                                          const T* wg, T un, int cbc, const T* gd, T* out) {
   out[0] = T(0);
+  if (cbc == BC_ELECTRODE) {
+    const BvRate<T> r = bv_rate(ph, v, gd);
+    const T W = bv_weight(ph, wv);
+    for (int k = 1; k < MF; ++k) out[k] = T(0);
+    out[0] = -r.dpa * W;
+    out[1] = -r.dj0 * W;
+    return;
+  }
   for (int k = 1; k < MF; ++k) {
     const T D = ph.D[k - 1], zD = ph.zD[k - 1];
     T Q = un - zD * g[0];

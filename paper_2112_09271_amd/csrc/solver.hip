@@ -3,6 +3,7 @@
 // line search (paper Sec. 4), mixed precision by iterative refinement, and the
 // adjoint of the outflow-flux objective.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -534,7 +535,10 @@ int newton_solve(dgnp_ctx& c, double* x, const dgnp_solve_opts& o, dgnp_solve_st
     }
     if (it == o.max_newton) break;
     const auto ts = clk::now();
-    set_state(c, x, o.prec, s, false, false, (phi_current ? PC_CONC : PC_ALL) | PC_WARM);
+    // the potential block depends on the concentrations only, so the initial
+    // guess's potential hierarchy serves the first Newton step; not with
+    // electrodes, whose Butler-Volmer term adds a potential-dependent part
+    set_state(c, x, o.prec, s, false, false, (phi_current && !c.has_electrode ? PC_CONC : PC_ALL) | PC_WARM);
     phi_current = false;
     st.t_setup += since(ts);
     vcopy<double>(W.r.p, W.b.p, N, s);
@@ -587,25 +591,81 @@ int newton_solve(dgnp_ctx& c, double* x, const dgnp_solve_opts& o, dgnp_solve_st
   return code;
 }
 
-double objective_value(dgnp_ctx& c, const double* x) {
-  hipStream_t s = c.work;
-  DGNP_HIP(hipDeviceSynchronize());
-  DevBuf<double> g;
-  g.alloc(size_t(c.N));
-  launch_dg(c.dim, c.p, c.m, false, M_OBJG, c.kargs(), x, nullptr, g.p, c.d_aux.p, s);
-  std::vector<double> part(static_cast<size_t>(2 * c.E));
+// kernel arguments of objective `kind` (0: outflow flux of species 1 through
+// x = x_max; 1: reaction rate on the first electrode face)
+KArgs objective_args(const dgnp_ctx& c, int kind) {
+  KArgs A = c.kargs();
+  DGNP_REQUIRE(kind == 0 || kind == 1, DGNP_E_ARG, "objective must be 0 (outflow) or 1 (electrode)");
+  A.objective_kind = kind;
+  A.objective_tag = 1;
+  if (kind == 1) {
+    A.objective_tag = -1;
+    for (int t = 2 * c.dim - 1; t >= 0; --t)
+      if (c.c_bc[t] == DGNP_C_ELECTRODE) A.objective_tag = t;
+    DGNP_REQUIRE(A.objective_tag >= 0, DGNP_E_ARG, "objective 1 needs an electrode face");
+  }
+  return A;
+}
+
+// per-element partial sums of the objective kernel: (J, dJ/dPe, dJ/dJ0, dJ/dphi_app)
+static std::array<double, 4> objective_sums(dgnp_ctx& c, const double* x, int kind, double* g, hipStream_t s) {
+  launch_dg(c.dim, c.p, c.m, false, M_OBJG, objective_args(c, kind), x, nullptr, g, c.d_aux.p, s);
+  std::vector<double> part(static_cast<size_t>(4 * c.E));
   DGNP_HIP(hipMemcpyAsync(part.data(), c.d_aux.p, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   DGNP_HIP(hipStreamSynchronize(s));
-  double J = 0.0;
-  for (int64_t e = 0; e < c.E; ++e) J += part[size_t(2 * e)];
-  return J;
+  std::array<double, 4> sum = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t e = 0; e < c.E; ++e)
+    for (int i = 0; i < 4; ++i) sum[size_t(i)] += part[size_t(4 * e + i)];
+  return sum;
+}
+
+double objective_value(dgnp_ctx& c, const double* x, int kind) {
+  hipStream_t s = c.work;
+  DGNP_HIP(hipDeviceSynchronize());
+  return objective_sums(c, x, kind, nullptr, s)[0];
+}
+
+// dJ/dtheta for the exchange currents and applied potentials of the electrode
+// faces: the objective's explicit derivatives (objective 1, on its face) minus
+// lambda^T dR/dtheta, summed per box face from the boundary-data kernel mode
+void electrode_gradient(dgnp_ctx& c, const double* x, int kind, const double* lambda, double* dJ_dj0,
+                        double* dJ_dpa) {
+  hipStream_t s = c.work;
+  DGNP_HIP(hipDeviceSynchronize());
+  const KArgs A = objective_args(c, kind);
+  const std::array<double, 4> ex = objective_sums(c, x, kind, nullptr, s);
+  for (int t = 0; t < 6; ++t) {
+    if (dJ_dj0) dJ_dj0[t] = 0.0;
+    if (dJ_dpa) dJ_dpa[t] = 0.0;
+  }
+  if (!c.has_electrode) return;
+  if (kind == 1) {
+    if (dJ_dj0) dJ_dj0[A.objective_tag] = ex[2];
+    if (dJ_dpa) dJ_dpa[A.objective_tag] = ex[3];
+  }
+  launch_dg(c.dim, c.p, c.m, false, M_DATAT, c.kargs(), x, lambda, nullptr, c.d_aux.p, s);
+  std::vector<double> zeta(size_t(2) * c.n_bface * c.nqf);
+  DGNP_HIP(hipMemcpyAsync(zeta.data(), c.d_aux.p, zeta.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  DGNP_HIP(hipStreamSynchronize(s));
+  for (int t = 0; t < 2 * c.dim; ++t) {
+    if (c.c_bc[t] != DGNP_C_ELECTRODE) continue;
+    const int64_t f0 = c.btag_off[t], f1 = f0 + c.E / c.n[t / 2];
+    double sp = 0.0, sj = 0.0;
+    for (int64_t bf = f0; bf < f1; ++bf)
+      for (int q = 0; q < c.nqf; ++q) {
+        sp += zeta[size_t(bf) * c.nqf + q];
+        sj += zeta[(size_t(c.n_bface) + bf) * c.nqf + q];
+      }
+    if (dJ_dj0) dJ_dj0[t] -= sj;
+    if (dJ_dpa) dJ_dpa[t] -= sp;
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Adjoint: J^T lambda = dJ/dx, gradients dJ/dtheta = dJ/dtheta|_x - lambda^T dR/dtheta
 // ---------------------------------------------------------------------------
-int adjoint_solve(dgnp_ctx& c, const double* x, double* dJ_dbc, double* dJ_dPe, double* J_out, double* lambda,
-                  const dgnp_solve_opts& o, dgnp_solve_stats& st) {
+int adjoint_solve(dgnp_ctx& c, const double* x, int kind, double* dJ_dbc, double* dJ_dPe, double* J_out,
+                  double* lambda, const dgnp_solve_opts& o, dgnp_solve_stats& st) {
   const auto t0 = clk::now();
   hipStream_t s = c.work;
   const int64_t N = c.N;
@@ -620,15 +680,8 @@ int adjoint_solve(dgnp_ctx& c, const double* x, double* dJ_dbc, double* dJ_dPe, 
   lam.alloc(size_t(N));
   dr.alloc(size_t(N));
   red.alloc(size_t(reduce_scratch_size()));
-  launch_dg(c.dim, c.p, c.m, false, M_OBJG, c.kargs(), c.d_x.p, nullptr, g.p, c.d_aux.p, s);
-  std::vector<double> part(static_cast<size_t>(2 * c.E));
-  DGNP_HIP(hipMemcpyAsync(part.data(), c.d_aux.p, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-  DGNP_HIP(hipStreamSynchronize(s));
-  double J = 0.0, dJdPe_x = 0.0;
-  for (int64_t e = 0; e < c.E; ++e) {
-    J += part[size_t(2 * e)];
-    dJdPe_x += part[size_t(2 * e + 1)];
-  }
+  const std::array<double, 4> ex = objective_sums(c, c.d_x.p, kind, g.p, s);
+  const double J = ex[0], dJdPe_x = ex[1];
   const double gn = vnorm2(g.p, N, red.p, s);
   vfill<double>(lam.p, 0.0, N, s);
   const auto tk = clk::now();

@@ -37,9 +37,12 @@ void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assem
 void jac_apply(dgnp_ctx& c, const void* v, void* y, bool f32, bool transpose, hipStream_t s,
                unsigned vmask = ~0u, bool phi_rows = false, const void* base = nullptr);
 dgnp_solve_opts default_solve_opts();
-double objective_value(dgnp_ctx& c, const double* x);
+KArgs objective_args(const dgnp_ctx& c, int kind);  // kernel arguments of objective 0 / 1
+double objective_value(dgnp_ctx& c, const double* x, int kind);
+void electrode_gradient(dgnp_ctx& c, const double* x, int kind, const double* lambda, double* dJ_dj0,
+                        double* dJ_dpa);
 int newton_solve(dgnp_ctx& c, double* x, const dgnp_solve_opts& o, dgnp_solve_stats& st);
-int adjoint_solve(dgnp_ctx& c, const double* x, double* dJ_dbc, double* dJ_dPe, double* J_out,
+int adjoint_solve(dgnp_ctx& c, const double* x, int kind, double* dJ_dbc, double* dJ_dPe, double* J_out,
                   double* lambda, const dgnp_solve_opts& o, dgnp_solve_stats& st);
 
 }  // namespace dgnp

@@ -21,6 +21,8 @@ DGNP_F64, DGNP_F32 = 0, 1
 DGNP_STATE_ASSEMBLE_ONLY = 0x100
 DGNP_STATE_APPLY_ONLY = 0x200
 DGNP_PC_P2, DGNP_PC_P1 = 0, 1
+DGNP_C_ELECTRODE = 4
+DGNP_OBJ_OUTFLOW, DGNP_OBJ_ELECTRODE = 0, 1
 # potential multigrid: automatic / Q1 Galerkin start / p-multigrid (re-discretised, Galerkin p = 1 level)
 DGNP_PHIMG_AUTO, DGNP_PHIMG_Q1, DGNP_PHIMG_P, DGNP_PHIMG_PG = 0, 1, 2, 3
 DGNP_PHIOP_ASSEMBLED, DGNP_PHIOP_MATFREE = 0, 1  # potential-block apply: assembled / matrix-free
@@ -44,10 +46,16 @@ ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
+class dgnp_electrode(C.Structure):
+    _fields_ = [("ion", C.c_int32), ("alpha_a", C.c_double), ("alpha_c", C.c_double), ("j0", C.c_double * 6),
+                ("phi_app", C.c_double * 6), ("j0_profile", C.c_int32)]
+
+
 class dgnp_options(C.Structure):
     _fields_ = [("c_ip", C.c_double), ("mms", C.c_int32), ("bc_conc", C.POINTER(C.c_double)),
                 ("phi_mg", C.c_int32), ("src_vol", C.POINTER(C.c_double)), ("dir_face", C.POINTER(C.c_double)),
-                ("alloc", ALLOC_FN), ("free_", FREE_FN), ("alloc_ctx", C.c_void_p)]
+                ("alloc", ALLOC_FN), ("free_", FREE_FN), ("alloc_ctx", C.c_void_p),
+                ("electrode", C.POINTER(dgnp_electrode))]
 
 
 class TorchAllocator:
@@ -100,6 +108,8 @@ _SIGS = {
     "dgnp_setup": [C.POINTER(dgnp_mesh), C.c_int32, C.POINTER(dgnp_species), C.POINTER(dgnp_velocity),
                    C.POINTER(dgnp_options), _vp, C.POINTER(_vp)],
     "dgnp_set_params": [_vp, _vp, C.c_double],
+    "dgnp_set_electrode": [_vp, C.POINTER(dgnp_electrode)],
+    "dgnp_electrode_gradient": [_vp, _vp, C.c_int32, _vp, _vp, _vp],
     "dgnp_sizes": [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                    C.POINTER(C.c_int64)],
     "dgnp_n_faces": [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
@@ -268,6 +278,10 @@ class Problem:
         if allocator is not None:
             opt.alloc = allocator.c_alloc
             opt.free_ = allocator.c_free
+        self._el = None
+        if any(mesh.c_bc[t] == DGNP_C_ELECTRODE for t in range(2 * d)):
+            self._el = self._electrode(cfg.bv_j0, cfg.bv_phi_app)
+            opt.electrode = C.pointer(self._el)
         self.Pe = float(vel.Pe)
         self.ctx = dgnp_setup(mesh, cfg.p, sp, vel, opt, _stream())
         E, Nf, nb = C.c_int64(), C.c_int64(), C.c_int64()
@@ -297,6 +311,33 @@ class Problem:
         if Pe is not None:
             self.Pe = float(Pe)
         _check(lib().dgnp_set_params(self.ctx, ptr, self.Pe))
+
+    def _electrode(self, j0, phi_app):
+        cfg = self.cfg
+        el = dgnp_electrode()
+        el.ion = int(cfg.bv_ion)
+        el.alpha_a, el.alpha_c = float(cfg.bv_alpha[0]), float(cfg.bv_alpha[1])
+        for t in range(6):
+            el.j0[t] = float(j0[t]) if t < len(j0) else 0.0
+            el.phi_app[t] = float(phi_app[t]) if t < len(phi_app) else 0.0
+        el.j0_profile = int(cfg.bv_j0_profile)
+        return el
+
+    def set_electrode(self, j0, phi_app):
+        """New exchange currents and applied potentials per box face (invalidates the state)."""
+        self._el = self._electrode(j0, phi_app)
+        _check(lib().dgnp_set_electrode(self.ctx, C.byref(self._el)))
+
+    def electrode_gradient(self, x, lam, objective=DGNP_OBJ_ELECTRODE):
+        """(dJ/dJ0 [6], dJ/dphi_app [6]) of an objective from its adjoint solution lam."""
+        import torch
+        x = self._dev(x, torch.float64)
+        lam = self._dev(lam, torch.float64)
+        dj0, dpa = np.zeros(6), np.zeros(6)
+        torch.cuda.synchronize()
+        _check(lib().dgnp_electrode_gradient(self.ctx, x.data_ptr(), int(objective), lam.data_ptr(),
+                                             dj0.ctypes.data, dpa.ctypes.data))
+        return dj0, dpa
 
     def current_bc(self):
         """The nodal boundary data [m-1][n_bnode] the context holds (None with a manufactured solution)."""
@@ -420,16 +461,17 @@ class Problem:
         dgnp_solve(self.ctx, x.data_ptr(), self.solve_opts(**kw), st)
         return x, st
 
-    def objective(self, x):
-        """Outflow flux of species 1 through x = x_max at the state x."""
+    def objective(self, x, objective=DGNP_OBJ_OUTFLOW):
+        """Objective at the state x: 0 the outflow flux of species 1 through
+        x = x_max, 1 the reaction rate integrated over the first electrode face."""
         import torch
         x = self._dev(x, torch.float64)
         J = np.zeros(1)
         torch.cuda.synchronize()
-        _check(lib().dgnp_objective(self.ctx, x.data_ptr(), 0, J.ctypes.data))
+        _check(lib().dgnp_objective(self.ctx, x.data_ptr(), int(objective), J.ctypes.data))
         return float(J[0])
 
-    def adjoint(self, x, **kw):
+    def adjoint(self, x, objective=DGNP_OBJ_OUTFLOW, **kw):
         """Returns (J, dJ/d(bc data) [m-1][n_bnode], dJ/dPe, lambda, stats)."""
         import torch
         x = self._dev(x, torch.float64)
@@ -438,6 +480,7 @@ class Problem:
         J = np.zeros(1)
         lam = torch.empty_like(x)
         st = dgnp_solve_stats()
-        dgnp_adjoint(self.ctx, x.data_ptr(), 0, dbc.ctypes.data, dpe.ctypes.data, J.ctypes.data,
+        dgnp_adjoint(self.ctx, x.data_ptr(), int(objective),
+                     dbc.ctypes.data if self._face is None else None, dpe.ctypes.data, J.ctypes.data,
                      lam.data_ptr(), self.solve_opts(**kw), st)
         return float(J[0]), dbc, float(dpe[0]), lam, st

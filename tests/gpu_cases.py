@@ -6,6 +6,7 @@ from oracle.dg import DG
 from oracle.problem import Problem as OProblem
 from tests.oracle_cases import adj2d
 from workload import boundary_data, get_config
+from workload.configs import Config
 
 torch = pytest.importorskip("torch")
 
@@ -15,7 +16,10 @@ def gpu_available():
 
 
 def config(name, **kw):
-    cfg = adj2d() if name == "adj2d" else get_config(name)
+    if isinstance(name, Config):
+        cfg = name
+    else:
+        cfg = adj2d() if name == "adj2d" else get_config(name)
     return cfg.with_(**kw) if kw else cfg
 
 
@@ -23,7 +27,7 @@ def pair(name, with_oracle=True, phi_mg=0, **kw):
     from paper_2112_09271_amd.dgnp import Problem
     cfg = config(name, **kw)
     data = None if cfg.mms else boundary_data(cfg)
-    print(f"[case] {name} n={cfg.n} p={cfg.p} m={cfg.m} phi_mg={phi_mg}", flush=True)
+    print(f"[case] {cfg.name} n={cfg.n} p={cfg.p} m={cfg.m} phi_mg={phi_mg}", flush=True)
     gp = Problem(cfg, data, phi_mg=phi_mg)
     od = None
     if with_oracle:

@@ -4,7 +4,8 @@ import sympy as sp
 from oracle.dg import DG
 from oracle.problem import Problem
 from workload import boundary_data, get_config
-from workload.configs import C_DIRICHLET, C_OUTFLOW, PHI_DIRICHLET, VEL_CONST, Config
+from workload.configs import (C_DIRICHLET, C_ELECTRODE, C_INFLOW, C_OUTFLOW, J0_PARABOLIC_Z, PHI_DIRICHLET,
+                              VEL_CONST, VEL_POISEUILLE_X, Config)
 
 X, Y, Z = sp.symbols("x y z")
 
@@ -38,3 +39,25 @@ def poly_problem(dim=2, p=2, n=None):
         ex = [0.1 * X * Y + 0.05 * X - 0.02 * Y * Z, 1 + X / 2 + Y / 4 - Z / 8,
               1.2 - 0.3 * X + 0.2 * Y + 0.1 * Z]
     return DG(Problem(cfg, exact_exprs=ex))
+
+
+def bv2d(ion=1, **kw):
+    """2-D channel with Butler-Volmer electrodes at y = 0 (anode) and y = 0.5
+    (cathode), three ions, Poiseuille flow; the potential is free everywhere."""
+    base = dict(c_bc=(C_INFLOW, C_OUTFLOW, C_ELECTRODE, C_ELECTRODE), phi_bc=(0, 0, 0, 0),
+                phi_val=(0.0,) * 4, bv_ion=ion, bv_alpha=(1.0, 1.0), bv_j0=(0.0, 0.0, 1.0, 1.0),
+                bv_phi_app=(0.0, 0.0, 0.0, 1.1676))
+    base.update(kw)
+    return Config("bv2d", 2, (6, 4), (0.0, 0.0), (1.0, 0.5), 2, (1.0, -1.0, 2.0), (1.0, 1.5, 0.7),
+                  VEL_POISEUILLE_X, 100.0, seed=5, **base)
+
+
+def bv3t(ion=1, p=2, **kw):
+    """3-D channel with Butler-Volmer electrodes at y = 0 and y = 0.5, the
+    exchange current parabolic across z, three ions, Poiseuille flow."""
+    base = dict(c_bc=(C_INFLOW, C_OUTFLOW, C_ELECTRODE, C_ELECTRODE, 0, 0), phi_bc=(0,) * 6,
+                phi_val=(0.0,) * 6, bv_ion=ion, bv_alpha=(1.0, 1.0), bv_j0=(0.0, 0.0, 1.0, 1.0, 0.0, 0.0),
+                bv_phi_app=(0.0, 0.0, 0.0, 1.1676, 0.0, 0.0), bv_j0_profile=J0_PARABOLIC_Z)
+    base.update(kw)
+    return Config("bv3t", 3, (4, 2, 2), (0.0, 0.0, 0.0), (1.0, 0.5, 0.25), p, (1.0, -1.0, 2.0), (1.0, 1.5, 0.7),
+                  VEL_POISEUILLE_X, 100.0, seed=6, **base)

@@ -41,14 +41,37 @@ def _species(z=(1.0, -1.0), D=(1.0, 1.0)):
     return dgnp.dgnp_species(len(z), zz, dd), (zz, dd)
 
 
-@pytest.mark.parametrize("case", ["order", "dim", "ions", "zero_charge", "bc_kind", "no_data"])
+@pytest.mark.parametrize("case", ["order", "dim", "ions", "zero_charge", "bc_kind", "no_data", "phi_free",
+                                  "electrode_no_params", "electrode_phi_dirichlet", "electrode_bad_ion",
+                                  "electrode_nan", "half_allocator"])
 def test_setup_rejects_bad_arguments(case):
+    """Every one of these is refused on the host before any GPU call."""
     mesh = _mesh()
+    mesh.phi_bc[0] = 1   # a potential-Dirichlet face fixes the potential
     order = 2
     sp, keep = _species()
     vel = dgnp.dgnp_velocity()
     opt = dgnp.dgnp_options()
     opt.c_ip = 10.0
+    el = dgnp.dgnp_electrode()
+    el.ion, el.alpha_a, el.alpha_c = 1, 1.0, 1.0
+    if case == "phi_free":
+        mesh.phi_bc[0] = 0   # all-Neumann potential: singular, reported instead of solved
+    elif case == "electrode_no_params":
+        mesh.c_bc[2] = dgnp.DGNP_C_ELECTRODE
+    elif case == "electrode_phi_dirichlet":
+        mesh.c_bc[0] = dgnp.DGNP_C_ELECTRODE
+        opt.electrode = C.pointer(el)
+    elif case == "electrode_bad_ion":
+        mesh.c_bc[2] = dgnp.DGNP_C_ELECTRODE
+        el.ion = 5
+        opt.electrode = C.pointer(el)
+    elif case == "electrode_nan":
+        mesh.c_bc[2] = dgnp.DGNP_C_ELECTRODE
+        el.j0[2] = float("nan")
+        opt.electrode = C.pointer(el)
+    elif case == "half_allocator":
+        opt.alloc = dgnp.ALLOC_FN(lambda n, ctx: None)
     if case == "order":
         order = 7
     elif case == "dim":
@@ -67,8 +90,10 @@ def test_setup_rejects_bad_arguments(case):
     assert code != dgnp.DGNP_OK
     assert ctx.value is None
     assert len(dgnp.lib().dgnp_last_error()) > 0
-    if case != "no_data":
-        assert code == dgnp.DGNP_E_ARG
+    if case == "electrode_nan":
+        assert code == dgnp.DGNP_E_NONFINITE
+    elif case != "no_data":
+        assert code == dgnp.DGNP_E_ARG, (code, dgnp.lib().dgnp_last_error())
 
 
 def test_null_arguments():

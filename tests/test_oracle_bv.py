@@ -21,6 +21,7 @@ import sympy as sp
 from oracle import solve
 from oracle.dg import DG
 from oracle.problem import Problem
+from tests.oracle_cases import bv2d
 from workload import boundary_data, random_state, random_vector
 from workload.configs import (C_DIRICHLET, C_ELECTRODE, C_INFLOW, C_OUTFLOW, PHI_DIRICHLET, VEL_CONST,
                               VEL_POISEUILLE_X, Config)
@@ -68,20 +69,9 @@ def test_linear_solution_satisfying_the_electrode_condition(alpha, ion):
     assert np.abs(dgb.residual(_interp(dgb))).max() > 1e-6 * scale
 
 
-def _bv2d(ion=1, **kw):
-    """2-D channel with Butler-Volmer electrodes at y = 0 (anode) and y = 0.5
-    (cathode), three ions, Poiseuille flow; the potential is free everywhere."""
-    base = dict(c_bc=(C_INFLOW, C_OUTFLOW, C_ELECTRODE, C_ELECTRODE), phi_bc=(0, 0, 0, 0),
-                phi_val=(0.0,) * 4, bv_ion=ion, bv_alpha=(1.0, 1.0), bv_j0=(0.0, 0.0, 1.0, 1.0),
-                bv_phi_app=(0.0, 0.0, 0.0, 1.1676))
-    base.update(kw)
-    return Config("bv2d", 2, (6, 4), (0.0, 0.0), (1.0, 0.5), 2, (1.0, -1.0, 2.0), (1.0, 1.5, 0.7),
-                  VEL_POISEUILLE_X, 100.0, seed=5, **base)
-
-
 @pytest.mark.parametrize("ion", [1, 3])
 def test_bv_jacobian_matches_central_differences(ion):
-    cfg = _bv2d(ion)
+    cfg = bv2d(ion)
     dg = DG(Problem(cfg, boundary_data(cfg)))
     x = random_state(cfg)
     v = random_vector(cfg)
@@ -97,7 +87,7 @@ def test_bv_jacobian_matches_central_differences(ion):
 
 @pytest.mark.parametrize("ion", [1, 3])
 def test_bv_parameter_derivatives(ion):
-    cfg = _bv2d(ion)
+    cfg = bv2d(ion)
     data = boundary_data(cfg)
     dg = DG(Problem(cfg, data))
     x = random_state(cfg)
@@ -122,7 +112,7 @@ def test_bv_parameter_derivatives(ion):
 
 @pytest.mark.parametrize("ion", [1, 3])
 def test_bv_charge_balance_and_adjoint(ion):
-    cfg = _bv2d(ion)
+    cfg = bv2d(ion)
     data = boundary_data(cfg)
     dg = DG(Problem(cfg, data))
     x, hist = solve.newton(dg, tol=1e-13)

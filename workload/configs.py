@@ -104,11 +104,13 @@ CONFIGS["cfg3s"] = CONFIGS["cfg3"].with_(name="cfg3s", n=(8, 4, 2), hi=(1.0, 0.5
 # y = 0 anode (applied potential 0) and y = y_max cathode (applied potential
 # 0.03 V, i.e. 0.03 F/RT = 1.1676 nondimensional), alpha_1 = alpha_2 = 0.5 and
 # n = 2 (exponents alpha n = 1), the exchange current with the paper's parabolic
-# profile across z; the reacting ion is the doubly charged cation (ion 3,
-# eliminated by electroneutrality); the potential is free (natural) on the
-# electrodes, where the Butler-Volmer current fixes it.
+# profile across z; the reacting ion is the cation of the first species (a
+# primary unknown: the eliminated ion's concentration (c_2 - c_1)/2 is near
+# zero for inflow data drawn from U[0.5, 1.5], too little for the cathode to
+# balance the anode); the potential is free (natural) on the electrodes, where
+# the Butler-Volmer current fixes it.
 _BV = dict(c_bc=(C_INFLOW, C_OUTFLOW, C_ELECTRODE, C_ELECTRODE, 0, 0), phi_bc=(0,) * 6,
-           phi_val=(0.0,) * 6, bv_ion=3, bv_alpha=(1.0, 1.0), bv_j0=(0.0, 0.0, 1.0, 1.0, 0.0, 0.0),
+           phi_val=(0.0,) * 6, bv_ion=1, bv_alpha=(1.0, 1.0), bv_j0=(0.0, 0.0, 1.0, 1.0, 0.0, 0.0),
            bv_phi_app=(0.0, 0.0, 0.0, 1.1676, 0.0, 0.0), bv_j0_profile=J0_PARABOLIC_Z)
 CONFIGS["bv3s"] = CONFIGS["cfg3s"].with_(name="bv3s", note="BV channel 8x4x2 p=3", **_BV)
 CONFIGS["bv3"] = CONFIGS["cfg3"].with_(name="bv3", note="BV channel 64x16x8 p=3", **_BV)
