@@ -32,12 +32,13 @@ PEAK_FP32_TFLOPS = 157.3       # vector FP32 (published; counts packed FP32 FMAs
 PEAK_FP32_UNPACKED_TFLOPS = 78.6  # 256 CUs x 64 lanes x 2 flops x 2.4 GHz (packed FP32 disabled at compile time)
 PEAK_FP64_TFLOPS = 78.6        # vector FP64
 METRIC = "Newton-GMRES time-to-1e-8 (FP64 vs mixed); Jacobian-apply HBM GB/s"
+REPS = 5  # repetitions behind every median of the extra legs
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--apply-workload", default="cfg5")
@@ -127,6 +128,17 @@ def source_hash(*names):
     return h.hexdigest()[:16]
 
 
+def profile_ranking(workload):
+    """The dominant kernel family of this workload's timed solve by total kernel
+    time in the committed rocprofv3 statistics, with its average duration."""
+    path = os.path.join(ROOT, "profiles", "dominant_kernels.json")
+    try:
+        with open(path) as f:
+            return json.load(f).get(workload)
+    except (OSError, ValueError):
+        return None
+
+
 def measured_traffic(kernel_key, src_hash):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when it is missing or was taken on different kernel sources."""
@@ -142,9 +154,11 @@ def measured_traffic(kernel_key, src_hash):
 
 
 # ---- legs ---------------------------------------------------------------------------
-def cpu_baseline():
+def cpu_baseline(gpu_same_input_s):
     """The oracle (NumPy/SciPy, SuperLU) solving the same physics on a bounded
-    sample: the 4^3-element cube (1/64 of the elements), to the same 1e-8."""
+    sample: the 4^3-element cube (1/64 of the elements; the 16^3 cube's direct
+    solves do not finish in minutes), to the same 1e-8, with all host threads;
+    the GPU's mixed solve of that same sample is reported beside it."""
     from threadpoolctl import threadpool_info
 
     from oracle import solve as osolve
@@ -160,7 +174,54 @@ def cpu_baseline():
     return {"value": dt, "unit": "s", "cores": threads, "kind": "oracle",
             "sample": f"oracle Newton + SuperLU to 1e-8 on the same physics with 4^3 elements "
                       f"({od.N} DOFs, 1/64 of the workload's elements; {len(hist) - 1} Newton steps); "
-                      "SuperLU factorisation is single-threaded, BLAS parts use the listed threads"}
+                      "SuperLU factorisation is single-threaded, BLAS parts use the listed threads",
+            "gpu_mixed_same_input_s": gpu_same_input_s,
+            "oracle_over_gpu_same_input": dt / gpu_same_input_s if gpu_same_input_s else None}
+
+
+def oracle_operator_timings(names=("cfg2", "cfg3", "cfg5"), reps=3):
+    """The oracle's vectorised residual and Jacobian apply (NumPy, full tabulated
+    basis matrices) on the bench's operator inputs, median of `reps` after one
+    warm-up, with one BLAS thread and with all host threads."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle.dg import DG
+    from oracle.problem import Problem as OProblem
+    from workload import boundary_data, get_config, random_state, random_vector
+    import numpy as np
+    allt = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    out = {"cores_all": allt, "cpu": _cpu_model()}
+    for name in names:
+        cfg = get_config(name)
+        od = DG(OProblem(cfg, boundary_data(cfg)))
+        x, v = random_state(cfg), random_vector(cfg)
+        rec = {"dofs": od.N}
+        for label, lim in (("1_thread", 1), ("all_threads", allt)):
+            with threadpool_limits(limits=lim):
+                for what, fn in (("residual_s", lambda: od.residual(x)), ("jac_apply_s", lambda: od.jac_apply(x, v))):
+                    fn()
+                    ts = []
+                    for _ in range(reps):
+                        t0 = time.perf_counter()
+                        fn()
+                        ts.append(time.perf_counter() - t0)
+                    rec[f"{what}_{label}"] = float(np.median(ts))
+        out[name] = rec
+        log(f"[bench] oracle {name}: residual {rec['residual_s_1_thread']:.2f}/{rec['residual_s_all_threads']:.2f} s, "
+            f"J apply {rec['jac_apply_s_1_thread']:.2f}/{rec['jac_apply_s_all_threads']:.2f} s (1/all threads)")
+        del od
+    return out
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def apply_bandwidth(name, reps=20):
@@ -198,13 +259,26 @@ def apply_bandwidth(name, reps=20):
         if word == 4:  # without packed FP32 instructions one lane retires one FP32 FMA per cycle
             out[tag]["alu_frac_unpacked_issue"] = tfl / PEAK_FP32_UNPACKED_TFLOPS
         log(f"[bench] J apply {tag} on {cfg.name}: {1e6 * sec:.1f} us, {gbs:.0f} GB/s, {tfl:.2f} TFLOP/s")
+        # the coupling block of Eq. P2 (potential rows, concentration input)
+        ycs = [torch.empty(prob.Nf, dtype=dt_, device="cuda") for _ in range(4)]
+        for i in range(3):
+            D.dgnp_coupling_apply(prob.ctx, vs[i % 4].data_ptr(), ycs[i % 4].data_ptr(), prec, st)
+        torch.cuda.synchronize()
+        e0.record()
+        for i in range(reps):
+            D.dgnp_coupling_apply(prob.ctx, vs[i % 4].data_ptr(), ycs[i % 4].data_ptr(), prec, st)
+        e1.record()
+        torch.cuda.synchronize()
+        csec = e0.elapsed_time(e1) * 1e-3 / reps
+        out[tag]["coupling_us_per_apply"] = 1e6 * csec
+        out[tag]["coupling_over_full_apply"] = csec / sec
     prob.close()
     return out
 
 
 def channel_solves(names):
     """Time-to-solution on the channel configurations: mixed and FP64 solves from
-    the initial guess to 1e-8 (after one untimed mixed solve), their agreement,
+    the initial guess to 1e-8 (medians of REPS runs after one untimed run of each), their agreement,
     on the largest one a mixed-precision adjoint gradient, and the mixed solve
     with the other potential-block multigrids."""
     import torch
@@ -226,20 +300,31 @@ def channel_solves(names):
                 raise RuntimeError(f"{name} solve failed with status {st.status}")
             return x, st, time.perf_counter() - t0
 
+        import numpy as np
         run(DGNP_F32)
-        x32, st32, t32 = run(DGNP_F32)
-        x64, st64, t64 = run(DGNP_F64)
+        runs32 = [run(DGNP_F32) for _ in range(REPS)]
+        x32, st32 = runs32[-1][0], runs32[-1][1]
+        t32 = float(np.median([r[2] for r in runs32]))
+        del runs32[:-1]
+        run(DGNP_F64)
+        runs64 = [run(DGNP_F64) for _ in range(REPS)]
+        x64, st64 = runs64[-1][0], runs64[-1][1]
+        t64 = float(np.median([r[2] for r in runs64]))
+        del runs64
         rec.update({"mixed_s": t32, "fp64_s": t64, "mixed_speedup_vs_fp64": t64 / t32,
                     "newton_its": st32.newton_its, "fgmres_its_mixed": st32.lin_its_total,
                     "fgmres_its_fp64": st64.lin_its_total, "setup_s_mixed": st32.t_setup,
                     "krylov_s_mixed": st32.t_krylov,
                     "mixed_vs_fp64_rel_l2": (x64 - x32).norm().item() / x64.norm().item()})
         if name == names[-1]:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            prob.adjoint(x32, prec=DGNP_F32, rtol=1e-8)
-            torch.cuda.synchronize()
-            rec["adjoint_s"] = time.perf_counter() - t0
+            ta = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                prob.adjoint(x32, prec=DGNP_F32, rtol=1e-8)
+                torch.cuda.synchronize()
+                ta.append(time.perf_counter() - t0)
+            rec["adjoint_s"] = float(np.median(ta))
         log(f"[bench] {name}: mixed {t32:.3f}s fp64 {t64:.3f}s ({st32.lin_its_total} / {st64.lin_its_total} its)")
         prob.close()
         del x64
@@ -341,8 +426,12 @@ def main():
     solve(DGNP_F32)
     kern = prob.timers()
     prob.profile(False)
-    # roofline of the dominant kernel: the kernel family with the largest
-    # event-timed total among those with an algorithmic byte model
+    # roofline of the dominant kernel.  The family is the one with the largest
+    # total kernel time in the committed rocprofv3 statistics of this solve
+    # (profiles/dominant_kernels.json, written from the kernel-trace summary);
+    # its average launch duration is measured here with the library's per-launch
+    # HIP events on its own stream (they include the dispatch gap that the
+    # profiler's durations exclude, so the fraction is slightly low).
     models = {
         "cheb_blk_f32": (cheb_blk_bytes(cfg, 4),
                          "k_cheb_blk<float> (fused Chebyshev step of the potential smoother on the element blocks)"),
@@ -350,24 +439,33 @@ def main():
                         "k_ilu_dfp<fwd> (dataflow BILU(0) forward sweep, both concentration blocks)"),
         "ilu_bwd_f32": (ilu_sweep_bytes(cfg, 4, backward=True),
                         "k_ilu_dfp<bwd> (dataflow BILU(0) backward sweep, both concentration blocks)"),
-        "jac_apply_f32": (float(japply_bytes(prob.N, 4)), "k_dg<JAC, float> (Jacobian apply)"),
+        "jac_apply_f32": (float(japply_bytes(prob.N, 4)), "k_jlin<float> (Jacobian apply, tabulated state)"),
     }
     present = {k: v for k, v in kern.items() if k in models}
-    dom = max(present.items(), key=lambda kv: kv[1][0])[0]
+    ranking = profile_ranking(cfg.name)
+    if ranking and ranking.get("family") in present:
+        dom, chosen_by = ranking["family"], "largest total kernel time in the rocprofv3 statistics of this solve"
+    else:
+        dom = max(present.items(), key=lambda kv: kv[1][0])[0]
+        chosen_by = "largest event-timed total (no rocprofv3 ranking for this workload)"
     tot, launches = kern[dom]
     avg = tot / launches
     per_launch_bytes, kname = models[dom]
     achieved = per_launch_bytes / avg / 1e9
     keys = {"cheb_blk_f32": "k_cheb_blk_f32_cfg2", "ilu_fwd_f32": "k_ilu_dfp_fwd_cfg2",
-            "ilu_bwd_f32": "k_ilu_dfp_bwd_cfg2", "jac_apply_f32": "k_dg_jac_f32_cfg2"}
-    srcs = ("kernels_dg.hip", "dg_device.hpp", "pointwise.hpp") if dom == "jac_apply_f32" else ("kernels_block.hip",)
+            "ilu_bwd_f32": "k_ilu_dfp_bwd_cfg2", "jac_apply_f32": "k_jlin_f32_cfg2"}
+    srcs = ("kernels_jac.hip", "dg_device.hpp", "pointwise.hpp") if dom == "jac_apply_f32" else ("kernels_block.hip",)
     copy_gbs = copy_bandwidth()
     roofline = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "avg_launch_us": 1e6 * avg, "launches": launches,
-                "bytes_per_launch": per_launch_bytes,
+                "bytes_per_launch": per_launch_bytes, "chosen_by": chosen_by,
                 "traffic": measured_traffic(keys[dom], source_hash(*srcs)),
                 # context, not the peak: what a plain device-to-device copy sustains here
                 "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs if copy_gbs else None}
+    if ranking and ranking.get("family") == dom and ranking.get("avg_us"):
+        # the same kernel's average duration in the committed profile, for comparison
+        roofline["rocprof_avg_launch_us"] = ranking["avg_us"]
+        roofline["frac_rocprof"] = per_launch_bytes / (1e-6 * ranking["avg_us"]) / 1e9 / PEAK_HBM_GBS
     log(f"[bench] dominant kernel {dom}: {tot:.3f}s in {launches} launches, {1e6 * avg:.2f} us/launch, "
         f"{achieved:.0f} GB/s")
     others = {}
@@ -396,27 +494,49 @@ def main():
         "other_kernels": others,
         "kernel_seconds_per_solve": {k: round(v[0], 6) for k, v in kern.items()},
     }
+    out["median_step_s"] = float(np.median(times))
     if not args.no_extra:
-        x64, st64, t64 = solve(DGNP_F64)
+        solve(DGNP_F64)
+        r64 = [solve(DGNP_F64) for _ in range(REPS)]
+        x64, st64 = r64[-1][0], r64[-1][1]
+        t64 = float(np.median([r[2] for r in r64]))
+        del r64
         out["fp64_time_s"] = t64
         out["mixed_speedup_vs_fp64"] = t64 / t_mixed
         out["mixed_vs_fp64_rel_l2"] = (x64 - x32).norm().item() / x64.norm().item()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        J, dg, dpe, lam, ast = prob.adjoint(x32, prec=DGNP_F32, rtol=1e-8)
-        torch.cuda.synchronize()
-        out["adjoint_time_s"] = time.perf_counter() - t0
+        ta = []
+        for _ in range(REPS):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            J, dg, dpe, lam, ast = prob.adjoint(x32, prec=DGNP_F32, rtol=1e-8)
+            torch.cuda.synchronize()
+            ta.append(time.perf_counter() - t0)
+        out["adjoint_time_s"] = float(np.median(ta))
         log(f"[bench] fp64 {t64:.3f}s, adjoint {out['adjoint_time_s']:.3f}s")
         prob.close()
         ja = apply_bandwidth(args.apply_workload)
-        ja["traffic_f32"] = measured_traffic("k_dg_jac_f32_cfg5", source_hash("kernels_dg.hip", "dg_device.hpp",
-                                                                              "pointwise.hpp"))
+        ja["traffic_f32"] = measured_traffic("k_jlin_f32_cfg5", source_hash("kernels_jac.hip", "dg_device.hpp",
+                                                                            "pointwise.hpp"))
         out["jacobian_apply"] = ja
         out["channel_solves"] = channel_solves(["cfg3", "cfg5"])
     if not args.no_cpu:
-        cb = cpu_baseline()
-        log(f"[bench] cpu oracle: {cb['value']:.2f}s ({cb['sample']})")
+        # the GPU's mixed solve of the oracle's sample input, beside the oracle
+        small = get_config("cfg2t")
+        sp = Problem(small, boundary_data(small))
+        sp.solve(rtol=small.newton_tol, prec=DGNP_F32)
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sp.solve(rtol=small.newton_tol, prec=DGNP_F32)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        sp.close()
+        cb = cpu_baseline(float(np.median(ts)))
+        log(f"[bench] cpu oracle: {cb['value']:.2f}s ({cb['sample']}); GPU on the same input {np.median(ts):.4f}s")
         out["cpu_baseline"] = cb
+        if not args.no_extra:
+            out["oracle_operator_timings"] = oracle_operator_timings()
     print(json.dumps(out), flush=True)
 
 

@@ -1,6 +1,7 @@
 // Vector kernels for the Krylov and Newton drivers.  Reductions are two-pass
 // (fixed block partials, then one block), so results do not depend on timing.
 #include "blas.hpp"
+#include <cmath>
 
 namespace dgnp {
 
@@ -233,7 +234,7 @@ double vdot(const double* x, const double* y, int64_t n, double* scratch_dev, hi
 
 double vnorm2(const double* x, int64_t n, double* scratch_dev, hipStream_t s) {
   double d = vdot(x, x, n, scratch_dev, s);
-  return d > 0.0 ? sqrt(d) : 0.0;
+  return std::isnan(d) ? d : (d > 0.0 ? sqrt(d) : 0.0);  // a NaN entry must not read as a zero norm
 }
 
 // partial[blk] = sum over the block's chunk of x^2 (accumulated in double)
@@ -279,7 +280,7 @@ double vnorm2(const float* x, int64_t n, double* scratch_dev, hipStream_t s) {
   double h = 0.0;
   DGNP_HIP(hipMemcpyAsync(&h, scratch_dev, sizeof(double), hipMemcpyDeviceToHost, s));
   DGNP_HIP(hipStreamSynchronize(s));
-  return h > 0.0 ? sqrt(h) : 0.0;
+  return std::isnan(h) ? h : (h > 0.0 ? sqrt(h) : 0.0);
 }
 
 // ---- delayed classical Gram-Schmidt (reorthogonalisation one step late) -------
@@ -363,7 +364,7 @@ __device__ void dcgs_scalars_block(double* __restrict__ out, int j, int with_w, 
   }
   if (threadIdx.x == 0) {
     const double a2 = out[j] - ss;
-    const double alpha = a2 > 0.0 ? sqrt(a2) : 0.0;
+    const double alpha = __builtin_isnan(a2) ? a2 : (a2 > 0.0 ? sqrt(a2) : 0.0);  // NaN reaches the host check
     const double ia = alpha > 0.0 ? 1.0 / alpha : 0.0;
     out[DC_ALPHA] = alpha;
     out[DC_IALPHA] = ia;

@@ -1578,13 +1578,17 @@ __global__ void __launch_bounds__(BT) k_q1_galerkin(const double* __restrict__ b
 // sweep instead of one per hyperplane level: the grid is small enough to be
 // resident on the device at once, work-group b takes the elements b, b + G,
 // b + 2G, ... of the level order (reversed for the backward sweep), and an
-// element waits only for the neighbours it reads.  Each element has a
-// completion counter per sweep direction; an element that has completed s
-// sweeps waits until its neighbours' counters reach s + 1, so no reset is
-// needed between sweeps (and a captured graph can replay them).  Vector
-// entries and counters that cross work-groups are written and read with
-// device-scope relaxed atomics (coherent across the XCD caches); the writer
-// waits for its stores to complete before it publishes the counter.  The
+// element waits only for the neighbours it reads.  Every exchanged vector
+// entry travels together with its sweep count in 64-bit words (count high,
+// 32 value bits low: one word per single-precision entry, two per double, the
+// low half of the double first), written and read with device-scope relaxed
+// atomics.  A consumer polls each word it needs until the word carries the
+// sweep's count; since a word is written and read whole, the value bits it
+// holds are the ones published with that count, and no ordering between
+// different words (no counter, no fence, no wait for store completion) is
+// needed.  An element that has completed s sweeps expects count s + 1, so no
+// reset is needed between sweeps (and a captured graph can replay them).  The
+// plain result is also written to `out` for the kernels that follow.  The
 // residency of the whole grid makes the schedule deadlock-free (the least
 // unfinished element always has its inputs); a wait that exceeds its spin
 // limit sets *err and ends the work-group, so the sweep cannot hang.  Once
@@ -1622,42 +1626,80 @@ __device__ __forceinline__ bool df_failed(const int* err, int* s_abort, int tid)
   return *s_abort != 0;
 }
 
-// wait until cnt[j] >= target for every valid j in nb[0..n): one thread per
-// entry; the counter load acquires what its producer released
-__device__ inline void df_wait(const unsigned* cnt, const int* nb, int n, unsigned target, int spin_limit,
-                               int* err, int* s_abort, int tid) {
-  if (tid < n) {
-    const int j = nb[tid];
-    if (j >= 0) {
-      int spins = 0;
-      while (__hip_atomic_load(cnt + j, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        if (df_give_up(++spins, spin_limit, err)) {
-          st_dev(err, 1);
-          *s_abort = 1;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
-      }
-    }
+// packed words per vector entry
+template <typename T>
+struct DfWords;
+template <>
+struct DfWords<float> {
+  static constexpr int W = 1;
+  __device__ static unsigned half(float v, int) { return __float_as_uint(v); }
+  __device__ static float join(const unsigned* h) { return __uint_as_float(h[0]); }
+};
+template <>
+struct DfWords<double> {
+  static constexpr int W = 2;
+  __device__ static unsigned half(double v, int k) {
+    const uint64_t b = uint64_t(__double_as_longlong(v));
+    return unsigned(k == 0 ? b : b >> 32);
   }
-  __syncthreads();
-  // the other threads of the work-group read the neighbours' results next
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __device__ static double join(const unsigned* h) {
+    return __longlong_as_double((long long)((uint64_t(h[1]) << 32) | uint64_t(h[0])));
+  }
+};
+
+// publish entry `e` (word index e * W) with sweep count `target`
+template <typename T>
+__device__ __forceinline__ void df_publish(uint64_t* wp, int64_t e, unsigned target, T v) {
+  constexpr int W = DfWords<T>::W;
+#pragma unroll
+  for (int k = 0; k < W; ++k) st_dev(wp + e * W + k, (uint64_t(target) << 32) | uint64_t(DfWords<T>::half(v, k)));
+}
+
+// the sweep count published with entry e (its first word)
+template <typename T>
+__device__ __forceinline__ unsigned df_count(const uint64_t* wp, int64_t e) {
+  return unsigned(ld_dev(wp + e * DfWords<T>::W) >> 32);
+}
+
+// poll entry e until every word of it carries `target`; false when the wait
+// gave up (then *err is set)
+template <typename T, int SLEEP>
+__device__ __forceinline__ bool df_fetch(const uint64_t* wp, int64_t e, unsigned target, int spin_limit, int* err,
+                                         T* v) {
+  constexpr int W = DfWords<T>::W;
+  unsigned h[W];
+  int spins = 0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    const uint64_t* src = wp + e * W + k;
+    uint64_t word = ld_dev(src);
+    while (unsigned(word >> 32) != target) {
+      if (df_give_up(++spins, spin_limit, err)) {
+        st_dev(err, 1);
+        return false;
+      }
+      __builtin_amdgcn_s_sleep(SLEEP);
+      word = ld_dev(src);
+    }
+    h[k] = unsigned(word);
+  }
+  *v = DfWords<T>::join(h);
+  return true;
 }
 
 // kind 0 (forward): w_i = D_i^{-1} r_i - sum_{s lower} Lhat_{i,s} w_nbr
 // kind 1 (backward): z_i = w_i - sum_{s upper} Uhat_{i,s} z_nbr   (z may alias w)
 template <typename T, int NB, int DIM, int KIND>
-__global__ void __launch_bounds__(BT) k_ilu_df(const T* __restrict__ blk, const int* __restrict__ nbr,
-                                               const int* __restrict__ order, int64_t E, const T* in, T* out,
-                                               int64_t bstride, int64_t vstride, unsigned* cnt, int* err,
-                                               int spin_limit) {
+__global__ void __launch_bounds__(BT) k_ilu_dfp(const T* __restrict__ blk, const int* __restrict__ nbr,
+                                                const int* __restrict__ order, int64_t E, const T* in, T* out,
+                                                int64_t bstride, int64_t vstride, uint64_t* wp, int* err,
+                                                int spin_limit) {
   constexpr int NSLOT = 2 * DIM + 1;
   constexpr int QL = (NB + 3) / 4;
   blk += blockIdx.y * bstride;
   in += blockIdx.y * vstride;
   out += blockIdx.y * vstride;
-  cnt += blockIdx.y * E;
+  wp += blockIdx.y * vstride * DfWords<T>::W;
   __shared__ T xs[DIM + 1][NB];
   __shared__ int s_nb[DIM];
   __shared__ int s_abort;
@@ -1683,19 +1725,20 @@ __global__ void __launch_bounds__(BT) k_ilu_df(const T* __restrict__ blk, const 
       }
     }
     for (int idx = tid; idx < NB; idx += BT) xs[0][idx] = in[i * NB + idx];
-    const unsigned target = ld_dev(cnt + i) + 1u;
+    const unsigned target = df_count<T>(wp, i * NB) + 1u;
     __syncthreads();
-    df_wait(cnt, s_nb, DIM, target, spin_limit, err, &s_abort, tid);
+    for (int idx = tid; idx < DIM * NB; idx += BT) {
+      const int d = idx / NB, l = idx % NB;
+      const int j = s_nb[d];
+      T v = T(0);
+      if (j >= 0 && !df_fetch<T, 1>(wp, int64_t(j) * NB + l, target, spin_limit, err, &v)) s_abort = 1;
+      xs[1 + d][l] = v;
+    }
+    __syncthreads();
     if (s_abort) {
       df_poison<T, NB>(out, i, tid);
       return;
     }
-    for (int idx = tid; idx < DIM * NB; idx += BT) {
-      const int d = idx / NB, l = idx % NB;
-      const int j = s_nb[d];
-      xs[1 + d][l] = j >= 0 ? ld_dev(out + int64_t(j) * NB + l) : T(0);
-    }
-    __syncthreads();
     if (row < NB) {
       T acc = T(0);
       if constexpr (KIND == 0) {
@@ -1712,102 +1755,8 @@ __global__ void __launch_bounds__(BT) k_ilu_df(const T* __restrict__ blk, const 
       acc += __shfl_xor(acc, 1, 64);
       acc += __shfl_xor(acc, 2, 64);
       if (KIND == 1) acc = xs[0][row] + acc;
-      if (part == 0) st_dev(out + i * NB + row, acc);
-    }
-    // every thread releases its stores at agent scope, then one thread
-    // publishes the element's count with a release store
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (tid == 0) __hip_atomic_store(cnt + i, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
-// Single-precision variant: every exchanged vector entry travels together
-// with its sweep count in one 64-bit word (value bits low, count high), so a
-// consumer polls the entries it needs directly and a producer publishes a row
-// with one store; no separate counter, no wait for store completion.  The
-// plain result is also written to `out` for the kernels that follow.
-template <int NB, int DIM, int KIND>
-__global__ void __launch_bounds__(BT) k_ilu_dfp(const float* __restrict__ blk, const int* __restrict__ nbr,
-                                                const int* __restrict__ order, int64_t E, const float* in,
-                                                float* out, int64_t bstride, int64_t vstride, uint64_t* wp, int* err,
-                                                int spin_limit) {
-  constexpr int NSLOT = 2 * DIM + 1;
-  constexpr int QL = (NB + 3) / 4;
-  blk += blockIdx.y * bstride;
-  in += blockIdx.y * vstride;
-  out += blockIdx.y * vstride;
-  wp += blockIdx.y * vstride;
-  __shared__ float xs[DIM + 1][NB];
-  __shared__ int s_nb[DIM];
-  __shared__ int s_abort;
-  const int tid = threadIdx.x, row = tid >> 2, part = tid & 3;
-  if (df_failed(err, &s_abort, tid)) {
-    if (int64_t(blockIdx.x) < E) df_poison<float, NB>(out, order[KIND == 0 ? blockIdx.x : E - 1 - blockIdx.x], tid);
-    return;
-  }
-  for (int64_t t = blockIdx.x; t < E; t += gridDim.x) {
-    const int64_t i = order[KIND == 0 ? t : E - 1 - t];
-    if (tid < DIM) s_nb[tid] = nbr[i * 2 * DIM + 2 * tid + KIND];
-    const float* bi = blk + i * NSLOT * NB * NB;
-    float m[DIM + 1][QL];
-#pragma unroll
-    for (int b = 0; b <= DIM; ++b) {
-      const int slot = KIND == 0 ? (b == 0 ? 0 : 1 + 2 * (b - 1)) : (b == 0 ? 0 : 2 + 2 * (b - 1));
-#pragma unroll
-      for (int c = 0; c < QL; ++c) {
-        const int cc = part * QL + c;
-        m[b][c] = (row < NB && cc < NB && (KIND == 0 || b > 0)) ? bi[int64_t(slot) * NB * NB + row * NB + cc]
-                                                                  : 0.0f;
-      }
-    }
-    for (int idx = tid; idx < NB; idx += BT) xs[0][idx] = in[i * NB + idx];
-    const unsigned target = unsigned(ld_dev(wp + i * NB) >> 32) + 1u;
-    __syncthreads();
-    for (int idx = tid; idx < DIM * NB; idx += BT) {
-      const int d = idx / NB, l = idx % NB;
-      const int j = s_nb[d];
-      float v = 0.0f;
-      if (j >= 0) {
-        const uint64_t* src = wp + int64_t(j) * NB + l;
-        uint64_t word = ld_dev(src);
-        int spins = 0;
-        while (unsigned(word >> 32) != target) {
-          if (df_give_up(++spins, spin_limit, err)) {
-            st_dev(err, 1);
-            s_abort = 1;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          word = ld_dev(src);
-        }
-        v = __uint_as_float(unsigned(word));
-      }
-      xs[1 + d][l] = v;
-    }
-    __syncthreads();
-    if (s_abort) {
-      df_poison<float, NB>(out, i, tid);
-      return;
-    }
-    if (row < NB) {
-      float acc = 0.0f;
-      if constexpr (KIND == 0) {
-#pragma unroll
-        for (int c = 0; c < QL; ++c) acc += m[0][c] * xs[0][part * QL + c < NB ? part * QL + c : 0];
-      }
-#pragma unroll
-      for (int b = 1; b <= DIM; ++b) {
-        float sb = 0.0f;
-#pragma unroll
-        for (int c = 0; c < QL; ++c) sb += m[b][c] * xs[b][part * QL + c < NB ? part * QL + c : 0];
-        acc -= sb;
-      }
-      acc += __shfl_xor(acc, 1, 64);
-      acc += __shfl_xor(acc, 2, 64);
-      if (KIND == 1) acc = xs[0][row] + acc;
       if (part == 0) {
-        st_dev(wp + i * NB + row, (uint64_t(target) << 32) | uint64_t(__float_as_uint(acc)));
+        df_publish<T>(wp, i * NB + row, target, acc);
         out[i * NB + row] = acc;
       }
     }
@@ -2283,43 +2232,27 @@ void launch_vertex_stencil(int dim, const double* gal, const int* nbr, const int
 }
 
 template <typename T, int NB, int DIM>
-static void df_t(int kind, const T* blk, const int* nbr, const int* order, int64_t E, int nfields,
-                 int64_t bstride, int64_t vstride, const T* in, T* out, unsigned* cnt, int* err, int spin_limit,
-                 int grid, hipStream_t s) {
+static void dfp_t(int kind, const T* blk, const int* nbr, const int* order, int64_t E, int nfields, int64_t bstride,
+                  int64_t vstride, const T* in, T* out, uint64_t* wp, int* err, int spin_limit, int grid,
+                  hipStream_t s) {
   const dim3 g = dim3(unsigned(grid), unsigned(nfields)), b = dim3(BT);
   if (kind == 0)
-    hipLaunchKernelGGL((k_ilu_df<T, NB, DIM, 0>), g, b, 0, s, blk, nbr, order, E, in, out, bstride, vstride, cnt,
+    hipLaunchKernelGGL((k_ilu_dfp<T, NB, DIM, 0>), g, b, 0, s, blk, nbr, order, E, in, out, bstride, vstride, wp,
                        err, spin_limit);
   else
-    hipLaunchKernelGGL((k_ilu_df<T, NB, DIM, 1>), g, b, 0, s, blk, nbr, order, E, in, out, bstride, vstride, cnt,
+    hipLaunchKernelGGL((k_ilu_dfp<T, NB, DIM, 1>), g, b, 0, s, blk, nbr, order, E, in, out, bstride, vstride, wp,
                        err, spin_limit);
-}
-
-template <int NB, int DIM>
-static void dfp_t(int kind, const float* blk, const int* nbr, const int* order, int64_t E, int nfields,
-                  int64_t bstride, int64_t vstride, const float* in, float* out, uint64_t* wp, int* err,
-                  int spin_limit, int grid, hipStream_t s) {
-  const dim3 g = dim3(unsigned(grid), unsigned(nfields)), b = dim3(BT);
-  if (kind == 0)
-    hipLaunchKernelGGL((k_ilu_dfp<NB, DIM, 0>), g, b, 0, s, blk, nbr, order, E, in, out, bstride, vstride, wp, err,
-                       spin_limit);
-  else
-    hipLaunchKernelGGL((k_ilu_dfp<NB, DIM, 1>), g, b, 0, s, blk, nbr, order, E, in, out, bstride, vstride, wp, err,
-                       spin_limit);
 }
 
 template <typename T, int NB, int DIM>
 static int df_resident(int nfields) {
-  int dev = 0, ncu = 0, per_cu = 0;
+  int dev = 0, ncu = 0;
   DGNP_HIP(hipGetDevice(&dev));
   DGNP_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  int occ[4] = {0, 0, 0, 0};
-  DGNP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], (k_ilu_df<T, NB, DIM, 0>), BT, 0));
-  DGNP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], (k_ilu_df<T, NB, DIM, 1>), BT, 0));
-  DGNP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[2], (k_ilu_dfp<NB, DIM, 0>), BT, 0));
-  DGNP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[3], (k_ilu_dfp<NB, DIM, 1>), BT, 0));
-  per_cu = std::min(std::min(occ[0], occ[1]), std::min(occ[2], occ[3]));
-  return (ncu * per_cu) / (2 * nfields);  // half the resident capacity per field
+  int occ[2] = {0, 0};
+  DGNP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[0], (k_ilu_dfp<T, NB, DIM, 0>), BT, 0));
+  DGNP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ[1], (k_ilu_dfp<T, NB, DIM, 1>), BT, 0));
+  return (ncu * std::min(occ[0], occ[1])) / (2 * nfields);  // half the resident capacity per field
 }
 
 template <typename T>
@@ -2348,42 +2281,21 @@ template int ilu_dataflow_grid<float>(int, int, int64_t, int);
 
 template <typename T>
 void launch_ilu_dataflow(int kind, int nb, int dim, const T* blk, const int* nbr, const int* order, int64_t E,
-                         int nfields, int64_t bstride, int64_t vstride, const T* in, T* out, unsigned* cnt, int* err,
+                         int nfields, int64_t bstride, int64_t vstride, const T* in, T* out, uint64_t* wp, int* err,
                          int spin_limit, int grid, hipStream_t s) {
   if (E == 0 || nfields == 0) return;
   if (dim == 3) {
     switch (nb) {
-      case 8: df_t<T, 8, 3>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, cnt, err, spin_limit, grid, s); break;
-      case 27: df_t<T, 27, 3>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, cnt, err, spin_limit, grid, s); break;
-      case 64: df_t<T, 64, 3>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, cnt, err, spin_limit, grid, s); break;
+      case 8: dfp_t<T, 8, 3>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
+      case 27: dfp_t<T, 27, 3>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
+      case 64: dfp_t<T, 64, 3>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
       default: throw Error(DGNP_E_ARG, "unsupported block size");
     }
   } else {
     switch (nb) {
-      case 4: df_t<T, 4, 2>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, cnt, err, spin_limit, grid, s); break;
-      case 9: df_t<T, 9, 2>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, cnt, err, spin_limit, grid, s); break;
-      case 16: df_t<T, 16, 2>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, cnt, err, spin_limit, grid, s); break;
-      default: throw Error(DGNP_E_ARG, "unsupported block size");
-    }
-  }
-  DGNP_HIP(hipGetLastError());
-}
-void launch_ilu_dataflow_packed(int kind, int nb, int dim, const float* blk, const int* nbr, const int* order,
-                                int64_t E, int nfields, int64_t bstride, int64_t vstride, const float* in, float* out,
-                                uint64_t* wp, int* err, int spin_limit, int grid, hipStream_t s) {
-  if (E == 0 || nfields == 0) return;
-  if (dim == 3) {
-    switch (nb) {
-      case 8: dfp_t<8, 3>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
-      case 27: dfp_t<27, 3>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
-      case 64: dfp_t<64, 3>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
-      default: throw Error(DGNP_E_ARG, "unsupported block size");
-    }
-  } else {
-    switch (nb) {
-      case 4: dfp_t<4, 2>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
-      case 9: dfp_t<9, 2>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
-      case 16: dfp_t<16, 2>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
+      case 4: dfp_t<T, 4, 2>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
+      case 9: dfp_t<T, 9, 2>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
+      case 16: dfp_t<T, 16, 2>(kind, blk, nbr, order, E, nfields, bstride, vstride, in, out, wp, err, spin_limit, grid, s); break;
       default: throw Error(DGNP_E_ARG, "unsupported block size");
     }
   }
@@ -2462,9 +2374,9 @@ void launch_ilu_lines(int kind, int nb, int dim, const float* blk, const int* nb
 }
 
 template void launch_ilu_dataflow<double>(int, int, int, const double*, const int*, const int*, int64_t, int, int64_t,
-                                          int64_t, const double*, double*, unsigned*, int*, int, int, hipStream_t);
+                                          int64_t, const double*, double*, uint64_t*, int*, int, int, hipStream_t);
 template void launch_ilu_dataflow<float>(int, int, int, const float*, const int*, const int*, int64_t, int, int64_t,
-                                         int64_t, const float*, float*, unsigned*, int*, int, int, hipStream_t);
+                                         int64_t, const float*, float*, uint64_t*, int*, int, int, hipStream_t);
 
 // One Chebyshev smoothing step on the element-block level, fused:
 //   r = base - A u - sub    (u null: no product; sub null: no subtrahend)

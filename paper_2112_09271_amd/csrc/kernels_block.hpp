@@ -23,20 +23,18 @@ template <typename T>
 void launch_ilu_solve(int kind, int nb, int dim, const T* blk, const int* nbr, const int* lev, int64_t first,
                       int64_t count, int nfields, int64_t bstride, int64_t vstride, const T* in, T* out, T* aux,
                       hipStream_t s);
-// dataflow sweeps (kind 0 forward, 1 backward) over the level order `order`
-// with per-element completion counters cnt[nfields][E]; grid from
+// dataflow sweeps (kind 0 forward, 1 backward) over the level order `order`;
+// every entry is published with its sweep count in packed 64-bit words,
+// wp[nfields][Nf * W] with W = 1 word per float entry and 2 per double (the
+// words of one buffer start at equal counts, zero at first); grid from
 // ilu_dataflow_grid (resident on the device at once)
 template <typename T>
 int ilu_dataflow_grid(int nb, int dim, int64_t E, int nfields);
 template <typename T>
 void launch_ilu_dataflow(int kind, int nb, int dim, const T* blk, const int* nbr, const int* order, int64_t E,
-                         int nfields, int64_t bstride, int64_t vstride, const T* in, T* out, unsigned* cnt, int* err,
+                         int nfields, int64_t bstride, int64_t vstride, const T* in, T* out, uint64_t* wp, int* err,
                          int spin_limit, int grid, hipStream_t s);
-// single precision with (value, sweep count) packed in the 64-bit words wp[nfields][Nf]
-void launch_ilu_dataflow_packed(int kind, int nb, int dim, const float* blk, const int* nbr, const int* order,
-                                int64_t E, int nfields, int64_t bstride, int64_t vstride, const float* in, float* out,
-                                uint64_t* wp, int* err, int spin_limit, int grid, hipStream_t s);
-// line sweeps (single precision, packed words as launch_ilu_dataflow_packed):
+// line sweeps (single precision, packed words as launch_ilu_dataflow):
 // lines of `len` elements along axis ax, first elements line_first[0..nline)
 // ordered by level, element stride lstride; grid from ilu_lines_grid
 int ilu_lines_grid(int nb, int dim, int nline, int nfields);

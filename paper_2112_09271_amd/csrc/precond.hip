@@ -148,9 +148,9 @@ struct Precond {
   DevBuf<float> vN32, yN32, tN32;
   DevBuf<double> red;
   PinnedStage stage;
-  // dataflow sweeps: completion counters [forward / backward][field][E], timeout flag
-  DevBuf<unsigned> df_cnt;
-  DevBuf<uint64_t> df_wp;   // single precision: packed (value, count) [forward / backward][field][Nf]
+  // dataflow sweeps: packed (value, count) words [forward / backward][field][Nf * W]
+  // (W = 1 in single, 2 in double precision), timeout flag
+  DevBuf<uint64_t> df_wp, df_wp64;
   DevBuf<int> df_err;
   int df_grid[2] = {0, 0};  // double, float
   int df_spin = 1 << 22;
@@ -254,11 +254,11 @@ void precond_symbolic(dgnp_ctx& c) {
   const double width = double(c.E) / double(P.lev_ptr.size() - 1);
   P.df_on = getenv("DGNP_NO_DATAFLOW") == nullptr && (width < 256.0 || getenv("DGNP_DATAFLOW") != nullptr);
   if (const char* sl = getenv("DGNP_DATAFLOW_SPIN")) P.df_spin = std::max(0, atoi(sl));
-  P.df_cnt.alloc(size_t(2) * nf * c.E);
   P.df_wp.alloc(size_t(2) * nf * c.Nf);
+  P.df_wp64.alloc(size_t(4) * nf * c.Nf);
   P.df_err.alloc(1);
-  DGNP_HIP(hipMemsetAsync(P.df_cnt.p, 0, P.df_cnt.n * sizeof(unsigned), c.stream));
   DGNP_HIP(hipMemsetAsync(P.df_wp.p, 0, P.df_wp.n * sizeof(uint64_t), c.stream));
+  DGNP_HIP(hipMemsetAsync(P.df_wp64.p, 0, P.df_wp64.n * sizeof(uint64_t), c.stream));
   DGNP_HIP(hipMemsetAsync(P.df_err.p, 0, sizeof(int), c.stream));
   DGNP_HIP(hipStreamSynchronize(c.stream));
   P.df_grid[0] = ilu_dataflow_grid<double>(c.nb, c.dim, c.E, nf);
@@ -312,8 +312,8 @@ void precond_check(dgnp_ctx& c, bool report) {
   DGNP_HIP(hipDeviceSynchronize());
   DGNP_HIP(hipMemcpy(&h, P.df_err.p, sizeof(int), hipMemcpyDeviceToHost));
   if (h == 0) return;
-  DGNP_HIP(hipMemset(P.df_cnt.p, 0, P.df_cnt.n * sizeof(unsigned)));
   DGNP_HIP(hipMemset(P.df_wp.p, 0, P.df_wp.n * sizeof(uint64_t)));
+  DGNP_HIP(hipMemset(P.df_wp64.p, 0, P.df_wp64.n * sizeof(uint64_t)));
   DGNP_HIP(hipMemset(P.df_err.p, 0, sizeof(int)));
   DGNP_HIP(hipDeviceSynchronize());
   if (report) throw Error(DGNP_E_BREAKDOWN, "ILU dataflow sweep exceeded its wait limit");
@@ -928,34 +928,19 @@ static void ilu_solve(dgnp_ctx& c, Precond& P, bool transpose, const T* in, T* o
     }
     return;
   }
-  if (!transpose && P.df_on && f32) {
-    uint64_t* wp = P.df_wp.p;
-    const float* bf = reinterpret_cast<const float*>(blk);
-    {
-      ScopeTimer tm(c, names[0][1], s);
-      launch_ilu_dataflow_packed(0, c.nb, c.dim, bf, c.d_nbr.p, P.lev_elems.p, c.E, nf, fstride, c.Nf,
-                                 reinterpret_cast<const float*>(in), reinterpret_cast<float*>(out), wp, P.df_err.p,
-                                 P.df_spin, P.df_grid[1], s);
-    }
-    {
-      ScopeTimer tm(c, names[1][1], s);
-      launch_ilu_dataflow_packed(1, c.nb, c.dim, bf, c.d_nbr.p, P.lev_elems.p, c.E, nf, fstride, c.Nf,
-                                 reinterpret_cast<const float*>(out), reinterpret_cast<float*>(out),
-                                 wp + int64_t(nf) * c.Nf, P.df_err.p, P.df_spin, P.df_grid[1], s);
-    }
-    return;
-  }
   if (!transpose && P.df_on) {
-    unsigned* cnt = P.df_cnt.p;
+    // packed words: one per entry in single precision, two in double
+    uint64_t* wp = f32 ? P.df_wp.p : P.df_wp64.p;
+    const int64_t half = int64_t(nf) * c.Nf * (f32 ? 1 : 2);
     {
       ScopeTimer tm(c, names[0][f32], s);
-      launch_ilu_dataflow<T>(0, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, c.E, nf, fstride, c.Nf, in, out, cnt,
+      launch_ilu_dataflow<T>(0, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, c.E, nf, fstride, c.Nf, in, out, wp,
                              P.df_err.p, P.df_spin, P.df_grid[f32], s);
     }
     {
       ScopeTimer tm(c, names[1][f32], s);
       launch_ilu_dataflow<T>(1, c.nb, c.dim, blk, c.d_nbr.p, P.lev_elems.p, c.E, nf, fstride, c.Nf, out, out,
-                             cnt + int64_t(nf) * c.E, P.df_err.p, P.df_spin, P.df_grid[f32], s);
+                             wp + half, P.df_err.p, P.df_spin, P.df_grid[f32], s);
     }
     return;
   }

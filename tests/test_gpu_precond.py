@@ -129,9 +129,11 @@ def test_precond_transpose_is_adjoint(name, pc_kind):
 
 @pytest.mark.parametrize("name", ["cfg2t", "cfg3s", "cfg1"])
 def test_dataflow_and_level_scheduled_sweeps_agree(name, monkeypatch):
-    """The dataflow ILU sweeps (one launch, per-element completion counters) and
-    the level-by-level launches compute the same triangular solves; they differ
-    only in the order of the partial sums of each row."""
+    """The dataflow ILU sweeps (one launch, each entry published with its sweep
+    count in packed words: one per FP32 entry, two per FP64 entry) and the
+    level-by-level launches compute the same triangular solves; they differ only
+    in the order of the partial sums of each row.  Sweeps of the two precisions
+    alternate on the same problem (each has its own packed words)."""
     from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64
     monkeypatch.setenv("DGNP_DATAFLOW", "1")
     cfg, _, g_df = pair(name, with_oracle=False)
@@ -142,8 +144,8 @@ def test_dataflow_and_level_scheduled_sweeps_agree(name, monkeypatch):
     r = random_vector(cfg, 41)
     for gp in (g_df, g_lv):
         gp.set_state(x, prec=DGNP_F32)
-    for prec, tol in ((DGNP_F64, 1e-12), (DGNP_F32, 1e-5)):
-        for rep in range(3):  # repeated sweeps reuse the completion counters
+    for rep in range(3):  # repeated sweeps reuse the packed sweep counts
+        for prec, tol in ((DGNP_F64, 1e-12), (DGNP_F32, 1e-5)):
             a = host(g_df.precond_apply(r, prec=prec))
             b = host(g_lv.precond_apply(r, prec=prec))
             assert rel_err(a, b) <= tol, (prec, rep, rel_err(a, b))
@@ -171,16 +173,18 @@ def test_line_sweeps_agree_with_level_sweeps(name, monkeypatch):
         assert rel_err(a, b) <= 1e-5, (rep, rel_err(a, b))
 
 
-def test_dataflow_wait_limit_is_reported(monkeypatch):
+@pytest.mark.parametrize("prec_name", ["f32", "f64"])
+def test_dataflow_wait_limit_is_reported(monkeypatch, prec_name):
     """A sweep whose waits run out (spin limit 0) ends every work-group and the
     solve reports an error instead of hanging; a new problem solves normally."""
-    from paper_2112_09271_amd.dgnp import DGNP_E_BREAKDOWN, DGNP_F32, DgnpError
+    from paper_2112_09271_amd.dgnp import DGNP_E_BREAKDOWN, DGNP_F32, DGNP_F64, DgnpError
+    prec = DGNP_F32 if prec_name == "f32" else DGNP_F64
     monkeypatch.setenv("DGNP_DATAFLOW", "1")
     monkeypatch.setenv("DGNP_DATAFLOW_SPIN", "0")
     cfg, _, gp = pair("cfg2t", with_oracle=False)
     t0 = time.perf_counter()
     try:
-        x, st = gp.solve(prec=DGNP_F32, max_newton=2)
+        x, st = gp.solve(prec=prec, max_newton=2)
         failed = False
     except DgnpError as e:
         # the first sweep that gives up ends the linear solve with its own code
@@ -190,7 +194,7 @@ def test_dataflow_wait_limit_is_reported(monkeypatch):
     gp.close()
     monkeypatch.delenv("DGNP_DATAFLOW_SPIN")
     _, _, g2 = pair("cfg2t", with_oracle=False)
-    x, st = g2.solve(prec=DGNP_F32)
+    x, st = g2.solve(prec=prec)
     assert st.status == 0 and st.res_final <= 1e-8 * st.res0
     print("first solve failed:", failed)
 
