@@ -12,8 +12,9 @@
 //     element's own trace: phi, d phi / dx_axis, c_1 .. c_{m-1} (the neighbour's
 //     side of an interior face is the neighbour's own record of that face).
 // An apply then interpolates only v.  The velocity factors are separable in
-// every velocity kind (u_d = Pe alpha_d(x) beta_d(y)), so each element
-// evaluates them at its 1-D point sets once instead of at every point.
+// every velocity kind (u_d = Pe alpha_d(x) beta_d(y)): one small table per
+// element column and row, built with the state tables, gives them at the 1-D
+// point sets, and the apply does no double-precision or transcendental work.
 //
 // A work-group holds EPB elements (consecutive in the lexicographic order, so
 // x-neighbours of the face terms inside the group are read from LDS); every
@@ -22,8 +23,10 @@
 // transposed contractions (z, y, x), then the 6 faces element-centric: node
 // traces of own and neighbour element, tangential interpolation to the face
 // Gauss points, linearised numerical flux, tangential transposes, accumulation
-// into the own element.  Every output entry has one writer: no atomics, and
-// results are bitwise reproducible.
+// into the own element.  The face flux is taken from the own side's point of
+// view (face_jac_own: no side index chosen at run time, which would otherwise
+// become chains of selects).  Every output entry has one writer: no atomics,
+// and results are bitwise reproducible.
 #include <cstdlib>
 
 #include "dg_device.hpp"
@@ -33,14 +36,19 @@ namespace dgnp {
 
 void upload_ref_tables_jac(const RefTables* tabs, int count) { upload_ref_tables_tu(tabs, count); }
 
-// Launch shape: elements per work-group and threads.  The kernel is bound by
-// the latency of its phases (barrier, LDS round trip, table loads), so the
-// number of resident work-groups matters more than busy lanes: measured on the
-// 12.6M-DOF channel (p = 3) one element per group is fastest (FP32: 431 us with
-// 128 threads against 733 us with four elements and 256; FP64: 813 us with one
-// element and 256 threads against 1590 us with two and 128); on the 16^3 cube
-// (p = 2) one element and 64 threads (FP32, 20.8 us) and two elements and 256
-// threads (FP64, 33.4 us).
+// Launch shape: elements per work-group and threads.  In single precision the
+// kernel is bound by the vector-instruction issue rate (index, address and
+// select work beside the contractions), in double precision by latency at
+// its occupancy; the number of resident work-groups matters more than busy
+// lanes.  Measured on the 12.6M-DOF channel (p = 3), one element per group is
+// fastest (FP32: 128 threads, against 733 us with four elements and 256; FP64:
+// 256 threads, against 1590 us with two elements and 128); on the 16^3 cube
+// (p = 2) one element and 64 threads (FP32) and two elements and 256 threads
+// (FP64).  FP64 asks for five waves per SIMD (a register limit of 96), which
+// beats the occupancy of four that its unrestricted register count gives
+// (796 against 888 us).  The neighbours' inputs of the face traces are read
+// directly from global memory: staging them in LDS first cost more (427 against
+// 395 us in FP32).
 template <int P, typename T>
 struct Shape {
   static constexpr bool F64 = sizeof(T) == 8;
@@ -105,13 +113,53 @@ __global__ void __launch_bounds__(128) k_jlin_tab(KArgs A, const double* __restr
   }
 }
 
+// velocity factors at the 1-D point sets (the NQ Gauss points, then the lower
+// and upper end of the element): every velocity kind is separable,
+// u_d = Pe alpha_d(x) beta_d(y), so one row per element column (alpha) and one
+// per element row (beta) serve every element:
+//   va[(ex * 3 + d) * (NQ + 2) + q] = alpha_d,  vb[(ey * 3 + d) * (NQ + 2) + q] = beta_d
+template <int P, typename T>
+__global__ void __launch_bounds__(128) k_jlin_vel(KArgs A, T* __restrict__ va, T* __restrict__ vb) {
+  constexpr int NN = P + 1, NQ = P + 2, W = NQ + 2;
+  const double* cd = CT<double, P>::base();
+  const int n0 = A.n[0], n1 = A.n[1];
+  const int t = blockIdx.x * 128 + threadIdx.x;
+  if (t >= (n0 + n1) * 3 * W) return;
+  const bool isx = t < n0 * 3 * W;
+  const int r = isx ? t : t - n0 * 3 * W;
+  const int q = r % W, d = (r / W) % 3, col = r / (3 * W);
+  // point q < NQ: Gauss point; NQ, NQ + 1: lower / upper end of the element
+  const double tx = q < NQ ? 0.5 * (cd[2 * NQ * NN + NQ + q] + 1.0) : double(q - NQ);
+  const double x = A.lo[0] + (col + tx) * A.h[0];
+  const double y = A.lo[1] + (col + tx) * A.h[1];
+  double al = 0.0, be = 0.0;
+  if (A.vel_kind == DGNP_VEL_VORTEX) {
+    double sx, cx, sy, cy;
+    sincospi(x, &sx, &cx);
+    sincospi(y, &sy, &cy);
+    al = d == 0 ? sx : (d == 1 ? -cx : 0.0);
+    be = d == 0 ? cy : (d == 1 ? sy : 0.0);
+  } else if (A.vel_kind == DGNP_VEL_POISEUILLE_X) {
+    const double yy = y - A.vel_ylo;
+    al = d == 0 ? 1.0 : 0.0;
+    be = d == 0 ? 6.0 * yy * (A.vel_H - yy) / (A.vel_H * A.vel_H) : 0.0;
+  } else {
+    al = A.vel_param[d];
+    be = 1.0;
+  }
+  if (isx)
+    va[r] = T(al);
+  else
+    vb[r] = T(be);
+}
+
 // ---------------------------------------------------------------------------
 // the apply.  CPL = false: all rows of J v (input fields masked by vin_mask);
 // CPL = true: potential rows of J v for an input whose potential part is zero,
 // written as jbase - (J v) when jbase is set (the concentrations of v are read,
 // its potential is not).
 template <int P, int MF, typename T, bool CPL, int EPB, int NT>
-__global__ void __launch_bounds__(NT) k_jlin(KArgs A, const T* __restrict__ vin, const T* __restrict__ tv,
+__global__ void __launch_bounds__(NT, (sizeof(T) == 8 ? 5 : 1)) k_jlin(KArgs A, const T* __restrict__ vin, const T* __restrict__ tv,
                                                 const T* __restrict__ tf, T* __restrict__ out, int64_t gper) {
   using S = Sz<3, P>;
   constexpr int NN = S::NN, NQ = S::NQ, NB = S::NB, NQV = S::NQV, NFN = S::NFN, NQF = S::NQF;
@@ -140,12 +188,18 @@ __global__ void __launch_bounds__(NT) k_jlin(KArgs A, const T* __restrict__ vin,
   const int tid = threadIdx.x;
   const int64_t E = A.E, Nf = E * NB;
   using C = CT<T, P>;
-  const double* cd = CT<double, P>::base();  // double tables: Gauss points at cd[2 NQ NN + NQ + q]
   const Phys<T, MF> ph = make_phys<T, MF>(A);
-  T ih[3];
+  T ih[3], hh[3];
   for (int i = 0; i < 3; ++i) ih[i] = T(2.0 / A.h[i]);
+  // face Jacobian per axis: a quarter of the product of the two tangential widths
+  hh[0] = T(0.25 * A.h[1] * A.h[2]);
+  hh[1] = T(0.25 * A.h[0] * A.h[2]);
+  hh[2] = T(0.25 * A.h[0] * A.h[1]);
+  const T peT = T(A.Pe), detT = T(A.detJ);
+  // element coordinates (the element count fits in 32 bits; checked at launch)
   auto ecoord = [&](int64_t e, int d) -> int {
-    return d == 0 ? int(e % A.n[0]) : (d == 1 ? int((e / A.n[0]) % A.n[1]) : int(e / (int64_t(A.n[0]) * A.n[1])));
+    const int ei = int(e);
+    return d == 0 ? ei % A.n[0] : (d == 1 ? (ei / A.n[0]) % A.n[1] : ei / (A.n[0] * A.n[1]));
   };
 
   // ---- load v, neighbours, velocity factors
@@ -160,31 +214,15 @@ __global__ void __launch_bounds__(NT) k_jlin(KArgs A, const T* __restrict__ vin,
     const int64_t e = e0 + el;
     s_nb[el][g % 6] = e < E ? A.nbr[e * 6 + g % 6] : -1;
   }
-  for (int g = tid; g < EPB * 3 * (NQ + 2); g += NT) {
-    const int el = g / (3 * (NQ + 2)), r = g % (3 * (NQ + 2));
-    const int d = r / (NQ + 2), q = r % (NQ + 2);
-    const int64_t e = e0 + el < E ? e0 + el : E - 1;
-    // point q < NQ: Gauss point; NQ, NQ + 1: lower / upper end of the element
-    const double tx = q < NQ ? 0.5 * (cd[2 * NQ * NN + NQ + q] + 1.0) : double(q - NQ);
-    const double x = A.lo[0] + (ecoord(e, 0) + tx) * A.h[0];
-    const double y = A.lo[1] + (ecoord(e, 1) + tx) * A.h[1];
-    double al = 0.0, be = 0.0;
-    if (A.vel_kind == DGNP_VEL_VORTEX) {
-      double sx, cx, sy, cy;
-      sincospi(x, &sx, &cx);
-      sincospi(y, &sy, &cy);
-      al = d == 0 ? sx : (d == 1 ? -cx : 0.0);
-      be = d == 0 ? cy : (d == 1 ? sy : 0.0);
-    } else if (A.vel_kind == DGNP_VEL_POISEUILLE_X) {
-      const double yy = y - A.vel_ylo;
-      al = d == 0 ? 1.0 : 0.0;
-      be = d == 0 ? 6.0 * yy * (A.vel_H - yy) / (A.vel_H * A.vel_H) : 0.0;
-    } else {
-      al = A.vel_param[d];
-      be = 1.0;
+  {
+    const T* va = tv + E * NV * NQV;
+    const T* vb = va + int64_t(A.n[0]) * 3 * (NQ + 2);
+    for (int g = tid; g < EPB * 3 * (NQ + 2); g += NT) {
+      const int el = g / (3 * (NQ + 2)), r = g % (3 * (NQ + 2));
+      const int64_t e = e0 + el < E ? e0 + el : E - 1;
+      s_al[el][r / (NQ + 2)][r % (NQ + 2)] = va[ecoord(e, 0) * 3 * (NQ + 2) + r];
+      s_be[el][r / (NQ + 2)][r % (NQ + 2)] = vb[ecoord(e, 1) * 3 * (NQ + 2) + r];
     }
-    s_al[el][d][q] = T(al);
-    s_be[el][d][q] = T(be);
   }
   __syncthreads();
 
@@ -281,15 +319,14 @@ __global__ void __launch_bounds__(NT) k_jlin(KArgs A, const T* __restrict__ vin,
     const T* ts = tv + e * NV * NQV + qi;
     for (int k = 1; k < MF; ++k) val[k] = ts[(k - 1) * NQV];
     for (int d = 0; d < 3; ++d) grad[0][d] = ts[(MF - 1 + d) * NQV];
-    for (int d = 0; d < 3; ++d) u[d] = T(A.Pe * (double(s_al[el][d][qx]) * double(s_be[el][d][qy])));
+    for (int d = 0; d < 3; ++d) u[d] = peT * s_al[el][d][qx] * s_be[el][d][qy];
     const T* q = &R[el][0];
     for (int fi = 0; fi < MI; ++fi) {
       dv[FI0 + fi] = q[(fi * 4) * NQV + qi];
       for (int d = 0; d < 3; ++d) dg[FI0 + fi][d] = q[(fi * 4 + 1 + d) * NQV + qi];
     }
     vol_jac<T, MF, 3>(ph, val, grad, u, dv, dg, vg);
-    const T w = T(A.detJ) * C::base()[2 * NQ * NN + qx] * C::base()[2 * NQ * NN + qy] *
-                C::base()[2 * NQ * NN + qz];
+    const T w = detT * C::base()[2 * NQ * NN + qx] * C::base()[2 * NQ * NN + qy] * C::base()[2 * NQ * NN + qz];
     T* o = &R[el][0];
     for (int fo = 0; fo < MO; ++fo)
       for (int d = 0; d < 3; ++d) o[(fo * 4 + 1 + d) * NQV + qi] = vg[fo][d] * w * ih[d];
@@ -377,34 +414,21 @@ __global__ void __launch_bounds__(NT) k_jlin(KArgs A, const T* __restrict__ vin,
     const int el = g / ((NROW / 2) * NFN), r = g % ((NROW / 2) * NFN);
     const int ij = r % NFN, pr = r / NFN;  // pr = (fc, sd, fi)
     const int fi = pr % MI, sd = (pr / MI) & 1, fc = pr / (2 * MI);
-    const int f = FI0 + fi;
     const int ax = fc >> 1;
     const int side = (fc & 1) ? 1 : -1;
     const int sside = sd == 0 ? side : -side;
     const int i = ij % NN, j = ij / NN;
-    const T* u = nullptr;
-    if (sd == 0) {
-      u = &s_v[el][fi * NB];
-    } else {
-      const int nb = s_nb[el][fc];
-      if (nb >= 0) {
-        const int64_t d = int64_t(nb) - e0;
-        if (d >= 0 && d < EPB)
-          u = &s_v[d][fi * NB];
-        else if ((A.vin_mask >> f) & 1u)
-          u = vin + f * Nf + int64_t(nb) * NB;
-      }
-    }
-    T val = T(0), dn = T(0);
-    if (u) {
-      T x[NN];
+    const int f = FI0 + fi, nb = s_nb[el][fc];
+    const bool has = sd == 0 || (nb >= 0 && ((A.vin_mask >> f) & 1u));
+    const T* u = sd == 0 ? &s_v[el][fi * NB] : vin + f * Nf + int64_t(nb >= 0 ? nb : 0) * NB;
+    T x[NN];
 #pragma unroll
-      for (int l = 0; l < NN; ++l) x[l] = u[face_node<3, NN>(ax, l, i, j)];
-      val = sside < 0 ? x[0] : x[P];
+    for (int l = 0; l < NN; ++l) x[l] = has ? u[face_node<3, NN>(ax, l, i, j)] : T(0);
+    const T val = sside < 0 ? x[0] : x[P];
+    T dn = T(0);
 #pragma unroll
-      for (int l = 0; l < NN; ++l) dn += (sside < 0 ? C::De(0, l) : C::De(1, l)) * x[l];
-      dn *= ih[ax];
-    }
+    for (int l = 0; l < NN; ++l) dn += (sside < 0 ? C::De(0, l) : C::De(1, l)) * x[l];
+    dn *= ih[ax];
     T* fn = &R[el][NROW * NQF];
     fn[(2 * pr + 0) * NFN + ij] = val;
     fn[(2 * pr + 1) * NFN + ij] = dn;
@@ -452,54 +476,49 @@ __global__ void __launch_bounds__(NT) k_jlin(KArgs A, const T* __restrict__ vin,
     const T* fq = &R[el][0];
     if (e < E && (interior || cbc != BC_WALL || phid)) {
       const int qi = qf % NQ, qj = qf / NQ;
-      const int t1ax = ax == 0 ? 1 : 0, t2ax = ax == 2 ? 1 : 2;
-      const double* wq = cd + 2 * NQ * NN;
-      w = T(0.25 * A.h[t1ax] * A.h[t2ax] * wq[qi] * wq[qj]);
+      const T* wq = C::base() + 2 * NQ * NN;
+      w = hh[ax] * wq[qi] * wq[qj];
       // u . e_ax at the face point: x index (end point of x faces, else the
       // first tangential point), y index (end point of y faces, else the
       // first tangential point of x faces / the second of z faces)
       const int ix = ax == 0 ? NQ + (side > 0) : qi;
       const int iy = ax == 1 ? NQ + (side > 0) : (ax == 0 ? qi : qj);
-      const double uax = A.Pe * (double(s_al[el][ax][ix]) * double(s_be[el][ax][iy]));
+      const T uax = peT * s_al[el][ax][ix] * s_be[el][ax][iy];
       const T* so = tf + ((e * 6 + fc) * NFT) * NQF + qf;
-      T v[2][MF], gg[2][MF], tvv[2][MF], tgg[2][MF];
-      for (int s2 = 0; s2 < 2; ++s2)
-        for (int f = 0; f < MF; ++f) v[s2][f] = gg[s2][f] = tvv[s2][f] = tgg[s2][f] = T(0);
+      const T* sn = tf + ((interior ? int64_t(nb) * 6 + (fc ^ 1) : 0) * NFT) * NQF + qf;
+      // the own outward normal is side * e_ax: normal derivatives and the
+      // normal velocity are the d/dx_ax ones times sg
+      const T sg = T(side);
+      T vo[MF], tvo[MF], tgo[MF];
+      for (int f = 0; f < MF; ++f) vo[f] = tvo[f] = tgo[f] = T(0);
+      vo[0] = so[0];
+      for (int k = 1; k < MF; ++k) vo[k] = so[(1 + k) * NQF];
+      for (int fi = 0; fi < MI; ++fi) {
+        tvo[FI0 + fi] = fq[trow(fc, 0, fi, 0) * NQF + qf];
+        tgo[FI0 + fi] = sg * fq[trow(fc, 0, fi, 1) * NQF + qf];
+      }
       if (interior) {
-        const int own = side > 0 ? 0 : 1;  // the own element is the minus side of a +1 face
-        const T* sn = tf + ((int64_t(nb) * 6 + (fc ^ 1)) * NFT) * NQF + qf;
-        v[own][0] = so[0];
-        gg[own][0] = so[NQF];
-        v[1 - own][0] = sn[0];
-        gg[1 - own][0] = sn[NQF];
-        for (int k = 1; k < MF; ++k) {
-          v[own][k] = so[(1 + k) * NQF];
-          v[1 - own][k] = sn[(1 + k) * NQF];
-        }
+        T vn[MF], tvn[MF], tgn[MF], Gn[MF];
+        for (int f = 0; f < MF; ++f) vn[f] = tvn[f] = tgn[f] = T(0);
+        vn[0] = sn[0];
+        for (int k = 1; k < MF; ++k) vn[k] = sn[(1 + k) * NQF];
         for (int fi = 0; fi < MI; ++fi) {
-          tvv[own][FI0 + fi] = fq[trow(fc, 0, fi, 0) * NQF + qf];
-          tgg[own][FI0 + fi] = fq[trow(fc, 0, fi, 1) * NQF + qf];
-          tvv[1 - own][FI0 + fi] = fq[trow(fc, 1, fi, 0) * NQF + qf];
-          tgg[1 - own][FI0 + fi] = fq[trow(fc, 1, fi, 1) * NQF + qf];
+          tvn[FI0 + fi] = fq[trow(fc, 1, fi, 0) * NQF + qf];
+          tgn[FI0 + fi] = sg * fq[trow(fc, 1, fi, 1) * NQF + qf];
         }
-        face_jac<T, MF>(ph, v, gg, tvv, tgg, T(uax), own, Fo, Go);
+        face_jac_own<T, MF>(ph, vo, vn, sg * so[NQF], sg * sn[NQF], tvo, tvn, tgo, tgn, sg * uax, Fo, Gn);
+        for (int f = 0; f < MF; ++f) Go[f] = sg * Gn[f];  // outward normal derivative -> d/dx_ax
       } else {
-        int64_t lin;
         const int ex = ecoord(e, 0), ey = ecoord(e, 1), ez = ecoord(e, 2);
-        lin = ax == 0 ? ey + int64_t(A.n[1]) * ez : (ax == 1 ? ex + int64_t(A.n[0]) * ez : ex + int64_t(A.n[0]) * ey);
+        const int64_t lin =
+            ax == 0 ? ey + int64_t(A.n[1]) * ez : (ax == 1 ? ex + int64_t(A.n[0]) * ez : ex + int64_t(A.n[0]) * ey);
         const int64_t bf = A.btag_off[fc] + lin;
-        const T sd = T(side);
-        T gd[MF];
-        v[0][0] = so[0];
-        gg[0][0] = sd * so[NQF];
-        for (int k = 1; k < MF; ++k) v[0][k] = so[(1 + k) * NQF];
+        T gd[MF], gno[MF];
+        for (int f = 0; f < MF; ++f) gno[f] = T(0);
+        gno[0] = sg * so[NQF];
         for (int f = 0; f < MF; ++f) gd[f] = T(A.bcq[(f * A.n_bface + bf) * NQF + qf]);
-        for (int fi = 0; fi < MI; ++fi) {
-          tvv[0][FI0 + fi] = fq[trow(fc, 0, fi, 0) * NQF + qf];
-          tgg[0][FI0 + fi] = sd * fq[trow(fc, 0, fi, 1) * NQF + qf];
-        }
-        bnd_jac<T, MF>(ph, v[0], gg[0], tvv[0], tgg[0], T(side * uax), cbc, phid, gd, Fo, Go);
-        for (int f = 0; f < MF; ++f) Go[f] *= sd;  // outward normal derivative -> d/dx_ax
+        bnd_jac<T, MF>(ph, vo, gno, tvo, tgo, sg * uax, cbc, phid, gd, Fo, Go);
+        for (int f = 0; f < MF; ++f) Go[f] *= sg;  // outward normal derivative -> d/dx_ax
       }
     }
     T* cf = &R[el][NROW * NQF];
@@ -566,7 +585,13 @@ __global__ void __launch_bounds__(NT) k_jlin(KArgs A, const T* __restrict__ vin,
 // ---------------------------------------------------------------------------
 template <int P, int MF, typename T>
 static void tab_t(const KArgs& A, const double* xs, T* tv, T* tf, hipStream_t s) {
+  constexpr int NQ = P + 2;
   hipLaunchKernelGGL((k_jlin_tab<P, MF, T>), dim3(unsigned(A.E)), dim3(128), 0, s, A, xs, tv, tf);
+  DGNP_HIP(hipGetLastError());
+  T* va = tv + A.E * (MF + 2) * NQ * NQ * NQ;
+  T* vb = va + int64_t(A.n[0]) * 3 * (NQ + 2);
+  const int nv = (A.n[0] + A.n[1]) * 3 * (NQ + 2);
+  hipLaunchKernelGGL((k_jlin_vel<P, T>), dim3(unsigned((nv + 127) / 128)), dim3(128), 0, s, A, va, vb);
   DGNP_HIP(hipGetLastError());
 }
 
@@ -620,6 +645,7 @@ template <typename T>
 void launch_jlin(int p, int m, bool coupling, const KArgs& A, const T* v, const T* tv, const T* tf, T* y,
                  hipStream_t s) {
   if (A.E == 0) return;
+  DGNP_REQUIRE(A.E < (int64_t(1) << 31), DGNP_E_ARG, "tabulated Jacobian: element count beyond 32 bits");
 #define JL_CASE(PP, MM)                                                \
   if (p == PP && m == MM) {                                            \
     if (coupling) return jl_t<PP, MM, T, true>(A, v, tv, tf, y, s);    \
@@ -635,10 +661,10 @@ void launch_jlin(int p, int m, bool coupling, const KArgs& A, const T* v, const 
   throw Error(DGNP_E_ARG, "tabulated Jacobian: orders 1..3, 2 or 3 ions");
 }
 
-size_t jlin_table_sizes(int p, int m, int64_t E, size_t* nf) {
+size_t jlin_table_sizes(int p, int m, int64_t E, const int* n, size_t* nf) {
   const size_t nq = size_t(p) + 2;
   if (nf) *nf = size_t(E) * 6 * (m + 1) * nq * nq;
-  return size_t(E) * (m + 2) * nq * nq * nq;
+  return size_t(E) * (m + 2) * nq * nq * nq + size_t(n[0] + n[1]) * 3 * (nq + 2);
 }
 
 template void launch_jlin_tables<double>(int, int, const KArgs&, const double*, double*, double*, hipStream_t);

@@ -200,6 +200,47 @@ __host__ __device__ inline void face_jac(const Phys<T, MF>& ph, const T (*v)[MF]
   }
 }
 
+// The same forward linearisation written from one side's point of view: the
+// own side (o) and the neighbour side (n), every derivative and the velocity
+// taken along the own element's outward normal.  For the own side as the
+// minus side this is face_jac with o = 0; for the plus side every normal
+// quantity changes sign, and the jumps [w] and the factor sign_o of face_jac
+// change sign with it, so that both cases give the same expressions.  Outputs:
+// Fo, the coefficient of the own test value (as face_jac), and Gn, that of its
+// outward normal derivative (face_jac's Go is sign_o Gn).  No side index is
+// taken at run time.
+//   vo, vn: state values; gpo, gpn: state d phi/dn; tvo, tvn: trial values;
+//   tgo, tgn: trial d/dn (every field); un: u . n.
+template <typename T, int MF>
+__host__ __device__ inline void face_jac_own(const Phys<T, MF>& ph, const T* vo, const T* vn, T gpo, T gpn,
+                                             const T* tvo, const T* tvn, const T* tgo, const T* tgn, T un, T* Fo,
+                                             T* Gn) {
+  T kapo = T(0), kapn = T(0), dkapo = T(0), dkapn = T(0), sa = T(0), da = T(0);
+  for (int k = 1; k < MF; ++k) {
+    kapo += ph.b[k - 1] * vo[k];
+    kapn += ph.b[k - 1] * vn[k];
+    dkapo += ph.b[k - 1] * tvo[k];
+    dkapn += ph.b[k - 1] * tvn[k];
+    sa += ph.a[k - 1] * (tgo[k] + tgn[k]);
+    da += ph.a[k - 1] * (tvo[k] - tvn[k]);
+  }
+  const T jphi = vo[0] - vn[0], djphi = tvo[0] - tvn[0];
+  const T dcur = dkapo * gpo + kapo * tgo[0] + dkapn * gpn + kapn * tgn[0] + sa;
+  Fo[0] = -T(0.5) * dcur + T(0.5) * (dkapo + dkapn) * ph.delta * jphi + T(0.5) * (kapo + kapn) * ph.delta * djphi;
+  Gn[0] = -T(0.5) * da - T(0.5) * dkapo * jphi - T(0.5) * kapo * djphi;
+  for (int k = 1; k < MF; ++k) {
+    const T D = ph.D[k - 1], zD = ph.zD[k - 1];
+    const T Qo = un - zD * gpo, Qn = un - zD * gpn;
+    const T Qb = un - zD * T(0.5) * (gpo + gpn);
+    const T dQo = -zD * tgo[0], dQn = -zD * tgn[0];
+    const T jc = vo[k] - vn[k], djc = tvo[k] - tvn[k];
+    Fo[k] = -T(0.5) * D * (tgo[k] + tgn[k]) + D * ph.delta * djc +
+            T(0.5) * (tvo[k] * Qo + vo[k] * dQo + tvn[k] * Qn + vn[k] * dQn) +
+            T(0.25) * sgn(Qb) * (dQo + dQn) * jc + T(0.5) * fabs_(Qb) * djc;
+    Gn[k] = -T(0.5) * D * djc;
+  }
+}
+
 // transpose: test traces (wv, wg) on both sides -> coefficients of the trial
 // value and d/dn on side o
 template <typename T, int MF>

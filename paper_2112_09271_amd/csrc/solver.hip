@@ -32,7 +32,7 @@ void set_state(dgnp_ctx& c, const double* x, int prec, hipStream_t s, bool assem
   }
   if (c.dim == 3 && c.jac_tab) {
     size_t nf = 0;
-    const size_t nv = jlin_table_sizes(c.p, c.m, c.E, &nf);
+    const size_t nv = jlin_table_sizes(c.p, c.m, c.E, c.n, &nf);
     const KArgs A = c.kargs();
     c.d_jtv.alloc(nv);
     c.d_jtf.alloc(nf);
