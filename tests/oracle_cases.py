@@ -61,3 +61,14 @@ def bv3t(ion=1, p=2, **kw):
     base.update(kw)
     return Config("bv3t", 3, (4, 2, 2), (0.0, 0.0, 0.0), (1.0, 0.5, 0.25), p, (1.0, -1.0, 2.0), (1.0, 1.5, 0.7),
                   VEL_POISEUILLE_X, 100.0, seed=6, **base)
+
+
+def gmg_box(dim=2, n=(8, 8), p=1, Pe=1.0, seed=9):
+    """Box with inflow data at x = 0, outflow at x = 1, walls elsewhere, the
+    potential fixed on both x faces, constant velocity along x: the
+    concentration blocks are convection-diffusion operators whose convection
+    strength Pe sets."""
+    wall = (0,) * (2 * dim - 2)
+    return Config("gmgbox", dim, tuple(n), (0.0,) * dim, (1.0,) * dim, p, (1.0, -1.0, 2.0), (1.0, 1.5, 0.7),
+                  VEL_CONST, Pe, (C_INFLOW, C_OUTFLOW) + wall, (PHI_DIRICHLET, PHI_DIRICHLET) + wall,
+                  (0.05, 0.0) + (0.0,) * (2 * dim - 2), vel_param=(1.0, 0.0, 0.0), seed=seed)
