@@ -71,6 +71,8 @@ enum { DGNP_J0_CONST = 0, DGNP_J0_PARABOLIC_Z = 1 };
  * valence) */
 enum { DGNP_OBJ_OUTFLOW = 0, DGNP_OBJ_ELECTRODE = 1 };
 enum { DGNP_PHI_NEUMANN0 = 0, DGNP_PHI_DIRICHLET = 1 };
+/* concentration-block preconditioners (dgnp_options.conc_pc) */
+enum { DGNP_CPC_BILU = 0, DGNP_CPC_GMG = 1 };
 /* velocity u = Pe * u_hat(x):
  *   VORTEX        u_hat = (sin(pi x) cos(pi y), -cos(pi x) sin(pi y), 0)
  *   POISEUILLE_X  u_hat = (6 y'(H - y')/H^2, 0, 0), y' = y - lo[1], H = hi[1] - lo[1]
@@ -169,6 +171,16 @@ typedef struct {
   void (*free_)(void *ptr, void *alloc_ctx);
   void *alloc_ctx;
   const dgnp_electrode *electrode;  /* required when a face is DGNP_C_ELECTRODE, else NULL */
+  /* Concentration-block preconditioner (Sec. 4.1), DGNP_CPC_*: BILU (0, the
+   * default) one block-ILU(0) solve per concentration block; GMG one V-cycle
+   * of geometric multigrid per block: the box coarsened by 2 along every axis
+   * while every element count is even and a level has more than 2^d elements,
+   * Galerkin coarse operators with the nested DG prolongation, gmg_nu
+   * Richardson steps with the level's block ILU(0) before and after the coarse
+   * correction, and the coarsest level solved with its dense inverse (at most
+   * 1024 unknowns per field: DGNP_E_ARG otherwise). */
+  int32_t conc_pc;
+  int32_t gmg_nu;          /* smoothing steps per side, 1..8; 0: 2 */
 } dgnp_options;
 enum { DGNP_PHIMG_AUTO = 0, DGNP_PHIMG_Q1 = 1, DGNP_PHIMG_P = 2, DGNP_PHIMG_PG = 3 };
 

@@ -18,7 +18,7 @@ SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdgnp.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels_dg.hip", "kernels_jac.hip", "kernels_phi.hip", "kernels_block.hip", "kernels_csr.hip", "blas.hip", "precond.hip", "solver.hip",
+SOURCES = ["kernels_dg.hip", "kernels_jac.hip", "kernels_phi.hip", "kernels_block.hip", "kernels_csr.hip", "kernels_gmg.hip", "blas.hip", "precond.hip", "solver.hip",
            "abi.cpp", "tables.cpp", "amg.cpp"]
 ARCH = os.environ.get("DGNP_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-pthread", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",

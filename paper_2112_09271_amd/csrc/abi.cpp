@@ -227,6 +227,11 @@ int dgnp_setup(const dgnp_mesh* mesh, int32_t order, const dgnp_species* sp, con
     c->phi_mg = opt ? opt->phi_mg : DGNP_PHIMG_AUTO;
     DGNP_REQUIRE(c->phi_mg >= DGNP_PHIMG_AUTO && c->phi_mg <= DGNP_PHIMG_PG, DGNP_E_ARG, "unknown phi_mg");
     if (c->phi_mg == DGNP_PHIMG_AUTO) c->phi_mg = order >= 3 ? DGNP_PHIMG_PG : DGNP_PHIMG_Q1;
+    c->conc_pc = opt ? opt->conc_pc : DGNP_CPC_BILU;
+    DGNP_REQUIRE(c->conc_pc == DGNP_CPC_BILU || c->conc_pc == DGNP_CPC_GMG, DGNP_E_ARG,
+                 "unknown concentration preconditioner");
+    c->gmg_nu = opt && opt->gmg_nu != 0 ? opt->gmg_nu : 2;
+    DGNP_REQUIRE(c->gmg_nu >= 1 && c->gmg_nu <= 8, DGNP_E_ARG, "gmg_nu must be 1..8 (0: 2)");
     DGNP_REQUIRE(c->phi_mg == DGNP_PHIMG_Q1 || order >= 2, DGNP_E_ARG, "p-multigrid needs order 2 or 3");
     DGNP_REQUIRE(c->mms == 0 || c->m == 2, DGNP_E_ARG, "manufactured solutions need two ions");
     DGNP_REQUIRE(c->mms >= 0 && c->mms <= 2, DGNP_E_ARG, "unknown manufactured solution");

@@ -19,6 +19,8 @@ struct dgnp_ctx {
   double z[4] = {}, D[4] = {}, a[4] = {}, b[4] = {};
   double delta = 0, c_ip = 10;
   int phi_mg = 1;                 // DGNP_PHIMG_Q1 / _P / _PG (AUTO resolved at setup)
+  int conc_pc = 0;                // DGNP_CPC_BILU / _GMG
+  int gmg_nu = 2;                 // smoothing steps per side of the concentration V-cycle
   int mms = 0;
   dgnp_velocity vel{};
   int c_bc[6] = {}, phi_bc[6] = {};

@@ -1,0 +1,267 @@
+// Geometric multigrid on the concentration blocks (Sec. 4.1: an h-multigrid
+// preconditioner for A_{c_k c_k} whose smoother is the block ILU(0) and whose
+// coarsest grid is solved directly).  The levels are the structured box
+// coarsened by 2 along every axis; the coarse space of each level (degree-p
+// polynomials on every coarse element) lies inside the next finer one, and the
+// prolongation P evaluates a coarse element's polynomial at the nodes of its
+// 2^d children: on child c it is the nb x nb matrix Pi_c, the tensor product of
+// the 1-D Lagrange interpolants of the coarse nodes at the child's nodes.
+// Coarse operators are Galerkin products R A P with R = P^T, which keep the
+// 2d+1 block pattern of the element graph.
+//
+// Kernels: the Galerkin product (double), restriction and prolongation, and
+// the level residual b - A x or b - A^T x on the unfactored blocks.  The ILU(0)
+// factorisation and sweeps of the coarse levels and the coarsest dense solve
+// reuse the kernels of the fine level (kernels_block.hip).
+//
+// Child numbering: bit a of c is set for the upper half of the parent along
+// axis a; the fine element of child c of coarse element (X, Y, Z) is
+// (2X + bit0, 2Y + bit1, 2Z + bit2) in the lexicographic order of the fine grid.
+#include "kernels_gmg.hpp"
+
+namespace dgnp {
+
+namespace {
+constexpr int GT = 256;
+
+struct Dims {
+  int x, y, z;  // fine element counts per axis (z = 1 in 2-D)
+};
+
+__device__ __forceinline__ int64_t fine_child(const Dims& f, int64_t ec, int c) {
+  const int cx = f.x / 2, cy = f.y / 2;
+  const int64_t X = ec % cx, Y = (ec / cx) % cy, Z = ec / (int64_t(cx) * cy);
+  return (2 * X + (c & 1)) + int64_t(f.x) * ((2 * Y + ((c >> 1) & 1)) + int64_t(f.y) * (2 * Z + ((c >> 2) & 1)));
+}
+
+// parent and child index of fine element e
+__device__ __forceinline__ int64_t parent_of(const Dims& f, int64_t e, int* child) {
+  const int64_t x = e % f.x, y = (e / f.x) % f.y, z = e / (int64_t(f.x) * f.y);
+  *child = int(x & 1) | int(y & 1) << 1 | int(z & 1) << 2;
+  return (x >> 1) + int64_t(f.x / 2) * ((y >> 1) + int64_t(f.y / 2) * (z >> 1));
+}
+}  // namespace
+
+// Galerkin product: coarse block (Ec, slot s) = sum of Pi_c^T A_{e,t} Pi_c' over
+// the fine blocks (child e = child c of Ec, its slot t) whose column element
+// (child c' of Ec, or of Ec's neighbour in slot s) maps to it.  One work-group
+// per (coarse element, field); the products run one at a time through LDS,
+// every thread accumulating fixed entries of the coarse block in registers.
+template <int NB, int DIM>
+__global__ void __launch_bounds__(GT) k_gmg_galerkin(const double* __restrict__ Af, int64_t fsf,
+                                                     const int* __restrict__ nbr, Dims fd,
+                                                     const double* __restrict__ Pi, double* __restrict__ Ac,
+                                                     int64_t fsc) {
+  constexpr int NS = 2 * DIM + 1, NC = 1 << DIM, BB = NB * NB, PER = (BB + GT - 1) / GT;
+  const int64_t ec = blockIdx.x;
+  const int tid = threadIdx.x;
+  Af += blockIdx.y * fsf;
+  Ac += blockIdx.y * fsc;
+  __shared__ double sA[BB], sT[BB];
+  for (int s = 0; s < NS; ++s) {
+    double acc[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) acc[q] = 0.0;
+    for (int c = 0; c < NC; ++c) {
+      const int64_t e = fine_child(fd, ec, c);
+      for (int t = 0; t < NS; ++t) {
+        int cp = c;
+        if (t == 0) {
+          if (s != 0) continue;
+        } else {
+          const int a = (t - 1) >> 1, up = (t - 1) & 1;
+          if (nbr[e * 2 * DIM + t - 1] < 0) continue;
+          // a lower child going up, or an upper child going down, stays inside
+          // the coarse element; otherwise the neighbour is in coarse slot t
+          const bool inside = ((c >> a) & 1) != up;
+          if (inside ? s != 0 : s != t) continue;
+          cp = c ^ (1 << a);
+        }
+        __syncthreads();
+        for (int i = tid; i < BB; i += GT) sA[i] = Af[(e * NS + t) * BB + i];
+        __syncthreads();
+        const double* Pc = Pi + cp * BB;  // A_{e,t} Pi_c'
+        for (int i = tid; i < BB; i += GT) {
+          const int r = i / NB, col = i % NB;
+          double v = 0.0;
+#pragma unroll 8
+          for (int k = 0; k < NB; ++k) v += sA[r * NB + k] * Pc[k * NB + col];
+          sT[i] = v;
+        }
+        __syncthreads();
+        const double* Pr = Pi + c * BB;  // Pi_c^T (A Pi_c')
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int i = tid + q * GT;
+          if (i < BB) {
+            const int r = i / NB, col = i % NB;
+            double v = 0.0;
+#pragma unroll 8
+            for (int k = 0; k < NB; ++k) v += Pr[k * NB + r] * sT[k * NB + col];
+            acc[q] += v;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int i = tid + q * GT;
+      if (i < BB) Ac[(ec * NS + s) * BB + i] = acc[q];
+    }
+  }
+}
+
+// rc = P^T r: one thread per (coarse entry, field)
+template <typename T, int NB, int DIM>
+__global__ void __launch_bounds__(GT) k_gmg_restrict(const T* __restrict__ Pi, Dims fd, const T* __restrict__ r,
+                                                     int64_t nff, T* __restrict__ rc, int64_t nfc) {
+  constexpr int NC = 1 << DIM, BB = NB * NB;
+  const int64_t g = blockIdx.x * int64_t(GT) + threadIdx.x;
+  if (g >= nfc) return;
+  const int i = int(g % NB);
+  const int64_t ec = g / NB;
+  r += blockIdx.y * nff;
+  rc += blockIdx.y * nfc;
+  T acc = T(0);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const T* rf = r + fine_child(fd, ec, c) * NB;
+    const T* P = Pi + c * BB + i;
+#pragma unroll 8
+    for (int k = 0; k < NB; ++k) acc += P[k * NB] * rf[k];
+  }
+  rc[g] = acc;
+}
+
+// x += P xc: one thread per (fine entry, field)
+template <typename T, int NB>
+__global__ void __launch_bounds__(GT) k_gmg_prolong(const T* __restrict__ Pi, Dims fd, const T* __restrict__ xc,
+                                                    int64_t nfc, T* __restrict__ x, int64_t nff) {
+  const int64_t g = blockIdx.x * int64_t(GT) + threadIdx.x;
+  if (g >= nff) return;
+  const int k = int(g % NB);
+  int c = 0;
+  const int64_t ec = parent_of(fd, g / NB, &c);
+  xc += blockIdx.y * nfc + ec * NB;
+  x += blockIdx.y * nff;
+  const T* P = Pi + (c * NB + k) * NB;
+  T acc = T(0);
+#pragma unroll 8
+  for (int i = 0; i < NB; ++i) acc += P[i] * xc[i];
+  x[g] += acc;
+}
+
+// r = b - A x (TR = false) or b - A^T x (TR = true) on a level's unfactored
+// blocks [field][E][slot][NB][NB]: one thread per (entry, field)
+template <typename T, int NB, int DIM, bool TR>
+__global__ void __launch_bounds__(GT) k_gmg_resid(const T* __restrict__ blk, int64_t fs,
+                                                  const int* __restrict__ nbr, int64_t E, const T* __restrict__ x,
+                                                  const T* __restrict__ b, T* __restrict__ r, int64_t nf) {
+  constexpr int NS = 2 * DIM + 1, BB = NB * NB;
+  const int64_t g = blockIdx.x * int64_t(GT) + threadIdx.x;
+  if (g >= nf) return;
+  const int row = int(g % NB);
+  const int64_t e = g / NB;
+  blk += blockIdx.y * fs;
+  x += blockIdx.y * nf;
+  b += blockIdx.y * nf;
+  r += blockIdx.y * nf;
+  T acc = T(0);
+  for (int t = 0; t < NS; ++t) {
+    const int64_t j = t == 0 ? e : int64_t(nbr[e * 2 * DIM + t - 1]);
+    if (j < 0) continue;
+    const T* xj = x + j * NB;
+    if constexpr (!TR) {
+      const T* a = blk + (e * NS + t) * BB + row * NB;
+#pragma unroll 8
+      for (int col = 0; col < NB; ++col) acc += a[col] * xj[col];
+    } else {
+      // block of row j that couples j to e: the opposite slot of t
+      const int tj = t == 0 ? 0 : (((t - 1) ^ 1) + 1);
+      const T* a = blk + (j * NS + tj) * BB + row;
+#pragma unroll 8
+      for (int col = 0; col < NB; ++col) acc += a[col * NB] * xj[col];
+    }
+  }
+  r[g] = b[g] - acc;
+}
+
+// ---------------------------------------------------------------------------
+#define GMG_NB_SWITCH(nb, dim, CALL)                              \
+  do {                                                            \
+    if (dim == 3) {                                               \
+      switch (nb) {                                               \
+        case 8: { constexpr int NB_ = 8, D_ = 3; CALL; } break;   \
+        case 27: { constexpr int NB_ = 27, D_ = 3; CALL; } break; \
+        case 64: { constexpr int NB_ = 64, D_ = 3; CALL; } break; \
+        default: throw Error(DGNP_E_ARG, "unsupported block size"); \
+      }                                                           \
+    } else {                                                      \
+      switch (nb) {                                               \
+        case 4: { constexpr int NB_ = 4, D_ = 2; CALL; } break;   \
+        case 9: { constexpr int NB_ = 9, D_ = 2; CALL; } break;   \
+        case 16: { constexpr int NB_ = 16, D_ = 2; CALL; } break; \
+        default: throw Error(DGNP_E_ARG, "unsupported block size"); \
+      }                                                           \
+    }                                                             \
+  } while (0)
+
+static Dims dims_of(int dim, const int* n) { return Dims{n[0], n[1], dim == 3 ? n[2] : 1}; }
+
+void launch_gmg_galerkin(int nb, int dim, int nfields, const double* Af, int64_t fsf, const int* nbr,
+                         const int* nfine, const double* Pi, double* Ac, int64_t fsc, int64_t Ec, hipStream_t s) {
+  if (Ec == 0 || nfields == 0) return;
+  const Dims fd = dims_of(dim, nfine);
+  const dim3 g = dim3(unsigned(Ec), unsigned(nfields));
+  GMG_NB_SWITCH(nb, dim,
+                hipLaunchKernelGGL((k_gmg_galerkin<NB_, D_>), g, dim3(GT), 0, s, Af, fsf, nbr, fd, Pi, Ac, fsc));
+  DGNP_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_gmg_restrict(int nb, int dim, int nfields, const T* Pi, const int* nfine, const T* r, int64_t nff,
+                         T* rc, int64_t nfc, hipStream_t s) {
+  if (nfc == 0 || nfields == 0) return;
+  const Dims fd = dims_of(dim, nfine);
+  const dim3 g = dim3(unsigned((nfc + GT - 1) / GT), unsigned(nfields));
+  GMG_NB_SWITCH(nb, dim, hipLaunchKernelGGL((k_gmg_restrict<T, NB_, D_>), g, dim3(GT), 0, s, Pi, fd, r, nff, rc, nfc));
+  DGNP_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_gmg_prolong(int nb, int dim, int nfields, const T* Pi, const int* nfine, const T* xc, int64_t nfc, T* x,
+                        int64_t nff, hipStream_t s) {
+  if (nff == 0 || nfields == 0) return;
+  const Dims fd = dims_of(dim, nfine);
+  const dim3 g = dim3(unsigned((nff + GT - 1) / GT), unsigned(nfields));
+  GMG_NB_SWITCH(nb, dim, (void)D_; hipLaunchKernelGGL((k_gmg_prolong<T, NB_>), g, dim3(GT), 0, s, Pi, fd, xc, nfc, x, nff));
+  DGNP_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_gmg_resid(int nb, int dim, int nfields, bool transpose, const T* blk, int64_t fs, const int* nbr,
+                      int64_t E, const T* x, const T* b, T* r, hipStream_t s) {
+  const int64_t nf = E * nb;
+  if (nf == 0 || nfields == 0) return;
+  const dim3 g = dim3(unsigned((nf + GT - 1) / GT), unsigned(nfields));
+  if (transpose)
+    GMG_NB_SWITCH(nb, dim, hipLaunchKernelGGL((k_gmg_resid<T, NB_, D_, true>), g, dim3(GT), 0, s, blk, fs, nbr, E, x, b, r, nf));
+  else
+    GMG_NB_SWITCH(nb, dim, hipLaunchKernelGGL((k_gmg_resid<T, NB_, D_, false>), g, dim3(GT), 0, s, blk, fs, nbr, E, x, b, r, nf));
+  DGNP_HIP(hipGetLastError());
+}
+
+template void launch_gmg_restrict<double>(int, int, int, const double*, const int*, const double*, int64_t, double*,
+                                          int64_t, hipStream_t);
+template void launch_gmg_restrict<float>(int, int, int, const float*, const int*, const float*, int64_t, float*,
+                                         int64_t, hipStream_t);
+template void launch_gmg_prolong<double>(int, int, int, const double*, const int*, const double*, int64_t, double*,
+                                         int64_t, hipStream_t);
+template void launch_gmg_prolong<float>(int, int, int, const float*, const int*, const float*, int64_t, float*,
+                                        int64_t, hipStream_t);
+template void launch_gmg_resid<double>(int, int, int, bool, const double*, int64_t, const int*, int64_t,
+                                       const double*, const double*, double*, hipStream_t);
+template void launch_gmg_resid<float>(int, int, int, bool, const float*, int64_t, const int*, int64_t, const float*,
+                                      const float*, float*, hipStream_t);
+
+}  // namespace dgnp

@@ -21,6 +21,7 @@
 #include "amg.hpp"
 #include "blas.hpp"
 #include "kernels_block.hpp"
+#include "kernels_gmg.hpp"
 #include "kernels_phi.hpp"
 #include "solver.hpp"
 
@@ -161,6 +162,29 @@ struct Precond {
   DevBuf<int> line_first;
   int nline = 0, line_len = 0, line_ax = 0, line_grid = 0;
   int64_t line_stride = 1;
+  // geometric multigrid on the concentration blocks (instead of one BILU(0)
+  // solve): level 0 is the fine grid (its unfactored blocks in A; its factors
+  // are blk / blk32 above), levels 1.. the coarsened boxes with their Galerkin
+  // operators and factors; the last level is solved with its dense inverse
+  struct GLevel {
+    int n[3] = {1, 1, 1};
+    int64_t E = 0;
+    DevBuf<int> nbr;
+    std::vector<int64_t> lev_ptr;
+    DevBuf<int> lev_elems;
+    DevBuf<double> A, F;  // [m-1][E][nslot][bsz]: operator, BILU(0) factors
+    DevBuf<float> A32, F32;
+    DevBuf<double> x, b, r, z, aux;  // [m-1][E nb] work vectors
+    DevBuf<float> x32, b32, r32, z32, aux32;
+  };
+  bool gmg = false;
+  int gmg_nu = 2;
+  std::vector<GLevel> gl;
+  DevBuf<double> gmg_pi;  // [2^d][nb][nb] child prolongations
+  DevBuf<float> gmg_pi32;
+  int gmg_nc = 0;         // unknowns per field of the coarsest level
+  DevBuf<double> gmg_cinv, gmg_cinvT;  // [m-1][nc][nc] coarsest inverse and its transpose
+  DevBuf<float> gmg_cinv32, gmg_cinvT32;
   // numeric state: potential part (phi block, its inverse blocks, multigrid
   // hierarchy, lambda_max) and concentration part (BILU(0) factors), in double
   // and, for the mixed path, single precision
@@ -212,6 +236,144 @@ template <> struct Sel<float> {
   static float* tN(Precond& P) { return P.tN32.p; }
 };
 
+
+// ---- concentration-block multigrid: host set-up ----------------------------------
+// hyperplane levels ix + iy + iz of the lexicographic elements of an n grid
+static void hyperplane_order(int dim, const int* n, std::vector<int64_t>& ptr, std::vector<int>& flat) {
+  const int nz = dim == 3 ? n[2] : 1;
+  const int64_t E = int64_t(n[0]) * n[1] * nz;
+  std::vector<std::vector<int>> lv(size_t(n[0] + n[1] + nz - 2));
+  for (int64_t e = 0; e < E; ++e) {
+    const int x = int(e % n[0]), y = int((e / n[0]) % n[1]), z = int(e / (int64_t(n[0]) * n[1]));
+    lv[size_t(x + y + z)].push_back(int(e));
+  }
+  ptr.assign(1, 0);
+  flat.clear();
+  for (auto& v : lv) {
+    flat.insert(flat.end(), v.begin(), v.end());
+    ptr.push_back(int64_t(flat.size()));
+  }
+}
+
+// slot-ordered neighbours (-x, +x, -y, +y, -z, +z), -1 on the boundary
+static std::vector<int> grid_neighbours(int dim, const int* n) {
+  const int nz = dim == 3 ? n[2] : 1;
+  const int64_t E = int64_t(n[0]) * n[1] * nz;
+  const int64_t stride[3] = {1, n[0], int64_t(n[0]) * n[1]};
+  std::vector<int> nbr(size_t(E) * 2 * dim, -1);
+  for (int64_t e = 0; e < E; ++e) {
+    const int id[3] = {int(e % n[0]), int((e / n[0]) % n[1]), int(e / stride[2])};
+    for (int a = 0; a < dim; ++a) {
+      if (id[a] > 0) nbr[size_t(e * 2 * dim + 2 * a)] = int(e - stride[a]);
+      if (id[a] < n[a] - 1) nbr[size_t(e * 2 * dim + 2 * a + 1)] = int(e + stride[a]);
+    }
+  }
+  return nbr;
+}
+
+// Pi[c][k][i]: the coarse nodal basis function i at fine node k of child c
+// (bit a of c: upper half along axis a), the tensor product of the 1-D Lagrange
+// interpolants of the p + 1 coarse nodes at the child's nodes
+static std::vector<double> child_prolongations(int p, int dim) {
+  const RefTables R = make_ref_tables(p);
+  const int nn = p + 1, nb = dim == 3 ? nn * nn * nn : nn * nn;
+  double V[2][4][4];  // V[s][k][i] = l_i((x_k + 2 s - 1) / 2)
+  for (int s = 0; s < 2; ++s)
+    for (int k = 0; k < nn; ++k) {
+      const double x = 0.5 * (R.xn[size_t(k)] + 2.0 * s - 1.0);
+      for (int i = 0; i < nn; ++i) {
+        double l = 1.0;
+        for (int j = 0; j < nn; ++j)
+          if (j != i) l *= (x - R.xn[size_t(j)]) / (R.xn[size_t(i)] - R.xn[size_t(j)]);
+        V[s][k][i] = l;
+      }
+    }
+  std::vector<double> Pi(size_t(1 << dim) * nb * nb);
+  for (int c = 0; c < (1 << dim); ++c)
+    for (int k = 0; k < nb; ++k)
+      for (int i = 0; i < nb; ++i) {
+        double v = 1.0;
+        int kk = k, ii = i;
+        for (int a = 0; a < dim; ++a) {
+          v *= V[(c >> a) & 1][kk % nn][ii % nn];
+          kk /= nn;
+          ii /= nn;
+        }
+        Pi[(size_t(c) * nb + k) * nb + i] = v;
+      }
+  return Pi;
+}
+
+static void gmg_symbolic(dgnp_ctx& c, Precond& P) {
+  P.gmg = true;
+  P.gmg_nu = c.gmg_nu;
+  P.gl.clear();
+  P.gl.emplace_back();
+  {
+    Precond::GLevel& g = P.gl.back();
+    for (int a = 0; a < 3; ++a) g.n[a] = c.n[a];
+    g.E = c.E;
+  }
+  // coarsen by 2 along every axis while every count is even and the level has
+  // more than 2^d elements
+  for (;;) {
+    const Precond::GLevel& f = P.gl.back();
+    bool even = true;
+    for (int a = 0; a < c.dim; ++a) even = even && f.n[a] % 2 == 0;
+    if (!even || f.E <= (int64_t(1) << c.dim)) break;
+    Precond::GLevel g;
+    for (int a = 0; a < 3; ++a) g.n[a] = a < c.dim ? f.n[a] / 2 : 1;
+    g.E = int64_t(g.n[0]) * g.n[1] * g.n[2];
+    P.gl.push_back(std::move(g));
+  }
+  const int64_t nc = P.gl.back().E * c.nb;
+  DGNP_REQUIRE(nc <= 1024, DGNP_E_ARG,
+               "the coarsest multigrid level has " + std::to_string(nc) +
+                   " unknowns per field (at most 1024): the element counts need more factors of 2");
+  P.gmg_nc = int(nc);
+  for (size_t l = 1; l < P.gl.size(); ++l) {
+    Precond::GLevel& g = P.gl[l];
+    g.nbr.upload(grid_neighbours(c.dim, g.n), c.stream);
+    std::vector<int> flat;
+    hyperplane_order(c.dim, g.n, g.lev_ptr, flat);
+    g.lev_elems.upload(flat, c.stream);
+  }
+  const std::vector<double> Pi = child_prolongations(c.p, c.dim);
+  P.gmg_pi.upload(Pi, c.stream);
+  std::vector<float> Pi32(Pi.begin(), Pi.end());
+  P.gmg_pi32.upload(Pi32, c.stream);
+  DGNP_HIP(hipStreamSynchronize(c.stream));
+}
+
+// In-place inverse of the dense n x n matrix a (row-major) by Gauss-Jordan
+// elimination with partial pivoting; DGNP_E_BREAKDOWN when a pivot vanishes.
+static void dense_inverse(std::vector<double>& a, int n) {
+  std::vector<int> piv(static_cast<size_t>(n), 0);
+  for (int k = 0; k < n; ++k) {
+    int r = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(a[size_t(i) * n + k]) > std::fabs(a[size_t(r) * n + k])) r = i;
+    DGNP_REQUIRE(a[size_t(r) * n + k] != 0.0 && std::isfinite(a[size_t(r) * n + k]), DGNP_E_BREAKDOWN,
+                 "singular coarsest multigrid level");
+    piv[size_t(k)] = r;
+    if (r != k)
+      for (int j = 0; j < n; ++j) std::swap(a[size_t(k) * n + j], a[size_t(r) * n + j]);
+    const double d = 1.0 / a[size_t(k) * n + k];
+    a[size_t(k) * n + k] = 1.0;
+    for (int j = 0; j < n; ++j) a[size_t(k) * n + j] *= d;
+    for (int i = 0; i < n; ++i) {
+      if (i == k) continue;
+      const double f = a[size_t(i) * n + k];
+      if (f == 0.0) continue;
+      a[size_t(i) * n + k] = 0.0;
+      for (int j = 0; j < n; ++j) a[size_t(i) * n + j] -= f * a[size_t(k) * n + j];
+    }
+  }
+  // undo the row interchanges as column interchanges, last first
+  for (int k = n - 1; k >= 0; --k)
+    if (piv[size_t(k)] != k)
+      for (int i = 0; i < n; ++i) std::swap(a[size_t(i) * n + k], a[size_t(i) * n + piv[size_t(k)]]);
+}
 
 void precond_symbolic(dgnp_ctx& c) {
   if (!c.pc) c.pc = new Precond();
@@ -299,6 +461,7 @@ void precond_symbolic(dgnp_ctx& c) {
       P.df_on = false;
     }
   }
+  if (c.conc_pc == DGNP_CPC_GMG) gmg_symbolic(c, P);
 }
 
 // Reports (and clears) a dataflow sweep that ended at its wait limit; the
@@ -514,6 +677,103 @@ struct PhaseClock {
   }
 };
 
+// Concentration multigrid, numeric part (see gmg_symbolic): the fine level's
+// unfactored blocks are kept, every coarser level gets its Galerkin operator
+// and (all but the coarsest) its BILU(0) factors, the coarsest its dense
+// inverse, computed on the host in double.  Single-precision copies with f32.
+static void gmg_numeric(dgnp_ctx& c, Precond& P, bool f32, hipStream_t s) {
+  const int nf = c.m - 1, ns = P.nslot, nb = c.nb;
+  auto per = [&](const Precond::GLevel& g) { return g.E * ns * P.bsz; };
+  Precond::GLevel& g0 = P.gl[0];
+  g0.A.alloc(size_t(nf * per(g0)));
+  DGNP_HIP(hipMemcpyAsync(g0.A.p, P.blk.p + per(g0), size_t(nf * per(g0)) * sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
+  if (f32) {
+    g0.A32.alloc(g0.A.n);
+    cvt_d2f(g0.A.p, g0.A32.p, int64_t(g0.A.n), s);
+  }
+  for (size_t l = 1; l < P.gl.size(); ++l) {
+    Precond::GLevel& f = P.gl[l - 1];
+    Precond::GLevel& g = P.gl[l];
+    g.A.alloc(size_t(nf * per(g)));
+    {
+      ScopeTimer tm(c, "gmg_galerkin", s);
+      launch_gmg_galerkin(nb, c.dim, nf, f.A.p, per(f), l == 1 ? c.d_nbr.p : f.nbr.p, f.n, P.gmg_pi.p, g.A.p,
+                          per(g), g.E, s);
+    }
+    if (l + 1 < P.gl.size()) {
+      g.F.alloc(g.A.n);
+      DGNP_HIP(hipMemcpyAsync(g.F.p, g.A.p, g.A.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      float* b32 = nullptr;
+      if (f32) {
+        g.F32.alloc(g.A.n);
+        b32 = g.F32.p;
+      }
+      ScopeTimer tm(c, "gmg_factor", s);
+      for (size_t lv = 0; lv + 1 < g.lev_ptr.size(); ++lv)
+        launch_ilu_factor(nb, c.dim, nf, per(g), g.F.p, g.nbr.p, g.lev_elems.p, g.lev_ptr[lv],
+                          g.lev_ptr[lv + 1] - g.lev_ptr[lv], s, b32);
+    }
+    if (f32) {
+      g.A32.alloc(g.A.n);
+      cvt_d2f(g.A.p, g.A32.p, int64_t(g.A.n), s);
+    }
+  }
+  // work vectors of every level
+  for (size_t l = 0; l < P.gl.size(); ++l) {
+    Precond::GLevel& g = P.gl[l];
+    const size_t n = size_t(nf * g.E * nb);
+    g.r.alloc(n);
+    g.z.alloc(n);
+    if (l > 0) {
+      g.x.alloc(n);
+      g.b.alloc(n);
+      g.aux.alloc(n);
+    }
+    if (f32) {
+      g.r32.alloc(n);
+      g.z32.alloc(n);
+      if (l > 0) {
+        g.x32.alloc(n);
+        g.b32.alloc(n);
+        g.aux32.alloc(n);
+      }
+    }
+  }
+  // coarsest level: dense inverse per field
+  Precond::GLevel& gc = P.gl.back();
+  const int n = P.gmg_nc;
+  std::vector<double> h(gc.A.n);
+  DGNP_HIP(hipMemcpyAsync(h.data(), gc.A.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  DGNP_HIP(hipStreamSynchronize(s));
+  const std::vector<int> nbr = grid_neighbours(c.dim, gc.n);
+  std::vector<double> inv(size_t(nf) * n * n), invT(inv.size());
+  for (int f = 0; f < nf; ++f) {
+    std::vector<double> M(size_t(n) * n, 0.0);
+    for (int64_t i = 0; i < gc.E; ++i)
+      for (int t = 0; t < ns; ++t) {
+        const int64_t j = t == 0 ? i : nbr[size_t(i * 2 * c.dim + t - 1)];
+        if (j < 0) continue;
+        const double* blk = h.data() + size_t(f * per(gc) + (i * ns + t) * P.bsz);
+        for (int r = 0; r < nb; ++r)
+          for (int q = 0; q < nb; ++q) M[size_t(i * nb + r) * n + size_t(j * nb + q)] = blk[r * nb + q];
+      }
+    dense_inverse(M, n);
+    for (int r = 0; r < n; ++r)
+      for (int q = 0; q < n; ++q) {
+        inv[size_t(f) * n * n + size_t(r) * n + q] = M[size_t(r) * n + q];
+        invT[size_t(f) * n * n + size_t(q) * n + r] = M[size_t(r) * n + q];
+      }
+  }
+  P.gmg_cinv.upload(inv, s);
+  P.gmg_cinvT.upload(invT, s);
+  if (f32) {
+    std::vector<float> i32(inv.begin(), inv.end()), t32(invT.begin(), invT.end());
+    P.gmg_cinv32.upload(i32, s);
+    P.gmg_cinvT32.upload(t32, s);
+  }
+}
+
 void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, int parts) {
   precond_check(c, false);
   Precond& P = *c.pc;
@@ -559,6 +819,12 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     if (f32) {
       P.blk32.alloc(size_t((c.m - 1) * per_field));
       b32 = P.blk32.p;
+    }
+    // multigrid levels from the unfactored fine blocks, before these are
+    // factorised in place
+    if (P.gmg) {
+      gmg_numeric(c, P, f32, s);
+      clk.mark("concentration multigrid levels");
     }
     for (size_t l = 0; l + 1 < P.lev_ptr.size(); ++l) {
       ScopeTimer tm(c, "ilu_factor", s);
@@ -960,6 +1226,100 @@ static void ilu_solve(dgnp_ctx& c, Precond& P, bool transpose, const T* in, T* o
   }
 }
 
+// ---- concentration multigrid: the V-cycle -----------------------------------------
+template <typename T> struct GSel;
+template <> struct GSel<double> {
+  using L = Precond::GLevel;
+  static const double* A(L& g) { return g.A.p; }
+  static const double* F(L& g) { return g.F.p; }
+  static double* x(L& g) { return g.x.p; }
+  static double* b(L& g) { return g.b.p; }
+  static double* r(L& g) { return g.r.p; }
+  static double* z(L& g) { return g.z.p; }
+  static double* aux(L& g) { return g.aux.p; }
+  static const double* pi(Precond& P) { return P.gmg_pi.p; }
+  static const double* cinv(Precond& P, bool tr) { return tr ? P.gmg_cinvT.p : P.gmg_cinv.p; }
+};
+template <> struct GSel<float> {
+  using L = Precond::GLevel;
+  static const float* A(L& g) { return g.A32.p; }
+  static const float* F(L& g) { return g.F32.p; }
+  static float* x(L& g) { return g.x32.p; }
+  static float* b(L& g) { return g.b32.p; }
+  static float* r(L& g) { return g.r32.p; }
+  static float* z(L& g) { return g.z32.p; }
+  static float* aux(L& g) { return g.aux32.p; }
+  static const float* pi(Precond& P) { return P.gmg_pi32.p; }
+  static const float* cinv(Precond& P, bool tr) { return tr ? P.gmg_cinvT32.p : P.gmg_cinv32.p; }
+};
+
+// BILU(0) solve (or its transpose) of every concentration field on level l:
+// the fine level through ilu_solve (dataflow or line sweeps where they run),
+// the coarser ones level-scheduled
+template <typename T>
+static void gmg_ilu(dgnp_ctx& c, Precond& P, int l, bool tr, const T* in, T* out, hipStream_t s) {
+  if (l == 0) return ilu_solve<T>(c, P, tr, in, out, s);
+  Precond::GLevel& g = P.gl[size_t(l)];
+  const int nf = c.m - 1;
+  const int64_t fs = g.E * P.nslot * P.bsz, vs = g.E * c.nb;
+  const T* blk = GSel<T>::F(g);
+  const int L = int(g.lev_ptr.size()) - 1;
+  T* aux = tr ? GSel<T>::aux(g) : nullptr;
+  const int k0 = tr ? 2 : 0;
+  for (int lv = 0; lv < L; ++lv)
+    launch_ilu_solve<T>(k0, c.nb, c.dim, blk, g.nbr.p, g.lev_elems.p, g.lev_ptr[lv], g.lev_ptr[lv + 1] - g.lev_ptr[lv],
+                        nf, fs, vs, in, tr ? aux : out, nullptr, s);
+  for (int lv = L - 1; lv >= 0; --lv)
+    launch_ilu_solve<T>(k0 + 1, c.nb, c.dim, blk, g.nbr.p, g.lev_elems.p, g.lev_ptr[lv],
+                        g.lev_ptr[lv + 1] - g.lev_ptr[lv], nf, fs, vs, tr ? nullptr : out, out, aux, s);
+}
+
+// One V-cycle from a zero initial guess on level l for every concentration
+// field: nu Richardson steps x <- x + M^{-1} (b - A x) with the level's BILU(0)
+// M, the coarse correction x <- x + P V_{l+1}(P^T (b - A x)), nu more steps; the
+// coarsest level multiplies by its dense inverse.  tr: the same cycle with A^T,
+// M^{-T} and the transposed coarsest inverse, which is the cycle's transpose
+// (restriction and prolongation are each other's transposes).
+template <typename T>
+static void gmg_vcycle(dgnp_ctx& c, Precond& P, bool tr, int l, const T* b, T* x, hipStream_t s) {
+  const int nf = c.m - 1, last = int(P.gl.size()) - 1;
+  Precond::GLevel& g = P.gl[size_t(l)];
+  const int64_t nfl = g.E * c.nb;
+  if (l == last) {
+    const int n = P.gmg_nc;
+    for (int f = 0; f < nf; ++f)
+      launch_dense_gemv<T>(n, GSel<T>::cinv(P, tr) + int64_t(f) * n * n, b + f * nfl, x + f * nfl, s);
+    return;
+  }
+  const T* A = GSel<T>::A(g);
+  const int* nbr = l == 0 ? c.d_nbr.p : g.nbr.p;
+  const int64_t fs = g.E * P.nslot * P.bsz;
+  T* r = GSel<T>::r(g);
+  T* z = GSel<T>::z(g);
+  auto richardson = [&]() {
+    launch_gmg_resid<T>(c.nb, c.dim, nf, tr, A, fs, nbr, g.E, x, b, r, s);
+    gmg_ilu<T>(c, P, l, tr, r, z, s);
+    vaxpy<T>(T(1), z, x, nf * nfl, s);
+  };
+  gmg_ilu<T>(c, P, l, tr, b, x, s);  // first step from x = 0
+  for (int k = 1; k < P.gmg_nu; ++k) richardson();
+  Precond::GLevel& gc = P.gl[size_t(l + 1)];
+  const int64_t nfc = gc.E * c.nb;
+  launch_gmg_resid<T>(c.nb, c.dim, nf, tr, A, fs, nbr, g.E, x, b, r, s);
+  launch_gmg_restrict<T>(c.nb, c.dim, nf, GSel<T>::pi(P), g.n, r, nfl, GSel<T>::b(gc), nfc, s);
+  gmg_vcycle<T>(c, P, tr, l + 1, GSel<T>::b(gc), GSel<T>::x(gc), s);
+  launch_gmg_prolong<T>(c.nb, c.dim, nf, GSel<T>::pi(P), g.n, GSel<T>::x(gc), nfc, x, nfl, s);
+  for (int k = 0; k < P.gmg_nu; ++k) richardson();
+}
+
+// the concentration blocks' solve of the block-triangular preconditioner
+template <typename T>
+static void conc_solve(dgnp_ctx& c, Precond& P, bool transpose, const T* in, T* out, hipStream_t s) {
+  if (!P.gmg) return ilu_solve<T>(c, P, transpose, in, out, s);
+  ScopeTimer tm(c, std::is_same<T, float>::value ? "gmg_f32" : "gmg", s);
+  gmg_vcycle<T>(c, P, transpose, 0, in, out, s);
+}
+
 template <typename T>
 static void apply_t(dgnp_ctx& c, const T* r, T* z, bool transpose, int kind, hipStream_t s) {
   Precond& P = *c.pc;
@@ -973,7 +1333,7 @@ static void apply_t(dgnp_ctx& c, const T* r, T* z, bool transpose, int kind, hip
   // the coupling applies read z with the other part masked out (counted as zero)
   const unsigned phi_only = 1u, conc_only = ~1u;
   if (c_first) {
-    ilu_solve<T>(c, P, transpose, r + Nf, z + Nf, s);
+    conc_solve<T>(c, P, transpose, r + Nf, z + Nf, s);
     if (!transpose) {
       jac_apply(c, z, t, f32, false, s, conc_only, true, r);  // t = r - A_phic z_c, potential rows only
     } else {
@@ -989,7 +1349,7 @@ static void apply_t(dgnp_ctx& c, const T* r, T* z, bool transpose, int kind, hip
     }
     jac_apply(c, z, y, f32, transpose, s, phi_only);
     vsub<T>(r + Nf, y + Nf, t + Nf, (c.m - 1) * Nf, s);
-    ilu_solve<T>(c, P, transpose, t + Nf, z + Nf, s);
+    conc_solve<T>(c, P, transpose, t + Nf, z + Nf, s);
   }
 }
 

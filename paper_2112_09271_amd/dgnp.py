@@ -26,6 +26,7 @@ DGNP_OBJ_OUTFLOW, DGNP_OBJ_ELECTRODE = 0, 1
 # potential multigrid: automatic / Q1 Galerkin start / p-multigrid (re-discretised, Galerkin p = 1 level)
 DGNP_PHIMG_AUTO, DGNP_PHIMG_Q1, DGNP_PHIMG_P, DGNP_PHIMG_PG = 0, 1, 2, 3
 DGNP_PHIOP_ASSEMBLED, DGNP_PHIOP_MATFREE = 0, 1  # potential-block apply: assembled / matrix-free
+DGNP_CPC_BILU, DGNP_CPC_GMG = 0, 1  # concentration-block preconditioner
 MAX_HIST = 64
 
 
@@ -55,7 +56,7 @@ class dgnp_options(C.Structure):
     _fields_ = [("c_ip", C.c_double), ("mms", C.c_int32), ("bc_conc", C.POINTER(C.c_double)),
                 ("phi_mg", C.c_int32), ("src_vol", C.POINTER(C.c_double)), ("dir_face", C.POINTER(C.c_double)),
                 ("alloc", ALLOC_FN), ("free_", FREE_FN), ("alloc_ctx", C.c_void_p),
-                ("electrode", C.POINTER(dgnp_electrode))]
+                ("electrode", C.POINTER(dgnp_electrode)), ("conc_pc", C.c_int32), ("gmg_nu", C.c_int32)]
 
 
 class TorchAllocator:
@@ -231,9 +232,13 @@ class Problem:
     `bc_conc` the nodal boundary data [m-1][n_bnode] (None with a manufactured
     solution); `phi_mg` the potential-block multigrid (DGNP_PHIMG_AUTO: Q1 for
     p <= 2, PG for p = 3; DGNP_PHIMG_Q1; for orders 2 and 3 DGNP_PHIMG_P or
-    DGNP_PHIMG_PG: p-multigrid with a re-discretised or Galerkin p = 1 level)."""
+    DGNP_PHIMG_PG: p-multigrid with a re-discretised or Galerkin p = 1 level);
+    `conc_pc` the concentration-block preconditioner (DGNP_CPC_BILU, or
+    DGNP_CPC_GMG: one geometric-multigrid V-cycle with `gmg_nu` ILU(0)
+    Richardson steps per side, 0 for the default 2)."""
 
-    def __init__(self, cfg, bc_conc=None, Pe=None, phi_mg=0, src_vol=None, dir_face=None, allocator=None):
+    def __init__(self, cfg, bc_conc=None, Pe=None, phi_mg=0, src_vol=None, dir_face=None, allocator=None,
+                 conc_pc=DGNP_CPC_BILU, gmg_nu=0):
         """src_vol [m][E][nq^d], dir_face [m][n_bface][nq^(d-1)]: optional caller
         sources and boundary data at the Gauss points (dgnp_options); allocator:
         an optional TorchAllocator (or any object with c_alloc / c_free ctypes
@@ -263,6 +268,8 @@ class Problem:
         opt.c_ip = cfg.c_ip
         opt.mms = cfg.mms
         opt.phi_mg = int(phi_mg)
+        opt.conc_pc = int(conc_pc)
+        opt.gmg_nu = int(gmg_nu)
         self._bc = None
         if bc_conc is not None:
             self._bc = np.ascontiguousarray(bc_conc, dtype=np.float64)

@@ -1,0 +1,110 @@
+"""Geometric multigrid on the concentration blocks (Sec. 4.1 GMG with the
+block ILU(0) smoother; dgnp_options.conc_pc = DGNP_CPC_GMG) against the
+oracle's V-cycle (oracle/mg.py) on the same linearisation point: the
+concentration part of the block-triangular preconditioner (Eq. P2, which solves
+the concentration blocks first) is one V-cycle per block.  Also: the
+preconditioner's transpose with GMG is its adjoint, converged solves with GMG
+match the oracle's Newton solution, and a coarsest level beyond the dense
+limit is refused."""
+import numpy as np
+import pytest
+
+from oracle import mg
+from oracle import solve as osolve
+from oracle.dg import DG
+from oracle.problem import Problem as OProblem
+from tests.gpu_cases import gpu_available, host, rel_err
+from tests.oracle_cases import gmg_box
+from workload import boundary_data, get_config, random_state, random_vector
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+CASES = [(2, (8, 8), 1), (2, (6, 4), 1), (2, (4, 4), 2), (3, (4, 4, 4), 1), (3, (4, 4, 2), 2), (3, (8, 4, 4), 1)]
+
+
+def _gpu(cfg, nu=0):
+    from paper_2112_09271_amd.dgnp import DGNP_CPC_GMG, Problem
+    print(f"[case] {cfg.name} n={cfg.n} p={cfg.p} gmg nu={nu}", flush=True)
+    return Problem(cfg, boundary_data(cfg), conc_pc=DGNP_CPC_GMG, gmg_nu=nu)
+
+
+@pytest.mark.parametrize("dim,n,p", CASES)
+def test_vcycle_matches_oracle(dim, n, p):
+    from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64
+    cfg = gmg_box(dim, n, p, Pe=200.0)
+    dg = DG(OProblem(cfg, boundary_data(cfg)))
+    x = random_state(cfg)
+    r = random_vector(cfg, 31)
+    Nf = dg.msh.Nf
+    ref = np.zeros(len(r))
+    for k in range(1, cfg.m):
+        A = dg.jacobian(x, fields=[(k, k)]).tocsr()[k * Nf:(k + 1) * Nf, k * Nf:(k + 1) * Nf]
+        g = mg.GMG(A, n, p, nu=2)
+        ref[k * Nf:(k + 1) * Nf] = g.vcycle(r[k * Nf:(k + 1) * Nf])
+    print("levels", g.dims)
+    gp = _gpu(cfg)
+    for prec, tol in ((DGNP_F64, 1e-10), (DGNP_F32, 2e-4)):
+        gp.set_state(x, prec=prec)
+        z = host(gp.precond_apply(r, prec=prec))
+        err = rel_err(z[Nf:], ref[Nf:])
+        print(f"prec={prec}: rel err {err:.2e}")
+        assert err <= tol
+    gp.close()
+
+
+@pytest.mark.parametrize("dim,n,p", [(2, (8, 8), 1), (3, (4, 4, 4), 1), (3, (4, 4, 2), 2)])
+def test_transpose_is_adjoint(dim, n, p):
+    from paper_2112_09271_amd.dgnp import DGNP_F64, DGNP_PC_P1, DGNP_PC_P2
+    cfg = gmg_box(dim, n, p, Pe=200.0)
+    gp = _gpu(cfg, nu=1)
+    gp.set_state(random_state(cfg), prec=DGNP_F64)
+    r, w = random_vector(cfg, 41), random_vector(cfg, 42)
+    for kind in (DGNP_PC_P2, DGNP_PC_P1):
+        a = host(gp.precond_apply(r, pc_kind=kind)) @ w
+        b = r @ host(gp.precond_apply(w, transpose=True, pc_kind=kind))
+        print(kind, a, b)
+        assert abs(a - b) <= 1e-11 * abs(a)
+    gp.close()
+
+
+@pytest.mark.parametrize("cfg_fn", [lambda: gmg_box(3, (4, 4, 4), 1, Pe=100.0),
+                                    lambda: get_config("cfg2t"),
+                                    lambda: get_config("cfg2t").with_(p=1)])
+def test_solve_matches_oracle(cfg_fn):
+    from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64
+    cfg = cfg_fn()
+    od = DG(OProblem(cfg, boundary_data(cfg)))
+    x_ref, _ = osolve.newton(od, tol=1e-13)
+    gp = _gpu(cfg)
+    for prec in (DGNP_F64, DGNP_F32):
+        x, st = gp.solve(rtol=1e-11, prec=prec)
+        err = rel_err(host(x), x_ref)
+        print(f"{cfg.name} p={cfg.p} prec={prec}: newton {st.newton_its}, fgmres {st.lin_its_total}, rel err {err:.2e}")
+        assert st.status == 0 and st.res_final <= 1e-11 * st.res0
+        assert err <= 1e-8
+    gp.close()
+
+
+def test_fewer_krylov_iterations_than_bilu():
+    """On a p = 1 box with moderate convection the V-cycle is a better
+    approximate inverse of the concentration blocks than one BILU(0) solve."""
+    from paper_2112_09271_amd.dgnp import DGNP_F32, Problem
+    cfg = gmg_box(3, (16, 16, 16), 1, Pe=20.0)
+    data = boundary_data(cfg)
+    its = {}
+    for name, kw in (("bilu", {}), ("gmg", {"conc_pc": 1})):
+        gp = Problem(cfg, data, **kw)
+        x, st = gp.solve(prec=DGNP_F32)
+        assert st.status == 0
+        its[name] = st.lin_its_total
+        gp.close()
+    print(its)
+    assert its["gmg"] < its["bilu"]
+
+
+def test_coarsest_level_limit_is_refused():
+    from paper_2112_09271_amd.dgnp import DGNP_E_ARG, DgnpError
+    cfg = gmg_box(3, (9, 9, 9), 1, Pe=10.0)
+    with pytest.raises(DgnpError) as ei:
+        _gpu(cfg)
+    assert ei.value.code == DGNP_E_ARG and "coarsest" in str(ei.value)
