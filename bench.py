@@ -12,7 +12,9 @@ One JSON line is printed.  Besides the contract fields it carries the FP64
 time-to-solution on the same input, the adjoint-gradient time, the
 Jacobian-apply bandwidth on the largest channel (128x32x16 hexes, p = 3,
 12.6M DOFs), mixed and FP64 time-to-solution on the two channels (64x16x8 and
-128x32x16 hexes, p = 3) with an adjoint on the larger, the roofline of the
+128x32x16 hexes, p = 3) with an adjoint on the larger, the two
+concentration-block preconditioners (block ILU(0) and geometric multigrid) on
+the p = 1 channel of the same size (256x64x32 hexes), the roofline of the
 dominant kernel of the timed solve and the CPU oracle baseline.
 """
 from __future__ import annotations
@@ -46,6 +48,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the FP64, adjoint, large-apply and channel-solve legs")
     ap.add_argument("--only-apply", action="store_true", help="run only the large Jacobian-apply leg")
+    ap.add_argument("--only-gmg", action="store_true",
+                    help="run only the concentration-preconditioner comparison on the p = 1 channel")
     ap.add_argument("--apply-variants", default="",
                     help="comma-separated launch variants of the Jacobian apply to time (A/B), then exit")
     return ap.parse_args()
@@ -100,10 +104,11 @@ def japply_bytes(N, word):
 
 def japply_flops(cfg):
     """Floating-point operations of the sum-factorised contractions of one
-    Jacobian apply as the kernel performs them (2 per multiply-add): two
-    volume interpolations (state, input) and one integration per element; per
-    element face four trace evaluations (own and neighbour, state and input)
-    and one face integration.  The pointwise flux arithmetic is not counted."""
+    Jacobian apply as the kernel performs them (2 per multiply-add): the state
+    is tabulated at the quadrature points once per linearisation, so per
+    element one interpolation of the input and one integration; per element
+    face two trace evaluations of the input (own and neighbour) and one face
+    integration.  The pointwise flux arithmetic is not counted."""
     import numpy as np
     d, p, m = cfg.dim, cfg.p, cfg.m
     nn, nq = p + 1, p + 2
@@ -116,7 +121,7 @@ def japply_flops(cfg):
         vol = m * (2 * nn * nn * nq + 3 * nn * nq * nq)
         trace = m * (nn * nn + 2 * nn * nq)
         finteg = m * (2 * nn * nq + nn * nn)
-    per_elem = 3 * vol + 2 * d * (4 * trace + finteg)
+    per_elem = 2 * vol + 2 * d * (2 * trace + finteg)
     return 2.0 * per_elem * E
 
 
@@ -351,6 +356,56 @@ def channel_solves(names):
     return out
 
 
+def conc_pc_solves(names, reps=3):
+    """The p = 1 channel with the two concentration-block preconditioners of
+    Sec. 4.1: one block-ILU(0) solve (the one-subdomain ASM) against one
+    geometric-multigrid V-cycle (1 and 2 ILU(0) Richardson steps per side);
+    mixed-precision time-to-1e-8 (median of `reps` after one untimed run),
+    iterations, set-up / Krylov split and agreement with the BILU solution."""
+    import numpy as np
+    import torch
+
+    from paper_2112_09271_amd.dgnp import DGNP_CPC_GMG, DGNP_F32, Problem
+    from workload import boundary_data, get_config
+    out = {}
+    for name in names:
+        cfg = get_config(name)
+        data = boundary_data(cfg)
+        rec = {"workload": f"{cfg.name}: {cfg.note}"}
+        x_ref = None
+        for label, kw in (("bilu", {}), ("gmg_nu1", {"conc_pc": DGNP_CPC_GMG, "gmg_nu": 1}),
+                          ("gmg_nu2", {"conc_pc": DGNP_CPC_GMG, "gmg_nu": 2})):
+            prob = Problem(cfg, data, **kw)
+            rec["dofs"] = prob.N
+
+            def run():
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, st = prob.solve(rtol=cfg.newton_tol, prec=DGNP_F32)
+                torch.cuda.synchronize()
+                if st.status != 0:
+                    raise RuntimeError(f"{name} {label} solve failed with status {st.status}")
+                return x, st, time.perf_counter() - t0
+
+            run()
+            runs = [run() for _ in range(reps)]
+            x, st = runs[-1][0], runs[-1][1]
+            r = {"mixed_s": float(np.median([q[2] for q in runs])), "newton_its": st.newton_its,
+                 "fgmres_its": st.lin_its_total, "setup_s": st.t_setup, "krylov_s": st.t_krylov}
+            if x_ref is None:
+                x_ref = x.clone()
+            else:
+                r["vs_bilu_rel_l2"] = (x - x_ref).norm().item() / x_ref.norm().item()
+            rec[label] = r
+            log(f"[bench] {name} {label}: mixed {r['mixed_s']:.3f}s ({st.lin_its_total} its)")
+            del runs, x
+            prob.close()
+            torch.cuda.empty_cache()
+        rec["gmg_nu1_speedup_vs_bilu"] = rec["bilu"]["mixed_s"] / rec["gmg_nu1"]["mixed_s"]
+        out[name] = rec
+    return out
+
+
 def copy_bandwidth(mib=512, reps=20):
     """GB/s (read + write bytes) of a device-to-device copy of `mib` MiB, timed
     with events over `reps` copies after one untimed copy."""
@@ -386,6 +441,9 @@ def main():
     torch.cuda.set_device(0)
     if args.only_apply:
         print(json.dumps({"jacobian_apply": apply_bandwidth(args.apply_workload)}), flush=True)
+        return
+    if args.only_gmg:
+        print(json.dumps({"concentration_preconditioners": conc_pc_solves(["ch256p1"])}), flush=True)
         return
     if args.apply_variants:
         res = {}
@@ -519,6 +577,7 @@ def main():
                                                                             "pointwise.hpp"))
         out["jacobian_apply"] = ja
         out["channel_solves"] = channel_solves(["cfg3", "cfg5"])
+        out["concentration_preconditioners"] = conc_pc_solves(["ch256p1"])
     if not args.no_cpu:
         # the GPU's mixed solve of the oracle's sample input, beside the oracle
         small = get_config("cfg2t")

@@ -97,6 +97,13 @@ CONFIGS["cfg4"] = CONFIGS["cfg2"].with_(name="cfg4", note="adjoint on cfg2 cube"
 # Small variants used where the oracle's direct solver must finish quickly.
 CONFIGS["cfg2s"] = CONFIGS["cfg2"].with_(name="cfg2s", n=(8, 8, 8), note="cfg2 physics on 8^3")
 CONFIGS["cfg2t"] = CONFIGS["cfg2"].with_(name="cfg2t", n=(4, 4, 4), note="cfg2 physics on 4^3")
+# The channel at p = 1 with the same 12.6M DOFs as cfg5: one GPU's share (an
+# eighth) of the paper's 100.7M-DOF structured p = 1 strong-scaling channel,
+# where the concentration-block preconditioners ASM and GMG are compared.
+CONFIGS["ch256p1"] = CONFIGS["cfg5"].with_(name="ch256p1", n=(256, 64, 32), p=1,
+                                          note="channel 256x64x32 p=1 Poiseuille Pe=1e4")
+CONFIGS["ch64p1"] = CONFIGS["cfg5"].with_(name="ch64p1", n=(64, 16, 8), p=1,
+                                         note="channel 64x16x8 p=1 Poiseuille Pe=1e4")
 CONFIGS["cfg3s"] = CONFIGS["cfg3"].with_(name="cfg3s", n=(8, 4, 2), hi=(1.0, 0.5, 0.25),
                                          note="channel physics on 8x4x2")
 
