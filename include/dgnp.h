@@ -209,10 +209,17 @@ typedef struct {
   int32_t lin_its[DGNP_MAX_HIST];
 } dgnp_solve_stats;
 
-/* Builds mesh/face/DOF tables, reference tables (Gauss-Lobatto nodes, p+2
- * Gauss points per axis), boundary data and the symbolic preconditioner
- * setup; uploads them on `stream`.  order = p in 1..3.  Errors: DGNP_E_ARG
- * for unsupported sizes/kinds, DGNP_E_ALLOC / DGNP_E_HIP. */
+/* Sets up the DG discretisation of Sec. 3.3 (Eqs. NPDG and chargeDG, the
+ * nondimensional model of Sec. 2.3 in the charge-conservation form of
+ * Sec. 2.2) on a structured box of hexahedra of order p (Sec. 4: tensor-product
+ * elements): mesh/face/DOF tables, reference tables (Gauss-Lobatto nodes, p+2
+ * Gauss points per axis), boundary data (Sec. 2.1 boundary conditions;
+ * Butler-Volmer faces Eqs. electrode and bv) and the symbolic part of the
+ * block preconditioner of Sec. 4.1 / 4.2; uploads them on `stream`.
+ * order = p in 1..3.  The caller's arrays are copied; *out receives the new
+ * context (owned by the library until dgnp_destroy).  Errors: DGNP_E_ARG for
+ * unsupported sizes or kinds and for a potential that no face fixes,
+ * DGNP_E_NONFINITE for non-finite data, DGNP_E_ALLOC / DGNP_E_HIP. */
 int dgnp_setup(const dgnp_mesh *mesh, int32_t order, const dgnp_species *sp,
                const dgnp_velocity *vel, const dgnp_options *opt, void *stream,
                dgnp_ctx **out);
@@ -250,11 +257,18 @@ int dgnp_residual(dgnp_ctx *ctx, const double *x, double *r, void *stream);
  * velocity scale, |s|' = sign(s), sign(0) = 0).  Device double [N]. */
 int dgnp_residual_dpe(dgnp_ctx *ctx, const double *x, double *r, void *stream);
 
-/* Sets the linearisation point x (device double [N]) for the Jacobian and the
- * preconditioner: stores x (and a float copy), assembles the diagonal field
- * blocks A_phiphi, A_ckck on the device, factors element-block ILU(0) of
- * every A_ckck and sets up the AMG hierarchy of A_phiphi.  prec = DGNP_F32
- * also prepares float copies of all of it.  Synchronises. */
+/* Sets the linearisation point x (device double [N]) of the Newton step
+ * (Sec. 4, Eq. blockmatrix): stores x (and a float copy), tabulates the
+ * state at the quadrature points for the Jacobian apply, assembles the
+ * diagonal field blocks A_phiphi, A_ckck on the device, and builds the
+ * preconditioner of Sec. 4.1 / 4.2: element-block ILU(0) of every A_ckck (or
+ * their multigrid levels with conc_pc = DGNP_CPC_GMG) and the multigrid
+ * hierarchy of A_phiphi.  prec = DGNP_F32 also prepares float copies of all of
+ * it (the mixed-precision solve).  The flags DGNP_STATE_APPLY_ONLY (tables
+ * only, no preconditioner) and DGNP_STATE_ASSEMBLE_ONLY (blocks without
+ * factorisation) may be or-ed into prec.  x is read during the call only.
+ * Synchronises.  Errors: DGNP_E_ARG, DGNP_E_BREAKDOWN (singular coarsest
+ * multigrid level), DGNP_E_ALLOC / DGNP_E_HIP. */
 int dgnp_set_state(dgnp_ctx *ctx, const double *x, int32_t prec, void *stream);
 
 /* y = J(x) v (transpose = 0) or y = J(x)^T v (transpose = 1), matrix-free,
