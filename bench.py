@@ -3,10 +3,14 @@
 A step is one complete mixed-precision solve of the CNP DG system on the
 16^3-hex, p = 2, three-ion cube (vortex flow, Pe = 1e3) from the paper's
 initial guess to ||R|| <= 1e-8 ||R_0||: residual, block assembly, BILU(0)
-factorisation, multigrid set-up, FGMRES with the block-triangular
-preconditioner (ILU solves, V-cycle, coupling applies) and FP32 Jacobian
-applies under FP64 residuals and refinement, backtracking line search.  The
-seeded synthetic inputs are resident on the GPU before timing starts.
+factorisation of every multigrid level of the concentration blocks and their
+Galerkin operators, the potential multigrid set-up, FGMRES with the
+block-triangular preconditioner (one geometric-multigrid V-cycle per
+concentration block with ILU(0) smoothing, the potential V-cycle, coupling
+applies; Sec. 4.1's second approach, `--conc-pc bilu` for its first) and FP32
+Jacobian applies under FP64 residuals and refinement, backtracking line
+search.  The seeded synthetic inputs are resident on the GPU before timing
+starts.
 
 One JSON line is printed.  Besides the contract fields it carries the FP64
 time-to-solution on the same input, the adjoint-gradient time, the
@@ -50,6 +54,9 @@ def parse():
     ap.add_argument("--only-apply", action="store_true", help="run only the large Jacobian-apply leg")
     ap.add_argument("--only-gmg", action="store_true",
                     help="run only the concentration-preconditioner comparison on the p = 1 channel")
+    ap.add_argument("--conc-pc", default="gmg", choices=("gmg", "bilu"),
+                    help="concentration-block preconditioner of the timed solve (Sec. 4.1): one geometric-"
+                         "multigrid V-cycle with one ILU(0) smoothing step per side, or one block-ILU(0) solve")
     ap.add_argument("--apply-variants", default="",
                     help="comma-separated launch variants of the Jacobian apply to time (A/B), then exit")
     return ap.parse_args()
@@ -435,7 +442,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64, Problem
+    from paper_2112_09271_amd.dgnp import DGNP_CPC_GMG, DGNP_F32, DGNP_F64, Problem
     from workload import boundary_data, get_config
 
     torch.cuda.set_device(0)
@@ -454,8 +461,10 @@ def main():
         print(json.dumps({"jacobian_apply_variants": res}), flush=True)
         return
     cfg = get_config(args.workload)
-    prob = Problem(cfg, boundary_data(cfg))
-    log(f"[bench] workload {cfg.name}: {cfg.note}, N = {prob.N} DOFs")
+    pc_kw = {"conc_pc": DGNP_CPC_GMG, "gmg_nu": 1} if args.conc_pc == "gmg" else {}
+    pc_name = "GMG V-cycle, 1 ILU(0) step per side" if args.conc_pc == "gmg" else "BILU(0)"
+    prob = Problem(cfg, boundary_data(cfg), **pc_kw)
+    log(f"[bench] workload {cfg.name}: {cfg.note}, N = {prob.N} DOFs, concentration preconditioner {pc_name}")
 
     def solve(prec):
         torch.cuda.synchronize()
@@ -547,7 +556,8 @@ def main():
         "data": "synthetic (seeded inflow data U[0.5,1.5], random-free solve)",
         "config": {"workload": f"{cfg.name}: {cfg.note}", "elements": list(cfg.n), "order": cfg.p,
                    "ions": cfg.m, "dofs": prob.N, "newton_rtol": cfg.newton_tol,
-                   "newton_its": st32.newton_its, "fgmres_its": st32.lin_its_total},
+                   "newton_its": st32.newton_its, "fgmres_its": st32.lin_its_total,
+                   "concentration_preconditioner": pc_name},
         "roofline": roofline,
         "other_kernels": others,
         "kernel_seconds_per_solve": {k: round(v[0], 6) for k, v in kern.items()},
@@ -572,6 +582,29 @@ def main():
         out["adjoint_time_s"] = float(np.median(ta))
         log(f"[bench] fp64 {t64:.3f}s, adjoint {out['adjoint_time_s']:.3f}s")
         prob.close()
+        if pc_kw:
+            # the same solves with one block-ILU(0) solve per concentration block
+            pb = Problem(cfg, boundary_data(cfg))
+            rec = {}
+            for tag, prec in (("mixed_s", DGNP_F32), ("fp64_s", DGNP_F64)):
+                solve_with = [None]
+
+                def run_b():
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    x, st = pb.solve(rtol=cfg.newton_tol, prec=prec)
+                    torch.cuda.synchronize()
+                    if st.status != 0:
+                        raise RuntimeError(f"BILU solve failed with status {st.status}")
+                    solve_with[0] = st
+                    return time.perf_counter() - t0
+
+                run_b()
+                rec[tag] = float(np.median([run_b() for _ in range(REPS)]))
+                rec["fgmres_its" if prec == DGNP_F32 else "fgmres_its_fp64"] = solve_with[0].lin_its_total
+            pb.close()
+            out["bilu_concentration_preconditioner"] = rec
+            log(f"[bench] BILU(0): mixed {rec['mixed_s']:.4f}s, fp64 {rec['fp64_s']:.4f}s")
         ja = apply_bandwidth(args.apply_workload)
         ja["traffic_f32"] = measured_traffic("k_jlin_f32_cfg5", source_hash("kernels_jac.hip", "dg_device.hpp",
                                                                             "pointwise.hpp"))

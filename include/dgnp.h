@@ -174,7 +174,7 @@ typedef struct {
   /* Concentration-block preconditioner (Sec. 4.1), DGNP_CPC_*: BILU (0, the
    * default) one block-ILU(0) solve per concentration block; GMG one V-cycle
    * of geometric multigrid per block: the box coarsened by 2 along every axis
-   * while every element count is even and a level has more than 2^d elements,
+   * while every element count is even (down to one element where they allow),
    * Galerkin coarse operators with the nested DG prolongation, gmg_nu
    * Richardson steps with the level's block ILU(0) before and after the coarse
    * correction, and the coarsest level solved with its dense inverse (at most

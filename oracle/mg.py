@@ -11,7 +11,7 @@ the block ILU(0) of the whole level.
 
 Readings taken here (the paper fixes none of them):
   * levels: the structured box coarsened by 2 along every axis while every
-    element count is even and the level has more than 2^d elements;
+    element count is even (down to a single element where the counts allow);
   * coarse operators: Galerkin products P^T A P.  The coarse space (degree-p
     polynomials on each coarse element) lies inside the fine one, and P
     evaluates a coarse element's polynomial at the nodes of its 2^d children;
@@ -177,9 +177,9 @@ class BlockILU0:
 
 
 def coarsen_dims(n, max_elems=None):
-    """Element counts of the levels, finest first (see the module notes)."""
-    dim = len(n)
-    stop = 2 ** dim if max_elems is None else max_elems
+    """Element counts of the levels, finest first (see the module notes);
+    max_elems: stop at the first level with at most that many elements."""
+    stop = 1 if max_elems is None else max_elems
     dims = [tuple(int(v) for v in n)]
     while all(v % 2 == 0 for v in dims[-1]) and int(np.prod(dims[-1])) > stop:
         dims.append(tuple(v // 2 for v in dims[-1]))

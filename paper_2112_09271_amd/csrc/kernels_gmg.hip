@@ -186,6 +186,130 @@ __global__ void __launch_bounds__(GT) k_gmg_resid(const T* __restrict__ blk, int
   r[g] = b[g] - acc;
 }
 
+// Dense matrix of one field of a block level (the coarsest): M[(i nb + r) n +
+// j nb + q] = block (i, slot t) [r][q] with j the slot's neighbour; one thread
+// per (block entry, field).  M must be zeroed before.
+template <int NB, int DIM>
+__global__ void __launch_bounds__(GT) k_gmg_densify(const double* __restrict__ blk, int64_t fs,
+                                                    const int* __restrict__ nbr, int64_t E, double* __restrict__ M,
+                                                    int n) {
+  constexpr int NS = 2 * DIM + 1, BB = NB * NB;
+  const int64_t g = blockIdx.x * int64_t(GT) + threadIdx.x;
+  if (g >= E * NS * BB) return;
+  const int rq = int(g % BB), t = int((g / BB) % NS);
+  const int64_t i = g / (BB * NS);
+  const int64_t j = t == 0 ? i : int64_t(nbr[i * 2 * DIM + t - 1]);
+  if (j < 0) return;
+  const int r = rq / NB, q = rq % NB;
+  M[blockIdx.y * int64_t(n) * n + (i * NB + r) * n + j * NB + q] = blk[blockIdx.y * fs + g];
+}
+
+// In-place inverse of one dense n x n matrix per work-group (row-major) by
+// Gauss-Jordan elimination with partial pivoting (ties to the lower row),
+// then its transpose into MT.  When a pivot vanishes or is not finite, *err
+// is set and both matrices are filled with NaN, so that the solve using them
+// reports a non-finite vector.  n <= 1024; up to order 128 the elimination
+// runs on a copy in LDS (each step is then bound by barriers, not by global
+// memory round trips).
+constexpr int DI = 1024;
+constexpr int DI_LDS = 128;  // matrices up to this order are eliminated in LDS
+template <bool SH>
+__global__ void __launch_bounds__(DI) k_dense_inverse(double* __restrict__ Mg, double* __restrict__ MT, int n,
+                                                      int* __restrict__ err) {
+  Mg += blockIdx.x * int64_t(n) * n;
+  MT += blockIdx.x * int64_t(n) * n;
+  __shared__ double sM[SH ? DI_LDS * DI_LDS : 1];
+  double* M = SH ? sM : Mg;
+  if constexpr (SH) {
+    for (int64_t idx = threadIdx.x; idx < int64_t(n) * n; idx += DI) sM[idx] = Mg[idx];
+    __syncthreads();
+  }
+  __shared__ int perm[DI];
+  __shared__ double colk[DI];
+  __shared__ double rv[DI / 64];
+  __shared__ int ri[DI / 64];
+  __shared__ int s_piv, s_bad;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int k = 0; k < n; ++k) {
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + tid; i < n; i += DI) {
+      const double v = fabs(M[int64_t(i) * n + k]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      rv[wave] = best;
+      ri[wave] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double b = rv[0];
+      int p = ri[0];
+      for (int w = 1; w < DI / 64; ++w)
+        if (rv[w] > b || (rv[w] == b && ri[w] < p)) {
+          b = rv[w];
+          p = ri[w];
+        }
+      s_piv = p;
+      s_bad = !(b > 0.0) || !isfinite(b);
+      perm[k] = p;
+    }
+    __syncthreads();
+    if (s_bad) {
+      // a singular level: NaN everywhere, so the first use reports it
+      for (int64_t idx = tid; idx < int64_t(n) * n; idx += DI) Mg[idx] = MT[idx] = __builtin_nan("");
+      if (tid == 0) *err = 1;
+      return;
+    }
+    const int p = s_piv;
+    if (p != k)
+      for (int j = tid; j < n; j += DI) {
+        const double t = M[int64_t(k) * n + j];
+        M[int64_t(k) * n + j] = M[int64_t(p) * n + j];
+        M[int64_t(p) * n + j] = t;
+      }
+    __syncthreads();
+    const double d = 1.0 / M[int64_t(k) * n + k];
+    __syncthreads();
+    for (int j = tid; j < n; j += DI) M[int64_t(k) * n + j] = (j == k ? 1.0 : M[int64_t(k) * n + j]) * d;
+    for (int i = tid; i < n; i += DI) colk[i] = i == k ? 0.0 : M[int64_t(i) * n + k];
+    __syncthreads();
+    for (int64_t idx = tid; idx < int64_t(n) * n; idx += DI) {
+      const int i = int(idx / n), j = int(idx % n);
+      const double f = colk[i];
+      if (i == k || f == 0.0) continue;
+      M[idx] = (j == k ? 0.0 : M[idx]) - f * M[int64_t(k) * n + j];
+    }
+    __syncthreads();
+  }
+  // undo the row interchanges as column interchanges, last first
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = perm[k];
+    if (p != k)
+      for (int i = tid; i < n; i += DI) {
+        const double t = M[int64_t(i) * n + k];
+        M[int64_t(i) * n + k] = M[int64_t(i) * n + p];
+        M[int64_t(i) * n + p] = t;
+      }
+    __syncthreads();
+  }
+  for (int64_t idx = tid; idx < int64_t(n) * n; idx += DI) {
+    MT[(idx % n) * n + idx / n] = M[idx];
+    if constexpr (SH) Mg[idx] = M[idx];
+  }
+}
+
 // ---------------------------------------------------------------------------
 #define GMG_NB_SWITCH(nb, dim, CALL)                              \
   do {                                                            \
@@ -248,6 +372,24 @@ void launch_gmg_resid(int nb, int dim, int nfields, bool transpose, const T* blk
     GMG_NB_SWITCH(nb, dim, hipLaunchKernelGGL((k_gmg_resid<T, NB_, D_, true>), g, dim3(GT), 0, s, blk, fs, nbr, E, x, b, r, nf));
   else
     GMG_NB_SWITCH(nb, dim, hipLaunchKernelGGL((k_gmg_resid<T, NB_, D_, false>), g, dim3(GT), 0, s, blk, fs, nbr, E, x, b, r, nf));
+  DGNP_HIP(hipGetLastError());
+}
+
+void launch_gmg_dense_inverse(int nb, int dim, int nfields, const double* blk, int64_t fs, const int* nbr,
+                               int64_t E, double* M, double* MT, int* err, hipStream_t s) {
+  const int n = int(E * nb);
+  if (n == 0 || nfields == 0) return;
+  DGNP_REQUIRE(n <= DI, DGNP_E_ARG, "dense inverse on the device: at most 1024 unknowns");
+  DGNP_HIP(hipMemsetAsync(M, 0, size_t(nfields) * n * n * sizeof(double), s));
+  const int NS = 2 * dim + 1;
+  const int64_t cnt = E * NS * int64_t(nb) * nb;
+  const dim3 g = dim3(unsigned((cnt + GT - 1) / GT), unsigned(nfields));
+  GMG_NB_SWITCH(nb, dim, hipLaunchKernelGGL((k_gmg_densify<NB_, D_>), g, dim3(GT), 0, s, blk, fs, nbr, E, M, n));
+  DGNP_HIP(hipGetLastError());
+  if (n <= DI_LDS)
+    hipLaunchKernelGGL(k_dense_inverse<true>, dim3(unsigned(nfields)), dim3(DI), 0, s, M, MT, n, err);
+  else
+    hipLaunchKernelGGL(k_dense_inverse<false>, dim3(unsigned(nfields)), dim3(DI), 0, s, M, MT, n, err);
   DGNP_HIP(hipGetLastError());
 }
 

@@ -19,6 +19,11 @@ void launch_gmg_restrict(int nb, int dim, int nfields, const T* Pi, const int* n
 template <typename T>
 void launch_gmg_prolong(int nb, int dim, int nfields, const T* Pi, const int* nfine, const T* xc, int64_t nfc, T* x,
                         int64_t nff, hipStream_t s);
+// inverse of every field's dense matrix of the block level (blk, nbr, E):
+// M, MT [nfields][n][n] with n = E nb <= 1024 receive the inverse and its
+// transpose; *err is set to 1 when a pivot vanishes (not cleared here)
+void launch_gmg_dense_inverse(int nb, int dim, int nfields, const double* blk, int64_t fs, const int* nbr,
+                               int64_t E, double* M, double* MT, int* err, hipStream_t s);
 // r = b - A x, or b - A^T x with transpose
 template <typename T>
 void launch_gmg_resid(int nb, int dim, int nfields, bool transpose, const T* blk, int64_t fs, const int* nbr,

@@ -176,8 +176,12 @@ struct Precond {
     DevBuf<float> A32, F32;
     DevBuf<double> x, b, r, z, aux;  // [m-1][E nb] work vectors
     DevBuf<float> x32, b32, r32, z32, aux32;
+    // dataflow sweeps of the level (as the fine level's): packed words and grids
+    DevBuf<uint64_t> wp, wp64;
+    int df_grid[2] = {0, 0};  // double, float
   };
   bool gmg = false;
+  bool gmg_df = true;  // coarse-level sweeps as dataflow launches
   int gmg_nu = 2;
   std::vector<GLevel> gl;
   DevBuf<double> gmg_pi;  // [2^d][nb][nb] child prolongations
@@ -185,6 +189,7 @@ struct Precond {
   int gmg_nc = 0;         // unknowns per field of the coarsest level
   DevBuf<double> gmg_cinv, gmg_cinvT;  // [m-1][nc][nc] coarsest inverse and its transpose
   DevBuf<float> gmg_cinv32, gmg_cinvT32;
+  DevBuf<int> gmg_err;    // set when the coarsest level is singular (its inverse is then NaN)
   // numeric state: potential part (phi block, its inverse blocks, multigrid
   // hierarchy, lambda_max) and concentration part (BILU(0) factors), in double
   // and, for the mixed path, single precision
@@ -314,13 +319,13 @@ static void gmg_symbolic(dgnp_ctx& c, Precond& P) {
     for (int a = 0; a < 3; ++a) g.n[a] = c.n[a];
     g.E = c.E;
   }
-  // coarsen by 2 along every axis while every count is even and the level has
-  // more than 2^d elements
+  // coarsen by 2 along every axis while every count is even (down to a
+  // single element where the counts allow)
   for (;;) {
     const Precond::GLevel& f = P.gl.back();
     bool even = true;
     for (int a = 0; a < c.dim; ++a) even = even && f.n[a] % 2 == 0;
-    if (!even || f.E <= (int64_t(1) << c.dim)) break;
+    if (!even || f.E <= 1) break;
     Precond::GLevel g;
     for (int a = 0; a < 3; ++a) g.n[a] = a < c.dim ? f.n[a] / 2 : 1;
     g.E = int64_t(g.n[0]) * g.n[1] * g.n[2];
@@ -331,48 +336,31 @@ static void gmg_symbolic(dgnp_ctx& c, Precond& P) {
                "the coarsest multigrid level has " + std::to_string(nc) +
                    " unknowns per field (at most 1024): the element counts need more factors of 2");
   P.gmg_nc = int(nc);
+  P.gmg_df = getenv("DGNP_NO_DATAFLOW") == nullptr;
+  const int nf = c.m - 1;
   for (size_t l = 1; l < P.gl.size(); ++l) {
     Precond::GLevel& g = P.gl[l];
     g.nbr.upload(grid_neighbours(c.dim, g.n), c.stream);
     std::vector<int> flat;
     hyperplane_order(c.dim, g.n, g.lev_ptr, flat);
     g.lev_elems.upload(flat, c.stream);
+    if (P.gmg_df && l + 1 < P.gl.size()) {
+      // packed (value, count) words of the forward and backward sweeps, all
+      // fields: one word per float entry, two per double entry
+      const size_t ne = size_t(nf) * size_t(g.E) * c.nb;
+      g.wp.alloc(2 * ne);
+      g.wp64.alloc(4 * ne);
+      DGNP_HIP(hipMemset(g.wp.p, 0, g.wp.n * sizeof(uint64_t)));
+      DGNP_HIP(hipMemset(g.wp64.p, 0, g.wp64.n * sizeof(uint64_t)));
+      g.df_grid[0] = ilu_dataflow_grid<double>(c.nb, c.dim, g.E, nf);
+      g.df_grid[1] = ilu_dataflow_grid<float>(c.nb, c.dim, g.E, nf);
+    }
   }
   const std::vector<double> Pi = child_prolongations(c.p, c.dim);
   P.gmg_pi.upload(Pi, c.stream);
   std::vector<float> Pi32(Pi.begin(), Pi.end());
   P.gmg_pi32.upload(Pi32, c.stream);
   DGNP_HIP(hipStreamSynchronize(c.stream));
-}
-
-// In-place inverse of the dense n x n matrix a (row-major) by Gauss-Jordan
-// elimination with partial pivoting; DGNP_E_BREAKDOWN when a pivot vanishes.
-static void dense_inverse(std::vector<double>& a, int n) {
-  std::vector<int> piv(static_cast<size_t>(n), 0);
-  for (int k = 0; k < n; ++k) {
-    int r = k;
-    for (int i = k + 1; i < n; ++i)
-      if (std::fabs(a[size_t(i) * n + k]) > std::fabs(a[size_t(r) * n + k])) r = i;
-    DGNP_REQUIRE(a[size_t(r) * n + k] != 0.0 && std::isfinite(a[size_t(r) * n + k]), DGNP_E_BREAKDOWN,
-                 "singular coarsest multigrid level");
-    piv[size_t(k)] = r;
-    if (r != k)
-      for (int j = 0; j < n; ++j) std::swap(a[size_t(k) * n + j], a[size_t(r) * n + j]);
-    const double d = 1.0 / a[size_t(k) * n + k];
-    a[size_t(k) * n + k] = 1.0;
-    for (int j = 0; j < n; ++j) a[size_t(k) * n + j] *= d;
-    for (int i = 0; i < n; ++i) {
-      if (i == k) continue;
-      const double f = a[size_t(i) * n + k];
-      if (f == 0.0) continue;
-      a[size_t(i) * n + k] = 0.0;
-      for (int j = 0; j < n; ++j) a[size_t(i) * n + j] -= f * a[size_t(k) * n + j];
-    }
-  }
-  // undo the row interchanges as column interchanges, last first
-  for (int k = n - 1; k >= 0; --k)
-    if (piv[size_t(k)] != k)
-      for (int i = 0; i < n; ++i) std::swap(a[size_t(i) * n + k], a[size_t(i) * n + piv[size_t(k)]]);
 }
 
 void precond_symbolic(dgnp_ctx& c) {
@@ -447,9 +435,12 @@ void precond_symbolic(dgnp_ctx& c) {
     // 64-row blocks (p = 3) go by lines at any level width: with every line
     // resident the sweep streams the factors (64x16x8 channel 531 -> 296 us,
     // 128x32x16 channel 2.0 -> 1.84 ms per forward sweep, against the element
-    // order and the level launches); smaller blocks keep the element order
-    // (narrow levels) or the level launches.
-    P.lines_on = c.nb >= 64 && getenv("DGNP_DATAFLOW") == nullptr && getenv("DGNP_NO_DATAFLOW") == nullptr;
+    // order and the level launches).  Smaller blocks go by lines where the
+    // levels are wide (256x64x32 channel at p = 1: 350 level launches per
+    // sweep; Krylov part of the solve 1.15 -> 0.85 s) and keep the element
+    // order where they are narrow (16^3 cube, p = 2: 68 against 81 us).
+    P.lines_on = (c.nb >= 64 || width >= 256.0) && getenv("DGNP_DATAFLOW") == nullptr &&
+                 getenv("DGNP_NO_DATAFLOW") == nullptr;
     const char* sw = getenv("DGNP_ILU_SWEEP");  // "line", "element" or "level"
     if (sw && std::string(sw) == "line") {
       P.lines_on = true;
@@ -477,6 +468,10 @@ void precond_check(dgnp_ctx& c, bool report) {
   if (h == 0) return;
   DGNP_HIP(hipMemset(P.df_wp.p, 0, P.df_wp.n * sizeof(uint64_t)));
   DGNP_HIP(hipMemset(P.df_wp64.p, 0, P.df_wp64.n * sizeof(uint64_t)));
+  for (auto& g : P.gl) {
+    if (g.wp.p) DGNP_HIP(hipMemset(g.wp.p, 0, g.wp.n * sizeof(uint64_t)));
+    if (g.wp64.p) DGNP_HIP(hipMemset(g.wp64.p, 0, g.wp64.n * sizeof(uint64_t)));
+  }
   DGNP_HIP(hipMemset(P.df_err.p, 0, sizeof(int)));
   DGNP_HIP(hipDeviceSynchronize());
   if (report) throw Error(DGNP_E_BREAKDOWN, "ILU dataflow sweep exceeded its wait limit");
@@ -680,17 +675,22 @@ struct PhaseClock {
 // Concentration multigrid, numeric part (see gmg_symbolic): the fine level's
 // unfactored blocks are kept, every coarser level gets its Galerkin operator
 // and (all but the coarsest) its BILU(0) factors, the coarsest its dense
-// inverse, computed on the host in double.  Single-precision copies with f32.
+// inverse (Gauss-Jordan on the device, in double); nothing waits for the
+// host, so the set-up stays queued behind the assembly.  Single-precision
+// copies with f32.
 static void gmg_numeric(dgnp_ctx& c, Precond& P, bool f32, hipStream_t s) {
   const int nf = c.m - 1, ns = P.nslot, nb = c.nb;
   auto per = [&](const Precond::GLevel& g) { return g.E * ns * P.bsz; };
   Precond::GLevel& g0 = P.gl[0];
   g0.A.alloc(size_t(nf * per(g0)));
-  DGNP_HIP(hipMemcpyAsync(g0.A.p, P.blk.p + per(g0), size_t(nf * per(g0)) * sizeof(double),
-                          hipMemcpyDeviceToDevice, s));
-  if (f32) {
-    g0.A32.alloc(g0.A.n);
-    cvt_d2f(g0.A.p, g0.A32.p, int64_t(g0.A.n), s);
+  {
+    ScopeTimer tm(c, "gmg_copy", s);
+    DGNP_HIP(hipMemcpyAsync(g0.A.p, P.blk.p + per(g0), size_t(nf * per(g0)) * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));
+    if (f32) {
+      g0.A32.alloc(g0.A.n);
+      cvt_d2f(g0.A.p, g0.A32.p, int64_t(g0.A.n), s);
+    }
   }
   for (size_t l = 1; l < P.gl.size(); ++l) {
     Precond::GLevel& f = P.gl[l - 1];
@@ -740,37 +740,22 @@ static void gmg_numeric(dgnp_ctx& c, Precond& P, bool f32, hipStream_t s) {
       }
     }
   }
-  // coarsest level: dense inverse per field
+  // coarsest level: dense inverse per field, on the device
   Precond::GLevel& gc = P.gl.back();
-  const int n = P.gmg_nc;
-  std::vector<double> h(gc.A.n);
-  DGNP_HIP(hipMemcpyAsync(h.data(), gc.A.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-  DGNP_HIP(hipStreamSynchronize(s));
-  const std::vector<int> nbr = grid_neighbours(c.dim, gc.n);
-  std::vector<double> inv(size_t(nf) * n * n), invT(inv.size());
-  for (int f = 0; f < nf; ++f) {
-    std::vector<double> M(size_t(n) * n, 0.0);
-    for (int64_t i = 0; i < gc.E; ++i)
-      for (int t = 0; t < ns; ++t) {
-        const int64_t j = t == 0 ? i : nbr[size_t(i * 2 * c.dim + t - 1)];
-        if (j < 0) continue;
-        const double* blk = h.data() + size_t(f * per(gc) + (i * ns + t) * P.bsz);
-        for (int r = 0; r < nb; ++r)
-          for (int q = 0; q < nb; ++q) M[size_t(i * nb + r) * n + size_t(j * nb + q)] = blk[r * nb + q];
-      }
-    dense_inverse(M, n);
-    for (int r = 0; r < n; ++r)
-      for (int q = 0; q < n; ++q) {
-        inv[size_t(f) * n * n + size_t(r) * n + q] = M[size_t(r) * n + q];
-        invT[size_t(f) * n * n + size_t(q) * n + r] = M[size_t(r) * n + q];
-      }
+  const int64_t n = P.gmg_nc;
+  P.gmg_cinv.alloc(size_t(nf * n * n));
+  P.gmg_cinvT.alloc(size_t(nf * n * n));
+  P.gmg_err.alloc(1);
+  {
+    ScopeTimer tm(c, "gmg_coarse_inverse", s);
+    launch_gmg_dense_inverse(nb, c.dim, nf, gc.A.p, per(gc), P.gl.size() == 1 ? c.d_nbr.p : gc.nbr.p, gc.E,
+                             P.gmg_cinv.p, P.gmg_cinvT.p, P.gmg_err.p, s);
   }
-  P.gmg_cinv.upload(inv, s);
-  P.gmg_cinvT.upload(invT, s);
   if (f32) {
-    std::vector<float> i32(inv.begin(), inv.end()), t32(invT.begin(), invT.end());
-    P.gmg_cinv32.upload(i32, s);
-    P.gmg_cinvT32.upload(t32, s);
+    P.gmg_cinv32.alloc(P.gmg_cinv.n);
+    P.gmg_cinvT32.alloc(P.gmg_cinvT.n);
+    cvt_d2f(P.gmg_cinv.p, P.gmg_cinv32.p, int64_t(P.gmg_cinv.n), s);
+    cvt_d2f(P.gmg_cinvT.p, P.gmg_cinvT32.p, int64_t(P.gmg_cinvT.n), s);
   }
 }
 
@@ -1263,6 +1248,17 @@ static void gmg_ilu(dgnp_ctx& c, Precond& P, int l, bool tr, const T* in, T* out
   const int nf = c.m - 1;
   const int64_t fs = g.E * P.nslot * P.bsz, vs = g.E * c.nb;
   const T* blk = GSel<T>::F(g);
+  if (!tr && g.wp.p) {
+    // one dataflow launch per sweep, as on the fine level
+    const bool f32 = std::is_same<T, float>::value;
+    uint64_t* wp = f32 ? g.wp.p : g.wp64.p;
+    const int64_t half = int64_t(nf) * vs * (f32 ? 1 : 2);
+    launch_ilu_dataflow<T>(0, c.nb, c.dim, blk, g.nbr.p, g.lev_elems.p, g.E, nf, fs, vs, in, out, wp, P.df_err.p,
+                           P.df_spin, g.df_grid[f32], s);
+    launch_ilu_dataflow<T>(1, c.nb, c.dim, blk, g.nbr.p, g.lev_elems.p, g.E, nf, fs, vs, out, out, wp + half,
+                           P.df_err.p, P.df_spin, g.df_grid[f32], s);
+    return;
+  }
   const int L = int(g.lev_ptr.size()) - 1;
   T* aux = tr ? GSel<T>::aux(g) : nullptr;
   const int k0 = tr ? 2 : 0;

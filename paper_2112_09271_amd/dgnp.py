@@ -428,7 +428,8 @@ class Problem:
                    "block_inverse", "ilu_factor", "ilu_fwd", "ilu_bwd", "ilu_fwdT", "ilu_bwdT", "ilu_fwd_f32",
                    "ilu_bwd_f32", "ilu_fwdT_f32", "ilu_bwdT_f32", "vcycle", "vcycle_f32", "bspmv",
                    "bspmv_f32", "cgs2", "cheb_blk", "cheb_blk_f32", "cheb_mf", "cheb_mf_f32", "cheb_blk1",
-                   "cheb_blk1_f32", "phi_apply", "phi_apply_f32")
+                   "cheb_blk1_f32", "phi_apply", "phi_apply_f32", "gmg", "gmg_f32", "gmg_galerkin", "gmg_factor",
+                   "gmg_coarse_inverse", "gmg_copy")
 
     def profile(self, enable=True, reset=True):
         """Turn per-kernel event timing on or off (reset clears the counters)."""

@@ -83,10 +83,11 @@ def test_block_ilu0_agrees_with_A_on_the_pattern(dim, n, nb):
 
 
 def test_level_sequence():
-    assert mg.coarsen_dims((16, 16, 16)) == [(16, 16, 16), (8, 8, 8), (4, 4, 4), (2, 2, 2)]
+    assert mg.coarsen_dims((16, 16, 16)) == [(16, 16, 16), (8, 8, 8), (4, 4, 4), (2, 2, 2), (1, 1, 1)]
     assert mg.coarsen_dims((64, 16, 8)) == [(64, 16, 8), (32, 8, 4), (16, 4, 2), (8, 2, 1)]
     assert mg.coarsen_dims((6, 4)) == [(6, 4), (3, 2)]
-    assert mg.coarsen_dims((4, 4)) == [(4, 4), (2, 2)]
+    assert mg.coarsen_dims((4, 4)) == [(4, 4), (2, 2), (1, 1)]
+    assert mg.coarsen_dims((4, 4), max_elems=4) == [(4, 4), (2, 2)]
 
 
 @pytest.mark.parametrize("dim,p", [(2, 1), (3, 1), (2, 2)])
