@@ -44,24 +44,36 @@ __device__ __forceinline__ int64_t parent_of(const Dims& f, int64_t e, int* chil
 
 // Galerkin product: coarse block (Ec, slot s) = sum of Pi_c^T A_{e,t} Pi_c' over
 // the fine blocks (child e = child c of Ec, its slot t) whose column element
-// (child c' of Ec, or of Ec's neighbour in slot s) maps to it.  One work-group
-// per (coarse element, field); the products run one at a time through LDS,
-// every thread accumulating fixed entries of the coarse block in registers.
+// (child c' of Ec, or of Ec's neighbour in slot s) maps to it: for s = 0 the
+// 2^d diagonal blocks and the 2^d d couplings between children, for a face
+// slot the 2^(d-1) couplings across that face.  One work-group per (coarse
+// element, field, coarse slot); the products run one after the other through
+// LDS, the next fine block loaded into registers while the current one is
+// multiplied, and each thread accumulates fixed entries of the coarse block
+// in registers.  The child prolongations sit in LDS when they fit (n_b <= 27).
 template <int NB, int DIM>
 __global__ void __launch_bounds__(GT) k_gmg_galerkin(const double* __restrict__ Af, int64_t fsf,
                                                      const int* __restrict__ nbr, Dims fd,
                                                      const double* __restrict__ Pi, double* __restrict__ Ac,
                                                      int64_t fsc) {
   constexpr int NS = 2 * DIM + 1, NC = 1 << DIM, BB = NB * NB, PER = (BB + GT - 1) / GT;
+  constexpr bool PI_LDS = NB <= 27;
+  constexpr int MAXC = NC * (DIM + 1);  // contributions of the diagonal slot
   const int64_t ec = blockIdx.x;
-  const int tid = threadIdx.x;
+  const int s = blockIdx.z, tid = threadIdx.x;
   Af += blockIdx.y * fsf;
   Ac += blockIdx.y * fsc;
   __shared__ double sA[BB], sT[BB];
-  for (int s = 0; s < NS; ++s) {
-    double acc[PER];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) acc[q] = 0.0;
+  __shared__ double sPi[PI_LDS ? NC * BB : 1];
+  if constexpr (PI_LDS)
+    for (int i = tid; i < NC * BB; i += GT) sPi[i] = Pi[i];
+  const double* PiS = PI_LDS ? sPi : Pi;
+  // the contributions (child, fine slot, column child), listed by one thread
+  __shared__ int64_t ce[MAXC];
+  __shared__ int ct[MAXC], cc[MAXC], ccp[MAXC];
+  __shared__ int s_n;
+  if (tid == 0) {
+    int n = 0;
     for (int c = 0; c < NC; ++c) {
       const int64_t e = fine_child(fd, ec, c);
       for (int t = 0; t < NS; ++t) {
@@ -70,44 +82,72 @@ __global__ void __launch_bounds__(GT) k_gmg_galerkin(const double* __restrict__ 
           if (s != 0) continue;
         } else {
           const int a = (t - 1) >> 1, up = (t - 1) & 1;
-          if (nbr[e * 2 * DIM + t - 1] < 0) continue;
           // a lower child going up, or an upper child going down, stays inside
           // the coarse element; otherwise the neighbour is in coarse slot t
           const bool inside = ((c >> a) & 1) != up;
           if (inside ? s != 0 : s != t) continue;
+          if (nbr[e * 2 * DIM + t - 1] < 0) continue;
           cp = c ^ (1 << a);
         }
-        __syncthreads();
-        for (int i = tid; i < BB; i += GT) sA[i] = Af[(e * NS + t) * BB + i];
-        __syncthreads();
-        const double* Pc = Pi + cp * BB;  // A_{e,t} Pi_c'
-        for (int i = tid; i < BB; i += GT) {
-          const int r = i / NB, col = i % NB;
-          double v = 0.0;
-#pragma unroll 8
-          for (int k = 0; k < NB; ++k) v += sA[r * NB + k] * Pc[k * NB + col];
-          sT[i] = v;
-        }
-        __syncthreads();
-        const double* Pr = Pi + c * BB;  // Pi_c^T (A Pi_c')
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-          const int i = tid + q * GT;
-          if (i < BB) {
-            const int r = i / NB, col = i % NB;
-            double v = 0.0;
-#pragma unroll 8
-            for (int k = 0; k < NB; ++k) v += Pr[k * NB + r] * sT[k * NB + col];
-            acc[q] += v;
-          }
-        }
+        ce[n] = e;
+        ct[n] = t;
+        cc[n] = c;
+        ccp[n] = cp;
+        ++n;
       }
     }
+    s_n = n;
+  }
+  __syncthreads();
+  const int n = s_n;
+  double acc[PER], pre[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    acc[q] = 0.0;
+    const int i = tid + q * GT;
+    pre[q] = (n > 0 && i < BB) ? Af[(ce[0] * NS + ct[0]) * BB + i] : 0.0;
+  }
+  for (int k = 0; k < n; ++k) {
+    __syncthreads();  // the previous product has finished reading sA / sT
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int i = tid + q * GT;
-      if (i < BB) Ac[(ec * NS + s) * BB + i] = acc[q];
+      if (i < BB) sA[i] = pre[q];
     }
+    __syncthreads();
+    if (k + 1 < n) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int i = tid + q * GT;
+        if (i < BB) pre[q] = Af[(ce[k + 1] * NS + ct[k + 1]) * BB + i];
+      }
+    }
+    const double* Pc = PiS + ccp[k] * BB;  // A_{e,t} Pi_c'
+    for (int i = tid; i < BB; i += GT) {
+      const int r = i / NB, col = i % NB;
+      double v = 0.0;
+#pragma unroll 9
+      for (int j = 0; j < NB; ++j) v += sA[r * NB + j] * Pc[j * NB + col];
+      sT[i] = v;
+    }
+    __syncthreads();
+    const double* Pr = PiS + cc[k] * BB;  // Pi_c^T (A Pi_c')
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int i = tid + q * GT;
+      if (i < BB) {
+        const int r = i / NB, col = i % NB;
+        double v = 0.0;
+#pragma unroll 9
+        for (int j = 0; j < NB; ++j) v += Pr[j * NB + r] * sT[j * NB + col];
+        acc[q] += v;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = tid + q * GT;
+    if (i < BB) Ac[(ec * NS + s) * BB + i] = acc[q];
   }
 }
 
@@ -152,12 +192,14 @@ __global__ void __launch_bounds__(GT) k_gmg_prolong(const T* __restrict__ Pi, Di
 }
 
 // r = b - A x (TR = false) or b - A^T x (TR = true) on a level's unfactored
-// blocks [field][E][slot][NB][NB]: one thread per (entry, field)
+// blocks [field][E][slot][NB][ld] (rows of ld >= NB entries): one thread per
+// (entry, field)
 template <typename T, int NB, int DIM, bool TR>
-__global__ void __launch_bounds__(GT) k_gmg_resid(const T* __restrict__ blk, int64_t fs,
+__global__ void __launch_bounds__(GT) k_gmg_resid(const T* __restrict__ blk, int64_t fs, int ld,
                                                   const int* __restrict__ nbr, int64_t E, const T* __restrict__ x,
                                                   const T* __restrict__ b, T* __restrict__ r, int64_t nf) {
-  constexpr int NS = 2 * DIM + 1, BB = NB * NB;
+  constexpr int NS = 2 * DIM + 1;
+  const int BB = NB * ld;
   const int64_t g = blockIdx.x * int64_t(GT) + threadIdx.x;
   if (g >= nf) return;
   const int row = int(g % NB);
@@ -172,7 +214,7 @@ __global__ void __launch_bounds__(GT) k_gmg_resid(const T* __restrict__ blk, int
     if (j < 0) continue;
     const T* xj = x + j * NB;
     if constexpr (!TR) {
-      const T* a = blk + (e * NS + t) * BB + row * NB;
+      const T* a = blk + (e * NS + t) * BB + row * ld;
 #pragma unroll 8
       for (int col = 0; col < NB; ++col) acc += a[col] * xj[col];
     } else {
@@ -180,7 +222,7 @@ __global__ void __launch_bounds__(GT) k_gmg_resid(const T* __restrict__ blk, int
       const int tj = t == 0 ? 0 : (((t - 1) ^ 1) + 1);
       const T* a = blk + (j * NS + tj) * BB + row;
 #pragma unroll 8
-      for (int col = 0; col < NB; ++col) acc += a[col * NB] * xj[col];
+      for (int col = 0; col < NB; ++col) acc += a[col * ld] * xj[col];
     }
   }
   r[g] = b[g] - acc;
@@ -336,7 +378,7 @@ void launch_gmg_galerkin(int nb, int dim, int nfields, const double* Af, int64_t
                          const int* nfine, const double* Pi, double* Ac, int64_t fsc, int64_t Ec, hipStream_t s) {
   if (Ec == 0 || nfields == 0) return;
   const Dims fd = dims_of(dim, nfine);
-  const dim3 g = dim3(unsigned(Ec), unsigned(nfields));
+  const dim3 g = dim3(unsigned(Ec), unsigned(nfields), unsigned(2 * dim + 1));
   GMG_NB_SWITCH(nb, dim,
                 hipLaunchKernelGGL((k_gmg_galerkin<NB_, D_>), g, dim3(GT), 0, s, Af, fsf, nbr, fd, Pi, Ac, fsc));
   DGNP_HIP(hipGetLastError());
@@ -363,15 +405,15 @@ void launch_gmg_prolong(int nb, int dim, int nfields, const T* Pi, const int* nf
 }
 
 template <typename T>
-void launch_gmg_resid(int nb, int dim, int nfields, bool transpose, const T* blk, int64_t fs, const int* nbr,
+void launch_gmg_resid(int nb, int dim, int nfields, bool transpose, const T* blk, int64_t fs, int ld, const int* nbr,
                       int64_t E, const T* x, const T* b, T* r, hipStream_t s) {
   const int64_t nf = E * nb;
   if (nf == 0 || nfields == 0) return;
   const dim3 g = dim3(unsigned((nf + GT - 1) / GT), unsigned(nfields));
   if (transpose)
-    GMG_NB_SWITCH(nb, dim, hipLaunchKernelGGL((k_gmg_resid<T, NB_, D_, true>), g, dim3(GT), 0, s, blk, fs, nbr, E, x, b, r, nf));
+    GMG_NB_SWITCH(nb, dim, hipLaunchKernelGGL((k_gmg_resid<T, NB_, D_, true>), g, dim3(GT), 0, s, blk, fs, ld, nbr, E, x, b, r, nf));
   else
-    GMG_NB_SWITCH(nb, dim, hipLaunchKernelGGL((k_gmg_resid<T, NB_, D_, false>), g, dim3(GT), 0, s, blk, fs, nbr, E, x, b, r, nf));
+    GMG_NB_SWITCH(nb, dim, hipLaunchKernelGGL((k_gmg_resid<T, NB_, D_, false>), g, dim3(GT), 0, s, blk, fs, ld, nbr, E, x, b, r, nf));
   DGNP_HIP(hipGetLastError());
 }
 
@@ -401,9 +443,9 @@ template void launch_gmg_prolong<double>(int, int, int, const double*, const int
                                          int64_t, hipStream_t);
 template void launch_gmg_prolong<float>(int, int, int, const float*, const int*, const float*, int64_t, float*,
                                         int64_t, hipStream_t);
-template void launch_gmg_resid<double>(int, int, int, bool, const double*, int64_t, const int*, int64_t,
+template void launch_gmg_resid<double>(int, int, int, bool, const double*, int64_t, int, const int*, int64_t,
                                        const double*, const double*, double*, hipStream_t);
-template void launch_gmg_resid<float>(int, int, int, bool, const float*, int64_t, const int*, int64_t, const float*,
-                                      const float*, float*, hipStream_t);
+template void launch_gmg_resid<float>(int, int, int, bool, const float*, int64_t, int, const int*, int64_t,
+                                      const float*, const float*, float*, hipStream_t);
 
 }  // namespace dgnp

@@ -24,8 +24,8 @@ void launch_gmg_prolong(int nb, int dim, int nfields, const T* Pi, const int* nf
 // transpose; *err is set to 1 when a pivot vanishes (not cleared here)
 void launch_gmg_dense_inverse(int nb, int dim, int nfields, const double* blk, int64_t fs, const int* nbr,
                                int64_t E, double* M, double* MT, int* err, hipStream_t s);
-// r = b - A x, or b - A^T x with transpose
+// r = b - A x, or b - A^T x with transpose; block rows of ld >= nb entries
 template <typename T>
-void launch_gmg_resid(int nb, int dim, int nfields, bool transpose, const T* blk, int64_t fs, const int* nbr,
+void launch_gmg_resid(int nb, int dim, int nfields, bool transpose, const T* blk, int64_t fs, int ld, const int* nbr,
                       int64_t E, const T* x, const T* b, T* r, hipStream_t s);
 }  // namespace dgnp

@@ -173,7 +173,7 @@ struct Precond {
     std::vector<int64_t> lev_ptr;
     DevBuf<int> lev_elems;
     DevBuf<double> A, F;  // [m-1][E][nslot][bsz]: operator, BILU(0) factors
-    DevBuf<float> A32, F32;
+    DevBuf<float> A32, F32;  // A32 with rows of pot_ld(nb, true) floats (the block SpMV's layout)
     DevBuf<double> x, b, r, z, aux;  // [m-1][E nb] work vectors
     DevBuf<float> x32, b32, r32, z32, aux32;
     // dataflow sweeps of the level (as the fine level's): packed words and grids
@@ -688,8 +688,8 @@ static void gmg_numeric(dgnp_ctx& c, Precond& P, bool f32, hipStream_t s) {
     DGNP_HIP(hipMemcpyAsync(g0.A.p, P.blk.p + per(g0), size_t(nf * per(g0)) * sizeof(double),
                             hipMemcpyDeviceToDevice, s));
     if (f32) {
-      g0.A32.alloc(g0.A.n);
-      cvt_d2f(g0.A.p, g0.A32.p, int64_t(g0.A.n), s);
+      g0.A32.alloc(g0.A.n / nb * pot_ld(nb, true));
+      cvt_d2f_rows(g0.A.p, g0.A32.p, int64_t(g0.A.n / nb), nb, pot_ld(nb, true), s);
     }
   }
   for (size_t l = 1; l < P.gl.size(); ++l) {
@@ -715,8 +715,8 @@ static void gmg_numeric(dgnp_ctx& c, Precond& P, bool f32, hipStream_t s) {
                           g.lev_ptr[lv + 1] - g.lev_ptr[lv], s, b32);
     }
     if (f32) {
-      g.A32.alloc(g.A.n);
-      cvt_d2f(g.A.p, g.A32.p, int64_t(g.A.n), s);
+      g.A32.alloc(g.A.n / nb * pot_ld(nb, true));
+      cvt_d2f_rows(g.A.p, g.A32.p, int64_t(g.A.n / nb), nb, pot_ld(nb, true), s);
     }
   }
   // work vectors of every level
@@ -1289,11 +1289,21 @@ static void gmg_vcycle(dgnp_ctx& c, Precond& P, bool tr, int l, const T* b, T* x
   }
   const T* A = GSel<T>::A(g);
   const int* nbr = l == 0 ? c.d_nbr.p : g.nbr.p;
-  const int64_t fs = g.E * P.nslot * P.bsz;
+  const int ld = pot_ld(c.nb, std::is_same<T, float>::value);
+  const int64_t fs = g.E * P.nslot * c.nb * ld;
   T* r = GSel<T>::r(g);
   T* z = GSel<T>::z(g);
+  // r = b - A x (forward: the block SpMV of the potential block, per field)
+  auto resid = [&]() {
+    if (tr) {
+      launch_gmg_resid<T>(c.nb, c.dim, nf, true, A, fs, ld, nbr, g.E, x, b, r, s);
+    } else {
+      for (int f = 0; f < nf; ++f)
+        launch_bspmv<T>(c.nb, c.dim, g.E, A + f * fs, nbr, x + f * nfl, b + f * nfl, T(-1), T(1), r + f * nfl, s);
+    }
+  };
   auto richardson = [&]() {
-    launch_gmg_resid<T>(c.nb, c.dim, nf, tr, A, fs, nbr, g.E, x, b, r, s);
+    resid();
     gmg_ilu<T>(c, P, l, tr, r, z, s);
     vaxpy<T>(T(1), z, x, nf * nfl, s);
   };
@@ -1301,7 +1311,7 @@ static void gmg_vcycle(dgnp_ctx& c, Precond& P, bool tr, int l, const T* b, T* x
   for (int k = 1; k < P.gmg_nu; ++k) richardson();
   Precond::GLevel& gc = P.gl[size_t(l + 1)];
   const int64_t nfc = gc.E * c.nb;
-  launch_gmg_resid<T>(c.nb, c.dim, nf, tr, A, fs, nbr, g.E, x, b, r, s);
+  resid();
   launch_gmg_restrict<T>(c.nb, c.dim, nf, GSel<T>::pi(P), g.n, r, nfl, GSel<T>::b(gc), nfc, s);
   gmg_vcycle<T>(c, P, tr, l + 1, GSel<T>::b(gc), GSel<T>::x(gc), s);
   launch_gmg_prolong<T>(c.nb, c.dim, nf, GSel<T>::pi(P), g.n, GSel<T>::x(gc), nfc, x, nfl, s);

@@ -54,16 +54,20 @@ def test_vcycle_matches_oracle(dim, n, p):
 
 @pytest.mark.parametrize("dim,n,p", [(2, (8, 8), 1), (3, (4, 4, 4), 1), (3, (4, 4, 2), 2)])
 def test_transpose_is_adjoint(dim, n, p):
-    from paper_2112_09271_amd.dgnp import DGNP_F64, DGNP_PC_P1, DGNP_PC_P2
+    """In both precisions (the single-precision cycle reads its operators with
+    padded rows, forward through the block SpMV, transposed through its own
+    residual kernel)."""
+    from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64, DGNP_PC_P1, DGNP_PC_P2
     cfg = gmg_box(dim, n, p, Pe=200.0)
     gp = _gpu(cfg, nu=1)
-    gp.set_state(random_state(cfg), prec=DGNP_F64)
+    gp.set_state(random_state(cfg), prec=DGNP_F32)
     r, w = random_vector(cfg, 41), random_vector(cfg, 42)
-    for kind in (DGNP_PC_P2, DGNP_PC_P1):
-        a = host(gp.precond_apply(r, pc_kind=kind)) @ w
-        b = r @ host(gp.precond_apply(w, transpose=True, pc_kind=kind))
-        print(kind, a, b)
-        assert abs(a - b) <= 1e-11 * abs(a)
+    for prec, tol in ((DGNP_F64, 1e-11), (DGNP_F32, 2e-5)):
+        for kind in (DGNP_PC_P2, DGNP_PC_P1):
+            a = host(gp.precond_apply(r, prec=prec, pc_kind=kind)) @ w
+            b = r @ host(gp.precond_apply(w, prec=prec, transpose=True, pc_kind=kind))
+            print(prec, kind, a, b)
+            assert abs(a - b) <= tol * abs(a)
     gp.close()
 
 
@@ -108,3 +112,24 @@ def test_coarsest_level_limit_is_refused():
     with pytest.raises(DgnpError) as ei:
         _gpu(cfg)
     assert ei.value.code == DGNP_E_ARG and "coarsest" in str(ei.value)
+
+
+def test_adjoint_with_gmg_matches_oracle():
+    """The adjoint solve (transposed operator, transposed preconditioner: the
+    transposed V-cycle on the concentration blocks) gives the oracle's
+    gradients, in both precisions of the preconditioner."""
+    from paper_2112_09271_amd.dgnp import DGNP_F32, DGNP_F64
+    cfg = get_config("cfg2t")
+    od = DG(OProblem(cfg, boundary_data(cfg)))
+    x_ref, _ = osolve.newton(od, tol=1e-14)
+    J_ref, dg_ref, dpe_ref, _ = osolve.adjoint(od, x_ref)
+    gp = _gpu(cfg, nu=1)
+    x, st = gp.solve(rtol=1e-13)
+    assert st.status == 0
+    for prec in (DGNP_F64, DGNP_F32):
+        J, dbc, dpe, lam, ast = gp.adjoint(x, rtol=1e-12, prec=prec)
+        print(prec, J, J_ref, dpe, dpe_ref, ast.lin_its_total)
+        assert abs(J - J_ref) <= 1e-9 * abs(J_ref)
+        assert np.linalg.norm(np.ravel(dbc) - np.ravel(dg_ref)) <= 1e-7 * np.linalg.norm(dg_ref)
+        assert abs(dpe - dpe_ref) <= 1e-7 * abs(dpe_ref)
+    gp.close()
