@@ -90,6 +90,31 @@ def ilu_sweep_bytes(cfg, word, backward=False):
     return float((cfg.m - 1) * per_field)
 
 
+def _levels(cfg):
+    return int(sum(cfg.n[: cfg.dim])) - cfg.dim + 1
+
+
+def ilu_factor_bytes(cfg):
+    """Algorithmic HBM bytes of one launch of the BILU(0) factorisation (one
+    hyperplane level), averaged over the levels: every element reads its
+    diagonal and coupling blocks (FP64) and, for the Schur update, the scaled
+    upper block of each lower neighbour; it writes D^-1 and its scaled
+    coupling blocks in FP64 and FP32 (both concentration fields)."""
+    E, nb, n_low = _couplings(cfg)
+    reads = (E + 2 * n_low + n_low) * nb * nb * 8
+    writes = (E + 2 * n_low) * nb * nb * (8 + 4)
+    return float((cfg.m - 1) * (reads + writes)) / _levels(cfg)
+
+
+def ilu_factor_flops(cfg):
+    """FP64 operations of one launch of the factorisation, averaged over the
+    levels: per element a Schur product per lower neighbour, the inversion of
+    D_i (Gauss-Jordan, 2 n_b^3) and the scaling of every coupling block, each
+    2 n_b^3."""
+    E, nb, n_low = _couplings(cfg)
+    return float((cfg.m - 1) * (n_low + E + 2 * n_low) * 2 * nb ** 3) / _levels(cfg)
+
+
 def cheb_blk_bytes(cfg, word):
     """Algorithmic HBM bytes per launch of the fused Chebyshev step on the
     element-block level, averaged over the four launches of one V-cycle: the
@@ -507,9 +532,12 @@ def main():
         "ilu_bwd_f32": (ilu_sweep_bytes(cfg, 4, backward=True),
                         "k_ilu_dfp<bwd> (dataflow BILU(0) backward sweep, both concentration blocks)"),
         "jac_apply_f32": (float(japply_bytes(prob.N, 4)), "k_jlin<float> (Jacobian apply, tabulated state)"),
+        "ilu_factor": (ilu_factor_bytes(cfg),
+                       "k_ilu_factor (BILU(0) factorisation of the fine concentration blocks, one hyperplane "
+                       "level per launch)"),
     }
     present = {k: v for k, v in kern.items() if k in models}
-    ranking = profile_ranking(cfg.name)
+    ranking = profile_ranking(cfg.name + ("_bilu" if args.conc_pc == "bilu" else ""))
     if ranking and ranking.get("family") in present:
         dom, chosen_by = ranking["family"], "largest total kernel time in the rocprofv3 statistics of this solve"
     else:
@@ -520,7 +548,8 @@ def main():
     per_launch_bytes, kname = models[dom]
     achieved = per_launch_bytes / avg / 1e9
     keys = {"cheb_blk_f32": "k_cheb_blk_f32_cfg2", "ilu_fwd_f32": "k_ilu_dfp_fwd_cfg2",
-            "ilu_bwd_f32": "k_ilu_dfp_bwd_cfg2", "jac_apply_f32": "k_jlin_f32_cfg2"}
+            "ilu_bwd_f32": "k_ilu_dfp_bwd_cfg2", "jac_apply_f32": "k_jlin_f32_cfg2",
+            "ilu_factor": "k_ilu_factor_fine_cfg2"}
     srcs = ("kernels_jac.hip", "dg_device.hpp", "pointwise.hpp") if dom == "jac_apply_f32" else ("kernels_block.hip",)
     copy_gbs = copy_bandwidth()
     roofline = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -533,6 +562,14 @@ def main():
         # the same kernel's average duration in the committed profile, for comparison
         roofline["rocprof_avg_launch_us"] = ranking["avg_us"]
         roofline["frac_rocprof"] = per_launch_bytes / (1e-6 * ranking["avg_us"]) / 1e9 / PEAK_HBM_GBS
+    if dom == "ilu_factor":
+        # its block products run on the FP64 matrix cores: their fraction too
+        # (the memory roof binds first at the speed of light: bytes / 8 TB/s
+        # exceeds flops / 78.6 TFLOP/s)
+        fl = ilu_factor_flops(cfg)
+        roofline["flops_per_launch"] = fl
+        roofline["fp64_mfma_TFLOPs"] = fl / avg / 1e12
+        roofline["fp64_mfma_frac"] = fl / avg / 1e12 / PEAK_FP64_TFLOPS
     log(f"[bench] dominant kernel {dom}: {tot:.3f}s in {launches} launches, {1e6 * avg:.2f} us/launch, "
         f"{achieved:.0f} GB/s")
     others = {}
