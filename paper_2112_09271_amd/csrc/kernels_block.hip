@@ -493,16 +493,22 @@ void launch_assemble(int dim, int p, int m, int f0, int nf, const KArgs& A, cons
 // ===========================================================================
 // Gauss-Jordan inversion (sweep form) with partial pivoting of an NB x NB
 // matrix (NB <= 64) held in LDS with leading dimension LD.  The matrix lives in
-// registers during the elimination: lane r of wave w owns row r at columns
-// w, w + 4, w + 8, ...  Rows are never interchanged; step k pivots column k on
-// the unused row p of largest magnitude (ties: smallest row), so that on exit
+// registers during the elimination: lane r of every wave holds row r, and wave
+// w holds the columns 16 j + 4 w + t (t = 0..3), i.e. panels of four
+// consecutive columns dealt round the four waves.  Rows are never
+// interchanged; step k pivots column k on the unused row p of largest
+// magnitude (ties: smallest row), so that on exit
 //   A^{-1}[i][j] = a[rsrc[i]][csrc[j]],  rsrc[k] = p_k,  csrc[p_k] = k.
-// Per step: the wave that owns column k finds the pivot with a lane reduction
-// and publishes column k and the pivot; after one barrier every lane updates
-// its row with one FMA per entry, taking the pivot row's entry of each of its
-// columns from lane p of its own wave (the same wave holds the same columns of
-// every row).  The published columns are double-buffered, so one barrier per
-// step suffices.
+// Step k with pivot p and inv = 1 / x[p][k]: every row r != p takes
+// x[r][c] -= g_r x[p][c] for c != k with g_r = x[r][k] inv, and x[r][k] = -g_r;
+// row p takes x[p][c] *= inv and x[p][k] = inv.
+// Per panel of four steps the owning wave alone runs the four pivot searches
+// and applies each step to its own panel columns (everything the next search
+// needs), then publishes the pivots, their inverses and the multipliers g_r;
+// after one barrier every wave applies the four steps to its other columns,
+// taking the pivot row's entries from lane p of its own registers.  Each entry
+// sees the same operations in the same order as in a step-by-step sweep; the
+// published data are double-buffered, so one barrier per panel suffices.
 // ===========================================================================
 // v (a double) of lane `lane` (wave-uniform) of the calling wave
 __device__ inline double readlane_d(double v, int lane) {
@@ -512,73 +518,96 @@ __device__ inline double readlane_d(double v, int lane) {
   return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
 
+// maximum of v over the 64 lanes of the wave (all lanes active), wave-uniform:
+// lane exchanges inside each row of 16 lanes (quad permutations, then row
+// rotations by 4 and 8), then the four row maxima through scalar registers
+__device__ inline int wave_max_i32(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xF, 0xF, false));  // row_ror 4
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false));  // row_ror 8
+  const int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+  const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+  return max(max(r0, r1), max(r2, r3));
+}
+
+// exchange buffers of gj_invert: per parity, the multipliers [64 rows][4 steps]
+// and the four inverse pivots (doubles), and the four pivot rows (ints)
+constexpr int GJ_SHD = 2 * (4 * 64 + 4);
+constexpr int GJ_SHI = 2 * 4;
+
 template <int NB, int LD>
 __device__ void gj_invert(double* a, double* sh, int* shi, int* rsrc, int* csrc, int tid) {
   static_assert(NB <= 64 && BT == 256, "one row per lane, four waves");
-  constexpr int NC = (NB + 3) / 4;
-  constexpr int SB = 64 + 1;  // doubles per buffer: column k, pivot value
+  constexpr int NC = 4 * ((NB + 15) / 16);  // registers per lane: column groups of 16, four per wave
   const int r = tid & 63, w = tid >> 6;
   const bool rowok = r < NB;
   double x[NC];
 #pragma unroll
   for (int j = 0; j < NC; ++j) {
-    const int c = w + 4 * j;
+    const int c = 16 * (j >> 2) + 4 * w + (j & 3);
     x[j] = (rowok && c < NB) ? a[r * LD + c] : 0.0;
   }
   bool used = !rowok;
-  for (int k = 0; k < NB; ++k) {
-    const int b = k & 1;
-    double* pcol = sh + b * SB;
-    double* pval = pcol + 64;
-    const int wk = k & 3, jk = k >> 2;
-    if (w == wk) {
-      double xk = 0.0;
 #pragma unroll
-      for (int j = 0; j < NC; ++j) xk = j == jk ? x[j] : xk;
-      // pivot: largest |x| among unused rows, compared on the upper word of its
-      // bit pattern (sign, exponent, 20 mantissa bits: non-negative doubles
-      // order like these integers), ties to the smallest row; the reduction is
-      // one 32-bit lane exchange per step and a ballot picks the row
-      const double ax = fabs(xk);
-      const int key = used ? -1 : int(uint32_t(uint64_t(__double_as_longlong(ax)) >> 32));
-      int mk = key;
-      for (int off = 32; off > 0; off >>= 1) mk = max(mk, __shfl_xor(mk, off, 64));
-      const uint64_t hit = __ballot(key == mk);
-      const int bi = __ffsll(static_cast<unsigned long long>(hit)) - 1;
-      pcol[r] = xk;
-      if (r == bi) {
-        shi[b] = bi;
-        pval[0] = xk;
-        rsrc[k] = bi;
-        csrc[bi] = k;
+  for (int kp = 0; kp < NB; kp += 4) {
+    const int pn = kp >> 2, wk = pn & 3, jk = 4 * (pn >> 2);  // panel, owner wave, owner's first register
+    const int tt = NB - kp < 4 ? NB - kp : 4;
+    double* gb = sh + (pn & 1) * (4 * 64 + 4);
+    int* pb = shi + 4 * (pn & 1);
+    if (w == wk) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t >= tt) break;
+        const double xk = x[jk + t];
+        // pivot: largest |x| among unused rows, compared on the upper word of its
+        // bit pattern (sign, exponent, 20 mantissa bits: non-negative doubles
+        // order like these integers), ties to the smallest row; the reduction is
+        // on 32-bit keys and a ballot picks the row
+        const int key = used ? -1 : int(uint32_t(uint64_t(__double_as_longlong(fabs(xk))) >> 32));
+        const int mk = wave_max_i32(key);
+        const uint64_t hit = __ballot(key == mk);
+        const int p = __ffsll(static_cast<unsigned long long>(hit)) - 1;
+        const double inv = 1.0 / readlane_d(xk, p);
+        const double g = (r == p || !rowok) ? 0.0 : xk * inv;
+#pragma unroll
+        for (int t2 = 0; t2 < 4; ++t2) {
+          if (t2 == t || t2 >= tt) continue;
+          const double pr = readlane_d(x[jk + t2], p);
+          x[jk + t2] = r == p ? x[jk + t2] * inv : fma(-g, pr, x[jk + t2]);
+        }
+        x[jk + t] = r == p ? inv : -g;
+        gb[r * 4 + t] = g;
+        if (r == p) {
+          used = true;
+          pb[t] = p;
+          gb[256 + t] = inv;
+          rsrc[kp + t] = p;
+          csrc[p] = kp + t;
+        }
       }
     }
     __syncthreads();
-    // one barrier per pivot: the buffers alternate, and each wave takes the
-    // pivot row's entries of its own columns from lane p of its own registers
-    const int p = __builtin_amdgcn_readfirstlane(shi[b]);
-    const double inv = 1.0 / pval[0];
-    if (r == p) used = true;
-    const double g = (r == p || !rowok) ? 0.0 : pcol[r] * inv;
 #pragma unroll
-    for (int j = 0; j < NC; ++j) {
-      const int c = w + 4 * j;
-      if (c < NB) x[j] = fma(-g, readlane_d(x[j], p), x[j]);
-    }
-    if (r == p) {
+    for (int t = 0; t < 4; ++t) {
+      if (t >= tt) break;
+      const int p = __builtin_amdgcn_readfirstlane(pb[t]);
+      const double inv = gb[256 + t];
+      const double g = gb[r * 4 + t];
+      if (r == p) used = true;
 #pragma unroll
-      for (int j = 0; j < NC; ++j) x[j] *= inv;
-    }
-    if (w == wk) {
-      const double xkn = r == p ? inv : -g;
-#pragma unroll
-      for (int j = 0; j < NC; ++j) x[j] = j == jk ? xkn : x[j];
+      for (int j = 0; j < NC; ++j) {
+        const int c = 16 * (j >> 2) + 4 * w + (j & 3);
+        if (c >= NB || (w == wk && j >= jk && j < jk + 4)) continue;  // past the end, or the owner's panel
+        const double pr = readlane_d(x[j], p);
+        x[j] = r == p ? x[j] * inv : fma(-g, pr, x[j]);
+      }
     }
   }
   if (rowok) {
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
-      const int c = w + 4 * j;
+      const int c = 16 * (j >> 2) + 4 * w + (j & 3);
       if (c < NB) a[r * LD + c] = x[j];
     }
   }
@@ -591,8 +620,8 @@ __global__ void __launch_bounds__(BT) k_block_inverse(const double* __restrict__
                                                       double* __restrict__ out) {
   constexpr int LD = NB + 1;
   __shared__ double a[NB * LD];
-  __shared__ double sh[2 * (64 + 1)];
-  __shared__ int shi[2], rsrc[NB], csrc[NB];
+  __shared__ double sh[GJ_SHD];
+  __shared__ int shi[GJ_SHI], rsrc[NB], csrc[NB];
   const int64_t e = blockIdx.x;
   const double* src = blk + e * nslot * NB * NB;
   for (int idx = threadIdx.x; idx < NB * NB; idx += BT) a[(idx / NB) * LD + idx % NB] = src[idx];
@@ -929,8 +958,8 @@ __global__ void __launch_bounds__(BT) k_ilu_factor(double* __restrict__ blk, int
   constexpr int LD = NB + 1;
   constexpr int NSLOT = 2 * DIM + 1;
   __shared__ double a[NB * LD];
-  __shared__ double sh[2 * (64 + 1)];
-  __shared__ int shi[2], rsrc[NB], csrc[NB];
+  __shared__ double sh[GJ_SHD];
+  __shared__ int shi[GJ_SHI], rsrc[NB], csrc[NB];
   const int tid = threadIdx.x;
   blk += blockIdx.y * fstride;
   const int64_t i = lev_elems[first + blockIdx.x];

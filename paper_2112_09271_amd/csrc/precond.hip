@@ -93,7 +93,41 @@ struct PinnedStage {
   }
 };
 
+// Two side streams (default priority) of the concentration set-up and a pool
+// of events for the fork / join hand-offs between them and the caller's
+// stream.  An event is recorded once per set-up; a wait takes the record that
+// precedes it, so reusing the pool in the next set-up is safe.
+struct SideStreams {
+  hipStream_t st[2] = {nullptr, nullptr};
+  std::vector<hipEvent_t> ev;
+  size_t next = 0;
+  SideStreams() = default;
+  SideStreams(const SideStreams&) = delete;
+  SideStreams& operator=(const SideStreams&) = delete;
+  ~SideStreams() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (hipStream_t q : st)
+      if (q) (void)hipStreamDestroy(q);
+  }
+  hipStream_t stream(int i) {
+    if (!st[i]) DGNP_HIP(hipStreamCreateWithFlags(&st[i], hipStreamNonBlocking));
+    return st[i];
+  }
+  // work queued on `to` after this call waits for the work queued on `from` before it
+  void order(hipStream_t from, hipStream_t to) {
+    if (next == ev.size()) {
+      hipEvent_t e = nullptr;
+      DGNP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      ev.push_back(e);
+    }
+    hipEvent_t e = ev[next++];
+    DGNP_HIP(hipEventRecord(e, from));
+    DGNP_HIP(hipStreamWaitEvent(to, e, 0));
+  }
+};
+
 struct Precond {
+  SideStreams side;
   int nslot = 0;
   int64_t bsz = 0;                  // doubles per block = nb * nb
   DevBuf<double> blk;               // [m][E][nslot][nb][nb]
@@ -673,25 +707,31 @@ struct PhaseClock {
 };
 
 // Concentration multigrid, numeric part (see gmg_symbolic): the fine level's
-// unfactored blocks are kept, every coarser level gets its Galerkin operator
-// and (all but the coarsest) its BILU(0) factors, the coarsest its dense
-// inverse (Gauss-Jordan on the device, in double); nothing waits for the
-// host, so the set-up stays queued behind the assembly.  Single-precision
-// copies with f32.
+// unfactored blocks are kept (gmg_copy_fine, before the fine blocks are
+// factorised in place), every coarser level gets its Galerkin operator and
+// (all but the coarsest) its BILU(0) factors, the coarsest its dense inverse
+// (Gauss-Jordan on the device, in double); nothing waits for the host, so the
+// set-up stays queued behind the assembly.  The Galerkin chain runs on s, each
+// level's factorisation on side stream 1 as soon as its operator exists; s
+// waits for them at the end.  Single-precision copies with f32.
+static void gmg_copy_fine(dgnp_ctx& c, Precond& P, bool f32, hipStream_t s) {
+  const int nf = c.m - 1, nb = c.nb;
+  Precond::GLevel& g0 = P.gl[0];
+  const int64_t per0 = g0.E * P.nslot * P.bsz;
+  g0.A.alloc(size_t(nf * per0));
+  ScopeTimer tm(c, "gmg_copy", s);
+  DGNP_HIP(hipMemcpyAsync(g0.A.p, P.blk.p + per0, size_t(nf * per0) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (f32) {
+    g0.A32.alloc(g0.A.n / nb * pot_ld(nb, true));
+    cvt_d2f_rows(g0.A.p, g0.A32.p, int64_t(g0.A.n / nb), nb, pot_ld(nb, true), s);
+  }
+}
+
 static void gmg_numeric(dgnp_ctx& c, Precond& P, bool f32, hipStream_t s) {
   const int nf = c.m - 1, ns = P.nslot, nb = c.nb;
   auto per = [&](const Precond::GLevel& g) { return g.E * ns * P.bsz; };
-  Precond::GLevel& g0 = P.gl[0];
-  g0.A.alloc(size_t(nf * per(g0)));
-  {
-    ScopeTimer tm(c, "gmg_copy", s);
-    DGNP_HIP(hipMemcpyAsync(g0.A.p, P.blk.p + per(g0), size_t(nf * per(g0)) * sizeof(double),
-                            hipMemcpyDeviceToDevice, s));
-    if (f32) {
-      g0.A32.alloc(g0.A.n / nb * pot_ld(nb, true));
-      cvt_d2f_rows(g0.A.p, g0.A32.p, int64_t(g0.A.n / nb), nb, pot_ld(nb, true), s);
-    }
-  }
+  hipStream_t fs = P.side.stream(1);
+  bool forked = false;
   for (size_t l = 1; l < P.gl.size(); ++l) {
     Precond::GLevel& f = P.gl[l - 1];
     Precond::GLevel& g = P.gl[l];
@@ -709,10 +749,12 @@ static void gmg_numeric(dgnp_ctx& c, Precond& P, bool f32, hipStream_t s) {
         g.F32.alloc(g.A.n);
         b32 = g.F32.p;
       }
-      ScopeTimer tm(c, "gmg_factor", s);
+      P.side.order(s, fs);
+      forked = true;
+      ScopeTimer tm(c, "gmg_factor", fs);
       for (size_t lv = 0; lv + 1 < g.lev_ptr.size(); ++lv)
         launch_ilu_factor(nb, c.dim, nf, per(g), g.F.p, g.nbr.p, g.lev_elems.p, g.lev_ptr[lv],
-                          g.lev_ptr[lv + 1] - g.lev_ptr[lv], s, b32);
+                          g.lev_ptr[lv + 1] - g.lev_ptr[lv], fs, b32);
     }
     if (f32) {
       g.A32.alloc(g.A.n / nb * pot_ld(nb, true));
@@ -757,12 +799,14 @@ static void gmg_numeric(dgnp_ctx& c, Precond& P, bool f32, hipStream_t s) {
     cvt_d2f(P.gmg_cinv.p, P.gmg_cinv32.p, int64_t(P.gmg_cinv.n), s);
     cvt_d2f(P.gmg_cinvT.p, P.gmg_cinvT32.p, int64_t(P.gmg_cinvT.n), s);
   }
+  if (forked) P.side.order(fs, s);
 }
 
 void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, int parts) {
   precond_check(c, false);
   Precond& P = *c.pc;
   P.stage.reset();  // precond_check has synchronised the device: earlier copies are complete
+  P.side.next = 0;
   PhaseClock clk(s);
   const int64_t per_field = c.E * P.nslot * P.bsz;
   const bool phi = (parts & PC_PHI) != 0, conc = (parts & PC_CONC) != 0;
@@ -805,18 +849,25 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
       P.blk32.alloc(size_t((c.m - 1) * per_field));
       b32 = P.blk32.p;
     }
-    // multigrid levels from the unfactored fine blocks, before these are
-    // factorised in place
+    // with the multigrid: its fine level keeps a copy of the unfactored
+    // blocks, then the fine factorisation (side stream 0) and the coarse
+    // levels (s, and side stream 1) run side by side; s waits for both
+    hipStream_t fs = s;
     if (P.gmg) {
-      gmg_numeric(c, P, f32, s);
-      clk.mark("concentration multigrid levels");
+      gmg_copy_fine(c, P, f32, s);
+      fs = P.side.stream(0);
+      P.side.order(s, fs);
     }
     for (size_t l = 0; l + 1 < P.lev_ptr.size(); ++l) {
-      ScopeTimer tm(c, "ilu_factor", s);
+      ScopeTimer tm(c, "ilu_factor", fs);
       launch_ilu_factor(c.nb, c.dim, c.m - 1, per_field, P.blk.p + per_field, c.d_nbr.p, P.lev_elems.p,
-                        P.lev_ptr[l], P.lev_ptr[l + 1] - P.lev_ptr[l], s, b32);
+                        P.lev_ptr[l], P.lev_ptr[l + 1] - P.lev_ptr[l], fs, b32);
     }
-    clk.mark("ilu factor (with single-precision copies)");
+    if (P.gmg) {
+      gmg_numeric(c, P, f32, s);
+      P.side.order(fs, s);
+    }
+    clk.mark("concentration factors (fine level, multigrid levels)");
   };
   if (phi) {
     // potential block: element-diagonal inverses (block-Jacobi smoother)
