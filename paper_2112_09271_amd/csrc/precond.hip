@@ -93,12 +93,12 @@ struct PinnedStage {
   }
 };
 
-// Two side streams (default priority) of the concentration set-up and a pool
+// Three side streams (default priority) of the concentration set-up and a pool
 // of events for the fork / join hand-offs between them and the caller's
 // stream.  An event is recorded once per set-up; a wait takes the record that
 // precedes it, so reusing the pool in the next set-up is safe.
 struct SideStreams {
-  hipStream_t st[2] = {nullptr, nullptr};
+  hipStream_t st[3] = {nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> ev;
   size_t next = 0;
   SideStreams() = default;
@@ -835,8 +835,18 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     return;
   }
   // concentration blocks: BILU(0) level by level, then their single copy; all
-  // of it is queued without a host wait, so that with both parts it runs on
-  // the device while the host builds the potential hierarchy
+  // of it is queued without a host wait on side streams (the fine chain, the
+  // multigrid levels), so that with both parts it runs on the device beside
+  // the potential's device work while the host builds the potential
+  // hierarchy; s waits for the side streams at the end of the set-up
+  hipStream_t conc_streams[2] = {nullptr, nullptr};
+  auto join_conc = [&]() {
+    for (hipStream_t& q : conc_streams)
+      if (q) {
+        P.side.order(q, s);
+        q = nullptr;
+      }
+  };
   auto conc_part = [&]() {
     if (split) {
       ScopeTimer tm(c, "assemble", s);
@@ -849,25 +859,28 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
       P.blk32.alloc(size_t((c.m - 1) * per_field));
       b32 = P.blk32.p;
     }
-    // with the multigrid: its fine level keeps a copy of the unfactored
-    // blocks, then the fine factorisation (side stream 0) and the coarse
-    // levels (s, and side stream 1) run side by side; s waits for both
-    hipStream_t fs = s;
-    if (P.gmg) {
-      gmg_copy_fine(c, P, f32, s);
-      fs = P.side.stream(0);
-      P.side.order(s, fs);
-    }
+    // the fine factorisation runs on side stream 0; with the multigrid its
+    // fine level first keeps a copy of the unfactored blocks, and the coarse
+    // levels run beside the fine factorisation (Galerkin chain on side
+    // stream 2, their factorisations on side stream 1)
+    if (P.gmg) gmg_copy_fine(c, P, f32, s);
+    conc_streams[0] = P.side.stream(0);
+    hipStream_t fs = conc_streams[0];
+    P.side.order(s, fs);
     for (size_t l = 0; l + 1 < P.lev_ptr.size(); ++l) {
       ScopeTimer tm(c, "ilu_factor", fs);
       launch_ilu_factor(c.nb, c.dim, c.m - 1, per_field, P.blk.p + per_field, c.d_nbr.p, P.lev_elems.p,
                         P.lev_ptr[l], P.lev_ptr[l + 1] - P.lev_ptr[l], fs, b32);
     }
     if (P.gmg) {
-      gmg_numeric(c, P, f32, s);
-      P.side.order(fs, s);
+      conc_streams[1] = P.side.stream(2);
+      P.side.order(s, conc_streams[1]);
+      gmg_numeric(c, P, f32, conc_streams[1]);
     }
-    clk.mark("concentration factors (fine level, multigrid levels)");
+    if (trace_setup()) {
+      join_conc();
+      clk.mark("concentration factors (fine level, multigrid levels)");
+    }
   };
   if (phi) {
     // potential block: element-diagonal inverses (block-Jacobi smoother)
@@ -1047,6 +1060,7 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
       ensure_work32(c, P);
     }
   }
+  join_conc();
   if (conc) {
     P.conc_ok = true;
     P.conc32_ok = f32;
