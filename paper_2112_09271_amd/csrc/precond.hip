@@ -817,9 +817,9 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     P.lvec1_64.release();
   }
   P.blk.alloc(size_t(c.m * per_field));
-  // with both parts the potential field is assembled first: its Galerkin
-  // stencil then reaches the host sooner, and the concentration fields are
-  // assembled (ahead of their factorisation) while the host builds the hierarchy
+  // with both parts the potential field is assembled here and the
+  // concentration fields by the concentration part on a side stream, so that
+  // their assembly and factorisation run beside the potential's set-up
   const bool split = phi && conc && !assemble_only;
   {
     ScopeTimer tm(c, "assemble", s);
@@ -848,9 +848,12 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
       }
   };
   auto conc_part = [&]() {
+    hipStream_t fs = P.side.stream(0);
+    P.side.order(s, fs);
+    conc_streams[0] = fs;
     if (split) {
-      ScopeTimer tm(c, "assemble", s);
-      launch_assemble(c.dim, c.p, c.m, 1, c.m - 1, c.kargs(), c.d_x.p, P.blk.p, s);
+      ScopeTimer tm(c, "assemble", fs);
+      launch_assemble(c.dim, c.p, c.m, 1, c.m - 1, c.kargs(), c.d_x.p, P.blk.p, fs);
     }
     // the single-precision copies are written by the factorisation kernels
     // themselves, block by block as each is finished
@@ -863,25 +866,23 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     // fine level first keeps a copy of the unfactored blocks, and the coarse
     // levels run beside the fine factorisation (Galerkin chain on side
     // stream 2, their factorisations on side stream 1)
-    if (P.gmg) gmg_copy_fine(c, P, f32, s);
-    conc_streams[0] = P.side.stream(0);
-    hipStream_t fs = conc_streams[0];
-    P.side.order(s, fs);
+    if (P.gmg) {
+      gmg_copy_fine(c, P, f32, fs);
+      conc_streams[1] = P.side.stream(2);
+      P.side.order(fs, conc_streams[1]);
+      gmg_numeric(c, P, f32, conc_streams[1]);
+    }
     for (size_t l = 0; l + 1 < P.lev_ptr.size(); ++l) {
       ScopeTimer tm(c, "ilu_factor", fs);
       launch_ilu_factor(c.nb, c.dim, c.m - 1, per_field, P.blk.p + per_field, c.d_nbr.p, P.lev_elems.p,
                         P.lev_ptr[l], P.lev_ptr[l + 1] - P.lev_ptr[l], fs, b32);
-    }
-    if (P.gmg) {
-      conc_streams[1] = P.side.stream(2);
-      P.side.order(s, conc_streams[1]);
-      gmg_numeric(c, P, f32, conc_streams[1]);
     }
     if (trace_setup()) {
       join_conc();
       clk.mark("concentration factors (fine level, multigrid levels)");
     }
   };
+  if (split) conc_part();
   if (phi) {
     // potential block: element-diagonal inverses (block-Jacobi smoother)
     P.dinv_phi.alloc(size_t(c.E * P.bsz));
@@ -939,16 +940,16 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     DGNP_HIP(hipStreamSynchronize(s));
     clk.mark("galerkin + stencil");
     // The vertex matrix and its aggregation hierarchy are built on a helper
-    // host thread, after this thread has queued the concentration
-    // factorisation and the single-precision potential blocks; this thread
-    // then runs the element levels' lambda_max estimates on the device.
+    // host thread, after this thread has queued the single-precision
+    // potential blocks (the concentration part is already queued on its side
+    // streams); this thread then runs the element levels' lambda_max
+    // estimates on the device.
     // Within one Newton solve the aggregates and smoothed prolongators of the
     // first set-up are kept (only R A P is recomputed): the potential block
     // changes with the concentrations, its vertex graph does not.
     const bool no_reuse = getenv("DGNP_NO_AMG_REUSE") != nullptr;
     const bool reuse =
         !no_reuse && (parts & PC_WARM) != 0 && !P.sa_prev.A.empty() && P.sa_prev.A[0].n == int(P.nvert);
-    if (conc) conc_part();  // device work behind the host set-up
     if (f32) {
       // single-precision potential blocks: they do not depend on the host
       // hierarchy, so they too run while the host builds it
