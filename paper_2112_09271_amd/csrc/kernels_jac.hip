@@ -49,11 +49,15 @@ void upload_ref_tables_jac(const RefTables* tabs, int count) { upload_ref_tables
 // (796 against 888 us).  The neighbours' inputs of the face traces are read
 // directly from global memory: staging them in LDS first cost more (427 against
 // 395 us in FP32).
-template <int P, typename T>
+// The coupling block (potential rows only) has a third of the full apply's
+// output work and is fastest with fewer threads per element at p = 3 (FP32:
+// 64 threads, 257 against 270 us; FP64: 128 threads, 427 against 482 us).
+template <int P, typename T, bool CPL = false>
 struct Shape {
   static constexpr bool F64 = sizeof(T) == 8;
   static constexpr int epb = P == 3 ? 1 : (P == 2 ? (F64 ? 2 : 1) : (F64 ? 2 : 4));
-  static constexpr int nt = P == 3 ? (F64 ? 256 : 128) : (P == 2 ? (F64 ? 256 : 64) : 256);
+  static constexpr int nt = P == 3 ? (CPL ? (F64 ? 128 : 64) : (F64 ? 256 : 128))
+                                   : (P == 2 ? (F64 ? 256 : 64) : 256);
 };
 
 // ---------------------------------------------------------------------------
@@ -638,7 +642,7 @@ static void jl_t(const KArgs& A, const T* v, const T* tv, const T* tf, T* y, hip
       default: break;
     }
   }
-  jl_v<P, MF, T, CPL, Shape<P, T>::epb, Shape<P, T>::nt>(A, v, tv, tf, y, s);
+  jl_v<P, MF, T, CPL, Shape<P, T, CPL>::epb, Shape<P, T, CPL>::nt>(A, v, tv, tf, y, s);
 }
 
 template <typename T>
