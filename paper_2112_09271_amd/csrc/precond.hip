@@ -138,6 +138,7 @@ struct Precond {
   AmgHierarchy sa_prev;
   std::vector<double> sa_x0;
   DevBuf<float> phi32;              // potential field: [E][nslot][nb][ld32], ld32 = pot_ld(nb, true)
+  bool phi32_blocks = false;        // phi32 holds the current blocks (with p-multigrid only on request)
   DevBuf<double> dinv_phi;          // [E][nb][nb]
   DevBuf<float> dinv_phi32;         // [E][nb][ld32]
   double lmax0 = 1.0;
@@ -827,7 +828,7 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     launch_assemble(c.dim, c.p, c.m, f0, f1 - f0, c.kargs(), c.d_x.p, P.blk.p, s);
   }
   clk.mark("assemble");
-  if (phi) P.phi_ok = P.phi32_ok = false;
+  if (phi) P.phi_ok = P.phi32_ok = P.phi32_blocks = false;
   if (conc) P.conc_ok = P.conc32_ok = false;
   if (assemble_only) {
     DGNP_HIP(hipStreamSynchronize(s));
@@ -953,9 +954,14 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     if (f32) {
       // single-precision potential blocks: they do not depend on the host
       // hierarchy, so they too run while the host builds it
+      // (the assembled blocks only without p-multigrid: its order-p level is
+      // applied matrix-free and needs the inverse diagonal blocks alone)
       const int ld32 = pot_ld(c.nb, true);
-      P.phi32.alloc(size_t(c.E) * P.nslot * c.nb * ld32);
-      cvt_d2f_rows(P.blk.p, P.phi32.p, c.E * P.nslot * c.nb, c.nb, ld32, s);
+      if (!P.pmg) {
+        P.phi32.alloc(size_t(c.E) * P.nslot * c.nb * ld32);
+        cvt_d2f_rows(P.blk.p, P.phi32.p, c.E * P.nslot * c.nb, c.nb, ld32, s);
+        P.phi32_blocks = true;
+      }
       P.dinv_phi32.alloc(size_t(c.E) * c.nb * ld32);
       cvt_d2f_rows(P.dinv_phi.p, P.dinv_phi32.p, c.E * c.nb, c.nb, ld32, s);
       if (P.pmg) {
@@ -1071,7 +1077,7 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
 }
 
 void precond_invalidate(dgnp_ctx& c) {
-  if (c.pc) c.pc->phi_ok = c.pc->phi32_ok = c.pc->conc_ok = c.pc->conc32_ok = c.pc->assembled = false;
+  if (c.pc) c.pc->phi_ok = c.pc->phi32_ok = c.pc->phi32_blocks = c.pc->conc_ok = c.pc->conc32_ok = c.pc->assembled = false;
 }
 
 void get_block(dgnp_ctx& c, int field, int64_t elem, int slot, double* out) {
@@ -1442,7 +1448,14 @@ void phi_block_apply(dgnp_ctx& c, const double* x, double* y, hipStream_t s) {
 }
 void phi_block_apply(dgnp_ctx& c, const float* x, float* y, hipStream_t s) {
   DGNP_REQUIRE(c.pc && c.pc->phi32_ok, DGNP_E_STATE, "single-precision potential block not set up");
-  launch_bspmv<float>(c.nb, c.dim, c.E, c.pc->phi32.p, c.d_nbr.p, x, nullptr, 1.0f, 0.0f, y, s);
+  Precond& P = *c.pc;
+  if (!P.phi32_blocks) {  // set-ups with p-multigrid leave the copy to the first request
+    const int ld32 = pot_ld(c.nb, true);
+    P.phi32.alloc(size_t(c.E) * P.nslot * c.nb * ld32);
+    cvt_d2f_rows(P.blk.p, P.phi32.p, c.E * P.nslot * c.nb, c.nb, ld32, s);
+    P.phi32_blocks = true;
+  }
+  launch_bspmv<float>(c.nb, c.dim, c.E, P.phi32.p, c.d_nbr.p, x, nullptr, 1.0f, 0.0f, y, s);
 }
 
 void phi_apply(dgnp_ctx& c, const void* x, void* y, bool f32, bool matfree, hipStream_t s) {
