@@ -1314,11 +1314,16 @@ __device__ inline float4 ld4(const float* p) { return *reinterpret_cast<const fl
 template <typename T, int NB, int DIM>
 __global__ void __launch_bounds__(BT) k_bspmv(const T* __restrict__ blk, const int* __restrict__ nbr,
                                               const T* __restrict__ x, const T* __restrict__ b, T alpha,
-                                              T beta, T* __restrict__ y) {
+                                              T beta, T* __restrict__ y, int64_t bstride, int64_t vstride) {
   constexpr int NSLOT = 2 * DIM + 1;
   using PR = PotRows<T, NB>;
   const int tid = threadIdx.x;
   const int64_t i = blockIdx.x;
+  // blockIdx.y: one of several independent systems at block / vector strides
+  blk += blockIdx.y * bstride;
+  x += blockIdx.y * vstride;
+  if (b) b += blockIdx.y * vstride;
+  y += blockIdx.y * vstride;
   if constexpr (PR::VEC) {
     constexpr int LD = PR::LD, QV = PR::QV;
     __shared__ __align__(16) float xv[NSLOT][LD];
@@ -2040,35 +2045,38 @@ template void launch_ilu_solve<float>(int, int, int, const float*, const int*, c
 
 template <typename T, int NB, int DIM>
 static void bsp_t(int64_t E, const T* blk, const int* nbr, const T* x, const T* b, T alpha, T beta, T* y,
-                  hipStream_t s) {
-  hipLaunchKernelGGL((k_bspmv<T, NB, DIM>), dim3(unsigned(E)), dim3(BT), 0, s, blk, nbr, x, b, alpha, beta, y);
+                  int nsys, int64_t bstride, int64_t vstride, hipStream_t s) {
+  hipLaunchKernelGGL((k_bspmv<T, NB, DIM>), dim3(unsigned(E), unsigned(nsys)), dim3(BT), 0, s, blk, nbr, x, b,
+                     alpha, beta, y, bstride, vstride);
 }
 
 template <typename T>
 void launch_bspmv(int nb, int dim, int64_t E, const T* blk, const int* nbr, const T* x, const T* b, T alpha,
-                  T beta, T* y, hipStream_t s) {
-  if (E == 0) return;
+                  T beta, T* y, hipStream_t s, int nsys, int64_t bstride, int64_t vstride) {
+  if (E == 0 || nsys == 0) return;
+#define BSP_ARGS E, blk, nbr, x, b, alpha, beta, y, nsys, bstride, vstride, s
   if (dim == 3) {
     switch (nb) {
-      case 8: bsp_t<T, 8, 3>(E, blk, nbr, x, b, alpha, beta, y, s); break;
-      case 27: bsp_t<T, 27, 3>(E, blk, nbr, x, b, alpha, beta, y, s); break;
-      case 64: bsp_t<T, 64, 3>(E, blk, nbr, x, b, alpha, beta, y, s); break;
+      case 8: bsp_t<T, 8, 3>(BSP_ARGS); break;
+      case 27: bsp_t<T, 27, 3>(BSP_ARGS); break;
+      case 64: bsp_t<T, 64, 3>(BSP_ARGS); break;
       default: throw Error(DGNP_E_ARG, "unsupported block size");
     }
   } else {
     switch (nb) {
-      case 4: bsp_t<T, 4, 2>(E, blk, nbr, x, b, alpha, beta, y, s); break;
-      case 9: bsp_t<T, 9, 2>(E, blk, nbr, x, b, alpha, beta, y, s); break;
-      case 16: bsp_t<T, 16, 2>(E, blk, nbr, x, b, alpha, beta, y, s); break;
+      case 4: bsp_t<T, 4, 2>(BSP_ARGS); break;
+      case 9: bsp_t<T, 9, 2>(BSP_ARGS); break;
+      case 16: bsp_t<T, 16, 2>(BSP_ARGS); break;
       default: throw Error(DGNP_E_ARG, "unsupported block size");
     }
   }
+#undef BSP_ARGS
   DGNP_HIP(hipGetLastError());
 }
 template void launch_bspmv<double>(int, int, int64_t, const double*, const int*, const double*, const double*,
-                                   double, double, double*, hipStream_t);
+                                   double, double, double*, hipStream_t, int, int64_t, int64_t);
 template void launch_bspmv<float>(int, int, int64_t, const float*, const int*, const float*, const float*,
-                                  float, float, float*, hipStream_t);
+                                  float, float, float*, hipStream_t, int, int64_t, int64_t);
 
 template <typename T>
 void launch_bdiag(int nb, int64_t E, const T* dinv, const T* x, T* y, hipStream_t s) {

@@ -46,10 +46,12 @@ void launch_ilu_lines(int kind, int nb, int dim, const float* blk, const int* nb
 // blocks of up to 32 rows have rows padded to a multiple of four floats (zeros
 // in the padding); all others are stored unpadded.
 inline int pot_ld(int nb, bool f32) { return (f32 && nb <= 32) ? ((nb + 3) & ~3) : nb; }
-// y = alpha A x + beta b over the element-block graph (block rows of pot_ld)
+// y = alpha A x + beta b over the element-block graph (block rows of pot_ld);
+// nsys independent systems in one launch, the k-th at blk + k bstride with
+// vectors at x, b, y + k vstride
 template <typename T>
 void launch_bspmv(int nb, int dim, int64_t E, const T* blk, const int* nbr, const T* x, const T* b, T alpha,
-                  T beta, T* y, hipStream_t s);
+                  T beta, T* y, hipStream_t s, int nsys = 1, int64_t bstride = 0, int64_t vstride = 0);
 template <typename T>
 void launch_bdiag(int nb, int64_t E, const T* dinv, const T* x, T* y, hipStream_t s);
 // restriction (d1 not null): also d1 = c1 (dinv .* b), the first Chebyshev
@@ -86,5 +88,6 @@ void launch_csr_spmv(int n, const int* rp, const int* ci, const T* v, const T* x
 template <typename T>
 void launch_vmul(int64_t n, const T* d, const T* x, T* y, hipStream_t s);  // y = d .* x
 template <typename T>
-void launch_dense_gemv(int n, const T* M, const T* x, T* y, hipStream_t s);  // y = M x
+void launch_dense_gemv(int n, const T* M, const T* x, T* y, hipStream_t s, int nsys = 1,
+                       int64_t xs = 0);  // y = M x for nsys systems (M + k n^2, x and y + k xs)
 }  // namespace dgnp

@@ -69,9 +69,14 @@ void launch_vmul(int64_t n, const T* d, const T* x, T* y, hipStream_t s) {
 template void launch_vmul<double>(int64_t, const double*, const double*, double*, hipStream_t);
 template void launch_vmul<float>(int64_t, const float*, const float*, float*, hipStream_t);
 
-// dense row-major n x n matrix-vector product, one 64-lane wave per row
+// dense row-major n x n matrix-vector product, one 64-lane wave per row;
+// blockIdx.y: one of several systems, the k-th at M + k n^2, x + k xs, y + k xs
 template <typename T>
-__global__ void k_dense_gemv(int n, const T* __restrict__ M, const T* __restrict__ x, T* __restrict__ y) {
+__global__ void k_dense_gemv(int n, const T* __restrict__ M, const T* __restrict__ x, T* __restrict__ y,
+                             int64_t xs) {
+  M += blockIdx.y * int64_t(n) * n;
+  x += blockIdx.y * xs;
+  y += blockIdx.y * xs;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   T acc = T(0);
@@ -82,13 +87,13 @@ __global__ void k_dense_gemv(int n, const T* __restrict__ M, const T* __restrict
 }
 
 template <typename T>
-void launch_dense_gemv(int n, const T* M, const T* x, T* y, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_dense_gemv<T>, dim3(unsigned((n + 3) / 4)), dim3(256), 0, s, n, M, x, y);
+void launch_dense_gemv(int n, const T* M, const T* x, T* y, hipStream_t s, int nsys, int64_t xs) {
+  if (n <= 0 || nsys <= 0) return;
+  hipLaunchKernelGGL(k_dense_gemv<T>, dim3(unsigned((n + 3) / 4), unsigned(nsys)), dim3(256), 0, s, n, M, x, y, xs);
   DGNP_HIP(hipGetLastError());
 }
-template void launch_dense_gemv<double>(int, const double*, const double*, double*, hipStream_t);
-template void launch_dense_gemv<float>(int, const float*, const float*, float*, hipStream_t);
+template void launch_dense_gemv<double>(int, const double*, const double*, double*, hipStream_t, int, int64_t);
+template void launch_dense_gemv<float>(int, const float*, const float*, float*, hipStream_t, int, int64_t);
 
 // One Chebyshev smoothing step on a scalar (CSR) level, fused:
 //   r = base - A u          (u null: r = base)

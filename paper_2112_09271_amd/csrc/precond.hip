@@ -1355,8 +1355,7 @@ static void gmg_vcycle(dgnp_ctx& c, Precond& P, bool tr, int l, const T* b, T* x
   const int64_t nfl = g.E * c.nb;
   if (l == last) {
     const int n = P.gmg_nc;
-    for (int f = 0; f < nf; ++f)
-      launch_dense_gemv<T>(n, GSel<T>::cinv(P, tr) + int64_t(f) * n * n, b + f * nfl, x + f * nfl, s);
+    launch_dense_gemv<T>(n, GSel<T>::cinv(P, tr), b, x, s, nf, nfl);
     return;
   }
   const T* A = GSel<T>::A(g);
@@ -1365,14 +1364,12 @@ static void gmg_vcycle(dgnp_ctx& c, Precond& P, bool tr, int l, const T* b, T* x
   const int64_t fs = g.E * P.nslot * c.nb * ld;
   T* r = GSel<T>::r(g);
   T* z = GSel<T>::z(g);
-  // r = b - A x (forward: the block SpMV of the potential block, per field)
+  // r = b - A x (forward: the block SpMV of the potential block, all fields in one launch)
   auto resid = [&]() {
-    if (tr) {
+    if (tr)
       launch_gmg_resid<T>(c.nb, c.dim, nf, true, A, fs, ld, nbr, g.E, x, b, r, s);
-    } else {
-      for (int f = 0; f < nf; ++f)
-        launch_bspmv<T>(c.nb, c.dim, g.E, A + f * fs, nbr, x + f * nfl, b + f * nfl, T(-1), T(1), r + f * nfl, s);
-    }
+    else
+      launch_bspmv<T>(c.nb, c.dim, g.E, A, nbr, x, b, T(-1), T(1), r, s, nf, fs, nfl);
   };
   auto richardson = [&]() {
     resid();
