@@ -151,6 +151,110 @@ __global__ void __launch_bounds__(GT) k_gmg_galerkin(const double* __restrict__ 
   }
 }
 
+// The same Galerkin product for blocks of 17..32 rows on the FP64 matrix
+// cores: both products of a contribution, T = A_{e,t} Pi_c' and then
+// Pi_c^T T, are padded to 32 x 32 and split into four 16 x 16 tiles, one per
+// wave (v_mfma_f64_16x16x4f64, the k loop in steps of four with entries past
+// NB read as zero).  Lane l of wave w holds A operand rows 16 (w >> 1) + l % 16
+// and B operand columns 16 (w & 1) + l % 16 at k = 4 s + l / 16; the four
+// accumulator entries of a lane are rows 16 (w >> 1) + 4 q + l / 16 of column
+// 16 (w & 1) + l % 16.  The fine block of the next contribution is read into
+// registers while the current one is multiplied; T passes through LDS; the
+// coarse block accumulates in the tiles' registers.
+typedef double gv4d __attribute__((ext_vector_type(4)));
+template <int NB, int DIM>
+__global__ void __launch_bounds__(GT) k_gmg_galerkin_mf(const double* __restrict__ Af, int64_t fsf,
+                                                        const int* __restrict__ nbr, Dims fd,
+                                                        const double* __restrict__ Pi, double* __restrict__ Ac,
+                                                        int64_t fsc) {
+  static_assert(NB > 16 && NB <= 32, "32 x 32 padded tiles");
+  constexpr int NS = 2 * DIM + 1, NC = 1 << DIM, BB = NB * NB, KS = (NB + 3) / 4;
+  constexpr int MAXC = NC * (DIM + 1);
+  const int64_t ec = blockIdx.x;
+  const int s = blockIdx.z, tid = threadIdx.x;
+  Af += blockIdx.y * fsf;
+  Ac += blockIdx.y * fsc;
+  __shared__ double sPi[NC * BB], sT[BB];
+  for (int i = tid; i < NC * BB; i += GT) sPi[i] = Pi[i];
+  __shared__ int64_t ce[MAXC];
+  __shared__ int ct[MAXC], cc[MAXC], ccp[MAXC];
+  __shared__ int s_n;
+  if (tid == 0) {
+    int n = 0;
+    for (int c = 0; c < NC; ++c) {
+      const int64_t e = fine_child(fd, ec, c);
+      for (int t = 0; t < NS; ++t) {
+        int cp = c;
+        if (t == 0) {
+          if (s != 0) continue;
+        } else {
+          const int a = (t - 1) >> 1, up = (t - 1) & 1;
+          const bool inside = ((c >> a) & 1) != up;
+          if (inside ? s != 0 : s != t) continue;
+          if (nbr[e * 2 * DIM + t - 1] < 0) continue;
+          cp = c ^ (1 << a);
+        }
+        ce[n] = e;
+        ct[n] = t;
+        cc[n] = c;
+        ccp[n] = cp;
+        ++n;
+      }
+    }
+    s_n = n;
+  }
+  __syncthreads();
+  const int n = s_n;
+  const int l = tid & 63, w = tid >> 6, lk = l >> 4;
+  const int ia = 16 * (w >> 1) + (l & 15), jb = 16 * (w & 1) + (l & 15);
+  auto load_a = [&](int k, double (&dst)[KS]) {
+    const double* A = Af + (ce[k] * NS + ct[k]) * BB;
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+      const int kk = 4 * q + lk;
+      dst[q] = (ia < NB && kk < NB) ? A[ia * NB + kk] : 0.0;
+    }
+  };
+  double xa[KS], na[KS];
+  if (n > 0) load_a(0, xa);
+  gv4d accC = gv4d{0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < n; ++k) {
+    if (k + 1 < n) load_a(k + 1, na);
+    const double* Pc = sPi + ccp[k] * BB;
+    gv4d accT = gv4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+      const int kk = 4 * q + lk;
+      const double b = (jb < NB && kk < NB) ? Pc[kk * NB + jb] : 0.0;
+      accT = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[q], b, accT, 0, 0, 0);
+    }
+    __syncthreads();  // the previous contribution has finished reading sT
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int rr = 16 * (w >> 1) + 4 * q + lk, col = jb;
+      if (rr < NB && col < NB) sT[rr * NB + col] = accT[q];
+    }
+    __syncthreads();
+    const double* Pr = sPi + cc[k] * BB;
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+      const int kk = 4 * q + lk;
+      const double a = (ia < NB && kk < NB) ? Pr[kk * NB + ia] : 0.0;
+      const double b = (jb < NB && kk < NB) ? sT[kk * NB + jb] : 0.0;
+      accC = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, accC, 0, 0, 0);
+    }
+    if (k + 1 < n) {
+#pragma unroll
+      for (int q = 0; q < KS; ++q) xa[q] = na[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int rr = 16 * (w >> 1) + 4 * q + lk, col = jb;
+    if (rr < NB && col < NB) Ac[(ec * NS + s) * BB + rr * NB + col] = accC[q];
+  }
+}
+
 // rc = P^T r: one thread per (coarse entry, field)
 template <typename T, int NB, int DIM>
 __global__ void __launch_bounds__(GT) k_gmg_restrict(const T* __restrict__ Pi, Dims fd, const T* __restrict__ r,
@@ -374,13 +478,22 @@ __global__ void __launch_bounds__(DI) k_dense_inverse(double* __restrict__ Mg, d
 
 static Dims dims_of(int dim, const int* n) { return Dims{n[0], n[1], dim == 3 ? n[2] : 1}; }
 
+// 17..32-row blocks on the matrix cores, the others on the vector ALU
+template <int NB, int DIM>
+static void galerkin_t(dim3 g, const double* Af, int64_t fsf, const int* nbr, Dims fd, const double* Pi, double* Ac,
+                       int64_t fsc, hipStream_t s) {
+  if constexpr (NB > 16 && NB <= 32)
+    hipLaunchKernelGGL((k_gmg_galerkin_mf<NB, DIM>), g, dim3(GT), 0, s, Af, fsf, nbr, fd, Pi, Ac, fsc);
+  else
+    hipLaunchKernelGGL((k_gmg_galerkin<NB, DIM>), g, dim3(GT), 0, s, Af, fsf, nbr, fd, Pi, Ac, fsc);
+}
+
 void launch_gmg_galerkin(int nb, int dim, int nfields, const double* Af, int64_t fsf, const int* nbr,
                          const int* nfine, const double* Pi, double* Ac, int64_t fsc, int64_t Ec, hipStream_t s) {
   if (Ec == 0 || nfields == 0) return;
   const Dims fd = dims_of(dim, nfine);
   const dim3 g = dim3(unsigned(Ec), unsigned(nfields), unsigned(2 * dim + 1));
-  GMG_NB_SWITCH(nb, dim,
-                hipLaunchKernelGGL((k_gmg_galerkin<NB_, D_>), g, dim3(GT), 0, s, Af, fsf, nbr, fd, Pi, Ac, fsc));
+  GMG_NB_SWITCH(nb, dim, (galerkin_t<NB_, D_>)(g, Af, fsf, nbr, fd, Pi, Ac, fsc, s));
   DGNP_HIP(hipGetLastError());
 }
 
