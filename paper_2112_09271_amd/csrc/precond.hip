@@ -818,13 +818,18 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     P.lvec1_64.release();
   }
   P.blk.alloc(size_t(c.m * per_field));
-  // with both parts the potential field is assembled here and the
+  // with both parts the potential field is assembled on s and the
   // concentration fields by the concentration part on a side stream, so that
-  // their assembly and factorisation run beside the potential's set-up
+  // their factorisation runs beside the potential's set-up.  Both assemblies
+  // fill the device, so they are ordered: the potential first (its hierarchy
+  // is then built on the host beside the factorisation), except with 64-row
+  // blocks, whose factorisation chain is the longest part of the set-up and
+  // starts first
   const bool split = phi && conc && !assemble_only;
-  {
+  const bool conc_first = split && c.nb >= 64;
+  if (!split) {
     ScopeTimer tm(c, "assemble", s);
-    const int f0 = phi ? 0 : 1, f1 = (conc && !split) ? c.m : 1;
+    const int f0 = phi ? 0 : 1, f1 = conc ? c.m : 1;
     launch_assemble(c.dim, c.p, c.m, f0, f1 - f0, c.kargs(), c.d_x.p, P.blk.p, s);
   }
   clk.mark("assemble");
@@ -856,6 +861,7 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
       ScopeTimer tm(c, "assemble", fs);
       launch_assemble(c.dim, c.p, c.m, 1, c.m - 1, c.kargs(), c.d_x.p, P.blk.p, fs);
     }
+    if (conc_first) P.side.order(fs, s);
     // the single-precision copies are written by the factorisation kernels
     // themselves, block by block as each is finished
     float* b32 = nullptr;
@@ -883,7 +889,14 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
       clk.mark("concentration factors (fine level, multigrid levels)");
     }
   };
-  if (split) conc_part();
+  if (split) {
+    if (conc_first) conc_part();
+    {
+      ScopeTimer tm(c, "assemble", s);
+      launch_assemble(c.dim, c.p, c.m, 0, 1, c.kargs(), c.d_x.p, P.blk.p, s);
+    }
+    if (!conc_first) conc_part();
+  }
   if (phi) {
     // potential block: element-diagonal inverses (block-Jacobi smoother)
     P.dinv_phi.alloc(size_t(c.E * P.bsz));
