@@ -547,15 +547,18 @@ def main():
     avg = tot / launches
     per_launch_bytes, kname = models[dom]
     achieved = per_launch_bytes / avg / 1e9
-    keys = {"cheb_blk_f32": "k_cheb_blk_f32_cfg2", "ilu_fwd_f32": "k_ilu_dfp_fwd_cfg2",
-            "ilu_bwd_f32": "k_ilu_dfp_bwd_cfg2", "jac_apply_f32": "k_jlin_f32_cfg2",
-            "ilu_factor": "k_ilu_factor_fine_cfg2"}
+    # counter-measured HBM bytes per launch (profiles/hbm_traffic.json), per workload
+    keys = {"cfg2": {"cheb_blk_f32": "k_cheb_blk_f32_cfg2", "ilu_fwd_f32": "k_ilu_dfp_fwd_cfg2",
+                     "ilu_bwd_f32": "k_ilu_dfp_bwd_cfg2", "jac_apply_f32": "k_jlin_f32_cfg2",
+                     "ilu_factor": "k_ilu_factor_fine_cfg2"},
+            "cfg5": {"ilu_fwd_f32": "k_ilu_dfl_fwd_cfg5", "ilu_bwd_f32": "k_ilu_dfl_bwd_cfg5",
+                     "jac_apply_f32": "k_jlin_f32_cfg5"}}.get(cfg.name, {})
     srcs = ("kernels_jac.hip", "dg_device.hpp", "pointwise.hpp") if dom == "jac_apply_f32" else ("kernels_block.hip",)
     copy_gbs = copy_bandwidth()
     roofline = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "avg_launch_us": 1e6 * avg, "launches": launches,
                 "bytes_per_launch": per_launch_bytes, "chosen_by": chosen_by,
-                "traffic": measured_traffic(keys[dom], source_hash(*srcs)),
+                "traffic": measured_traffic(keys[dom], source_hash(*srcs)) if dom in keys else None,
                 # context, not the peak: what a plain device-to-device copy sustains here
                 "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs if copy_gbs else None}
     if ranking and ranking.get("family") == dom and ranking.get("avg_us"):
