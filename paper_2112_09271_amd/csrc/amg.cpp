@@ -126,6 +126,10 @@ static void parallel_rows(int n, int ch, F&& fn) {
   HostPool::get().run(nch, job);
 }
 
+void host_parallel_rows(int n, const std::function<void(int, int)>& fn) {
+  parallel_rows(n, CH, [&](int, int, int r0, int r1) { fn(r0, r1); });
+}
+
 Csr csr_transpose(const Csr& A) {
   Csr T;
   T.n = A.m;
@@ -482,11 +486,11 @@ static void smoother_data(AmgHierarchy& H, const Csr& A, int iters, std::vector<
   H.dinv.push_back(std::move(dinv));
 }
 
-AmgHierarchy sa_setup(const Csr& A1, int max_levels, int coarse_size, double theta, std::vector<double>* x0) {
+AmgHierarchy sa_setup(Csr A1, int max_levels, int coarse_size, double theta, std::vector<double>* x0) {
   auto t0 = std::chrono::steady_clock::now();
   auto mark = [&](const char* what) { sa_mark(t0, what); };
   AmgHierarchy H;
-  H.A.push_back(A1);
+  H.A.push_back(std::move(A1));
   if (x0) x0->clear();  // cold: the estimate does not depend on earlier set-ups
   smoother_data(H, H.A.back(), 20, x0);
   mark("lmax");
@@ -512,14 +516,14 @@ AmgHierarchy sa_setup(const Csr& A1, int max_levels, int coarse_size, double the
   return H;
 }
 
-AmgHierarchy sa_setup_reuse(const Csr& A1, const AmgHierarchy& prev, std::vector<double>* x0) {
+AmgHierarchy sa_setup_reuse(Csr A1, const AmgHierarchy& prev, std::vector<double>* x0) {
   auto t0 = std::chrono::steady_clock::now();
   auto mark = [&](const char* what) { sa_mark(t0, what); };
   if (prev.A.empty() || prev.A[0].n != A1.n)
     throw Error(DGNP_E_STATE, "aggregation reuse: the vertex level changed size");
   AmgHierarchy H;
-  H.A.push_back(A1);
-  smoother_data(H, H.A.back(), x0 && x0->size() == size_t(A1.n) ? 8 : 20, x0);
+  H.A.push_back(std::move(A1));
+  smoother_data(H, H.A.back(), x0 && x0->size() == size_t(H.A[0].n) ? 8 : 20, x0);
   mark("lmax (warm)");
   for (size_t l = 0; l < prev.P.size(); ++l) {
     H.P.push_back(prev.P[l]);

@@ -1,6 +1,7 @@
 // Host CSR matrices and the smoothed-aggregation setup (amg.cpp).
 #pragma once
 
+#include <functional>
 #include <vector>
 
 #include "dgnp_impl.hpp"
@@ -21,17 +22,20 @@ struct AmgHierarchy {
   std::vector<double> coarse_inv;  // dense row-major inverse of A.back()
 };
 
+// fn(first row, end row) over chunks of rows [0, n) on the host worker pool
+// (row-independent work only)
+void host_parallel_rows(int n, const std::function<void(int, int)>& fn);
 Csr csr_transpose(const Csr& A);
 Csr csr_matmul(const Csr& A, const Csr& B);
 // power iterations for the largest eigenvalue of D^{-1} A; x_io (may be null):
 // start vector in (used when its size matches), last vector out
 double lmax_dinvA(const Csr& A, const std::vector<double>& dinv, int iters, std::vector<double>* x_io = nullptr);
 // x0 (may be null) receives the finest level's last power-iteration vector
-AmgHierarchy sa_setup(const Csr& A1, int max_levels, int coarse_size, double theta,
+AmgHierarchy sa_setup(Csr A1, int max_levels, int coarse_size, double theta,
                       std::vector<double>* x0 = nullptr);
 // the same hierarchy shape for a new finest matrix with the aggregates and
 // prolongators of prev kept: only the Galerkin products, smoother data and
 // coarse inverse are recomputed; the finest estimate warm-starts from x0
-AmgHierarchy sa_setup_reuse(const Csr& A1, const AmgHierarchy& prev, std::vector<double>* x0);
+AmgHierarchy sa_setup_reuse(Csr A1, const AmgHierarchy& prev, std::vector<double>* x0);
 
 }  // namespace dgnp

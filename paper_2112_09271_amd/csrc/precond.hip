@@ -173,6 +173,7 @@ struct Precond {
   int64_t nvert = 0;
   DevBuf<double> gal;
   DevBuf<double> vst;               // [nvert][3^d] vertex stencil of the Galerkin operator
+  std::vector<double> st_host;      // its host copy
   std::vector<MgLevel> mg;          // mg[0] = vertex level
   DevBuf<double> cinv;
   DevBuf<float> cinv32;
@@ -515,33 +516,84 @@ void precond_check(dgnp_ctx& c, bool report) {
 // ---- vertex matrix from the per-element Galerkin blocks ----------------------
 // CSR of the Galerkin vertex operator from its dense per-vertex stencil
 // st[r][o] (o over {-1, 0, 1}^d, first axis fastest); exact zeros are dropped
-static Csr vertex_matrix(const dgnp_ctx& c, const Precond& P, const std::vector<double>& st) {
+// the vertex operator as CSR from its stencil st (exact zeros left out): row
+// lengths, their prefix sums, then the entries, row chunks on the host pool
+// (small operators in one serial pass).
+// storage (may be empty): a matrix of the same order whose arrays are reused,
+// so that a new set-up writes into memory that is already mapped
+static Csr vertex_matrix(const dgnp_ctx& c, const Precond& P, const double* st, Csr&& storage) {
   const int d = c.dim;
   const int ns = d == 3 ? 27 : 9;
+  const int n = int(P.nvert);
   Csr A;
-  A.n = A.m = int(P.nvert);
-  A.rp.assign(size_t(A.n) + 1, 0);
-  A.ci.reserve(st.size());
-  A.v.reserve(st.size());
-  for (int64_t r = 0; r < P.nvert; ++r) {
-    int rc[3] = {int(r % P.nvx[0]), int((r / P.nvx[0]) % P.nvx[1]), int(r / (int64_t(P.nvx[0]) * P.nvx[1]))};
-    for (int off = 0; off < ns; ++off) {
-      int oc[3] = {off % 3 - 1, (off / 3) % 3 - 1, off / 9 - 1};
-      bool ok = true;
-      int64_t col = 0, mul = 1;
-      for (int a = 0; a < d; ++a) {
-        const int cc = rc[a] + oc[a];
-        if (cc < 0 || cc >= P.nvx[a]) ok = false;
-        col += cc * mul;
-        mul *= P.nvx[a];
-      }
-      const double val = st[size_t(r) * ns + off];
-      if (!ok || val == 0.0) continue;
-      A.ci.push_back(int(col));
-      A.v.push_back(val);
-    }
-    A.rp[r + 1] = int(A.ci.size());
+  if (storage.n == n) {
+    A.rp = std::move(storage.rp);
+    A.ci = std::move(storage.ci);
+    A.v = std::move(storage.v);
   }
+  A.n = A.m = n;
+  A.rp.resize(size_t(n) + 1);
+  A.rp[0] = 0;
+  // columns of the ns stencil entries of row r (-1 outside the grid): the
+  // entry off couples vertex r to r + delta[off] when every coordinate moved
+  // stays inside the grid
+  int delta[27];
+  for (int off = 0; off < ns; ++off)
+    delta[off] = (off % 3 - 1) + (d > 1 ? ((off / 3) % 3 - 1) * P.nvx[0] : 0) +
+                 (d > 2 ? (off / 9 - 1) * P.nvx[0] * P.nvx[1] : 0);
+  auto columns = [&](int r, int* col) {
+    const int rc[3] = {r % P.nvx[0], (r / P.nvx[0]) % P.nvx[1], r / (P.nvx[0] * P.nvx[1])};
+    bool in[3][3];  // in[a][o]: coordinate a moved by o - 1 stays inside
+    for (int a = 0; a < 3; ++a)
+      for (int o = 0; o < 3; ++o) in[a][o] = a >= d ? o == 1 : (rc[a] + o - 1 >= 0 && rc[a] + o - 1 < P.nvx[a]);
+    for (int off = 0; off < ns; ++off) {
+      const bool ok = in[0][off % 3] && in[1][(off / 3) % 3] && (d < 3 || in[2][off / 9]);
+      col[off] = ok ? r + delta[off] : -1;
+    }
+  };
+  if (n < 8192) {  // small: one serial pass (the pool would run it serially anyway)
+    A.ci.clear();
+    A.v.clear();
+    int col[27];
+    for (int r = 0; r < n; ++r) {
+      columns(r, col);
+      for (int off = 0; off < ns; ++off) {
+        const double val = st[size_t(r) * ns + off];
+        if (val == 0.0 || col[off] < 0) continue;
+        A.ci.push_back(col[off]);
+        A.v.push_back(val);
+      }
+      A.rp[size_t(r) + 1] = int(A.ci.size());
+    }
+    return A;
+  }
+  host_parallel_rows(n, [&](int r0, int r1) {
+    int col[27];
+    for (int r = r0; r < r1; ++r) {
+      columns(r, col);
+      int k = 0;
+      for (int off = 0; off < ns; ++off)
+        if (st[size_t(r) * ns + off] != 0.0 && col[off] >= 0) ++k;
+      A.rp[size_t(r) + 1] = k;
+    }
+  });
+  for (int r = 0; r < n; ++r) A.rp[size_t(r) + 1] += A.rp[size_t(r)];
+  A.ci.resize(size_t(A.rp[size_t(n)]));
+  A.v.resize(A.ci.size());
+  host_parallel_rows(n, [&](int r0, int r1) {
+    int col[27];
+    for (int r = r0; r < r1; ++r) {
+      columns(r, col);
+      int k = A.rp[size_t(r)];
+      for (int off = 0; off < ns; ++off) {
+        const double val = st[size_t(r) * ns + off];
+        if (val == 0.0 || col[off] < 0) continue;
+        A.ci[size_t(k)] = col[off];
+        A.v[size_t(k)] = val;
+        ++k;
+      }
+    }
+  });
   return A;
 }
 
@@ -949,8 +1001,11 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     launch_q1_galerkin(c.dim, gal_p, c.E, gal_blk, P.gal.p, s);
     P.vst.alloc(size_t(P.nvert) * (c.dim == 3 ? 27 : 9));
     launch_vertex_stencil(c.dim, P.gal.p, c.d_nbr.p, c.n, P.nvert, P.vst.p, s);
-    std::vector<double> st(P.vst.n);
-    DGNP_HIP(hipMemcpyAsync(st.data(), P.vst.p, st.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    // the stencil comes back into a host array kept between set-ups (mapped
+    // once: a fresh array of this size costs its page faults at every set-up)
+    P.st_host.resize(P.vst.n);
+    double* st = P.st_host.data();
+    DGNP_HIP(hipMemcpyAsync(st, P.vst.p, P.vst.n * sizeof(double), hipMemcpyDeviceToHost, s));
     DGNP_HIP(hipStreamSynchronize(s));
     clk.mark("galerkin + stencil");
     // The vertex matrix and its aggregation hierarchy are built on a helper
@@ -990,8 +1045,18 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     std::exception_ptr sa_err;
     std::thread sa_thread([&]() {
       try {
-        const Csr A1 = vertex_matrix(c, P, st);
-        H = reuse ? sa_setup_reuse(A1, P.sa_prev, &P.sa_x0) : sa_setup(A1, 12, 256, 0.0, &P.sa_x0);
+        // the previous set-up's vertex matrix lends its arrays (only its order is
+        // read afterwards, by the reuse check)
+        Csr storage;
+        if (!P.sa_prev.A.empty() && P.sa_prev.A[0].n == int(P.nvert)) {
+          storage.n = P.sa_prev.A[0].n;
+          storage.rp = std::move(P.sa_prev.A[0].rp);
+          storage.ci = std::move(P.sa_prev.A[0].ci);
+          storage.v = std::move(P.sa_prev.A[0].v);
+        }
+        Csr A1 = vertex_matrix(c, P, st, std::move(storage));
+        H = reuse ? sa_setup_reuse(std::move(A1), P.sa_prev, &P.sa_x0)
+                  : sa_setup(std::move(A1), 12, 256, 0.0, &P.sa_x0);
       } catch (...) {
         sa_err = std::current_exception();
       }
