@@ -17,6 +17,7 @@
 #include <functional>
 #include <mutex>
 #include <thread>
+#include <type_traits>
 
 namespace dgnp {
 
@@ -149,28 +150,55 @@ Csr csr_transpose(const Csr& A) {
   return T;
 }
 
-// Gustavson row-by-row product with a dense accumulator per chunk; columns sorted.
-Csr csr_matmul(const Csr& A, const Csr& B) {
-  Csr C;
+// Gustavson row-by-row product with a dense accumulator per host thread, in
+// two passes over the rows: the number of distinct columns of every row, then,
+// after a prefix sum, its sorted columns and values written in place.  Every
+// entry is summed over A's row in order and, within it, over B's row in order,
+// so the result does not depend on the chunking.  `storage` lends its arrays
+// (kept between set-ups, so that a large product does not pay the page faults
+// of fresh memory every time).
+Csr csr_matmul(const Csr& A, const Csr& B, Csr&& storage) {
+  Csr C = std::move(storage);
   C.n = A.n;
   C.m = B.m;
   C.rp.assign(size_t(C.n) + 1, 0);
-  const int nch = (A.n + CHM - 1) / CHM;
-  std::vector<std::vector<int>> cch(static_cast<size_t>(nch));
-  std::vector<std::vector<double>> vch(static_cast<size_t>(nch));
-  const int nt = host_threads(nch);
+  const int nt = host_threads(0);
   std::vector<std::vector<double>> accs(static_cast<size_t>(nt));
   std::vector<std::vector<int>> marks(static_cast<size_t>(nt)), colss(static_cast<size_t>(nt));
-  parallel_rows(A.n, CHM, [&](int t, int ch, int r0, int r1) {
-    std::vector<double>& acc = accs[size_t(t)];
-    std::vector<int>& mark = marks[size_t(t)];
-    std::vector<int>& cols = colss[size_t(t)];
-    if (acc.size() != size_t(B.m)) {
-      acc.assign(size_t(B.m), 0.0);
-      mark.assign(size_t(B.m), -1);
+  auto scratch = [&](int t) {
+    if (marks[size_t(t)].size() != size_t(B.m)) {
+      accs[size_t(t)].assign(size_t(B.m), 0.0);
+      marks[size_t(t)].assign(size_t(B.m), -1);
     }
-    std::vector<int>& ci = cch[size_t(ch)];
-    std::vector<double>& cv = vch[size_t(ch)];
+  };
+  // pass 1: row i of the product marks its columns with 2 i
+  parallel_rows(A.n, CHM, [&](int t, int, int r0, int r1) {
+    scratch(t);
+    int* mark = marks[size_t(t)].data();
+    for (int i = r0; i < r1; ++i) {
+      int cnt = 0;
+      for (int ka = A.rp[i]; ka < A.rp[i + 1]; ++ka) {
+        const int j = A.ci[ka];
+        for (int kb = B.rp[j]; kb < B.rp[j + 1]; ++kb) {
+          const int c = B.ci[kb];
+          if (mark[c] != 2 * i) {
+            mark[c] = 2 * i;
+            ++cnt;
+          }
+        }
+      }
+      C.rp[i + 1] = cnt;
+    }
+  });
+  for (int i = 0; i < C.n; ++i) C.rp[i + 1] += C.rp[i];
+  C.ci.resize(size_t(C.rp[C.n]));
+  C.v.resize(size_t(C.rp[C.n]));
+  // pass 2: the values, marks 2 i + 1
+  parallel_rows(A.n, CHM, [&](int t, int, int r0, int r1) {
+    scratch(t);
+    double* acc = accs[size_t(t)].data();
+    int* mark = marks[size_t(t)].data();
+    std::vector<int>& cols = colss[size_t(t)];
     for (int i = r0; i < r1; ++i) {
       cols.clear();
       for (int ka = A.rp[i]; ka < A.rp[i + 1]; ++ka) {
@@ -178,8 +206,8 @@ Csr csr_matmul(const Csr& A, const Csr& B) {
         const double a = A.v[ka];
         for (int kb = B.rp[j]; kb < B.rp[j + 1]; ++kb) {
           const int c = B.ci[kb];
-          if (mark[c] != i) {
-            mark[c] = i;
+          if (mark[c] != 2 * i + 1) {
+            mark[c] = 2 * i + 1;
             acc[c] = 0.0;
             cols.push_back(c);
           }
@@ -187,21 +215,68 @@ Csr csr_matmul(const Csr& A, const Csr& B) {
         }
       }
       std::sort(cols.begin(), cols.end());
-      for (int c : cols) {
-        ci.push_back(c);
-        cv.push_back(acc[c]);
+      int* ci = C.ci.data() + C.rp[i];
+      double* cv = C.v.data() + C.rp[i];
+      for (size_t k = 0; k < cols.size(); ++k) {
+        ci[k] = cols[k];
+        cv[k] = acc[cols[k]];
       }
-      C.rp[i + 1] = int(cols.size());
     }
   });
-  for (int i = 0; i < C.n; ++i) C.rp[i + 1] += C.rp[i];
-  C.ci.reserve(size_t(C.rp[C.n]));
-  C.v.reserve(size_t(C.rp[C.n]));
-  for (int ch = 0; ch < nch; ++ch) {
-    C.ci.insert(C.ci.end(), cch[size_t(ch)].begin(), cch[size_t(ch)].end());
-    C.v.insert(C.v.end(), vch[size_t(ch)].begin(), vch[size_t(ch)].end());
-  }
   return C;
+}
+
+Csr csr_matmul(const Csr& A, const Csr& B) { return csr_matmul(A, B, Csr()); }
+
+// C = A B into the rows and columns C already holds (the product of matrices
+// with the same patterns, formed earlier): only the values, in the order of
+// csr_matmul, so they equal its result bit for bit.  Returns false (C's values
+// then undefined) when C has another shape, a term of the product falls
+// outside C's row, or one of C's columns receives none.
+static bool csr_matmul_values(const Csr& A, const Csr& B, Csr& C) {
+  if (C.n != A.n || C.m != B.m || C.rp.size() != size_t(A.n) + 1 || C.ci.size() != size_t(C.rp[C.n]) ||
+      C.v.size() != C.ci.size())
+    return false;
+  const int nt = host_threads(0);
+  std::vector<std::vector<double>> accs(static_cast<size_t>(nt));
+  std::vector<std::vector<int>> marks(static_cast<size_t>(nt));
+  std::atomic<bool> ok{true};
+  parallel_rows(A.n, CHM, [&](int t, int, int r0, int r1) {
+    if (marks[size_t(t)].size() != size_t(B.m)) {
+      accs[size_t(t)].assign(size_t(B.m), 0.0);
+      marks[size_t(t)].assign(size_t(B.m), -1);
+    }
+    double* acc = accs[size_t(t)].data();
+    int* mark = marks[size_t(t)].data();
+    for (int i = r0; i < r1 && ok.load(std::memory_order_relaxed); ++i) {
+      const int c0 = C.rp[i], c1 = C.rp[i + 1];
+      for (int k = c0; k < c1; ++k) mark[C.ci[k]] = 2 * i;  // column of the row, not yet reached
+      int reached = 0;
+      for (int ka = A.rp[i]; ka < A.rp[i + 1]; ++ka) {
+        const int j = A.ci[ka];
+        const double a = A.v[ka];
+        for (int kb = B.rp[j]; kb < B.rp[j + 1]; ++kb) {
+          const int c = B.ci[kb];
+          if (mark[c] != 2 * i + 1) {
+            if (mark[c] != 2 * i) {
+              ok.store(false, std::memory_order_relaxed);
+              return;
+            }
+            mark[c] = 2 * i + 1;
+            acc[c] = 0.0;
+            ++reached;
+          }
+          acc[c] += a * B.v[kb];
+        }
+      }
+      if (reached != c1 - c0) {
+        ok.store(false, std::memory_order_relaxed);
+        return;
+      }
+      for (int k = c0; k < c1; ++k) C.v[k] = acc[C.ci[k]];
+    }
+  });
+  return ok.load();
 }
 
 static std::vector<double> diag_of(const Csr& A) {
@@ -312,14 +387,70 @@ static bool cholesky_inverse(std::vector<double>& a, int n) {
   return true;
 }
 
-static std::vector<double> dense_inverse(const Csr& A) {
+// The same for a matrix whose entries lie within bw of the diagonal: the
+// Cholesky factor stays inside that band, so the factorisation costs about
+// n bw^2 / 2 flops; then, column by column on the worker pool, M = L^{-1} e_j
+// (a banded forward substitution from row j on) and the part i >= j of
+// column j of A^{-1} = L^{-T} M by a banded back substitution stopped at row j
+// (about n^2 bw flops in all, against n^3 for the dense route).
+static bool band_cholesky_inverse(std::vector<double>& a, int n, int bw) {
+  auto at = [&](int i, int j) -> double& { return a[size_t(i) * n + j]; };
+  for (int j = 0; j < n; ++j) {
+    const double* rj = &a[size_t(j) * n];
+    const int k0 = std::max(0, j - bw);
+    double d = at(j, j) - dot4(rj + k0, rj + k0, j - k0);
+    if (!(d > 0.0)) return false;
+    d = std::sqrt(d);
+    at(j, j) = d;
+    const double id = 1.0 / d;
+    const int i1 = std::min(n - 1, j + bw);
+    for (int i = j + 1; i <= i1; ++i) {
+      const int ki = std::max(0, i - bw);  // row i of L starts at column i - bw
+      at(i, j) = (at(i, j) - dot4(&a[size_t(i) * n] + ki, rj + ki, j - ki)) * id;
+    }
+  }
+  // lt[i][t] = L_{i+t, i}: the band of L^T row by row; rd[i] = 1 / L_ii
+  const int W = bw + 1;
+  std::vector<double> lt(size_t(n) * W, 0.0), rd(static_cast<size_t>(n));
+  for (int i = 0; i < n; ++i) {
+    rd[i] = 1.0 / at(i, i);
+    for (int t = 0; t < W && i + t < n; ++t) lt[size_t(i) * W + t] = at(i + t, i);
+  }
+  std::vector<double> m(size_t(n) * n, 0.0), inv(size_t(n) * n);
+  parallel_rows(n, CHD, [&](int, int, int j0, int j1) {
+    for (int j = j0; j < j1; ++j) {
+      double* mj = &m[size_t(j) * n];  // column j of M, rows j .. n-1
+      mj[j] = rd[j];
+      for (int i = j + 1; i < n; ++i) {
+        const int k0 = std::max(j, i - bw);
+        mj[i] = -dot4(&a[size_t(i) * n] + k0, mj + k0, i - k0) * rd[i];
+      }
+      // (A^{-1})_{ij} for i >= j, kept in row j (symmetry) and mirrored into
+      // column j (rows below j: not written by their own row)
+      double* xj = &inv[size_t(j) * n];
+      for (int i = n - 1; i >= j; --i) {
+        const int len = std::min(bw, n - 1 - i);
+        xj[i] = (mj[i] - dot4(&lt[size_t(i) * W + 1], xj + i + 1, len)) * rd[i];
+      }
+      for (int i = j + 1; i < n; ++i) inv[size_t(i) * n + j] = xj[i];
+    }
+  });
+  a.swap(inv);
+  return true;
+}
+
+std::vector<double> dense_inverse(const Csr& A) {
   const int n = A.n;
   std::vector<double> a(static_cast<size_t>(n) * n, 0.0);
+  int bw = 0;
   for (int i = 0; i < n; ++i)
-    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) a[size_t(i) * n + A.ci[k]] += A.v[k];
+    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      a[size_t(i) * n + A.ci[k]] += A.v[k];
+      bw = std::max(bw, std::abs(A.ci[k] - i));
+    }
   {
     std::vector<double> c = a;
-    if (cholesky_inverse(c, n)) return c;
+    if (3 * bw <= n ? band_cholesky_inverse(c, n, bw) : cholesky_inverse(c, n)) return c;
   }
   // not positive definite: Gauss-Jordan with partial pivoting
   std::vector<int> piv(static_cast<size_t>(n));
@@ -500,7 +631,9 @@ AmgHierarchy sa_setup(Csr A1, int max_levels, int coarse_size, double theta, std
     mark("prolongator");
     if (P.m >= A.n * 0.9 || P.m == 0) break;  // stalled coarsening
     Csr R = csr_transpose(P);
-    Csr Ac = csr_matmul(R, csr_matmul(A, P));
+    Csr AP = csr_matmul(A, P);
+    Csr Ac = csr_matmul(R, AP);
+    H.work.push_back(std::move(AP));
     mark("RAP");
     H.P.push_back(std::move(P));
     H.R.push_back(std::move(R));
@@ -516,25 +649,59 @@ AmgHierarchy sa_setup(Csr A1, int max_levels, int coarse_size, double theta, std
   return H;
 }
 
-AmgHierarchy sa_setup_reuse(Csr A1, const AmgHierarchy& prev, std::vector<double>* x0) {
+// a non-const prev gives up its prolongators, restrictions and product arrays
+// (moved, not copied); a const one is copied from
+template <typename Prev>
+static AmgHierarchy reuse_impl(Csr A1, Prev& prev, std::vector<double>* x0) {
+  constexpr bool consume = !std::is_const<Prev>::value;
   auto t0 = std::chrono::steady_clock::now();
   auto mark = [&](const char* what) { sa_mark(t0, what); };
-  if (prev.A.empty() || prev.A[0].n != A1.n)
+  if (prev.A.empty() || prev.A[0].n != A1.n || prev.P.size() + 1 != prev.A.size() ||
+      prev.R.size() != prev.P.size())
     throw Error(DGNP_E_STATE, "aggregation reuse: the vertex level changed size");
+  for (size_t l = 0; l < prev.P.size(); ++l) {
+    const Csr &P = prev.P[l], &R = prev.R[l];
+    if (P.n != prev.A[l].n || P.m != prev.A[l + 1].n || P.rp.size() != size_t(P.n) + 1 || R.n != P.m ||
+        R.m != P.n || R.rp.size() != size_t(R.n) + 1)
+      throw Error(DGNP_E_STATE, "aggregation reuse: the kept hierarchy is incomplete");
+  }
   AmgHierarchy H;
   H.A.push_back(std::move(A1));
   smoother_data(H, H.A.back(), x0 && x0->size() == size_t(H.A[0].n) ? 8 : 20, x0);
   mark("lmax (warm)");
+  // the products A_l P_l and R_l (A_l P_l): values only, into the previous
+  // set-up's arrays, while the vertex graph and with it every pattern is the
+  // same; built afresh otherwise
+  H.work.resize(prev.P.size());
   for (size_t l = 0; l < prev.P.size(); ++l) {
-    H.P.push_back(prev.P[l]);
-    H.R.push_back(prev.R[l]);
-    H.A.push_back(csr_matmul(H.R.back(), csr_matmul(H.A[l], H.P.back())));
+    Csr store;
+    if constexpr (consume) {
+      H.P.push_back(std::move(prev.P[l]));
+      H.R.push_back(std::move(prev.R[l]));
+      store = std::move(prev.A[l + 1]);
+      if (l < prev.work.size()) H.work[l] = std::move(prev.work[l]);
+    } else {
+      H.P.push_back(prev.P[l]);
+      H.R.push_back(prev.R[l]);
+    }
+    Csr& AP = H.work[l];
+    if (!csr_matmul_values(H.A[l], H.P.back(), AP)) AP = csr_matmul(H.A[l], H.P.back(), std::move(AP));
+    if (!csr_matmul_values(H.R.back(), AP, store)) store = csr_matmul(H.R.back(), AP, std::move(store));
+    H.A.push_back(std::move(store));
     smoother_data(H, H.A.back(), 20, nullptr);
   }
   mark("RAP (kept P)");
   H.coarse_inv = dense_inverse(H.A.back());
   mark("coarse inverse");
   return H;
+}
+
+AmgHierarchy sa_setup_reuse(Csr A1, const AmgHierarchy& prev, std::vector<double>* x0) {
+  return reuse_impl(std::move(A1), prev, x0);
+}
+
+AmgHierarchy sa_setup_reuse(Csr A1, AmgHierarchy&& prev, std::vector<double>* x0) {
+  return reuse_impl(std::move(A1), prev, x0);
 }
 
 }  // namespace dgnp

@@ -20,6 +20,7 @@ struct AmgHierarchy {
   std::vector<std::vector<double>> dinv;
   std::vector<double> lmax;   // largest eigenvalue estimate of D^{-1} A per level
   std::vector<double> coarse_inv;  // dense row-major inverse of A.back()
+  std::vector<Csr> work;  // the products A_l P_l, kept for the next set-up
 };
 
 // fn(first row, end row) over chunks of rows [0, n) on the host worker pool
@@ -27,6 +28,12 @@ struct AmgHierarchy {
 void host_parallel_rows(int n, const std::function<void(int, int)>& fn);
 Csr csr_transpose(const Csr& A);
 Csr csr_matmul(const Csr& A, const Csr& B);
+// the same product built in the arrays of `storage` (any earlier matrix)
+Csr csr_matmul(const Csr& A, const Csr& B, Csr&& storage);
+// inverse of a square CSR matrix as a dense row-major array: Cholesky when it is
+// positive definite (banded when its entries lie within a third of the order of
+// the diagonal), else Gauss-Jordan with partial pivoting; throws when singular
+std::vector<double> dense_inverse(const Csr& A);
 // power iterations for the largest eigenvalue of D^{-1} A; x_io (may be null):
 // start vector in (used when its size matches), last vector out
 double lmax_dinvA(const Csr& A, const std::vector<double>& dinv, int iters, std::vector<double>* x_io = nullptr);
@@ -37,5 +44,8 @@ AmgHierarchy sa_setup(Csr A1, int max_levels, int coarse_size, double theta,
 // prolongators of prev kept: only the Galerkin products, smoother data and
 // coarse inverse are recomputed; the finest estimate warm-starts from x0
 AmgHierarchy sa_setup_reuse(Csr A1, const AmgHierarchy& prev, std::vector<double>* x0);
+// the same, taking prev's prolongators and product arrays instead of copying
+// them (prev is left without a usable hierarchy)
+AmgHierarchy sa_setup_reuse(Csr A1, AmgHierarchy&& prev, std::vector<double>* x0);
 
 }  // namespace dgnp

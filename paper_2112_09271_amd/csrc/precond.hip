@@ -27,11 +27,18 @@
 
 namespace dgnp {
 
+// A device CSR matrix; its row pointers and column indices may be another
+// matrix's (rpx, cix not null: the single-precision copy of a level shares the
+// double copy's index arrays)
 template <typename T>
 struct DevCsr {
   int n = 0;
   DevBuf<int> rp, ci;
   DevBuf<T> v;
+  const int* rpx = nullptr;
+  const int* cix = nullptr;
+  const int* rptr() const { return rpx ? rpx : rp.p; }
+  const int* cptr() const { return cix ? cix : ci.p; }
 };
 
 struct MgLevel {  // scalar levels (index >= 1 in the V-cycle)
@@ -82,13 +89,20 @@ struct PinnedStage {
     used += bytes;
     return r;
   }
-  // dst = (T) src[0..n), asynchronously on s
+  // dst = (T) src[0..n), asynchronously on s (large arrays are staged by row
+  // chunks on the host worker pool)
   template <typename T, typename S>
   void upload(DevBuf<T>& dst, const S* src, size_t n, hipStream_t s) {
     dst.fit(n);
     if (n == 0) return;
     T* h = static_cast<T*>(take(n * sizeof(T)));
-    for (size_t i = 0; i < n; ++i) h[i] = T(src[i]);
+    if (n >= (size_t(1) << 20) && n < (size_t(1) << 31)) {
+      host_parallel_rows(int(n), [&](int i0, int i1) {
+        for (int i = i0; i < i1; ++i) h[i] = T(src[i]);
+      });
+    } else {
+      for (size_t i = 0; i < n; ++i) h[i] = T(src[i]);
+    }
     DGNP_HIP(hipMemcpyAsync(dst.p, h, n * sizeof(T), hipMemcpyHostToDevice, s));
   }
 };
@@ -173,7 +187,6 @@ struct Precond {
   int64_t nvert = 0;
   DevBuf<double> gal;
   DevBuf<double> vst;               // [nvert][3^d] vertex stencil of the Galerkin operator
-  std::vector<double> st_host;      // its host copy
   std::vector<MgLevel> mg;          // mg[0] = vertex level
   DevBuf<double> cinv;
   DevBuf<float> cinv32;
@@ -597,12 +610,23 @@ static Csr vertex_matrix(const dgnp_ctx& c, const Precond& P, const double* st, 
   return A;
 }
 
-template <typename T>
-static void upload_csr(DevCsr<T>& D, const Csr& A, PinnedStage& st, hipStream_t s) {
+static void upload_csr(DevCsr<double>& D, const Csr& A, PinnedStage& st, hipStream_t s) {
   D.n = A.n;
   st.upload(D.rp, A.rp.data(), A.rp.size(), s);
   st.upload(D.ci, A.ci.data(), A.ci.size(), s);
   st.upload(D.v, A.v.data(), A.v.size(), s);
+}
+
+// single-precision copy of a device matrix: its values converted on the
+// device, its index arrays those of the double copy
+static void copy_csr32(DevCsr<float>& D, const DevCsr<double>& A, hipStream_t s) {
+  D.n = A.n;
+  D.rp.release();
+  D.ci.release();
+  D.rpx = A.rptr();
+  D.cix = A.cptr();
+  D.v.alloc(A.v.n);
+  cvt_d2f(A.v.p, D.v.p, int64_t(A.v.n), s);
 }
 
 // per V-cycle level: 5 vectors (x, b, r, d, z) for each precision; arrays of
@@ -879,6 +903,10 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
   // starts first
   const bool split = phi && conc && !assemble_only;
   const bool conc_first = split && c.nb >= 64;
+  // with a large vertex grid the host hierarchy is the longest part of the
+  // set-up: the concentration part is then queued behind the kernels of the
+  // vertex stencil the host waits for
+  const bool conc_late = split && !conc_first && P.nvert >= (int64_t(1) << 16);
   if (!split) {
     ScopeTimer tm(c, "assemble", s);
     const int f0 = phi ? 0 : 1, f1 = conc ? c.m : 1;
@@ -947,7 +975,7 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
       ScopeTimer tm(c, "assemble", s);
       launch_assemble(c.dim, c.p, c.m, 0, 1, c.kargs(), c.d_x.p, P.blk.p, s);
     }
-    if (!conc_first) conc_part();
+    if (!conc_first && !conc_late) conc_part();
   }
   if (phi) {
     // potential block: element-diagonal inverses (block-Jacobi smoother)
@@ -1001,10 +1029,11 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     launch_q1_galerkin(c.dim, gal_p, c.E, gal_blk, P.gal.p, s);
     P.vst.alloc(size_t(P.nvert) * (c.dim == 3 ? 27 : 9));
     launch_vertex_stencil(c.dim, P.gal.p, c.d_nbr.p, c.n, P.nvert, P.vst.p, s);
-    // the stencil comes back into a host array kept between set-ups (mapped
-    // once: a fresh array of this size costs its page faults at every set-up)
-    P.st_host.resize(P.vst.n);
-    double* st = P.st_host.data();
+    if (conc_late) conc_part();
+    // the stencil comes back into the pinned staging memory (kept between
+    // set-ups: a copy into pageable memory goes through the runtime's bounce
+    // buffer, and a fresh array of this size costs its page faults every time)
+    double* st = static_cast<double*>(P.stage.take(P.vst.n * sizeof(double)));
     DGNP_HIP(hipMemcpyAsync(st, P.vst.p, P.vst.n * sizeof(double), hipMemcpyDeviceToHost, s));
     DGNP_HIP(hipStreamSynchronize(s));
     clk.mark("galerkin + stencil");
@@ -1055,10 +1084,13 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
           storage.v = std::move(P.sa_prev.A[0].v);
         }
         Csr A1 = vertex_matrix(c, P, st, std::move(storage));
-        H = reuse ? sa_setup_reuse(std::move(A1), P.sa_prev, &P.sa_x0)
+        // the kept hierarchy gives up its prolongators and product arrays
+        H = reuse ? sa_setup_reuse(std::move(A1), std::move(P.sa_prev), &P.sa_x0)
                   : sa_setup(std::move(A1), 12, 256, 0.0, &P.sa_x0);
+        if (reuse) P.sa_prev = AmgHierarchy();  // taken apart; H replaces it below
       } catch (...) {
         sa_err = std::current_exception();
+        P.sa_prev = AmgHierarchy();  // possibly taken apart: the next set-up starts afresh
       }
     });
     struct Joiner {
@@ -1097,18 +1129,25 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     clk.mark("lmax level 0");
     sa_thread.join();
     if (sa_err) std::rethrow_exception(sa_err);
+    // kept again only once this hierarchy's uploads are queued: a set-up that
+    // fails from here on leaves none, and the next one starts afresh
+    P.sa_prev = AmgHierarchy();
     clk.mark(reuse ? "vertex matrix + sa setup (prolongators kept)" : "vertex matrix + sa setup");
     if (trace_setup()) {
       fprintf(stderr, "[setup] hierarchy: DG %lld", (long long)c.Nf);
       for (auto& A : H.A) fprintf(stderr, " -> %d (nnz %zu)", A.n, A.v.size());
       fprintf(stderr, "\n");
     }
+    // with the prolongators kept, the device already holds them: the
+    // hierarchy they came from was uploaded in full by the previous set-up
+    // (it is kept only once its uploads are queued)
+    const bool keep_pr = reuse && P.mg.size() == H.A.size();
     P.mg.resize(H.A.size());  // device arrays of equal size are reused
     for (size_t l = 0; l < H.A.size(); ++l) {
       MgLevel& L = P.mg[l];
       L.n = H.A[l].n;
       upload_csr(L.A, H.A[l], P.stage, s);
-      if (l + 1 < H.A.size()) {
+      if (l + 1 < H.A.size() && !keep_pr) {
         upload_csr(L.P, H.P[l], P.stage, s);
         upload_csr(L.R, H.R[l], P.stage, s);
       }
@@ -1121,16 +1160,19 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
     ensure_work(c, P);
     clk.mark("work vectors");
     if (f32) {
+      // single-precision copies converted on the device from the double ones
       for (size_t l = 0; l < H.A.size(); ++l) {
         MgLevel& L = P.mg[l];
-        upload_csr(L.A32, H.A[l], P.stage, s);
+        copy_csr32(L.A32, L.A, s);
         if (l + 1 < H.A.size()) {
-          upload_csr(L.P32, H.P[l], P.stage, s);
-          upload_csr(L.R32, H.R[l], P.stage, s);
+          copy_csr32(L.P32, L.P, s);
+          copy_csr32(L.R32, L.R, s);
         }
-        P.stage.upload(L.dinv32, H.dinv[l].data(), H.dinv[l].size(), s);
+        L.dinv32.alloc(L.dinv.n);
+        cvt_d2f(L.dinv.p, L.dinv32.p, int64_t(L.dinv.n), s);
       }
-      P.stage.upload(P.cinv32, H.coarse_inv.data(), H.coarse_inv.size(), s);
+      P.cinv32.alloc(P.cinv.n);
+      cvt_d2f(P.cinv.p, P.cinv32.p, int64_t(P.cinv.n), s);
       ensure_work32(c, P);
       clk.mark("float copies (phi)");
     }
@@ -1209,9 +1251,9 @@ struct Mg {
       }
     } else {
       DevCsr<T>& M = Sel<T>::A(csr(l));
-      launch_csr_spmv<T>(M.n, M.rp.p, M.ci.p, M.v.p, x, b, T(-1), T(1), r, s);
+      launch_csr_spmv<T>(M.n, M.rptr(), M.cptr(), M.v.p, x, b, T(-1), T(1), r, s);
       DevCsr<T>& R = Sel<T>::R(csr(l));
-      launch_csr_spmv<T>(R.n, R.rp.p, R.ci.p, R.v.p, r, nullptr, T(1), T(0), rc, s, int64_t(R.v.n));
+      launch_csr_spmv<T>(R.n, R.rptr(), R.cptr(), R.v.p, r, nullptr, T(1), T(0), rc, s, int64_t(R.v.n));
     }
   }
   void prolong_add(int l, const T* xc, T* x) {
@@ -1221,7 +1263,7 @@ struct Mg {
       launch_q1<T>(true, c.dim, bp(), c.n, xc, x, T(1), c.E, P.nvert, s);
     } else {
       DevCsr<T>& Pm = Sel<T>::Pm(csr(l));
-      launch_csr_spmv<T>(Pm.n, Pm.rp.p, Pm.ci.p, Pm.v.p, xc, x, T(1), T(1), x, s);
+      launch_csr_spmv<T>(Pm.n, Pm.rptr(), Pm.cptr(), Pm.v.p, xc, x, T(1), T(1), x, s);
     }
   }
   // one fused Chebyshev step on level l (see launch_cheb_blk)
@@ -1243,7 +1285,7 @@ struct Mg {
                          T(c2), r_out, d_out, x_out, s);
     } else {
       DevCsr<T>& M = Sel<T>::A(csr(l));
-      launch_cheb_csr<T>(M.n, M.rp.p, M.ci.p, M.v.p, Sel<T>::ldinv(csr(l)), u, base, dprev, x_in, T(c1), T(c2),
+      launch_cheb_csr<T>(M.n, M.rptr(), M.cptr(), M.v.p, Sel<T>::ldinv(csr(l)), u, base, dprev, x_in, T(c1), T(c2),
                          r_out, d_out, x_out, s);
     }
   }

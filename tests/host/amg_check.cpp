@@ -4,6 +4,7 @@
 // bitwise-identical hierarchies across repeated runs, and the set-up that
 // keeps an earlier hierarchy's prolongators.  Prints "ok" and
 // returns 0, or names the failed check and returns 1.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -140,6 +141,118 @@ int main() {
       threw = true;
     }
     if (!threw) return fail("reuse: a vertex level of another size must be refused");
+  }
+  // the reuse that takes over the previous hierarchy (prolongators moved, the
+  // products formed into its arrays, values only while the patterns agree)
+  // gives the copying reuse's hierarchy, kept products included, bit for bit:
+  // twice in a row, then for a matrix of a smaller pattern (one symmetric pair
+  // of entries removed: a row of A P loses a column) and back (it gains one),
+  // where its products are rebuilt
+  {
+    auto same = [](const dgnp::AmgHierarchy& a, const dgnp::AmgHierarchy& b) {
+      if (a.A.size() != b.A.size() || a.lmax != b.lmax || a.coarse_inv != b.coarse_inv) return false;
+      for (size_t l = 0; l < a.A.size(); ++l)
+        if (a.A[l].v != b.A[l].v || a.A[l].ci != b.A[l].ci || a.A[l].rp != b.A[l].rp) return false;
+      if (a.work.size() != b.work.size()) return false;
+      for (size_t l = 0; l < a.work.size(); ++l)
+        if (a.work[l].v != b.work[l].v || a.work[l].ci != b.work[l].ci || a.work[l].rp != b.work[l].rp)
+          return false;
+      return true;
+    };
+    Csr A2 = A, A3 = A, A4;
+    for (double& v : A2.v) v *= 2.0;
+    for (int i = 0; i < A3.n; ++i)
+      for (int k = A3.rp[i]; k < A3.rp[i + 1]; ++k)
+        if (A3.ci[k] == i) A3.v[k] += 0.5;
+    {
+      const int r0 = 0, r1 = 1;  // drop the coupling of rows 0 and 1
+      A4.n = A4.m = A.n;
+      A4.rp.push_back(0);
+      for (int i = 0; i < A.n; ++i) {
+        for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+          const int j = A.ci[k];
+          if ((i == r0 && j == r1) || (i == r1 && j == r0)) continue;
+          A4.ci.push_back(j);
+          A4.v.push_back(A.v[k]);
+        }
+        A4.rp.push_back(int(A4.ci.size()));
+      }
+    }
+    std::vector<double> xa, xb;
+    dgnp::AmgHierarchy Hc = dgnp::sa_setup(A, 12, 256, 0.0, &xa);
+    xb = xa;
+    dgnp::AmgHierarchy Hm = Hc;
+    dgnp::AmgHierarchy R1 = dgnp::sa_setup_reuse(A2, Hc, &xa);
+    dgnp::AmgHierarchy M1 = dgnp::sa_setup_reuse(A2, std::move(Hm), &xb);
+    if (!same(R1, M1) || xa != xb) return fail("consuming reuse differs (first call)");
+    dgnp::AmgHierarchy R2 = dgnp::sa_setup_reuse(A3, R1, &xa);
+    dgnp::AmgHierarchy M2 = dgnp::sa_setup_reuse(A3, std::move(M1), &xb);
+    if (!same(R2, M2) || xa != xb) return fail("consuming reuse differs (second call)");
+    dgnp::AmgHierarchy R3 = dgnp::sa_setup_reuse(A4, R2, &xa);
+    dgnp::AmgHierarchy M3 = dgnp::sa_setup_reuse(A4, std::move(M2), &xb);
+    if (!same(R3, M3) || xa != xb) return fail("consuming reuse differs (pattern changed)");
+    if (R3.A[0].rp[R3.A[0].n] != A.rp[A.n] - 2) return fail("pattern change not taken");
+    if (R3.work[0].rp[R3.work[0].n] == R2.work[0].rp[R2.work[0].n]) return fail("A P kept its pattern");
+    dgnp::AmgHierarchy R4 = dgnp::sa_setup_reuse(A, R3, &xa);
+    dgnp::AmgHierarchy M4 = dgnp::sa_setup_reuse(A, std::move(M3), &xb);
+    if (!same(R4, M4) || xa != xb) return fail("consuming reuse differs (pattern restored)");
+  }
+  // the inverse of the coarsest level: banded Cholesky (entries within a third
+  // of the order of the diagonal: the 7-point Laplacian of a 7^3 grid plus a
+  // shift, bandwidth 49 of 343), the dense Cholesky for the same matrix with
+  // its unknowns reversed in pairs of halves (a band of about the order), and
+  // Gauss-Jordan for an indefinite banded matrix; each A^{-1} A = I to 1e-12,
+  // and the two Cholesky routes give the same inverse up to the renumbering
+  {
+    Csr L = laplace3d(7);
+    for (int i = 0; i < L.n; ++i)
+      for (int k = L.rp[i]; k < L.rp[i + 1]; ++k)
+        if (L.ci[k] == i) L.v[k] += 0.25;
+    const int n = L.n, h = n / 2;
+    auto perm = [&](int i) { return i < h ? h - 1 - i + (n - h) : i - h; };  // a bijection of 0..n-1
+    Csr Lp;
+    Lp.n = Lp.m = n;
+    {
+      std::vector<std::vector<std::pair<int, double>>> rows(static_cast<size_t>(n));
+      for (int i = 0; i < n; ++i)
+        for (int k = L.rp[i]; k < L.rp[i + 1]; ++k) rows[size_t(perm(i))].push_back({perm(L.ci[k]), L.v[k]});
+      Lp.rp.push_back(0);
+      for (auto& r : rows) {
+        std::sort(r.begin(), r.end());
+        for (auto& e : r) {
+          Lp.ci.push_back(e.first);
+          Lp.v.push_back(e.second);
+        }
+        Lp.rp.push_back(int(Lp.ci.size()));
+      }
+    }
+    Csr Li = L;  // indefinite: a large negative shift
+    for (int i = 0; i < n; ++i)
+      for (int k = Li.rp[i]; k < Li.rp[i + 1]; ++k)
+        if (Li.ci[k] == i) Li.v[k] -= 6.0;
+    auto identity_err = [](const Csr& M, const std::vector<double>& inv) {
+      const int n = M.n;
+      std::vector<double> d = dense(M);
+      double err = 0.0;
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          double s = 0.0;
+          for (int k = 0; k < n; ++k) s += inv[size_t(i) * n + k] * d[size_t(k) * n + j];
+          err = std::fmax(err, std::fabs(s - (i == j ? 1.0 : 0.0)));
+        }
+      return err;
+    };
+    std::vector<double> ib = dgnp::dense_inverse(L), id = dgnp::dense_inverse(Lp), ii = dgnp::dense_inverse(Li);
+    if (identity_err(L, ib) > 1e-12) return fail("banded Cholesky inverse");
+    if (identity_err(Lp, id) > 1e-12) return fail("dense Cholesky inverse");
+    if (identity_err(Li, ii) > 1e-12) return fail("Gauss-Jordan inverse of an indefinite matrix");
+    double dmax = 0.0, imax = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        dmax = std::fmax(dmax, std::fabs(ib[size_t(i) * n + j] - id[size_t(perm(i)) * n + perm(j)]));
+        imax = std::fmax(imax, std::fabs(ib[size_t(i) * n + j]));
+      }
+    if (dmax > 1e-13 * imax) return fail("banded and dense Cholesky inverses differ");
   }
   // checksum of every value of the hierarchy (bit patterns), to compare runs
   uint64_t h = 1469598103934665603ull;
