@@ -60,7 +60,7 @@ struct AsmPairs {
 };
 
 template <int DIM, int P, int MF>
-__global__ void __launch_bounds__(BT)
+__global__ void __launch_bounds__(BT, P == 2 ? 3 : 1)
     k_assemble(KArgs A, const double* __restrict__ xs, double* __restrict__ blk, int f0) {
   using S = Sz<DIM, P>;
   using PR = AsmPairs<DIM>;
