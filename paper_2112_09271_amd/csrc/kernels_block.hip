@@ -41,6 +41,12 @@ static constexpr int BT = 256;  // threads per block kernel
 // two tangential directions.  2-D problems run the same code with a third
 // direction of one node and one point.
 // ===========================================================================
+// a0, a1 or a2 by a run-time index d (selects, not an indexed array)
+template <typename T>
+__device__ __forceinline__ T sel3(T a0, T a1, T a2, int d) {
+  return d == 0 ? a0 : (d == 1 ? a1 : a2);
+}
+
 template <int DIM>
 struct AsmPairs {
   static constexpr int NC = DIM + 1;
@@ -60,7 +66,7 @@ struct AsmPairs {
 };
 
 template <int DIM, int P, int MF>
-__global__ void __launch_bounds__(BT, P == 2 ? 3 : 1)
+__global__ void __launch_bounds__(BT, P >= 2 ? 3 : 1)
     k_assemble(KArgs A, const double* __restrict__ xs, double* __restrict__ blk, int f0) {
   using S = Sz<DIM, P>;
   using PR = AsmPairs<DIM>;
@@ -77,14 +83,29 @@ __global__ void __launch_bounds__(BT, P == 2 ? 3 : 1)
   constexpr int Y1K = NN2 * NQ * Q3;   // per key: [q3][q2][i1 j1]
   constexpr int Y2G = NN2 * NN2 * Q3;  // per third-direction type: [q3][i2 j2][i1 j1]
   constexpr int VOL1 = NKMAX * Y1K;
-  constexpr int VOL2A = QV + S1 + S2 + NCB * NQV;
-  constexpr int VOL2B = 4 * Y2G;
-  constexpr int VOLR = VOL1 + (VOL2A > VOL2B ? VOL2A : VOL2B);
+  // LDS of the volume part, by lifetime: M (pointwise coefficients) from the
+  // pointwise step to direction 1; the interpolation temporaries before it
+  // (above M); Y1 from direction 1 to the last direction-2 pass (over the
+  // temporaries); Y2 over M.  At order 3 Y2 holds one third-direction type at
+  // a time (the LDS then admits three work-groups per CU), below it every type
+  // at once (fewer barriers; LDS is not the limit there)
+  constexpr bool Y2ONE = P >= 3;
+  constexpr int Y2SZ = Y2ONE ? Y2G : 4 * Y2G;
+  constexpr int MSZ = NCB * NQV;
+  constexpr int OY1 = MSZ > Y2SZ ? MSZ : Y2SZ;
+  // loop unrolling of the face slots: at order 3 one slot at a time and two
+  // block entries per step, which keeps the registers within three
+  // work-groups per CU
+  constexpr int UNR_SLOT = Y2ONE ? 1 : 2 * DIM;
+  constexpr int UNR_ENT = Y2ONE ? 2 : (NB * NB + BT - 1) / BT;
+  constexpr int VOLA = MSZ + QV + S1 + S2, VOLB = OY1 + VOL1;
+  constexpr int VOLR = VOLA > VOLB ? VOLA : VOLB;
   constexpr int NFACE = 2 * DIM;
   constexpr int NROWF = NFACE * 2 * MF * 2;  // face trace rows: face, side (own / neighbour), field, value / dn
   constexpr int ZSZ = 8 * NN2 * Q3;
   constexpr int CSZ = 8 * NN2 * N3 * N3;
-  constexpr int FACR = NROWF * (NFN + NQF) + NFACE * NQF * 8 + ZSZ + CSZ;
+  constexpr int TRS = NROWF * (NFN + NQF);
+  constexpr int FACR = NFACE * NQF * 8 + (TRS > ZSZ + CSZ ? TRS : ZSZ + CSZ);
   constexpr int REG = VOLR > FACR ? VOLR : FACR;
   constexpr int ENT = (NB * NB + BT - 1) / BT;
   constexpr int NSLOT = 2 * DIM + 1;
@@ -119,12 +140,12 @@ __global__ void __launch_bounds__(BT, P == 2 ? 3 : 1)
   for (int k = 0; k < ENT; ++k) acc[k] = 0.0;
   // ---- volume
   {
-    double* Y1 = R;
-    double* q_x = R + VOL1;
+    double* M = R;  // M[c][q]
+    double* q_x = R + MSZ;
     double* t1 = q_x + QV;
     double* t2 = t1 + S1;
-    double* M = t2 + S2;  // M[c][q]
-    double* Y2 = R + VOL1;
+    double* Y1 = R + OY1;
+    double* Y2 = R;
     interp<DIM, P, MF, BT, double>(s_x, q_x, t1, t2, tb, ih, tid);
     for (int qi = tid; qi < NQV; qi += BT) {
       const int qc[3] = {qi % NQ, (qi / NQ) % NQ, qi / (NQ * NQ)};
@@ -200,41 +221,76 @@ __global__ void __launch_bounds__(BT, P == 2 ? 3 : 1)
     }
     __syncthreads();
     // direction 2: Y2[t3][q3][i2 j2][i1 j1] = sum_{keys with t3} sum_q2 G_t2(q2, i2, j2) Y1[key][q3][q2][i1 j1]
-    for (int o = tid; o < n3 * Y2G; o += BT) {
-      const int gg = o / Y2G, r = o % Y2G;
-      const int ij1 = r % NN2, ij2 = (r / NN2) % NN2, q3 = r / (NN2 * NN2);
-      const int t3 = s_t3[gg];
-      double s = 0.0;
-      for (int kk = 0; kk < nk; ++kk) {
-        const int key = s_keys[kk];
-        if ((key >> 2) != t3) continue;
-        const double* g = G + (key & 3) * NQ * NN2 + ij2;
-        const double* y = Y1 + kk * Y1K + q3 * NQ * NN2 + ij1;
-#pragma unroll
-        for (int q2 = 0; q2 < NQ; ++q2) s += g[q2 * NN2] * y[q2 * NN2];
-      }
-      Y2[o] = s;
-    }
-    __syncthreads();
-    // direction 3: A_ij = sum_t3 sum_q3 G_t3(q3, i3, j3) Y2[t3][q3][i2 j2][i1 j1]
-    for (int k = 0; k < ENT; ++k) {
-      const int idx = tid + k * BT;
-      if (idx >= NB * NB) break;
-      const int i = idx / NB, j = idx % NB;
-      const int i1 = i % NN, i2 = (i / NN) % NN, i3 = i / NN2;
-      const int j1 = j % NN, j2 = (j / NN) % NN, j3 = j / NN2;
-      const double* y = Y2 + (i2 * NN + j2) * NN2 + i1 * NN + j1;
-      double s = 0.0;
+    if constexpr (Y2ONE) {
       for (int gg = 0; gg < n3; ++gg) {
         const int t3 = s_t3[gg];
-        for (int q3 = 0; q3 < Q3; ++q3) {
-          const double g = DIM == 3 ? G[((t3 * NQ + q3) * NN + i3) * NN + j3] : 1.0;
-          s += g * y[gg * Y2G + q3 * NN2 * NN2];
+        for (int o = tid; o < Y2G; o += BT) {
+          const int ij1 = o % NN2, ij2 = (o / NN2) % NN2, q3 = o / (NN2 * NN2);
+          double s = 0.0;
+          for (int kk = 0; kk < nk; ++kk) {
+            const int key = s_keys[kk];
+            if ((key >> 2) != t3) continue;
+            const double* g = G + (key & 3) * NQ * NN2 + ij2;
+            const double* y = Y1 + kk * Y1K + q3 * NQ * NN2 + ij1;
+  #pragma unroll
+            for (int q2 = 0; q2 < NQ; ++q2) s += g[q2 * NN2] * y[q2 * NN2];
+          }
+          Y2[o] = s;
         }
+        __syncthreads();
+        for (int k = 0; k < ENT; ++k) {
+          const int idx = tid + k * BT;
+          if (idx >= NB * NB) break;
+          const int i = idx / NB, j = idx % NB;
+          const int i1 = i % NN, i2 = (i / NN) % NN, i3 = i / NN2;
+          const int j1 = j % NN, j2 = (j / NN) % NN, j3 = j / NN2;
+          const double* y = Y2 + (i2 * NN + j2) * NN2 + i1 * NN + j1;
+          double s = acc[k];
+          for (int q3 = 0; q3 < Q3; ++q3) {
+            const double g = DIM == 3 ? G[((t3 * NQ + q3) * NN + i3) * NN + j3] : 1.0;
+            s += g * y[q3 * NN2 * NN2];
+          }
+          acc[k] = s;
+        }
+        __syncthreads();
       }
-      acc[k] = s;
+    } else {
+      // every type at once: Y2[t3][q3][i2 j2][i1 j1], then A_ij = sum_t3 sum_q3 G_t3(q3, i3, j3) Y2[t3]..
+      for (int o = tid; o < n3 * Y2G; o += BT) {
+        const int gg = o / Y2G, r = o % Y2G;
+        const int ij1 = r % NN2, ij2 = (r / NN2) % NN2, q3 = r / (NN2 * NN2);
+        const int t3 = s_t3[gg];
+        double s = 0.0;
+        for (int kk = 0; kk < nk; ++kk) {
+          const int key = s_keys[kk];
+          if ((key >> 2) != t3) continue;
+          const double* g = G + (key & 3) * NQ * NN2 + ij2;
+          const double* y = Y1 + kk * Y1K + q3 * NQ * NN2 + ij1;
+#pragma unroll
+          for (int q2 = 0; q2 < NQ; ++q2) s += g[q2 * NN2] * y[q2 * NN2];
+        }
+        Y2[o] = s;
+      }
+      __syncthreads();
+      for (int k = 0; k < ENT; ++k) {
+        const int idx = tid + k * BT;
+        if (idx >= NB * NB) break;
+        const int i = idx / NB, j = idx % NB;
+        const int i1 = i % NN, i2 = (i / NN) % NN, i3 = i / NN2;
+        const int j1 = j % NN, j2 = (j / NN) % NN, j3 = j / NN2;
+        const double* y = Y2 + (i2 * NN + j2) * NN2 + i1 * NN + j1;
+        double s = 0.0;
+        for (int gg = 0; gg < n3; ++gg) {
+          const int t3 = s_t3[gg];
+          for (int q3 = 0; q3 < Q3; ++q3) {
+            const double g = DIM == 3 ? G[((t3 * NQ + q3) * NN + i3) * NN + j3] : 1.0;
+            s += g * y[gg * Y2G + q3 * NN2 * NN2];
+          }
+        }
+        acc[k] = s;
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 
   // ---- faces
@@ -244,10 +300,10 @@ __global__ void __launch_bounds__(BT, P == 2 ? 3 : 1)
   // FC: the pointwise face Jacobian for every (face, point, trial direction),
   //     Mf[face][qf][test value / dn][trial: own v, own g, nb v, nb g];
   // then, face by face, the tangential contractions and the expansion below.
-  double* fnod = R;                              // [NROWF][NFN]
+  double* MfA = R;                               // [NFACE][NQF][8]
+  double* fnod = MfA + NFACE * NQF * 8;          // [NROWF][NFN]
   double* fq = fnod + NROWF * NFN;               // [NROWF][NQF]
-  double* MfA = fq + NROWF * NQF;                // [NFACE][NQF][8]
-  double* Z = MfA + NFACE * NQF * 8;             // [8][q2][i1 j1]
+  double* Z = fnod;                              // [8][q2][i1 j1]
   double* Cf = Z + ZSZ;                          // [8][i2 j2][i1 j1]
   double* out = blk + ((int64_t(f) * A.E + e) * NSLOT) * NB * NB;
   {
@@ -272,7 +328,7 @@ __global__ void __launch_bounds__(BT, P == 2 ? 3 : 1)
           dn += De[l] * x;
           if (l == (sside < 0 ? 0 : P)) val = x;
         }
-        dn *= ih[ax];
+        dn *= sel3(ih[0], ih[1], ih[2], ax);
       }
       fnod[(2 * pr + 0) * NFN + ij] = val;
       fnod[(2 * pr + 1) * NFN + ij] = dn;
@@ -320,28 +376,37 @@ __global__ void __launch_bounds__(BT, P == 2 ? 3 : 1)
       const int t1ax = DIM == 3 ? (ax == 0 ? 1 : 0) : 1 - ax;
       const int t2ax = DIM == 3 ? (ax == 2 ? 1 : 2) : 0;
       const int qi = qf % NQ, qj = qf / NQ;
+      // the face point: the face's coordinate along ax, Gauss points along
+      // the tangential axes (every array index fixed at compile time: arrays
+      // indexed by a run-time axis would live in scratch memory)
       double xp[3];
-      xp[ax] = A.lo[ax] + (eid[ax] + (side > 0 ? 1.0 : 0.0)) * A.h[ax];
-      xp[t1ax] = A.lo[t1ax] + (eid[t1ax] + 0.5 * (tb.X[qi] + 1.0)) * A.h[t1ax];
-      double w = 0.5 * A.h[t1ax] * tb.W[qi];
-      if constexpr (DIM == 3) {
-        xp[t2ax] = A.lo[t2ax] + (eid[t2ax] + 0.5 * (tb.X[qj] + 1.0)) * A.h[t2ax];
-        w *= 0.5 * A.h[t2ax] * tb.W[qj];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double ed = d < DIM ? double(eid[d]) : 0.0;
+        const double xd = d == ax ? (side > 0 ? 1.0 : 0.0) : 0.5 * (tb.X[d == t1ax ? qi : qj] + 1.0);
+        xp[d] = d < DIM ? A.lo[d] + (ed + xd) * A.h[d] : 0.0;
       }
+      const double ihx = sel3(ih[0], ih[1], ih[2], ax);
+      double w = 0.5 * sel3(A.h[0], A.h[1], A.h[2], t1ax) * tb.W[qi];
+      if constexpr (DIM == 3) w *= 0.5 * sel3(A.h[0], A.h[1], A.h[2], t2ax) * tb.W[qj];
       double uh[3];
       velocity_hat(A, xp, DIM, uh);
+      const double uax = sel3(uh[0], uh[1], uh[2], ax);
       double fo = 0.0, go = 0.0;
       if (interior) {
-        const double un = A.Pe * uh[ax];
+        const double un = A.Pe * uax;
         const int own = side > 0 ? 0 : 1;
         double v[2][MF], g[2][MF], tv[2][MF], tg[2][MF];
         const int sdb = beta < 2 ? own : 1 - own;
 #pragma unroll
         for (int c = 0; c < MF; ++c) {
-          v[own][c] = fq[trow(fc, 0, c, 0) * NQF + qf];
-          g[own][c] = fq[trow(fc, 0, c, 1) * NQF + qf];
-          v[1 - own][c] = fq[trow(fc, 1, c, 0) * NQF + qf];
-          g[1 - own][c] = fq[trow(fc, 1, c, 1) * NQF + qf];
+          // own side first when it is the minus side (selects: see above)
+          const double vo = fq[trow(fc, 0, c, 0) * NQF + qf], go_ = fq[trow(fc, 0, c, 1) * NQF + qf];
+          const double vn = fq[trow(fc, 1, c, 0) * NQF + qf], gn = fq[trow(fc, 1, c, 1) * NQF + qf];
+          v[0][c] = own == 0 ? vo : vn;
+          v[1][c] = own == 0 ? vn : vo;
+          g[0][c] = own == 0 ? go_ : gn;
+          g[1][c] = own == 0 ? gn : go_;
 #pragma unroll
           for (int s2 = 0; s2 < 2; ++s2) {
             tv[s2][c] = (s2 == sdb && c == f && beta % 2 == 0) ? 1.0 : 0.0;
@@ -355,9 +420,9 @@ __global__ void __launch_bounds__(BT, P == 2 ? 3 : 1)
           fo = c == f ? Fo[c] : fo;
           go = c == f ? Go[c] : go;
         }
-        const double sb = (beta % 2 == 0) ? 1.0 : ih[ax];
+        const double sb = (beta % 2 == 0) ? 1.0 : ihx;
         M[0 * 4 + beta] = fo * w * sb;
-        M[1 * 4 + beta] = go * w * sb * ih[ax];
+        M[1 * 4 + beta] = go * w * sb * ihx;
       } else {
         int64_t lin;
         if constexpr (DIM == 3)
@@ -366,7 +431,7 @@ __global__ void __launch_bounds__(BT, P == 2 ? 3 : 1)
         else
           lin = ax == 0 ? eid[1] : eid[0];
         const int64_t bf = A.btag_off[fc] + lin;
-        const double un = side * A.Pe * uh[ax];
+        const double un = side * A.Pe * uax;
         double v[MF], g[MF], gd[MF], tv[MF], tg[MF];
 #pragma unroll
         for (int c = 0; c < MF; ++c) {
@@ -383,13 +448,14 @@ __global__ void __launch_bounds__(BT, P == 2 ? 3 : 1)
           fo = c == f ? Fo[c] : fo;
           go = c == f ? Go[c] : go;
         }
-        const double sb = beta == 0 ? 1.0 : side * ih[ax];
+        const double sb = beta == 0 ? 1.0 : side * ihx;
         M[0 * 4 + beta] = fo * w * sb;
-        M[1 * 4 + beta] = go * w * sb * side * ih[ax];
+        M[1 * 4 + beta] = go * w * sb * side * ihx;
       }
     }
     __syncthreads();
   }
+#pragma unroll UNR_SLOT
   for (int slot = 0; slot < 2 * DIM; ++slot) {
     const int ax = slot >> 1, side = (slot & 1) ? 1 : -1;
     const int nb = A.nbr[e * 2 * DIM + slot];
@@ -406,6 +472,7 @@ __global__ void __launch_bounds__(BT, P == 2 ? 3 : 1)
     const double* Mf = MfA + slot * NQF * 8;
     __syncthreads();
     // first tangential direction: Z[ab][qj][i1 j1] = sum_qi B(qi, i1) B(qi, j1) Mf[qi, qj][ab]
+#pragma unroll 1
     for (int o = tid; o < 8 * Q3 * NN2; o += BT) {
       const int ij = o % NN2, qj = (o / NN2) % Q3, ab = o / (Q3 * NN2);
       if ((ab & 3) >= 2 && !interior) continue;
@@ -416,6 +483,7 @@ __global__ void __launch_bounds__(BT, P == 2 ? 3 : 1)
     }
     __syncthreads();
     // second tangential direction: Cf[ab][i2 j2][i1 j1] = sum_qj B(qj, i2) B(qj, j2) Z[ab][qj][i1 j1]
+#pragma unroll 1
     for (int o = tid; o < 8 * N3 * N3 * NN2; o += BT) {
       const int ij1 = o % NN2, ij2 = (o / NN2) % (N3 * N3), ab = o / (N3 * N3 * NN2);
       if ((ab & 3) >= 2 && !interior) continue;
@@ -434,15 +502,19 @@ __global__ void __launch_bounds__(BT, P == 2 ? 3 : 1)
     const int lend_nb = side < 0 ? P : 0;
     const double* De_own = tb.De[side < 0 ? 0 : 1];
     const double* De_nb = tb.De[side < 0 ? 1 : 0];
+#pragma unroll UNR_ENT
     for (int k = 0; k < ENT; ++k) {
       const int idx = tid + k * BT;
       if (idx >= NB * NB) break;
       const int i = idx / NB, j = idx % NB;
-      const int ic[3] = {i % NN, (i / NN) % NN, DIM == 3 ? i / NN2 : 0};
-      const int jc[3] = {j % NN, (j / NN) % NN, DIM == 3 ? j / NN2 : 0};
-      const int li = ic[ax], lj = jc[ax];
-      const int tix = ic[t1ax] * NN + jc[t1ax];
-      const int t2x = DIM == 3 ? ic[t2ax] * N3 + jc[t2ax] : 0;
+      // node coordinates picked by run-time axes with selects (an array
+      // indexed at run time would live in scratch memory)
+      const int i0 = i % NN, i1 = (i / NN) % NN, i2 = DIM == 3 ? i / NN2 : 0;
+      const int j0 = j % NN, j1 = (j / NN) % NN, j2 = DIM == 3 ? j / NN2 : 0;
+      auto pick = [](int a0, int a1, int a2, int d) { return d == 0 ? a0 : (d == 1 ? a1 : a2); };
+      const int li = pick(i0, i1, i2, ax), lj = pick(j0, j1, j2, ax);
+      const int tix = pick(i0, i1, i2, t1ax) * NN + pick(j0, j1, j2, t1ax);
+      const int t2x = DIM == 3 ? pick(i0, i1, i2, t2ax) * N3 + pick(j0, j1, j2, t2ax) : 0;
       const double* c = Cf + t2x * NN2 + tix;
       constexpr int CS = N3 * N3 * NN2;  // stride between pairs ab
       const double pi0 = li == lend_own ? 1.0 : 0.0, pi1 = De_own[li];
