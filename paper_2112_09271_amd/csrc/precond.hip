@@ -905,8 +905,11 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
   const bool conc_first = split && c.nb >= 64;
   // with a large vertex grid the host hierarchy is the longest part of the
   // set-up: the concentration part is then queued behind the kernels of the
-  // vertex stencil the host waits for
-  const bool conc_late = split && !conc_first && P.nvert >= (int64_t(1) << 16);
+  // vertex stencil the host waits for (DGNP_CONC_LATE=0 / 1 forces the choice;
+  // the order changes no result)
+  const char* late_env = getenv("DGNP_CONC_LATE");
+  const bool conc_late =
+      split && !conc_first && (late_env ? atoi(late_env) != 0 : P.nvert >= (int64_t(1) << 16));
   if (!split) {
     ScopeTimer tm(c, "assemble", s);
     const int f0 = phi ? 0 : 1, f1 = conc ? c.m : 1;

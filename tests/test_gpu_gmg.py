@@ -89,6 +89,32 @@ def test_solve_matches_oracle(cfg_fn):
     gp.close()
 
 
+def test_setup_order_changes_no_result(monkeypatch):
+    """The set-up queues the concentration part before the potential's stencil
+    kernels or, on large vertex grids, behind them (DGNP_CONC_LATE forces
+    either); the order of independent device work and the host's aggregation
+    set-up (fresh, then with kept prolongators and values-only products) change
+    no result: both orders give bitwise the same mixed and double solutions."""
+    from paper_2112_09271_amd.dgnp import DGNP_CPC_GMG, DGNP_F32, DGNP_F64, Problem
+    cfg = get_config("cfg2t")
+    data = boundary_data(cfg)
+    out = {}
+    for late in ("0", "1"):
+        monkeypatch.setenv("DGNP_CONC_LATE", late)
+        print(f"[case] {cfg.name} conc_late={late}", flush=True)
+        gp = Problem(cfg, data, conc_pc=DGNP_CPC_GMG)
+        res = []
+        for prec in (DGNP_F32, DGNP_F64):
+            x, st = gp.solve(prec=prec)
+            assert st.status == 0
+            res.append((host(x).copy(), st.lin_its_total))
+        out[late] = res
+        gp.close()
+    for (x0, i0), (x1, i1) in zip(out["0"], out["1"]):
+        assert i0 == i1
+        assert np.array_equal(x0, x1)
+
+
 def test_fewer_krylov_iterations_than_bilu():
     """On a p = 1 box with moderate convection the V-cycle is a better
     approximate inverse of the concentration blocks than one BILU(0) solve."""
