@@ -158,6 +158,7 @@ Csr csr_transpose(const Csr& A) {
 // (kept between set-ups, so that a large product does not pay the page faults
 // of fresh memory every time).
 Csr csr_matmul(const Csr& A, const Csr& B, Csr&& storage) {
+  if (A.n >= (1 << 30)) throw Error(DGNP_E_ARG, "sparse product: 2^30 rows or more");  // marks 2 i + 1
   Csr C = std::move(storage);
   C.n = A.n;
   C.m = B.m;
@@ -234,7 +235,7 @@ Csr csr_matmul(const Csr& A, const Csr& B) { return csr_matmul(A, B, Csr()); }
 // then undefined) when C has another shape, a term of the product falls
 // outside C's row, or one of C's columns receives none.
 static bool csr_matmul_values(const Csr& A, const Csr& B, Csr& C) {
-  if (C.n != A.n || C.m != B.m || C.rp.size() != size_t(A.n) + 1 || C.ci.size() != size_t(C.rp[C.n]) ||
+  if (A.n >= (1 << 30) || C.n != A.n || C.m != B.m || C.rp.size() != size_t(A.n) + 1 || C.ci.size() != size_t(C.rp[C.n]) ||
       C.v.size() != C.ci.size())
     return false;
   const int nt = host_threads(0);

@@ -1090,7 +1090,6 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
         // the kept hierarchy gives up its prolongators and product arrays
         H = reuse ? sa_setup_reuse(std::move(A1), std::move(P.sa_prev), &P.sa_x0)
                   : sa_setup(std::move(A1), 12, 256, 0.0, &P.sa_x0);
-        if (reuse) P.sa_prev = AmgHierarchy();  // taken apart; H replaces it below
       } catch (...) {
         sa_err = std::current_exception();
         P.sa_prev = AmgHierarchy();  // possibly taken apart: the next set-up starts afresh
