@@ -1653,28 +1653,71 @@ __global__ void k_p1_restrict(const T* __restrict__ rp, const T* __restrict__ su
   r1[t] = T(acc);
 }
 
-// gal[e][s][u][v] = sum_ij N_u(i) A_{e,s}[i][j] N_v(j)   (s = 0 diag, 1 + slot)
+// gal[e][s][u][v] = sum_ij N_u(i) A_{e,s}[i][j] N_v(j)   (s = 0 diag, 1 + slot).
+// The rows are contracted first: lane t of the G = BT / NB row groups owns
+// column j = t mod NB and the rows g, g + G, ... of its group g = t / NB, so
+// every load instruction of a wave reads consecutive entries of the block
+// (address t + NB G r); the groups' partial sums W_g[u][j] are added in group
+// order, then gal = W N.
 template <int DIM, int P>
 __global__ void __launch_bounds__(BT) k_q1_galerkin(const double* __restrict__ blk, double* __restrict__ gal) {
   constexpr int NN = P + 1;
   constexpr int NB = DIM == 3 ? NN * NN * NN : NN * NN;
   constexpr int NV = 1 << DIM;
   constexpr int NSLOT = 2 * DIM + 1;
-  __shared__ double T[NB * NV];
+  constexpr int G = BT / NB;  // row groups
+  static_assert(G >= 1, "one row group at least");
+  __shared__ double sN[NB <= 8 ? 1 : NB * NV];
+  __shared__ double Wg[NB <= 8 ? 1 : G * NV * NB];
+  __shared__ double W[NV * NB];
   const int64_t e = blockIdx.x;
   const int s = blockIdx.y;
+  const int t = threadIdx.x;
   const double* A = blk + (e * NSLOT + s) * NB * NB;
-  for (int idx = threadIdx.x; idx < NB * NV; idx += BT) {
-    const int i = idx / NV, v = idx % NV;
-    double acc = 0.0;
-    for (int j = 0; j < NB; ++j) acc += A[i * NB + j] * q1_shape<DIM, P>(j, v);
-    T[idx] = acc;
+  if constexpr (NB <= 8) {
+    // blocks of at most 8 rows: T = A N straight from the block, then N^T T
+    // (the row groups would be mostly empty)
+    for (int idx = t; idx < NB * NV; idx += BT) {
+      const int i = idx / NV, v = idx % NV;
+      double acc = 0.0;
+      for (int j = 0; j < NB; ++j) acc += A[i * NB + j] * q1_shape<DIM, P>(j, v);
+      W[idx] = acc;
+    }
+    __syncthreads();
+    for (int idx = t; idx < NV * NV; idx += BT) {
+      const int u = idx / NV, v = idx % NV;
+      double acc = 0.0;
+      for (int i = 0; i < NB; ++i) acc += q1_shape<DIM, P>(i, u) * W[i * NV + v];
+      gal[(e * NSLOT + s) * NV * NV + idx] = acc;
+    }
+    return;
+  }
+  for (int idx = t; idx < NB * NV; idx += BT) sN[idx] = q1_shape<DIM, P>(idx / NV, idx % NV);
+  __syncthreads();
+  if (t < G * NB) {
+    const int j = t % NB, g = t / NB;
+    double w[NV];
+#pragma unroll
+    for (int u = 0; u < NV; ++u) w[u] = 0.0;
+    for (int i = g; i < NB; i += G) {
+      const double a = A[i * NB + j];
+#pragma unroll
+      for (int u = 0; u < NV; ++u) w[u] += sN[i * NV + u] * a;
+    }
+#pragma unroll
+    for (int u = 0; u < NV; ++u) Wg[(g * NV + u) * NB + j] = w[u];
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < NV * NV; idx += BT) {
+  for (int idx = t; idx < NV * NB; idx += BT) {
+    double w = 0.0;
+    for (int g = 0; g < G; ++g) w += Wg[g * NV * NB + idx];
+    W[idx] = w;
+  }
+  __syncthreads();
+  for (int idx = t; idx < NV * NV; idx += BT) {
     const int u = idx / NV, v = idx % NV;
     double acc = 0.0;
-    for (int i = 0; i < NB; ++i) acc += q1_shape<DIM, P>(i, u) * T[i * NV + v];
+    for (int j = 0; j < NB; ++j) acc += W[u * NB + j] * sN[j * NV + v];
     gal[(e * NSLOT + s) * NV * NV + idx] = acc;
   }
 }
