@@ -552,7 +552,7 @@ def main():
                      "ilu_bwd_f32": "k_ilu_dfp_bwd_cfg2", "jac_apply_f32": "k_jlin_f32_cfg2",
                      "ilu_factor": "k_ilu_factor_fine_cfg2"},
             "cfg5": {"ilu_fwd_f32": "k_ilu_dfl_fwd_cfg5", "ilu_bwd_f32": "k_ilu_dfl_bwd_cfg5",
-                     "jac_apply_f32": "k_jlin_f32_cfg5"}}.get(cfg.name, {})
+                     "jac_apply_f32": "k_jlin_f32_cfg5", "ilu_factor": "k_ilu_factor_cfg5"}}.get(cfg.name, {})
     srcs = ("kernels_jac.hip", "dg_device.hpp", "pointwise.hpp") if dom == "jac_apply_f32" else ("kernels_block.hip",)
     copy_gbs = copy_bandwidth()
     roofline = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
