@@ -131,8 +131,10 @@ void host_parallel_rows(int n, const std::function<void(int, int)>& fn) {
   parallel_rows(n, CH, [&](int, int, int r0, int r1) { fn(r0, r1); });
 }
 
-Csr csr_transpose(const Csr& A) {
-  Csr T;
+Csr csr_transpose(const Csr& A) { return csr_transpose(A, Csr()); }
+
+Csr csr_transpose(const Csr& A, Csr&& storage) {
+  Csr T = std::move(storage);
   T.n = A.m;
   T.m = A.n;
   T.rp.assign(size_t(T.n) + 1, 0);
@@ -282,9 +284,11 @@ static bool csr_matmul_values(const Csr& A, const Csr& B, Csr& C) {
 
 static std::vector<double> diag_of(const Csr& A) {
   std::vector<double> d(static_cast<size_t>(A.n), 0.0);
-  for (int i = 0; i < A.n; ++i)
-    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k)
-      if (A.ci[k] == i) d[i] = A.v[k];
+  parallel_rows(A.n, CH, [&](int, int, int r0, int r1) {
+    for (int i = r0; i < r1; ++i)
+      for (int k = A.rp[i]; k < A.rp[i + 1]; ++k)
+        if (A.ci[k] == i) d[i] = A.v[k];
+  });
   return d;
 }
 
@@ -482,17 +486,19 @@ std::vector<double> dense_inverse(const Csr& A) {
 }
 
 // one coarsening step: returns the smoothed prolongator
-static Csr sa_prolongator(const Csr& A, double theta, double lam_A) {
+static Csr sa_prolongator(const Csr& A, double theta, double lam_A, Csr&& storage) {
   const int n = A.n;
   const std::vector<double> d = diag_of(A);
   // strength of connection
   std::vector<char> strong(A.v.size(), 0);
-  for (int i = 0; i < n; ++i)
-    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-      const int j = A.ci[k];
-      if (j != i && (theta == 0.0 || std::fabs(A.v[k]) >= theta * std::sqrt(std::fabs(d[i] * d[j]))))
-        strong[k] = 1;
-    }
+  parallel_rows(n, CH, [&](int, int, int r0, int r1) {
+    for (int i = r0; i < r1; ++i)
+      for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+        const int j = A.ci[k];
+        if (j != i && (theta == 0.0 || std::fabs(A.v[k]) >= theta * std::sqrt(std::fabs(d[i] * d[j]))))
+          strong[k] = 1;
+      }
+  });
   // aggregation
   std::vector<int> agg(static_cast<size_t>(n), -1);
   int na = 0;
@@ -570,33 +576,48 @@ static Csr sa_prolongator(const Csr& A, double theta, double lam_A) {
   const double lam = theta == 0.0 && lam_A > 0.0 ? lam_A : lmax_dinvA(Af, dinv, 20, nullptr);
   const double omega = (4.0 / 3.0) / lam;
   Csr AP = csr_matmul(Af, Pt);
-  for (int i = 0; i < n; ++i)
-    for (int k = AP.rp[i]; k < AP.rp[i + 1]; ++k) AP.v[k] *= -omega * dinv[i];
-  // P = Pt - omega D^{-1} Af Pt
-  Csr P;
+  // P = Pt - omega D^{-1} Af Pt, in two passes over the rows on the worker
+  // pool: the row lengths (the own aggregate's column is added when Af Pt
+  // lacks it), then the columns in order with the values
+  Csr P = std::move(storage);
   P.n = n;
   P.m = na;
   P.rp.assign(size_t(n) + 1, 0);
-  for (int i = 0; i < n; ++i) {
-    bool own = false;
-    for (int k = AP.rp[i]; k < AP.rp[i + 1]; ++k) {
-      double v = AP.v[k];
-      if (AP.ci[k] == agg[i]) {
-        v += 1.0;
-        own = true;
+  auto has_own = [&](int i) {
+    for (int k = AP.rp[i]; k < AP.rp[i + 1]; ++k)
+      if (AP.ci[k] == agg[i]) return true;
+    return false;
+  };
+  parallel_rows(n, CH, [&](int, int, int r0, int r1) {
+    for (int i = r0; i < r1; ++i) P.rp[i + 1] = AP.rp[i + 1] - AP.rp[i] + (has_own(i) ? 0 : 1);
+  });
+  for (int i = 0; i < n; ++i) P.rp[i + 1] += P.rp[i];
+  P.ci.resize(size_t(P.rp[n]));
+  P.v.resize(size_t(P.rp[n]));
+  parallel_rows(n, CH, [&](int, int, int r0, int r1) {
+    for (int i = r0; i < r1; ++i) {
+      const int a = agg[i];
+      bool pending = !has_own(i);  // the own column still to be placed (value 1)
+      int o = P.rp[i];
+      for (int k = AP.rp[i]; k < AP.rp[i + 1]; ++k) {
+        const int c = AP.ci[k];
+        if (pending && a < c) {
+          P.ci[o] = a;
+          P.v[o++] = 1.0;
+          pending = false;
+        }
+        double v = AP.v[k];
+        v *= -omega * dinv[i];
+        if (c == a) v += 1.0;
+        P.ci[o] = c;
+        P.v[o++] = v;
       }
-      P.ci.push_back(AP.ci[k]);
-      P.v.push_back(v);
+      if (pending) {
+        P.ci[o] = a;
+        P.v[o] = 1.0;
+      }
     }
-    if (!own) {
-      // keep columns sorted
-      auto it = std::lower_bound(P.ci.begin() + P.rp[i], P.ci.end(), agg[i]);
-      const size_t pos = size_t(it - P.ci.begin());
-      P.ci.insert(it, agg[i]);
-      P.v.insert(P.v.begin() + long(pos), 1.0);
-    }
-    P.rp[i + 1] = int(P.ci.size());
-  }
+  });
   return P;
 }
 
@@ -618,7 +639,8 @@ static void smoother_data(AmgHierarchy& H, const Csr& A, int iters, std::vector<
   H.dinv.push_back(std::move(dinv));
 }
 
-AmgHierarchy sa_setup(Csr A1, int max_levels, int coarse_size, double theta, std::vector<double>* x0) {
+AmgHierarchy sa_setup(Csr A1, int max_levels, int coarse_size, double theta, std::vector<double>* x0,
+                      AmgHierarchy* recycle) {
   auto t0 = std::chrono::steady_clock::now();
   auto mark = [&](const char* what) { sa_mark(t0, what); };
   AmgHierarchy H;
@@ -628,12 +650,20 @@ AmgHierarchy sa_setup(Csr A1, int max_levels, int coarse_size, double theta, std
   mark("lmax");
   while (int(H.A.size()) < max_levels && H.A.back().n > coarse_size) {
     const Csr& A = H.A.back();
-    Csr P = sa_prolongator(A, theta, H.lmax.back());
+    // arrays lent by the recycled hierarchy (empty when it has no such level)
+    const size_t l = H.A.size() - 1;
+    auto lend = [&](std::vector<Csr>* v, size_t i) {
+      return recycle && v && i < v->size() ? std::move((*v)[i]) : Csr();
+    };
+    Csr P = sa_prolongator(A, theta, H.lmax.back(), lend(recycle ? &recycle->P : nullptr, l));
     mark("prolongator");
     if (P.m >= A.n * 0.9 || P.m == 0) break;  // stalled coarsening
-    Csr R = csr_transpose(P);
-    Csr AP = csr_matmul(A, P);
-    Csr Ac = csr_matmul(R, AP);
+    Csr R = csr_transpose(P, lend(recycle ? &recycle->R : nullptr, l));
+    // the products values-only into the lent arrays when their patterns agree
+    Csr AP = lend(recycle ? &recycle->work : nullptr, l);
+    if (!csr_matmul_values(A, P, AP)) AP = csr_matmul(A, P, std::move(AP));
+    Csr Ac = lend(recycle ? &recycle->A : nullptr, l + 1);
+    if (!csr_matmul_values(R, AP, Ac)) Ac = csr_matmul(R, AP, std::move(Ac));
     H.work.push_back(std::move(AP));
     mark("RAP");
     H.P.push_back(std::move(P));

@@ -27,6 +27,8 @@ struct AmgHierarchy {
 // (row-independent work only)
 void host_parallel_rows(int n, const std::function<void(int, int)>& fn);
 Csr csr_transpose(const Csr& A);
+// the same built in the arrays of `storage` (any earlier matrix)
+Csr csr_transpose(const Csr& A, Csr&& storage);
 Csr csr_matmul(const Csr& A, const Csr& B);
 // the same product built in the arrays of `storage` (any earlier matrix)
 Csr csr_matmul(const Csr& A, const Csr& B, Csr&& storage);
@@ -37,9 +39,11 @@ std::vector<double> dense_inverse(const Csr& A);
 // power iterations for the largest eigenvalue of D^{-1} A; x_io (may be null):
 // start vector in (used when its size matches), last vector out
 double lmax_dinvA(const Csr& A, const std::vector<double>& dinv, int iters, std::vector<double>* x_io = nullptr);
-// x0 (may be null) receives the finest level's last power-iteration vector
+// x0 (may be null) receives the finest level's last power-iteration vector;
+// recycle (may be null) lends the arrays of an earlier hierarchy, which is
+// left without a usable hierarchy (the result does not depend on it)
 AmgHierarchy sa_setup(Csr A1, int max_levels, int coarse_size, double theta,
-                      std::vector<double>* x0 = nullptr);
+                      std::vector<double>* x0 = nullptr, AmgHierarchy* recycle = nullptr);
 // the same hierarchy shape for a new finest matrix with the aggregates and
 // prolongators of prev kept: only the Galerkin products, smoother data and
 // coarse inverse are recomputed; the finest estimate warm-starts from x0

@@ -1089,7 +1089,7 @@ void precond_numeric(dgnp_ctx& c, bool f32, hipStream_t s, bool assemble_only, i
         Csr A1 = vertex_matrix(c, P, st, std::move(storage));
         // the kept hierarchy gives up its prolongators and product arrays
         H = reuse ? sa_setup_reuse(std::move(A1), std::move(P.sa_prev), &P.sa_x0)
-                  : sa_setup(std::move(A1), 12, 256, 0.0, &P.sa_x0);
+                  : sa_setup(std::move(A1), 12, 256, 0.0, &P.sa_x0, &P.sa_prev);  // lends its arrays
       } catch (...) {
         sa_err = std::current_exception();
         P.sa_prev = AmgHierarchy();  // possibly taken apart: the next set-up starts afresh

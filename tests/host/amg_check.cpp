@@ -254,6 +254,46 @@ int main() {
       }
     if (dmax > 1e-13 * imax) return fail("banded and dense Cholesky inverses differ");
   }
+  // a fresh set-up that recycles an earlier hierarchy's arrays (values-only
+  // products where the patterns agree) builds bitwise the same hierarchy as
+  // one without: recycling a hierarchy of the same matrix, of a matrix of
+  // another pattern, and of another size
+  {
+    auto same_levels = [](const dgnp::AmgHierarchy& a, const dgnp::AmgHierarchy& b) {
+      if (a.A.size() != b.A.size() || a.lmax != b.lmax || a.coarse_inv != b.coarse_inv) return false;
+      for (size_t l = 0; l < a.A.size(); ++l)
+        if (a.A[l].v != b.A[l].v || a.A[l].ci != b.A[l].ci || a.A[l].rp != b.A[l].rp) return false;
+      for (size_t l = 0; l < a.P.size(); ++l)
+        if (a.P[l].v != b.P[l].v || a.P[l].ci != b.P[l].ci || a.R[l].v != b.R[l].v || a.R[l].ci != b.R[l].ci)
+          return false;
+      return true;
+    };
+    std::vector<double> xa, xb;
+    const dgnp::AmgHierarchy ref = dgnp::sa_setup(A, 12, 256, 0.0, &xa);
+    Csr Ad = A;  // another pattern: the coupling of rows 0 and 1 dropped
+    {
+      Csr B;
+      B.n = B.m = A.n;
+      B.rp.push_back(0);
+      for (int i = 0; i < A.n; ++i) {
+        for (int k = A.rp[i]; k < A.rp[i + 1]; ++k)
+          if (!((i == 0 && A.ci[k] == 1) || (i == 1 && A.ci[k] == 0))) {
+            B.ci.push_back(A.ci[k]);
+            B.v.push_back(A.v[k]);
+          }
+        B.rp.push_back(int(B.ci.size()));
+      }
+      Ad = B;
+    }
+    const Csr* donors[3] = {&A, &Ad, nullptr};
+    Csr small = laplace3d(12);
+    donors[2] = &small;
+    for (const Csr* dm : donors) {
+      dgnp::AmgHierarchy donor = dgnp::sa_setup(*dm, 12, 256, 0.0);
+      dgnp::AmgHierarchy H1 = dgnp::sa_setup(A, 12, 256, 0.0, &xb, &donor);
+      if (!same_levels(H1, ref) || xa != xb) return fail("recycled fresh set-up differs");
+    }
+  }
   // checksum of every value of the hierarchy (bit patterns), to compare runs
   uint64_t h = 1469598103934665603ull;
   auto mix = [&](double x) {
