@@ -16,6 +16,8 @@
 // One work-group per element, as the general operator kernel: sum-factorised
 // volume term, then the 6 faces element-centric (own and neighbour traces at
 // the face Gauss points, flux, integration into the own element only).
+#include <cstdlib>
+
 #include "dg_device.hpp"
 #include "kernels_phi.hpp"
 
@@ -87,12 +89,12 @@ __global__ void __launch_bounds__(PHI_NT(P)) k_phi_kappa(KArgs A, const double* 
 }
 
 // y = A_phiphi u
-template <int P, typename T>
-__global__ void __launch_bounds__(PHI_NT(P)) k_phi_op(KArgs A, const T* __restrict__ u, const T* __restrict__ kv,
-                                                      const T* __restrict__ kf, T* __restrict__ y, int64_t eper) {
+template <int P, typename T, int NT>
+__global__ void __launch_bounds__(NT) k_phi_op(KArgs A, const T* __restrict__ u, const T* __restrict__ kv,
+                                               const T* __restrict__ kf, T* __restrict__ y, int64_t eper) {
   using S = Sz<3, P>;
   constexpr int NN = S::NN, NQ = S::NQ, NB = S::NB, NQV = S::NQV, NFN = S::NFN, NQF = S::NQF;
-  constexpr int NT = PHI_NT(P);
+  static_assert(NT >= NQ * NN && NT >= 2 * NN && NT >= 6, "the table loads take one lane per entry");
   constexpr int VOLR = 4 * NQV + NN * NN * 2 * NQ + NN * 3 * NQ * NQ;
   constexpr int NROW = 6 * 2 * 2;  // face, side (own, neighbour), value / d/dx_ax
   constexpr int FACR = NROW * NFN + NROW * NQF;
@@ -274,15 +276,29 @@ void launch_phi_kappa(int p, int m, const KArgs& A, const double* xs, T* kv, T* 
   DGNP_HIP(hipGetLastError());
 }
 
+// threads per element: one wave (64), or 128 / 256 by DGNP_PHI_NT (A/B
+// measurement).  Most phases have fewer items than 256 lanes (16 to 192 at
+// p = 3), so one wave per element keeps the lanes busy and lets more elements
+// share a CU: on the 12.6M-DOF channel, p = 3, 106 / 135 / 193 us per apply in
+// single precision and 216 / 223 / 310 us in double with 64 / 128 / 256 threads.
+template <int P, typename T>
+static void phi_op_t(const KArgs& A, const T* u, const T* kv, const T* kf, T* y, hipStream_t s) {
+  const int64_t eper = (A.E + 7) / 8;
+  const dim3 g(unsigned(8 * eper));
+  const char* env = getenv("DGNP_PHI_NT");
+  const int nt = env ? atoi(env) : 64;
+  if (nt == 64) hipLaunchKernelGGL((k_phi_op<P, T, 64>), g, dim3(64), 0, s, A, u, kv, kf, y, eper);
+  else if (nt == 128) hipLaunchKernelGGL((k_phi_op<P, T, 128>), g, dim3(128), 0, s, A, u, kv, kf, y, eper);
+  else hipLaunchKernelGGL((k_phi_op<P, T, 256>), g, dim3(256), 0, s, A, u, kv, kf, y, eper);
+  DGNP_HIP(hipGetLastError());
+}
+
 template <typename T>
 void launch_phi_op(int p, const KArgs& A, const T* u, const T* kv, const T* kf, T* y, hipStream_t s) {
   if (A.E == 0) return;
-  const int64_t eper = (A.E + 7) / 8;
-  const dim3 g(unsigned(8 * eper));
-  if (p == 2) hipLaunchKernelGGL((k_phi_op<2, T>), g, dim3(PHI_NT(2)), 0, s, A, u, kv, kf, y, eper);
-  else if (p == 3) hipLaunchKernelGGL((k_phi_op<3, T>), g, dim3(PHI_NT(3)), 0, s, A, u, kv, kf, y, eper);
+  if (p == 2) phi_op_t<2, T>(A, u, kv, kf, y, s);
+  else if (p == 3) phi_op_t<3, T>(A, u, kv, kf, y, s);
   else throw Error(DGNP_E_ARG, "potential operator: orders 2 and 3");
-  DGNP_HIP(hipGetLastError());
 }
 
 template void launch_phi_kappa<double>(int, int, const KArgs&, const double*, double*, double*, hipStream_t);
