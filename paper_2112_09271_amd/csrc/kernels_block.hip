@@ -1370,6 +1370,9 @@ struct PotRows {
   static constexpr bool VEC = std::is_same<T, float>::value && NB <= 32;
   static constexpr int LD = VEC ? ((NB + 3) & ~3) : NB;
   static constexpr int QV = LD / 4;
+  // single-precision rows take 8 lanes each; blocks of up to 8 (16) rows
+  // share a work-group four (two) at a time, 64 (128) lanes per element
+  static constexpr int EPB = VEC ? (NB <= 8 ? 4 : (NB <= 16 ? 2 : 1)) : 1;
 };
 
 __device__ inline float dot4(const float4& a, const float4& b) {
@@ -1386,42 +1389,46 @@ __device__ inline float4 ld4(const float* p) { return *reinterpret_cast<const fl
 template <typename T, int NB, int DIM>
 __global__ void __launch_bounds__(BT) k_bspmv(const T* __restrict__ blk, const int* __restrict__ nbr,
                                               const T* __restrict__ x, const T* __restrict__ b, T alpha,
-                                              T beta, T* __restrict__ y, int64_t bstride, int64_t vstride) {
+                                              T beta, T* __restrict__ y, int64_t bstride, int64_t vstride,
+                                              int64_t E) {
   constexpr int NSLOT = 2 * DIM + 1;
   using PR = PotRows<T, NB>;
   const int tid = threadIdx.x;
-  const int64_t i = blockIdx.x;
   // blockIdx.y: one of several independent systems at block / vector strides
   blk += blockIdx.y * bstride;
   x += blockIdx.y * vstride;
   if (b) b += blockIdx.y * vstride;
   y += blockIdx.y * vstride;
   if constexpr (PR::VEC) {
-    constexpr int LD = PR::LD, QV = PR::QV;
-    __shared__ __align__(16) float xv[NSLOT][LD];
-    const int row = tid >> 3, part = tid & 7;
-    const bool on = row < NB && part < QV;
+    constexpr int LD = PR::LD, QV = PR::QV, EPB = PR::EPB, TPE = BT / EPB;
+    __shared__ __align__(16) float xv[EPB][NSLOT][LD];
+    const int el = tid / TPE, lt = tid % TPE;  // element of the group, lane within it
+    const int64_t i = int64_t(blockIdx.x) * EPB + el;
+    const bool live = i < E;
+    const int row = lt >> 3, part = lt & 7;
+    const bool on = live && row < NB && part < QV;
     const float* bi = blk + i * NSLOT * NB * LD + row * LD + 4 * part;
     float4 mr[NSLOT];
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) mr[s] = on ? ld4(bi + s * NB * LD) : make_float4(0.f, 0.f, 0.f, 0.f);
     int nb[NSLOT];
-    nb[0] = int(i);
-    for (int s = 0; s < 2 * DIM; ++s) nb[1 + s] = nbr[i * 2 * DIM + s];
-    for (int idx = tid; idx < NSLOT * LD; idx += BT) {
+    nb[0] = live ? int(i) : -1;
+    for (int s = 0; s < 2 * DIM; ++s) nb[1 + s] = live ? nbr[i * 2 * DIM + s] : -1;
+    for (int idx = lt; idx < NSLOT * LD; idx += TPE) {
       const int sl = idx / LD, c = idx - sl * LD;
-      xv[sl][c] = (c < NB && nb[sl] >= 0) ? x[int64_t(nb[sl]) * NB + c] : 0.f;
+      xv[el][sl][c] = (c < NB && nb[sl] >= 0) ? x[int64_t(nb[sl]) * NB + c] : 0.f;
     }
     __syncthreads();
     float acc = 0.f;
     if (on) {
 #pragma unroll
       for (int s = 0; s < NSLOT; ++s)
-        if (nb[s] >= 0) acc += dot4(mr[s], ld4(&xv[s][4 * part]));
+        if (nb[s] >= 0) acc += dot4(mr[s], ld4(&xv[el][s][4 * part]));
     }
     acc = sum8(acc);
-    if (row < NB && part == 0) y[i * NB + row] = alpha * acc + (b ? beta * b[i * NB + row] : 0.f);
+    if (live && row < NB && part == 0) y[i * NB + row] = alpha * acc + (b ? beta * b[i * NB + row] : 0.f);
   } else {
+    const int64_t i = blockIdx.x;
     __shared__ T xs[NSLOT][NB];
     const int row = tid >> 2, part = tid & 3;
     int nb[NSLOT];
@@ -2161,8 +2168,9 @@ template void launch_ilu_solve<float>(int, int, int, const float*, const int*, c
 template <typename T, int NB, int DIM>
 static void bsp_t(int64_t E, const T* blk, const int* nbr, const T* x, const T* b, T alpha, T beta, T* y,
                   int nsys, int64_t bstride, int64_t vstride, hipStream_t s) {
-  hipLaunchKernelGGL((k_bspmv<T, NB, DIM>), dim3(unsigned(E), unsigned(nsys)), dim3(BT), 0, s, blk, nbr, x, b,
-                     alpha, beta, y, bstride, vstride);
+  constexpr int EPB = PotRows<T, NB>::EPB;
+  hipLaunchKernelGGL((k_bspmv<T, NB, DIM>), dim3(unsigned((E + EPB - 1) / EPB), unsigned(nsys)), dim3(BT), 0, s,
+                     blk, nbr, x, b, alpha, beta, y, bstride, vstride, E);
 }
 
 template <typename T>
@@ -2541,17 +2549,21 @@ template <typename T, int NB, int DIM>
 __global__ void __launch_bounds__(BT) k_cheb_blk(const T* __restrict__ blk, const int* __restrict__ nbr,
                                                  const T* __restrict__ dinv, const T* u, const T* base,
                                                  const T* sub, const T* dprev, const T* x_in, T c1, T c2,
-                                                 T* r_out, T* d_out, T* x_out) {
+                                                 T* r_out, T* d_out, T* x_out, int64_t E) {
   constexpr int NSLOT = 2 * DIM + 1;
   using PR = PotRows<T, NB>;
   const int tid = threadIdx.x;
-  const int64_t i = blockIdx.x;
   if constexpr (PR::VEC) {
-    constexpr int LD = PR::LD, QV = PR::QV;
-    __shared__ __align__(16) float xv[NSLOT][LD];
-    __shared__ __align__(16) float rv[LD];
-    const int row = tid >> 3, part = tid & 7;
-    const bool on = row < NB && part < QV;
+    constexpr int LD = PR::LD, QV = PR::QV, EPB = PR::EPB, TPE = BT / EPB;
+    __shared__ __align__(16) float xv_[EPB][NSLOT][LD];
+    __shared__ __align__(16) float rv_[EPB][LD];
+    const int el = tid / TPE, lt = tid % TPE;  // element of the group, lane within it
+    float(*xv)[LD] = xv_[el];
+    float* rv = rv_[el];
+    const int64_t i = int64_t(blockIdx.x) * EPB + el;
+    const bool live = i < E;
+    const int row = lt >> 3, part = lt & 7;
+    const bool on = live && row < NB && part < QV;
     // the block rows and the inverse diagonal row go out first: they do not
     // depend on the neighbour table
     const float* bi = blk + i * NSLOT * NB * LD + row * LD + 4 * part;
@@ -2561,10 +2573,10 @@ __global__ void __launch_bounds__(BT) k_cheb_blk(const T* __restrict__ blk, cons
       mr[s] = (u && on) ? ld4(bi + s * NB * LD) : make_float4(0.f, 0.f, 0.f, 0.f);
     const float4 dr = on ? ld4(dinv + (i * NB + row) * LD + 4 * part) : make_float4(0.f, 0.f, 0.f, 0.f);
     int nb[NSLOT];
-    nb[0] = int(i);
-    for (int s = 0; s < 2 * DIM; ++s) nb[1 + s] = nbr[i * 2 * DIM + s];
+    nb[0] = live ? int(i) : -1;
+    for (int s = 0; s < 2 * DIM; ++s) nb[1 + s] = live ? nbr[i * 2 * DIM + s] : -1;
     if (u) {
-      for (int idx = tid; idx < NSLOT * LD; idx += BT) {
+      for (int idx = lt; idx < NSLOT * LD; idx += TPE) {
         const int sl = idx / LD, c = idx - sl * LD;
         xv[sl][c] = (c < NB && nb[sl] >= 0) ? u[int64_t(nb[sl]) * NB + c] : 0.f;
       }
@@ -2577,15 +2589,15 @@ __global__ void __launch_bounds__(BT) k_cheb_blk(const T* __restrict__ blk, cons
         if (nb[s] >= 0) acc += dot4(mr[s], ld4(&xv[s][4 * part]));
     }
     acc = sum8(acc);
-    if (row < NB && part == 0) {
+    if (live && row < NB && part == 0) {
       const float r = base[i * NB + row] - acc - (sub ? sub[i * NB + row] : 0.f);
       rv[row] = r;
       if (r_out) r_out[i * NB + row] = r;
     }
-    if (tid < LD - NB) rv[NB + tid] = 0.f;
+    if (lt < LD - NB) rv[NB + lt] = 0.f;
     __syncthreads();
     const float z = sum8(on ? dot4(dr, ld4(&rv[4 * part])) : 0.f);
-    if (row < NB && part == 0) {
+    if (live && row < NB && part == 0) {
       const int64_t k = i * NB + row;
       float d = c1 * z;
       if (dprev) d += c2 * dprev[k];
@@ -2593,6 +2605,7 @@ __global__ void __launch_bounds__(BT) k_cheb_blk(const T* __restrict__ blk, cons
       x_out[k] = (x_in ? x_in[k] : 0.f) + d;
     }
   } else {
+    const int64_t i = blockIdx.x;
     __shared__ T xs[NSLOT][NB];
     __shared__ T rs[NB];
     const int row = tid >> 2, part = tid & 3;
@@ -2666,8 +2679,9 @@ template <typename T, int NB, int DIM>
 static void cheb_blk_t(int64_t E, const T* blk, const int* nbr, const T* dinv, const T* u, const T* base,
                        const T* sub, const T* dprev, const T* x_in, T c1, T c2, T* r_out, T* d_out, T* x_out,
                        hipStream_t s) {
-  hipLaunchKernelGGL((k_cheb_blk<T, NB, DIM>), dim3(unsigned(E)), dim3(BT), 0, s, blk, nbr, dinv, u, base, sub,
-                     dprev, x_in, c1, c2, r_out, d_out, x_out);
+  constexpr int EPB = PotRows<T, NB>::EPB;
+  hipLaunchKernelGGL((k_cheb_blk<T, NB, DIM>), dim3(unsigned((E + EPB - 1) / EPB)), dim3(BT), 0, s, blk, nbr, dinv,
+                     u, base, sub, dprev, x_in, c1, c2, r_out, d_out, x_out, E);
 }
 
 template <typename T>
